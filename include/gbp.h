@@ -1,0 +1,208 @@
+/*
+ * gbp.h -- C ABI of the Geodesic-BP hot path for AMD Instinct MI355X (gfx950).
+ *
+ * Geodesic-BP (Grandits et al., arXiv 2308.08410) computes cardiac activation
+ * times with the anisotropic eikonal equation on a tetrahedral mesh (Sec. 2.1,
+ * Eq. (anisotropic_eikonal_eq)), differentiates them with respect to the model
+ * parameters by back-propagation along geodesic parents (Sec. 2.3), and maps
+ * them to body-surface ECGs with a precomputed lead-field operator (Sec. 2.4).
+ *
+ * General conventions (every entry point):
+ *   - Array arguments are caller-owned, contiguous, row-major.  "device" means
+ *     memory allocated with hipMalloc (e.g. a PyTorch tensor on the GPU);
+ *     "host" means ordinary CPU memory.  Nothing passed in is retained after
+ *     the call returns, except that a plan keeps its own copies of the mesh.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it; the eikonal forward and backward synchronise with it
+ *     internally (their iteration counts are decided on the device); the ECG,
+ *     loss and Adam calls are fully asynchronous.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Return value: GBP_OK (0) or a negative GBP_ERR_* code; gbp_last_error()
+ *     then returns a message (thread-local, valid until the next call).
+ *   - Symmetric 3x3 tensors are packed as 6 floats (xx, yy, zz, xy, xz, yz).
+ *     Gradients with respect to such a tensor store the off-diagonal entries
+ *     doubled (dL/dA_xy + dL/dA_yx), so that sum_k A6[k]*dA6[k] = <A, dL/dA>_F.
+ *   - Floating point is FP32 on the device.
+ */
+#ifndef GBP_H
+#define GBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GBP_OK = 0,
+    GBP_ERR_ARG = -1,             /* bad size, pointer or index */
+    GBP_ERR_DEGENERATE_TET = -2,  /* an element with (near) zero volume */
+    GBP_ERR_NOT_SPD = -3,         /* a velocity tensor that is not positive definite */
+    GBP_ERR_NONFINITE = -4,       /* NaN or Inf in an input that must be finite */
+    GBP_ERR_NOT_CONVERGED = -5,   /* iteration cap reached; outputs are still written */
+    GBP_ERR_HIP = -6,             /* a HIP runtime call failed */
+    GBP_ERR_NOMEM = -7            /* device or host allocation failed */
+};
+
+/* Opaque per-mesh plan: node/element reordering, adjacency, device workspace. */
+typedef struct gbp_plan_s *gbp_plan;
+
+typedef struct {
+    float eps_rel;     /* change threshold: a node counts as changed when its value
+                          drops by more than eps_rel*max(1,|T|); 0 -> 2^-20 */
+    int max_rounds;    /* cap on global relaxation rounds; 0 -> 64 + 8*n_v^(1/3)*... (library default) */
+    int reorder;       /* 0 -> default (locality reordering on), -1 -> keep caller order */
+    int reserved[5];   /* must be zero */
+} gbp_options;
+
+typedef struct {
+    int rounds;            /* global relaxation rounds executed */
+    int converged;         /* 1 when the change set emptied before max_rounds */
+    int64_t face_solves;   /* local problems evaluated */
+    int64_t node_updates;  /* node value decreases by more than the threshold */
+    int unreached;         /* nodes left at +inf (not connected to any root) */
+    int reserved[3];
+} gbp_stats;
+
+/*
+ * gbp_plan_create -- analyse a P1 tetrahedral mesh (Sec. 2.1: vertices V,
+ * elements E_j, patches omega_i of elements around each vertex).
+ *   xyz   host  float [n_v*3]  vertex coordinates
+ *   tets  host  int32 [n_e*4]  vertex ids of each element (0-based)
+ *   opt   host  may be NULL (defaults)
+ *   out   host  receives the plan; destroy with gbp_plan_destroy.
+ * Errors: GBP_ERR_ARG (sizes, ids out of range, repeated vertex in an element),
+ * GBP_ERR_NONFINITE (coordinates), GBP_ERR_DEGENERATE_TET (|volume| below
+ * 1e-7 of the cube of the element's longest edge), GBP_ERR_NOMEM, GBP_ERR_HIP.
+ * Uses the current HIP device; all later calls with this plan must run there.
+ */
+int gbp_plan_create(const float *xyz, int n_v, const int32_t *tets, int n_e,
+                    const gbp_options *opt, gbp_plan *out);
+void gbp_plan_destroy(gbp_plan plan);
+int gbp_plan_sizes(gbp_plan plan, int *n_v, int *n_e);
+
+/*
+ * gbp_eikonal_forward -- activation times phi at the vertices: the fixed point
+ * of the Hopf-Lax rule phi_i = min over elements E_j around v_i of the local
+ * minimum phi*_{j\i} = min_{x in face opposite v_i} phi(x) + ||v_i - x||
+ * (Sec. 2.1 Eq. (hopflax_global), Eq. (hopflax_local); solved on each face in
+ * barycentric form, Sec. 2.2 Eq. (upwind_eq_lsqr)), with phi = t_r at the roots
+ * (initial conditions X_0, Sec. 2.1).  Iterated to convergence as in Alg. 2.
+ *   D          device float [n_e*6]  velocity tensor per element (the paper's M,
+ *                                    units length^2/time^2); a step e inside E_j
+ *                                    costs sqrt(e^T D_eff^{-1} e)
+ *   vscale     device float [n_v] or NULL (all ones): nodal velocity scale; the
+ *                                    element uses D_eff = sbar^2 D with sbar the
+ *                                    mean of its four nodal scales
+ *   root_node  device int32 [n_roots]   vertex of each initial condition
+ *   root_t     device float [n_roots]   its onset time; duplicates take the min
+ *   T_init     device float [n_v] or NULL.  NULL: cold start from +inf.
+ *              Non-NULL: a guess; the solve then uses the two-sided update
+ *              (every node re-takes the minimum over its faces, roots also
+ *              min with their onset), which converges to the same fixed point
+ *              from any finite or infinite guess.
+ *   T_out      device float [n_v]  (may alias T_init)
+ *   stats      host, may be NULL
+ * Unreached vertices get +inf.  Errors: GBP_ERR_ARG (root id out of range,
+ * n_roots < 0), GBP_ERR_NONFINITE / GBP_ERR_NOT_SPD (D, vscale <= 0 or
+ * non-finite, non-finite onsets), GBP_ERR_NOT_CONVERGED (T_out still written).
+ */
+int gbp_eikonal_forward(gbp_plan plan, const float *D, const float *vscale,
+                        const int32_t *root_node, const float *root_t, int n_roots,
+                        const float *T_init, float *T_out, gbp_stats *stats, void *stream);
+
+/*
+ * gbp_eikonal_backward -- vector-Jacobian product of the forward solve
+ * (Sec. 2.3, Eq. (dto_grad)): with the geodesic parents frozen (the
+ * minimising element and barycentric weights alpha of each vertex, recomputed
+ * here from the converged T, never stored), L = sum_i dL_dT[i] T[i] has
+ *   dL/dt_r  = lambda at the root's vertex if root r is active (its onset is
+ *              not beaten by the upwind value, Sec. 2.5), else 0,
+ *   dL/dD_j  = sum over vertices i parented by E_j of
+ *              lambda_i * (-sbar_j^-2 D_j^-1 e e^T D_j^-1 / (2 h)),
+ *   dL/ds_n  = 1/4 sum_{j containing n} sum_i lambda_i * (-h / sbar_j),
+ * where e = sum_k alpha_k (v_k - v_i), h = sqrt(e^T D_eff,j^-1 e) and lambda
+ * solves lambda = dL_dT + P^T lambda (P: parent weights).
+ *   D, vscale, root_node, root_t, n_roots: as passed to the forward
+ *   T          device float [n_v]   converged forward output
+ *   dL_dT      device float [n_v]   incoming gradient (ignored at +inf nodes)
+ *   dL_dD      device float [n_e*6] or NULL   (off-diagonals doubled)
+ *   dL_dvscale device float [n_v]   or NULL
+ *   dL_droot_t device float [n_roots] or NULL
+ * Errors: as the forward; GBP_ERR_NOT_CONVERGED if the adjoint did not settle.
+ */
+int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
+                         const int32_t *root_node, const float *root_t, int n_roots,
+                         const float *T, const float *dL_dT, float *dL_dD,
+                         float *dL_dvscale, float *dL_droot_t, void *stream);
+
+/*
+ * gbp_parent_map -- the geodesic parents used by the backward pass, exposed
+ * for inspection: for every vertex the minimising element (Sec. 2.3: the
+ * element whose face carries the upwind point), the three face vertices and
+ * their barycentric weights alpha (zero off the support).
+ *   par_tet   device int32 [n_v]    element id (caller numbering), -1 for a
+ *                                   vertex that is its own parent (active root)
+ *                                   or unreached
+ *   par_node  device int32 [n_v*3]  face vertices (caller numbering), -1 if none
+ *   par_alpha device float [n_v*3]  weights
+ *   best      device float [n_v] or NULL: minimum upwind value per vertex
+ */
+int gbp_parent_map(gbp_plan plan, const float *D, const float *vscale,
+                   const int32_t *root_node, const float *root_t, int n_roots,
+                   const float *T, int32_t *par_tet, int32_t *par_node, float *par_alpha,
+                   float *best, void *stream);
+
+/* Action-potential template and time grid (Sec. 2.4 Eq. (tanh_waveform), read
+ * with K0 the resting and K1 the peak potential):
+ *   U(xi) = K0 + (K1 - K0) / (1 + exp(-4 xi / tau)),  t_s = t0 + s*dt, s < n_steps. */
+typedef struct {
+    float K0, K1, tau, t0, dt;
+    int n_steps;
+} gbp_ap;
+
+/*
+ * gbp_ecg_forward -- lead-field ECG (Sec. 2.4): ecg[s*L + l] =
+ *   sum_n W[n*L + l] * U(t_s - T[n]).  W is the discretised lead-field operator
+ *   B (one column per lead).  Vertices with T = +inf stay at rest (U = K0).
+ *   T   device float [n_v];  W device float [n_v*L];  ecg device float [n_steps*L]
+ *   1 <= L <= 16.
+ */
+int gbp_ecg_forward(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
+                    float *ecg, void *stream);
+
+/*
+ * gbp_ecg_backward -- dL_dT[n] = -sum_s U'(t_s - T[n]) sum_l dL_decg[s*L+l] W[n*L+l]
+ * (Sec. 2.4: the gradient of V_l is -B^T U' times the gradient of phi).
+ *   dL_decg device float [n_steps*L];  dL_dT device float [n_v] (overwritten)
+ */
+int gbp_ecg_backward(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
+                     const float *dL_decg, float *dL_dT, void *stream);
+
+/*
+ * gbp_ecg_loss -- objective of Sec. 2.4 Eq. (inverse_ecg) with the time
+ * integral as a rectangle rule: loss = sum (ecg - target)^2 / n and
+ * dL_decg = 2 (ecg - target) / n, n = number of entries.
+ *   ecg, target device float [n];  loss device float [1];  dL_decg device [n] or NULL
+ */
+int gbp_ecg_loss(const float *ecg, const float *target, int n, float *loss, float *dL_decg,
+                 void *stream);
+
+/*
+ * gbp_adam_step -- one Adam update (the optimiser of Sec. 2.4) on n parameters:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * All arrays device float [n]; step >= 1.  Optional bounds: if lo < hi the
+ * result is clamped to [lo, hi].
+ */
+int gbp_adam_step(float *param, const float *grad, float *m, float *v, int n, float lr,
+                  float beta1, float beta2, float eps, int step, float lo, float hi,
+                  void *stream);
+
+const char *gbp_last_error(void);
+const char *gbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBP_H */

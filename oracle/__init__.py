@@ -222,17 +222,12 @@ def parent_matrix(par, n_v):
     """P[c, k] = alpha^c_k: the weights of node c's value on its parents
     (Eq. (dto_grad): the gradient of a node value is the alpha-weighted sum of
     the gradients of the face values it was computed from)."""
-    rows, cols, vals = [], [], []
-    for c in range(n_v):
-        if par["par_tet"][c] < 0:
-            continue
-        for k in range(3):
-            a = par["par_alpha"][c, k]
-            if a > 0:
-                rows.append(c)
-                cols.append(par["par_node"][c, k])
-                vals.append(a)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(n_v, n_v))
+    c = np.nonzero(par["par_tet"] >= 0)[0]
+    rows = np.repeat(c, 3)
+    cols = par["par_node"][c].reshape(-1)
+    vals = par["par_alpha"][c].reshape(-1)
+    keep = vals > 0
+    return sp.csr_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n_v, n_v))
 
 
 def adjoint(xyz, tets, D6, vscale, root_node, root_t, T, g, par=None):
@@ -269,17 +264,16 @@ def adjoint(xyz, tets, D6, vscale, root_node, root_t, T, g, par=None):
     Minv3 = unpack_sym(Minv)
     dD = np.zeros((len(tets), 3, 3))
     dsbar = np.zeros(len(tets))
-    for i in range(n_v):
-        j = par["par_tet"][i]
-        if j < 0 or lam[i] == 0.0:
-            continue
-        e = np.zeros(3)
-        for k in range(3):
-            e += par["par_alpha"][i, k] * (x[par["par_node"][i, k]] - x[i])
-        hh = np.sqrt(e @ Minv3[j] @ e)
-        u = Dinv[j] @ e
-        dD[j] += lam[i] * (-(np.outer(u, u)) / (sbar[j] ** 2 * 2.0 * hh))
-        dsbar[j] += lam[i] * (-hh / sbar[j])
+    i = np.nonzero((par["par_tet"] >= 0) & (lam != 0.0))[0]
+    j = par["par_tet"][i]
+    e = np.zeros((len(i), 3))
+    for k in range(3):
+        e += par["par_alpha"][i, k][:, None] * (x[par["par_node"][i, k]] - x[i])
+    hh = np.sqrt(np.einsum("ni,nij,nj->n", e, Minv3[j], e))
+    u = np.einsum("nij,nj->ni", Dinv[j], e)
+    coef = lam[i] / (sbar[j] ** 2 * 2.0 * hh)
+    np.add.at(dD, j, -coef[:, None, None] * u[:, :, None] * u[:, None, :])
+    np.add.at(dsbar, j, lam[i] * (-hh / sbar[j]))
     dvs = np.zeros(n_v)
     np.add.at(dvs, tets.reshape(-1), np.repeat(dsbar / 4.0, 4))
     dD6 = pack_sym(dD)

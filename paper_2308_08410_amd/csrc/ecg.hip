@@ -1,0 +1,386 @@
+// Lead-field ECG (Sec. 2.4) and its backward pass on gfx950 matrix cores.
+//
+//   ecg[s,l] = sum_n W[n,l] U(t_s - T_n),   U(xi) = K0 + (K1-K0) sigma(4 xi / tau)
+//
+// The template saturates: for |4 xi / tau| >= 24, sigma equals 1 to FP32
+// precision on the upper side (1 - sigma < 4e-11) and is below 4e-11 on the lower
+// side.  A wavefront owns 64 consecutive vertices; their finite activation times
+// span [Tmin, Tmax], so for t_s < Tmin - 6 tau every term is at rest and for
+// t_s > Tmax + 6 tau every term is at K1.  Only the window in between needs the
+// template; there the contraction (time x vertices) . (vertices x leads) runs on
+// MFMA 16x16x16 bf16 tiles whose A operand is generated in registers from T.
+// Both operands are split into bf16 hi + lo parts (three products, FP32
+// accumulation), since the lead weights sum to ~0 and the ECG is a cancellation.
+// The saturated part is a step function: the window's weight sum is added once at
+// the first saturated step and prefix-summed over time at the end.
+//
+// Backward:  dT_n = -sum_s U'(t_s - T_n) sum_l G[s,l] W[n,l], with U' zero outside
+// the same window; R = U' G runs on MFMA (vertices x time) . (time x leads) and the
+// row-wise dot with W finishes in registers.  No atomics: deterministic.
+#include <math.h>
+#include <mutex>
+
+#include "gbp_internal.h"
+
+namespace {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr float kSat = 24.f;          // |4 xi / tau| beyond which sigma is saturated
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr int kMaxSteps = 992;      // keeps the LDS of both kernels within 64 KB
+
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
+    const unsigned h = bf16_rne(x);
+    hi = (short)h;
+    lo = (short)bf16_rne(x - __uint_as_float(h << 16));
+}
+
+__device__ __forceinline__ floatx4 mfma3(bf16x4_t ah, bf16x4_t al, bf16x4_t bh, bf16x4_t bl,
+                                         floatx4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    return acc;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+struct ApDev {
+    float K0, amp, c4, dudx, t0, dt, halfw;  // c4 = 4 log2(e)/tau, dudx = amp*4/tau, halfw = 6 tau
+    int S;
+};
+
+// window [s_lo, s_hi) of a wave's finite activation times; empty if none finite
+__device__ __forceinline__ void wave_window(float Tv, const ApDev& ap, int& s_lo, int& s_hi,
+                                            bool& any) {
+    const bool fin = Tv < __builtin_huge_valf();
+    const float tmin = wave_min(fin ? Tv : __builtin_huge_valf());
+    const float tmax = wave_max(fin ? Tv : -__builtin_huge_valf());
+    any = tmin < __builtin_huge_valf();
+    if (!any) {
+        s_lo = s_hi = ap.S;
+        return;
+    }
+    const float lo = ceilf((tmin - ap.halfw - ap.t0) / ap.dt);
+    const float hi = floorf((tmax + ap.halfw - ap.t0) / ap.dt) + 1.f;
+    s_lo = (int)fminf(fmaxf(lo, 0.f), (float)ap.S);
+    s_hi = (int)fminf(fmaxf(hi, 0.f), (float)ap.S);
+    if (s_hi < s_lo) s_hi = s_lo;
+}
+
+// ------------------------------------------------------------------ forward
+// Block: 4 waves; each wave takes 64-vertex groups of the block's range.
+// Dynamic LDS: win[S_pad*16] floats.  The step histogram goes to global memory
+// directly (one 16-wide add per 64-vertex group).
+__global__ void __launch_bounds__(256)
+    k_ecg_fwd(const float* __restrict__ T, const float* __restrict__ W, int n_v, int L,
+              ApDev ap, int S_pad, int groups_per_block, float* __restrict__ g_win,
+              float* __restrict__ g_hist, float* __restrict__ g_wsum) {
+    extern __shared__ float win[];
+    __shared__ int blo, bhi;
+    __shared__ float wsum_sh[4][16];
+    for (int x = threadIdx.x; x < S_pad * 16; x += blockDim.x) win[x] = 0.f;
+    if (threadIdx.x == 0) {
+        blo = ap.S;
+        bhi = 0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    float wsum_all = 0.f;   // lane: lead col, vertices 4kq+r of each K-step
+    for (int gi = wave; gi < groups_per_block; gi += 4) {
+        const int g0 = (blockIdx.x * groups_per_block + gi) * 64;
+        if (g0 >= n_v) break;
+        const int nl = g0 + lane;
+        const float Tl = nl < n_v ? T[nl] : __builtin_huge_valf();
+        int s_lo, s_hi;
+        bool any;
+        wave_window(Tl, ap, s_lo, s_hi, any);
+        float wsum_fin = 0.f;
+        // W fragments and sums (4 K-steps of 16 vertices)
+        for (int ks = 0; ks < 4; ++ks) {
+            for (int r = 0; r < 4; ++r) {
+                const int n = g0 + ks * 16 + kq * 4 + r;
+                const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
+                const float t = n < n_v ? T[n] : __builtin_huge_valf();
+                wsum_all += w;
+                if (t < __builtin_huge_valf()) wsum_fin += w;
+            }
+        }
+        if (!any) continue;
+        // window contraction, up to 4 time tiles per pass
+        for (int s0 = s_lo; s0 < s_hi; s0 += 64) {
+            floatx4 acc[4];
+            for (int m = 0; m < 4; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int ntile = min(4, (s_hi - s0 + 15) / 16);
+            for (int ks = 0; ks < 4; ++ks) {
+                float tv[4];
+                bf16x4_t bh, bl;
+                for (int r = 0; r < 4; ++r) {
+                    const int n = g0 + ks * 16 + kq * 4 + r;
+                    const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
+                    tv[r] = n < n_v ? T[n] : __builtin_huge_valf();
+                    short h, l;
+                    split_bf16(w, h, l);
+                    bh[r] = h;
+                    bl[r] = l;
+                }
+                for (int m = 0; m < 4; ++m) {
+                    if (m >= ntile) break;
+                    const float t = ap.t0 + (float)(s0 + 16 * m + col) * ap.dt;
+                    bf16x4_t ah, al;
+                    for (int r = 0; r < 4; ++r) {
+                        const float e = __builtin_amdgcn_exp2f((tv[r] - t) * ap.c4);
+                        const float a = ap.amp * __builtin_amdgcn_rcpf(1.f + e);
+                        short h, l;
+                        split_bf16(a, h, l);
+                        ah[r] = h;
+                        al[r] = l;
+                    }
+                    acc[m] = mfma3(ah, al, bh, bl, acc[m]);
+                }
+            }
+            for (int m = 0; m < ntile; ++m)
+                for (int r = 0; r < 4; ++r) {
+                    const int s = s0 + 16 * m + kq * 4 + r;
+                    if (s < s_hi && col < L) atomicAdd(&win[s * 16 + col], acc[m][r]);
+                }
+        }
+        // saturated part: step at s_hi
+        float hsum = wsum_fin;
+        hsum += __shfl_xor(hsum, 16);
+        hsum += __shfl_xor(hsum, 32);
+        if (s_hi < ap.S && kq == 0 && col < L) atomicAdd(&g_hist[s_hi * 16 + col], ap.amp * hsum);
+        if (lane == 0) {
+            atomicMin(&blo, s_lo);
+            atomicMax(&bhi, s_hi);
+        }
+    }
+    wsum_all += __shfl_xor(wsum_all, 16);
+    wsum_all += __shfl_xor(wsum_all, 32);
+    if (kq == 0) wsum_sh[wave][col] = wsum_all;
+    __syncthreads();
+    if (threadIdx.x < 16 && threadIdx.x < L) {
+        const float v = wsum_sh[0][threadIdx.x] + wsum_sh[1][threadIdx.x] +
+                        wsum_sh[2][threadIdx.x] + wsum_sh[3][threadIdx.x];
+        atomicAdd(&g_wsum[threadIdx.x], v);
+    }
+    const int lo = blo, hi = min(bhi, ap.S);
+    for (int x = lo * 16 + threadIdx.x; x < hi * 16; x += blockDim.x) {
+        if ((x & 15) >= L) continue;
+        const float a = win[x];
+        if (a != 0.f) atomicAdd(&g_win[x], a);
+    }
+}
+
+__global__ void k_ecg_zero(float* __restrict__ p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+// ecg[s,l] = K0 * sum W + prefix_s(hist) + win
+__global__ void k_ecg_finish(const float* __restrict__ g_win, const float* __restrict__ g_hist,
+                             const float* __restrict__ g_wsum, int S, int L, float K0,
+                             float* __restrict__ ecg) {
+    // one thread per lead does the running sum (S <= 2048, L <= 16)
+    const int l = threadIdx.x;
+    if (l >= L) return;
+    const float base = K0 * g_wsum[l];
+    float run = 0.f;
+    for (int s = 0; s < S; ++s) {
+        run += g_hist[s * 16 + l];
+        ecg[(size_t)s * L + l] = base + run + g_win[s * 16 + l];
+    }
+}
+
+// ------------------------------------------------------------------ backward
+__global__ void __launch_bounds__(256)
+    k_ecg_bwd(const float* __restrict__ T, const float* __restrict__ W,
+              const float* __restrict__ G, int n_v, int L, ApDev ap, int S_pad,
+              float* __restrict__ dT) {
+    extern __shared__ short gl[];  // [S_pad*16] hi, then [S_pad*16] lo
+    short* gh = gl;
+    short* glo = gl + S_pad * 16;
+    for (int x = threadIdx.x; x < S_pad * 16; x += blockDim.x) {
+        const int s = x >> 4, l = x & 15;
+        const float v = (s < ap.S && l < L) ? G[(size_t)s * L + l] : 0.f;
+        short h, lo;
+        split_bf16(v, h, lo);
+        gh[x] = h;
+        glo[x] = lo;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, kq = lane >> 4;
+    const int nwaves = gridDim.x * 4;
+    for (int grp = blockIdx.x * 4 + wave; grp * 64 < n_v; grp += nwaves) {
+        const int g0 = grp * 64;
+        const int nl = g0 + lane;
+        const float Tl = nl < n_v ? T[nl] : __builtin_huge_valf();
+        int s_lo, s_hi;
+        bool any;
+        wave_window(Tl, ap, s_lo, s_hi, any);
+        // 4 vertex tiles of 16
+        for (int mt = 0; mt < 4; ++mt) {
+            const int nrow = g0 + mt * 16 + col;   // A row: vertex
+            const float tn = nrow < n_v ? T[nrow] : __builtin_huge_valf();
+            floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (any) {
+                for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
+                    bf16x4_t ah, al, bh, bl;
+                    for (int r = 0; r < 4; ++r) {
+                        const int s = s0 + kq * 4 + r;
+                        const float t = ap.t0 + (float)s * ap.dt;
+                        const float e = __builtin_amdgcn_exp2f((tn - t) * ap.c4);
+                        const float q = __builtin_amdgcn_rcpf(1.f + e);
+                        const float omq = e < 1.f ? e * q : 1.f - q;
+                        const float a = (s < ap.S) ? ap.dudx * q * omq : 0.f;
+                        short h, l;
+                        split_bf16(a, h, l);
+                        ah[r] = h;
+                        al[r] = l;
+                        const int sc = s < S_pad ? s : S_pad - 1;
+                        bh[r] = (s < ap.S) ? gh[sc * 16 + col] : (short)0;
+                        bl[r] = (s < ap.S) ? glo[sc * 16 + col] : (short)0;
+                    }
+                    acc = mfma3(ah, al, bh, bl, acc);
+                }
+            }
+            // acc[r]: R[vertex g0+mt*16+kq*4+r][lead col]
+            float out[4];
+            for (int r = 0; r < 4; ++r) {
+                const int n = g0 + mt * 16 + kq * 4 + r;
+                const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
+                float v = acc[r] * w;
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
+                out[r] = v;
+            }
+            if (col == 0)
+                for (int r = 0; r < 4; ++r) {
+                    const int n = g0 + mt * 16 + kq * 4 + r;
+                    if (n < n_v) dT[n] = -out[r];
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ workspace
+struct EcgWork {
+    float* buf = nullptr;
+    size_t cap = 0;
+};
+std::mutex g_mu;
+EcgWork g_work[64];
+
+int ecg_workspace(size_t nfloat, float** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        gbp_set_error("no HIP device");
+        return GBP_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    EcgWork& w = g_work[dev];
+    if (w.cap < nfloat) {
+        if (w.buf) (void)hipFree(w.buf);
+        w.buf = nullptr;
+        w.cap = 0;
+        if (hipMalloc((void**)&w.buf, nfloat * sizeof(float)) != hipSuccess) {
+            gbp_set_error("ECG workspace allocation failed");
+            return GBP_ERR_NOMEM;
+        }
+        w.cap = nfloat;
+    }
+    *out = w.buf;
+    return GBP_OK;
+}
+
+int check_ap(const float* T, int n_v, const float* W, int L, const gbp_ap* ap) {
+    if (!T || !W || !ap || n_v <= 0 || L < 1 || L > 16) {
+        gbp_set_error("ECG: need T, W, ap, n_v > 0 and 1 <= L <= 16 (L=%d)", L);
+        return GBP_ERR_ARG;
+    }
+    if (ap->n_steps < 1 || ap->n_steps > kMaxSteps || !(ap->dt > 0.f) || !(ap->tau > 0.f) ||
+        !std::isfinite(ap->K0) || !std::isfinite(ap->K1) || !std::isfinite(ap->t0)) {
+        gbp_set_error("ECG: bad template/time grid (n_steps in [1,%d], dt > 0, tau > 0)", kMaxSteps);
+        return GBP_ERR_ARG;
+    }
+    return GBP_OK;
+}
+
+ApDev make_ap(const gbp_ap* a) {
+    ApDev d;
+    d.K0 = a->K0;
+    d.amp = a->K1 - a->K0;
+    d.c4 = 4.f * kLog2e / a->tau;
+    d.dudx = (a->K1 - a->K0) * 4.f / a->tau;
+    d.t0 = a->t0;
+    d.dt = a->dt;
+    d.halfw = kSat * a->tau / 4.f;
+    d.S = a->n_steps;
+    return d;
+}
+
+}  // namespace
+
+extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, const gbp_ap* ap,
+                               float* ecg, void* stream) {
+    int rc = check_ap(T, n_v, W, L, ap);
+    if (rc) return rc;
+    if (!ecg) {
+        gbp_set_error("ecg is NULL");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const ApDev d = make_ap(ap);
+    const int S_pad = (d.S + 15) / 16 * 16 + 16;
+    float* work;
+    if ((rc = ecg_workspace((size_t)2 * S_pad * 16 + 16, &work))) return rc;
+    float* g_win = work;
+    float* g_hist = work + S_pad * 16;
+    float* g_wsum = work + 2 * S_pad * 16;
+    k_ecg_zero<<<64, 256, 0, s>>>(work, 2 * S_pad * 16 + 16);
+    const int groups = (n_v + 63) / 64;
+    const int gpb = 16;   // 64-vertex groups per block (4 per wave)
+    const int blocks = (groups + gpb - 1) / gpb;
+    const size_t lds = (size_t)S_pad * 16 * sizeof(float);
+    k_ecg_fwd<<<blocks, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, g_win, g_hist, g_wsum);
+    k_ecg_finish<<<1, 64, 0, s>>>(g_win, g_hist, g_wsum, d.S, L, d.K0, ecg);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_ecg_backward(const float* T, int n_v, const float* W, int L, const gbp_ap* ap,
+                                const float* dL_decg, float* dL_dT, void* stream) {
+    int rc = check_ap(T, n_v, W, L, ap);
+    if (rc) return rc;
+    if (!dL_decg || !dL_dT) {
+        gbp_set_error("dL_decg and dL_dT are required");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const ApDev d = make_ap(ap);
+    const int S_pad = (d.S + 15) / 16 * 16 + 16;
+    const int groups = (n_v + 63) / 64;
+    const int blocks = std::min((groups + 3) / 4, 2048);
+    const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
+    k_ecg_bwd<<<blocks, 256, lds, s>>>(T, W, dL_decg, n_v, L, d, S_pad, dL_dT);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}

@@ -1,0 +1,849 @@
+// Eikonal forward (Alg. 2 as an active-list relaxation) and its adjoint
+// (Sec. 2.3: back-propagation along the frozen geodesic parents) for gfx950.
+//
+// Forward.  Each sweep processes a work queue of vertices; a vertex takes the
+// minimum over the local problems of its patch (Eq. (hopflax_global)), every
+// local problem solved in closed form (local_solve.h).  A vertex whose value
+// drops by more than eps_rel*max(1,|T|) pushes its unique neighbours into the
+// next queue (deduplicated with per-vertex stamps).  This is the change mask of
+// Alg. 2 applied at vertex granularity; updates are in place (chaotic
+// relaxation), which reaches the same fixed point because every value read is an
+// upper bound of the solution and the update is monotone.
+//
+// Adjoint.  lambda = g + P^T lambda with P the parent weights.  The parent graph
+// is walked leaves-first in levels (Kahn order): a vertex is finished once all of
+// its children are, and then pulls their contributions in a fixed order, so the
+// result is deterministic.  Vertices left over by a cycle in the (non-causal)
+// anisotropic parent graph are finished with Jacobi sweeps.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "gbp_internal.h"
+#include "local_solve.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ bool finitef(float x) { return x == x && fabsf(x) < GBP_INF; }
+
+// ------------------------------------------------------------------ preparation
+__global__ void k_vscale_in(const float* __restrict__ vs_user, const int* __restrict__ node_user,
+                            float* __restrict__ vs, int n_v, GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    float s = 1.f;
+    if (vs_user) {
+        s = vs_user[node_user[i]];
+        if (!(s > 0.f) || !finitef(s)) {
+            atomicOr(&ctl->err, ERRBIT_VSCALE);
+            s = 1.f;
+        }
+    }
+    vs[i] = s;
+}
+
+// Per element: M = D_eff^{-1} = D^{-1} / sbar^2 and G = F^T M F (F: edges from v0).
+__global__ void k_metric(const float* __restrict__ D, const int* __restrict__ tet_user,
+                         const int4* __restrict__ tetv, const float4* __restrict__ xyz,
+                         const float* __restrict__ vs, float4* __restrict__ tetg, int n_e,
+                         GbpCtl* ctl) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_e) return;
+    const int u = tet_user[j];
+    const float2* d2 = reinterpret_cast<const float2*>(D + 6 * (size_t)u);
+    const float2 da = d2[0], db = d2[1], dc = d2[2];
+    const float a = da.x, b = da.y, c = db.x, d = db.y, e = dc.x, f = dc.y;  // xx yy zz xy xz yz
+    const int4 v = tetv[j];
+    const float sbar = 0.25f * (vs[v.x] + vs[v.y] + vs[v.z] + vs[v.w]);
+    const float A00 = b * c - f * f, A11 = a * c - e * e, A22 = a * b - d * d;
+    const float A01 = e * f - d * c, A02 = d * f - e * b, A12 = d * e - a * f;
+    const float det = a * A00 + d * A01 + e * A02;
+    const bool fin = finitef(a) && finitef(b) && finitef(c) && finitef(d) && finitef(e) && finitef(f);
+    if (!fin) atomicOr(&ctl->err, ERRBIT_D_NONFINITE);
+    else if (!(a > 0.f && A22 > 0.f && det > 0.f)) atomicOr(&ctl->err, ERRBIT_D_NOT_SPD);
+    const float s = 1.f / (det * sbar * sbar);
+    const float m00 = A00 * s, m11 = A11 * s, m22 = A22 * s, m01 = A01 * s, m02 = A02 * s, m12 = A12 * s;
+    const float4 x0 = xyz[v.x], x1 = xyz[v.y], x2 = xyz[v.z], x3 = xyz[v.w];
+    const float F1x = x1.x - x0.x, F1y = x1.y - x0.y, F1z = x1.z - x0.z;
+    const float F2x = x2.x - x0.x, F2y = x2.y - x0.y, F2z = x2.z - x0.z;
+    const float F3x = x3.x - x0.x, F3y = x3.y - x0.y, F3z = x3.z - x0.z;
+    // M F_a
+    const float M1x = m00 * F1x + m01 * F1y + m02 * F1z, M1y = m01 * F1x + m11 * F1y + m12 * F1z,
+                M1z = m02 * F1x + m12 * F1y + m22 * F1z;
+    const float M2x = m00 * F2x + m01 * F2y + m02 * F2z, M2y = m01 * F2x + m11 * F2y + m12 * F2z,
+                M2z = m02 * F2x + m12 * F2y + m22 * F2z;
+    const float M3x = m00 * F3x + m01 * F3y + m02 * F3z, M3y = m01 * F3x + m11 * F3y + m12 * F3z,
+                M3z = m02 * F3x + m12 * F3y + m22 * F3z;
+    const float G11 = F1x * M1x + F1y * M1y + F1z * M1z;
+    const float G22 = F2x * M2x + F2y * M2y + F2z * M2z;
+    const float G33 = F3x * M3x + F3y * M3y + F3z * M3z;
+    const float G12 = F1x * M2x + F1y * M2y + F1z * M2z;
+    const float G13 = F1x * M3x + F1y * M3y + F1z * M3z;
+    const float G23 = F2x * M3x + F2y * M3y + F2z * M3z;
+    tetg[2 * (size_t)j] = make_float4(G11, G22, G33, G12);
+    tetg[2 * (size_t)j + 1] = make_float4(G13, G23, sbar, 0.f);
+}
+
+__global__ void k_fill(float* __restrict__ x, float v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ void k_gather_in(const float* __restrict__ src_user, const int* __restrict__ node_user,
+                            float* __restrict__ dst, int n_v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    float x = src_user[node_user[i]];
+    if (x != x) x = GBP_INF;
+    dst[i] = x;
+}
+
+__global__ void k_scatter_out(const float* __restrict__ src, const int* __restrict__ node_int,
+                              float* __restrict__ dst_user, int n_v) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n_v) dst_user[u] = src[node_int[u]];
+}
+
+// Roots: sequential min (deterministic for duplicates), then (cold start) push
+// the neighbours of every root into the first queue.
+__global__ void k_roots(const int* __restrict__ root_node, const float* __restrict__ root_t,
+                        int n_roots, const int* __restrict__ node_int, int n_v,
+                        float* __restrict__ troot, float* __restrict__ T, int cold,
+                        const int* __restrict__ adj_ptr, const int* __restrict__ adj,
+                        int* __restrict__ qout, int* __restrict__ mark, int stamp, GbpCtl* ctl) {
+    if (threadIdx.x == 0) {
+        for (int r = 0; r < n_roots; ++r) {
+            const int u = root_node[r];
+            const float t = root_t[r];
+            if (u < 0 || u >= n_v) {
+                atomicOr(&ctl->err, ERRBIT_ROOT_RANGE);
+                continue;
+            }
+            if (!finitef(t)) {
+                atomicOr(&ctl->err, ERRBIT_ROOT_NONFINITE);
+                continue;
+            }
+            const int i = node_int[u];
+            troot[i] = fminf(troot[i], t);
+            if (cold) T[i] = fminf(T[i], t);
+        }
+    }
+    __syncthreads();
+    if (!cold) return;
+    for (int r = threadIdx.x; r < n_roots; r += blockDim.x) {
+        const int u = root_node[r];
+        if (u < 0 || u >= n_v) continue;
+        const int i = node_int[u];
+        for (int a = adj_ptr[i]; a < adj_ptr[i + 1]; ++a) {
+            const int nb = adj[a];
+            if (atomicMax(&mark[nb], stamp) < stamp) {
+                const int pos = atomicAdd(&ctl->count[0], 1);
+                qout[pos] = nb;
+            }
+        }
+    }
+}
+
+__global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int stamp, int n_v,
+                            GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ctl->count[0] = n_v;
+    if (i < n_v) {
+        q[i] = i;
+        mark[i] = stamp;
+    }
+}
+
+// ------------------------------------------------------------------ relaxation
+template <int K>
+__device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restrict__ nent,
+                                           const int4* __restrict__ tetv,
+                                           const float4* __restrict__ tetg, const float* T,
+                                           float& best) {
+    for (int c = 0; c < cnt; ++c) {
+        const int t = nent[e + c];
+        const int4 v = tetv[t];
+        const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
+        int a, b, cc;
+        face_nodes<K>(v, a, b, cc);
+        const float pa = T[a], pb = T[b], pc = T[cc];
+        best = fminf(best, local_min<false>(face_q<K>(g0, g1), pa, pb, pc));
+    }
+    e += cnt;
+}
+
+template <bool TWO_SIDED>
+__global__ void __launch_bounds__(TPB)
+    k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
+            const int4* __restrict__ tetv, const float4* __restrict__ tetg,
+            const float* __restrict__ troot, float* T, const int* __restrict__ qin,
+            int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
+            int* __restrict__ mark, GbpCtl* ctl, int s, int stamp_next, float eps_rel) {
+    const int n = ctl->count[s % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(s + 2) % 3] = 0;
+        if (n > 0) atomicMax(&ctl->pad[0], s + 1);
+    }
+    int* cnt_next = &ctl->count[(s + 1) % 3];
+    unsigned long long solves = 0, upd = 0;
+    for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
+        const int i = qin[qi];
+        const float told = T[i];
+        float best = TWO_SIDED ? troot[i] : told;
+        const int2 p = nptr[i];
+        int e = p.x;
+        relax_slot<0>(e, p.y & 255, nent, tetv, tetg, T, best);
+        relax_slot<1>(e, (p.y >> 8) & 255, nent, tetv, tetg, T, best);
+        relax_slot<2>(e, (p.y >> 16) & 255, nent, tetv, tetg, T, best);
+        relax_slot<3>(e, (p.y >> 24) & 255, nent, tetv, tetg, T, best);
+        solves += (unsigned)(e - p.x);
+        bool changed;
+        if (TWO_SIDED) {
+            if (best != told) T[i] = best;
+            const bool bf = best < GBP_INF, tf = told < GBP_INF;
+            changed = (bf != tf) ||
+                      (bf && fabsf(best - told) > eps_rel * fmaxf(1.f, fabsf(told)));
+        } else {
+            if (best < told) T[i] = best;
+            changed = (told < GBP_INF) ? (best < told - eps_rel * fmaxf(1.f, fabsf(told)))
+                                       : (best < GBP_INF);
+        }
+        if (changed) {
+            ++upd;
+            const int a1 = adj_ptr[i + 1];
+            for (int a = adj_ptr[i]; a < a1; ++a) {
+                const int nb = adj[a];
+                if (atomicMax(&mark[nb], stamp_next) < stamp_next) {
+                    const int pos = atomicAdd(cnt_next, 1);
+                    qout[pos] = nb;
+                }
+            }
+        }
+    }
+    if (solves) atomicAdd(&ctl->solves, solves);
+    if (upd) atomicAdd(&ctl->updates, upd);
+}
+
+__global__ void k_count_inf(const float* __restrict__ T, int n_v, GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = (i < n_v && !(T[i] < GBP_INF)) ? 1 : 0;
+    if (c) atomicAdd(&ctl->unreached, 1);
+}
+
+// ------------------------------------------------------------------ parents
+template <int K>
+__device__ __forceinline__ void parent_slot(int& e, int cnt, const int* __restrict__ nent,
+                                            const int4* __restrict__ tetv,
+                                            const float4* __restrict__ tetg,
+                                            const float* __restrict__ T, float& best, int& bpar,
+                                            float& b0, float& b1, float& b2) {
+    for (int c = 0; c < cnt; ++c) {
+        const int t = nent[e + c];
+        const int4 v = tetv[t];
+        const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
+        int a, b, cc;
+        face_nodes<K>(v, a, b, cc);
+        float a0, a1, a2;
+        const float val = local_min<true>(face_q<K>(g0, g1), T[a], T[b], T[cc], &a0, &a1, &a2);
+        if (val < best) {
+            best = val;
+            bpar = (t << 2) | K;
+            b0 = a0;
+            b1 = a1;
+            b2 = a2;
+        }
+    }
+    e += cnt;
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_parent(const int2* __restrict__ nptr, const int* __restrict__ nent,
+             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
+             const float* __restrict__ T, const float* __restrict__ troot, int n_v,
+             int* __restrict__ par, float4* __restrict__ pa) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    float best = GBP_INF, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    int bpar = -1;
+    if (T[i] < GBP_INF) {
+        const int2 p = nptr[i];
+        int e = p.x;
+        parent_slot<0>(e, p.y & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
+        parent_slot<1>(e, (p.y >> 8) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
+        parent_slot<2>(e, (p.y >> 16) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
+        parent_slot<3>(e, (p.y >> 24) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
+        if (troot[i] <= best) bpar = -1;
+    }
+    par[i] = bpar;
+    pa[i] = make_float4(b0, b1, b2, best);
+}
+
+__device__ __forceinline__ void face_nodes_rt(const int4 v, int K, int& a, int& b, int& c) {
+    switch (K) {
+        case 0: a = v.y; b = v.z; c = v.w; break;
+        case 1: a = v.x; b = v.z; c = v.w; break;
+        case 2: a = v.x; b = v.y; c = v.w; break;
+        default: a = v.x; b = v.y; c = v.z; break;
+    }
+}
+
+__device__ __forceinline__ int face_target_rt(const int4 v, int K) {
+    return K == 0 ? v.x : K == 1 ? v.y : K == 2 ? v.z : v.w;
+}
+
+// ------------------------------------------------------------------ adjoint
+__global__ void k_child_count(const int* __restrict__ par, const float4* __restrict__ pa,
+                              const int4* __restrict__ tetv, int n_v, int* __restrict__ cnt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_v) return;
+    const int pr = par[c];
+    if (pr < 0) return;
+    int f[3];
+    face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+    const float4 w = pa[c];
+    const float al[3] = {w.x, w.y, w.z};
+    for (int k = 0; k < 3; ++k)
+        if (al[k] > 0.f) atomicAdd(&cnt[f[k]], 1);
+}
+
+__global__ void k_child_fill(const int* __restrict__ par, const float4* __restrict__ pa,
+                             const int4* __restrict__ tetv, int n_v, const int* __restrict__ cptr,
+                             int* __restrict__ cfill, int* __restrict__ cchild,
+                             float* __restrict__ calpha) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_v) return;
+    const int pr = par[c];
+    if (pr < 0) return;
+    int f[3];
+    face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+    const float4 w = pa[c];
+    const float al[3] = {w.x, w.y, w.z};
+    for (int k = 0; k < 3; ++k)
+        if (al[k] > 0.f) {
+            const int pos = cptr[f[k]] + atomicAdd(&cfill[f[k]], 1);
+            cchild[pos] = c;
+            calpha[pos] = al[k];
+        }
+}
+
+// Sort each child list by child id (fixed summation order -> deterministic).
+__global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cchild,
+                             float* __restrict__ calpha, int n_v) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_v) return;
+    const int b = cptr[p], e = cptr[p + 1];
+    for (int x = b + 1; x < e; ++x) {
+        const int kc = cchild[x];
+        const float ka = calpha[x];
+        int y = x - 1;
+        while (y >= b && cchild[y] > kc) {
+            cchild[y + 1] = cchild[y];
+            calpha[y + 1] = calpha[y];
+            --y;
+        }
+        cchild[y + 1] = kc;
+        calpha[y + 1] = ka;
+    }
+}
+
+__global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __restrict__ node_user,
+                           const float* __restrict__ T, const int* __restrict__ rem, int n_v,
+                           float* __restrict__ g, float* __restrict__ lam, int* __restrict__ done,
+                           int* __restrict__ q, GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    const bool reached = T[i] < GBP_INF;
+    float gi = reached ? dLdT_user[node_user[i]] : 0.f;
+    if (gi != gi) gi = 0.f;
+    g[i] = gi;
+    lam[i] = gi;
+    done[i] = reached ? 0 : 1;
+    if (reached && rem[i] == 0) {
+        const int pos = atomicAdd(&ctl->count[0], 1);
+        q[pos] = i;
+    }
+}
+
+__global__ void __launch_bounds__(TPB)
+    k_adj_level(const int* __restrict__ qin, int* __restrict__ qout, const int* __restrict__ cptr,
+                const int* __restrict__ cchild, const float* __restrict__ calpha,
+                const float* __restrict__ g, float* lam, int* __restrict__ done,
+                const int* __restrict__ par, const float4* __restrict__ pa,
+                const int4* __restrict__ tetv, int* __restrict__ rem, GbpCtl* ctl, int s) {
+    const int n = ctl->count[s % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(s + 2) % 3] = 0;
+        if (n > 0) atomicMax(&ctl->pad[0], s + 1);
+    }
+    int* cnt_next = &ctl->count[(s + 1) % 3];
+    for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
+        const int c = qin[qi];
+        float l = g[c];
+        for (int x = cptr[c]; x < cptr[c + 1]; ++x) l += calpha[x] * lam[cchild[x]];
+        lam[c] = l;
+        done[c] = 1;
+        const int pr = par[c];
+        if (pr < 0) continue;
+        int f[3];
+        face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+        const float4 w = pa[c];
+        const float al[3] = {w.x, w.y, w.z};
+        for (int k = 0; k < 3; ++k)
+            if (al[k] > 0.f && atomicSub(&rem[f[k]], 1) == 1) {
+                const int pos = atomicAdd(cnt_next, 1);
+                qout[pos] = f[k];
+            }
+    }
+}
+
+__global__ void k_adj_remaining(const int* __restrict__ done, int n_v, GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_v && !done[i]) atomicAdd(&ctl->remaining, 1);
+}
+
+// Jacobi sweep over the vertices the level walk could not finish.
+__global__ void k_adj_jacobi(const int* __restrict__ done, const int* __restrict__ cptr,
+                             const int* __restrict__ cchild, const float* __restrict__ calpha,
+                             const float* __restrict__ g, const float* __restrict__ lam_in,
+                             float* __restrict__ lam_out, int n_v, GbpCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    if (done[i]) {
+        lam_out[i] = lam_in[i];
+        return;
+    }
+    float l = g[i];
+    for (int x = cptr[i]; x < cptr[i + 1]; ++x) l += calpha[x] * lam_in[cchild[x]];
+    lam_out[i] = l;
+    const float d = fabsf(l - lam_in[i]) / fmaxf(1e-30f, fabsf(l));
+    atomicMax(reinterpret_cast<int*>(&ctl->maxdiff), __float_as_int(d));
+}
+
+// ------------------------------------------------------------------ gradients
+__global__ void k_grad_tet(const int4* __restrict__ tetv, const float4* __restrict__ tetg,
+                           const float4* __restrict__ xyz, const float* __restrict__ D,
+                           const int* __restrict__ tet_user, const int* __restrict__ par,
+                           const float4* __restrict__ pa, const float* __restrict__ lam,
+                           int n_e, float* __restrict__ dD_user, float* __restrict__ dsbar) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_e) return;
+    const int4 v = tetv[j];
+    const int vv[4] = {v.x, v.y, v.z, v.w};
+    const float sbar = tetg[2 * (size_t)j + 1].z;
+    const int u = tet_user[j];
+    const float* d6 = D + 6 * (size_t)u;
+    const float a = d6[0], b = d6[1], c = d6[2], d = d6[3], e = d6[4], f = d6[5];
+    const float A00 = b * c - f * f, A11 = a * c - e * e, A22 = a * b - d * d;
+    const float A01 = e * f - d * c, A02 = d * f - e * b, A12 = d * e - a * f;
+    const float idet = 1.f / (a * A00 + d * A01 + e * A02);
+    float g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, gs = 0;
+    for (int K = 0; K < 4; ++K) {
+        const int i = vv[K];
+        if (par[i] != ((j << 2) | K)) continue;
+        const float l = lam[i];
+        if (l == 0.f) continue;
+        int f3[3];
+        face_nodes_rt(v, K, f3[0], f3[1], f3[2]);
+        const float4 w = pa[i];
+        const float al[3] = {w.x, w.y, w.z};
+        const float4 xi = xyz[i];
+        float ex = 0, ey = 0, ez = 0;
+        for (int k = 0; k < 3; ++k) {
+            const float4 xk = xyz[f3[k]];
+            ex += al[k] * (xk.x - xi.x);
+            ey += al[k] * (xk.y - xi.y);
+            ez += al[k] * (xk.z - xi.z);
+        }
+        // u = D^{-1} e
+        const float ux = (A00 * ex + A01 * ey + A02 * ez) * idet;
+        const float uy = (A01 * ex + A11 * ey + A12 * ez) * idet;
+        const float uz = (A02 * ex + A12 * ey + A22 * ez) * idet;
+        const float h = sqrtf(fmaxf(ex * ux + ey * uy + ez * uz, 0.f)) / sbar;
+        if (!(h > 0.f)) continue;
+        const float cf = -l / (2.f * h * sbar * sbar);
+        g00 += cf * ux * ux;
+        g11 += cf * uy * uy;
+        g22 += cf * uz * uz;
+        g01 += cf * ux * uy;
+        g02 += cf * ux * uz;
+        g12 += cf * uy * uz;
+        gs += l * (-h / sbar);
+    }
+    if (dD_user) {
+        float* o = dD_user + 6 * (size_t)u;
+        o[0] = g00;
+        o[1] = g11;
+        o[2] = g22;
+        o[3] = 2.f * g01;
+        o[4] = 2.f * g02;
+        o[5] = 2.f * g12;
+    }
+    dsbar[j] = gs;
+}
+
+__global__ void k_grad_node(const int2* __restrict__ nptr, const int* __restrict__ nent,
+                            const float* __restrict__ dsbar, const int* __restrict__ node_user,
+                            int n_v, float* __restrict__ dvs_user) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_v) return;
+    const int2 p = nptr[i];
+    const int tot = (p.y & 255) + ((p.y >> 8) & 255) + ((p.y >> 16) & 255) + ((p.y >> 24) & 255);
+    float s = 0.f;
+    for (int c = 0; c < tot; ++c) s += dsbar[nent[p.x + c]];
+    dvs_user[node_user[i]] = 0.25f * s;
+}
+
+__global__ void k_grad_root(const int* __restrict__ root_node, const float* __restrict__ root_t,
+                            int n_roots, const int* __restrict__ node_int, int n_v,
+                            const int* __restrict__ par, const float* __restrict__ troot,
+                            const float* __restrict__ T, const float* __restrict__ lam,
+                            float* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_roots) return;
+    const int u = root_node[r];
+    float val = 0.f;
+    if (u >= 0 && u < n_v) {
+        const int i = node_int[u];
+        bool active = par[i] < 0 && T[i] < GBP_INF && root_t[r] == troot[i];
+        for (int q = 0; q < r && active; ++q)
+            if (root_node[q] == u && root_t[q] == root_t[r]) active = false;
+        if (active) val = lam[i];
+    }
+    out[r] = val;
+}
+
+__global__ void k_parent_out(const int* __restrict__ par, const float4* __restrict__ pa,
+                             const int4* __restrict__ tetv, const int* __restrict__ tet_user,
+                             const int* __restrict__ node_user, const int* __restrict__ node_int,
+                             int n_v, int* __restrict__ par_tet, int* __restrict__ par_node,
+                             float* __restrict__ par_alpha, float* __restrict__ best) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_v) return;
+    const int i = node_int[u];
+    const int pr = par[i];
+    const float4 w = pa[i];
+    if (best) best[u] = w.w;
+    if (pr < 0) {
+        par_tet[u] = -1;
+        for (int k = 0; k < 3; ++k) {
+            par_node[3 * u + k] = -1;
+            par_alpha[3 * u + k] = 0.f;
+        }
+        return;
+    }
+    int f[3];
+    face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+    par_tet[u] = tet_user[pr >> 2];
+    const float al[3] = {w.x, w.y, w.z};
+    for (int k = 0; k < 3; ++k) {
+        par_node[3 * u + k] = node_user[f[k]];
+        par_alpha[3 * u + k] = al[k];
+    }
+}
+
+// ------------------------------------------------------------------ scan
+__global__ void k_scan_block(const int* __restrict__ in, int* __restrict__ out, int n,
+                             int* __restrict__ bsum) {
+    __shared__ int sh[1024];
+    const int base = blockIdx.x * 1024;
+    int v[4], s = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int idx = base + threadIdx.x * 4 + k;
+        v[k] = idx < n ? in[idx] : 0;
+        s += v[k];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = sh[threadIdx.x] - s;  // exclusive prefix of this thread
+    for (int k = 0; k < 4; ++k) {
+        const int idx = base + threadIdx.x * 4 + k;
+        if (idx < n) out[idx] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) bsum[blockIdx.x] = sh[255];
+}
+
+__global__ void k_scan_top(int* __restrict__ bsum, int nb, int* __restrict__ total_out) {
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int b = 0; b < nb; ++b) {
+            const int t = bsum[b];
+            bsum[b] = run;
+            run += t;
+        }
+        *total_out = run;
+    }
+}
+
+__global__ void k_scan_add(int* __restrict__ out, int n, const int* __restrict__ bsum) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] += bsum[idx / 1024];
+}
+
+}  // namespace
+
+int gbp_scan_exclusive(const int* in, int* out, int n, int* tmp, hipStream_t s) {
+    const int nb = (n + 1023) / 1024;
+    k_scan_block<<<nb, 256, 0, s>>>(in, out, n, tmp);
+    k_scan_top<<<1, 64, 0, s>>>(tmp, nb, out + n);
+    k_scan_add<<<gbp_blocks(n, TPB), TPB, 0, s>>>(out, n, tmp);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+// ====================================================================== host
+static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB), 2048); }
+
+static int read_ctl(gbp_plan p, hipStream_t s) {
+    GBP_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
+static int err_from_bits(int bits) {
+    if (bits & ERRBIT_ROOT_RANGE) {
+        gbp_set_error("root vertex id out of range");
+        return GBP_ERR_ARG;
+    }
+    if (bits & ERRBIT_ROOT_NONFINITE) {
+        gbp_set_error("non-finite root onset time");
+        return GBP_ERR_NONFINITE;
+    }
+    if (bits & ERRBIT_D_NONFINITE) {
+        gbp_set_error("non-finite velocity tensor entry");
+        return GBP_ERR_NONFINITE;
+    }
+    if (bits & ERRBIT_D_NOT_SPD) {
+        gbp_set_error("velocity tensor not positive definite");
+        return GBP_ERR_NOT_SPD;
+    }
+    if (bits & ERRBIT_VSCALE) {
+        gbp_set_error("velocity scale must be finite and > 0");
+        return GBP_ERR_NONFINITE;
+    }
+    gbp_set_error("device error bits 0x%x", bits);
+    return GBP_ERR_HIP;
+}
+
+// metric + roots, shared by forward, backward and parent map
+static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                   const float* root_t, int n_roots, int cold, const float* T_init,
+                   hipStream_t s) {
+    if (!D) {
+        gbp_set_error("D is NULL");
+        return GBP_ERR_ARG;
+    }
+    if (n_roots < 0 || (n_roots > 0 && (!root_node || !root_t))) {
+        gbp_set_error("bad roots (n_roots=%d)", n_roots);
+        return GBP_ERR_ARG;
+    }
+    const int n_v = p->n_v, n_e = p->n_e;
+    GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
+    k_vscale_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, p->node_user, p->vs, n_v, p->ctl);
+    k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs, p->tetg,
+                                                  n_e, p->ctl);
+    k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, GBP_INF, n_v);
+    if (cold == 1) {
+        k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, GBP_INF, n_v);
+    } else if (cold == 0) {
+        k_gather_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(T_init, p->node_user, p->T, n_v);
+    }
+    if (p->stamp > (1 << 30)) {
+        GBP_HIP(hipMemsetAsync(p->mark, 0, sizeof(int) * n_v, s));
+        p->stamp = 1;
+    }
+    k_roots<<<1, TPB, 0, s>>>(root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T,
+                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->stamp,
+                              p->ctl);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vscale,
+                                   const int32_t* root_node, const float* root_t, int n_roots,
+                                   const float* T_init, float* T_out, gbp_stats* stats,
+                                   void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T_out) {
+        gbp_set_error("T_out is NULL");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int n_v = p->n_v;
+    const bool cold = (T_init == nullptr);
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
+    if (!cold) {
+        k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, p->stamp, n_v, p->ctl);
+        GBP_LAUNCH_CHECK();
+    }
+    if ((rc = read_ctl(p, s))) return rc;
+    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+
+    const int grid = sweep_grid(n_v);
+    int sweep = 0, batch = 4;
+    bool converged = (p->ctl_host->count[0] == 0);
+    while (!converged && sweep < p->max_rounds) {
+        const int nb = std::min(batch, p->max_rounds - sweep);
+        for (int b = 0; b < nb; ++b, ++sweep) {
+            const int* qin = p->q[sweep & 1];
+            int* qout = p->q[(sweep + 1) & 1];
+            const int st = p->stamp + sweep + 1;
+            if (cold)
+                k_sweep<false><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
+                                                    p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
+                                                    p->ctl, sweep, st, p->eps_rel);
+            else
+                k_sweep<true><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
+                                                   p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
+                                                   p->ctl, sweep, st, p->eps_rel);
+        }
+        GBP_LAUNCH_CHECK();
+        if ((rc = read_ctl(p, s))) return rc;
+        converged = (p->ctl_host->count[sweep % 3] == 0);
+        batch = std::min(batch * 2, 16);
+    }
+    p->stamp += sweep + 2;
+    k_count_inf<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, n_v, p->ctl);
+    k_scatter_out<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, p->node_int, T_out, n_v);
+    GBP_LAUNCH_CHECK();
+    if ((rc = read_ctl(p, s))) return rc;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->rounds = p->ctl_host->pad[0];
+        stats->converged = converged ? 1 : 0;
+        stats->face_solves = (int64_t)p->ctl_host->solves;
+        stats->node_updates = (int64_t)p->ctl_host->updates;
+        stats->unreached = p->ctl_host->unreached;
+    }
+    if (!converged) {
+        gbp_set_error("eikonal forward: no convergence after %d rounds", sweep);
+        return GBP_ERR_NOT_CONVERGED;
+    }
+    return GBP_OK;
+}
+
+// parents at the converged T (internal order); T must already be in p->T
+static int run_parents(gbp_plan p, hipStream_t s) {
+    const int n_v = p->n_v;
+    k_parent<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->T,
+                                                  p->troot, n_v, p->par, p->pa);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_parent_map(gbp_plan p, const float* D, const float* vscale,
+                              const int32_t* root_node, const float* root_t, int n_roots,
+                              const float* T, int32_t* par_tet, int32_t* par_node,
+                              float* par_alpha, float* best, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T || !par_tet || !par_node || !par_alpha) {
+        gbp_set_error("NULL output or T");
+        return GBP_ERR_ARG;
+    }
+    if ((rc = gbp_alloc_backward(p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
+    if ((rc = read_ctl(p, s))) return rc;
+    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+    if ((rc = run_parents(p, s))) return rc;
+    k_parent_out<<<gbp_blocks(p->n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, p->tet_user,
+                                                         p->node_user, p->node_int, p->n_v,
+                                                         par_tet, par_node, par_alpha, best);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vscale,
+                                    const int32_t* root_node, const float* root_t, int n_roots,
+                                    const float* T, const float* dL_dT, float* dL_dD,
+                                    float* dL_dvscale, float* dL_droot_t, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T || !dL_dT) {
+        gbp_set_error("T and dL_dT are required");
+        return GBP_ERR_ARG;
+    }
+    if ((rc = gbp_alloc_backward(p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int n_v = p->n_v, n_e = p->n_e;
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
+    if ((rc = read_ctl(p, s))) return rc;
+    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+    if ((rc = run_parents(p, s))) return rc;
+    // children lists
+    GBP_HIP(hipMemsetAsync(p->rem, 0, sizeof(int) * n_v, s));
+    GBP_HIP(hipMemsetAsync(p->cfill, 0, sizeof(int) * n_v, s));
+    k_child_count<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->rem);
+    GBP_LAUNCH_CHECK();
+    if ((rc = gbp_scan_exclusive(p->rem, p->ccnt, n_v, p->scan_tmp, s))) return rc;
+    k_child_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->ccnt,
+                                                      p->cfill, p->cchild, p->calpha);
+    k_child_sort<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
+    // level walk
+    GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
+    k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
+                                                    p->lam, p->done, p->q[0], p->ctl);
+    GBP_LAUNCH_CHECK();
+    if ((rc = read_ctl(p, s))) return rc;
+    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+    const int grid = sweep_grid(n_v);
+    int level = 0, batch = 4;
+    bool empty = (p->ctl_host->count[0] == 0);
+    const int cap = p->max_rounds + n_v;
+    while (!empty && level < cap) {
+        for (int b = 0; b < batch; ++b, ++level)
+            k_adj_level<<<grid, TPB, 0, s>>>(p->q[level & 1], p->q[(level + 1) & 1], p->ccnt,
+                                              p->cchild, p->calpha, p->g, p->lam, p->done, p->par,
+                                              p->pa, p->tetv, p->rem, p->ctl, level);
+        GBP_LAUNCH_CHECK();
+        if ((rc = read_ctl(p, s))) return rc;
+        empty = (p->ctl_host->count[level % 3] == 0);
+        batch = std::min(batch * 2, 16);
+    }
+    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->ctl);
+    GBP_LAUNCH_CHECK();
+    if ((rc = read_ctl(p, s))) return rc;
+    if (p->ctl_host->remaining > 0) {
+        // cycles in the parent graph: Jacobi on the unfinished vertices
+        bool ok = false;
+        for (int it = 0; it < 4 * p->max_rounds && !ok; it += 16) {
+            for (int b = 0; b < 16; ++b) {
+                GBP_HIP(hipMemsetAsync(&p->ctl->maxdiff, 0, sizeof(float), s));
+                k_adj_jacobi<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, p->ccnt, p->cchild,
+                                                                  p->calpha, p->g, p->lam,
+                                                                  p->lam2, n_v, p->ctl);
+                std::swap(p->lam, p->lam2);
+            }
+            GBP_LAUNCH_CHECK();
+            if ((rc = read_ctl(p, s))) return rc;
+            ok = p->ctl_host->maxdiff <= 1e-7f;
+        }
+        if (!ok) {
+            gbp_set_error("adjoint did not settle on %d cyclic vertices", p->ctl_host->remaining);
+            return GBP_ERR_NOT_CONVERGED;
+        }
+    }
+    // gradients
+    k_grad_tet<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(p->tetv, p->tetg, p->xyz, D, p->tet_user,
+                                                    p->par, p->pa, p->lam, n_e, dL_dD, p->dsbar);
+    if (dL_dvscale)
+        k_grad_node<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->dsbar, p->node_user,
+                                                         n_v, dL_dvscale);
+    if (dL_droot_t && n_roots > 0)
+        k_grad_root<<<gbp_blocks(n_roots, TPB), TPB, 0, s>>>(root_node, root_t, n_roots,
+                                                             p->node_int, n_v, p->par, p->troot,
+                                                             p->T, p->lam, dL_droot_t);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}

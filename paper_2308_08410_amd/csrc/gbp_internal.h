@@ -1,0 +1,112 @@
+// Internal declarations shared by the translation units of libgbp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gbp.h"
+
+// ---------------------------------------------------------------- errors
+void gbp_set_error(const char* fmt, ...);
+
+#define GBP_HIP(call)                                                           \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            gbp_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                          __FILE__, __LINE__);                                  \
+            return GBP_ERR_HIP;                                                 \
+        }                                                                       \
+    } while (0)
+
+#define GBP_LAUNCH_CHECK()                                                   \
+    do {                                                                     \
+        hipError_t e_ = hipGetLastError();                                   \
+        if (e_ != hipSuccess) {                                              \
+            gbp_set_error("kernel launch failed: %s (%s:%d)",                \
+                          hipGetErrorString(e_), __FILE__, __LINE__);        \
+            return GBP_ERR_HIP;                                              \
+        }                                                                    \
+    } while (0)
+
+// Device-side error bits (set by kernels, read back at synchronisation points).
+enum : int {
+    ERRBIT_ROOT_RANGE = 1,
+    ERRBIT_ROOT_NONFINITE = 2,
+    ERRBIT_D_NONFINITE = 4,
+    ERRBIT_D_NOT_SPD = 8,
+    ERRBIT_VSCALE = 16,
+    ERRBIT_SPIN = 32,
+};
+
+// Control block of the relaxation loops (device memory, mirrored to pinned host).
+struct GbpCtl {
+    int count[3];                  // rotating queue lengths
+    int err;                       // ERRBIT_* flags
+    unsigned long long solves;     // local problems evaluated
+    unsigned long long updates;    // nodes that changed
+    int unreached;
+    int remaining;                 // adjoint: nodes not finished by the level sweep
+    float maxdiff;                 // adjoint fallback: largest change of a sweep (as int bits)
+    int pad[3];
+};
+
+struct gbp_plan_s {
+    int device = 0;
+    int n_v = 0, n_e = 0;
+    int n_adj = 0;
+    int max_rounds = 0;
+    float eps_rel = 0.f;
+
+    // mesh, internal numbering (device)
+    float4* xyz = nullptr;        // [n_v]  (x, y, z, 0)
+    int4* tetv = nullptr;         // [n_e]  internal vertex ids
+    int* tet_user = nullptr;      // [n_e]  internal element -> caller element id
+    int* node_user = nullptr;     // [n_v]  internal node -> caller node id
+    int* node_int = nullptr;      // [n_v]  caller node id -> internal node
+    int2* nptr = nullptr;         // [n_v]  (first entry, 4 packed 8-bit counts per local slot)
+    int* nent = nullptr;          // [4 n_e] element ids sorted by (node, local slot, element)
+    int* adj_ptr = nullptr;       // [n_v+1] unique neighbour lists
+    int* adj = nullptr;           // [n_adj]
+
+    // per-call workspace (device)
+    float4* tetg = nullptr;       // [2 n_e]: (G11,G22,G33,G12), (G13,G23,sbar,0)
+    float* vs = nullptr;          // [n_v] nodal velocity scale (internal order)
+    float* T = nullptr;           // [n_v] activation times (internal order)
+    float* troot = nullptr;       // [n_v] min onset per node (+inf elsewhere)
+    int* q[2] = {nullptr, nullptr};  // work queues
+    int* mark = nullptr;          // [n_v] queue stamps
+    int stamp = 1;                // next stamp base (host side)
+    GbpCtl* ctl = nullptr;        // device control block
+    GbpCtl* ctl_host = nullptr;   // pinned mirror
+
+    // backward workspace (allocated on first use)
+    bool bwd_ready = false;
+    int* par = nullptr;           // [n_v] (element << 2 | local slot) or -1
+    float4* pa = nullptr;         // [n_v] (alpha0, alpha1, alpha2, best)
+    int* ccnt = nullptr;          // [n_v+1] children per node, then exclusive scan
+    int* cfill = nullptr;         // [n_v]
+    int* rem = nullptr;           // [n_v]
+    int* cchild = nullptr;        // [3 n_v]
+    float* calpha = nullptr;      // [3 n_v]
+    float* lam = nullptr;         // [n_v]
+    float* lam2 = nullptr;        // [n_v]
+    float* g = nullptr;           // [n_v]
+    float* dsbar = nullptr;       // [n_e]
+    int* done = nullptr;          // [n_v] adjoint finished flag
+    int* scan_tmp = nullptr;      // block sums
+};
+
+int gbp_plan_check(gbp_plan p);
+int gbp_alloc_backward(gbp_plan p);
+
+// exclusive scan of n ints in place into out[0..n] (out[n] = total); device
+int gbp_scan_exclusive(const int* in, int* out, int n, int* tmp, hipStream_t s);
+
+static inline int gbp_blocks(long long n, int threads) {
+    long long b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    return (int)b;
+}

@@ -1,0 +1,70 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/gbp.h declares, and rejects bad meshes before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gbp_inputs as gi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gbp.h")
+LIB = os.path.join(ROOT, "paper_2308_08410_amd", "libgbp.so")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*(gbp_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for need in ["gbp_plan_create", "gbp_plan_destroy", "gbp_eikonal_forward", "gbp_eikonal_backward",
+                 "gbp_parent_map", "gbp_ecg_forward", "gbp_ecg_backward", "gbp_ecg_loss", "gbp_adam_step",
+                 "gbp_last_error"]:
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first: python -m paper_2308_08410_amd.build"
+    lib = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_imports_and_reports_version():
+    from paper_2308_08410_amd import binding as B
+    assert "gfx950" in B.version()
+
+
+def _create(xyz, tets):
+    from paper_2308_08410_amd import binding as B
+    h = ctypes.c_void_p()
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    tets = np.ascontiguousarray(tets, np.int32)
+    rc = B._plan_create(xyz.ctypes.data, len(xyz), tets.ctypes.data, len(tets), None, ctypes.byref(h))
+    return rc, B._last_error().decode()
+
+
+def test_plan_rejects_bad_meshes_before_gpu():
+    xyz, tets = gi.kuhn_cube(2)
+    bad = tets.copy()
+    bad[3, 2] = len(xyz) + 5
+    rc, msg = _create(xyz, bad)
+    assert rc == -1 and "out of range" in msg
+    bad = tets.copy()
+    bad[0, 1] = bad[0, 0]
+    rc, msg = _create(xyz, bad)
+    assert rc == -1 and "repeats" in msg
+    flat = xyz.copy()
+    flat[:, 2] = 0.0                                # every element collapses
+    rc, msg = _create(flat, tets)
+    assert rc == -2 and "degenerate" in msg
+    nan = xyz.copy()
+    nan[4, 0] = np.nan
+    rc, msg = _create(nan, tets)
+    assert rc == -4
+    rc, msg = _create(xyz[:0], tets)
+    assert rc == -1
