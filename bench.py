@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Geodesic-BP iterations per second on one MI355X.
+
+One step = one full Geodesic-BP iteration on the synthetic 500k-vertex
+biventricular shell: cold eikonal solve (active-list relaxation of Alg. 2),
+lead-field ECG (12 leads x 500 steps of 1 ms), misfit against a target ECG made
+from a hidden seeded parameter set, ECG backward, eikonal adjoint (parents
+recomputed, gradients w.r.t. the nodal velocity scale and the root onsets), and
+one Adam step on those parameters.  All of it runs in libgbp's HIP kernels on
+torch's current stream; inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  `python bench.py --gpus 1 --steps 20 --warmup 3`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "Geodesic-BP iters/s (FIM+adjoint+ECG) at 500k nodes; speedup vs plain"
+# Nominal FP32 operations of one closed-form local solve (vertex, edge and
+# interior KKT candidates, see local_solve.h; an FMA counts as two operations).
+FLOP_PER_FACE = 185.0
+# MI355X peaks: FP32 vector without packed math (256 CU x 64 lanes x 2 x 2.4 GHz)
+# and HBM3E bandwidth.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nodes", type=int, default=500_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--cpu-sample-nodes", type=int, default=62_500)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_state(prob, dev, torch, gi, B):
+    """Plan, device inputs, a target ECG from hidden parameters, and the
+    parameters being fitted (velocity scale, root onsets) with Adam moments."""
+    plan = B.Plan(prob.xyz, prob.tets)
+    f32 = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev).contiguous()
+    st = dict(plan=plan, D=f32(prob.D), W=f32(prob.W), rn=torch.as_tensor(prob.root_node, device=dev))
+    ap = prob.ap
+    st["ap"] = B.make_ap(ap["K0"], ap["K1"], ap["tau"], ap["t0"], ap["dt"], ap["n_steps"])
+    # hidden parameter set -> target ECG
+    vs_true = f32(gi.smooth_field(prob.xyz, 0.7, 1.3, seed=20))
+    rt_true = f32(prob.root_t)
+    T_true, _ = B.eikonal_forward(plan, st["D"], vs_true, st["rn"], rt_true)
+    st["target"] = B.ecg_forward(T_true, st["W"], st["ap"]).clone()
+    # initial guess of the fit
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(21))
+    st["vs"] = f32(np.ones(prob.n_v))
+    st["rt"] = f32(prob.root_t + rng.uniform(-5, 5, size=len(prob.root_t)))
+    for k in ("vs", "rt"):
+        st["m_" + k] = torch.zeros_like(st[k])
+        st["v_" + k] = torch.zeros_like(st[k])
+    st["k"] = 0
+    return st
+
+
+def gbp_step(st, B):
+    st["k"] += 1
+    T, stats = B.eikonal_forward(st["plan"], st["D"], st["vs"], st["rn"], st["rt"])
+    ecg = B.ecg_forward(T, st["W"], st["ap"])
+    loss, G = B.ecg_loss(ecg, st["target"])
+    gT = B.ecg_backward(T, st["W"], st["ap"], G)
+    _, dvs, drt = B.eikonal_backward(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], T, gT,
+                                     want_D=False)
+    B.adam_step(st["vs"], dvs, st["m_vs"], st["v_vs"], st["k"], lr=0.01, lo=0.2, hi=5.0)
+    B.adam_step(st["rt"], drt, st["m_rt"], st["v_rt"], st["k"], lr=0.5)
+    return loss, stats
+
+
+def cpu_baseline(n_sample, n_full):
+    """The FP64 oracle, as it stands, timed on the host for one complete
+    iteration on a smaller member of the same shell family, scaled to the
+    full workload: the eikonal part by (n_full/n_sample)^(4/3) (work ~ vertices x
+    sweeps, sweeps ~ vertices^(1/3)), the rest linearly."""
+    import numpy as np
+    import gbp_inputs as gi
+    import oracle as O
+    p = gi.shell_problem(n_sample, seed=2, n_roots=5, n_leads=12)
+    vs = np.ones(p.n_v)
+    t0 = time.perf_counter()
+    Minv = O.metric_inverse(p.D, vs, p.tets)
+    T, st = O.fim(p.xyz, p.tets, Minv, p.root_node, p.root_t)
+    t1 = time.perf_counter()
+    par = O.parent_map(p.xyz, p.tets, Minv, p.root_node, p.root_t, T)
+    e = O.ecg_forward(T, p.W, p.ap)
+    _, G = O.ecg_loss(e, 0.9 * e)
+    g = O.ecg_backward(T, p.W, p.ap, G)
+    res = O.adjoint(p.xyz, p.tets, p.D, vs, p.root_node, p.root_t, T, g, par=par)
+    O.adam_step(vs, res["dvscale"], np.zeros_like(vs), np.zeros_like(vs), 1, lr=0.01)
+    t2 = time.perf_counter()
+    ratio = n_full / p.n_v
+    t_est = (t1 - t0) * ratio ** (4.0 / 3.0) + (t2 - t1) * ratio
+    return dict(value=1.0 / t_est, unit="iter/s", cores=1, kind="oracle",
+                sample=(f"one full FP64 oracle iteration (Alg. 2 Jacobi, parents, sparse adjoint, ECG fwd/bwd, "
+                        f"Adam) on the {p.n_v}-vertex member of the same shell family took "
+                        f"{t2 - t0:.2f} s ({t1 - t0:.2f} s eikonal, {st['sweeps']} sweeps); scaled to "
+                        f"{n_full} vertices: eikonal x{ratio:.2f}^(4/3), rest x{ratio:.2f} -> {t_est:.1f} s/iter; "
+                        f"single thread"))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the solve of one mesh runs on "
+              "one MI355X; see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import gbp_inputs as gi
+    from paper_2308_08410_amd import binding as B
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t = time.time()
+    prob = gi.shell_problem(args.nodes, seed=2, n_roots=5, n_leads=12)
+    log(f"[bench] shell n_v={prob.n_v} n_e={prob.n_e} generated in {time.time() - t:.1f}s")
+    st = make_state(prob, dev, torch, gi, B)
+    for w in range(args.warmup):
+        loss, stats = gbp_step(st, B)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done: loss={float(loss[0]):.4g} rounds={stats['rounds']}")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    face_solves = 0
+    for k in range(args.steps):
+        loss, stats = gbp_step(st, B)
+        face_solves += stats["face_solves"]
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step (wall {1e3 * t_wall / args.steps:.3f}) "
+        f"loss={float(loss[0]):.4g}")
+
+    roofline = None
+    detail = dict(fim_rounds=stats["rounds"], face_solves_per_step=face_solves // args.steps,
+                  node_updates=stats["node_updates"], wall_ms_per_step=1e3 * t_wall / args.steps)
+    if not args.no_profile:
+        # per-kernel HIP-event timing on the launching stream, separate steps
+        B.profile_reset()
+        B.profile_enable(True)
+        nprof = 3
+        fs = 0
+        for k in range(nprof):
+            _, s2 = gbp_step(st, B)
+            fs += s2["face_solves"]
+        torch.cuda.synchronize()
+        prof = B.profile_read()
+        B.profile_enable(False)
+        n_sw, ms_sw = prof["fim_sweep"]
+        avg_ms = ms_sw / max(n_sw, 1)
+        flop_per_launch = fs * FLOP_PER_FACE / max(n_sw, 1)
+        achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+        roofline = dict(kernel="k_sweep (eikonal relaxation round)", bound="alu", achieved=achieved,
+                        peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS,
+                        traffic=None, avg_launch_ms=avg_ms, launches_per_step=n_sw / nprof,
+                        flop_per_launch=flop_per_launch)
+        detail["kernel_ms_per_step"] = {k: v[1] / nprof for k, v in prof.items() if v[0]}
+        detail["kernel_launches_per_step"] = {k: v[0] / nprof for k, v in prof.items() if v[0]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        cpu = cpu_baseline(args.cpu_sample_nodes, prob.n_v)
+        log(f"[bench] cpu baseline {time.time() - t:.1f}s: {cpu['value']:.4g} iter/s (estimated)")
+    out = {
+        "metric": METRIC, "value": 1000.0 / ms, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"biventricular shell {prob.n_v} vertices / {prob.n_e} tets, helix fibres, "
+                               f"D=diag(0.36,0.09,0.09), 5 endocardial roots, 12 leads x 500 steps; "
+                               f"cold eikonal + ECG + loss + ECG bwd + adjoint + Adam",
+                   "n_v": prob.n_v, "n_e": prob.n_e, "leads": 12, "time_steps": 500, "roots": 5,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "detail": detail,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

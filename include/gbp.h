@@ -50,7 +50,7 @@ typedef struct gbp_plan_s *gbp_plan;
 typedef struct {
     float eps_rel;     /* change threshold: a node counts as changed when its value
                           drops by more than eps_rel*max(1,|T|); 0 -> 2^-20 */
-    int max_rounds;    /* cap on global relaxation rounds; 0 -> 64 + 8*n_v^(1/3)*... (library default) */
+    int max_rounds;    /* cap on global relaxation rounds; 0 -> 20000 */
     int reorder;       /* 0 -> default (locality reordering on), -1 -> keep caller order */
     int reserved[5];   /* must be zero */
 } gbp_options;
@@ -137,6 +137,15 @@ int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
                          float *dL_dvscale, float *dL_droot_t, void *stream);
 
 /*
+ * gbp_backward_info -- diagnostics of the last gbp_eikonal_backward on this
+ * plan: number of leaves-first levels walked, vertices that the walk could not
+ * finish because they lie on or above a cycle of the parent graph (possible in
+ * anisotropic media, where a face vertex may be later than the vertex it
+ * updates), and Gauss-Seidel sweeps used to finish them.  Any pointer may be NULL.
+ */
+int gbp_backward_info(gbp_plan plan, int *levels, int *cyclic, int *gs_sweeps);
+
+/*
  * gbp_parent_map -- the geodesic parents used by the backward pass, exposed
  * for inspection: for every vertex the minimising element (Sec. 2.3: the
  * element whose face carries the upwind point), the three face vertices and
@@ -198,6 +207,20 @@ int gbp_ecg_loss(const float *ecg, const float *target, int n, float *loss, floa
 int gbp_adam_step(float *param, const float *grad, float *m, float *v, int n, float lr,
                   float beta1, float beta2, float eps, int step, float lo, float hi,
                   void *stream);
+
+/*
+ * Kernel timing for diagnostics and roofline reports.  While enabled, each
+ * launch of the library's kernels is bracketed by two HIP events recorded on the
+ * stream the kernel runs on; gbp_profile_read synchronises those events and
+ * returns, for one kernel family, the number of timed launches and their summed
+ * duration in milliseconds.  Families: "metric", "fim_sweep", "parent",
+ * "child_lists", "adj_level", "grad", "ecg_fwd", "ecg_bwd", "aux".
+ * Enabling adds host overhead per launch; leave it off for throughput runs.
+ * gbp_profile_read returns GBP_ERR_ARG for an unknown family name.
+ */
+int gbp_profile_enable(int on);
+void gbp_profile_reset(void);
+int gbp_profile_read(const char *kernel, int64_t *launches, double *total_ms);
 
 const char *gbp_last_error(void);
 const char *gbp_version(void);

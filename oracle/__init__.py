@@ -125,7 +125,7 @@ def local_solve(Q, Phi):
     Phi, pp = _d(Phi)
     val = np.zeros(1)
     alpha = np.zeros(3)
-    mask = lib.orc_local_solve(qp, pp, _d(val)[1] if False else val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+    mask = lib.orc_local_solve(qp, pp, val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return float(val[0]), alpha, int(mask)
 
@@ -254,9 +254,15 @@ def adjoint(xyz, tets, D6, vscale, root_node, root_t, T, g, par=None):
     P = parent_matrix(par, n_v)
     g = np.asarray(g, dtype=np.float64).copy()
     g[~np.isfinite(np.asarray(T, dtype=np.float64))] = 0.0
-    A = (sp.identity(n_v, format="csc") - P.T.tocsc())
-    lam = spla.spsolve(A, g)
-    lam = np.asarray(lam).reshape(-1)
+    A = (sp.identity(n_v, format="csr") - P.T.tocsr())
+    # Order unknowns by decreasing T: a parent is (almost always) earlier than its
+    # child, so the permuted system is nearly triangular and the direct solve
+    # stays sparse.  The solution does not depend on the ordering.
+    Tn = np.asarray(T, dtype=np.float64)
+    order = np.argsort(-np.where(np.isfinite(Tn), Tn, np.inf), kind="stable")
+    Ap = A[order][:, order].tocsc()
+    lam = np.empty(n_v)
+    lam[order] = np.asarray(spla.spsolve(Ap, g[order], permc_spec="NATURAL")).reshape(-1)
 
     D = unpack_sym(D6)
     Dinv = np.linalg.inv(D)

@@ -80,12 +80,41 @@ _ecg_bwd = _sig("gbp_ecg_backward", [c_void_p, c_int, c_void_p, c_int, ctypes.PO
 _ecg_loss = _sig("gbp_ecg_loss", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p])
 _adam = _sig("gbp_adam_step", [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_float, c_float, c_float,
                                c_float, c_int, c_float, c_float, c_void_p])
+_bwd_info = _sig("gbp_backward_info", [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_int)])
+_prof_enable = _sig("gbp_profile_enable", [c_int])
+_prof_reset = _sig("gbp_profile_reset", [], None)
+_prof_read = _sig("gbp_profile_read", [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)])
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
 
 def version() -> str:
     return _version().decode()
+
+
+PROFILE_KERNELS = ("metric", "fim_sweep", "parent", "child_lists", "adj_level", "grad", "ecg_fwd",
+                   "ecg_bwd", "aux")
+
+
+def profile_enable(on=True):
+    _check(_prof_enable(1 if on else 0))
+
+
+def profile_reset():
+    _prof_reset()
+
+
+def profile_read():
+    """{kernel family: (timed launches, total ms)} from the library's event timers."""
+    out = {}
+    for k in PROFILE_KERNELS:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_prof_read(k.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        out[k] = (int(n.value), float(ms.value))
+    return out
 
 
 def _check(rc):
@@ -133,11 +162,17 @@ class Plan:
         self.n_v, self.n_e = len(xyz), len(tets)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _plan_destroy is not None:
             _plan_destroy(h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     @property
     def handle(self):
@@ -178,6 +213,13 @@ def eikonal_backward(plan: Plan, D, vscale, root_node, root_t, T, dL_dT, want_D=
                      _ptr(dvs, torch.float32, (n_v,), "dL_dvscale"),
                      _ptr(dt, torch.float32, (R,), "dL_droot_t"), _stream(stream)))
     return dD, dvs, dt
+
+
+def backward_info(plan: Plan):
+    """(levels, cyclic vertices, Gauss-Seidel sweeps) of the last backward on ``plan``."""
+    a, b, c = c_int(), c_int(), c_int()
+    _check(_bwd_info(plan.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return dict(levels=a.value, cyclic=b.value, gs_sweeps=c.value)
 
 
 def parent_map(plan: Plan, D, vscale, root_node, root_t, T, stream=None):

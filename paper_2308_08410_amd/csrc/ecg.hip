@@ -21,6 +21,7 @@
 #include <mutex>
 
 #include "gbp_internal.h"
+#include "profile.h"
 
 namespace {
 
@@ -192,18 +193,28 @@ __global__ void k_ecg_zero(float* __restrict__ p, int n) {
         p[i] = 0.f;
 }
 
-// ecg[s,l] = K0 * sum W + prefix_s(hist) + win
-__global__ void k_ecg_finish(const float* __restrict__ g_win, const float* __restrict__ g_hist,
-                             const float* __restrict__ g_wsum, int S, int L, float K0,
-                             float* __restrict__ ecg) {
-    // one thread per lead does the running sum (S <= 2048, L <= 16)
-    const int l = threadIdx.x;
-    if (l >= L) return;
-    const float base = K0 * g_wsum[l];
+// ecg[s,l] = K0 * sum W + prefix_s(hist) + win.  One block of 1024 threads:
+// thread (c, l) owns lead l and the c-th of 64 contiguous chunks of time steps.
+__global__ void __launch_bounds__(1024)
+    k_ecg_finish(const float* __restrict__ g_win, const float* __restrict__ g_hist,
+                 const float* __restrict__ g_wsum, int S, int L, float K0, float* __restrict__ ecg) {
+    __shared__ float part[64][17];
+    const int l = threadIdx.x & 15, c = threadIdx.x >> 4;
+    const int len = (S + 63) / 64;
+    const int s0 = c * len, s1 = min(S, s0 + len);
     float run = 0.f;
-    for (int s = 0; s < S; ++s) {
-        run += g_hist[s * 16 + l];
-        ecg[(size_t)s * L + l] = base + run + g_win[s * 16 + l];
+    for (int s = s0; s < s1; ++s) run += g_hist[s * 16 + l];
+    part[c][l] = run;
+    __syncthreads();
+    float off = 0.f;
+    for (int k = 0; k < c; ++k) off += part[k][l];
+    if (l < L) {
+        const float base = K0 * g_wsum[l];
+        float r = off;
+        for (int s = s0; s < s1; ++s) {
+            r += g_hist[s * 16 + l];
+            ecg[(size_t)s * L + l] = base + r + g_win[s * 16 + l];
+        }
     }
 }
 
@@ -360,8 +371,11 @@ extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, c
     const int gpb = 16;   // 64-vertex groups per block (4 per wave)
     const int blocks = (groups + gpb - 1) / gpb;
     const size_t lds = (size_t)S_pad * 16 * sizeof(float);
-    k_ecg_fwd<<<blocks, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, g_win, g_hist, g_wsum);
-    k_ecg_finish<<<1, 64, 0, s>>>(g_win, g_hist, g_wsum, d.S, L, d.K0, ecg);
+    {
+        ProfScope ps(GBP_PROF_ECG_FWD, s);
+        k_ecg_fwd<<<blocks, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, g_win, g_hist, g_wsum);
+    }
+    k_ecg_finish<<<1, 1024, 0, s>>>(g_win, g_hist, g_wsum, d.S, L, d.K0, ecg);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -380,6 +394,7 @@ extern "C" int gbp_ecg_backward(const float* T, int n_v, const float* W, int L, 
     const int groups = (n_v + 63) / 64;
     const int blocks = std::min((groups + 3) / 4, 2048);
     const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
+    ProfScope ps(GBP_PROF_ECG_BWD, s);
     k_ecg_bwd<<<blocks, 256, lds, s>>>(T, W, dL_decg, n_v, L, d, S_pad, dL_dT);
     GBP_LAUNCH_CHECK();
     return GBP_OK;

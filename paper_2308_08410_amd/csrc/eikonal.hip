@@ -22,12 +22,86 @@
 
 #include "gbp_internal.h"
 #include "local_solve.h"
+#include "profile.h"
 
 namespace {
 
 constexpr int TPB = 256;
 
 __device__ __forceinline__ bool finitef(float x) { return x == x && fabsf(x) < GBP_INF; }
+
+// Sum over the block (fixed order); result valid in thread 0.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v) {
+    __shared__ unsigned long long red[TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < TPB / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ float block_max_f(float v) {
+    __shared__ float red[TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < TPB / 64; ++w) t = fmaxf(t, red[w]);
+    __syncthreads();
+    return t;
+}
+
+// Block-level queue buffer: pushes land in LDS; one atomic per block reserves
+// room in the global queue at flush time (overflow goes straight to global).
+constexpr int kPushCap = 4096;
+
+struct PushBuf {
+    int* q;      // LDS [kPushCap]
+    int* n;      // LDS counter
+};
+
+__device__ __forceinline__ void push_node(PushBuf b, int v, int* __restrict__ qout,
+                                          int* cnt_next) {
+    const int pos = atomicAdd(b.n, 1);
+    if (pos < kPushCap) {
+        b.q[pos] = v;
+    } else {
+        qout[atomicAdd(cnt_next, 1)] = v;
+    }
+}
+
+__device__ __forceinline__ void push_flush(PushBuf b, int* __restrict__ qout, int* cnt_next,
+                                           int* base_sh) {
+    __syncthreads();
+    const int n = min(*b.n, kPushCap);
+    if (threadIdx.x == 0) *base_sh = n > 0 ? atomicAdd(cnt_next, n) : 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) qout[*base_sh + k] = b.q[k];
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Sum the per-block counters of the relaxation rounds into the control block.
+__global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCtl* ctl) {
+    unsigned long long a = 0, b = 0;
+    for (int i = threadIdx.x; i < kStatBlocks; i += blockDim.x) {
+        a += blk[2 * i];
+        b += blk[2 * i + 1];
+    }
+    a = block_sum_u64(a);
+    b = block_sum_u64(b);
+    if (threadIdx.x == 0) {
+        ctl->solves = a;
+        ctl->updates = b;
+    }
+}
 
 // ------------------------------------------------------------------ preparation
 __global__ void k_vscale_in(const float* __restrict__ vs_user, const int* __restrict__ node_user,
@@ -175,79 +249,152 @@ __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restric
     e += cnt;
 }
 
+// One relaxation round.  Each vertex of the queue is handled by a half-wave
+// (32 lanes): lane c evaluates the c-th local problem of the vertex's patch
+// (slot picked at run time), a half-wave min-reduction forms the Hopf-Lax
+// minimum, and on a change the lanes push the unique neighbours in parallel.
 template <bool TWO_SIDED>
 __global__ void __launch_bounds__(TPB)
     k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
-            int* __restrict__ mark, GbpCtl* ctl, int s, int stamp_next, float eps_rel) {
+            int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
+            int stamp_next, float eps_rel) {
     const int n = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
         if (n > 0) atomicMax(&ctl->pad[0], s + 1);
     }
+    if (blockIdx.x * (TPB / 32) >= n) return;       // no vertex for this block
     int* cnt_next = &ctl->count[(s + 1) % 3];
+    __shared__ int push_q[kPushCap];
+    __shared__ int push_n, push_base;
+    if (threadIdx.x == 0) push_n = 0;
+    __syncthreads();
+    const PushBuf pb{push_q, &push_n};
+    const int lane = threadIdx.x & 31;
+    const int sub = threadIdx.x >> 5;               // vertex slot of this half-wave
+    constexpr int PER_BLOCK = TPB / 32;
     unsigned long long solves = 0, upd = 0;
-    for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
-        const int i = qin[qi];
+    for (int base = blockIdx.x * PER_BLOCK; base < n; base += gridDim.x * PER_BLOCK) {
+        const int qi = base + sub;
+        const bool act = qi < n;                    // uniform over the half-wave
+        const int i = act ? qin[qi] : 0;
+        const int2 p = act ? nptr[i] : make_int2(0, 0);
+        const int c0 = p.y & 255, c1 = (p.y >> 8) & 255, c2 = (p.y >> 16) & 255,
+                  c3 = (p.y >> 24) & 255;
+        const int tot = c0 + c1 + c2 + c3;
+        float best = GBP_INF;
+        for (int c = lane; c < tot; c += 32) {
+            const int K = (c < c0) ? 0 : (c < c0 + c1) ? 1 : (c < c0 + c1 + c2) ? 2 : 3;
+            const int t = nent[p.x + c];
+            const int4 v = tetv[t];
+            const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
+            int a, b, cc;
+            face_nodes_sel(v, K, a, b, cc);
+            best = fminf(best, local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]));
+            ++solves;
+        }
+        best = fminf(best, __shfl_xor(best, 16));
+        best = fminf(best, __shfl_xor(best, 8));
+        best = fminf(best, __shfl_xor(best, 4));
+        best = fminf(best, __shfl_xor(best, 2));
+        best = fminf(best, __shfl_xor(best, 1));
+        if (!act) continue;
         const float told = T[i];
-        float best = TWO_SIDED ? troot[i] : told;
-        const int2 p = nptr[i];
-        int e = p.x;
-        relax_slot<0>(e, p.y & 255, nent, tetv, tetg, T, best);
-        relax_slot<1>(e, (p.y >> 8) & 255, nent, tetv, tetg, T, best);
-        relax_slot<2>(e, (p.y >> 16) & 255, nent, tetv, tetg, T, best);
-        relax_slot<3>(e, (p.y >> 24) & 255, nent, tetv, tetg, T, best);
-        solves += (unsigned)(e - p.x);
         bool changed;
         if (TWO_SIDED) {
-            if (best != told) T[i] = best;
+            best = fminf(best, troot[i]);
+            if (lane == 0 && best != told) T[i] = best;
             const bool bf = best < GBP_INF, tf = told < GBP_INF;
             changed = (bf != tf) ||
                       (bf && fabsf(best - told) > eps_rel * fmaxf(1.f, fabsf(told)));
         } else {
-            if (best < told) T[i] = best;
+            if (lane == 0 && best < told) T[i] = best;
             changed = (told < GBP_INF) ? (best < told - eps_rel * fmaxf(1.f, fabsf(told)))
                                        : (best < GBP_INF);
         }
         if (changed) {
-            ++upd;
+            if (lane == 0) ++upd;
             const int a1 = adj_ptr[i + 1];
-            for (int a = adj_ptr[i]; a < a1; ++a) {
+            for (int a = adj_ptr[i] + lane; a < a1; a += 32) {
                 const int nb = adj[a];
-                if (atomicMax(&mark[nb], stamp_next) < stamp_next) {
-                    const int pos = atomicAdd(cnt_next, 1);
-                    qout[pos] = nb;
-                }
+                if (atomicMax(&mark[nb], stamp_next) < stamp_next) push_node(pb, nb, qout, cnt_next);
             }
         }
     }
-    if (solves) atomicAdd(&ctl->solves, solves);
-    if (upd) atomicAdd(&ctl->updates, upd);
+    push_flush(pb, qout, cnt_next, &push_base);
+    // per-block counters: one writer per slot, no contended atomics
+    solves = block_sum_u64(solves);
+    upd = block_sum_u64(upd);
+    if (threadIdx.x == 0) {
+        blk[2 * blockIdx.x] += solves;
+        blk[2 * blockIdx.x + 1] += upd;
+    }
 }
 
 __global__ void k_count_inf(const float* __restrict__ T, int n_v, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int c = (i < n_v && !(T[i] < GBP_INF)) ? 1 : 0;
-    if (c) atomicAdd(&ctl->unreached, 1);
+    const unsigned long long c = (i < n_v && !(T[i] < GBP_INF)) ? 1ull : 0ull;
+    const unsigned long long t = block_sum_u64(c);
+    if (threadIdx.x == 0 && t) atomicAdd(&ctl->unreached, (int)t);
 }
 
 // ------------------------------------------------------------------ parents
+// The parent of a vertex is an argmin over its local problems: a decision taken
+// by floating point.  It is taken here in FP64 from the raw inputs (coordinates,
+// velocity tensor, nodal scales, activation times), the precision of the
+// reference, so that near-ties resolve the same way on both sides.
+struct Sym64 {
+    double xx, yy, zz, xy, xz, yz;
+};
+
+__device__ __forceinline__ Sym64 inv_metric64(const float* __restrict__ D6, double sbar) {
+    const double a = D6[0], b = D6[1], c = D6[2], d = D6[3], e = D6[4], f = D6[5];
+    const double A00 = b * c - f * f, A11 = a * c - e * e, A22 = a * b - d * d;
+    const double A01 = e * f - d * c, A02 = d * f - e * b, A12 = d * e - a * f;
+    const double s = 1.0 / ((a * A00 + d * A01 + e * A02) * sbar * sbar);
+    return Sym64{A00 * s, A11 * s, A22 * s, A01 * s, A02 * s, A12 * s};
+}
+
+__device__ __forceinline__ double quad64(const Sym64& M, double x0, double x1, double x2, double y0,
+                                         double y1, double y2) {
+    return x0 * (M.xx * y0 + M.xy * y1 + M.xz * y2) + x1 * (M.xy * y0 + M.yy * y1 + M.yz * y2) +
+           x2 * (M.xz * y0 + M.yz * y1 + M.zz * y2);
+}
+
 template <int K>
-__device__ __forceinline__ void parent_slot(int& e, int cnt, const int* __restrict__ nent,
+__device__ __forceinline__ void parent_slot(int& e, int cnt, int self, const int* __restrict__ nent,
                                             const int4* __restrict__ tetv,
-                                            const float4* __restrict__ tetg,
-                                            const float* __restrict__ T, float& best, int& bpar,
-                                            float& b0, float& b1, float& b2) {
+                                            const int* __restrict__ tet_user,
+                                            const float* __restrict__ D,
+                                            const float* __restrict__ vs,
+                                            const float4* __restrict__ xyz,
+                                            const float* __restrict__ T, double& best, int& bpar,
+                                            double& b0, double& b1, double& b2) {
+    const float4 xi = xyz[self];
     for (int c = 0; c < cnt; ++c) {
         const int t = nent[e + c];
         const int4 v = tetv[t];
-        const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
-        int a, b, cc;
-        face_nodes<K>(v, a, b, cc);
-        float a0, a1, a2;
-        const float val = local_min<true>(face_q<K>(g0, g1), T[a], T[b], T[cc], &a0, &a1, &a2);
+        const double sbar = 0.25 * ((double)vs[v.x] + (double)vs[v.y] + (double)vs[v.z] + (double)vs[v.w]);
+        const Sym64 M = inv_metric64(D + 6 * (size_t)tet_user[t], sbar);
+        int n0, n1, n2;
+        face_nodes<K>(v, n0, n1, n2);
+        const float4 x0 = xyz[n0], x1 = xyz[n1], x2 = xyz[n2];
+        const double e0x = (double)x0.x - xi.x, e0y = (double)x0.y - xi.y, e0z = (double)x0.z - xi.z;
+        const double e1x = (double)x1.x - xi.x, e1y = (double)x1.y - xi.y, e1z = (double)x1.z - xi.z;
+        const double e2x = (double)x2.x - xi.x, e2y = (double)x2.y - xi.y, e2z = (double)x2.z - xi.z;
+        LocalQT<double> q;
+        q.q00 = quad64(M, e0x, e0y, e0z, e0x, e0y, e0z);
+        q.q11 = quad64(M, e1x, e1y, e1z, e1x, e1y, e1z);
+        q.q22 = quad64(M, e2x, e2y, e2z, e2x, e2y, e2z);
+        q.q01 = quad64(M, e0x, e0y, e0z, e1x, e1y, e1z);
+        q.q02 = quad64(M, e0x, e0y, e0z, e2x, e2y, e2z);
+        q.q12 = quad64(M, e1x, e1y, e1z, e2x, e2y, e2z);
+        double a0, a1, a2;
+        const double val = local_min<true, double>(q, (double)T[n0], (double)T[n1], (double)T[n2],
+                                                   &a0, &a1, &a2);
         if (val < best) {
             best = val;
             bpar = (t << 2) | K;
@@ -261,24 +408,26 @@ __device__ __forceinline__ void parent_slot(int& e, int cnt, const int* __restri
 
 __global__ void __launch_bounds__(TPB)
     k_parent(const int2* __restrict__ nptr, const int* __restrict__ nent,
-             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
-             const float* __restrict__ T, const float* __restrict__ troot, int n_v,
-             int* __restrict__ par, float4* __restrict__ pa) {
+             const int4* __restrict__ tetv, const int* __restrict__ tet_user,
+             const float* __restrict__ D, const float* __restrict__ vs,
+             const float4* __restrict__ xyz, const float* __restrict__ T,
+             const float* __restrict__ troot, int n_v, int* __restrict__ par,
+             float4* __restrict__ pa) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
-    float best = GBP_INF, b0 = 0.f, b1 = 0.f, b2 = 0.f;
+    double best = __builtin_huge_val(), b0 = 0, b1 = 0, b2 = 0;
     int bpar = -1;
     if (T[i] < GBP_INF) {
         const int2 p = nptr[i];
         int e = p.x;
-        parent_slot<0>(e, p.y & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
-        parent_slot<1>(e, (p.y >> 8) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
-        parent_slot<2>(e, (p.y >> 16) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
-        parent_slot<3>(e, (p.y >> 24) & 255, nent, tetv, tetg, T, best, bpar, b0, b1, b2);
-        if (troot[i] <= best) bpar = -1;
+        parent_slot<0>(e, p.y & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
+        parent_slot<1>(e, (p.y >> 8) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
+        parent_slot<2>(e, (p.y >> 16) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
+        parent_slot<3>(e, (p.y >> 24) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
+        if ((double)troot[i] <= best) bpar = -1;
     }
     par[i] = bpar;
-    pa[i] = make_float4(b0, b1, b2, best);
+    pa[i] = make_float4((float)b0, (float)b1, (float)b2, (float)best);
 }
 
 __device__ __forceinline__ void face_nodes_rt(const int4 v, int K, int& a, int& b, int& c) {
@@ -378,7 +527,13 @@ __global__ void __launch_bounds__(TPB)
         ctl->count[(s + 2) % 3] = 0;
         if (n > 0) atomicMax(&ctl->pad[0], s + 1);
     }
+    if (blockIdx.x * blockDim.x >= n) return;
     int* cnt_next = &ctl->count[(s + 1) % 3];
+    __shared__ int push_q[kPushCap];
+    __shared__ int push_n, push_base;
+    if (threadIdx.x == 0) push_n = 0;
+    __syncthreads();
+    const PushBuf pb{push_q, &push_n};
     for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
         const int c = qin[qi];
         float l = g[c];
@@ -392,34 +547,44 @@ __global__ void __launch_bounds__(TPB)
         const float4 w = pa[c];
         const float al[3] = {w.x, w.y, w.z};
         for (int k = 0; k < 3; ++k)
-            if (al[k] > 0.f && atomicSub(&rem[f[k]], 1) == 1) {
-                const int pos = atomicAdd(cnt_next, 1);
-                qout[pos] = f[k];
-            }
+            if (al[k] > 0.f && atomicSub(&rem[f[k]], 1) == 1) push_node(pb, f[k], qout, cnt_next);
     }
+    push_flush(pb, qout, cnt_next, &push_base);
 }
 
-__global__ void k_adj_remaining(const int* __restrict__ done, int n_v, GbpCtl* ctl) {
+__global__ void k_adj_remaining(const int* __restrict__ done, int n_v, int* __restrict__ list,
+                                GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_v && !done[i]) atomicAdd(&ctl->remaining, 1);
+    if (i < n_v && !done[i]) list[atomicAdd(&ctl->remaining, 1)] = i;
 }
 
-// Jacobi sweep over the vertices the level walk could not finish.
-__global__ void k_adj_jacobi(const int* __restrict__ done, const int* __restrict__ cptr,
-                             const int* __restrict__ cchild, const float* __restrict__ calpha,
-                             const float* __restrict__ g, const float* __restrict__ lam_in,
-                             float* __restrict__ lam_out, int n_v, GbpCtl* ctl) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_v) return;
-    if (done[i]) {
-        lam_out[i] = lam_in[i];
-        return;
+// Gauss-Seidel sweep (in place) over the vertices the level walk could not
+// finish because of a cycle in the parent graph.  Every cycle leaks weight to
+// parents outside it, so the sweeps contract to the unique solution.  Records
+// the largest |change| and the largest |lambda| of the sweep (as float bits).
+__global__ void k_adj_gs(const int* __restrict__ list, int n_list, const int* __restrict__ cptr,
+                         const int* __restrict__ cchild, const float* __restrict__ calpha,
+                         const float* __restrict__ g, float* lam, GbpCtl* ctl, int slot) {
+    // change of this sweep goes to slot (slot&1); the other slot is cleared for the next
+    int* md = slot & 1 ? &ctl->pad[2] : reinterpret_cast<int*>(&ctl->maxdiff);
+    int* md_next = slot & 1 ? reinterpret_cast<int*>(&ctl->maxdiff) : &ctl->pad[2];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *md_next = 0;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    float d = 0.f, a = 0.f;
+    if (q < n_list) {
+        const int i = list[q];
+        float l = g[i];
+        for (int x = cptr[i]; x < cptr[i + 1]; ++x) l += calpha[x] * lam[cchild[x]];
+        d = fabsf(l - lam[i]);
+        a = fabsf(l);
+        lam[i] = l;
     }
-    float l = g[i];
-    for (int x = cptr[i]; x < cptr[i + 1]; ++x) l += calpha[x] * lam_in[cchild[x]];
-    lam_out[i] = l;
-    const float d = fabsf(l - lam_in[i]) / fmaxf(1e-30f, fabsf(l));
-    atomicMax(reinterpret_cast<int*>(&ctl->maxdiff), __float_as_int(d));
+    d = block_max_f(d);
+    a = block_max_f(a);
+    if (threadIdx.x == 0) {
+        atomicMax(md, __float_as_int(d));
+        atomicMax(&ctl->pad[1], __float_as_int(a));
+    }
 }
 
 // ------------------------------------------------------------------ gradients
@@ -484,16 +649,23 @@ __global__ void k_grad_tet(const int4* __restrict__ tetv, const float4* __restri
     dsbar[j] = gs;
 }
 
+// dL/ds_n = 1/4 sum over the elements of n of dL/dsbar_j; 16 lanes per vertex,
+// fixed reduction order.
 __global__ void k_grad_node(const int2* __restrict__ nptr, const int* __restrict__ nent,
                             const float* __restrict__ dsbar, const int* __restrict__ node_user,
                             int n_v, float* __restrict__ dvs_user) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_v) return;
+    const int lane = threadIdx.x & 15;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (i >= n_v) return;                           // uniform over the 16-lane group
     const int2 p = nptr[i];
     const int tot = (p.y & 255) + ((p.y >> 8) & 255) + ((p.y >> 16) & 255) + ((p.y >> 24) & 255);
     float s = 0.f;
-    for (int c = 0; c < tot; ++c) s += dsbar[nent[p.x + c]];
-    dvs_user[node_user[i]] = 0.25f * s;
+    for (int c = lane; c < tot; c += 16) s += dsbar[nent[p.x + c]];
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    if (lane == 0) dvs_user[node_user[i]] = 0.25f * s;
 }
 
 __global__ void k_grad_root(const int* __restrict__ root_node, const float* __restrict__ root_t,
@@ -572,16 +744,30 @@ __global__ void k_scan_block(const int* __restrict__ in, int* __restrict__ out, 
     if (threadIdx.x == 255) bsum[blockIdx.x] = sh[255];
 }
 
-__global__ void k_scan_top(int* __restrict__ bsum, int nb, int* __restrict__ total_out) {
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int b = 0; b < nb; ++b) {
-            const int t = bsum[b];
-            bsum[b] = run;
-            run += t;
+// Exclusive scan of the block sums by one block of 1024 threads (chunks of 1024).
+__global__ void __launch_bounds__(1024) k_scan_top(int* __restrict__ bsum, int nb,
+                                                   int* __restrict__ total_out) {
+    __shared__ int sh[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int idx = base + threadIdx.x;
+        const int v = idx < nb ? bsum[idx] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
         }
-        *total_out = run;
+        if (idx < nb) bsum[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *total_out = carry;
 }
 
 __global__ void k_scan_add(int* __restrict__ out, int n, const int* __restrict__ bsum) {
@@ -594,14 +780,14 @@ __global__ void k_scan_add(int* __restrict__ out, int n, const int* __restrict__
 int gbp_scan_exclusive(const int* in, int* out, int n, int* tmp, hipStream_t s) {
     const int nb = (n + 1023) / 1024;
     k_scan_block<<<nb, 256, 0, s>>>(in, out, n, tmp);
-    k_scan_top<<<1, 64, 0, s>>>(tmp, nb, out + n);
+    k_scan_top<<<1, 1024, 0, s>>>(tmp, nb, out + n);
     k_scan_add<<<gbp_blocks(n, TPB), TPB, 0, s>>>(out, n, tmp);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
 
 // ====================================================================== host
-static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB), 2048); }
+static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB / 32), 2048); }
 
 static int read_ctl(gbp_plan p, hipStream_t s) {
     GBP_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
@@ -649,8 +835,11 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     const int n_v = p->n_v, n_e = p->n_e;
     GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
     k_vscale_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, p->node_user, p->vs, n_v, p->ctl);
-    k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs, p->tetg,
-                                                  n_e, p->ctl);
+    {
+        ProfScope ps(GBP_PROF_METRIC, s);
+        k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs,
+                                                      p->tetg, n_e, p->ctl);
+    }
     k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, GBP_INF, n_v);
     if (cold == 1) {
         k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, GBP_INF, n_v);
@@ -682,6 +871,7 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
     const int n_v = p->n_v;
     const bool cold = (T_init == nullptr);
     if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
+    k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
     if (!cold) {
         k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, p->stamp, n_v, p->ctl);
         GBP_LAUNCH_CHECK();
@@ -698,14 +888,15 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
             const int* qin = p->q[sweep & 1];
             int* qout = p->q[(sweep + 1) & 1];
             const int st = p->stamp + sweep + 1;
+            ProfScope ps(GBP_PROF_FIM_SWEEP, s);
             if (cold)
                 k_sweep<false><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
                                                     p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
-                                                    p->ctl, sweep, st, p->eps_rel);
+                                                    p->ctl, p->blk, sweep, st, p->eps_rel);
             else
                 k_sweep<true><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
                                                    p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
-                                                   p->ctl, sweep, st, p->eps_rel);
+                                                   p->ctl, p->blk, sweep, st, p->eps_rel);
         }
         GBP_LAUNCH_CHECK();
         if ((rc = read_ctl(p, s))) return rc;
@@ -713,6 +904,7 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
         batch = std::min(batch * 2, 16);
     }
     p->stamp += sweep + 2;
+    k_reduce_stats<<<1, TPB, 0, s>>>(p->blk, p->ctl);
     k_count_inf<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, n_v, p->ctl);
     k_scatter_out<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, p->node_int, T_out, n_v);
     GBP_LAUNCH_CHECK();
@@ -733,10 +925,11 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
 }
 
 // parents at the converged T (internal order); T must already be in p->T
-static int run_parents(gbp_plan p, hipStream_t s) {
+static int run_parents(gbp_plan p, const float* D_in, hipStream_t s) {
     const int n_v = p->n_v;
-    k_parent<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->T,
-                                                  p->troot, n_v, p->par, p->pa);
+    ProfScope ps(GBP_PROF_PARENT, s);
+    k_parent<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tet_user, D_in,
+                                                  p->vs, p->xyz, p->T, p->troot, n_v, p->par, p->pa);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -756,11 +949,20 @@ extern "C" int gbp_parent_map(gbp_plan p, const float* D, const float* vscale,
     if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
     if ((rc = read_ctl(p, s))) return rc;
     if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
-    if ((rc = run_parents(p, s))) return rc;
+    if ((rc = run_parents(p, D, s))) return rc;
     k_parent_out<<<gbp_blocks(p->n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, p->tet_user,
                                                          p->node_user, p->node_int, p->n_v,
                                                          par_tet, par_node, par_alpha, best);
     GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_backward_info(gbp_plan p, int* levels, int* cyclic, int* gs_sweeps) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (levels) *levels = p->bwd_levels;
+    if (cyclic) *cyclic = p->bwd_cyclic;
+    if (gs_sweeps) *gs_sweeps = p->bwd_gs_sweeps;
     return GBP_OK;
 }
 
@@ -780,8 +982,10 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
     if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
     if ((rc = read_ctl(p, s))) return rc;
     if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
-    if ((rc = run_parents(p, s))) return rc;
+    if ((rc = run_parents(p, D, s))) return rc;
     // children lists
+    {
+    ProfScope ps_child(GBP_PROF_CHILD, s);
     GBP_HIP(hipMemsetAsync(p->rem, 0, sizeof(int) * n_v, s));
     GBP_HIP(hipMemsetAsync(p->cfill, 0, sizeof(int) * n_v, s));
     k_child_count<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->rem);
@@ -790,6 +994,7 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
     k_child_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->ccnt,
                                                       p->cfill, p->cchild, p->calpha);
     k_child_sort<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
+    }
     // level walk
     GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
@@ -802,44 +1007,54 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
     bool empty = (p->ctl_host->count[0] == 0);
     const int cap = p->max_rounds + n_v;
     while (!empty && level < cap) {
-        for (int b = 0; b < batch; ++b, ++level)
+        for (int b = 0; b < batch; ++b, ++level) {
+            ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
             k_adj_level<<<grid, TPB, 0, s>>>(p->q[level & 1], p->q[(level + 1) & 1], p->ccnt,
                                               p->cchild, p->calpha, p->g, p->lam, p->done, p->par,
                                               p->pa, p->tetv, p->rem, p->ctl, level);
+        }
         GBP_LAUNCH_CHECK();
         if ((rc = read_ctl(p, s))) return rc;
         empty = (p->ctl_host->count[level % 3] == 0);
         batch = std::min(batch * 2, 16);
     }
-    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->ctl);
+    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->q[0], p->ctl);
     GBP_LAUNCH_CHECK();
     if ((rc = read_ctl(p, s))) return rc;
+    p->bwd_levels = level;
+    p->bwd_cyclic = p->ctl_host->remaining;
+    p->bwd_gs_sweeps = 0;
     if (p->ctl_host->remaining > 0) {
-        // cycles in the parent graph: Jacobi on the unfinished vertices
+        const int nl = p->ctl_host->remaining;
         bool ok = false;
-        for (int it = 0; it < 4 * p->max_rounds && !ok; it += 16) {
-            for (int b = 0; b < 16; ++b) {
-                GBP_HIP(hipMemsetAsync(&p->ctl->maxdiff, 0, sizeof(float), s));
-                k_adj_jacobi<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, p->ccnt, p->cchild,
-                                                                  p->calpha, p->g, p->lam,
-                                                                  p->lam2, n_v, p->ctl);
-                std::swap(p->lam, p->lam2);
+        int it = 0;
+        const int cap = 4 * p->max_rounds + 1000;
+        while (!ok && it < cap) {
+            for (int b = 0; b < 16; ++b, ++it) {
+                ProfScope ps_gs(GBP_PROF_AUX, s);
+                k_adj_gs<<<gbp_blocks(nl, TPB), TPB, 0, s>>>(p->q[0], nl, p->ccnt, p->cchild,
+                                                             p->calpha, p->g, p->lam, p->ctl, it);
             }
             GBP_LAUNCH_CHECK();
             if ((rc = read_ctl(p, s))) return rc;
-            ok = p->ctl_host->maxdiff <= 1e-7f;
+            const float lmax = __builtin_bit_cast(float, p->ctl_host->pad[1]);
+            const int last = (it - 1) & 1;
+            const float md = last ? __builtin_bit_cast(float, p->ctl_host->pad[2]) : p->ctl_host->maxdiff;
+            ok = md <= 1e-6f * lmax;
         }
+        p->bwd_gs_sweeps = it;
         if (!ok) {
-            gbp_set_error("adjoint did not settle on %d cyclic vertices", p->ctl_host->remaining);
+            gbp_set_error("adjoint did not settle on %d vertices left by parent-graph cycles", nl);
             return GBP_ERR_NOT_CONVERGED;
         }
     }
     // gradients
+    ProfScope ps_grad(GBP_PROF_GRAD, s);
     k_grad_tet<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(p->tetv, p->tetg, p->xyz, D, p->tet_user,
                                                     p->par, p->pa, p->lam, n_e, dL_dD, p->dsbar);
     if (dL_dvscale)
-        k_grad_node<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->dsbar, p->node_user,
-                                                         n_v, dL_dvscale);
+        k_grad_node<<<gbp_blocks(16LL * n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->dsbar,
+                                                                p->node_user, n_v, dL_dvscale);
     if (dL_droot_t && n_roots > 0)
         k_grad_root<<<gbp_blocks(n_roots, TPB), TPB, 0, s>>>(root_node, root_t, n_roots,
                                                              p->node_int, n_v, p->par, p->troot,

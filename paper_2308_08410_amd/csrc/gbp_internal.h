@@ -80,10 +80,12 @@ struct gbp_plan_s {
     int* mark = nullptr;          // [n_v] queue stamps
     int stamp = 1;                // next stamp base (host side)
     GbpCtl* ctl = nullptr;        // device control block
+    unsigned long long* blk = nullptr;  // [2 * kStatBlocks] per-block (solves, updates)
     GbpCtl* ctl_host = nullptr;   // pinned mirror
 
     // backward workspace (allocated on first use)
     bool bwd_ready = false;
+    int bwd_levels = 0, bwd_cyclic = 0, bwd_gs_sweeps = 0;   // last backward
     int* par = nullptr;           // [n_v] (element << 2 | local slot) or -1
     float4* pa = nullptr;         // [n_v] (alpha0, alpha1, alpha2, best)
     int* ccnt = nullptr;          // [n_v+1] children per node, then exclusive scan
@@ -98,6 +100,8 @@ struct gbp_plan_s {
     int* done = nullptr;          // [n_v] adjoint finished flag
     int* scan_tmp = nullptr;      // block sums
 };
+
+constexpr int kStatBlocks = 2048;   // max grid of the relaxation kernels
 
 int gbp_plan_check(gbp_plan p);
 int gbp_alloc_backward(gbp_plan p);

@@ -24,9 +24,18 @@
 
 #define GBP_INF __builtin_huge_valf()
 
-struct LocalQ {
-    float q00, q11, q22, q01, q02, q12;
+template <typename R>
+struct LocalQT {
+    R q00, q11, q22, q01, q02, q12;
 };
+using LocalQ = LocalQT<float>;
+
+__device__ __forceinline__ float gbp_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double gbp_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float gbp_sqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double gbp_sqrt(double x) { return __builtin_sqrt(x); }
+template <typename R>
+__device__ __forceinline__ R gbp_inf() { return (R)__builtin_huge_val(); }
 
 // Element data: G = F^T M F with F_a = v_a - v_0 (a = 1..3), packed as
 // g0 = (G11, G22, G33, G12), g1 = (G13, G23, sbar, 0).  Q of the face opposite
@@ -63,6 +72,38 @@ __device__ __forceinline__ LocalQ face_q(const float4 g0, const float4 g1) {
     return q;
 }
 
+// Same, with the slot known only at run time (selects, no divergence).  With
+// G4 the 4x4 Gram of (0, F1, F2, F3), the face opposite K uses the other three
+// indices o0 < o1 < o2 and Q_ab = G4[oa][ob] - G4[oa][K] - G4[K][ob] + G4[K][K];
+// column K of G4 vanishes at row 0, which removes most terms.
+__device__ __forceinline__ LocalQ face_q_rt(const float4 g0, const float4 g1, int K) {
+    const float G11 = g0.x, G22 = g0.y, G33 = g0.z, G12 = g0.w, G13 = g1.x, G23 = g1.y;
+    const bool k0 = K == 0, k1 = K == 1, k2 = K == 2;
+    const float d = k0 ? 0.f : k1 ? G11 : k2 ? G22 : G33;        // G4[K][K]
+    const float c1 = k0 ? 0.f : k1 ? G12 : k2 ? G12 : G13;       // G4[o1][K]
+    const float c2 = k0 ? 0.f : k1 ? G13 : k2 ? G23 : G23;       // G4[o2][K]
+    const float g00 = k0 ? G11 : 0.f;                            // G4[o0][o0]
+    const float g11 = (k0 || k1) ? G22 : G11;                    // G4[o1][o1]
+    const float g22 = (K <= 2) ? G33 : G22;                      // G4[o2][o2]
+    const float g01 = k0 ? G12 : 0.f;                            // G4[o0][o1]
+    const float g02 = k0 ? G13 : 0.f;                            // G4[o0][o2]
+    const float g12 = (k0 || k1) ? G23 : k2 ? G13 : G12;         // G4[o1][o2]
+    LocalQ q;
+    q.q00 = g00 + d;
+    q.q11 = g11 - 2.f * c1 + d;
+    q.q22 = g22 - 2.f * c2 + d;
+    q.q01 = g01 - c1 + d;
+    q.q02 = g02 - c2 + d;
+    q.q12 = g12 - c1 - c2 + d;
+    return q;
+}
+
+__device__ __forceinline__ void face_nodes_sel(const int4 v, int K, int& a, int& b, int& c) {
+    a = (K == 0) ? v.y : v.x;
+    b = (K <= 1) ? v.z : v.y;
+    c = (K <= 2) ? v.w : v.z;
+}
+
 // Face vertices of the face opposite local vertex K (in increasing local order).
 template <int K>
 __device__ __forceinline__ void face_nodes(const int4 v, int& a, int& b, int& c) {
@@ -81,99 +122,102 @@ __device__ __forceinline__ int face_target(const int4 v) {
 }
 
 // Two-vertex candidate on the edge (a, b) of the face.
-__device__ __forceinline__ void edge_candidate(float qaa, float qbb, float qab, float Pa, float Pb,
-                                               bool ok, float& val, float& ua, float& ub) {
-    const float wa = qbb - qab, wb = qaa - qab;
-    const float at = wa + wb;                       // |e_b - e_a|^2_M > 0
-    const float inv = __builtin_amdgcn_rcpf(at);
-    const float pbar = (wa * Pa + wb * Pb) * inv;
-    const float d = Pb - Pa;
-    const float det = qaa * qbb - qab * qab;
-    const float rad = det * (at - d * d) * inv * inv;
-    const float r = __builtin_sqrtf(fmaxf(rad, 0.f));
-    const float pca = Pa - pbar, pcb = Pb - pbar;
+template <typename R>
+__device__ __forceinline__ void edge_candidate(R qaa, R qbb, R qab, R Pa, R Pb, bool ok, R& val,
+                                               R& ua, R& ub) {
+    const R wa = qbb - qab, wb = qaa - qab;
+    const R at = wa + wb;                           // |e_b - e_a|^2_M > 0
+    const R inv = gbp_rcp(at);
+    const R pbar = (wa * Pa + wb * Pb) * inv;
+    const R d = Pb - Pa;
+    const R det = qaa * qbb - qab * qab;
+    const R rad = det * (at - d * d) * inv * inv;
+    const R r = gbp_sqrt(rad > R(0) ? rad : R(0));
+    const R pca = Pa - pbar, pcb = Pb - pbar;
     ua = r * wa - (qbb * pca - qab * pcb);
     ub = r * wb - (qaa * pcb - qab * pca);
-    const bool feas = ok && (rad > 0.f) && (ua >= 0.f) && (ub >= 0.f);
-    val = feas ? pbar + r : GBP_INF;
+    const bool feas = ok && (rad > R(0)) && (ua >= R(0)) && (ub >= R(0));
+    val = feas ? pbar + r : gbp_inf<R>();
 }
 
-// Full local solve.  Returns the minimum (GBP_INF if all three vertices are
-// unreached).  With WANT_ALPHA also the minimiser's barycentric weights.
-template <bool WANT_ALPHA>
-__device__ __forceinline__ float local_min(const LocalQ q, float p0, float p1, float p2,
-                                           float* a0 = nullptr, float* a1 = nullptr,
-                                           float* a2 = nullptr) {
-    const bool f0 = p0 < GBP_INF, f1 = p1 < GBP_INF, f2 = p2 < GBP_INF;
-    const float m = fminf(fminf(p0, p1), p2);
-    const float P0 = f0 ? p0 - m : 0.f;
-    const float P1 = f1 ? p1 - m : 0.f;
-    const float P2 = f2 ? p2 - m : 0.f;
+// Full local solve in precision R.  Returns the minimum (+inf if all three
+// vertices are unreached).  With WANT_ALPHA also the minimiser's barycentric
+// weights.  Candidate order (first wins on ties): vertices 0,1,2, edges 01,02,12,
+// interior.
+template <bool WANT_ALPHA, typename R = float>
+__device__ __forceinline__ R local_min(const LocalQT<R> q, R p0, R p1, R p2, R* a0 = nullptr,
+                                       R* a1 = nullptr, R* a2 = nullptr) {
+    const R INF = gbp_inf<R>();
+    const bool f0 = p0 < INF, f1 = p1 < INF, f2 = p2 < INF;
+    const R m = fmin(fmin(p0, p1), p2);
+    const R P0 = f0 ? p0 - m : R(0);
+    const R P1 = f1 ? p1 - m : R(0);
+    const R P2 = f2 ? p2 - m : R(0);
 
     // vertex candidates
-    float best = f0 ? P0 + __builtin_sqrtf(q.q00) : GBP_INF;
-    float b0 = 1.f, b1 = 0.f, b2 = 0.f;
+    R best = f0 ? P0 + gbp_sqrt(q.q00) : INF;
+    R b0 = 1, b1 = 0, b2 = 0;
     {
-        const float v = f1 ? P1 + __builtin_sqrtf(q.q11) : GBP_INF;
-        if (v < best) { best = v; if (WANT_ALPHA) { b0 = 0.f; b1 = 1.f; b2 = 0.f; } }
+        const R v = f1 ? P1 + gbp_sqrt(q.q11) : INF;
+        if (v < best) { best = v; if (WANT_ALPHA) { b0 = 0; b1 = 1; b2 = 0; } }
     }
     {
-        const float v = f2 ? P2 + __builtin_sqrtf(q.q22) : GBP_INF;
-        if (v < best) { best = v; if (WANT_ALPHA) { b0 = 0.f; b1 = 0.f; b2 = 1.f; } }
+        const R v = f2 ? P2 + gbp_sqrt(q.q22) : INF;
+        if (v < best) { best = v; if (WANT_ALPHA) { b0 = 0; b1 = 0; b2 = 1; } }
     }
     // edge candidates
     {
-        float v, ua, ub;
-        edge_candidate(q.q00, q.q11, q.q01, P0, P1, f0 && f1, v, ua, ub);
+        R v, ua, ub;
+        edge_candidate<R>(q.q00, q.q11, q.q01, P0, P1, f0 && f1, v, ua, ub);
         if (v < best) {
             best = v;
-            if (WANT_ALPHA) { const float s = 1.f / (ua + ub); b0 = ua * s; b1 = ub * s; b2 = 0.f; }
+            if (WANT_ALPHA) { const R s = R(1) / (ua + ub); b0 = ua * s; b1 = ub * s; b2 = 0; }
         }
     }
     {
-        float v, ua, ub;
-        edge_candidate(q.q00, q.q22, q.q02, P0, P2, f0 && f2, v, ua, ub);
+        R v, ua, ub;
+        edge_candidate<R>(q.q00, q.q22, q.q02, P0, P2, f0 && f2, v, ua, ub);
         if (v < best) {
             best = v;
-            if (WANT_ALPHA) { const float s = 1.f / (ua + ub); b0 = ua * s; b1 = 0.f; b2 = ub * s; }
+            if (WANT_ALPHA) { const R s = R(1) / (ua + ub); b0 = ua * s; b1 = 0; b2 = ub * s; }
         }
     }
     {
-        float v, ua, ub;
-        edge_candidate(q.q11, q.q22, q.q12, P1, P2, f1 && f2, v, ua, ub);
+        R v, ua, ub;
+        edge_candidate<R>(q.q11, q.q22, q.q12, P1, P2, f1 && f2, v, ua, ub);
         if (v < best) {
             best = v;
-            if (WANT_ALPHA) { const float s = 1.f / (ua + ub); b0 = 0.f; b1 = ua * s; b2 = ub * s; }
+            if (WANT_ALPHA) { const R s = R(1) / (ua + ub); b0 = 0; b1 = ua * s; b2 = ub * s; }
         }
     }
     // interior candidate
     {
-        const float A00 = q.q11 * q.q22 - q.q12 * q.q12;
-        const float A11 = q.q00 * q.q22 - q.q02 * q.q02;
-        const float A22 = q.q00 * q.q11 - q.q01 * q.q01;
-        const float A01 = q.q02 * q.q12 - q.q01 * q.q22;
-        const float A02 = q.q01 * q.q12 - q.q02 * q.q11;
-        const float A12 = q.q01 * q.q02 - q.q00 * q.q12;
-        const float det = q.q00 * A00 + q.q01 * A01 + q.q02 * A02;
-        const float w0 = A00 + A01 + A02, w1 = A01 + A11 + A12, w2 = A02 + A12 + A22;
-        const float at = w0 + w1 + w2;
-        const float inv = __builtin_amdgcn_rcpf(at);
-        const float pbar = (w0 * P0 + w1 * P1 + w2 * P2) * inv;
-        const float c0 = P0 - pbar, c1 = P1 - pbar, c2 = P2 - pbar;
-        const float y0 = A00 * c0 + A01 * c1 + A02 * c2;
-        const float y1 = A01 * c0 + A11 * c1 + A12 * c2;
-        const float y2 = A02 * c0 + A12 * c1 + A22 * c2;
-        const float s = c0 * y0 + c1 * y1 + c2 * y2;
-        const float rad = (det - s) * inv;
-        const float r = __builtin_sqrtf(fmaxf(rad, 0.f));
-        const float u0 = r * w0 - y0, u1 = r * w1 - y1, u2 = r * w2 - y2;
-        const bool feas = f0 && f1 && f2 && (rad > 0.f) && (u0 >= 0.f) && (u1 >= 0.f) && (u2 >= 0.f);
-        const float v = feas ? pbar + r : GBP_INF;
+        const R A00 = q.q11 * q.q22 - q.q12 * q.q12;
+        const R A11 = q.q00 * q.q22 - q.q02 * q.q02;
+        const R A22 = q.q00 * q.q11 - q.q01 * q.q01;
+        const R A01 = q.q02 * q.q12 - q.q01 * q.q22;
+        const R A02 = q.q01 * q.q12 - q.q02 * q.q11;
+        const R A12 = q.q01 * q.q02 - q.q00 * q.q12;
+        const R det = q.q00 * A00 + q.q01 * A01 + q.q02 * A02;
+        const R w0 = A00 + A01 + A02, w1 = A01 + A11 + A12, w2 = A02 + A12 + A22;
+        const R at = w0 + w1 + w2;
+        const R inv = gbp_rcp(at);
+        const R pbar = (w0 * P0 + w1 * P1 + w2 * P2) * inv;
+        const R c0 = P0 - pbar, c1 = P1 - pbar, c2 = P2 - pbar;
+        const R y0 = A00 * c0 + A01 * c1 + A02 * c2;
+        const R y1 = A01 * c0 + A11 * c1 + A12 * c2;
+        const R y2 = A02 * c0 + A12 * c1 + A22 * c2;
+        const R s = c0 * y0 + c1 * y1 + c2 * y2;
+        const R rad = (det - s) * inv;
+        const R r = gbp_sqrt(rad > R(0) ? rad : R(0));
+        const R u0 = r * w0 - y0, u1 = r * w1 - y1, u2 = r * w2 - y2;
+        const bool feas = f0 && f1 && f2 && (rad > R(0)) && (u0 >= R(0)) && (u1 >= R(0)) && (u2 >= R(0));
+        const R v = feas ? pbar + r : INF;
         if (v < best) {
             best = v;
-            if (WANT_ALPHA) { const float sc = 1.f / (u0 + u1 + u2); b0 = u0 * sc; b1 = u1 * sc; b2 = u2 * sc; }
+            if (WANT_ALPHA) { const R sc = R(1) / (u0 + u1 + u2); b0 = u0 * sc; b1 = u1 * sc; b2 = u2 * sc; }
         }
     }
     if (WANT_ALPHA) { *a0 = b0; *a1 = b1; *a2 = b2; }
-    return (best < GBP_INF) ? m + best : GBP_INF;
+    return (best < INF) ? m + best : INF;
 }

@@ -69,7 +69,7 @@ static void plan_free(gbp_plan p) {
     if (!p) return;
     void* ptrs[] = {p->xyz, p->tetv, p->tet_user, p->node_user, p->node_int, p->nptr, p->nent,
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
-                    p->mark, p->ctl, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
+                    p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
                     p->calpha, p->lam, p->lam2, p->g, p->dsbar, p->done, p->scan_tmp};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -293,6 +293,7 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(dalloc(&p->q[1], n_v));
     TRY(dalloc(&p->mark, n_v));
     TRY(dalloc(&p->ctl, 1));
+    TRY(dalloc(&p->blk, 2 * (size_t)kStatBlocks));
 #undef TRY
     if (hipMemset(p->mark, 0, sizeof(int) * n_v) != hipSuccess ||
         hipMemset(p->ctl, 0, sizeof(GbpCtl)) != hipSuccess) {
