@@ -138,10 +138,13 @@ int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
 
 /*
  * gbp_backward_info -- diagnostics of the last gbp_eikonal_backward on this
- * plan: number of leaves-first levels walked, vertices that the walk could not
- * finish because they lie on or above a cycle of the parent graph (possible in
- * anisotropic media, where a face vertex may be later than the vertex it
- * updates), and Gauss-Seidel sweeps used to finish them.  Any pointer may be NULL.
+ * plan.  The adjoint walks the parent graph leaves-first in levels; two vertices
+ * that are each other's weighted parents (possible in anisotropic media, where
+ * a face vertex may be later than the vertex it updates) are solved together as
+ * a 2x2 system.  `levels` is the number of levels walked, `cyclic` the number of
+ * vertices the walk could not finish (on or above a longer cycle), and
+ * `gs_sweeps` the Gauss-Seidel sweeps used to finish those.  Any pointer may be
+ * NULL.
  */
 int gbp_backward_info(gbp_plan plan, int *levels, int *cyclic, int *gs_sweeps);
 

@@ -249,10 +249,24 @@ __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restric
     e += cnt;
 }
 
-// One relaxation round.  Each vertex of the queue is handled by a half-wave
-// (32 lanes): lane c evaluates the c-th local problem of the vertex's patch
-// (slot picked at run time), a half-wave min-reduction forms the Hopf-Lax
-// minimum, and on a change the lanes push the unique neighbours in parallel.
+// One relaxation round.  Each vertex of the queue is handled by 16 lanes; lane c
+// evaluates local problems c and c+16 of the vertex's patch (slot picked at run
+// time, both problems' loads in flight together), a 16-lane min-reduction forms
+// the Hopf-Lax minimum, and on a change the lanes push the unique neighbours.
+constexpr int kLanesPerVertex = 16;
+
+__device__ __forceinline__ float face_value(const int* __restrict__ nent,
+                                            const int4* __restrict__ tetv,
+                                            const float4* __restrict__ tetg, const float* T,
+                                            int e, int K) {
+    const int t = nent[e];
+    const int4 v = tetv[t];
+    const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
+    int a, b, cc;
+    face_nodes_sel(v, K, a, b, cc);
+    return local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]);
+}
+
 template <bool TWO_SIDED>
 __global__ void __launch_bounds__(TPB)
     k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
@@ -261,51 +275,54 @@ __global__ void __launch_bounds__(TPB)
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
             int stamp_next, float eps_rel) {
+    constexpr int L = kLanesPerVertex;
+    constexpr int PER_BLOCK = TPB / L;
     const int n = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
         if (n > 0) atomicMax(&ctl->pad[0], s + 1);
     }
-    if (blockIdx.x * (TPB / 32) >= n) return;       // no vertex for this block
+    if (blockIdx.x * PER_BLOCK >= n) return;        // no vertex for this block
     int* cnt_next = &ctl->count[(s + 1) % 3];
     __shared__ int push_q[kPushCap];
     __shared__ int push_n, push_base;
     if (threadIdx.x == 0) push_n = 0;
     __syncthreads();
     const PushBuf pb{push_q, &push_n};
-    const int lane = threadIdx.x & 31;
-    const int sub = threadIdx.x >> 5;               // vertex slot of this half-wave
-    constexpr int PER_BLOCK = TPB / 32;
+    const int lane = threadIdx.x & (L - 1);
+    const int sub = threadIdx.x / L;                // vertex slot of this lane group
     unsigned long long solves = 0, upd = 0;
     for (int base = blockIdx.x * PER_BLOCK; base < n; base += gridDim.x * PER_BLOCK) {
         const int qi = base + sub;
-        const bool act = qi < n;                    // uniform over the half-wave
+        const bool act = qi < n;                    // uniform over the lane group
         const int i = act ? qin[qi] : 0;
         const int2 p = act ? nptr[i] : make_int2(0, 0);
+        const float told = T[i];
+        const float tr = TWO_SIDED ? troot[i] : 0.f;
+        const int adj0 = adj_ptr[i], adj1 = adj_ptr[i + 1];
         const int c0 = p.y & 255, c1 = (p.y >> 8) & 255, c2 = (p.y >> 16) & 255,
                   c3 = (p.y >> 24) & 255;
-        const int tot = c0 + c1 + c2 + c3;
+        const int e01 = c0 + c1, e012 = e01 + c2;
+        const int tot = e012 + c3;
         float best = GBP_INF;
-        for (int c = lane; c < tot; c += 32) {
-            const int K = (c < c0) ? 0 : (c < c0 + c1) ? 1 : (c < c0 + c1 + c2) ? 2 : 3;
-            const int t = nent[p.x + c];
-            const int4 v = tetv[t];
-            const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
-            int a, b, cc;
-            face_nodes_sel(v, K, a, b, cc);
-            best = fminf(best, local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]));
-            ++solves;
+        for (int c = lane; c < tot; c += 2 * L) {
+            const int d = c + L;
+            const bool okd = d < tot;
+            const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
+            const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
+            const float vc = face_value(nent, tetv, tetg, T, p.x + c, Kc);
+            const float vd = face_value(nent, tetv, tetg, T, p.x + (okd ? d : c), Kd);
+            best = fminf(best, okd ? fminf(vc, vd) : vc);
+            solves += okd ? 2 : 1;
         }
-        best = fminf(best, __shfl_xor(best, 16));
         best = fminf(best, __shfl_xor(best, 8));
         best = fminf(best, __shfl_xor(best, 4));
         best = fminf(best, __shfl_xor(best, 2));
         best = fminf(best, __shfl_xor(best, 1));
         if (!act) continue;
-        const float told = T[i];
         bool changed;
         if (TWO_SIDED) {
-            best = fminf(best, troot[i]);
+            best = fminf(best, tr);
             if (lane == 0 && best != told) T[i] = best;
             const bool bf = best < GBP_INF, tf = told < GBP_INF;
             changed = (bf != tf) ||
@@ -317,8 +334,7 @@ __global__ void __launch_bounds__(TPB)
         }
         if (changed) {
             if (lane == 0) ++upd;
-            const int a1 = adj_ptr[i + 1];
-            for (int a = adj_ptr[i] + lane; a < a1; a += 32) {
+            for (int a = adj0 + lane; a < adj1; a += L) {
                 const int nb = adj[a];
                 if (atomicMax(&mark[nb], stamp_next) < stamp_next) push_node(pb, nb, qout, cnt_next);
             }
@@ -444,34 +460,86 @@ __device__ __forceinline__ int face_target_rt(const int4 v, int K) {
 }
 
 // ------------------------------------------------------------------ adjoint
-__global__ void k_child_count(const int* __restrict__ par, const float4* __restrict__ pa,
-                              const int4* __restrict__ tetv, int n_v, int* __restrict__ cnt) {
+// Parent face vertices carrying weight, and two-cycle detection: a and c are
+// partners when each is a weighted parent of the other (the anisotropic scheme
+// is not causal).  The mutual edges are left out of the readiness counts; the
+// pair is solved jointly once both members' other children are finished.
+__global__ void k_pnodes(const int* __restrict__ par, const float4* __restrict__ pa,
+                         const int4* __restrict__ tetv, int n_v, int4* __restrict__ pnode) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_v) return;
     const int pr = par[c];
-    if (pr < 0) return;
-    int f[3];
-    face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
-    const float4 w = pa[c];
-    const float al[3] = {w.x, w.y, w.z};
-    for (int k = 0; k < 3; ++k)
-        if (al[k] > 0.f) atomicAdd(&cnt[f[k]], 1);
+    int4 out = make_int4(-1, -1, -1, -1);
+    if (pr >= 0) {
+        int f[3];
+        face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+        const float4 w = pa[c];
+        out.x = w.x > 0.f ? f[0] : -1;
+        out.y = w.y > 0.f ? f[1] : -1;
+        out.z = w.z > 0.f ? f[2] : -1;
+    }
+    pnode[c] = out;
 }
 
-__global__ void k_child_fill(const int* __restrict__ par, const float4* __restrict__ pa,
-                             const int4* __restrict__ tetv, int n_v, const int* __restrict__ cptr,
-                             int* __restrict__ cfill, int* __restrict__ cchild,
-                             float* __restrict__ calpha) {
+__device__ __forceinline__ bool has_parent(int4 pn, int x) {
+    return pn.x == x || pn.y == x || pn.z == x;
+}
+
+__global__ void k_partner(const int4* __restrict__ pnode, int n_v, int* __restrict__ partner) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    const int4 pn = pnode[a];
+    const int cand[3] = {pn.x, pn.y, pn.z};
+    int best = -1;
+    for (int k = 0; k < 3; ++k)
+        if (cand[k] >= 0 && has_parent(pnode[cand[k]], a) && (best < 0 || cand[k] < best))
+            best = cand[k];
+    partner[a] = best;
+}
+
+// keep a pair only if both members chose each other; prime the pair counter
+// (pairrem: 2 at the smaller member of a pair, -1 at the larger, 0 elsewhere)
+__global__ void k_partner_sym(const int* __restrict__ partner, int n_v, int* __restrict__ pairrem) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    const int c = partner[a];
+    const bool ok = c >= 0 && partner[c] == a;
+    pairrem[a] = ok ? (a < c ? 2 : -1) : 0;
+}
+
+__global__ void k_partner_fix(int* __restrict__ partner, int* __restrict__ pairrem, int n_v) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    const int r = pairrem[a];
+    if (r == 0) partner[a] = -1;
+    if (r < 0) pairrem[a] = 0;
+}
+
+__global__ void k_child_count(const int4* __restrict__ pnode, const int* __restrict__ partner,
+                              int n_v, int* __restrict__ cnt_all, int* __restrict__ cnt_wait) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_v) return;
-    const int pr = par[c];
-    if (pr < 0) return;
-    int f[3];
-    face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
+    const int4 pn = pnode[c];
+    const int f[3] = {pn.x, pn.y, pn.z};
+    const int q = partner[c];
+    for (int k = 0; k < 3; ++k)
+        if (f[k] >= 0) {
+            atomicAdd(&cnt_all[f[k]], 1);
+            if (f[k] != q) atomicAdd(&cnt_wait[f[k]], 1);
+        }
+}
+
+__global__ void k_child_fill(const int4* __restrict__ pnode, const float4* __restrict__ pa,
+                             int n_v, const int* __restrict__ cptr, int* __restrict__ cfill,
+                             int* __restrict__ cchild, float* __restrict__ calpha) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_v) return;
+    const int4 pn = pnode[c];
+    const int f[3] = {pn.x, pn.y, pn.z};
     const float4 w = pa[c];
     const float al[3] = {w.x, w.y, w.z};
     for (int k = 0; k < 3; ++k)
-        if (al[k] > 0.f) {
+        if (f[k] >= 0) {
             const int pos = cptr[f[k]] + atomicAdd(&cfill[f[k]], 1);
             cchild[pos] = c;
             calpha[pos] = al[k];
@@ -516,12 +584,26 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
     }
 }
 
+__device__ __forceinline__ void release_parents(int x, int skip, const int4* __restrict__ pnode,
+                                                int* __restrict__ rem, PushBuf pb,
+                                                int* __restrict__ qout, int* cnt_next) {
+    const int4 pn = pnode[x];
+    const int f[3] = {pn.x, pn.y, pn.z};
+    for (int k = 0; k < 3; ++k)
+        if (f[k] >= 0 && f[k] != skip && atomicSub(&rem[f[k]], 1) == 1)
+            push_node(pb, f[k], qout, cnt_next);
+}
+
+// One leaves-first level: every queued vertex has all (non-partner) children
+// finished.  A vertex pulls lambda = g + sum alpha_c lambda_c in child order;
+// the second member of a two-cycle to arrive solves the pair
+//   lam_a = S_a + w_ca lam_c,  lam_c = S_c + w_ac lam_a.
 __global__ void __launch_bounds__(TPB)
     k_adj_level(const int* __restrict__ qin, int* __restrict__ qout, const int* __restrict__ cptr,
                 const int* __restrict__ cchild, const float* __restrict__ calpha,
                 const float* __restrict__ g, float* lam, int* __restrict__ done,
-                const int* __restrict__ par, const float4* __restrict__ pa,
-                const int4* __restrict__ tetv, int* __restrict__ rem, GbpCtl* ctl, int s) {
+                const int4* __restrict__ pnode, const int* __restrict__ partner,
+                int* __restrict__ pairrem, int* __restrict__ rem, GbpCtl* ctl, int s) {
     const int n = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
@@ -535,19 +617,38 @@ __global__ void __launch_bounds__(TPB)
     __syncthreads();
     const PushBuf pb{push_q, &push_n};
     for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
-        const int c = qin[qi];
-        float l = g[c];
-        for (int x = cptr[c]; x < cptr[c + 1]; ++x) l += calpha[x] * lam[cchild[x]];
-        lam[c] = l;
-        done[c] = 1;
-        const int pr = par[c];
-        if (pr < 0) continue;
-        int f[3];
-        face_nodes_rt(tetv[pr >> 2], pr & 3, f[0], f[1], f[2]);
-        const float4 w = pa[c];
-        const float al[3] = {w.x, w.y, w.z};
-        for (int k = 0; k < 3; ++k)
-            if (al[k] > 0.f && atomicSub(&rem[f[k]], 1) == 1) push_node(pb, f[k], qout, cnt_next);
+        const int x = qin[qi];
+        const int q = partner[x];
+        if (q < 0) {
+            float l = g[x];
+            for (int k = cptr[x]; k < cptr[x + 1]; ++k) l += calpha[k] * lam[cchild[k]];
+            lam[x] = l;
+            done[x] = 1;
+            release_parents(x, -1, pnode, rem, pb, qout, cnt_next);
+            continue;
+        }
+        if (atomicSub(&pairrem[min(x, q)], 1) != 1) continue;   // partner not ready yet
+        float S[2], w[2];
+        const int pr[2] = {x, q};
+        for (int m = 0; m < 2; ++m) {
+            const int a = pr[m], o = pr[1 - m];
+            float l = g[a], wo = 0.f;
+            for (int k = cptr[a]; k < cptr[a + 1]; ++k) {
+                const int ch = cchild[k];
+                if (ch == o) wo = calpha[k];
+                else l += calpha[k] * lam[ch];
+            }
+            S[m] = l;
+            w[m] = wo;     // weight of a in o's parent face
+        }
+        const float lx = (S[0] + w[0] * S[1]) / (1.f - w[0] * w[1]);
+        const float lq = S[1] + w[1] * lx;
+        lam[x] = lx;
+        lam[q] = lq;
+        done[x] = 1;
+        done[q] = 1;
+        release_parents(x, q, pnode, rem, pb, qout, cnt_next);
+        release_parents(q, x, pnode, rem, pb, qout, cnt_next);
     }
     push_flush(pb, qout, cnt_next, &push_base);
 }
@@ -787,7 +888,7 @@ int gbp_scan_exclusive(const int* in, int* out, int n, int* tmp, hipStream_t s) 
 }
 
 // ====================================================================== host
-static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB / 32), 2048); }
+static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB / kLanesPerVertex), kStatBlocks); }
 
 static int read_ctl(gbp_plan p, hipStream_t s) {
     GBP_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
@@ -983,26 +1084,33 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
     if ((rc = read_ctl(p, s))) return rc;
     if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
     if ((rc = run_parents(p, D, s))) return rc;
-    // children lists
+    // parent lists, two-cycle partners, children lists
     {
-    ProfScope ps_child(GBP_PROF_CHILD, s);
-    GBP_HIP(hipMemsetAsync(p->rem, 0, sizeof(int) * n_v, s));
-    GBP_HIP(hipMemsetAsync(p->cfill, 0, sizeof(int) * n_v, s));
-    k_child_count<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->rem);
-    GBP_LAUNCH_CHECK();
-    if ((rc = gbp_scan_exclusive(p->rem, p->ccnt, n_v, p->scan_tmp, s))) return rc;
-    k_child_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->ccnt,
-                                                      p->cfill, p->cchild, p->calpha);
-    k_child_sort<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
+        ProfScope ps_child(GBP_PROF_CHILD, s);
+        const int nb = gbp_blocks(n_v, TPB);
+        GBP_HIP(hipMemsetAsync(p->rem, 0, sizeof(int) * n_v, s));
+        GBP_HIP(hipMemsetAsync(p->done, 0, sizeof(int) * n_v, s));   // all-children counts
+        GBP_HIP(hipMemsetAsync(p->cfill, 0, sizeof(int) * n_v, s));
+        k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode);
+        k_partner<<<nb, TPB, 0, s>>>(p->pnode, n_v, p->partner);
+        k_partner_sym<<<nb, TPB, 0, s>>>(p->partner, n_v, p->pairrem);
+        k_partner_fix<<<nb, TPB, 0, s>>>(p->partner, p->pairrem, n_v);
+        k_child_count<<<nb, TPB, 0, s>>>(p->pnode, p->partner, n_v, p->done, p->rem);
+        GBP_LAUNCH_CHECK();
+        if ((rc = gbp_scan_exclusive(p->done, p->ccnt, n_v, p->scan_tmp, s))) return rc;
+        k_child_fill<<<nb, TPB, 0, s>>>(p->pnode, p->pa, n_v, p->ccnt, p->cfill, p->cchild,
+                                        p->calpha);
+        k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
+        GBP_LAUNCH_CHECK();
     }
-    // level walk
+    // leaves-first level walk
     GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
                                                     p->lam, p->done, p->q[0], p->ctl);
     GBP_LAUNCH_CHECK();
     if ((rc = read_ctl(p, s))) return rc;
     if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
-    const int grid = sweep_grid(n_v);
+    const int grid = std::min(gbp_blocks(n_v, TPB), 256);   // small frontiers: cheap dispatch
     int level = 0, batch = 4;
     bool empty = (p->ctl_host->count[0] == 0);
     const int cap = p->max_rounds + n_v;
@@ -1010,29 +1118,32 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
         for (int b = 0; b < batch; ++b, ++level) {
             ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
             k_adj_level<<<grid, TPB, 0, s>>>(p->q[level & 1], p->q[(level + 1) & 1], p->ccnt,
-                                              p->cchild, p->calpha, p->g, p->lam, p->done, p->par,
-                                              p->pa, p->tetv, p->rem, p->ctl, level);
+                                              p->cchild, p->calpha, p->g, p->lam, p->done,
+                                              p->pnode, p->partner, p->pairrem, p->rem, p->ctl,
+                                              level);
         }
         GBP_LAUNCH_CHECK();
         if ((rc = read_ctl(p, s))) return rc;
         empty = (p->ctl_host->count[level % 3] == 0);
         batch = std::min(batch * 2, 16);
     }
-    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->q[0], p->ctl);
+    // vertices on or above longer cycles of the parent graph
+    GBP_HIP(hipMemsetAsync(&p->ctl->remaining, 0, sizeof(int), s));
+    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->cfill, p->ctl);
     GBP_LAUNCH_CHECK();
     if ((rc = read_ctl(p, s))) return rc;
-    p->bwd_levels = level;
     p->bwd_cyclic = p->ctl_host->remaining;
+    p->bwd_levels = level;
     p->bwd_gs_sweeps = 0;
     if (p->ctl_host->remaining > 0) {
-        const int nl = p->ctl_host->remaining;
+        const int nl = p->ctl_host->remaining;   // list in p->cfill
         bool ok = false;
         int it = 0;
         const int cap = 4 * p->max_rounds + 1000;
         while (!ok && it < cap) {
             for (int b = 0; b < 16; ++b, ++it) {
                 ProfScope ps_gs(GBP_PROF_AUX, s);
-                k_adj_gs<<<gbp_blocks(nl, TPB), TPB, 0, s>>>(p->q[0], nl, p->ccnt, p->cchild,
+                k_adj_gs<<<gbp_blocks(nl, TPB), TPB, 0, s>>>(p->cfill, nl, p->ccnt, p->cchild,
                                                              p->calpha, p->g, p->lam, p->ctl, it);
             }
             GBP_LAUNCH_CHECK();
