@@ -225,6 +225,115 @@ int gbp_profile_enable(int on);
 void gbp_profile_reset(void);
 int gbp_profile_read(const char *kernel, int64_t *launches, double *total_ms);
 
+/*
+ * gbp_plan_status -- synchronises `stream` and reports the device-side status of
+ * the last call on the plan: the error code its inputs raised (GBP_OK if none),
+ * whether the last forward converged within its rounds, whether the last
+ * backward settled, and the rounds / levels that carried work.  Needed after the
+ * budgeted (graph-captured) calls, which do not synchronise.
+ */
+int gbp_plan_status(gbp_plan plan, int *err_code, int *forward_converged,
+                    int *backward_settled, int *rounds, int *levels, void *stream);
+
+/*
+ * gbp_plan_set_launch / gbp_plan_get_launch -- launch configuration of the
+ * relaxation rounds and adjoint levels (chosen by an autotuner):
+ *   lanes        lanes per vertex in a relaxation round: 8, 16 or 32
+ *   sweep_blocks grid of a relaxation round, 64..2048
+ *   level_blocks grid of an adjoint level, 16..2048
+ *   sync_batch   launches between convergence checks in synchronous calls, 1..64
+ * Results do not depend on the configuration beyond rounding order.
+ * Errors: GBP_ERR_ARG for values outside those ranges.
+ */
+int gbp_plan_set_launch(gbp_plan plan, int lanes, int sweep_blocks, int level_blocks,
+                        int sync_batch);
+int gbp_plan_get_launch(gbp_plan plan, int *lanes, int *sweep_blocks, int *level_blocks,
+                        int *sync_batch);
+/* Rounds and levels that carried work in the last synchronous forward/backward. */
+int gbp_plan_last_counts(gbp_plan plan, int *rounds, int *levels);
+
+/*
+ * Batches.  Many meshes solve together as one plan over their disjoint union
+ * (the instances are its connected components, vertices numbered instance by
+ * instance); a batch descriptor records where each instance's vertices start
+ * so that the ECG and the misfit are evaluated per instance.
+ *   offsets  host int32 [n_inst+1], offsets[0] = 0, non-decreasing; instance i
+ *            owns vertices [offsets[i], offsets[i+1]) of the union
+ *   max_steps largest n_steps the batch will be used with (<= 992)
+ * Errors: GBP_ERR_ARG, GBP_ERR_NOMEM, GBP_ERR_HIP.
+ */
+typedef struct gbp_batch_s *gbp_batch;
+int gbp_batch_create(const int32_t *offsets, int n_inst, int max_steps, gbp_batch *out);
+void gbp_batch_destroy(gbp_batch batch);
+int gbp_batch_sizes(gbp_batch batch, int *n_inst, int *n_total);
+
+/*
+ * gbp_ecg_forward_batched / gbp_ecg_backward_batched -- Sec. 2.4 per instance:
+ *   ecg[i][s][l] = sum over vertices n of instance i of W[n*L+l] U(t_s - T[n])
+ *   T, W, dL_dT over the union (vertex order of the offsets); ecg and dL_decg
+ *   device float [n_inst*n_steps*L].  Enqueue only (graph-capturable).
+ */
+int gbp_ecg_forward_batched(gbp_batch batch, const float *T, const float *W, int L,
+                            const gbp_ap *ap, float *ecg, void *stream);
+int gbp_ecg_backward_batched(gbp_batch batch, const float *T, const float *W, int L,
+                             const gbp_ap *ap, const float *dL_decg, float *dL_dT,
+                             void *stream);
+/*
+ * gbp_ecg_loss_batched -- per instance i: loss[i] = mean over its n_per entries of
+ * (ecg - target)^2 and dL_decg = 2 (ecg - target) / n_per (so the gradient of
+ * sum_i loss[i]).  ecg, target, dL_decg device float [n_inst*n_per]; loss device
+ * float [n_inst].
+ */
+int gbp_ecg_loss_batched(const float *ecg, const float *target, int n_inst, int n_per,
+                         float *loss, float *dL_decg, void *stream);
+
+/*
+ * gbp_adam_step_dev -- gbp_adam_step with the step number read from device memory
+ * (*step >= 1), so that a captured graph can advance it; the caller (or
+ * gbp_counter_add) increments it.
+ */
+int gbp_adam_step_dev(float *param, const float *grad, float *m, float *v, int n, float lr,
+                      float beta1, float beta2, float eps, const int *step, float lo, float hi,
+                      void *stream);
+int gbp_counter_add(int *counter, int delta, void *stream);
+
+/*
+ * One Geodesic-BP iteration captured in a HIP graph (the batched, graph-launched
+ * form).  gbp_step_create records, on a private capture stream, the budgeted
+ * forward (cold, or warm from the previous iteration's T), the batched ECG,
+ * misfit, ECG backward, budgeted adjoint and Adam on the velocity scale and the
+ * root onsets, then instantiates the graph; gbp_step_launch replays it on
+ * `stream`.  All buffers named in the descriptor are caller-owned device memory
+ * that must stay allocated while the step exists; the step owns its scratch
+ * (gradients, Adam moments, the step counter).  Budgets come from a synchronous
+ * run (gbp_plan_last_counts) with a margin; gbp_plan_status tells whether they
+ * sufficed.  Calls on one plan must not overlap.
+ */
+typedef struct {
+    gbp_plan plan;
+    gbp_batch batch;            /* instances of the plan's union mesh */
+    const float *D;             /* [n_e*6] */
+    float *vscale;              /* [n_v], updated by Adam */
+    const int32_t *root_node;   /* [n_roots] union vertex ids */
+    float *root_t;              /* [n_roots], updated by Adam */
+    int n_roots;
+    const float *W;             /* [n_v*L] */
+    int L;
+    gbp_ap ap;
+    const float *target;        /* [n_inst*n_steps*L] */
+    float *T;                   /* [n_v] activation times (output; warm-start input) */
+    float *ecg;                 /* [n_inst*n_steps*L] output */
+    float *loss;                /* [n_inst] output */
+    float lr_vscale, lr_root_t, vscale_lo, vscale_hi;
+    int round_budget, level_budget, gs_budget;
+    int warm;                   /* 1: forward starts from T (two-sided update) */
+    int reserved[4];            /* must be zero */
+} gbp_step_desc;
+typedef struct gbp_step_s *gbp_step;
+int gbp_step_create(const gbp_step_desc *desc, gbp_step *out);
+int gbp_step_launch(gbp_step step, void *stream);
+void gbp_step_destroy(gbp_step step);
+
 const char *gbp_last_error(void);
 const char *gbp_version(void);
 

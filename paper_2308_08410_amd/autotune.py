@@ -1,0 +1,103 @@
+"""Launch-configuration autotuner.
+
+For a plan and a representative problem it times the eikonal forward (and
+optionally the adjoint) under each candidate configuration -- lanes per vertex
+in a relaxation round, grid of a round, grid of an adjoint level -- keeps the
+fastest, and records the rounds/levels that carried work so that graph-captured
+iterations can be given launch budgets.  Results are cached in a JSON file
+keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import binding as B
+
+SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=lb)
+         for lanes in (8, 16, 32) for sb in (512, 1024, 2048) for lb in (128, 256)]
+
+
+def cache_path() -> str:
+    return os.environ.get("GBP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "gbp", "launch.json"))
+
+
+def size_key(plan: B.Plan) -> str:
+    b = lambda x: 2 ** int(round(math.log2(max(x, 1))))
+    return f"gfx950/v{b(plan.n_v)}/e{b(plan.n_e)}"
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(db):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(fn, repeats):
+    ts = []
+    for _ in range(repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, repeats=3,
+         use_cache=True, save=True):
+    """Pick and apply the fastest launch configuration; returns its record
+    (configuration, ms per forward[+backward], rounds, levels)."""
+    key = size_key(plan)
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        rec = db[key]
+        B.set_launch(plan, rec["lanes"], rec["sweep_blocks"], rec["level_blocks"])
+        return dict(rec, cached=True)
+    gT = torch.ones(plan.n_v, dtype=torch.float32, device=D.device)
+    T = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
+
+    def run():
+        B.eikonal_forward(plan, D, vscale, root_node, root_t, out=T)
+        if backward:
+            B.eikonal_backward(plan, D, vscale, root_node, root_t, T, gT, want_D=False)
+
+    best = None
+    for cfg in (space or SPACE):
+        B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], cfg["level_blocks"])
+        run()                                    # warm-up
+        ms = _time(run, repeats)
+        if best is None or ms < best["ms"]:
+            best = dict(cfg, ms=ms)
+    B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"])
+    run()
+    best.update(B.last_counts(plan))
+    if save:
+        db = _load()
+        db[key] = best
+        _save(db)
+    return dict(best, cached=False)
+
+
+def budgets(plan: B.Plan, margin=1.25, extra=16, gs=32):
+    """Launch budgets for a captured iteration from the last synchronous counts."""
+    c = B.last_counts(plan)
+    return dict(round_budget=int(math.ceil(c["rounds"] * margin)) + extra,
+                level_budget=int(math.ceil(c["levels"] * margin)) + extra, gs_budget=gs)

@@ -86,6 +86,23 @@ _prof_enable = _sig("gbp_profile_enable", [c_int])
 _prof_reset = _sig("gbp_profile_reset", [], None)
 _prof_read = _sig("gbp_profile_read", [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double)])
+_plan_status = _sig("gbp_plan_status", [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                        ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                        ctypes.POINTER(c_int), c_void_p])
+_set_launch = _sig("gbp_plan_set_launch", [c_void_p, c_int, c_int, c_int, c_int])
+_get_launch = _sig("gbp_plan_get_launch", [c_void_p] + [ctypes.POINTER(c_int)] * 4)
+_last_counts = _sig("gbp_plan_last_counts", [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)])
+_batch_create = _sig("gbp_batch_create", [c_void_p, c_int, c_int, ctypes.POINTER(c_void_p)])
+_batch_destroy = _sig("gbp_batch_destroy", [c_void_p], None)
+_ecg_fwd_b = _sig("gbp_ecg_forward_batched", [c_void_p, c_void_p, c_void_p, c_int, ctypes.POINTER(AP),
+                                              c_void_p, c_void_p])
+_ecg_bwd_b = _sig("gbp_ecg_backward_batched", [c_void_p, c_void_p, c_void_p, c_int, ctypes.POINTER(AP),
+                                               c_void_p, c_void_p, c_void_p])
+_ecg_loss_b = _sig("gbp_ecg_loss_batched", [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p,
+                                            c_void_p])
+_step_create = _sig("gbp_step_create", [c_void_p, ctypes.POINTER(c_void_p)])
+_step_launch = _sig("gbp_step_launch", [c_void_p, c_void_p])
+_step_destroy = _sig("gbp_step_destroy", [c_void_p], None)
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -274,3 +291,144 @@ def adam_step(param, grad, m, v, step, lr=0.5, beta1=0.9, beta2=0.999, eps=1e-8,
     _check(_adam(_ptr(param, torch.float32, None, "param"), _ptr(grad, torch.float32, param.shape, "grad"),
                  _ptr(m, torch.float32, param.shape, "m"), _ptr(v, torch.float32, param.shape, "v"), n,
                  lr, beta1, beta2, eps, int(step), lo, hi, _stream(stream)))
+
+
+# ---------------------------------------------------------------- plan control
+def plan_status(plan: Plan, stream=None):
+    """Synchronises and returns the device-side status of the last call."""
+    e, f, b, r, l = c_int(), c_int(), c_int(), c_int(), c_int()
+    _check(_plan_status(plan.handle, ctypes.byref(e), ctypes.byref(f), ctypes.byref(b), ctypes.byref(r),
+                        ctypes.byref(l), _stream(stream)))
+    return dict(err=e.value, forward_converged=bool(f.value), backward_settled=bool(b.value),
+                rounds=r.value, levels=l.value)
+
+
+def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=256, sync_batch=16):
+    _check(_set_launch(plan.handle, lanes, sweep_blocks, level_blocks, sync_batch))
+
+
+def get_launch(plan: Plan):
+    v = [c_int() for _ in range(4)]
+    _check(_get_launch(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(lanes=v[0].value, sweep_blocks=v[1].value, level_blocks=v[2].value, sync_batch=v[3].value)
+
+
+def last_counts(plan: Plan):
+    r, l = c_int(), c_int()
+    _check(_last_counts(plan.handle, ctypes.byref(r), ctypes.byref(l)))
+    return dict(rounds=r.value, levels=l.value)
+
+
+# ---------------------------------------------------------------- batches
+class Batch:
+    """Instance offsets of a union mesh (gbp_batch)."""
+
+    def __init__(self, offsets, max_steps):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+        h = c_void_p()
+        _check(_batch_create(off.ctypes.data, len(off) - 1, int(max_steps), ctypes.byref(h)))
+        self._h = h
+        self.offsets = off
+        self.n_inst = len(off) - 1
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _batch_destroy is not None:
+            _batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ecg_forward_batched(batch: Batch, T, W, ap: AP, out=None, stream=None):
+    n_v, L = W.shape
+    if out is None:
+        out = torch.empty((batch.n_inst, ap.n_steps, L), dtype=torch.float32, device=T.device)
+    _check(_ecg_fwd_b(batch.handle, _ptr(T, torch.float32, (n_v,), "T"), _ptr(W, torch.float32, (n_v, L), "W"),
+                      L, ctypes.byref(ap), _ptr(out, torch.float32, (batch.n_inst, ap.n_steps, L), "ecg"),
+                      _stream(stream)))
+    return out
+
+
+def ecg_backward_batched(batch: Batch, T, W, ap: AP, dL_decg, out=None, stream=None):
+    n_v, L = W.shape
+    if out is None:
+        out = torch.empty(n_v, dtype=torch.float32, device=T.device)
+    _check(_ecg_bwd_b(batch.handle, _ptr(T, torch.float32, (n_v,), "T"), _ptr(W, torch.float32, (n_v, L), "W"),
+                      L, ctypes.byref(ap), _ptr(dL_decg, torch.float32, (batch.n_inst, ap.n_steps, L), "dL_decg"),
+                      _ptr(out, torch.float32, (n_v,), "dL_dT"), _stream(stream)))
+    return out
+
+
+def ecg_loss_batched(ecg, target, grad=True, stream=None):
+    n_inst = ecg.shape[0]
+    n_per = ecg[0].numel()
+    loss = torch.empty(n_inst, dtype=torch.float32, device=ecg.device)
+    g = torch.empty_like(ecg) if grad else None
+    _check(_ecg_loss_b(_ptr(ecg, torch.float32, None, "ecg"), _ptr(target, torch.float32, ecg.shape, "target"),
+                       n_inst, n_per, loss.data_ptr(), g.data_ptr() if g is not None else None,
+                       _stream(stream)))
+    return loss, g
+
+
+# ---------------------------------------------------------------- captured iteration
+class StepDesc(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("batch", c_void_p), ("D", c_void_p), ("vscale", c_void_p),
+                ("root_node", c_void_p), ("root_t", c_void_p), ("n_roots", c_int), ("W", c_void_p),
+                ("L", c_int), ("ap", AP), ("target", c_void_p), ("T", c_void_p), ("ecg", c_void_p),
+                ("loss", c_void_p), ("lr_vscale", c_float), ("lr_root_t", c_float),
+                ("vscale_lo", c_float), ("vscale_hi", c_float), ("round_budget", c_int),
+                ("level_budget", c_int), ("gs_budget", c_int), ("warm", c_int), ("reserved", c_int * 4)]
+
+
+class Step:
+    """One Geodesic-BP iteration captured in a HIP graph (gbp_step).  The tensors
+    passed in are kept referenced for the lifetime of the step."""
+
+    def __init__(self, plan: Plan, batch: Batch, D, vscale, root_node, root_t, W, ap: AP, target, T, ecg,
+                 loss, round_budget, level_budget, gs_budget=32, warm=False, lr_vscale=0.01,
+                 lr_root_t=0.5, vscale_lo=0.2, vscale_hi=5.0):
+        n_v, L = W.shape
+        R = root_node.numel()
+        self._keep = (plan, batch, D, vscale, root_node, root_t, W, target, T, ecg, loss)
+        d = StepDesc()
+        d.plan, d.batch = plan.handle, batch.handle
+        d.D = _ptr(D, torch.float32, (plan.n_e, 6), "D")
+        d.vscale = _ptr(vscale, torch.float32, (n_v,), "vscale")
+        d.root_node = _ptr(root_node, torch.int32, (R,), "root_node")
+        d.root_t = _ptr(root_t, torch.float32, (R,), "root_t")
+        d.n_roots = R
+        d.W, d.L, d.ap = _ptr(W, torch.float32, (n_v, L), "W"), L, ap
+        d.target = _ptr(target, torch.float32, (batch.n_inst, ap.n_steps, L), "target")
+        d.T = _ptr(T, torch.float32, (n_v,), "T")
+        d.ecg = _ptr(ecg, torch.float32, (batch.n_inst, ap.n_steps, L), "ecg")
+        d.loss = _ptr(loss, torch.float32, (batch.n_inst,), "loss")
+        d.lr_vscale, d.lr_root_t, d.vscale_lo, d.vscale_hi = lr_vscale, lr_root_t, vscale_lo, vscale_hi
+        d.round_budget, d.level_budget, d.gs_budget = int(round_budget), int(level_budget), int(gs_budget)
+        d.warm = 1 if warm else 0
+        h = c_void_p()
+        _check(_step_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_step_launch(self._h, _stream(stream)))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _step_destroy is not None:
+            _step_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

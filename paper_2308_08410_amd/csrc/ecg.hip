@@ -87,11 +87,19 @@ __device__ __forceinline__ void wave_window(float Tv, const ApDev& ap, int& s_lo
 // Block: 4 waves; each wave takes 64-vertex groups of the block's range.
 // Dynamic LDS: win[S_pad*16] floats.  The step histogram goes to global memory
 // directly (one 16-wide add per 64-vertex group).
+// Grid (blocks per instance, instances); instance i owns vertices
+// [off[i], off[i+1]) (off == nullptr: one instance of n_v vertices).
 __global__ void __launch_bounds__(256)
     k_ecg_fwd(const float* __restrict__ T, const float* __restrict__ W, int n_v, int L,
-              ApDev ap, int S_pad, int groups_per_block, float* __restrict__ g_win,
-              float* __restrict__ g_hist, float* __restrict__ g_wsum) {
+              ApDev ap, int S_pad, int groups_per_block, const int* __restrict__ off,
+              float* __restrict__ g_win_all, float* __restrict__ g_hist_all,
+              float* __restrict__ g_wsum_all) {
     extern __shared__ float win[];
+    const int inst = blockIdx.y;
+    const int vbeg = off ? off[inst] : 0, vend = off ? off[inst + 1] : n_v;
+    float* g_win = g_win_all + (size_t)inst * S_pad * 16;
+    float* g_hist = g_hist_all + (size_t)inst * S_pad * 16;
+    float* g_wsum = g_wsum_all + (size_t)inst * 16;
     __shared__ int blo, bhi;
     __shared__ float wsum_sh[4][16];
     for (int x = threadIdx.x; x < S_pad * 16; x += blockDim.x) win[x] = 0.f;
@@ -104,10 +112,10 @@ __global__ void __launch_bounds__(256)
     const int col = lane & 15, kq = lane >> 4;
     float wsum_all = 0.f;   // lane: lead col, vertices 4kq+r of each K-step
     for (int gi = wave; gi < groups_per_block; gi += 4) {
-        const int g0 = (blockIdx.x * groups_per_block + gi) * 64;
-        if (g0 >= n_v) break;
+        const int g0 = vbeg + (blockIdx.x * groups_per_block + gi) * 64;
+        if (g0 >= vend) break;
         const int nl = g0 + lane;
-        const float Tl = nl < n_v ? T[nl] : __builtin_huge_valf();
+        const float Tl = nl < vend ? T[nl] : __builtin_huge_valf();
         int s_lo, s_hi;
         bool any;
         wave_window(Tl, ap, s_lo, s_hi, any);
@@ -116,8 +124,8 @@ __global__ void __launch_bounds__(256)
         for (int ks = 0; ks < 4; ++ks) {
             for (int r = 0; r < 4; ++r) {
                 const int n = g0 + ks * 16 + kq * 4 + r;
-                const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
-                const float t = n < n_v ? T[n] : __builtin_huge_valf();
+                const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
+                const float t = n < vend ? T[n] : __builtin_huge_valf();
                 wsum_all += w;
                 if (t < __builtin_huge_valf()) wsum_fin += w;
             }
@@ -133,8 +141,8 @@ __global__ void __launch_bounds__(256)
                 bf16x4_t bh, bl;
                 for (int r = 0; r < 4; ++r) {
                     const int n = g0 + ks * 16 + kq * 4 + r;
-                    const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
-                    tv[r] = n < n_v ? T[n] : __builtin_huge_valf();
+                    const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
+                    tv[r] = n < vend ? T[n] : __builtin_huge_valf();
                     short h, l;
                     split_bf16(w, h, l);
                     bh[r] = h;
@@ -196,9 +204,15 @@ __global__ void k_ecg_zero(float* __restrict__ p, int n) {
 // ecg[s,l] = K0 * sum W + prefix_s(hist) + win.  One block of 1024 threads:
 // thread (c, l) owns lead l and the c-th of 64 contiguous chunks of time steps.
 __global__ void __launch_bounds__(1024)
-    k_ecg_finish(const float* __restrict__ g_win, const float* __restrict__ g_hist,
-                 const float* __restrict__ g_wsum, int S, int L, float K0, float* __restrict__ ecg) {
+    k_ecg_finish(const float* __restrict__ g_win_all, const float* __restrict__ g_hist_all,
+                 const float* __restrict__ g_wsum_all, int S, int S_pad, int L, float K0,
+                 float* __restrict__ ecg_all) {
     __shared__ float part[64][17];
+    const int inst = blockIdx.x;
+    const float* g_win = g_win_all + (size_t)inst * S_pad * 16;
+    const float* g_hist = g_hist_all + (size_t)inst * S_pad * 16;
+    const float* g_wsum = g_wsum_all + (size_t)inst * 16;
+    float* ecg = ecg_all + (size_t)inst * S * L;
     const int l = threadIdx.x & 15, c = threadIdx.x >> 4;
     const int len = (S + 63) / 64;
     const int s0 = c * len, s1 = min(S, s0 + len);
@@ -221,9 +235,12 @@ __global__ void __launch_bounds__(1024)
 // ------------------------------------------------------------------ backward
 __global__ void __launch_bounds__(256)
     k_ecg_bwd(const float* __restrict__ T, const float* __restrict__ W,
-              const float* __restrict__ G, int n_v, int L, ApDev ap, int S_pad,
-              float* __restrict__ dT) {
+              const float* __restrict__ G_all, int n_v, int L, ApDev ap, int S_pad,
+              const int* __restrict__ off, float* __restrict__ dT) {
     extern __shared__ short gl[];  // [S_pad*16] hi, then [S_pad*16] lo
+    const int inst = blockIdx.y;
+    const int vbeg = off ? off[inst] : 0, vend = off ? off[inst + 1] : n_v;
+    const float* G = G_all + (size_t)inst * ap.S * L;
     short* gh = gl;
     short* glo = gl + S_pad * 16;
     for (int x = threadIdx.x; x < S_pad * 16; x += blockDim.x) {
@@ -238,17 +255,17 @@ __global__ void __launch_bounds__(256)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
     const int nwaves = gridDim.x * 4;
-    for (int grp = blockIdx.x * 4 + wave; grp * 64 < n_v; grp += nwaves) {
-        const int g0 = grp * 64;
+    for (int grp = blockIdx.x * 4 + wave; vbeg + grp * 64 < vend; grp += nwaves) {
+        const int g0 = vbeg + grp * 64;
         const int nl = g0 + lane;
-        const float Tl = nl < n_v ? T[nl] : __builtin_huge_valf();
+        const float Tl = nl < vend ? T[nl] : __builtin_huge_valf();
         int s_lo, s_hi;
         bool any;
         wave_window(Tl, ap, s_lo, s_hi, any);
         // 4 vertex tiles of 16
         for (int mt = 0; mt < 4; ++mt) {
             const int nrow = g0 + mt * 16 + col;   // A row: vertex
-            const float tn = nrow < n_v ? T[nrow] : __builtin_huge_valf();
+            const float tn = nrow < vend ? T[nrow] : __builtin_huge_valf();
             floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
             if (any) {
                 for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
@@ -275,7 +292,7 @@ __global__ void __launch_bounds__(256)
             float out[4];
             for (int r = 0; r < 4; ++r) {
                 const int n = g0 + mt * 16 + kq * 4 + r;
-                const float w = (n < n_v && col < L) ? W[(size_t)n * L + col] : 0.f;
+                const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
                 float v = acc[r] * w;
                 v += __shfl_xor(v, 1);
                 v += __shfl_xor(v, 2);
@@ -286,7 +303,7 @@ __global__ void __launch_bounds__(256)
             if (col == 0)
                 for (int r = 0; r < 4; ++r) {
                     const int n = g0 + mt * 16 + kq * 4 + r;
-                    if (n < n_v) dT[n] = -out[r];
+                    if (n < vend) dT[n] = -out[r];
                 }
         }
     }
@@ -348,7 +365,125 @@ ApDev make_ap(const gbp_ap* a) {
     return d;
 }
 
+struct EcgLaunch {
+    const int* off;       // device offsets or nullptr
+    int n_inst;
+    int max_verts;        // largest instance
+    float* work;          // n_inst * (2*S_pad*16 + 16) floats
+};
+
+int ecg_forward_launch(const EcgLaunch& el, const float* T, int n_v, const float* W, int L,
+                       const ApDev& d, float* ecg, hipStream_t s) {
+    const int S_pad = (d.S + 15) / 16 * 16 + 16;
+    float* g_win = el.work;
+    float* g_hist = el.work + (size_t)el.n_inst * S_pad * 16;
+    float* g_wsum = el.work + (size_t)2 * el.n_inst * S_pad * 16;
+    const int total = el.n_inst * (2 * S_pad * 16 + 16);
+    k_ecg_zero<<<std::min((total + 255) / 256, 1024), 256, 0, s>>>(el.work, total);
+    const int groups = (el.max_verts + 63) / 64;
+    const int gpb = 16;   // 64-vertex groups per block (4 per wave)
+    const dim3 grid((groups + gpb - 1) / gpb, el.n_inst);
+    const size_t lds = (size_t)S_pad * 16 * sizeof(float);
+    {
+        ProfScope ps(GBP_PROF_ECG_FWD, s);
+        k_ecg_fwd<<<grid, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, el.off, g_win, g_hist, g_wsum);
+    }
+    k_ecg_finish<<<el.n_inst, 1024, 0, s>>>(g_win, g_hist, g_wsum, d.S, S_pad, L, d.K0, ecg);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+int ecg_backward_launch(const EcgLaunch& el, const float* T, int n_v, const float* W, int L,
+                        const ApDev& d, const float* G, float* dT, hipStream_t s) {
+    const int S_pad = (d.S + 15) / 16 * 16 + 16;
+    const int groups = (el.max_verts + 63) / 64;
+    const dim3 grid(std::max(1, std::min((groups + 3) / 4, 2048 / std::max(1, el.n_inst) + 1)),
+                    el.n_inst);
+    const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
+    ProfScope ps(GBP_PROF_ECG_BWD, s);
+    k_ecg_bwd<<<grid, 256, lds, s>>>(T, W, G, n_v, L, d, S_pad, el.off, dT);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
 }  // namespace
+
+struct gbp_batch_s {
+    int device = 0;
+    int n_inst = 0, max_verts = 0, total = 0, max_steps = 0;
+    int* off = nullptr;
+    float* work = nullptr;
+};
+
+extern "C" int gbp_batch_create(const int32_t* offsets, int n_inst, int max_steps, gbp_batch* out) {
+    if (!out || !offsets || n_inst < 1 || max_steps < 1 || max_steps > kMaxSteps) {
+        gbp_set_error("batch: need offsets, n_inst >= 1, 1 <= max_steps <= %d", kMaxSteps);
+        return GBP_ERR_ARG;
+    }
+    *out = nullptr;
+    if (offsets[0] != 0) {
+        gbp_set_error("batch: offsets[0] must be 0");
+        return GBP_ERR_ARG;
+    }
+    int mx = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (offsets[i + 1] < offsets[i]) {
+            gbp_set_error("batch: offsets must be non-decreasing");
+            return GBP_ERR_ARG;
+        }
+        mx = std::max(mx, offsets[i + 1] - offsets[i]);
+    }
+    gbp_batch b = new gbp_batch_s();
+    (void)hipGetDevice(&b->device);
+    b->n_inst = n_inst;
+    b->max_verts = std::max(mx, 1);
+    b->total = offsets[n_inst];
+    b->max_steps = max_steps;
+    const int S_pad = (max_steps + 15) / 16 * 16 + 16;
+    const size_t nwork = (size_t)n_inst * (2 * S_pad * 16 + 16);
+    if (hipMalloc((void**)&b->off, sizeof(int) * (n_inst + 1)) != hipSuccess ||
+        hipMalloc((void**)&b->work, sizeof(float) * nwork) != hipSuccess) {
+        gbp_set_error("batch: allocation failed");
+        gbp_batch_destroy(b);
+        return GBP_ERR_NOMEM;
+    }
+    if (hipMemcpy(b->off, offsets, sizeof(int) * (n_inst + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        gbp_set_error("batch: copy failed");
+        gbp_batch_destroy(b);
+        return GBP_ERR_HIP;
+    }
+    *out = b;
+    return GBP_OK;
+}
+
+extern "C" int gbp_batch_sizes(gbp_batch b, int* n_inst, int* n_total) {
+    if (!b) {
+        gbp_set_error("batch is NULL");
+        return GBP_ERR_ARG;
+    }
+    if (n_inst) *n_inst = b->n_inst;
+    if (n_total) *n_total = b->total;
+    return GBP_OK;
+}
+
+extern "C" void gbp_batch_destroy(gbp_batch b) {
+    if (!b) return;
+    if (b->off) (void)hipFree(b->off);
+    if (b->work) (void)hipFree(b->work);
+    delete b;
+}
+
+static int check_batch(gbp_batch b, const gbp_ap* ap) {
+    if (!b) {
+        gbp_set_error("batch is NULL");
+        return GBP_ERR_ARG;
+    }
+    if (ap && ap->n_steps > b->max_steps) {
+        gbp_set_error("n_steps %d exceeds the batch's max_steps %d", ap->n_steps, b->max_steps);
+        return GBP_ERR_ARG;
+    }
+    return GBP_OK;
+}
 
 extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, const gbp_ap* ap,
                                float* ecg, void* stream) {
@@ -358,26 +493,12 @@ extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, c
         gbp_set_error("ecg is NULL");
         return GBP_ERR_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
     const ApDev d = make_ap(ap);
     const int S_pad = (d.S + 15) / 16 * 16 + 16;
     float* work;
     if ((rc = ecg_workspace((size_t)2 * S_pad * 16 + 16, &work))) return rc;
-    float* g_win = work;
-    float* g_hist = work + S_pad * 16;
-    float* g_wsum = work + 2 * S_pad * 16;
-    k_ecg_zero<<<64, 256, 0, s>>>(work, 2 * S_pad * 16 + 16);
-    const int groups = (n_v + 63) / 64;
-    const int gpb = 16;   // 64-vertex groups per block (4 per wave)
-    const int blocks = (groups + gpb - 1) / gpb;
-    const size_t lds = (size_t)S_pad * 16 * sizeof(float);
-    {
-        ProfScope ps(GBP_PROF_ECG_FWD, s);
-        k_ecg_fwd<<<blocks, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, g_win, g_hist, g_wsum);
-    }
-    k_ecg_finish<<<1, 1024, 0, s>>>(g_win, g_hist, g_wsum, d.S, L, d.K0, ecg);
-    GBP_LAUNCH_CHECK();
-    return GBP_OK;
+    return ecg_forward_launch(EcgLaunch{nullptr, 1, n_v, work}, T, n_v, W, L, d, ecg,
+                              (hipStream_t)stream);
 }
 
 extern "C" int gbp_ecg_backward(const float* T, int n_v, const float* W, int L, const gbp_ap* ap,
@@ -388,14 +509,33 @@ extern "C" int gbp_ecg_backward(const float* T, int n_v, const float* W, int L, 
         gbp_set_error("dL_decg and dL_dT are required");
         return GBP_ERR_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    const ApDev d = make_ap(ap);
-    const int S_pad = (d.S + 15) / 16 * 16 + 16;
-    const int groups = (n_v + 63) / 64;
-    const int blocks = std::min((groups + 3) / 4, 2048);
-    const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
-    ProfScope ps(GBP_PROF_ECG_BWD, s);
-    k_ecg_bwd<<<blocks, 256, lds, s>>>(T, W, dL_decg, n_v, L, d, S_pad, dL_dT);
-    GBP_LAUNCH_CHECK();
-    return GBP_OK;
+    return ecg_backward_launch(EcgLaunch{nullptr, 1, n_v, nullptr}, T, n_v, W, L, make_ap(ap),
+                               dL_decg, dL_dT, (hipStream_t)stream);
+}
+
+extern "C" int gbp_ecg_forward_batched(gbp_batch b, const float* T, const float* W, int L,
+                                       const gbp_ap* ap, float* ecg, void* stream) {
+    int rc = check_batch(b, ap);
+    if (rc) return rc;
+    if ((rc = check_ap(T, b->total, W, L, ap))) return rc;
+    if (!ecg) {
+        gbp_set_error("ecg is NULL");
+        return GBP_ERR_ARG;
+    }
+    return ecg_forward_launch(EcgLaunch{b->off, b->n_inst, b->max_verts, b->work}, T, b->total, W,
+                              L, make_ap(ap), ecg, (hipStream_t)stream);
+}
+
+extern "C" int gbp_ecg_backward_batched(gbp_batch b, const float* T, const float* W, int L,
+                                        const gbp_ap* ap, const float* dL_decg, float* dL_dT,
+                                        void* stream) {
+    int rc = check_batch(b, ap);
+    if (rc) return rc;
+    if ((rc = check_ap(T, b->total, W, L, ap))) return rc;
+    if (!dL_decg || !dL_dT) {
+        gbp_set_error("dL_decg and dL_dT are required");
+        return GBP_ERR_ARG;
+    }
+    return ecg_backward_launch(EcgLaunch{b->off, b->n_inst, b->max_verts, nullptr}, T, b->total, W,
+                               L, make_ap(ap), dL_decg, dL_dT, (hipStream_t)stream);
 }

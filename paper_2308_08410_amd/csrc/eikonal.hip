@@ -187,7 +187,8 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
                         int n_roots, const int* __restrict__ node_int, int n_v,
                         float* __restrict__ troot, float* __restrict__ T, int cold,
                         const int* __restrict__ adj_ptr, const int* __restrict__ adj,
-                        int* __restrict__ qout, int* __restrict__ mark, int stamp, GbpCtl* ctl) {
+                        int* __restrict__ qout, int* __restrict__ mark, GbpCtl* ctl) {
+    const int stamp = ctl->stamp;
     if (threadIdx.x == 0) {
         for (int r = 0; r < n_roots; ++r) {
             const int u = root_node[r];
@@ -221,14 +222,47 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
     }
 }
 
-__global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int stamp, int n_v,
-                            GbpCtl* ctl) {
+__global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int n_v, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) ctl->count[0] = n_v;
     if (i < n_v) {
         q[i] = i;
-        mark[i] = stamp;
+        mark[i] = ctl->stamp;
     }
+}
+
+// Control-block reset at the start of a call.  The queue stamp base survives;
+// so does the forward's status bit when a backward starts (keep_fwd), so that one
+// status read after a captured iteration reports both passes.
+__global__ void k_ctl_reset(GbpCtl* ctl, int keep_fwd) {
+    if (threadIdx.x == 0) {
+        const int stamp = ctl->stamp;
+        const int st = keep_fwd ? (ctl->status & 1) : 0;
+        GbpCtl z{};
+        z.stamp = stamp > (1 << 30) ? 1 : stamp;
+        z.status = st;
+        *ctl = z;
+    }
+}
+
+// Stamps restart from 1 before they could overflow: clear the marks first.
+__global__ void k_mark_reset_if(int* __restrict__ mark, int n_v, const GbpCtl* ctl) {
+    if (ctl->stamp <= (1 << 30)) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_v; i += gridDim.x * blockDim.x)
+        mark[i] = 0;
+}
+
+// After `launched` relaxation rounds: advance the stamp base past every stamp
+// used, and flag non-convergence if the next queue is not empty.
+__global__ void k_forward_end(GbpCtl* ctl, int launched) {
+    if (threadIdx.x == 0) {
+        ctl->stamp += launched + 2;
+        if (ctl->count[launched % 3] != 0) ctl->status |= 1;
+    }
+}
+
+__global__ void k_fill_i(int* __restrict__ x, int v, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
 }
 
 // ------------------------------------------------------------------ relaxation
@@ -249,12 +283,10 @@ __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restric
     e += cnt;
 }
 
-// One relaxation round.  Each vertex of the queue is handled by 16 lanes; lane c
-// evaluates local problems c and c+16 of the vertex's patch (slot picked at run
+// One relaxation round.  Each vertex of the queue is handled by L lanes (8, 16 or
+// 32, autotuned); lane c evaluates local problems c and c+L of the vertex's patch (slot picked at run
 // time, both problems' loads in flight together), a 16-lane min-reduction forms
 // the Hopf-Lax minimum, and on a change the lanes push the unique neighbours.
-constexpr int kLanesPerVertex = 16;
-
 __device__ __forceinline__ float face_value(const int* __restrict__ nent,
                                             const int4* __restrict__ tetv,
                                             const float4* __restrict__ tetg, const float* T,
@@ -267,20 +299,20 @@ __device__ __forceinline__ float face_value(const int* __restrict__ nent,
     return local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]);
 }
 
-template <bool TWO_SIDED>
+template <bool TWO_SIDED, int L>
 __global__ void __launch_bounds__(TPB)
     k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
-            int stamp_next, float eps_rel) {
-    constexpr int L = kLanesPerVertex;
+            float eps_rel) {
     constexpr int PER_BLOCK = TPB / L;
     const int n = ctl->count[s % 3];
+    const int stamp_next = ctl->stamp + s + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
-        if (n > 0) atomicMax(&ctl->pad[0], s + 1);
+        if (n > 0) atomicMax(&ctl->rounds, s + 1);
     }
     if (blockIdx.x * PER_BLOCK >= n) return;        // no vertex for this block
     int* cnt_next = &ctl->count[(s + 1) % 3];
@@ -306,19 +338,16 @@ __global__ void __launch_bounds__(TPB)
         const int tot = e012 + c3;
         float best = GBP_INF;
         for (int c = lane; c < tot; c += 2 * L) {
-            const int d = c + L;
+            const int d = c + L;       // second local problem of this lane
             const bool okd = d < tot;
             const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
             const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
             const float vc = face_value(nent, tetv, tetg, T, p.x + c, Kc);
-            const float vd = face_value(nent, tetv, tetg, T, p.x + (okd ? d : c), Kd);
+            const float vd = face_value(nent, tetv, tetg, T, p.x + (okd ? d : c), okd ? Kd : Kc);
             best = fminf(best, okd ? fminf(vc, vd) : vc);
             solves += okd ? 2 : 1;
         }
-        best = fminf(best, __shfl_xor(best, 8));
-        best = fminf(best, __shfl_xor(best, 4));
-        best = fminf(best, __shfl_xor(best, 2));
-        best = fminf(best, __shfl_xor(best, 1));
+        for (int o = L / 2; o > 0; o >>= 1) best = fminf(best, __shfl_xor(best, o));
         if (!act) continue;
         bool changed;
         if (TWO_SIDED) {
@@ -328,7 +357,7 @@ __global__ void __launch_bounds__(TPB)
             changed = (bf != tf) ||
                       (bf && fabsf(best - told) > eps_rel * fmaxf(1.f, fabsf(told)));
         } else {
-            if (lane == 0 && best < told) T[i] = best;
+            if (lane == 0 && best < told) T[i] = best;   // the only writer of T[i]
             changed = (told < GBP_INF) ? (best < told - eps_rel * fmaxf(1.f, fabsf(told)))
                                        : (best < GBP_INF);
         }
@@ -607,7 +636,7 @@ __global__ void __launch_bounds__(TPB)
     const int n = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
-        if (n > 0) atomicMax(&ctl->pad[0], s + 1);
+        if (n > 0) atomicMax(&ctl->levels, s + 1);
     }
     if (blockIdx.x * blockDim.x >= n) return;
     int* cnt_next = &ctl->count[(s + 1) % 3];
@@ -663,29 +692,38 @@ __global__ void k_adj_remaining(const int* __restrict__ done, int n_v, int* __re
 // finish because of a cycle in the parent graph.  Every cycle leaks weight to
 // parents outside it, so the sweeps contract to the unique solution.  Records
 // the largest |change| and the largest |lambda| of the sweep (as float bits).
-__global__ void k_adj_gs(const int* __restrict__ list, int n_list, const int* __restrict__ cptr,
+__global__ void k_adj_gs(const int* __restrict__ list, const int* __restrict__ cptr,
                          const int* __restrict__ cchild, const float* __restrict__ calpha,
                          const float* __restrict__ g, float* lam, GbpCtl* ctl, int slot) {
     // change of this sweep goes to slot (slot&1); the other slot is cleared for the next
-    int* md = slot & 1 ? &ctl->pad[2] : reinterpret_cast<int*>(&ctl->maxdiff);
-    int* md_next = slot & 1 ? reinterpret_cast<int*>(&ctl->maxdiff) : &ctl->pad[2];
+    int* md = reinterpret_cast<int*>(slot & 1 ? &ctl->maxdiff2 : &ctl->maxdiff);
+    int* md_next = reinterpret_cast<int*>(slot & 1 ? &ctl->maxdiff : &ctl->maxdiff2);
     if (blockIdx.x == 0 && threadIdx.x == 0) *md_next = 0;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_list = ctl->remaining;
     float d = 0.f, a = 0.f;
-    if (q < n_list) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_list; q += gridDim.x * blockDim.x) {
         const int i = list[q];
         float l = g[i];
         for (int x = cptr[i]; x < cptr[i + 1]; ++x) l += calpha[x] * lam[cchild[x]];
-        d = fabsf(l - lam[i]);
-        a = fabsf(l);
+        d = fmaxf(d, fabsf(l - lam[i]));
+        a = fmaxf(a, fabsf(l));
         lam[i] = l;
     }
     d = block_max_f(d);
     a = block_max_f(a);
     if (threadIdx.x == 0) {
         atomicMax(md, __float_as_int(d));
-        atomicMax(&ctl->pad[1], __float_as_int(a));
+        atomicMax(&ctl->lmax_bits, __float_as_int(a));
     }
+}
+
+// Adjoint status after `sweeps` Gauss-Seidel sweeps: unsettled if the last
+// sweep still moved lambda by more than 1e-6 of its largest magnitude.
+__global__ void k_backward_end(GbpCtl* ctl, int sweeps) {
+    if (threadIdx.x != 0 || ctl->remaining == 0) return;
+    const float md = ((sweeps - 1) & 1) ? ctl->maxdiff2 : ctl->maxdiff;
+    const float lmax = __int_as_float(ctl->lmax_bits);
+    if (sweeps == 0 || !(md <= 1e-6f * lmax)) ctl->status |= 2;
 }
 
 // ------------------------------------------------------------------ gradients
@@ -888,15 +926,13 @@ int gbp_scan_exclusive(const int* in, int* out, int n, int* tmp, hipStream_t s) 
 }
 
 // ====================================================================== host
-static int sweep_grid(int n_v) { return std::min(gbp_blocks(n_v, TPB / kLanesPerVertex), kStatBlocks); }
-
 static int read_ctl(gbp_plan p, hipStream_t s) {
     GBP_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
     GBP_HIP(hipStreamSynchronize(s));
     return GBP_OK;
 }
 
-static int err_from_bits(int bits) {
+int gbp_err_from_bits(int bits) {
     if (bits & ERRBIT_ROOT_RANGE) {
         gbp_set_error("root vertex id out of range");
         return GBP_ERR_ARG;
@@ -921,10 +957,7 @@ static int err_from_bits(int bits) {
     return GBP_ERR_HIP;
 }
 
-// metric + roots, shared by forward, backward and parent map
-static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
-                   const float* root_t, int n_roots, int cold, const float* T_init,
-                   hipStream_t s) {
+static int check_roots(const float* D, const int32_t* root_node, const float* root_t, int n_roots) {
     if (!D) {
         gbp_set_error("D is NULL");
         return GBP_ERR_ARG;
@@ -933,8 +966,17 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
         gbp_set_error("bad roots (n_roots=%d)", n_roots);
         return GBP_ERR_ARG;
     }
+    return GBP_OK;
+}
+
+// Control reset, metric, onsets and (cold == 1) +inf start with the roots' neighbours
+// queued, (cold == 0) T from T_init.  Enqueue only; no synchronisation.
+static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                   const float* root_t, int n_roots, int cold, const float* T_init,
+                   hipStream_t s) {
     const int n_v = p->n_v, n_e = p->n_e;
-    GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
+    k_mark_reset_if<<<std::min(gbp_blocks(n_v, TPB), 1024), TPB, 0, s>>>(p->mark, n_v, p->ctl);
+    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, cold == 2 ? 1 : 0);
     k_vscale_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, p->node_user, p->vs, n_v, p->ctl);
     {
         ProfScope ps(GBP_PROF_METRIC, s);
@@ -942,19 +984,90 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
                                                       p->tetg, n_e, p->ctl);
     }
     k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, GBP_INF, n_v);
-    if (cold == 1) {
+    if (cold == 1)
         k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, GBP_INF, n_v);
-    } else if (cold == 0) {
+    else   // 0: warm start from T_init; 2: T given (backward, parent map)
         k_gather_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(T_init, p->node_user, p->T, n_v);
-    }
-    if (p->stamp > (1 << 30)) {
-        GBP_HIP(hipMemsetAsync(p->mark, 0, sizeof(int) * n_v, s));
-        p->stamp = 1;
-    }
     k_roots<<<1, TPB, 0, s>>>(root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T,
-                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->stamp,
-                              p->ctl);
+                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl);
     GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
+    const int* qin = p->q[r & 1];
+    int* qout = p->q[(r + 1) & 1];
+    const int grid = std::min(p->sweep_blocks, kStatBlocks);
+    ProfScope ps(GBP_PROF_FIM_SWEEP, s);
+#define GBP_SWEEP(TS, LN)                                                                       \
+    k_sweep<TS, LN><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, qin, \
+                                         qout, p->adj_ptr, p->adj, p->mark, p->ctl, p->blk, r,   \
+                                         p->eps_rel)
+    if (cold) {
+        if (p->lanes == 8) GBP_SWEEP(false, 8);
+        else if (p->lanes == 32) GBP_SWEEP(false, 32);
+        else GBP_SWEEP(false, 16);
+    } else {
+        if (p->lanes == 8) GBP_SWEEP(true, 8);
+        else if (p->lanes == 32) GBP_SWEEP(true, 32);
+        else GBP_SWEEP(true, 16);
+    }
+#undef GBP_SWEEP
+}
+
+// Forward.  budget <= 0: synchronous, rounds until the queue empties (checked every
+// sync_batch rounds).  budget > 0: exactly `budget` rounds, no host synchronisation
+// (graph-capturable); empty rounds return at once and status bit 0 reports a queue
+// left non-empty.
+int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                     const float* root_t, int n_roots, const float* T_init, float* T_out,
+                     gbp_stats* stats, hipStream_t s, int budget) {
+    int rc = check_roots(D, root_node, root_t, n_roots);
+    if (rc) return rc;
+    const int n_v = p->n_v;
+    const bool cold = (T_init == nullptr);
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
+    k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
+    if (!cold) k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, n_v, p->ctl);
+    GBP_LAUNCH_CHECK();
+    int r = 0;
+    bool converged = true;
+    if (budget > 0) {
+        for (; r < budget; ++r) launch_round(p, cold, r, s);
+    } else {
+        if ((rc = read_ctl(p, s))) return rc;
+        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
+        converged = (p->ctl_host->count[0] == 0);
+        int batch = 4;
+        while (!converged && r < p->max_rounds) {
+            const int nb = std::min(batch, p->max_rounds - r);
+            for (int b = 0; b < nb; ++b, ++r) launch_round(p, cold, r, s);
+            GBP_LAUNCH_CHECK();
+            if ((rc = read_ctl(p, s))) return rc;
+            converged = (p->ctl_host->count[r % 3] == 0);
+            batch = std::min(batch * 2, p->sync_batch);
+        }
+    }
+    k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);
+    k_reduce_stats<<<1, TPB, 0, s>>>(p->blk, p->ctl);
+    k_count_inf<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, n_v, p->ctl);
+    k_scatter_out<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, p->node_int, T_out, n_v);
+    GBP_LAUNCH_CHECK();
+    if (budget > 0) return GBP_OK;
+    if ((rc = read_ctl(p, s))) return rc;
+    p->last_rounds = p->ctl_host->rounds;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->rounds = p->ctl_host->rounds;
+        stats->converged = converged ? 1 : 0;
+        stats->face_solves = (int64_t)p->ctl_host->solves;
+        stats->node_updates = (int64_t)p->ctl_host->updates;
+        stats->unreached = p->ctl_host->unreached;
+    }
+    if (!converged) {
+        gbp_set_error("eikonal forward: no convergence after %d rounds", r);
+        return GBP_ERR_NOT_CONVERGED;
+    }
     return GBP_OK;
 }
 
@@ -968,61 +1081,8 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
         gbp_set_error("T_out is NULL");
         return GBP_ERR_ARG;
     }
-    hipStream_t s = (hipStream_t)stream;
-    const int n_v = p->n_v;
-    const bool cold = (T_init == nullptr);
-    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
-    k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
-    if (!cold) {
-        k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, p->stamp, n_v, p->ctl);
-        GBP_LAUNCH_CHECK();
-    }
-    if ((rc = read_ctl(p, s))) return rc;
-    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
-
-    const int grid = sweep_grid(n_v);
-    int sweep = 0, batch = 4;
-    bool converged = (p->ctl_host->count[0] == 0);
-    while (!converged && sweep < p->max_rounds) {
-        const int nb = std::min(batch, p->max_rounds - sweep);
-        for (int b = 0; b < nb; ++b, ++sweep) {
-            const int* qin = p->q[sweep & 1];
-            int* qout = p->q[(sweep + 1) & 1];
-            const int st = p->stamp + sweep + 1;
-            ProfScope ps(GBP_PROF_FIM_SWEEP, s);
-            if (cold)
-                k_sweep<false><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
-                                                    p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
-                                                    p->ctl, p->blk, sweep, st, p->eps_rel);
-            else
-                k_sweep<true><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,
-                                                   p->T, qin, qout, p->adj_ptr, p->adj, p->mark,
-                                                   p->ctl, p->blk, sweep, st, p->eps_rel);
-        }
-        GBP_LAUNCH_CHECK();
-        if ((rc = read_ctl(p, s))) return rc;
-        converged = (p->ctl_host->count[sweep % 3] == 0);
-        batch = std::min(batch * 2, 16);
-    }
-    p->stamp += sweep + 2;
-    k_reduce_stats<<<1, TPB, 0, s>>>(p->blk, p->ctl);
-    k_count_inf<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, n_v, p->ctl);
-    k_scatter_out<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, p->node_int, T_out, n_v);
-    GBP_LAUNCH_CHECK();
-    if ((rc = read_ctl(p, s))) return rc;
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->rounds = p->ctl_host->pad[0];
-        stats->converged = converged ? 1 : 0;
-        stats->face_solves = (int64_t)p->ctl_host->solves;
-        stats->node_updates = (int64_t)p->ctl_host->updates;
-        stats->unreached = p->ctl_host->unreached;
-    }
-    if (!converged) {
-        gbp_set_error("eikonal forward: no convergence after %d rounds", sweep);
-        return GBP_ERR_NOT_CONVERGED;
-    }
-    return GBP_OK;
+    return gbp_forward_impl(p, D, vscale, root_node, root_t, n_roots, T_init, T_out, stats,
+                            (hipStream_t)stream, 0);
 }
 
 // parents at the converged T (internal order); T must already be in p->T
@@ -1045,11 +1105,12 @@ extern "C" int gbp_parent_map(gbp_plan p, const float* D, const float* vscale,
         gbp_set_error("NULL output or T");
         return GBP_ERR_ARG;
     }
+    if ((rc = check_roots(D, root_node, root_t, n_roots))) return rc;
     if ((rc = gbp_alloc_backward(p))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 2, T, s))) return rc;
     if ((rc = read_ctl(p, s))) return rc;
-    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+    if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
     if ((rc = run_parents(p, D, s))) return rc;
     k_parent_out<<<gbp_blocks(p->n_v, TPB), TPB, 0, s>>>(p->par, p->pa, p->tetv, p->tet_user,
                                                          p->node_user, p->node_int, p->n_v,
@@ -1067,30 +1128,45 @@ extern "C" int gbp_backward_info(gbp_plan p, int* levels, int* cyclic, int* gs_s
     return GBP_OK;
 }
 
-extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vscale,
-                                    const int32_t* root_node, const float* root_t, int n_roots,
-                                    const float* T, const float* dL_dT, float* dL_dD,
-                                    float* dL_dvscale, float* dL_droot_t, void* stream) {
-    int rc = gbp_plan_check(p);
+static void launch_level(gbp_plan p, int level, hipStream_t s) {
+    ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
+    k_adj_level<<<std::max(1, std::min(p->level_blocks, gbp_blocks(p->n_v, TPB))), TPB, 0, s>>>(
+        p->q[level & 1], p->q[(level + 1) & 1], p->ccnt, p->cchild, p->calpha, p->g, p->lam,
+        p->done, p->pnode, p->partner, p->pairrem, p->rem, p->ctl, level);
+}
+
+static void launch_gs(gbp_plan p, int it, hipStream_t s) {
+    ProfScope ps(GBP_PROF_AUX, s);
+    k_adj_gs<<<std::min(gbp_blocks(p->n_v, TPB), 1024), TPB, 0, s>>>(
+        p->cfill, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->ctl, it);
+}
+
+// Backward.  level_budget <= 0: synchronous (levels until the frontier empties,
+// Gauss-Seidel on what cycles leave until settled).  level_budget > 0: exactly
+// that many levels then gs_budget sweeps, no host synchronisation; status bit 1
+// reports an unsettled remainder.
+int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                      const float* root_t, int n_roots, const float* T, const float* dL_dT,
+                      float* dL_dD, float* dL_dvscale, float* dL_droot_t, hipStream_t s,
+                      int level_budget, int gs_budget) {
+    int rc = check_roots(D, root_node, root_t, n_roots);
     if (rc) return rc;
-    if (!T || !dL_dT) {
-        gbp_set_error("T and dL_dT are required");
-        return GBP_ERR_ARG;
-    }
     if ((rc = gbp_alloc_backward(p))) return rc;
-    hipStream_t s = (hipStream_t)stream;
     const int n_v = p->n_v, n_e = p->n_e;
-    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 0, T, s))) return rc;
-    if ((rc = read_ctl(p, s))) return rc;
-    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
+    const bool sync = level_budget <= 0;
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 2, T, s))) return rc;
+    if (sync) {
+        if ((rc = read_ctl(p, s))) return rc;
+        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
+    }
     if ((rc = run_parents(p, D, s))) return rc;
     // parent lists, two-cycle partners, children lists
     {
         ProfScope ps_child(GBP_PROF_CHILD, s);
         const int nb = gbp_blocks(n_v, TPB);
-        GBP_HIP(hipMemsetAsync(p->rem, 0, sizeof(int) * n_v, s));
-        GBP_HIP(hipMemsetAsync(p->done, 0, sizeof(int) * n_v, s));   // all-children counts
-        GBP_HIP(hipMemsetAsync(p->cfill, 0, sizeof(int) * n_v, s));
+        k_fill_i<<<nb, TPB, 0, s>>>(p->rem, 0, n_v);
+        k_fill_i<<<nb, TPB, 0, s>>>(p->done, 0, n_v);   // all-children counts
+        k_fill_i<<<nb, TPB, 0, s>>>(p->cfill, 0, n_v);
         k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode);
         k_partner<<<nb, TPB, 0, s>>>(p->pnode, n_v, p->partner);
         k_partner_sym<<<nb, TPB, 0, s>>>(p->partner, n_v, p->pairrem);
@@ -1104,60 +1180,56 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
         GBP_LAUNCH_CHECK();
     }
     // leaves-first level walk
-    GBP_HIP(hipMemsetAsync(p->ctl, 0, sizeof(GbpCtl), s));
+    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 1);
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
                                                     p->lam, p->done, p->q[0], p->ctl);
     GBP_LAUNCH_CHECK();
-    if ((rc = read_ctl(p, s))) return rc;
-    if (p->ctl_host->err) return err_from_bits(p->ctl_host->err);
-    const int grid = std::min(gbp_blocks(n_v, TPB), 256);   // small frontiers: cheap dispatch
-    int level = 0, batch = 4;
-    bool empty = (p->ctl_host->count[0] == 0);
-    const int cap = p->max_rounds + n_v;
-    while (!empty && level < cap) {
-        for (int b = 0; b < batch; ++b, ++level) {
-            ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
-            k_adj_level<<<grid, TPB, 0, s>>>(p->q[level & 1], p->q[(level + 1) & 1], p->ccnt,
-                                              p->cchild, p->calpha, p->g, p->lam, p->done,
-                                              p->pnode, p->partner, p->pairrem, p->rem, p->ctl,
-                                              level);
-        }
-        GBP_LAUNCH_CHECK();
+    int level = 0;
+    if (!sync) {
+        for (; level < level_budget; ++level) launch_level(p, level, s);
+    } else {
         if ((rc = read_ctl(p, s))) return rc;
-        empty = (p->ctl_host->count[level % 3] == 0);
-        batch = std::min(batch * 2, 16);
-    }
-    // vertices on or above longer cycles of the parent graph
-    GBP_HIP(hipMemsetAsync(&p->ctl->remaining, 0, sizeof(int), s));
-    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->cfill, p->ctl);
-    GBP_LAUNCH_CHECK();
-    if ((rc = read_ctl(p, s))) return rc;
-    p->bwd_cyclic = p->ctl_host->remaining;
-    p->bwd_levels = level;
-    p->bwd_gs_sweeps = 0;
-    if (p->ctl_host->remaining > 0) {
-        const int nl = p->ctl_host->remaining;   // list in p->cfill
-        bool ok = false;
-        int it = 0;
-        const int cap = 4 * p->max_rounds + 1000;
-        while (!ok && it < cap) {
-            for (int b = 0; b < 16; ++b, ++it) {
-                ProfScope ps_gs(GBP_PROF_AUX, s);
-                k_adj_gs<<<gbp_blocks(nl, TPB), TPB, 0, s>>>(p->cfill, nl, p->ccnt, p->cchild,
-                                                             p->calpha, p->g, p->lam, p->ctl, it);
-            }
+        bool empty = (p->ctl_host->count[0] == 0);
+        int batch = 4;
+        const int cap = p->max_rounds + n_v;
+        while (!empty && level < cap) {
+            for (int b = 0; b < batch; ++b, ++level) launch_level(p, level, s);
             GBP_LAUNCH_CHECK();
             if ((rc = read_ctl(p, s))) return rc;
-            const float lmax = __builtin_bit_cast(float, p->ctl_host->pad[1]);
-            const int last = (it - 1) & 1;
-            const float md = last ? __builtin_bit_cast(float, p->ctl_host->pad[2]) : p->ctl_host->maxdiff;
-            ok = md <= 1e-6f * lmax;
+            empty = (p->ctl_host->count[level % 3] == 0);
+            batch = std::min(batch * 2, p->sync_batch);
+        }
+    }
+    // vertices on or above cycles longer than two: Gauss-Seidel on the remainder
+    k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->cfill, p->ctl);
+    GBP_LAUNCH_CHECK();
+    int it = 0;
+    if (!sync) {
+        for (; it < gs_budget; ++it) launch_gs(p, it, s);
+        k_backward_end<<<1, 64, 0, s>>>(p->ctl, it);
+    } else {
+        if ((rc = read_ctl(p, s))) return rc;
+        p->bwd_levels = p->ctl_host->levels;
+        p->last_levels = p->ctl_host->levels;
+        p->bwd_cyclic = p->ctl_host->remaining;
+        if (p->ctl_host->remaining > 0) {
+            bool ok = false;
+            const int cap = 4 * p->max_rounds + 1000;
+            while (!ok && it < cap) {
+                for (int b = 0; b < 16; ++b, ++it) launch_gs(p, it, s);
+                GBP_LAUNCH_CHECK();
+                if ((rc = read_ctl(p, s))) return rc;
+                const float lmax = __builtin_bit_cast(float, p->ctl_host->lmax_bits);
+                const float md = ((it - 1) & 1) ? p->ctl_host->maxdiff2 : p->ctl_host->maxdiff;
+                ok = md <= 1e-6f * lmax;
+            }
+            if (!ok) {
+                gbp_set_error("adjoint did not settle on %d vertices left by parent-graph cycles",
+                              p->bwd_cyclic);
+                return GBP_ERR_NOT_CONVERGED;
+            }
         }
         p->bwd_gs_sweeps = it;
-        if (!ok) {
-            gbp_set_error("adjoint did not settle on %d vertices left by parent-graph cycles", nl);
-            return GBP_ERR_NOT_CONVERGED;
-        }
     }
     // gradients
     ProfScope ps_grad(GBP_PROF_GRAD, s);
@@ -1171,5 +1243,33 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
                                                              p->node_int, n_v, p->par, p->troot,
                                                              p->T, p->lam, dL_droot_t);
     GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vscale,
+                                    const int32_t* root_node, const float* root_t, int n_roots,
+                                    const float* T, const float* dL_dT, float* dL_dD,
+                                    float* dL_dvscale, float* dL_droot_t, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T || !dL_dT) {
+        gbp_set_error("T and dL_dT are required");
+        return GBP_ERR_ARG;
+    }
+    return gbp_backward_impl(p, D, vscale, root_node, root_t, n_roots, T, dL_dT, dL_dD, dL_dvscale,
+                             dL_droot_t, (hipStream_t)stream, 0, 0);
+}
+
+extern "C" int gbp_plan_status(gbp_plan p, int* err_code, int* forward_converged,
+                               int* backward_settled, int* rounds, int* levels, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if ((rc = read_ctl(p, (hipStream_t)stream))) return rc;
+    const GbpCtl& c = *p->ctl_host;
+    if (err_code) *err_code = c.err ? gbp_err_from_bits(c.err) : GBP_OK;
+    if (forward_converged) *forward_converged = (c.status & 1) ? 0 : 1;
+    if (backward_settled) *backward_settled = (c.status & 2) ? 0 : 1;
+    if (rounds) *rounds = c.rounds;
+    if (levels) *levels = c.levels;
     return GBP_OK;
 }

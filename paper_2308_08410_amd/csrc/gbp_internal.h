@@ -48,9 +48,15 @@ struct GbpCtl {
     unsigned long long solves;     // local problems evaluated
     unsigned long long updates;    // nodes that changed
     int unreached;
-    int remaining;                 // adjoint: nodes not finished by the level sweep
-    float maxdiff;                 // adjoint fallback: largest change of a sweep (as int bits)
-    int pad[3];
+    int remaining;                 // adjoint: vertices the level walk did not finish
+    float maxdiff;                 // adjoint fallback: largest change of an even sweep
+    float maxdiff2;                // ... of an odd sweep
+    int rounds;                    // forward: last round with work + 1
+    int lmax_bits;                 // adjoint fallback: largest |lambda| (float bits)
+    int stamp;                     // queue stamp base, kept across calls
+    int status;                    // bit 0: forward not converged, bit 1: adjoint not settled
+    int levels;                    // adjoint: last level with work + 1
+    int pad;
 };
 
 struct gbp_plan_s {
@@ -78,7 +84,12 @@ struct gbp_plan_s {
     float* troot = nullptr;       // [n_v] min onset per node (+inf elsewhere)
     int* q[2] = {nullptr, nullptr};  // work queues
     int* mark = nullptr;          // [n_v] queue stamps
-    int stamp = 1;                // next stamp base (host side)
+    // launch configuration (autotunable)
+    int lanes = 16;               // lanes per vertex in a relaxation round (8, 16 or 32)
+    int sweep_blocks = 2048;      // grid of a relaxation round (<= kStatBlocks)
+    int level_blocks = 256;       // grid of an adjoint level
+    int sync_batch = 16;          // launches between convergence checks (synchronous mode)
+    int last_rounds = 0, last_levels = 0;   // of the last synchronous calls
     GbpCtl* ctl = nullptr;        // device control block
     unsigned long long* blk = nullptr;  // [2 * kStatBlocks] per-block (solves, updates)
     GbpCtl* ctl_host = nullptr;   // pinned mirror
@@ -107,6 +118,15 @@ struct gbp_plan_s {
 constexpr int kStatBlocks = 2048;   // max grid of the relaxation kernels
 
 int gbp_plan_check(gbp_plan p);
+int gbp_err_from_bits(int bits);
+// budget <= 0: synchronous; > 0: fixed launch counts, graph-capturable
+int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                     const float* root_t, int n_roots, const float* T_init, float* T_out,
+                     gbp_stats* stats, hipStream_t s, int budget);
+int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
+                      const float* root_t, int n_roots, const float* T, const float* dL_dT,
+                      float* dL_dD, float* dL_dvscale, float* dL_droot_t, hipStream_t s,
+                      int level_budget, int gs_budget);
 int gbp_alloc_backward(gbp_plan p);
 
 // exclusive scan of n ints in place into out[0..n] (out[n] = total); device

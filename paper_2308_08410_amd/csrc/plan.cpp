@@ -296,8 +296,10 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(dalloc(&p->ctl, 1));
     TRY(dalloc(&p->blk, 2 * (size_t)kStatBlocks));
 #undef TRY
+    GbpCtl c0{};
+    c0.stamp = 1;
     if (hipMemset(p->mark, 0, sizeof(int) * n_v) != hipSuccess ||
-        hipMemset(p->ctl, 0, sizeof(GbpCtl)) != hipSuccess) {
+        hipMemcpy(p->ctl, &c0, sizeof(GbpCtl), hipMemcpyHostToDevice) != hipSuccess) {
         gbp_set_error("hipMemset failed");
         plan_free(p);
         return GBP_ERR_HIP;
@@ -327,5 +329,44 @@ int gbp_alloc_backward(gbp_plan p) {
         (rc = dalloc(&p->scan_tmp, (size_t)(n_v / 256 + 2))))
         return rc;
     p->bwd_ready = true;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_launch(gbp_plan p, int lanes, int sweep_blocks, int level_blocks,
+                                   int sync_batch) {
+    if (!p || !(lanes == 8 || lanes == 16 || lanes == 32) || sweep_blocks < 64 ||
+        sweep_blocks > kStatBlocks || level_blocks < 16 || level_blocks > 2048 || sync_batch < 1 ||
+        sync_batch > 64) {
+        gbp_set_error("set_launch: lanes in {8,16,32}, sweep_blocks 64..%d, level_blocks 16..2048, "
+                      "sync_batch 1..64", kStatBlocks);
+        return GBP_ERR_ARG;
+    }
+    p->lanes = lanes;
+    p->sweep_blocks = sweep_blocks;
+    p->level_blocks = level_blocks;
+    p->sync_batch = sync_batch;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_launch(gbp_plan p, int* lanes, int* sweep_blocks, int* level_blocks,
+                                   int* sync_batch) {
+    if (!p) {
+        gbp_set_error("null plan");
+        return GBP_ERR_ARG;
+    }
+    if (lanes) *lanes = p->lanes;
+    if (sweep_blocks) *sweep_blocks = p->sweep_blocks;
+    if (level_blocks) *level_blocks = p->level_blocks;
+    if (sync_batch) *sync_batch = p->sync_batch;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_last_counts(gbp_plan p, int* rounds, int* levels) {
+    if (!p) {
+        gbp_set_error("null plan");
+        return GBP_ERR_ARG;
+    }
+    if (rounds) *rounds = p->last_rounds;
+    if (levels) *levels = p->last_levels;
     return GBP_OK;
 }

@@ -1,0 +1,150 @@
+"""Batched form: several uneven meshes solved as one union plan, the batched ECG and
+misfit, the graph-captured iteration (replayed several times and checked against
+the same operations run eagerly), and the autotuner."""
+import numpy as np
+import pytest
+
+import gbp_inputs as gi
+import oracle as O
+from test_gpu_parity import B, _dev, i32, rel_l2, rel_max, t32
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def make_batch():
+    from paper_2308_08410_amd.batch import concat, shift_roots, union_mesh
+    probs = [gi.shell_problem(n, seed=30 + k, n_roots=1 + 2 * k, vscale_range=(0.5, 1.5))
+             for k, n in enumerate((3_000, 9_000, 5_000))]
+    probs.append(gi.cube_problem(7, jitter=0.1, n_leads=12))
+    xyz, tets, voff, eoff = union_mesh([p.xyz for p in probs], [p.tets for p in probs])
+    D = concat([p.D for p in probs])
+    vs = concat([p.vscale for p in probs])
+    W = concat([p.W for p in probs])
+    rn = shift_roots([p.root_node for p in probs], voff)
+    rt = concat([p.root_t for p in probs])
+    return probs, xyz, tets, voff, D, vs, W, rn, rt
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return make_batch()
+
+
+AP = dict(K0=-85.0, K1=30.0, tau=1.0, t0=0.0, dt=1.0, n_steps=160)
+
+
+def test_union_forward_equals_instances_and_oracle(batch):
+    dev = _dev()
+    probs, xyz, tets, voff, D, vs, W, rn, rt = batch
+    plan = B().Plan(xyz, tets)
+    T, st = B().eikonal_forward(plan, t32(D, dev), t32(vs, dev), i32(rn, dev), t32(rt, dev))
+    Tg = T.cpu().numpy()
+    assert st["converged"] and st["unreached"] == 0
+    for k, p in enumerate(probs):
+        sl = slice(voff[k], voff[k + 1])
+        To, _ = O.solve(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t)
+        assert rel_max(Tg[sl], To) <= 1e-4
+
+
+def test_batched_ecg_and_loss_equal_per_instance(batch):
+    dev = _dev()
+    probs, xyz, tets, voff, D, vs, W, rn, rt = batch
+    bt = B().Batch(voff, AP["n_steps"])
+    r = np.random.Generator(np.random.PCG64(1))
+    T = np.concatenate([r.uniform(0, 120, size=len(p.xyz)) for p in probs]).astype(np.float32)
+    ap = B().make_ap(**AP)
+    e = B().ecg_forward_batched(bt, t32(T, dev), t32(W, dev), ap).cpu().numpy()
+    tgt = r.normal(size=e.shape).astype(np.float32) * np.abs(e).max()
+    loss, G = B().ecg_loss_batched(t32(e, dev), t32(tgt, dev))
+    dT = B().ecg_backward_batched(bt, t32(T, dev), t32(W, dev), ap, G).cpu().numpy()
+    for k, p in enumerate(probs):
+        sl = slice(voff[k], voff[k + 1])
+        eo = O.ecg_forward(T[sl], W[sl], AP)
+        assert np.abs(e[k] - eo).max() / np.abs(eo).max() <= 1e-3
+        lo, Go = O.ecg_loss(e[k], tgt[k])
+        assert float(loss[k]) == pytest.approx(lo, rel=1e-5)
+        do = O.ecg_backward(T[sl], W[sl], AP, Go)
+        assert rel_l2(dT[sl], do) <= 1e-3
+
+
+def _eager_iteration(plan, bt, D, vs, rn, rt, W, ap, tgt, st, lr_vs=0.01, lr_rt=0.5, warm_T=None):
+    T, _ = B().eikonal_forward(plan, D, vs, rn, rt, T_init=warm_T)
+    e = B().ecg_forward_batched(bt, T, W, ap)
+    loss, G = B().ecg_loss_batched(e, tgt)
+    gT = B().ecg_backward_batched(bt, T, W, ap, G)
+    _, dvs, drt = B().eikonal_backward(plan, D, vs, rn, rt, T, gT, want_D=False)
+    st["k"] += 1
+    B().adam_step(vs, dvs, st["mv"], st["vv"], st["k"], lr=lr_vs, lo=0.2, hi=5.0)
+    B().adam_step(rt, drt, st["mr"], st["vr"], st["k"], lr=lr_rt)
+    return T, e, loss
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_graph_step_replays_match_eager(batch, warm):
+    dev = _dev()
+    from paper_2308_08410_amd import autotune
+    probs, xyz, tets, voff, D, vs, W, rn, rt = batch
+    plan = B().Plan(xyz, tets)
+    bt = B().Batch(voff, AP["n_steps"])
+    ap = B().make_ap(**AP)
+    Dd, Wd, rnd = t32(D, dev), t32(W, dev), i32(rn, dev)
+    # target from perturbed parameters (oracle only)
+    tgt = np.zeros((bt.n_inst, AP["n_steps"], W.shape[1]), np.float32)
+    for k, p in enumerate(probs):
+        To, _ = O.solve(p.xyz, p.tets, p.D, p.vscale * 1.1, p.root_node, p.root_t)
+        tgt[k] = O.ecg_forward(To, p.W, AP)
+    tgtd = t32(tgt, dev)
+    # eager reference
+    vs_e, rt_e = t32(vs, dev), t32(rt, dev)
+    st = dict(k=0, mv=torch.zeros_like(vs_e), vv=torch.zeros_like(vs_e), mr=torch.zeros_like(rt_e),
+              vr=torch.zeros_like(rt_e))
+    B().eikonal_forward(plan, Dd, vs_e, rnd, rt_e)
+    B().eikonal_backward(plan, Dd, vs_e, rnd, rt_e, B().eikonal_forward(plan, Dd, vs_e, rnd, rt_e)[0],
+                         torch.ones_like(vs_e))
+    bud = autotune.budgets(plan)
+    # captured step on its own parameter copies
+    vs_g, rt_g = t32(vs, dev), t32(rt, dev)
+    T_g = torch.empty(len(xyz), dtype=torch.float32, device=dev)
+    if warm:
+        B().eikonal_forward(plan, Dd, vs_g, rnd, rt_g, out=T_g)
+    ecg_g = torch.empty((bt.n_inst, AP["n_steps"], W.shape[1]), dtype=torch.float32, device=dev)
+    loss_g = torch.empty(bt.n_inst, dtype=torch.float32, device=dev)
+    step = B().Step(plan, bt, Dd, vs_g, rnd, rt_g, Wd, ap, tgtd, T_g, ecg_g, loss_g, warm=warm, **bud)
+    T_prev = T_g.clone() if warm else None
+    for rep in range(3):
+        T_e, e_e, l_e = _eager_iteration(plan, bt, Dd, vs_e, rnd, rt_e, Wd, ap, tgtd, st,
+                                         warm_T=T_prev)
+        torch.cuda.synchronize()
+        step.launch()
+        status = B().plan_status(plan)
+        assert status["forward_converged"] and status["backward_settled"] and status["err"] == 0
+        torch.cuda.synchronize()
+        assert rel_max(T_g.cpu().numpy(), T_e.cpu().numpy()) <= 1e-5, rep
+        assert torch.allclose(loss_g, l_e, rtol=1e-4), rep
+        assert torch.allclose(vs_g, vs_e, rtol=1e-4, atol=1e-5), rep
+        assert torch.allclose(rt_g, rt_e, rtol=1e-4, atol=1e-4), rep
+        if warm:
+            T_prev = T_g.clone()
+    step.close()
+
+
+def test_autotuner_selects_valid_config(batch, tmp_path, monkeypatch):
+    dev = _dev()
+    from paper_2308_08410_amd import autotune
+    monkeypatch.setenv("GBP_TUNE_CACHE", str(tmp_path / "launch.json"))
+    probs, xyz, tets, voff, D, vs, W, rn, rt = batch
+    plan = B().Plan(xyz, tets)
+    Dd, vsd, rnd, rtd = t32(D, dev), t32(vs, dev), i32(rn, dev), t32(rt, dev)
+    T0, _ = B().eikonal_forward(plan, Dd, vsd, rnd, rtd)
+    rec = autotune.tune(plan, Dd, vsd, rnd, rtd, repeats=1)
+    assert rec["lanes"] in (8, 16, 32) and rec["rounds"] > 0 and rec["levels"] > 0
+    assert B().get_launch(plan)["lanes"] == rec["lanes"]
+    T1, _ = B().eikonal_forward(plan, Dd, vsd, rnd, rtd)
+    assert rel_max(T1.cpu().numpy(), T0.cpu().numpy()) <= 1e-5
+    rec2 = autotune.tune(plan, Dd, vsd, rnd, rtd)
+    assert rec2["cached"] and rec2["lanes"] == rec["lanes"]
+    for lanes in (8, 32):
+        B().set_launch(plan, lanes, 1024, 128)
+        T2, _ = B().eikonal_forward(plan, Dd, vsd, rnd, rtd)
+        assert rel_max(T2.cpu().numpy(), T0.cpu().numpy()) <= 1e-5
