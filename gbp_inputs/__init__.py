@@ -31,7 +31,7 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = [
-    "kuhn_cube", "shell_mesh", "Shell", "fibre_tensor", "endocardial_nodes",
+    "kuhn_cube", "shell_mesh", "Shell", "mlp_params", "mlp_rows", "MLP_SIZES", "fibre_tensor", "endocardial_nodes",
     "random_roots", "smooth_field", "sphere_electrodes", "lead_weights",
     "jitter_nodes", "Problem", "cube_problem", "shell_problem", "AP_CUBE",
     "AP_SHELL", "tet_volumes",
@@ -121,6 +121,7 @@ class Shell:
     fibre: np.ndarray        # float32 [n_e, 3] unit fibre direction per tet
     endo: np.ndarray         # int32 node ids on the endocardial surfaces
     radius: float            # max distance of a node from the bbox centre
+    node_fibre: np.ndarray = None   # float32 [n_v, 3] the same fibre field at the nodes
 
 
 # Geometry of the synthetic biventricular shell (mm).  LV: truncated prolate
@@ -217,9 +218,16 @@ def shell_mesh(target_nodes: int, seed: int = 2, jitter: float = 0.1) -> Shell:
     endo = np.nonzero(lv_e | rv_e)[0].astype(np.int32)
     centre = 0.5 * (xyz.min(0) + xyz.max(0))
     radius = float(np.linalg.norm(xyz - centre, axis=1).max())
+    lv_n = _in_ell(xyz, (0, 0, 0), tuple(a * 1.0001 for a in _LV_EPI))
+    fn = np.empty((len(xyz), 3))
+    if lv_n.any():
+        fn[lv_n] = _fibres(xyz[lv_n], (0, 0, 0), _LV_ENDO, _LV_EPI, 60.0, -60.0)
+    if (~lv_n).any():
+        fn[~lv_n] = _fibres(xyz[~lv_n], _RV_C, _RV_ENDO, _RV_EPI, 60.0, -60.0)
     xyz_j = jitter_nodes(xyz, h, jitter, seed) if jitter > 0 else xyz.astype(np.float32)
     return Shell(xyz=xyz_j, tets=tets.astype(np.int32), h=float(h),
-                 fibre=f.astype(np.float32), endo=endo, radius=radius)
+                 fibre=f.astype(np.float32), endo=endo, radius=radius,
+                 node_fibre=fn.astype(np.float32))
 
 
 def _shell_grid(h):
@@ -371,9 +379,10 @@ def cube_problem(n_cells: int = 20, seed: int = 1, n_leads: int = 8, jitter: flo
         vscale = np.ones(len(xyz), dtype=np.float32)
     el = sphere_electrodes((0.5, 0.5, 0.5), 3.0, n_leads, seed)
     W = lead_weights(xyz, tets, el)
+    nf = np.tile(np.array([[1.0, 0.0, 0.0]], np.float32), (len(xyz), 1))
     return Problem("cube", xyz, tets, np.asarray(D, np.float32), np.asarray(vscale, np.float32),
                    np.array([0], np.int32), np.array([0.0], np.float32), W, dict(AP_CUBE), h,
-                   extra=dict(electrodes=el))
+                   extra=dict(electrodes=el, node_fibre=nf))
 
 
 def shell_problem(target_nodes: int = 500_000, seed: int = 2, n_roots: int = 5, n_leads: int = 12,
@@ -393,4 +402,42 @@ def shell_problem(target_nodes: int = 500_000, seed: int = 2, n_roots: int = 5, 
     el = sphere_electrodes(centre, 3.0 * sh.radius, n_leads, seed + 3)
     W = lead_weights(sh.xyz, sh.tets, el)
     return Problem("shell", sh.xyz, sh.tets, D, vs, rn, rt, W, dict(AP_SHELL), sh.h,
-                   extra=dict(electrodes=el, endo=sh.endo, fibre=sh.fibre))
+                   extra=dict(electrodes=el, endo=sh.endo, fibre=sh.fibre, node_fibre=sh.node_fibre))
+
+
+# ---------------------------------------------------------------- warm-start network
+MLP_SIZES = (("W1", (256, 16)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+             ("W3", (256, 256)), ("b3", (256,)), ("W4", (256, 256)), ("b4", (256,)),
+             ("w5", (256,)), ("b5", (1,)))
+
+
+def mlp_params(seed: int, bias_scale: float = 0.1) -> np.ndarray:
+    """Random parameter vector for the 16 -> 4x256 -> 1 network in its flat order
+    (W1, b1, ..., W4, b4, w5, b5): He-normal weights (fan-in 15 for W1, whose
+    16th column is zero), normal biases of std ``bias_scale``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for name, shape in MLP_SIZES:
+        if name == "W1":
+            w = rng.normal(0.0, np.sqrt(2.0 / 15.0), size=shape)
+            w[:, 15] = 0.0
+        elif name[0] == "W":
+            w = rng.normal(0.0, np.sqrt(2.0 / shape[1]), size=shape)
+        elif name == "w5":
+            w = rng.normal(0.0, np.sqrt(1.0 / 256.0), size=shape)
+        else:
+            w = rng.normal(0.0, bias_scale, size=shape)
+        parts.append(w.ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_rows(m: int, seed: int, scale: float = 1.0):
+    """m random network input rows of 16 bfloat16 numbers (the last one 0):
+    normal draws times ``scale`` stored as float32, of which the upper 16 bits
+    are kept.  Returns (bit patterns as int16 [m, 16], values as float64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = (rng.normal(size=(m, 16)) * scale).astype(np.float32)
+    x[:, 15] = 0.0
+    bits = (x.view(np.uint32) >> 16).astype(np.uint16)
+    vals = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return bits.view(np.int16), vals

@@ -334,6 +334,69 @@ int gbp_step_create(const gbp_step_desc *desc, gbp_step *out);
 int gbp_step_launch(gbp_step step, void *stream);
 void gbp_step_destroy(gbp_step step);
 
+/*
+ * Learned warm start (an extension beyond the paper, which solves every
+ * forward from scratch): a multilayer perceptron 16 -> 256 -> 256 -> 256 -> 256
+ * -> 1 with ReLU activations predicts activation times from per-vertex
+ * features; its prediction seeds gbp_eikonal_forward's T_init (two-sided
+ * update), whose fixed point is the cold solution whatever the guess.
+ *
+ * Precision: features and hidden weights are bf16, products accumulate in
+ * fp32 on the matrix cores, hidden activations are stored as bf16; the output
+ * layer, master weights, gradients and Adam moments are fp32.  Backward rounds
+ * the back-propagated activations' gradients to bf16 at each layer.
+ * Parameter vector (fp32, gbp_mlp_num_params entries, this order): W1[256][16],
+ * b1[256], W2[256][256], b2, W3[256][256], b3, W4[256][256], b4, w5[256], b5[1]
+ * (row-major, W_l maps layer l-1 to layer l).
+ *
+ * gbp_mlp_create: allocates a network for batches of up to max_rows rows
+ *   (1 <= max_rows <= 2^21),
+ *   He-normal weights from `seed` (column 16 of W1, the pad feature, is zero),
+ *   zero biases and moments.  Errors: GBP_ERR_ARG, GBP_ERR_NOMEM, GBP_ERR_HIP.
+ * gbp_mlp_set_params / gbp_mlp_get_params: host fp32 copies of the parameter
+ *   vector (and of the last gradient); synchronous on `stream`.
+ * gbp_mlp_features: X[r][16] (bf16 bit patterns, device) for the vertices
+ *   rows[r] (device int32, or NULL for rows r = 0..n_rows-1, n_rows <= n_v) of a
+ *   mesh given by xyz[n_v*3] and unit fibre directions fibre[n_v*3] (device,
+ *   user order); a row id outside [0, n_v) gives zero features and a NaN target:
+ *     0-2   (x - c) / len_scale
+ *     3-5   fibre direction
+ *     6-13  the 8 values |x - x_r| / len_scale + t_r / time_scale over the roots
+ *           (root_xyz[n_roots*3], root_t[n_roots], device; 1 <= n_roots <= 8,
+ *           fewer than 8 repeat root 0), sorted ascending
+ *     14    vscale[i] (device, or NULL for 1)
+ *     15    0
+ *   norm: HOST float[5] = {cx, cy, cz, len_scale, time_scale}.  With T (device
+ *   [n_v]) and target (device [n_rows]) non-NULL, also target[r] = T[rows[r]] /
+ *   time_scale (training data).  Errors: GBP_ERR_ARG.
+ * gbp_mlp_forward: y[m] = out_scale * MLP(X) for m <= max_rows rows (device);
+ *   non-finite predictions are written as +inf, which the warm-started solve
+ *   treats as no information.
+ * gbp_mlp_gradient: forward, mean squared error against target[m] (device),
+ *   written to *loss (device, may be NULL), and the parameter gradient (kept in
+ *   the network; read with gbp_mlp_get_params).
+ * gbp_mlp_train_step: gbp_mlp_gradient followed by one Adam step (beta 0.9,
+ *   0.999, eps 1e-8, bias-corrected) with learning rate lr on the fp32 masters
+ *   and a refresh of their bf16 copies.
+ * All calls on one network are stream-ordered and must not overlap.
+ */
+typedef struct gbp_mlp_s *gbp_mlp;
+int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp *out);
+void gbp_mlp_destroy(gbp_mlp mlp);
+int gbp_mlp_num_params(gbp_mlp mlp);
+int gbp_mlp_set_params(gbp_mlp mlp, const float *params, void *stream);
+int gbp_mlp_get_params(gbp_mlp mlp, float *params, float *grads, void *stream);
+int gbp_mlp_features(const float *xyz, const float *fibre, const float *vscale, int n_v,
+                     const int32_t *rows, int n_rows, const float *root_xyz,
+                     const float *root_t, int n_roots, const float *norm, const float *T,
+                     uint16_t *X, float *target, void *stream);
+int gbp_mlp_forward(gbp_mlp mlp, const uint16_t *X, int m, float out_scale, float *y,
+                    void *stream);
+int gbp_mlp_gradient(gbp_mlp mlp, const uint16_t *X, int m, const float *target, float *loss,
+                     void *stream);
+int gbp_mlp_train_step(gbp_mlp mlp, const uint16_t *X, int m, const float *target, float lr,
+                       float *loss, void *stream);
+
 const char *gbp_last_error(void);
 const char *gbp_version(void);
 

@@ -432,3 +432,103 @@ class Step:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned warm start (MLP)
+_mlp_create = _sig("gbp_mlp_create", [c_int, ctypes.c_uint64, ctypes.POINTER(c_void_p)])
+_mlp_destroy = _sig("gbp_mlp_destroy", [c_void_p], None)
+_mlp_nparams = _sig("gbp_mlp_num_params", [c_void_p])
+_mlp_set = _sig("gbp_mlp_set_params", [c_void_p, c_void_p, c_void_p])
+_mlp_get = _sig("gbp_mlp_get_params", [c_void_p, c_void_p, c_void_p, c_void_p])
+_mlp_features = _sig("gbp_mlp_features", [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p,
+                                          c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p])
+_mlp_forward = _sig("gbp_mlp_forward", [c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p])
+_mlp_gradient = _sig("gbp_mlp_gradient", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p])
+_mlp_train = _sig("gbp_mlp_train_step", [c_void_p, c_void_p, c_int, c_void_p, c_float, c_void_p,
+                                         c_void_p])
+
+MLP_IN = 16
+
+
+class MLP:
+    """The warm-start network (gbp_mlp): parameters live on the device."""
+
+    def __init__(self, max_rows, seed=0):
+        h = c_void_p()
+        _check(_mlp_create(int(max_rows), int(seed), ctypes.byref(h)))
+        self._h = h
+        self.max_rows = int(max_rows)
+        self.n_params = _mlp_nparams(h)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _mlp_destroy is not None:
+            _mlp_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get_params(self, grads=False, stream=None):
+        p = np.empty(self.n_params, np.float32)
+        g = np.empty(self.n_params, np.float32) if grads else None
+        _check(_mlp_get(self._h, p.ctypes.data, g.ctypes.data if grads else None, _stream(stream)))
+        return (p, g) if grads else p
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(np.asarray(params, np.float32))
+        if p.shape != (self.n_params,):
+            raise ValueError(f"params must have shape ({self.n_params},)")
+        _check(_mlp_set(self._h, p.ctypes.data, _stream(stream)))
+
+    def forward(self, X, out_scale=1.0, out=None, stream=None):
+        m = X.shape[0]
+        if out is None:
+            out = torch.empty(m, dtype=torch.float32, device=X.device)
+        _check(_mlp_forward(self._h, _ptr(X, torch.int16, (m, MLP_IN), "X"), m, float(out_scale),
+                            _ptr(out, torch.float32, (m,), "y"), _stream(stream)))
+        return out
+
+    def gradient(self, X, target, stream=None):
+        m = X.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(_mlp_gradient(self._h, _ptr(X, torch.int16, (m, MLP_IN), "X"), m,
+                             _ptr(target, torch.float32, (m,), "target"), loss.data_ptr(), _stream(stream)))
+        return loss
+
+    def train_step(self, X, target, lr, loss=None, stream=None):
+        m = X.shape[0]
+        _check(_mlp_train(self._h, _ptr(X, torch.int16, (m, MLP_IN), "X"), m,
+                          _ptr(target, torch.float32, (m,), "target"), float(lr),
+                          _ptr(loss, torch.float32, (1,), "loss"), _stream(stream)))
+
+
+def mlp_features(xyz, fibre, root_xyz, root_t, norm, vscale=None, rows=None, T=None, n_rows=None,
+                 stream=None):
+    """Feature rows (bf16 bit patterns in an int16 tensor [n_rows, 16]) and, with
+    T, the training targets T[rows] / time_scale.  norm = (cx, cy, cz, len_scale,
+    time_scale)."""
+    n_v = xyz.shape[0]
+    R = root_t.numel()
+    n = rows.numel() if rows is not None else (n_rows if n_rows is not None else n_v)
+    X = torch.empty((n, MLP_IN), dtype=torch.int16, device=xyz.device)
+    tgt = torch.empty(n, dtype=torch.float32, device=xyz.device) if T is not None else None
+    nrm = np.ascontiguousarray(np.asarray(norm, np.float32))
+    if nrm.shape != (5,):
+        raise ValueError("norm must hold 5 values")
+    _check(_mlp_features(_ptr(xyz, torch.float32, (n_v, 3), "xyz"), _ptr(fibre, torch.float32, (n_v, 3), "fibre"),
+                         _ptr(vscale, torch.float32, (n_v,), "vscale"), n_v,
+                         _ptr(rows, torch.int32, (n,), "rows"),
+                         n, _ptr(root_xyz, torch.float32, (R, 3), "root_xyz"),
+                         _ptr(root_t, torch.float32, (R,), "root_t"), R, nrm.ctypes.data,
+                         _ptr(T, torch.float32, (n_v,), "T"), X.data_ptr(),
+                         tgt.data_ptr() if tgt is not None else None, _stream(stream)))
+    return (X, tgt) if T is not None else X

@@ -1,0 +1,523 @@
+// Learned warm start: a small MLP (16 inputs -> 4 x 256 ReLU -> 1) that predicts
+// activation times from per-vertex features, trained and evaluated with BF16
+// matrix-core kernels (v_mfma_f32_16x16x16_bf16, FP32 accumulation).
+//
+// Precision policy (mirrored by the reference):
+//   features X and the hidden-layer weights W1..W4 are rounded to bf16;
+//   Z_l = H_{l-1} W_l^T + b_l accumulates in fp32, H_l = bf16(relu(Z_l));
+//   y = H_4 . w5 + b5 in fp32 (w5, b5 fp32);
+//   backward: dy = 2 (y - t) / m; dZ_4 = bf16(dy w5 [H_4 > 0]);
+//   dW_l = dZ_l^T H_{l-1} and db_l = sum_i dZ_l accumulate in fp32;
+//   dZ_{l-1} = bf16((dZ_l W_l) [H_{l-1} > 0]);  Adam on fp32 master weights.
+#include <math.h>
+
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "gbp_internal.h"
+
+namespace {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;
+
+constexpr int IN = 16;      // 15 features + 1 zero pad
+constexpr int HID = 256;
+constexpr int NLAYER = 4;   // hidden layers
+
+__device__ __forceinline__ bf16 to_bf16(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (bf16)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
+
+// ---------------------------------------------------------------- GEMM
+// C[i][j] = sum_k A(i,k) B(k,j) with A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc]
+// (bf16), 64x64 tile per block of 4 waves, each wave 32x32 = 2x2 MFMA tiles, K in
+// steps of 16 staged through LDS (B stored transposed so fragments are contiguous).
+enum { EPI_BIAS_RELU = 0, EPI_MASK = 1, EPI_PARTIAL = 2 };
+
+template <int EPI>
+__global__ void __launch_bounds__(256)
+    k_gemm(const bf16* __restrict__ A, int ar, int ac, const bf16* __restrict__ Bm, int br, int bc,
+           int M, int N, int K, int kchunk, const float* __restrict__ bias,
+           const bf16* __restrict__ mask, bf16* __restrict__ out, float* __restrict__ part) {
+    __shared__ bf16 As[64][16 + 4];
+    __shared__ bf16 Bt[64][16 + 4];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    floatx4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+            const int r = e >> 4, kk = e & 15;
+            const int gi = i0 + r, gk = k0 + kk;
+            As[r][kk] = (gi < M && gk < ke) ? A[(size_t)gi * ar + (size_t)gk * ac] : (bf16)0;
+            const int gj = j0 + r;
+            Bt[r][kk] = (gj < N && gk < ke) ? Bm[(size_t)gk * br + (size_t)gj * bc] : (bf16)0;
+        }
+        __syncthreads();
+        bf16x4_t af[2], bfv[2];
+        for (int t = 0; t < 2; ++t) {
+            const int ra = wi + t * 16 + (lane & 15), rb = wj + t * 16 + (lane & 15);
+            const int kq = (lane >> 4) * 4;
+            for (int q = 0; q < 4; ++q) {
+                af[t][q] = (short)As[ra][kq + q];
+                bfv[t][q] = (short)Bt[rb][kq + q];
+            }
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfv[b], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wi + a * 16 + (lane >> 4) * 4 + r;
+                const int j = j0 + wj + b * 16 + (lane & 15);
+                if (i >= M || j >= N) continue;
+                const float v = acc[a][b][r];
+                if (EPI == EPI_BIAS_RELU) {
+                    out[(size_t)i * N + j] = to_bf16(fmaxf(v + bias[j], 0.f));
+                } else if (EPI == EPI_MASK) {
+                    const bf16 h = mask[(size_t)i * N + j];
+                    out[(size_t)i * N + j] = to_bf16((h != 0 && !(h & 0x8000)) ? v : 0.f);
+                } else {
+                    part[(size_t)blockIdx.z * M * N + (size_t)i * N + j] = v;
+                }
+            }
+}
+
+// sum of split-K partials (fixed order)
+__global__ void k_reduce_parts(const float* __restrict__ part, int splits, int n,
+                               float* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + t];
+    out[t] = s;
+}
+
+// column sums of a bf16 [m x n] matrix (bias gradients), fixed order per column
+__global__ void k_colsum_bf16(const bf16* __restrict__ X, int m, int n, float* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float s = 0.f;
+    for (int i = 0; i < m; ++i) s += from_bf16(X[(size_t)i * n + j]);
+    out[j] = s;
+}
+
+// ---------------------------------------------------------------- head, loss
+// y_i = H4_i . w5 + b5 (16 lanes per row, fp32)
+__global__ void k_head(const bf16* __restrict__ H, int m, const float* __restrict__ w5,
+                       const float* __restrict__ b5, float* __restrict__ y) {
+    const int lane = threadIdx.x & 15;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    if (i >= m) return;
+    float s = 0.f;
+    for (int j = lane; j < HID; j += 16) s += from_bf16(H[(size_t)i * HID + j]) * w5[j];
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) y[i] = s + b5[0];
+}
+
+// dy = 2 (y - t) / m, squared error partial sums per block
+__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int m,
+                      float* __restrict__ dy, float* __restrict__ part) {
+    __shared__ float sh[256];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float e = 0.f;
+    if (i < m) {
+        const float d = y[i] - t[i];
+        dy[i] = 2.f * d / (float)m;
+        e = d * d;
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_parts(const float* __restrict__ part, int n, float scale, float* __restrict__ out) {
+    __shared__ float sh[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0] * scale;
+}
+
+// dZ4 = bf16(dy_i w5_j [H4 > 0])
+__global__ void k_head_bwd(const float* __restrict__ dy, const bf16* __restrict__ H, int m,
+                           const float* __restrict__ w5, bf16* __restrict__ dZ) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (size_t)m * HID) return;
+    const int i = (int)(t / HID), j = (int)(t % HID);
+    const bf16 h = H[t];
+    dZ[t] = to_bf16((h != 0 && !(h & 0x8000)) ? dy[i] * w5[j] : 0.f);
+}
+
+// dw5_j = sum_i dy_i H4_ij (one thread per column, fixed order); db5 = sum dy
+__global__ void k_head_wgrad(const float* __restrict__ dy, const bf16* __restrict__ H, int m,
+                             float* __restrict__ dw5, float* __restrict__ db5) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < HID) {
+        float s = 0.f;
+        for (int i = 0; i < m; ++i) s += dy[i] * from_bf16(H[(size_t)i * HID + j]);
+        dw5[j] = s;
+    }
+    if (j == HID) {
+        float s = 0.f;
+        for (int i = 0; i < m; ++i) s += dy[i];
+        db5[0] = s;
+    }
+}
+
+// prediction out: scale * y, non-finite values as +inf (no information)
+__global__ void k_scale_out(const float* __restrict__ y, int m, float scale, float* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const float v = scale * y[t];
+    out[t] = isfinite(v) ? v : __builtin_huge_valf();
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, int n, bf16* __restrict__ y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = to_bf16(x[t]);
+}
+
+__global__ void k_adam_flat(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float c1, float c2) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gi = g[t];
+    const float mi = 0.9f * m[t] + 0.1f * gi;
+    const float vi = 0.999f * v[t] + 0.001f * gi * gi;
+    m[t] = mi;
+    v[t] = vi;
+    p[t] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+// ---------------------------------------------------------------- features
+// Per row (15 used + 1 zero pad): position relative to the centre / len_scale (3),
+// fibre direction (3), the eight root features
+//     a_r = |x - x_r| / len_scale + t_r / time_scale
+// sorted ascending (so the set of roots enters symmetrically and the first one
+// is the nearest-root guess; fewer than 8 roots repeat root 0), velocity scale.
+// With T given, the row's training target T[i] / time_scale is written as well.
+__global__ void k_features(const float* __restrict__ xyz, const float* __restrict__ fibre,
+                           const float* __restrict__ vscale, int n_v, const int* __restrict__ rows,
+                           int n_rows, const float* __restrict__ root_xyz,
+                           const float* __restrict__ root_t, int n_roots, float cx, float cy,
+                           float cz, float len_scale, float time_scale, const float* __restrict__ T,
+                           bf16* __restrict__ X, float* __restrict__ target) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int i = rows ? rows[r] : r;
+    bf16* o = X + (size_t)r * IN;
+    if (i < 0 || i >= n_v) {   // invalid row id: zero features, NaN target
+        for (int k = 0; k < IN; ++k) o[k] = 0;
+        if (target) target[r] = __builtin_nanf("");
+        return;
+    }
+    const float x = xyz[3 * (size_t)i], y = xyz[3 * (size_t)i + 1], z = xyz[3 * (size_t)i + 2];
+    const float il = 1.f / len_scale, it = 1.f / time_scale;
+    float a[8];
+    for (int k = 0; k < 8; ++k) {
+        const int q = k < n_roots ? k : 0;
+        const float dx = x - root_xyz[3 * q], dy = y - root_xyz[3 * q + 1], dz = z - root_xyz[3 * q + 2];
+        a[k] = sqrtf(dx * dx + dy * dy + dz * dz) * il + root_t[q] * it;
+    }
+    for (int k = 1; k < 8; ++k) {   // insertion sort, 8 values
+        const float v = a[k];
+        int j = k - 1;
+        while (j >= 0 && a[j] > v) {
+            a[j + 1] = a[j];
+            --j;
+        }
+        a[j + 1] = v;
+    }
+    o[0] = to_bf16((x - cx) * il);
+    o[1] = to_bf16((y - cy) * il);
+    o[2] = to_bf16((z - cz) * il);
+    o[3] = to_bf16(fibre[3 * (size_t)i]);
+    o[4] = to_bf16(fibre[3 * (size_t)i + 1]);
+    o[5] = to_bf16(fibre[3 * (size_t)i + 2]);
+    for (int k = 0; k < 8; ++k) o[6 + k] = to_bf16(a[k]);
+    o[14] = to_bf16(vscale ? vscale[i] : 1.f);
+    o[15] = 0;
+    if (T && target) target[r] = T[i] * it;
+}
+
+}  // namespace
+
+// ====================================================================== host
+struct gbp_mlp_s {
+    int device = 0;
+    int max_rows = 0;
+    int n_params = 0;
+    int step = 0;
+    float* params = nullptr;   // fp32 masters, flat
+    float* grads = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    bf16* wbf[NLAYER] = {};    // bf16 copies of W1..W4
+    bf16* H[NLAYER + 1] = {};  // H[0] unused (X is the input), H[1..4] activations [rows x 256]
+    bf16* dZ[2] = {};          // ping-pong [rows x 256]
+    float* y = nullptr;
+    float* dy = nullptr;
+    float* part = nullptr;     // split-K partials / loss partials
+    size_t part_n = 0;
+    float* loss = nullptr;     // [1]
+};
+
+namespace {
+// flat layout: W1 [256x16], b1, W2 [256x256], b2, W3, b3, W4, b4, w5 [256], b5 [1]
+int off_W(int l) {   // l = 1..4
+    if (l == 1) return 0;
+    return HID * IN + HID + (l - 2) * (HID * HID + HID);
+}
+int off_b(int l) { return off_W(l) + (l == 1 ? HID * IN : HID * HID); }
+int off_w5() { return off_W(4) + HID * HID + HID; }
+int n_params_total() { return off_w5() + HID + 1; }
+int in_dim(int l) { return l == 1 ? IN : HID; }
+
+void free_mlp(gbp_mlp p) {
+    if (!p) return;
+    void* ptrs[] = {p->params, p->grads, p->m, p->v, p->y, p->dy, p->part, p->loss,
+                    p->dZ[0], p->dZ[1]};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (int l = 0; l < NLAYER; ++l)
+        if (p->wbf[l]) (void)hipFree(p->wbf[l]);
+    for (int l = 0; l <= NLAYER; ++l)
+        if (p->H[l]) (void)hipFree(p->H[l]);
+    delete p;
+}
+
+int refresh_bf16(gbp_mlp p, hipStream_t s) {
+    for (int l = 1; l <= NLAYER; ++l) {
+        const int n = HID * in_dim(l);
+        k_cast_bf16<<<gbp_blocks(n, 256), 256, 0, s>>>(p->params + off_W(l), n, p->wbf[l - 1]);
+    }
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+void gemm_fwd(const bf16* Hin, int m, int in, const bf16* W, const float* bias, bf16* out,
+              hipStream_t s) {
+    // out[m x 256] = relu(Hin[m x in] W^T + b): A(i,k) = Hin[i*in + k], B(k,j) = W[j*in + k]
+    dim3 grid((HID + 63) / 64, (m + 63) / 64, 1);
+    k_gemm<EPI_BIAS_RELU><<<grid, 256, 0, s>>>(Hin, in, 1, W, 1, in, m, HID, in, in, bias, nullptr,
+                                                out, nullptr);
+}
+
+int forward_all(gbp_mlp p, const bf16* X, int m, hipStream_t s) {
+    const bf16* hin = X;
+    for (int l = 1; l <= NLAYER; ++l) {
+        gemm_fwd(hin, m, in_dim(l), p->wbf[l - 1], p->params + off_b(l), p->H[l], s);
+        hin = p->H[l];
+    }
+    k_head<<<gbp_blocks(16LL * m, 256), 256, 0, s>>>(p->H[NLAYER], m, p->params + off_w5(),
+                                                     p->params + off_w5() + HID, p->y);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+int backward_all(gbp_mlp p, const bf16* X, int m, const float* target, hipStream_t s) {
+    const int nb = gbp_blocks(m, 256);
+    k_mse<<<nb, 256, 0, s>>>(p->y, target, m, p->dy, p->part);
+    k_sum_parts<<<1, 256, 0, s>>>(p->part, nb, 1.f / (float)m, p->loss);
+    k_head_wgrad<<<gbp_blocks(HID + 1, 64), 64, 0, s>>>(p->dy, p->H[NLAYER], m, p->grads + off_w5(),
+                                                        p->grads + off_w5() + HID);
+    k_head_bwd<<<gbp_blocks((long long)m * HID, 256), 256, 0, s>>>(p->dy, p->H[NLAYER], m,
+                                                                    p->params + off_w5(), p->dZ[0]);
+    int cur = 0;
+    for (int l = NLAYER; l >= 1; --l) {
+        const int in = in_dim(l);
+        const bf16* hprev = l > 1 ? p->H[l - 1] : X;
+        // dW_l [256 x in] = dZ^T Hprev: A(i,k) = dZ[k*256 + i], B(k,j) = Hprev[k*in + j], split K
+        const int kchunk = 4096;
+        const int splits = (m + kchunk - 1) / kchunk;
+        dim3 g1((in + 63) / 64, (HID + 63) / 64, splits);
+        k_gemm<EPI_PARTIAL><<<g1, 256, 0, s>>>(p->dZ[cur], 1, HID, hprev, in, 1, HID, in, m, kchunk,
+                                               nullptr, nullptr, nullptr, p->part);
+        k_reduce_parts<<<gbp_blocks(HID * in, 256), 256, 0, s>>>(p->part, splits, HID * in,
+                                                                 p->grads + off_W(l));
+        k_colsum_bf16<<<1, 256, 0, s>>>(p->dZ[cur], m, HID, p->grads + off_b(l));
+        if (l > 1) {
+            // dZ_{l-1} [m x in] = (dZ W_l) masked: A(i,k) = dZ[i*256 + k], B(k,j) = W[k*in + j]
+            dim3 g2((in + 63) / 64, (m + 63) / 64, 1);
+            k_gemm<EPI_MASK><<<g2, 256, 0, s>>>(p->dZ[cur], HID, 1, p->wbf[l - 1], in, 1, m, in, HID,
+                                                HID, nullptr, hprev, p->dZ[1 - cur], nullptr);
+            cur = 1 - cur;
+        }
+    }
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+int check_rows(gbp_mlp p, int m) {
+    if (!p || m < 1 || m > p->max_rows) {
+        gbp_set_error("mlp: rows must be in [1, max_rows=%d]", p ? p->max_rows : 0);
+        return GBP_ERR_ARG;
+    }
+    return GBP_OK;
+}
+}  // namespace
+
+extern "C" int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp* out) {
+    if (!out || max_rows < 1 || max_rows > (1 << 21)) {
+        gbp_set_error("mlp: need 1 <= max_rows <= 2097152");
+        return GBP_ERR_ARG;
+    }
+    *out = nullptr;
+    gbp_mlp p = new gbp_mlp_s();
+    (void)hipGetDevice(&p->device);
+    p->max_rows = max_rows;
+    p->n_params = n_params_total();
+    const int kchunk = 4096;
+    p->part_n = std::max((size_t)((max_rows + kchunk - 1) / kchunk) * HID * HID,
+                         (size_t)gbp_blocks(max_rows, 256));
+    bool ok = hipMalloc((void**)&p->params, sizeof(float) * p->n_params) == hipSuccess &&
+              hipMalloc((void**)&p->grads, sizeof(float) * p->n_params) == hipSuccess &&
+              hipMalloc((void**)&p->m, sizeof(float) * p->n_params) == hipSuccess &&
+              hipMalloc((void**)&p->v, sizeof(float) * p->n_params) == hipSuccess &&
+              hipMalloc((void**)&p->y, sizeof(float) * max_rows) == hipSuccess &&
+              hipMalloc((void**)&p->dy, sizeof(float) * max_rows) == hipSuccess &&
+              hipMalloc((void**)&p->part, sizeof(float) * p->part_n) == hipSuccess &&
+              hipMalloc((void**)&p->loss, sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&p->dZ[0], sizeof(bf16) * max_rows * HID) == hipSuccess &&
+              hipMalloc((void**)&p->dZ[1], sizeof(bf16) * max_rows * HID) == hipSuccess;
+    for (int l = 1; ok && l <= NLAYER; ++l)
+        ok = hipMalloc((void**)&p->wbf[l - 1], sizeof(bf16) * HID * in_dim(l)) == hipSuccess &&
+             hipMalloc((void**)&p->H[l], sizeof(bf16) * max_rows * HID) == hipSuccess;
+    if (!ok) {
+        gbp_set_error("mlp: allocation failed");
+        free_mlp(p);
+        return GBP_ERR_NOMEM;
+    }
+    // He-normal initialisation of the weights, zero biases
+    std::vector<float> h(p->n_params, 0.f);
+    std::mt19937_64 rng(seed);
+    for (int l = 1; l <= NLAYER; ++l) {
+        std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (l == 1 ? 15.f : (float)HID)));
+        for (int k = 0; k < HID * in_dim(l); ++k) h[off_W(l) + k] = nd(rng);
+        if (l == 1)
+            for (int j = 0; j < HID; ++j) h[off_W(1) + j * IN + (IN - 1)] = 0.f;   // pad input
+    }
+    std::normal_distribution<float> nd5(0.f, std::sqrt(1.f / HID));
+    for (int j = 0; j < HID; ++j) h[off_w5() + j] = nd5(rng);
+    if (hipMemcpy(p->params, h.data(), sizeof(float) * p->n_params, hipMemcpyHostToDevice) ||
+        hipMemset(p->m, 0, sizeof(float) * p->n_params) || hipMemset(p->v, 0, sizeof(float) * p->n_params) ||
+        refresh_bf16(p, nullptr) || hipDeviceSynchronize()) {
+        gbp_set_error("mlp: initialisation failed");
+        free_mlp(p);
+        return GBP_ERR_HIP;
+    }
+    *out = p;
+    return GBP_OK;
+}
+
+extern "C" void gbp_mlp_destroy(gbp_mlp p) { free_mlp(p); }
+
+extern "C" int gbp_mlp_num_params(gbp_mlp p) { return p ? p->n_params : 0; }
+
+extern "C" int gbp_mlp_set_params(gbp_mlp p, const float* host, void* stream) {
+    if (!p || !host) {
+        gbp_set_error("mlp: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    GBP_HIP(hipMemcpyAsync(p->params, host, sizeof(float) * p->n_params, hipMemcpyHostToDevice, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    return refresh_bf16(p, s);
+}
+
+extern "C" int gbp_mlp_get_params(gbp_mlp p, float* host, float* grads_host, void* stream) {
+    if (!p || (!host && !grads_host)) {
+        gbp_set_error("mlp: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (host)
+        GBP_HIP(hipMemcpyAsync(host, p->params, sizeof(float) * p->n_params, hipMemcpyDeviceToHost, s));
+    if (grads_host)
+        GBP_HIP(hipMemcpyAsync(grads_host, p->grads, sizeof(float) * p->n_params,
+                               hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
+extern "C" int gbp_mlp_features(const float* xyz, const float* fibre, const float* vscale, int n_v,
+                                const int32_t* rows, int n_rows, const float* root_xyz,
+                                const float* root_t, int n_roots, const float* norm,
+                                const float* T, uint16_t* X, float* target, void* stream) {
+    if (!xyz || !fibre || !root_xyz || !root_t || !norm || !X || n_v < 1 || n_rows < 1 ||
+        (!rows && n_rows > n_v) || n_roots < 1 ||
+        n_roots > 8 || !(norm[3] > 0.f) || !(norm[4] > 0.f) || (!T != !target)) {
+        gbp_set_error("mlp_features: bad arguments (1 <= n_roots <= 8, scales > 0, T and target together)");
+        return GBP_ERR_ARG;
+    }
+    k_features<<<gbp_blocks(n_rows, 256), 256, 0, (hipStream_t)stream>>>(
+        xyz, fibre, vscale, n_v, rows, n_rows, root_xyz, root_t, n_roots, norm[0], norm[1], norm[2],
+        norm[3], norm[4], T, (bf16*)X, target);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_mlp_forward(gbp_mlp p, const uint16_t* X, int m, float out_scale, float* y,
+                               void* stream) {
+    int rc = check_rows(p, m);
+    if (rc) return rc;
+    if (!X || !y) {
+        gbp_set_error("mlp_forward: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = forward_all(p, (const bf16*)X, m, s))) return rc;
+    k_scale_out<<<gbp_blocks(m, 256), 256, 0, s>>>(p->y, m, out_scale, y);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
+
+extern "C" int gbp_mlp_gradient(gbp_mlp p, const uint16_t* X, int m, const float* target,
+                                float* loss, void* stream) {
+    int rc = check_rows(p, m);
+    if (rc) return rc;
+    if (!X || !target) {
+        gbp_set_error("mlp_gradient: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = forward_all(p, (const bf16*)X, m, s))) return rc;
+    if ((rc = backward_all(p, (const bf16*)X, m, target, s))) return rc;
+    if (loss) GBP_HIP(hipMemcpyAsync(loss, p->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
+    return GBP_OK;
+}
+
+extern "C" int gbp_mlp_train_step(gbp_mlp p, const uint16_t* X, int m, const float* target,
+                                  float lr, float* loss, void* stream) {
+    int rc = gbp_mlp_gradient(p, X, m, target, loss, stream);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    p->step += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, p->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, p->step)));
+    k_adam_flat<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->params, p->grads, p->m, p->v,
+                                                             p->n_params, lr, c1, c2);
+    GBP_LAUNCH_CHECK();
+    return refresh_bf16(p, s);
+}

@@ -68,3 +68,21 @@ def test_plan_rejects_bad_meshes_before_gpu():
     assert rc == -4
     rc, msg = _create(xyz[:0], tets)
     assert rc == -1
+
+
+def test_mlp_entry_points_validate_before_gpu():
+    lib = ctypes.CDLL(LIB)
+    h = ctypes.c_void_p()
+    for bad in (0, -3, (1 << 21) + 1):
+        assert lib.gbp_mlp_create(bad, ctypes.c_uint64(0), ctypes.byref(h)) == -1
+    f = lib.gbp_mlp_features
+    f.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5
+    norm = (ctypes.c_float * 5)(0, 0, 0, 1, 1)
+    fake = ctypes.c_void_p(16)   # never dereferenced: the checks run first
+    # 9 roots, n_rows > n_v without a row list, zero length scale, T without target
+    assert f(fake, fake, None, 10, None, 5, fake, fake, 9, norm, None, fake, None, None) == -1
+    assert f(fake, fake, None, 10, None, 11, fake, fake, 2, norm, None, fake, None, None) == -1
+    norm0 = (ctypes.c_float * 5)(0, 0, 0, 0, 1)
+    assert f(fake, fake, None, 10, None, 5, fake, fake, 2, norm0, None, fake, None, None) == -1
+    assert f(fake, fake, None, 10, None, 5, fake, fake, 2, norm, fake, fake, None, None) == -1
