@@ -1,0 +1,127 @@
+"""HBM traffic of a kernel from rocprofv3 counter runs.
+
+Two separate `rocprofv3 --pmc` runs of the same command (FETCH_SIZE, then
+WRITE_SIZE; both in KiB per dispatch) are reduced to bytes per launch of one
+kernel.  Each counter is scaled by what it reads for a plain copy kernel of known
+size that ran in the same process (the benchmark's `--calibrate-copy`: a
+`torch.neg` of a float32 buffer, which reads and writes the buffer once).
+
+    python -m paper_2308_08410_amd.profiling \\
+        --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write \\
+        --kernel k_sweep --copy-mib 256 --out profiles/k_sweep_shell500k_traffic.md
+
+The summary written is Markdown with one fenced JSON block; `bench.py` reads it
+and reports the traffic only while the kernel sources still hash the same.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/eikonal.hip", "csrc/local_solve.h", "csrc/gbp_internal.h")
+
+
+def source_hash(files=KERNEL_SOURCES) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(_HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_csv(path):
+    if os.path.isfile(path):
+        return path
+    hits = sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *counter_collection.csv under {path}")
+    return hits[-1]
+
+
+def per_kernel(path, counter):
+    """{kernel name: [value per dispatch]} for one counter (values summed over
+    the rows a dispatch may be split into)."""
+    rows = {}
+    with open(_counter_csv(path), newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Kernel_Name"])
+            rows[key] = rows.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (_, name), v in rows.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def _mean_of(d, substr):
+    vals = [v for name, vs in d.items() if substr in name for v in vs]
+    if not vals:
+        raise KeyError(f"no dispatch of a kernel matching {substr!r}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic(fetch_path, write_path, kernel="k_sweep", copy_substr="neg", copy_mib=256):
+    fetch = per_kernel(fetch_path, "FETCH_SIZE")
+    write = per_kernel(write_path, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    f_k, n_f = _mean_of(fetch, kernel)
+    w_k, n_w = _mean_of(write, kernel)
+    f_c, _ = _mean_of(fetch, copy_substr)
+    w_c, _ = _mean_of(write, copy_substr)
+    sf, sw = copy_kib / f_c, copy_kib / w_c
+    return dict(kernel=kernel, dispatches=[n_f, n_w], fetch_kib_raw=f_k, write_kib_raw=w_k,
+                copy_fetch_kib_raw=f_c, copy_write_kib_raw=w_c, copy_mib=copy_mib,
+                fetch_scale=sf, write_scale=sw,
+                bytes_per_launch=1024.0 * (f_k * sf + w_k * sw),
+                source_hash=source_hash())
+
+
+def read_summary(path):
+    """The JSON block of a summary written by this module, or None."""
+    try:
+        with open(path) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", default="k_sweep")
+    ap.add_argument("--copy", default="neg")
+    ap.add_argument("--copy-mib", type=float, default=256)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command", default="", help="the profiled command, recorded in the summary")
+    args = ap.parse_args(argv)
+    t = traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_mib)
+    with open(args.out, "w") as f:
+        f.write(f"# HBM traffic per launch: {args.kernel}\n\n")
+        f.write("Two rocprofv3 counter runs of the same command, FETCH_SIZE then WRITE_SIZE (KiB per\n"
+                "dispatch), each scaled by the same counter on a plain copy of known size\n"
+                f"(`{args.copy}`, {args.copy_mib:g} MiB read and written) in the same process.\n\n")
+        if args.command:
+            f.write("Commands (repository root, GPU box):\n\n")
+            for line in args.command.split(";;"):
+                f.write(f"    {line.strip()}\n")
+            f.write("\n")
+        f.write(f"Per launch: {t['bytes_per_launch'] / 1e6:.2f} MB "
+                f"(fetch {t['fetch_kib_raw']:.0f} KiB x {t['fetch_scale']:.3f}, "
+                f"write {t['write_kib_raw']:.0f} KiB x {t['write_scale']:.3f}).\n\n")
+        f.write("```json\n" + json.dumps(t, indent=1) + "\n```\n")
+    print(json.dumps(t))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
