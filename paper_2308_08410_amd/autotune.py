@@ -2,7 +2,7 @@
 
 For a plan and a representative problem it times the eikonal forward (and
 optionally the adjoint) under each candidate configuration -- lanes per vertex
-in a relaxation round, grid of a round, grid of an adjoint level -- keeps the
+in a relaxation round, grid of a round -- keeps the
 fastest, and records the rounds/levels that carried work so that graph-captured
 iterations can be given launch budgets.  Results are cached in a JSON file
 keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
@@ -17,8 +17,8 @@ import torch
 
 from . import binding as B
 
-SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=lb)
-         for lanes in (8, 16, 32) for sb in (512, 1024, 2048) for lb in (128, 256)]
+SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=256)
+         for lanes in (8, 16, 32) for sb in (512, 1024, 2048)]
 
 
 def cache_path() -> str:

@@ -595,10 +595,16 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
     }
 }
 
+// Readiness stamps of the level walk: the launch from which a vertex may be
+// finished (0 for leaves), or one of the markers below.
+constexpr int kRdyNever = 0x7fffffff;   // waiting for children (or unreached)
+constexpr int kRdyWait = 0x7ffffffe;    // first member of a two-cycle, partner not ready
+constexpr int kRdyDone = 0x7ffffffd;    // finished
+
 __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __restrict__ node_user,
                            const float* __restrict__ T, const int* __restrict__ rem, int n_v,
                            float* __restrict__ g, float* __restrict__ lam, int* __restrict__ done,
-                           int* __restrict__ q, GbpCtl* ctl) {
+                           int* __restrict__ rdy, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
     const bool reached = T[i] < GBP_INF;
@@ -607,56 +613,66 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
     g[i] = gi;
     lam[i] = gi;
     done[i] = reached ? 0 : 1;
-    if (reached && rem[i] == 0) {
-        const int pos = atomicAdd(&ctl->count[0], 1);
-        q[pos] = i;
-    }
+    const bool leaf = reached && rem[i] == 0;
+    rdy[i] = leaf ? 0 : kRdyNever;
+    if (leaf) ctl->count[0] = 1;   // flag: the first launch has work
 }
 
-__device__ __forceinline__ void release_parents(int x, int skip, const int4* __restrict__ pnode,
-                                                int* __restrict__ rem, PushBuf pb,
-                                                int* __restrict__ qout, int* cnt_next) {
+// A finished vertex releases its parents; a parent whose last child this was
+// becomes ready for the next launch (stamped with a plain store: it is only
+// read after this launch ends).
+__device__ __forceinline__ bool release_parents(int x, int skip, const int4* __restrict__ pnode,
+                                                int* __restrict__ rem, int* __restrict__ rdy,
+                                                int next) {
     const int4 pn = pnode[x];
     const int f[3] = {pn.x, pn.y, pn.z};
+    bool any = false;
     for (int k = 0; k < 3; ++k)
-        if (f[k] >= 0 && f[k] != skip && atomicSub(&rem[f[k]], 1) == 1)
-            push_node(pb, f[k], qout, cnt_next);
+        if (f[k] >= 0 && f[k] != skip && atomicSub(&rem[f[k]], 1) == 1) {
+            rdy[f[k]] = next;
+            any = true;
+        }
+    return any;
 }
 
-// One leaves-first level: every queued vertex has all (non-partner) children
-// finished.  A vertex pulls lambda = g + sum alpha_c lambda_c in child order;
-// the second member of a two-cycle to arrive solves the pair
+// One leaves-first level, as a scan over all vertices (one thread per vertex):
+// every vertex stamped ready for this launch has all (non-partner) children
+// finished in earlier launches, so their values are visible.  It pulls
+// lambda = g + sum alpha_c lambda_c in child order (deterministic); the second
+// member of a two-cycle to become ready solves the pair
 //   lam_a = S_a + w_ca lam_c,  lam_c = S_c + w_ac lam_a.
 __global__ void __launch_bounds__(TPB)
-    k_adj_level(const int* __restrict__ qin, int* __restrict__ qout, const int* __restrict__ cptr,
+    k_adj_level(int* __restrict__ rdy, const int* __restrict__ cptr,
                 const int* __restrict__ cchild, const float* __restrict__ calpha,
                 const float* __restrict__ g, float* lam, int* __restrict__ done,
                 const int4* __restrict__ pnode, const int* __restrict__ partner,
-                int* __restrict__ pairrem, int* __restrict__ rem, GbpCtl* ctl, int s) {
-    const int n = ctl->count[s % 3];
+                int* __restrict__ pairrem, int* __restrict__ rem, int n_v, GbpCtl* ctl, int s) {
+    const int flag = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
-        if (n > 0) atomicMax(&ctl->levels, s + 1);
+        if (flag != 0) atomicMax(&ctl->levels, s + 1);
     }
-    if (blockIdx.x * blockDim.x >= n) return;
-    int* cnt_next = &ctl->count[(s + 1) % 3];
-    __shared__ int push_q[kPushCap];
-    __shared__ int push_n, push_base;
-    if (threadIdx.x == 0) push_n = 0;
+    if (flag == 0) return;
+    __shared__ int any_sh;
+    if (threadIdx.x == 0) any_sh = 0;
     __syncthreads();
-    const PushBuf pb{push_q, &push_n};
-    for (int qi = blockIdx.x * blockDim.x + threadIdx.x; qi < n; qi += gridDim.x * blockDim.x) {
-        const int x = qin[qi];
+    bool any = false;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n_v; x += gridDim.x * blockDim.x) {
+        if (rdy[x] > s) continue;                   // not ready yet, waiting or finished
         const int q = partner[x];
         if (q < 0) {
             float l = g[x];
             for (int k = cptr[x]; k < cptr[x + 1]; ++k) l += calpha[k] * lam[cchild[k]];
             lam[x] = l;
             done[x] = 1;
-            release_parents(x, -1, pnode, rem, pb, qout, cnt_next);
+            rdy[x] = kRdyDone;
+            any |= release_parents(x, -1, pnode, rem, rdy, s + 1);
             continue;
         }
-        if (atomicSub(&pairrem[min(x, q)], 1) != 1) continue;   // partner not ready yet
+        if (atomicSub(&pairrem[min(x, q)], 1) != 1) {   // partner not ready yet
+            rdy[x] = kRdyWait;
+            continue;
+        }
         float S[2], w[2];
         const int pr[2] = {x, q};
         for (int m = 0; m < 2; ++m) {
@@ -676,10 +692,14 @@ __global__ void __launch_bounds__(TPB)
         lam[q] = lq;
         done[x] = 1;
         done[q] = 1;
-        release_parents(x, q, pnode, rem, pb, qout, cnt_next);
-        release_parents(q, x, pnode, rem, pb, qout, cnt_next);
+        rdy[x] = kRdyDone;
+        rdy[q] = kRdyDone;
+        any |= release_parents(x, q, pnode, rem, rdy, s + 1);
+        any |= release_parents(q, x, pnode, rem, rdy, s + 1);
     }
-    push_flush(pb, qout, cnt_next, &push_base);
+    if (any) any_sh = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && any_sh) ctl->count[(s + 1) % 3] = 1;
 }
 
 __global__ void k_adj_remaining(const int* __restrict__ done, int n_v, int* __restrict__ list,
@@ -1130,14 +1150,14 @@ extern "C" int gbp_backward_info(gbp_plan p, int* levels, int* cyclic, int* gs_s
 
 static void launch_level(gbp_plan p, int level, hipStream_t s) {
     ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
-    k_adj_level<<<std::max(1, std::min(p->level_blocks, gbp_blocks(p->n_v, TPB))), TPB, 0, s>>>(
-        p->q[level & 1], p->q[(level + 1) & 1], p->ccnt, p->cchild, p->calpha, p->g, p->lam,
-        p->done, p->pnode, p->partner, p->pairrem, p->rem, p->ctl, level);
+    k_adj_level<<<std::max(1, gbp_blocks(p->n_v, TPB)), TPB, 0, s>>>(
+        p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->done, p->pnode, p->partner,
+        p->pairrem, p->rem, p->n_v, p->ctl, level);
 }
 
 static void launch_gs(gbp_plan p, int it, hipStream_t s) {
     ProfScope ps(GBP_PROF_AUX, s);
-    k_adj_gs<<<std::min(gbp_blocks(p->n_v, TPB), 1024), TPB, 0, s>>>(
+    k_adj_gs<<<std::max(1, std::min(gbp_blocks(p->n_v, TPB), p->level_blocks)), TPB, 0, s>>>(
         p->cfill, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->ctl, it);
 }
 
@@ -1182,7 +1202,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     // leaves-first level walk
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 1);
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
-                                                    p->lam, p->done, p->q[0], p->ctl);
+                                                    p->lam, p->done, p->rdy, p->ctl);
     GBP_LAUNCH_CHECK();
     int level = 0;
     if (!sync) {

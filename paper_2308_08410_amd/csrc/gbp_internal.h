@@ -109,6 +109,7 @@ struct gbp_plan_s {
     float* g = nullptr;           // [n_v]
     float* dsbar = nullptr;       // [n_e]
     int* done = nullptr;          // [n_v] adjoint finished flag
+    int* rdy = nullptr;           // [n_v] adjoint readiness stamp (launch index or marker)
     int4* pnode = nullptr;        // [n_v] parent face vertices with alpha > 0 (-1 otherwise)
     int* partner = nullptr;       // [n_v] mutual parent (two-cycle partner) or -1
     int* pairrem = nullptr;       // [n_v] members of a two-cycle not yet ready (at min id)

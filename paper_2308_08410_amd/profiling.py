@@ -25,14 +25,30 @@ import re
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/eikonal.hip", "csrc/local_solve.h", "csrc/gbp_internal.h")
 
 
-def source_hash(files=KERNEL_SOURCES) -> str:
+def _kernel_text(src: str, name: str) -> str:
+    """Source text of one __global__ function template (from its template line to
+    the closing brace at column 0)."""
+    m = re.search(r"\n(template <[^\n]*>\n__global__[^\n]*\n\s*" + re.escape(name) + r"\(.*?\n}\n)",
+                  src, re.S)
+    if not m:
+        raise KeyError(name)
+    return m.group(1)
+
+
+def source_hash(kernel: str = "k_sweep") -> str:
+    """Hash of what the relaxation round is compiled from: the kernel's own text,
+    the queue-push helpers it calls and the local solver."""
+    with open(os.path.join(_HERE, "csrc", "eikonal.hip")) as f:
+        eik = f.read()
+    with open(os.path.join(_HERE, "csrc", "local_solve.h")) as f:
+        ls = f.read()
+    i = eik.index("constexpr int kPushCap")
+    j = eik.index("__global__", i)
     h = hashlib.sha256()
-    for f in files:
-        with open(os.path.join(_HERE, f), "rb") as fh:
-            h.update(fh.read())
+    for part in (eik[i:j], _kernel_text(eik, kernel), ls):
+        h.update(part.encode())
     return h.hexdigest()[:16]
 
 
