@@ -409,67 +409,110 @@ __device__ __forceinline__ double quad64(const Sym64& M, double x0, double x1, d
            x2 * (M.xz * y0 + M.yz * y1 + M.zz * y2);
 }
 
-template <int K>
-__device__ __forceinline__ void parent_slot(int& e, int cnt, int self, const int* __restrict__ nent,
-                                            const int4* __restrict__ tetv,
-                                            const int* __restrict__ tet_user,
-                                            const float* __restrict__ D,
-                                            const float* __restrict__ vs,
-                                            const float4* __restrict__ xyz,
-                                            const float* __restrict__ T, double& best, int& bpar,
-                                            double& b0, double& b1, double& b2) {
+// FP64 value and weights of the local problem of entry `e` (slot K) of vertex i,
+// from the raw inputs (coordinates, velocity tensor, nodal scales, T).
+__device__ __forceinline__ double parent_face64(int t, int K, int self, const int4* __restrict__ tetv,
+                                                const int* __restrict__ tet_user,
+                                                const float* __restrict__ D,
+                                                const float* __restrict__ vs,
+                                                const float4* __restrict__ xyz,
+                                                const float* __restrict__ T, double& a0,
+                                                double& a1, double& a2) {
     const float4 xi = xyz[self];
-    for (int c = 0; c < cnt; ++c) {
-        const int t = nent[e + c];
-        const int4 v = tetv[t];
-        const double sbar = 0.25 * ((double)vs[v.x] + (double)vs[v.y] + (double)vs[v.z] + (double)vs[v.w]);
-        const Sym64 M = inv_metric64(D + 6 * (size_t)tet_user[t], sbar);
-        int n0, n1, n2;
-        face_nodes<K>(v, n0, n1, n2);
-        const float4 x0 = xyz[n0], x1 = xyz[n1], x2 = xyz[n2];
-        const double e0x = (double)x0.x - xi.x, e0y = (double)x0.y - xi.y, e0z = (double)x0.z - xi.z;
-        const double e1x = (double)x1.x - xi.x, e1y = (double)x1.y - xi.y, e1z = (double)x1.z - xi.z;
-        const double e2x = (double)x2.x - xi.x, e2y = (double)x2.y - xi.y, e2z = (double)x2.z - xi.z;
-        LocalQT<double> q;
-        q.q00 = quad64(M, e0x, e0y, e0z, e0x, e0y, e0z);
-        q.q11 = quad64(M, e1x, e1y, e1z, e1x, e1y, e1z);
-        q.q22 = quad64(M, e2x, e2y, e2z, e2x, e2y, e2z);
-        q.q01 = quad64(M, e0x, e0y, e0z, e1x, e1y, e1z);
-        q.q02 = quad64(M, e0x, e0y, e0z, e2x, e2y, e2z);
-        q.q12 = quad64(M, e1x, e1y, e1z, e2x, e2y, e2z);
-        double a0, a1, a2;
-        const double val = local_min<true, double>(q, (double)T[n0], (double)T[n1], (double)T[n2],
-                                                   &a0, &a1, &a2);
-        if (val < best) {
-            best = val;
-            bpar = (t << 2) | K;
-            b0 = a0;
-            b1 = a1;
-            b2 = a2;
-        }
-    }
-    e += cnt;
+    const int4 v = tetv[t];
+    const double sbar = 0.25 * ((double)vs[v.x] + (double)vs[v.y] + (double)vs[v.z] + (double)vs[v.w]);
+    const Sym64 M = inv_metric64(D + 6 * (size_t)tet_user[t], sbar);
+    int n0, n1, n2;
+    face_nodes_sel(v, K, n0, n1, n2);
+    const float4 x0 = xyz[n0], x1 = xyz[n1], x2 = xyz[n2];
+    const double e0x = (double)x0.x - xi.x, e0y = (double)x0.y - xi.y, e0z = (double)x0.z - xi.z;
+    const double e1x = (double)x1.x - xi.x, e1y = (double)x1.y - xi.y, e1z = (double)x1.z - xi.z;
+    const double e2x = (double)x2.x - xi.x, e2y = (double)x2.y - xi.y, e2z = (double)x2.z - xi.z;
+    LocalQT<double> q;
+    q.q00 = quad64(M, e0x, e0y, e0z, e0x, e0y, e0z);
+    q.q11 = quad64(M, e1x, e1y, e1z, e1x, e1y, e1z);
+    q.q22 = quad64(M, e2x, e2y, e2z, e2x, e2y, e2z);
+    q.q01 = quad64(M, e0x, e0y, e0z, e1x, e1y, e1z);
+    q.q02 = quad64(M, e0x, e0y, e0z, e2x, e2y, e2z);
+    q.q12 = quad64(M, e1x, e1y, e1z, e2x, e2y, e2z);
+    return local_min<true, double>(q, (double)T[n0], (double)T[n1], (double)T[n2], &a0, &a1, &a2);
 }
 
+// Parents: L lanes per vertex.  Every local problem of the patch is first solved
+// in FP32 (from the element Gram records); only those within 1e-4*max(1,|T|) of
+// the FP32 minimum -- a margin about a hundred times the FP32 error -- are
+// solved again in FP64, and the FP64 values decide the argmin (ties: first
+// entry in (slot, element) order).
+template <int L>
 __global__ void __launch_bounds__(TPB)
     k_parent(const int2* __restrict__ nptr, const int* __restrict__ nent,
-             const int4* __restrict__ tetv, const int* __restrict__ tet_user,
-             const float* __restrict__ D, const float* __restrict__ vs,
-             const float4* __restrict__ xyz, const float* __restrict__ T,
-             const float* __restrict__ troot, int n_v, int* __restrict__ par,
-             float4* __restrict__ pa) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_v) return;
+             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
+             const int* __restrict__ tet_user, const float* __restrict__ D,
+             const float* __restrict__ vs, const float4* __restrict__ xyz,
+             const float* __restrict__ T, const float* __restrict__ troot, int n_v,
+             int* __restrict__ par, float4* __restrict__ pa) {
+    const int lane = threadIdx.x & (L - 1);
+    const int i0 = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const bool act = i0 < n_v;                      // uniform over the lane group
+    const int i = act ? i0 : 0;
+    const bool reached = act && T[i] < GBP_INF;
+    const int2 p = reached ? nptr[i] : make_int2(0, 0);
+    const int c0 = p.y & 255, c1 = (p.y >> 8) & 255, c2 = (p.y >> 16) & 255, c3 = (p.y >> 24) & 255;
+    const int e01 = c0 + c1, e012 = e01 + c2, tot = e012 + c3;
+    // FP32 screen
+    float b32 = GBP_INF;
+    for (int c = lane; c < tot; c += L) {
+        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
+        const int t = nent[p.x + c];
+        const int4 v = tetv[t];
+        int a, b, cc;
+        face_nodes_sel(v, K, a, b, cc);
+        b32 = fminf(b32, local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
+                                          T[a], T[b], T[cc]));
+    }
+    for (int o = L / 2; o > 0; o >>= 1) b32 = fminf(b32, __shfl_xor(b32, o));
+    const float cut = b32 + 1e-4f * fmaxf(1.f, fabsf(b32));
+    // FP64 decision among the candidates
     double best = __builtin_huge_val(), b0 = 0, b1 = 0, b2 = 0;
+    int bpos = 0x7fffffff;
+    for (int c = lane; c < tot && b32 < GBP_INF; c += L) {
+        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
+        const int t = nent[p.x + c];
+        const int4 v = tetv[t];
+        int a, b, cc;
+        face_nodes_sel(v, K, a, b, cc);
+        const float v32 = local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
+                                           T[a], T[b], T[cc]);
+        if (!(v32 <= cut)) continue;
+        double x0, x1, x2;
+        const double val = parent_face64(t, K, i, tetv, tet_user, D, vs, xyz, T, x0, x1, x2);
+        if (val < best) {
+            best = val;
+            bpos = c;
+            b0 = x0;
+            b1 = x1;
+            b2 = x2;
+        }
+    }
+    // group argmin of (value, entry position)
+    for (int o = L / 2; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int op = __shfl_xor(bpos, o);
+        const double o0 = __shfl_xor(b0, o), o1 = __shfl_xor(b1, o), o2 = __shfl_xor(b2, o);
+        if (ob < best || (ob == best && op < bpos)) {
+            best = ob;
+            bpos = op;
+            b0 = o0;
+            b1 = o1;
+            b2 = o2;
+        }
+    }
+    if (!act || lane != 0) return;
     int bpar = -1;
-    if (T[i] < GBP_INF) {
-        const int2 p = nptr[i];
-        int e = p.x;
-        parent_slot<0>(e, p.y & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
-        parent_slot<1>(e, (p.y >> 8) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
-        parent_slot<2>(e, (p.y >> 16) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
-        parent_slot<3>(e, (p.y >> 24) & 255, i, nent, tetv, tet_user, D, vs, xyz, T, best, bpar, b0, b1, b2);
-        if ((double)troot[i] <= best) bpar = -1;
+    if (bpos != 0x7fffffff) {
+        const int K = (bpos < c0) ? 0 : (bpos < e01) ? 1 : (bpos < e012) ? 2 : 3;
+        bpar = (nent[p.x + bpos] << 2) | K;
+        if ((double)troot[i] <= best) bpar = -1;   // an active root keeps its onset
     }
     par[i] = bpar;
     pa[i] = make_float4((float)b0, (float)b1, (float)b2, (float)best);
@@ -1109,8 +1152,9 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
 static int run_parents(gbp_plan p, const float* D_in, hipStream_t s) {
     const int n_v = p->n_v;
     ProfScope ps(GBP_PROF_PARENT, s);
-    k_parent<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tet_user, D_in,
-                                                  p->vs, p->xyz, p->T, p->troot, n_v, p->par, p->pa);
+    k_parent<16><<<gbp_blocks(16LL * n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg,
+                                                             p->tet_user, D_in, p->vs, p->xyz, p->T,
+                                                             p->troot, n_v, p->par, p->pa);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
