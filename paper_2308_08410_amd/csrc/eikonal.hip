@@ -238,9 +238,11 @@ __global__ void k_ctl_reset(GbpCtl* ctl, int keep_fwd) {
     if (threadIdx.x == 0) {
         const int stamp = ctl->stamp;
         const int st = keep_fwd ? (ctl->status & 1) : 0;
+        const int err = keep_fwd == 2 ? ctl->err : 0;   // 2: mid-call reset, keep input errors
         GbpCtl z{};
         z.stamp = stamp > (1 << 30) ? 1 : stamp;
         z.status = st;
+        z.err = err;
         *ctl = z;
     }
 }
@@ -995,6 +997,61 @@ static int read_ctl(gbp_plan p, hipStream_t s) {
     return GBP_OK;
 }
 
+// Pipelined convergence checks of the synchronous loops: after each batch of
+// launches an asynchronous copy of the control block is queued (pinned slot 1 or
+// 2, with an event); the host waits for batch k's copy only after batch k+1 is
+// queued, so the device never idles on the check.  A finished loop costs at most
+// one batch of empty launches (each returns at once).
+static int status_post(gbp_plan p, int slot, hipStream_t s) {
+    GBP_HIP(hipMemcpyAsync(p->ctl_host + 1 + slot, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipEventRecord(p->ev[slot], s));
+    return GBP_OK;
+}
+
+static int status_wait(gbp_plan p, int slot) {
+    GBP_HIP(hipEventSynchronize(p->ev[slot]));
+    return GBP_OK;
+}
+
+// Runs launch(k) for k = 0, 1, ... in growing batches until done(ctl, k_end)
+// holds for the status taken after a batch ending at k_end, or `cap` launches.
+// Returns GBP_OK, or the device error bits' code; `launched` and `finished` out.
+template <class Launch, class Done>
+static int run_pipelined(gbp_plan p, hipStream_t s, int cap, Launch launch, Done done,
+                         int& launched, bool& finished) {
+    int r = 0, slot = 0, batch = 4;
+    int pend[2] = {0, 0};
+    finished = false;
+    int nb = std::min(batch, cap);
+    for (int b = 0; b < nb; ++b, ++r) launch(r);
+    launched = r;
+    GBP_LAUNCH_CHECK();
+    int rc = status_post(p, slot, s);
+    if (rc) return rc;
+    pend[slot] = r;
+    while (true) {
+        const int other = slot ^ 1;
+        batch = std::min(batch * 2, p->sync_batch);
+        const int nb2 = std::min(batch, cap - r);
+        if (nb2 > 0) {
+            for (int b = 0; b < nb2; ++b, ++r) launch(r);
+            launched = r;
+            GBP_LAUNCH_CHECK();
+            if ((rc = status_post(p, other, s))) return rc;
+            pend[other] = r;
+        }
+        if ((rc = status_wait(p, slot))) return rc;
+        const GbpCtl& c = p->ctl_host[1 + slot];
+        if (c.err) return gbp_err_from_bits(c.err);
+        if (done(c, pend[slot])) {
+            finished = true;
+            return GBP_OK;
+        }
+        if (nb2 <= 0) return GBP_OK;              // cap reached
+        slot = other;
+    }
+}
+
 int gbp_err_from_bits(int bits) {
     if (bits & ERRBIT_ROOT_RANGE) {
         gbp_set_error("root vertex id out of range");
@@ -1098,17 +1155,12 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
     if (budget > 0) {
         for (; r < budget; ++r) launch_round(p, cold, r, s);
     } else {
-        if ((rc = read_ctl(p, s))) return rc;
-        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
-        converged = (p->ctl_host->count[0] == 0);
-        int batch = 4;
-        while (!converged && r < p->max_rounds) {
-            const int nb = std::min(batch, p->max_rounds - r);
-            for (int b = 0; b < nb; ++b, ++r) launch_round(p, cold, r, s);
-            GBP_LAUNCH_CHECK();
-            if ((rc = read_ctl(p, s))) return rc;
-            converged = (p->ctl_host->count[r % 3] == 0);
-            batch = std::min(batch * 2, p->sync_batch);
+        rc = run_pipelined(
+            p, s, p->max_rounds, [&](int k) { launch_round(p, cold, k, s); },
+            [](const GbpCtl& c, int k_end) { return c.count[k_end % 3] == 0; }, r, converged);
+        if (rc) {
+            k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);   // stamps used so far stay retired
+            return rc;
         }
     }
     k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);
@@ -1219,11 +1271,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     const int n_v = p->n_v, n_e = p->n_e;
     const bool sync = level_budget <= 0;
     if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, 2, T, s))) return rc;
-    if (sync) {
-        if ((rc = read_ctl(p, s))) return rc;
-        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
-    }
-    if ((rc = run_parents(p, D, s))) return rc;
+    if ((rc = run_parents(p, D, s))) return rc;   // input errors surface at the first status read
     // parent lists, two-cycle partners, children lists
     {
         ProfScope ps_child(GBP_PROF_CHILD, s);
@@ -1244,7 +1292,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
         GBP_LAUNCH_CHECK();
     }
     // leaves-first level walk
-    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 1);
+    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 2);
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
                                                     p->lam, p->done, p->rdy, p->ctl);
     GBP_LAUNCH_CHECK();
@@ -1252,17 +1300,11 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     if (!sync) {
         for (; level < level_budget; ++level) launch_level(p, level, s);
     } else {
-        if ((rc = read_ctl(p, s))) return rc;
-        bool empty = (p->ctl_host->count[0] == 0);
-        int batch = 4;
-        const int cap = p->max_rounds + n_v;
-        while (!empty && level < cap) {
-            for (int b = 0; b < batch; ++b, ++level) launch_level(p, level, s);
-            GBP_LAUNCH_CHECK();
-            if ((rc = read_ctl(p, s))) return rc;
-            empty = (p->ctl_host->count[level % 3] == 0);
-            batch = std::min(batch * 2, p->sync_batch);
-        }
+        bool empty = false;
+        rc = run_pipelined(
+            p, s, p->max_rounds + n_v, [&](int k) { launch_level(p, k, s); },
+            [](const GbpCtl& c, int k_end) { return c.count[k_end % 3] == 0; }, level, empty);
+        if (rc) return rc;
     }
     // vertices on or above cycles longer than two: Gauss-Seidel on the remainder
     k_adj_remaining<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->done, n_v, p->cfill, p->ctl);

@@ -92,7 +92,8 @@ struct gbp_plan_s {
     int last_rounds = 0, last_levels = 0;   // of the last synchronous calls
     GbpCtl* ctl = nullptr;        // device control block
     unsigned long long* blk = nullptr;  // [2 * kStatBlocks] per-block (solves, updates)
-    GbpCtl* ctl_host = nullptr;   // pinned mirror
+    GbpCtl* ctl_host = nullptr;   // pinned mirror [3]: [0] status reads, [1..2] pipelined checks
+    hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the pipelined status copies
 
     // backward workspace (allocated on first use)
     bool bwd_ready = false;

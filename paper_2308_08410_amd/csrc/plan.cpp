@@ -75,6 +75,8 @@ static void plan_free(gbp_plan p) {
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -304,12 +306,14 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
         plan_free(p);
         return GBP_ERR_HIP;
     }
-    if (hipHostMalloc((void**)&p->ctl_host, sizeof(GbpCtl), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&p->ctl_host, 3 * sizeof(GbpCtl), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev[1], hipEventDisableTiming) != hipSuccess) {
         gbp_set_error("hipHostMalloc failed");
         plan_free(p);
         return GBP_ERR_NOMEM;
     }
-    memset(p->ctl_host, 0, sizeof(GbpCtl));
+    memset(p->ctl_host, 0, 3 * sizeof(GbpCtl));
     *out = p;
     return GBP_OK;
 }

@@ -39,7 +39,7 @@ def test_autograd_iteration_matches_oracle_chain():
     lo, Go = O.ecg_loss(eo, target.cpu().numpy())
     go = O.ecg_backward(To, p.W, a, Go)
     res = O.adjoint(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t, To, go)
-    assert float(loss) == pytest.approx(lo, rel=1e-3)
+    assert float(loss.detach()) == pytest.approx(lo, rel=1e-3)
     assert rel_l2(vs.grad.cpu().numpy(), res["dvscale"]) <= 1e-3
     assert rel_l2(rt.grad.cpu().numpy(), res["droot_t"]) <= 1e-3
     assert rel_l2(D.grad.cpu().numpy(), res["dD"]) <= 1e-3
