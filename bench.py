@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--cpu-sample-nodes", type=int, default=125_000)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the warm-started single and batched forms")
+    ap.add_argument("--form-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="MIB",
                     help="run one plain copy of this many MiB first (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE/WRITE_SIZE counters)")
@@ -102,6 +105,116 @@ def gbp_step(st, B):
     B.adam_step(st["vs"], dvs, st["m_vs"], st["v_vs"], st["k"], lr=0.01, lo=0.2, hi=5.0)
     B.adam_step(st["rt"], drt, st["m_rt"], st["v_rt"], st["k"], lr=0.5)
     return loss, stats
+
+
+def _replay_timed(step, steps, torch):
+    step.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _warm_accuracy(step, plan, D, vs, rn, rt, T, B, torch):
+    """One more replay from saved parameters, then a cold solve with the same
+    parameters: max |T_warm - T_cold| / max |T_cold| over reached vertices."""
+    vs0, rt0 = vs.clone(), rt.clone()
+    step.launch()
+    torch.cuda.synchronize()
+    st = B.plan_status(plan)
+    Tc, _ = B.eikonal_forward(plan, D, vs0, rn, rt0)
+    fin = torch.isfinite(Tc)
+    err = float((T[fin] - Tc[fin]).abs().max() / Tc[fin].abs().max())
+    return err, st
+
+
+def warm_single_form(st, prob, steps, torch, B, autotune):
+    """The same 500k iteration as one HIP-graph replay whose forward starts
+    (two-sided) from the previous iteration's activation times."""
+    plan, dev = st["plan"], st["D"].device
+    L = prob.W.shape[1]
+    S = prob.ap["n_steps"]
+    bt = B.Batch([0, prob.n_v], S)
+    T = torch.empty(prob.n_v, dtype=torch.float32, device=dev)
+    ecg = torch.empty((1, S, L), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    tgt = st["target"].reshape(1, S, L).contiguous()
+    B.eikonal_forward(plan, st["D"], st["vs"], st["rn"], st["rt"], out=T)
+    B.eikonal_backward(plan, st["D"], st["vs"], st["rn"], st["rt"], T, torch.ones_like(T), want_D=False)
+    bud = autotune.budgets(plan, margin=1.5, extra=32)
+    step = B.Step(plan, bt, st["D"], st["vs"], st["rn"], st["rt"], st["W"], st["ap"], tgt, T, ecg, loss,
+                  warm=True, **bud)
+    ms = _replay_timed(step, steps, torch)
+    err, status = _warm_accuracy(step, plan, st["D"], st["vs"], st["rn"], st["rt"], T, B, torch)
+    step.close()
+    return dict(iters_per_s=1000.0 / ms, ms_per_step=ms, max_rel_T_vs_cold=err,
+                converged=bool(status["forward_converged"] and status["backward_settled"]), budgets=bud)
+
+
+def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed=31):
+    """Many uneven meshes and parameter sets as one union plan, one HIP-graph
+    replay per iteration for all instances (forward -- cold, then warm-started
+    from the previous iteration -- batched ECG and misfit, adjoint, Adam),
+    launch configuration from the autotuner."""
+    import numpy as np
+    from paper_2308_08410_amd.batch import concat, shift_roots, union_mesh
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.sort(rng.integers(10_000, 200_001, size=n_meshes))
+    t0 = time.time()
+    meshes = [gi.shell_problem(int(n), seed=seed + 7 * k, n_roots=1, n_leads=12) for k, n in enumerate(sizes)]
+    inst = [meshes[i % n_meshes] for i in range(n_inst)]
+    xyz, tets, voff, _ = union_mesh([m.xyz for m in inst], [m.tets for m in inst])
+    rns, rts, vs_true, vs0 = [], [], [], []
+    for i, m in enumerate(inst):
+        R = int(rng.integers(1, 9))
+        rn, rt = gi.random_roots(m.extra["endo"], R, 0.0, 20.0, seed=seed + 1000 + i)
+        rns.append(rn)
+        rts.append(rt)
+        vs_true.append(gi.smooth_field(m.xyz, 0.5, 1.5, seed=seed + 2000 + i))
+        vs0.append(np.ones(m.n_v, np.float32))
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    D, W = f32(concat([m.D for m in inst])), f32(concat([m.W for m in inst]))
+    rn = torch.as_tensor(shift_roots(rns, voff), device=dev)
+    rt_true = f32(concat(rts))
+    rt = f32(concat(rts) + rng.uniform(-3, 3, size=len(rn)).astype(np.float32))
+    vs = f32(concat(vs0))
+    plan = B.Plan(xyz, tets)
+    ap = inst[0].ap
+    S, L = ap["n_steps"], W.shape[1]
+    apc = B.make_ap(ap["K0"], ap["K1"], ap["tau"], ap["t0"], ap["dt"], S)
+    bt = B.Batch(voff, S)
+    t_setup = time.time() - t0
+    T_true, _ = B.eikonal_forward(plan, D, f32(concat(vs_true)), rn, rt_true)
+    target = B.ecg_forward_batched(bt, T_true, W, apc).clone()
+    tune = autotune.tune(plan, D, vs, rn, rt, use_cache=False, save=False, repeats=1)
+    out = dict(instances=n_inst, distinct_meshes=n_meshes, mesh_sizes=[int(m.n_v) for m in meshes],
+               total_vertices=int(voff[-1]), total_tets=int(len(tets)), setup_s=t_setup,
+               launch=dict(lanes=tune["lanes"], sweep_blocks=tune["sweep_blocks"]))
+    vs_start, rt_start = vs.clone(), rt.clone()
+    for warm in (False, True):
+        vs.copy_(vs_start)
+        rt.copy_(rt_start)
+        T = torch.empty(len(xyz), dtype=torch.float32, device=dev)
+        B.eikonal_forward(plan, D, vs, rn, rt, out=T)
+        B.eikonal_backward(plan, D, vs, rn, rt, T, torch.ones_like(T), want_D=False)
+        # a two-sided warm solve can need more rounds than the cold one it is sized from
+        bud = autotune.budgets(plan, margin=2.0 if warm else 1.5, extra=64 if warm else 32)
+        ecg = torch.empty((n_inst, S, L), dtype=torch.float32, device=dev)
+        loss = torch.empty(n_inst, dtype=torch.float32, device=dev)
+        step = B.Step(plan, bt, D, vs, rn, rt, W, apc, target, T, ecg, loss, warm=warm, **bud)
+        ms = _replay_timed(step, steps, torch)
+        err, status = _warm_accuracy(step, plan, D, vs, rn, rt, T, B, torch)
+        step.close()
+        out["warm" if warm else "cold"] = dict(
+            ms_per_step=ms, instance_iters_per_s=n_inst * 1000.0 / ms,
+            vertex_iters_per_s=int(voff[-1]) * 1000.0 / ms, max_rel_T_vs_cold=err,
+            converged=bool(status["forward_converged"] and status["backward_settled"]), status=status,
+            budgets=bud, backward=B.backward_info(plan))
+    return out
 
 
 def cpu_baseline(n_sample, n_full):
@@ -207,6 +320,25 @@ def main():
                         alu_tflops=tflops, alu_frac=tflops / PEAK_FP32_TFLOPS)
         detail["kernel_ms_per_step"] = {k: v[1] / nprof for k, v in prof.items() if v[0]}
         detail["kernel_launches_per_step"] = {k: v[0] / nprof for k, v in prof.items() if v[0]}
+    if not args.no_forms:
+        from paper_2308_08410_amd import autotune
+        t = time.time()
+        ws = warm_single_form(st, prob, args.form_steps, torch, B, autotune)
+        ws["speedup_vs_plain"] = ws["iters_per_s"] / (1000.0 / ms)
+        detail["warm_single_500k"] = ws
+        log(f"[bench] warm single form: {ws['iters_per_s']:.1f} iter/s (x{ws['speedup_vs_plain']:.2f}), "
+            f"max rel T vs cold {ws['max_rel_T_vs_cold']:.1e} ({time.time() - t:.1f}s)")
+        t = time.time()
+        bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
+        for k in ("cold", "warm"):
+            f = bw[k]
+            f["speedup_vs_plain_vertex_iters"] = f["vertex_iters_per_s"] / (prob.n_v * 1000.0 / ms)
+            log(f"[bench] batched form ({k}): {bw['instances']} instances / {bw['total_vertices']} vertices, "
+                f"{f['instance_iters_per_s']:.1f} instance-iter/s, x{f['speedup_vs_plain_vertex_iters']:.2f} "
+                f"vertex-iter/s vs plain, max rel T vs cold {f['max_rel_T_vs_cold']:.1e}, "
+                f"within budgets {f['converged']}")
+        detail["batched"] = bw
+        log(f"[bench] batched forms done ({time.time() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()

@@ -97,7 +97,11 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
 
 
 def budgets(plan: B.Plan, margin=1.25, extra=16, gs=32):
-    """Launch budgets for a captured iteration from the last synchronous counts."""
+    """Launch budgets for a captured iteration from the last synchronous counts
+    (relaxation rounds, adjoint levels and, where the parent graph had cycles,
+    the Gauss-Seidel sweeps they needed)."""
     c = B.last_counts(plan)
+    info = B.backward_info(plan)
+    gs_need = int(math.ceil(info["gs_sweeps"] * margin)) + extra if info["cyclic"] > 0 else 0
     return dict(round_budget=int(math.ceil(c["rounds"] * margin)) + extra,
-                level_budget=int(math.ceil(c["levels"] * margin)) + extra, gs_budget=gs)
+                level_budget=int(math.ceil(c["levels"] * margin)) + extra, gs_budget=max(gs, gs_need))
