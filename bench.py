@@ -31,6 +31,7 @@ BYTES_PER_FACE = 64.0
 # and HBM3E bandwidth.
 PEAK_FP32_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0   # dense bf16 matrix-core peak
 
 
 def parse():
@@ -51,16 +52,26 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "k_sweep_shell500k_traffic.md")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
-def stored_traffic(n_v):
-    """Bytes per k_sweep launch from the committed counter summary, while the
-    kernel sources are unchanged since the counters were taken (else None)."""
+def stored_mfma(kernel):
+    """Matrix-core figures of an ECG kernel from the committed counter summary,
+    while its source is unchanged (else None)."""
     from paper_2308_08410_amd import profiling
-    t = profiling.read_summary(TRAFFIC_SUMMARY)
-    if not t or t.get("source_hash") != profiling.source_hash() or t.get("n_v") not in (None, n_v):
+    t = profiling.read_summary(os.path.join(PROFILES, f"{kernel}_shell500k_mfma.md"))
+    if not t or t.get("source_hash") != profiling.source_hash(kernel, "ecg.hip"):
+        return None
+    return t
+
+
+def stored_traffic(kernel="k_sweep"):
+    """Measured HBM bytes per launch of a kernel on this workload, from the
+    committed counter summary, while the kernel's source is unchanged since the
+    counters were taken (else None)."""
+    from paper_2308_08410_amd import profiling
+    t = profiling.read_summary(os.path.join(PROFILES, f"{kernel}_shell500k_traffic.md"))
+    if not t or t.get("source_hash") != profiling.source_hash(kernel):
         return None
     return t["bytes_per_launch"]
 
@@ -315,9 +326,29 @@ def main():
         tflops = faces_per_launch * FLOP_PER_FACE / (avg_ms * 1e-3) / 1e12
         roofline = dict(kernel="k_sweep (eikonal relaxation round)", bound="hbm", achieved=achieved,
                         peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                        traffic=stored_traffic(prob.n_v), algorithmic_bytes_per_launch=faces_per_launch * BYTES_PER_FACE,
+                        traffic=stored_traffic("k_sweep"), algorithmic_bytes_per_launch=faces_per_launch * BYTES_PER_FACE,
                         avg_launch_ms=avg_ms, launches_per_step=n_sw / nprof,
                         alu_tflops=tflops, alu_frac=tflops / PEAK_FP32_TFLOPS)
+        # adjoint levels: latency-bound; measured traffic against HBM peak
+        n_lv, ms_lv = prof["adj_level"]
+        lv_ms = ms_lv / max(n_lv, 1)
+        lv_bytes = stored_traffic("k_adj_level")
+        detail["adjoint_level"] = dict(
+            kernel="k_adj_level", avg_launch_ms=lv_ms, launches_per_step=n_lv / nprof,
+            traffic=lv_bytes,
+            achieved_GBps=None if lv_bytes is None else lv_bytes / (lv_ms * 1e-3) / 1e9,
+            frac_of_hbm_peak=None if lv_bytes is None else lv_bytes / (lv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+        # ECG contraction on the matrix cores: executed bf16 MFMA flops (counters)
+        # over the launch time measured here
+        for fam, kern in (("ecg_fwd", "k_ecg_fwd"), ("ecg_bwd", "k_ecg_bwd")):
+            n_k, ms_k = prof[fam]
+            m = stored_mfma(kern)
+            if m and n_k:
+                avg = ms_k / n_k
+                tf = m["mfma_flops_per_launch"] / (avg * 1e-3) / 1e12
+                detail[kern] = dict(avg_launch_ms=avg, mfma_flops_per_launch=m["mfma_flops_per_launch"],
+                                    mfma_tflops=tf, peak_tflops=PEAK_BF16_TFLOPS, frac=tf / PEAK_BF16_TFLOPS,
+                                    mfma_busy_pct=m["mfma_busy_pct"])
         detail["kernel_ms_per_step"] = {k: v[1] / nprof for k, v in prof.items() if v[0]}
         detail["kernel_launches_per_step"] = {k: v[0] / nprof for k, v in prof.items() if v[0]}
     if not args.no_forms:

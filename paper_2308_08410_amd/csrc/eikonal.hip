@@ -461,23 +461,11 @@ __global__ void __launch_bounds__(TPB)
     const int2 p = reached ? nptr[i] : make_int2(0, 0);
     const int c0 = p.y & 255, c1 = (p.y >> 8) & 255, c2 = (p.y >> 16) & 255, c3 = (p.y >> 24) & 255;
     const int e01 = c0 + c1, e012 = e01 + c2, tot = e012 + c3;
-    // FP32 screen
+    // FP32 screen (the first kKeep values of each lane are kept for the second pass)
+    constexpr int kKeep = 4;
+    float keep[kKeep];
     float b32 = GBP_INF;
-    for (int c = lane; c < tot; c += L) {
-        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
-        const int t = nent[p.x + c];
-        const int4 v = tetv[t];
-        int a, b, cc;
-        face_nodes_sel(v, K, a, b, cc);
-        b32 = fminf(b32, local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
-                                          T[a], T[b], T[cc]));
-    }
-    for (int o = L / 2; o > 0; o >>= 1) b32 = fminf(b32, __shfl_xor(b32, o));
-    const float cut = b32 + 1e-4f * fmaxf(1.f, fabsf(b32));
-    // FP64 decision among the candidates
-    double best = __builtin_huge_val(), b0 = 0, b1 = 0, b2 = 0;
-    int bpos = 0x7fffffff;
-    for (int c = lane; c < tot && b32 < GBP_INF; c += L) {
+    for (int c = lane, k = 0; c < tot; c += L, ++k) {
         const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
         const int t = nent[p.x + c];
         const int4 v = tetv[t];
@@ -485,7 +473,29 @@ __global__ void __launch_bounds__(TPB)
         face_nodes_sel(v, K, a, b, cc);
         const float v32 = local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
                                            T[a], T[b], T[cc]);
+        if (k < kKeep) keep[k] = v32;
+        b32 = fminf(b32, v32);
+    }
+    for (int o = L / 2; o > 0; o >>= 1) b32 = fminf(b32, __shfl_xor(b32, o));
+    const float cut = b32 + 1e-4f * fmaxf(1.f, fabsf(b32));
+    // FP64 decision among the candidates
+    double best = __builtin_huge_val(), b0 = 0, b1 = 0, b2 = 0;
+    int bpos = 0x7fffffff;
+    for (int c = lane, k = 0; c < tot && b32 < GBP_INF; c += L, ++k) {
+        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
+        float v32;
+        if (k < kKeep) {
+            v32 = keep[k];
+        } else {
+            const int t = nent[p.x + c];
+            const int4 v = tetv[t];
+            int a, b, cc;
+            face_nodes_sel(v, K, a, b, cc);
+            v32 = local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
+                                   T[a], T[b], T[cc]);
+        }
         if (!(v32 <= cut)) continue;
+        const int t = nent[p.x + c];
         double x0, x1, x2;
         const double val = parent_face64(t, K, i, tetv, tet_user, D, vs, xyz, T, x0, x1, x2);
         if (val < best) {

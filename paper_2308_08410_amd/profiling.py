@@ -30,24 +30,24 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 def _kernel_text(src: str, name: str) -> str:
     """Source text of one __global__ function template (from its template line to
     the closing brace at column 0)."""
-    m = re.search(r"\n(template <[^\n]*>\n__global__[^\n]*\n\s*" + re.escape(name) + r"\(.*?\n}\n)",
+    m = re.search(r"\n((?:template <[^\n]*>\n)?__global__[^\n]*?\s+" + re.escape(name) + r"\(.*?\n}\n)",
                   src, re.S)
     if not m:
         raise KeyError(name)
     return m.group(1)
 
 
-def source_hash(kernel: str = "k_sweep") -> str:
-    """Hash of what the relaxation round is compiled from: the kernel's own text,
-    the queue-push helpers it calls and the local solver."""
-    with open(os.path.join(_HERE, "csrc", "eikonal.hip")) as f:
+def source_hash(kernel: str = "k_sweep", source: str = "eikonal.hip") -> str:
+    """Hash of what a kernel is compiled from: its own text, the queue-push
+    helpers and the local solver."""
+    with open(os.path.join(_HERE, "csrc", source)) as f:
         eik = f.read()
     with open(os.path.join(_HERE, "csrc", "local_solve.h")) as f:
         ls = f.read()
-    i = eik.index("constexpr int kPushCap")
-    j = eik.index("__global__", i)
+    i = eik.find("constexpr int kPushCap")
+    j = eik.index("__global__", i) if i >= 0 else 0
     h = hashlib.sha256()
-    for part in (eik[i:j], _kernel_text(eik, kernel), ls):
+    for part in (eik[max(i, 0):j], _kernel_text(eik, kernel), ls):
         h.update(part.encode())
     return h.hexdigest()[:16]
 
@@ -97,7 +97,35 @@ def traffic(fetch_path, write_path, kernel="k_sweep", copy_substr="neg", copy_mi
                 copy_fetch_kib_raw=f_c, copy_write_kib_raw=w_c, copy_mib=copy_mib,
                 fetch_scale=sf, write_scale=sw,
                 bytes_per_launch=1024.0 * (f_k * sf + w_k * sw),
-                source_hash=source_hash())
+                source_hash=source_hash(kernel))
+
+
+def mfma(path, kernel, source="ecg.hip", peak_tflops=2500.0):
+    """Matrix-core use of one kernel from a `--pmc MfmaFlopsBF16 MfmaUtil` run:
+    executed bf16 MFMA flops per dispatch, their rate over the dispatch's
+    duration, and the fraction of cycles the matrix units were busy."""
+    flops, util, dur = {}, {}, {}
+    with open(_counter_csv(path), newline="") as f:
+        for r in csv.DictReader(f):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            v = float(r["Counter_Value"])
+            if r["Counter_Name"] == "MfmaFlopsBF16":
+                flops[d] = flops.get(d, 0.0) + v
+            elif r["Counter_Name"] == "MfmaUtil":
+                util[d] = v
+            dur[d] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    if not flops:
+        raise KeyError(f"no MfmaFlopsBF16 rows for {kernel!r}")
+    n = len(flops)
+    f_avg = sum(flops.values()) / n
+    t_avg = sum(dur[d] for d in flops) / n
+    return dict(kernel=kernel, dispatches=n, mfma_flops_per_launch=f_avg,
+                avg_duration_s_under_counters=t_avg, achieved_tflops=f_avg / t_avg / 1e12,
+                peak_tflops=peak_tflops, frac=f_avg / t_avg / 1e12 / peak_tflops,
+                mfma_busy_pct=sum(util.values()) / max(len(util), 1),
+                source_hash=source_hash(kernel, source))
 
 
 def read_summary(path):
@@ -113,14 +141,35 @@ def read_summary(path):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--mfma", help="a --pmc MfmaFlopsBF16 MfmaUtil run (instead of --fetch/--write)")
     ap.add_argument("--kernel", default="k_sweep")
     ap.add_argument("--copy", default="neg")
     ap.add_argument("--copy-mib", type=float, default=256)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", default="", help="the profiled command, recorded in the summary")
     args = ap.parse_args(argv)
+    if args.mfma:
+        t = mfma(args.mfma, args.kernel)
+        with open(args.out, "w") as f:
+            f.write(f"# Matrix-core use: {args.kernel}\n\n")
+            f.write("One rocprofv3 counter run (derived counters MfmaFlopsBF16 = 512 x\n"
+                    "SQ_INSTS_VALU_MFMA_MOPS_BF16, MfmaUtil = MFMA-busy cycles over active cycles x SIMDs).\n\n")
+            if args.command:
+                f.write("Commands (repository root, GPU box):\n\n")
+                for line in args.command.split(";;"):
+                    f.write(f"    {line.strip()}\n")
+                f.write("\n")
+            f.write(f"Per launch: {t['mfma_flops_per_launch'] / 1e9:.3f} GFLOP executed on the matrix cores, "
+                    f"{t['achieved_tflops']:.2f} TFLOP/s over the counted dispatch time "
+                    f"({100 * t['frac']:.3f}% of the {t['peak_tflops']:.0f} TFLOP/s bf16 dense peak); "
+                    f"MFMA busy {t['mfma_busy_pct']:.3f}% of cycles.\n\n")
+            f.write("```json\n" + json.dumps(t, indent=1) + "\n```\n")
+        print(json.dumps(t))
+        return
+    if not (args.fetch and args.write):
+        ap.error("--fetch and --write are required without --mfma")
     t = traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_mib)
     with open(args.out, "w") as f:
         f.write(f"# HBM traffic per launch: {args.kernel}\n\n")
