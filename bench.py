@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--cpu-sample-nodes", type=int, default=125_000)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH",
+                    help="use this launch configuration instead of autotuning (e.g. to profile the "
+                         "configuration a timed run chose)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the warm-started single and batched forms")
     ap.add_argument("--form-steps", type=int, default=10)
@@ -275,6 +279,16 @@ def main():
     prob = gi.shell_problem(args.nodes, seed=2, n_roots=5, n_leads=12)
     log(f"[bench] shell n_v={prob.n_v} n_e={prob.n_e} generated in {time.time() - t:.1f}s")
     st = make_state(prob, dev, torch, gi, B)
+    tuned = None
+    if args.launch:
+        lanes, blocks, batch = (int(x) for x in args.launch.split(","))
+        B.set_launch(st["plan"], lanes, blocks, 256, batch)
+    elif not args.no_tune:
+        from paper_2308_08410_amd import autotune
+        t = time.time()
+        tuned = autotune.tune(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], use_cache=False, save=False)
+        log(f"[bench] autotuned launch: lanes={tuned['lanes']} sweep_blocks={tuned['sweep_blocks']} "
+            f"sync_batch={tuned['sync_batch']} ({time.time() - t:.1f}s)")
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 20)) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)
@@ -302,7 +316,8 @@ def main():
         f"loss={float(loss[0]):.4g}")
 
     roofline = None
-    detail = dict(fim_rounds=stats["rounds"], face_solves_per_step=face_solves // args.steps,
+    detail = dict(launch=B.get_launch(st["plan"]), fim_rounds=stats["rounds"],
+                  face_solves_per_step=face_solves // args.steps,
                   node_updates=stats["node_updates"], wall_ms_per_step=1e3 * t_wall / args.steps)
     if not args.no_profile:
         # per-kernel HIP-event timing on the launching stream, separate steps

@@ -2,7 +2,7 @@
 
 For a plan and a representative problem it times the eikonal forward (and
 optionally the adjoint) under each candidate configuration -- lanes per vertex
-in a relaxation round, grid of a round -- keeps the
+in a relaxation round, grid of a round, launches between convergence checks -- keeps the
 fastest, and records the rounds/levels that carried work so that graph-captured
 iterations can be given launch budgets.  Results are cached in a JSON file
 keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
@@ -17,8 +17,8 @@ import torch
 
 from . import binding as B
 
-SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=256)
-         for lanes in (8, 16, 32) for sb in (512, 1024, 2048)]
+SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=256, sync_batch=bt)
+         for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048) for bt in (16, 32, 64)]
 
 
 def cache_path() -> str:
@@ -69,7 +69,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
     db = _load() if use_cache else {}
     if use_cache and key in db:
         rec = db[key]
-        B.set_launch(plan, rec["lanes"], rec["sweep_blocks"], rec["level_blocks"])
+        B.set_launch(plan, rec["lanes"], rec["sweep_blocks"], rec["level_blocks"], rec.get("sync_batch", 16))
         return dict(rec, cached=True)
     gT = torch.ones(plan.n_v, dtype=torch.float32, device=D.device)
     T = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
@@ -81,12 +81,12 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
 
     best = None
     for cfg in (space or SPACE):
-        B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], cfg["level_blocks"])
+        B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], cfg["level_blocks"], cfg["sync_batch"])
         run()                                    # warm-up
         ms = _time(run, repeats)
         if best is None or ms < best["ms"]:
             best = dict(cfg, ms=ms)
-    B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"])
+    B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"], best["sync_batch"])
     run()
     best.update(B.last_counts(plan))
     if save:
