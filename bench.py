@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--cpu-sample-nodes", type=int, default=125_000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
-    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH",
+    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS",
                     help="use this launch configuration instead of autotuning (e.g. to profile the "
                          "configuration a timed run chose)")
     ap.add_argument("--no-forms", action="store_true",
@@ -281,14 +281,14 @@ def main():
     st = make_state(prob, dev, torch, gi, B)
     tuned = None
     if args.launch:
-        lanes, blocks, batch = (int(x) for x in args.launch.split(","))
-        B.set_launch(st["plan"], lanes, blocks, 256, batch)
+        lanes, blocks, batch, lblocks = (int(x) for x in args.launch.split(","))
+        B.set_launch(st["plan"], lanes, blocks, lblocks, batch)
     elif not args.no_tune:
         from paper_2308_08410_amd import autotune
         t = time.time()
         tuned = autotune.tune(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], use_cache=False, save=False)
         log(f"[bench] autotuned launch: lanes={tuned['lanes']} sweep_blocks={tuned['sweep_blocks']} "
-            f"sync_batch={tuned['sync_batch']} ({time.time() - t:.1f}s)")
+            f"sync_batch={tuned['sync_batch']} level_blocks={tuned['level_blocks']} ({time.time() - t:.1f}s)")
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 20)) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)

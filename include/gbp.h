@@ -240,8 +240,8 @@ int gbp_plan_status(gbp_plan plan, int *err_code, int *forward_converged,
  * relaxation rounds and adjoint levels (chosen by an autotuner):
  *   lanes        lanes per vertex in a relaxation round: 8, 16 or 32
  *   sweep_blocks grid of a relaxation round, 64..2048
- *   level_blocks grid of an adjoint Gauss-Seidel sweep over cycle remainders,
- *                16..2048 (adjoint levels use one thread per vertex)
+ *   level_blocks grid of an adjoint level (a scan of all vertices, at most 8 per
+ *                thread, so at least n_v / 2048 blocks are used), 16..2048
  *   sync_batch   launches between convergence checks in synchronous calls, 1..64
  * Results do not depend on the configuration beyond rounding order.
  * Errors: GBP_ERR_ARG for values outside those ranges.

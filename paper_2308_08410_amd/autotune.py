@@ -17,8 +17,9 @@ import torch
 
 from . import binding as B
 
-SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=256, sync_batch=bt)
+SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt)
          for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048) for bt in (16, 32, 64)]
+LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
 
 
 def cache_path() -> str:
@@ -86,6 +87,14 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
         ms = _time(run, repeats)
         if best is None or ms < best["ms"]:
             best = dict(cfg, ms=ms)
+    if backward and space is None:
+        for lb in LEVEL_SPACE:
+            cfg = dict(best, level_blocks=lb)
+            B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], lb, cfg["sync_batch"])
+            run()
+            ms = _time(run, repeats)
+            if ms < best["ms"]:
+                best = dict(cfg, ms=ms)
     B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"], best["sync_batch"])
     run()
     best.update(B.last_counts(plan))

@@ -303,7 +303,7 @@ def plan_status(plan: Plan, stream=None):
                 rounds=r.value, levels=l.value)
 
 
-def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=256, sync_batch=16):
+def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=2048, sync_batch=16):
     _check(_set_launch(plan.handle, lanes, sweep_blocks, level_blocks, sync_batch))
 
 

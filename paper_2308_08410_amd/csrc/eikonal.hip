@@ -655,6 +655,7 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
 constexpr int kRdyNever = 0x7fffffff;   // waiting for children (or unreached)
 constexpr int kRdyWait = 0x7ffffffe;    // first member of a two-cycle, partner not ready
 constexpr int kRdyDone = 0x7ffffffd;    // finished
+constexpr int kLevelPer = 8;            // vertices per thread in a level scan (grid >= n_v / (8 TPB))
 
 __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __restrict__ node_user,
                            const float* __restrict__ T, const int* __restrict__ rem, int n_v,
@@ -712,8 +713,19 @@ __global__ void __launch_bounds__(TPB)
     if (threadIdx.x == 0) any_sh = 0;
     __syncthreads();
     bool any = false;
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n_v; x += gridDim.x * blockDim.x) {
-        if (rdy[x] > s) continue;                   // not ready yet, waiting or finished
+    // up to kLevelPer vertices per thread: their stamps are loaded together first
+    const int stride = gridDim.x * blockDim.x;
+    const int xb = blockIdx.x * blockDim.x + threadIdx.x;
+    int rv[kLevelPer];
+#pragma unroll
+    for (int k = 0; k < kLevelPer; ++k) {
+        const int x = xb + k * stride;
+        rv[k] = x < n_v ? rdy[x] : kRdyNever;
+    }
+#pragma unroll
+    for (int k = 0; k < kLevelPer; ++k) {
+        if (rv[k] > s) continue;                    // not ready yet, waiting or finished
+        const int x = xb + k * stride;
         const int q = partner[x];
         if (q < 0) {
             float l = g[x];
@@ -1256,14 +1268,17 @@ extern "C" int gbp_backward_info(gbp_plan p, int* levels, int* cyclic, int* gs_s
 
 static void launch_level(gbp_plan p, int level, hipStream_t s) {
     ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
-    k_adj_level<<<std::max(1, gbp_blocks(p->n_v, TPB)), TPB, 0, s>>>(
+    const int need = gbp_blocks(p->n_v, TPB);
+    const int grid = std::max(std::max(1, gbp_blocks(p->n_v, (long long)TPB * kLevelPer)),
+                              std::min(need, p->level_blocks));
+    k_adj_level<<<grid, TPB, 0, s>>>(
         p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->done, p->pnode, p->partner,
         p->pairrem, p->rem, p->n_v, p->ctl, level);
 }
 
 static void launch_gs(gbp_plan p, int it, hipStream_t s) {
     ProfScope ps(GBP_PROF_AUX, s);
-    k_adj_gs<<<std::max(1, std::min(gbp_blocks(p->n_v, TPB), p->level_blocks)), TPB, 0, s>>>(
+    k_adj_gs<<<std::max(1, std::min(gbp_blocks(p->n_v, TPB), 1024)), TPB, 0, s>>>(
         p->cfill, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->ctl, it);
 }
 

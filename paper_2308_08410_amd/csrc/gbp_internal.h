@@ -87,7 +87,7 @@ struct gbp_plan_s {
     // launch configuration (autotunable)
     int lanes = 16;               // lanes per vertex in a relaxation round (8, 16 or 32)
     int sweep_blocks = 2048;      // grid of a relaxation round (<= kStatBlocks)
-    int level_blocks = 256;       // grid of an adjoint level
+    int level_blocks = 2048;      // grid of an adjoint level (scan; at least n_v / (8 * 256))
     int sync_batch = 16;          // launches between convergence checks (synchronous mode)
     int last_rounds = 0, last_levels = 0;   // of the last synchronous calls
     GbpCtl* ctl = nullptr;        // device control block
