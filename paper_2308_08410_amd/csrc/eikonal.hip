@@ -308,8 +308,13 @@ __global__ void __launch_bounds__(TPB)
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
-            float eps_rel) {
+            float eps_rel, int n_v) {
     constexpr int PER_BLOCK = TPB / L;
+    // the first queue entry of this lane group is loaded before the queue length
+    // is known (both loads in flight together); it is used only if it is in the
+    // queue, and clamped so that a stale entry never indexes out of range
+    const int qi0 = blockIdx.x * PER_BLOCK + threadIdx.x / L;
+    const int pre = qi0 < n_v ? qin[qi0] : 0;
     const int n = ctl->count[s % 3];
     const int stamp_next = ctl->stamp + s + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -329,7 +334,8 @@ __global__ void __launch_bounds__(TPB)
     for (int base = blockIdx.x * PER_BLOCK; base < n; base += gridDim.x * PER_BLOCK) {
         const int qi = base + sub;
         const bool act = qi < n;                    // uniform over the lane group
-        const int i = act ? qin[qi] : 0;
+        const int iq = act ? (qi == qi0 ? pre : qin[qi]) : 0;
+        const int i = min(max(iq, 0), n_v - 1);
         const int2 p = act ? nptr[i] : make_int2(0, 0);
         const float told = T[i];
         const float tr = TWO_SIDED ? troot[i] : 0.f;
@@ -703,6 +709,16 @@ __global__ void __launch_bounds__(TPB)
                 const float* __restrict__ g, float* lam, int* __restrict__ done,
                 const int4* __restrict__ pnode, const int* __restrict__ partner,
                 int* __restrict__ pairrem, int* __restrict__ rem, int n_v, GbpCtl* ctl, int s) {
+    // up to kLevelPer vertices per thread: their stamps are loaded together, and
+    // before the work flag, so that all these loads are in flight at once
+    const int stride = gridDim.x * blockDim.x;
+    const int xb = blockIdx.x * blockDim.x + threadIdx.x;
+    int rv[kLevelPer];
+#pragma unroll
+    for (int k = 0; k < kLevelPer; ++k) {
+        const int x = xb + k * stride;
+        rv[k] = x < n_v ? rdy[x] : kRdyNever;
+    }
     const int flag = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
@@ -713,15 +729,6 @@ __global__ void __launch_bounds__(TPB)
     if (threadIdx.x == 0) any_sh = 0;
     __syncthreads();
     bool any = false;
-    // up to kLevelPer vertices per thread: their stamps are loaded together first
-    const int stride = gridDim.x * blockDim.x;
-    const int xb = blockIdx.x * blockDim.x + threadIdx.x;
-    int rv[kLevelPer];
-#pragma unroll
-    for (int k = 0; k < kLevelPer; ++k) {
-        const int x = xb + k * stride;
-        rv[k] = x < n_v ? rdy[x] : kRdyNever;
-    }
 #pragma unroll
     for (int k = 0; k < kLevelPer; ++k) {
         if (rv[k] > s) continue;                    // not ready yet, waiting or finished
@@ -1144,7 +1151,7 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
 #define GBP_SWEEP(TS, LN)                                                                       \
     k_sweep<TS, LN><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, qin, \
                                          qout, p->adj_ptr, p->adj, p->mark, p->ctl, p->blk, r,   \
-                                         p->eps_rel)
+                                         p->eps_rel, p->n_v)
     if (cold) {
         if (p->lanes == 8) GBP_SWEEP(false, 8);
         else if (p->lanes == 32) GBP_SWEEP(false, 32);
