@@ -55,32 +55,49 @@ __device__ __forceinline__ float block_max_f(float v) {
     return t;
 }
 
-// Block-level queue buffer: pushes land in LDS; one atomic per block reserves
-// room in the global queue at flush time (overflow goes straight to global).
+// Capacity of a block's LDS push buffer (entries, all sub-queue sections).
 constexpr int kPushCap = 4096;
 
-struct PushBuf {
-    int* q;      // LDS [kPushCap]
-    int* n;      // LDS counter
+__device__ __forceinline__ int xcd_of(int i, int R) { return (i / R) & 7; }
+// position of vertex i inside its sub-queue when every vertex is queued
+__device__ __forceinline__ int xcd_rank(int i, int R) {
+    const int r = i / R;
+    return (r >> 3) * R + (i - r * R);
+}
+
+// Block-level buffer with one section per sub-queue; one atomic per non-empty
+// section and block at flush time (overflow goes straight to global).
+constexpr int kXSec = kPushCap / 8;
+
+struct XPushBuf {
+    int* q;      // LDS [8 * kXSec]
+    int* n;      // LDS [8]
 };
 
-__device__ __forceinline__ void push_node(PushBuf b, int v, int* __restrict__ qout,
-                                          int* cnt_next) {
-    const int pos = atomicAdd(b.n, 1);
-    if (pos < kPushCap) {
-        b.q[pos] = v;
+__device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& xq,
+                                           int* __restrict__ qout, int* cnt_next) {
+    const int x = xcd_of(v, xq.R);
+    const int pos = atomicAdd(&b.n[x], 1);
+    if (pos < kXSec) {
+        b.q[x * kXSec + pos] = v;
     } else {
-        qout[atomicAdd(cnt_next, 1)] = v;
+        qout[xq.off[x] + atomicAdd(&cnt_next[x], 1)] = v;
     }
 }
 
-__device__ __forceinline__ void push_flush(PushBuf b, int* __restrict__ qout, int* cnt_next,
-                                           int* base_sh) {
+__device__ __forceinline__ void xpush_flush(XPushBuf b, const XcdQueues& xq, int* __restrict__ qout,
+                                            int* cnt_next, int* base_sh) {
     __syncthreads();
-    const int n = min(*b.n, kPushCap);
-    if (threadIdx.x == 0) *base_sh = n > 0 ? atomicAdd(cnt_next, n) : 0;
+    if (threadIdx.x < 8) {
+        const int m = min(b.n[threadIdx.x], kXSec);
+        base_sh[threadIdx.x] = m > 0 ? atomicAdd(&cnt_next[threadIdx.x], m) : 0;
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) qout[*base_sh + k] = b.q[k];
+    for (int x = 0; x < 8; ++x) {
+        const int m = min(b.n[x], kXSec);
+        for (int k = threadIdx.x; k < m; k += blockDim.x)
+            qout[xq.off[x] + base_sh[x] + k] = b.q[x * kXSec + k];
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long* __restrict__ p, int n) {
@@ -187,7 +204,8 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
                         int n_roots, const int* __restrict__ node_int, int n_v,
                         float* __restrict__ troot, float* __restrict__ T, int cold,
                         const int* __restrict__ adj_ptr, const int* __restrict__ adj,
-                        int* __restrict__ qout, int* __restrict__ mark, GbpCtl* ctl) {
+                        int* __restrict__ qout, int* __restrict__ mark, GbpCtl* ctl,
+                        XcdQueues xq) {
     const int stamp = ctl->stamp;
     if (threadIdx.x == 0) {
         for (int r = 0; r < n_roots; ++r) {
@@ -215,18 +233,19 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
         for (int a = adj_ptr[i]; a < adj_ptr[i + 1]; ++a) {
             const int nb = adj[a];
             if (atomicMax(&mark[nb], stamp) < stamp) {
-                const int pos = atomicAdd(&ctl->count[0], 1);
-                qout[pos] = nb;
+                const int x = xcd_of(nb, xq.R);
+                qout[xq.off[x] + atomicAdd(&ctl->qcnt[0][x], 1)] = nb;
             }
         }
     }
 }
 
-__global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int n_v, GbpCtl* ctl) {
+__global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int n_v, GbpCtl* ctl,
+                            XcdQueues xq) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) ctl->count[0] = n_v;
+    if (i < 8) ctl->qcnt[0][i] = xq.off[i + 1] - xq.off[i];
     if (i < n_v) {
-        q[i] = i;
+        q[xq.off[xcd_of(i, xq.R)] + xcd_rank(i, xq.R)] = i;
         mark[i] = ctl->stamp;
     }
 }
@@ -259,7 +278,9 @@ __global__ void k_mark_reset_if(int* __restrict__ mark, int n_v, const GbpCtl* c
 __global__ void k_forward_end(GbpCtl* ctl, int launched) {
     if (threadIdx.x == 0) {
         ctl->stamp += launched + 2;
-        if (ctl->count[launched % 3] != 0) ctl->status |= 1;
+        int left = 0;
+        for (int x = 0; x < 8; ++x) left += ctl->qcnt[launched % 3][x];
+        if (left != 0) ctl->status |= 1;
     }
 }
 
@@ -308,33 +329,37 @@ __global__ void __launch_bounds__(TPB)
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
-            float eps_rel, int n_v) {
+            float eps_rel, int n_v, XcdQueues xq) {
     constexpr int PER_BLOCK = TPB / L;
+    // blocks are placed on the 8 XCDs round-robin: block b serves sub-queue b % 8
+    const int x = blockIdx.x & 7;
+    const int lb = blockIdx.x >> 3, nbx = (gridDim.x + 7 - x) >> 3;
+    const int* qx = qin + xq.off[x];
     // the first queue entry of this lane group is loaded before the queue length
     // is known (both loads in flight together); it is used only if it is in the
     // queue, and clamped so that a stale entry never indexes out of range
-    const int qi0 = blockIdx.x * PER_BLOCK + threadIdx.x / L;
-    const int pre = qi0 < n_v ? qin[qi0] : 0;
-    const int n = ctl->count[s % 3];
+    const int qi0 = lb * PER_BLOCK + threadIdx.x / L;
+    const int pre = qi0 < xq.off[x + 1] - xq.off[x] ? qx[qi0] : 0;
+    const int n = ctl->qcnt[s % 3][x];
     const int stamp_next = ctl->stamp + s + 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[(s + 2) % 3] = 0;
-        if (n > 0) atomicMax(&ctl->rounds, s + 1);
+    if (blockIdx.x == 0 && threadIdx.x < 8) {
+        ctl->qcnt[(s + 2) % 3][threadIdx.x] = 0;
+        if (ctl->qcnt[s % 3][threadIdx.x] > 0) atomicMax(&ctl->rounds, s + 1);
     }
-    if (blockIdx.x * PER_BLOCK >= n) return;        // no vertex for this block
-    int* cnt_next = &ctl->count[(s + 1) % 3];
-    __shared__ int push_q[kPushCap];
-    __shared__ int push_n, push_base;
-    if (threadIdx.x == 0) push_n = 0;
+    if (lb * PER_BLOCK >= n) return;                // no vertex for this block
+    int* cnt_next = ctl->qcnt[(s + 1) % 3];
+    __shared__ int push_q[8 * kXSec];
+    __shared__ int push_n[8], push_base[8];
+    if (threadIdx.x < 8) push_n[threadIdx.x] = 0;
     __syncthreads();
-    const PushBuf pb{push_q, &push_n};
+    const XPushBuf pb{push_q, push_n};
     const int lane = threadIdx.x & (L - 1);
     const int sub = threadIdx.x / L;                // vertex slot of this lane group
     unsigned long long solves = 0, upd = 0;
-    for (int base = blockIdx.x * PER_BLOCK; base < n; base += gridDim.x * PER_BLOCK) {
+    for (int base = lb * PER_BLOCK; base < n; base += nbx * PER_BLOCK) {
         const int qi = base + sub;
         const bool act = qi < n;                    // uniform over the lane group
-        const int iq = act ? (qi == qi0 ? pre : qin[qi]) : 0;
+        const int iq = act ? (qi == qi0 ? pre : qx[qi]) : 0;
         const int i = min(max(iq, 0), n_v - 1);
         const int2 p = act ? nptr[i] : make_int2(0, 0);
         const float told = T[i];
@@ -373,11 +398,12 @@ __global__ void __launch_bounds__(TPB)
             if (lane == 0) ++upd;
             for (int a = adj0 + lane; a < adj1; a += L) {
                 const int nb = adj[a];
-                if (atomicMax(&mark[nb], stamp_next) < stamp_next) push_node(pb, nb, qout, cnt_next);
+                if (atomicMax(&mark[nb], stamp_next) < stamp_next)
+                    xpush_node(pb, nb, xq, qout, cnt_next);
             }
         }
     }
-    push_flush(pb, qout, cnt_next, &push_base);
+    xpush_flush(pb, xq, qout, cnt_next, push_base);
     // per-block counters: one writer per slot, no contended atomics
     solves = block_sum_u64(solves);
     upd = block_sum_u64(upd);
@@ -1138,7 +1164,8 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     else   // 0: warm start from T_init; 2: T given (backward, parent map)
         k_gather_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(T_init, p->node_user, p->T, n_v);
     k_roots<<<1, TPB, 0, s>>>(root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T,
-                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl);
+                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl,
+                              p->xq);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -1151,7 +1178,7 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
 #define GBP_SWEEP(TS, LN)                                                                       \
     k_sweep<TS, LN><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, qin, \
                                          qout, p->adj_ptr, p->adj, p->mark, p->ctl, p->blk, r,   \
-                                         p->eps_rel, p->n_v)
+                                         p->eps_rel, p->n_v, p->xq)
     if (cold) {
         if (p->lanes == 8) GBP_SWEEP(false, 8);
         else if (p->lanes == 32) GBP_SWEEP(false, 32);
@@ -1177,7 +1204,8 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
     const bool cold = (T_init == nullptr);
     if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
     k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
-    if (!cold) k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, n_v, p->ctl);
+    if (!cold)
+        k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, n_v, p->ctl, p->xq);
     GBP_LAUNCH_CHECK();
     int r = 0;
     bool converged = true;
@@ -1186,7 +1214,12 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
     } else {
         rc = run_pipelined(
             p, s, p->max_rounds, [&](int k) { launch_round(p, cold, k, s); },
-            [](const GbpCtl& c, int k_end) { return c.count[k_end % 3] == 0; }, r, converged);
+            [](const GbpCtl& c, int k_end) {
+                int left = 0;
+                for (int x = 0; x < 8; ++x) left += c.qcnt[k_end % 3][x];
+                return left == 0;
+            },
+            r, converged);
         if (rc) {
             k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);   // stamps used so far stay retired
             return rc;

@@ -57,6 +57,18 @@ struct GbpCtl {
     int status;                    // bit 0: forward not converged, bit 1: adjoint not settled
     int levels;                    // adjoint: last level with work + 1
     int pad;
+    int qcnt[3][8];                // forward: rotating lengths of the 8 sub-queues
+};
+
+// The forward's work queue is split into 8 sub-queues, one per XCD: the vertex
+// range (Morton order) is cut into kXcdRegions contiguous regions, region r
+// belongs to sub-queue r % 8, and the blocks of a relaxation round that the
+// hardware places on XCD x (blockIdx % 8 == x) work on sub-queue x.  Each XCD's
+// L2 then caches a fixed eighth of the mesh.
+constexpr int kXcdRegions = 512;
+struct XcdQueues {
+    int off[9];                    // segment of sub-queue x: [off[x], off[x+1])
+    int R;                         // vertices per region
 };
 
 struct gbp_plan_s {
@@ -84,6 +96,7 @@ struct gbp_plan_s {
     float* troot = nullptr;       // [n_v] min onset per node (+inf elsewhere)
     int* q[2] = {nullptr, nullptr};  // work queues
     int* mark = nullptr;          // [n_v] queue stamps
+    XcdQueues xq{};               // sub-queue layout of q[0], q[1]
     // launch configuration (autotunable)
     int lanes = 16;               // lanes per vertex in a relaxation round (8, 16 or 32)
     int sweep_blocks = 2048;      // grid of a relaxation round (<= kStatBlocks)

@@ -292,6 +292,14 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(dalloc(&p->vs, n_v));
     TRY(dalloc(&p->T, n_v));
     TRY(dalloc(&p->troot, n_v));
+    {   // sub-queue segments: region r (R vertices) belongs to sub-queue r % 8
+        const int R = std::max(1, (n_v + kXcdRegions - 1) / kXcdRegions);
+        int cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int r = 0; (long long)r * R < n_v; ++r) cap[r & 7] += std::min(R, n_v - r * R);
+        p->xq.R = R;
+        p->xq.off[0] = 0;
+        for (int x = 0; x < 8; ++x) p->xq.off[x + 1] = p->xq.off[x] + cap[x];
+    }
     TRY(dalloc(&p->q[0], n_v));
     TRY(dalloc(&p->q[1], n_v));
     TRY(dalloc(&p->mark, n_v));
