@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256)
     wsum_all += __shfl_xor(wsum_all, 32);
     if (kq == 0) wsum_sh[wave][col] = wsum_all;
     __syncthreads();
-    if (threadIdx.x < 16 && threadIdx.x < L) {
+    if (threadIdx.x < 16 && (int)threadIdx.x < L) {
         const float v = wsum_sh[0][threadIdx.x] + wsum_sh[1][threadIdx.x] +
                         wsum_sh[2][threadIdx.x] + wsum_sh[3][threadIdx.x];
         atomicAdd(&g_wsum[threadIdx.x], v);

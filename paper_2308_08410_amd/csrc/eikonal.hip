@@ -571,10 +571,6 @@ __device__ __forceinline__ void face_nodes_rt(const int4 v, int K, int& a, int& 
     }
 }
 
-__device__ __forceinline__ int face_target_rt(const int4 v, int K) {
-    return K == 0 ? v.x : K == 1 ? v.y : K == 2 ? v.z : v.w;
-}
-
 // ------------------------------------------------------------------ adjoint
 // Parent face vertices carrying weight, and two-cycle detection: a and c are
 // partners when each is a weighted parent of the other (the anisotropic scheme
@@ -989,7 +985,7 @@ __global__ void k_scan_block(const int* __restrict__ in, int* __restrict__ out, 
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        const int t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
         __syncthreads();
         sh[threadIdx.x] += t;
         __syncthreads();
@@ -1016,7 +1012,7 @@ __global__ void __launch_bounds__(1024) k_scan_top(int* __restrict__ bsum, int n
         sh[threadIdx.x] = v;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
-            const int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            const int t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
             __syncthreads();
             sh[threadIdx.x] += t;
             __syncthreads();

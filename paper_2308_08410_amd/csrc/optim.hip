@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(1024)
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) *loss = sh[0] * inv;
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(1024)
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 512; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) loss[blockIdx.x] = sh[0] * inv;
