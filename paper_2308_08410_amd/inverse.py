@@ -2,8 +2,10 @@
 and the root onsets so that the lead-field ECG matches a measured one, with Adam.
 
 Multi-starts run as the instances of one union plan (the batched form), every
-iteration is one replay of the graph-captured Geodesic-BP step, warm-started
-from the previous iteration's activation times.  All arithmetic runs in libgbp.
+iteration is one replay of the graph-captured Geodesic-BP step.  The forward is
+cold by default; `warm=True` starts it (two-sided) from the previous iteration's
+activation times, which reaches the same solution but is slower here, because
+every Adam step moves every activation time.  All arithmetic runs in libgbp.
 
     python -m paper_2308_08410_amd.inverse --nodes 100000 --starts 4 --iters 100
 """
@@ -26,7 +28,7 @@ class MultiStartFit:
     """``starts`` copies of one mesh, each with its own initial onsets (and
     scale), fitted to the same target ECG."""
 
-    def __init__(self, xyz, tets, D, W, root_node, target, ap: dict, vscale0, root_t0, warm=True,
+    def __init__(self, xyz, tets, D, W, root_node, target, ap: dict, vscale0, root_t0, warm=False,
                  lr_vscale=0.01, lr_root_t=0.5, vscale_bounds=(0.2, 5.0), device="cuda"):
         S = len(vscale0)
         n_v = len(xyz)
@@ -50,7 +52,8 @@ class MultiStartFit:
         B.eikonal_forward(self.plan, self.D, self.vs, self.rn, self.rt, out=self.T)
         B.eikonal_backward(self.plan, self.D, self.vs, self.rn, self.rt, self.T,
                            torch.ones_like(self.T), want_D=False)
-        self.budgets = autotune.budgets(self.plan, margin=1.5, extra=32)
+        # a two-sided warm solve can need more rounds than the cold one it is sized from
+        self.budgets = autotune.budgets(self.plan, margin=2.0 if warm else 1.5, extra=64 if warm else 32)
         self.step = B.Step(self.plan, self.batch, self.D, self.vs, self.rn, self.rt, self.W, self.ap,
                            self.target, self.T, self.ecg, self.loss, warm=warm, lr_vscale=lr_vscale,
                            lr_root_t=lr_root_t, vscale_lo=vscale_bounds[0], vscale_hi=vscale_bounds[1],
@@ -93,7 +96,8 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--roots", type=int, default=8)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--cold", action="store_true", help="cold forward every iteration")
+    ap.add_argument("--warm", action="store_true",
+                    help="start each forward from the previous iteration's activation times")
     args = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
     p, vs_true = synthetic_problem(args.nodes, args.roots, args.seed)
@@ -107,13 +111,13 @@ def main(argv=None):
     rng = np.random.Generator(np.random.PCG64(args.seed + 1))
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(args.starts)]
     rt0 = [rng.uniform(0.0, 20.0, size=args.roots).astype(np.float32) for _ in range(args.starts)]
-    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=not args.cold)
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=args.warm)
     out = fit.run(args.iters, log_every=max(1, args.iters // 10))
     final = out["history"][-1][1]
     best = int(np.argmin(final))
     vs_b, rt_b, T_b = fit.instance(best)
     err_T = float((T_b.cpu() - T_true.cpu()).abs().max())
-    print(json.dumps(dict(nodes=p.n_v, starts=args.starts, iters=args.iters, warm=not args.cold,
+    print(json.dumps(dict(nodes=p.n_v, starts=args.starts, iters=args.iters, warm=args.warm,
                           iters_per_s=out["iters_per_s"], seconds=out["seconds"], budgets=fit.budgets,
                           loss_first=[float(x) for x in out["history"][0][1]],
                           loss_final=[float(x) for x in final], best=best,
