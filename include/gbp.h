@@ -178,7 +178,9 @@ typedef struct {
  *   sum_n W[n*L + l] * U(t_s - T[n]).  W is the discretised lead-field operator
  *   B (one column per lead).  Vertices with T = +inf stay at rest (U = K0).
  *   T   device float [n_v];  W device float [n_v*L];  ecg device float [n_steps*L]
- *   1 <= L <= 16.
+ *   1 <= L <= 16.  Uses a library-owned scratch buffer per device (grown on
+ *   demand): forward calls that overlap on one device, on different streams or
+ *   host threads, race on it.
  */
 int gbp_ecg_forward(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
                     float *ecg, void *stream);

@@ -678,6 +678,23 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
     }
 }
 
+// Where each vertex sits in its weighted parents' (sorted) child lists, so that a
+// finished vertex can hand alpha * lambda to its parents' entries directly.
+__global__ void k_child_slots(const int4* __restrict__ pnode, const int* __restrict__ cptr,
+                              const int* __restrict__ cchild, int n_v, int4* __restrict__ cslot) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_v) return;
+    const int4 pn = pnode[c];
+    const int f[3] = {pn.x, pn.y, pn.z};
+    int pos[3] = {-1, -1, -1};
+    for (int k = 0; k < 3; ++k) {
+        if (f[k] < 0) continue;
+        for (int e = cptr[f[k]]; e < cptr[f[k] + 1]; ++e)
+            if (cchild[e] == c) pos[k] = e;
+    }
+    cslot[c] = make_int4(pos[0], pos[1], pos[2], -1);
+}
+
 // Readiness stamps of the level walk: the launch from which a vertex may be
 // finished (0 for leaves), or one of the markers below.
 constexpr int kRdyNever = 0x7fffffff;   // waiting for children (or unreached)
@@ -702,6 +719,17 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
     if (leaf) ctl->count[0] = 1;   // flag: the first launch has work
 }
 
+// A finished vertex hands alpha * lambda to its entries in its parents' child
+// lists (read only in later launches, after this one has ended).
+__device__ __forceinline__ void publish(int x, float l, const float4* __restrict__ pa,
+                                        const int4* __restrict__ cslot, float* __restrict__ contrib) {
+    const int4 cs = cslot[x];
+    const float4 w = pa[x];
+    if (cs.x >= 0) contrib[cs.x] = w.x * l;
+    if (cs.y >= 0) contrib[cs.y] = w.y * l;
+    if (cs.z >= 0) contrib[cs.z] = w.z * l;
+}
+
 // A finished vertex releases its parents; a parent whose last child this was
 // becomes ready for the next launch (stamped with a plain store: it is only
 // read after this launch ends).
@@ -721,16 +749,20 @@ __device__ __forceinline__ bool release_parents(int x, int skip, const int4* __r
 
 // One leaves-first level, as a scan over all vertices (one thread per vertex):
 // every vertex stamped ready for this launch has all (non-partner) children
-// finished in earlier launches, so their values are visible.  It pulls
-// lambda = g + sum alpha_c lambda_c in child order (deterministic); the second
+// finished in earlier launches, so their contributions are visible.  It sums
+// lambda = g + sum alpha_c lambda_c over its child entries in a fixed order
+// (deterministic; each child wrote its alpha_c lambda_c there), then writes its
+// own contributions to its parents' entries; the second
 // member of a two-cycle to become ready solves the pair
 //   lam_a = S_a + w_ca lam_c,  lam_c = S_c + w_ac lam_a.
 __global__ void __launch_bounds__(TPB)
     k_adj_level(int* __restrict__ rdy, const int* __restrict__ cptr,
                 const int* __restrict__ cchild, const float* __restrict__ calpha,
                 const float* __restrict__ g, float* lam, int* __restrict__ done,
-                const int4* __restrict__ pnode, const int* __restrict__ partner,
-                int* __restrict__ pairrem, int* __restrict__ rem, int n_v, GbpCtl* ctl, int s) {
+                const int4* __restrict__ pnode, const float4* __restrict__ pa,
+                const int4* __restrict__ cslot, float* __restrict__ contrib,
+                const int* __restrict__ partner, int* __restrict__ pairrem, int* __restrict__ rem,
+                int n_v, GbpCtl* ctl, int s) {
     // up to kLevelPer vertices per thread: their stamps are loaded together, and
     // before the work flag, so that all these loads are in flight at once
     const int stride = gridDim.x * blockDim.x;
@@ -758,10 +790,11 @@ __global__ void __launch_bounds__(TPB)
         const int q = partner[x];
         if (q < 0) {
             float l = g[x];
-            for (int k = cptr[x]; k < cptr[x + 1]; ++k) l += calpha[k] * lam[cchild[k]];
+            for (int k = cptr[x]; k < cptr[x + 1]; ++k) l += contrib[k];
             lam[x] = l;
             done[x] = 1;
             rdy[x] = kRdyDone;
+            publish(x, l, pa, cslot, contrib);
             any |= release_parents(x, -1, pnode, rem, rdy, s + 1);
             continue;
         }
@@ -777,7 +810,7 @@ __global__ void __launch_bounds__(TPB)
             for (int k = cptr[a]; k < cptr[a + 1]; ++k) {
                 const int ch = cchild[k];
                 if (ch == o) wo = calpha[k];
-                else l += calpha[k] * lam[ch];
+                else l += contrib[k];
             }
             S[m] = l;
             w[m] = wo;     // weight of a in o's parent face
@@ -790,6 +823,8 @@ __global__ void __launch_bounds__(TPB)
         done[q] = 1;
         rdy[x] = kRdyDone;
         rdy[q] = kRdyDone;
+        publish(x, lx, pa, cslot, contrib);
+        publish(q, lq, pa, cslot, contrib);
         any |= release_parents(x, q, pnode, rem, rdy, s + 1);
         any |= release_parents(q, x, pnode, rem, rdy, s + 1);
     }
@@ -1308,8 +1343,8 @@ static void launch_level(gbp_plan p, int level, hipStream_t s) {
     const int grid = std::max(std::max(1, gbp_blocks(p->n_v, (long long)TPB * kLevelPer)),
                               std::min(need, p->level_blocks));
     k_adj_level<<<grid, TPB, 0, s>>>(
-        p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->done, p->pnode, p->partner,
-        p->pairrem, p->rem, p->n_v, p->ctl, level);
+        p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->done, p->pnode, p->pa, p->cslot,
+        p->contrib, p->partner, p->pairrem, p->rem, p->n_v, p->ctl, level);
 }
 
 static void launch_gs(gbp_plan p, int it, hipStream_t s) {
@@ -1350,6 +1385,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
         k_child_fill<<<nb, TPB, 0, s>>>(p->pnode, p->pa, n_v, p->ccnt, p->cfill, p->cchild,
                                         p->calpha);
         k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
+        k_child_slots<<<nb, TPB, 0, s>>>(p->pnode, p->ccnt, p->cchild, n_v, p->cslot);
         GBP_LAUNCH_CHECK();
     }
     // leaves-first level walk

@@ -119,7 +119,8 @@ struct gbp_plan_s {
     int* cchild = nullptr;        // [3 n_v]
     float* calpha = nullptr;      // [3 n_v]
     float* lam = nullptr;         // [n_v]
-    float* lam2 = nullptr;        // [n_v]
+    float* contrib = nullptr;     // [3 n_v] alpha * lambda of each child entry, written by the child
+    int4* cslot = nullptr;        // [n_v] position of a vertex in each weighted parent's child list
     float* g = nullptr;           // [n_v]
     float* dsbar = nullptr;       // [n_e]
     int* done = nullptr;          // [n_v] adjoint finished flag

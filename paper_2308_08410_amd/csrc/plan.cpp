@@ -71,7 +71,7 @@ static void plan_free(gbp_plan p) {
     void* ptrs[] = {p->xyz, p->tetv, p->tet_user, p->node_user, p->node_int, p->nptr, p->nent,
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
-                    p->calpha, p->lam, p->lam2, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp,
+                    p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp,
                     p->pnode, p->partner, p->pairrem};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -335,7 +335,8 @@ int gbp_alloc_backward(gbp_plan p) {
         (rc = dalloc(&p->ccnt, n_v + 1)) || (rc = dalloc(&p->cfill, n_v)) ||
         (rc = dalloc(&p->rem, n_v)) || (rc = dalloc(&p->cchild, (size_t)3 * n_v)) ||
         (rc = dalloc(&p->calpha, (size_t)3 * n_v)) || (rc = dalloc(&p->lam, n_v)) ||
-        (rc = dalloc(&p->lam2, n_v)) || (rc = dalloc(&p->g, n_v)) ||
+        (rc = dalloc(&p->contrib, (size_t)3 * n_v)) || (rc = dalloc(&p->cslot, n_v)) ||
+        (rc = dalloc(&p->g, n_v)) ||
         (rc = dalloc(&p->dsbar, n_e)) || (rc = dalloc(&p->done, n_v)) || (rc = dalloc(&p->rdy, n_v)) ||
         (rc = dalloc(&p->pnode, n_v)) || (rc = dalloc(&p->partner, n_v)) ||
         (rc = dalloc(&p->pairrem, n_v)) ||
