@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--cpu-sample-nodes", type=int, default=125_000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
-    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS",
+    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS,SPLIT",
                     help="use this launch configuration instead of autotuning (e.g. to profile the "
                          "configuration a timed run chose)")
     ap.add_argument("--no-forms", action="store_true",
@@ -208,7 +208,7 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
     tune = autotune.tune(plan, D, vs, rn, rt, use_cache=False, save=False, repeats=1)
     out = dict(instances=n_inst, distinct_meshes=n_meshes, mesh_sizes=[int(m.n_v) for m in meshes],
                total_vertices=int(voff[-1]), total_tets=int(len(tets)), setup_s=t_setup,
-               launch=dict(lanes=tune["lanes"], sweep_blocks=tune["sweep_blocks"]))
+               launch=dict(lanes=tune["lanes"], sweep_blocks=tune["sweep_blocks"], split=tune["split"]))
     vs_start, rt_start = vs.clone(), rt.clone()
     for warm in (False, True):
         vs.copy_(vs_start)
@@ -281,14 +281,16 @@ def main():
     st = make_state(prob, dev, torch, gi, B)
     tuned = None
     if args.launch:
-        lanes, blocks, batch, lblocks = (int(x) for x in args.launch.split(","))
+        lanes, blocks, batch, lblocks, split = (int(x) for x in args.launch.split(","))
         B.set_launch(st["plan"], lanes, blocks, lblocks, batch)
+        B.set_queue_split(st["plan"], split)
     elif not args.no_tune:
         from paper_2308_08410_amd import autotune
         t = time.time()
         tuned = autotune.tune(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], use_cache=False, save=False)
         log(f"[bench] autotuned launch: lanes={tuned['lanes']} sweep_blocks={tuned['sweep_blocks']} "
-            f"sync_batch={tuned['sync_batch']} level_blocks={tuned['level_blocks']} ({time.time() - t:.1f}s)")
+            f"sync_batch={tuned['sync_batch']} level_blocks={tuned['level_blocks']} split={tuned['split']} "
+            f"({time.time() - t:.1f}s)")
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 20)) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)
@@ -316,7 +318,8 @@ def main():
         f"loss={float(loss[0]):.4g}")
 
     roofline = None
-    detail = dict(launch=B.get_launch(st["plan"]), fim_rounds=stats["rounds"],
+    detail = dict(launch=dict(B.get_launch(st["plan"]), split=int(B.get_queue_split(st["plan"]))),
+                  fim_rounds=stats["rounds"],
                   face_solves_per_step=face_solves // args.steps,
                   node_updates=stats["node_updates"], wall_ms_per_step=1e3 * t_wall / args.steps)
     if not args.no_profile:

@@ -252,6 +252,17 @@ int gbp_plan_set_launch(gbp_plan plan, int lanes, int sweep_blocks, int level_bl
                         int sync_batch);
 int gbp_plan_get_launch(gbp_plan plan, int *lanes, int *sweep_blocks, int *level_blocks,
                         int *sync_batch);
+
+/*
+ * Layout of the cold/warm relaxation queue (chosen by the autotuner).
+ * split = 1 (default): the vertex range (Morton order) is cut into 512 regions,
+ * region r is queued in sub-queue r mod 8, and the blocks the hardware places on
+ * XCD x serve sub-queue x, so each XCD's L2 caches a fixed eighth of the mesh.
+ * split = 0: one queue served by every block.  Results are the same fixed point.
+ * Errors: GBP_ERR_ARG.
+ */
+int gbp_plan_set_queue_split(gbp_plan plan, int split);
+int gbp_plan_get_queue_split(gbp_plan plan, int *split);
 /* Rounds and levels that carried work in the last synchronous forward/backward. */
 int gbp_plan_last_counts(gbp_plan plan, int *rounds, int *levels);
 

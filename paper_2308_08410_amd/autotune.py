@@ -2,7 +2,8 @@
 
 For a plan and a representative problem it times the eikonal forward (and
 optionally the adjoint) under each candidate configuration -- lanes per vertex
-in a relaxation round, grid of a round, launches between convergence checks -- keeps the
+in a relaxation round, grid of a round, launches between convergence checks,
+queue split over the XCDs or not -- keeps the
 fastest, and records the rounds/levels that carried work so that graph-captured
 iterations can be given launch budgets.  Results are cached in a JSON file
 keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
@@ -17,8 +18,9 @@ import torch
 
 from . import binding as B
 
-SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt)
-         for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048) for bt in (16, 32, 64)]
+SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt, split=sp)
+         for sp in (1, 0) for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048)
+         for bt in (16, 32, 64)]
 LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
 
 
@@ -71,6 +73,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
     if use_cache and key in db:
         rec = db[key]
         B.set_launch(plan, rec["lanes"], rec["sweep_blocks"], rec["level_blocks"], rec.get("sync_batch", 16))
+        B.set_queue_split(plan, rec.get("split", 1))
         return dict(rec, cached=True)
     gT = torch.ones(plan.n_v, dtype=torch.float32, device=D.device)
     T = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
@@ -83,6 +86,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
     best = None
     for cfg in (space or SPACE):
         B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], cfg["level_blocks"], cfg["sync_batch"])
+        B.set_queue_split(plan, cfg["split"])
         run()                                    # warm-up
         ms = _time(run, repeats)
         if best is None or ms < best["ms"]:
@@ -91,11 +95,13 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
         for lb in LEVEL_SPACE:
             cfg = dict(best, level_blocks=lb)
             B.set_launch(plan, cfg["lanes"], cfg["sweep_blocks"], lb, cfg["sync_batch"])
+            B.set_queue_split(plan, cfg["split"])
             run()
             ms = _time(run, repeats)
             if ms < best["ms"]:
                 best = dict(cfg, ms=ms)
     B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"], best["sync_batch"])
+    B.set_queue_split(plan, best["split"])
     run()
     best.update(B.last_counts(plan))
     if save:

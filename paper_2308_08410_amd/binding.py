@@ -91,6 +91,8 @@ _plan_status = _sig("gbp_plan_status", [c_void_p, ctypes.POINTER(c_int), ctypes.
                                         ctypes.POINTER(c_int), c_void_p])
 _set_launch = _sig("gbp_plan_set_launch", [c_void_p, c_int, c_int, c_int, c_int])
 _get_launch = _sig("gbp_plan_get_launch", [c_void_p] + [ctypes.POINTER(c_int)] * 4)
+_set_split = _sig("gbp_plan_set_queue_split", [c_void_p, c_int])
+_get_split = _sig("gbp_plan_get_queue_split", [c_void_p, ctypes.POINTER(c_int)])
 _last_counts = _sig("gbp_plan_last_counts", [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)])
 _batch_create = _sig("gbp_batch_create", [c_void_p, c_int, c_int, ctypes.POINTER(c_void_p)])
 _batch_destroy = _sig("gbp_batch_destroy", [c_void_p], None)
@@ -311,6 +313,17 @@ def get_launch(plan: Plan):
     v = [c_int() for _ in range(4)]
     _check(_get_launch(plan.handle, *[ctypes.byref(x) for x in v]))
     return dict(lanes=v[0].value, sweep_blocks=v[1].value, level_blocks=v[2].value, sync_batch=v[3].value)
+
+
+def set_queue_split(plan: Plan, split=True):
+    """Relaxation queue split into 8 XCD sub-queues (True) or one queue (False)."""
+    _check(_set_split(plan.handle, 1 if split else 0))
+
+
+def get_queue_split(plan: Plan) -> bool:
+    v = c_int()
+    _check(_get_split(plan.handle, ctypes.byref(v)))
+    return bool(v.value)
 
 
 def last_counts(plan: Plan):

@@ -331,9 +331,12 @@ __global__ void __launch_bounds__(TPB)
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
             float eps_rel, int n_v, XcdQueues xq) {
     constexpr int PER_BLOCK = TPB / L;
-    // blocks are placed on the 8 XCDs round-robin: block b serves sub-queue b % 8
-    const int x = blockIdx.x & 7;
-    const int lb = blockIdx.x >> 3, nbx = (gridDim.x + 7 - x) >> 3;
+    // blocks are placed on the 8 XCDs round-robin: with the split layout block b
+    // serves sub-queue b % 8, else every block serves the one queue
+    const bool split = xq.nq == 8;
+    const int x = split ? (blockIdx.x & 7) : 0;
+    const int lb = split ? (blockIdx.x >> 3) : blockIdx.x;
+    const int nbx = split ? (gridDim.x + 7 - x) >> 3 : gridDim.x;
     const int* qx = qin + xq.off[x];
     // the first queue entry of this lane group is loaded before the queue length
     // is known (both loads in flight together); it is used only if it is in the

@@ -69,7 +69,9 @@ constexpr int kXcdRegions = 512;
 struct XcdQueues {
     int off[9];                    // segment of sub-queue x: [off[x], off[x+1])
     int R;                         // vertices per region
+    int nq;                        // 8 (split) or 1 (one queue: R = n_v, every block serves it)
 };
+void gbp_set_queue_layout(gbp_plan p, int split);
 
 struct gbp_plan_s {
     int device = 0;

@@ -293,14 +293,7 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(dalloc(&p->vs, n_v));
     TRY(dalloc(&p->T, n_v));
     TRY(dalloc(&p->troot, n_v));
-    {   // sub-queue segments: region r (R vertices) belongs to sub-queue r % 8
-        const int R = std::max(1, (n_v + kXcdRegions - 1) / kXcdRegions);
-        int cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int r = 0; (long long)r * R < n_v; ++r) cap[r & 7] += std::min(R, n_v - r * R);
-        p->xq.R = R;
-        p->xq.off[0] = 0;
-        for (int x = 0; x < 8; ++x) p->xq.off[x + 1] = p->xq.off[x] + cap[x];
-    }
+    gbp_set_queue_layout(p, 1);
     TRY(dalloc(&p->q[0], n_v));
     TRY(dalloc(&p->q[1], n_v));
     TRY(dalloc(&p->mark, n_v));
@@ -359,6 +352,37 @@ extern "C" int gbp_plan_set_launch(gbp_plan p, int lanes, int sweep_blocks, int 
     p->sweep_blocks = sweep_blocks;
     p->level_blocks = level_blocks;
     p->sync_batch = sync_batch;
+    return GBP_OK;
+}
+
+// Sub-queue layout of the relaxation queues: split (region r of R vertices
+// belongs to sub-queue r % 8) or a single queue.
+void gbp_set_queue_layout(gbp_plan p, int split) {
+    const int n_v = p->n_v;
+    const int R = split ? std::max(1, (n_v + kXcdRegions - 1) / kXcdRegions) : std::max(1, n_v);
+    int cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int r = 0; (long long)r * R < n_v; ++r) cap[r & 7] += std::min(R, n_v - r * R);
+    p->xq.R = R;
+    p->xq.nq = split ? 8 : 1;
+    p->xq.off[0] = 0;
+    for (int x = 0; x < 8; ++x) p->xq.off[x + 1] = p->xq.off[x] + cap[x];
+}
+
+extern "C" int gbp_plan_set_queue_split(gbp_plan p, int split) {
+    if (!p || (split != 0 && split != 1)) {
+        gbp_set_error("set_queue_split: split must be 0 or 1");
+        return GBP_ERR_ARG;
+    }
+    gbp_set_queue_layout(p, split);
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_queue_split(gbp_plan p, int* split) {
+    if (!p || !split) {
+        gbp_set_error("get_queue_split: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    *split = p->xq.nq == 8 ? 1 : 0;
     return GBP_OK;
 }
 

@@ -114,6 +114,23 @@ def test_forward_is_repeatable(shell):
     assert rel_max(T2.cpu().numpy(), shell.T_orc) <= 1e-4
 
 
+@pytest.mark.parametrize("split", [False, True])
+def test_queue_layouts_reach_the_oracle(shell, split):
+    B().set_queue_split(shell.plan, split)
+    assert B().get_queue_split(shell.plan) == split
+    try:
+        T2, st = B().eikonal_forward(shell.plan, shell.D, shell.vs, shell.rn, shell.rt)
+        assert st["converged"]
+        assert rel_max(T2.cpu().numpy(), shell.T_orc) <= 1e-4
+        Tw, stw = B().eikonal_forward(shell.plan, shell.D, shell.vs, shell.rn, shell.rt,
+                                      T_init=torch.as_tensor(1.5 * shell.T_orc + 1.0, dtype=torch.float32,
+                                                             device=shell.dev))
+        assert stw["converged"]
+        assert rel_max(Tw.cpu().numpy(), shell.T_orc) <= 1e-4
+    finally:
+        B().set_queue_split(shell.plan, True)
+
+
 def test_warm_start_converges_to_cold(shell):
     r = np.random.Generator(np.random.PCG64(3))
     T = shell.T_orc
