@@ -65,38 +65,51 @@ __device__ __forceinline__ int xcd_rank(int i, int R) {
     return (r >> 3) * R + (i - r * R);
 }
 
-// Block-level buffer with one section per sub-queue; one atomic per non-empty
-// section and block at flush time (overflow goes straight to global).
-constexpr int kXSec = kPushCap / 8;
-
+// Block-level push buffer: pushes land in LDS (any sub-queue); at flush time the
+// entries are counted per sub-queue, one atomic per non-empty sub-queue reserves
+// room, and the entries are scattered to their sub-queues (overflow goes
+// straight to global).
 struct XPushBuf {
-    int* q;      // LDS [8 * kXSec]
-    int* n;      // LDS [8]
+    int* q;      // LDS [kPushCap]
+    int* n;      // LDS counter
 };
 
 __device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& xq,
                                            int* __restrict__ qout, int* cnt_next) {
-    const int x = xcd_of(v, xq.R);
-    const int pos = atomicAdd(&b.n[x], 1);
-    if (pos < kXSec) {
-        b.q[x * kXSec + pos] = v;
+    const int pos = atomicAdd(b.n, 1);
+    if (pos < kPushCap) {
+        b.q[pos] = v;
     } else {
+        const int x = xcd_of(v, xq.R);
         qout[xq.off[x] + atomicAdd(&cnt_next[x], 1)] = v;
     }
 }
 
+// cnt_sh, base_sh: LDS [8] scratch
 __device__ __forceinline__ void xpush_flush(XPushBuf b, const XcdQueues& xq, int* __restrict__ qout,
-                                            int* cnt_next, int* base_sh) {
+                                            int* cnt_next, int* cnt_sh, int* base_sh) {
+    __syncthreads();
+    const int n = min(*b.n, kPushCap);
+    if (xq.nq == 1) {   // one queue: a single reservation, entries in push order
+        if (threadIdx.x == 0) base_sh[0] = n > 0 ? atomicAdd(&cnt_next[0], n) : 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) qout[base_sh[0] + k] = b.q[k];
+        return;
+    }
+    if (threadIdx.x < 8) cnt_sh[threadIdx.x] = 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) atomicAdd(&cnt_sh[xcd_of(b.q[k], xq.R)], 1);
     __syncthreads();
     if (threadIdx.x < 8) {
-        const int m = min(b.n[threadIdx.x], kXSec);
-        base_sh[threadIdx.x] = m > 0 ? atomicAdd(&cnt_next[threadIdx.x], m) : 0;
+        const int m = cnt_sh[threadIdx.x];
+        base_sh[threadIdx.x] = m > 0 ? xq.off[threadIdx.x] + atomicAdd(&cnt_next[threadIdx.x], m) : 0;
+        cnt_sh[threadIdx.x] = 0;
     }
     __syncthreads();
-    for (int x = 0; x < 8; ++x) {
-        const int m = min(b.n[x], kXSec);
-        for (int k = threadIdx.x; k < m; k += blockDim.x)
-            qout[xq.off[x] + base_sh[x] + k] = b.q[x * kXSec + k];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const int v = b.q[k];
+        const int x = xcd_of(v, xq.R);
+        qout[base_sh[x] + atomicAdd(&cnt_sh[x], 1)] = v;
     }
 }
 
@@ -351,11 +364,11 @@ __global__ void __launch_bounds__(TPB)
     }
     if (lb * PER_BLOCK >= n) return;                // no vertex for this block
     int* cnt_next = ctl->qcnt[(s + 1) % 3];
-    __shared__ int push_q[8 * kXSec];
-    __shared__ int push_n[8], push_base[8];
-    if (threadIdx.x < 8) push_n[threadIdx.x] = 0;
+    __shared__ int push_q[kPushCap];
+    __shared__ int push_n, push_cnt[8], push_base[8];
+    if (threadIdx.x == 0) push_n = 0;
     __syncthreads();
-    const XPushBuf pb{push_q, push_n};
+    const XPushBuf pb{push_q, &push_n};
     const int lane = threadIdx.x & (L - 1);
     const int sub = threadIdx.x / L;                // vertex slot of this lane group
     unsigned long long solves = 0, upd = 0;
@@ -406,7 +419,7 @@ __global__ void __launch_bounds__(TPB)
             }
         }
     }
-    xpush_flush(pb, xq, qout, cnt_next, push_base);
+    xpush_flush(pb, xq, qout, cnt_next, push_cnt, push_base);
     // per-block counters: one writer per slot, no contended atomics
     solves = block_sum_u64(solves);
     upd = block_sum_u64(upd);
