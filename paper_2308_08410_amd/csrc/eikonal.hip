@@ -74,15 +74,33 @@ struct XPushBuf {
     int* n;      // LDS counter
 };
 
+// Overflow of the LDS buffer: the overflowing lanes of a wave reserve global room
+// together, one atomic per sub-queue present among them (a per-lane atomic on one
+// counter serialises the whole wave at L2; fronts of millions of vertices
+// overflow every block).
+__device__ __forceinline__ void xpush_global(int v, const XcdQueues& xq, int* __restrict__ qout,
+                                             int* cnt_next) {
+    const int x = xq.nq == 1 ? 0 : xcd_of(v, xq.R);
+    const unsigned long long below = (1ull << __lane_id()) - 1ull;
+    for (;;) {
+        const int x0 = __builtin_amdgcn_readfirstlane(x);
+        if (x == x0) {
+            const unsigned long long grp = __ballot(1);
+            const int rank = __popcll(grp & below);
+            int base = 0;
+            if (rank == 0) base = atomicAdd(&cnt_next[x0], __popcll(grp));
+            base = __shfl(base, __ffsll((unsigned long long)grp) - 1);
+            qout[xq.off[x0] + base + rank] = v;
+            break;
+        }
+    }
+}
+
 __device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& xq,
                                            int* __restrict__ qout, int* cnt_next) {
     const int pos = atomicAdd(b.n, 1);
-    if (pos < kPushCap) {
-        b.q[pos] = v;
-    } else {
-        const int x = xcd_of(v, xq.R);
-        qout[xq.off[x] + atomicAdd(&cnt_next[x], 1)] = v;
-    }
+    if (pos < kPushCap) b.q[pos] = v;
+    else xpush_global(v, xq, qout, cnt_next);
 }
 
 // cnt_sh, base_sh: LDS [8] scratch
