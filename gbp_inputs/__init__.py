@@ -32,7 +32,7 @@ import scipy.sparse as sp
 
 __all__ = [
     "kuhn_cube", "shell_mesh", "Shell", "mlp_params", "mlp_rows", "MLP_SIZES", "fibre_tensor", "endocardial_nodes",
-    "random_roots", "smooth_field", "sphere_electrodes", "lead_weights",
+    "random_roots", "random_point_roots", "tets_touching", "smooth_field", "sphere_electrodes", "lead_weights",
     "jitter_nodes", "Problem", "cube_problem", "shell_problem", "AP_CUBE",
     "AP_SHELL", "tet_volumes",
 ]
@@ -284,6 +284,27 @@ def random_roots(candidates: np.ndarray, n_roots: int, t_lo: float, t_hi: float,
     nodes = rng.choice(np.asarray(candidates), size=n_roots, replace=False)
     t = rng.uniform(t_lo, t_hi, size=n_roots)
     return nodes.astype(np.int32), t.astype(np.float32)
+
+
+def random_point_roots(xyz: np.ndarray, tets: np.ndarray, candidate_tets: np.ndarray, n_roots: int,
+                       t_lo: float, t_hi: float, seed: int):
+    """Activation sites at points inside elements: n_roots distinct elements
+    drawn from ``candidate_tets``, a point in each with uniform random
+    barycentric coordinates (Dirichlet(1,1,1,1)), onsets t ~ U[t_lo, t_hi].
+    Returns (root_tet int32 [R], root_xyz float32 [R,3], root_t float32 [R])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = rng.choice(np.asarray(candidate_tets), size=n_roots, replace=False)
+    w = rng.dirichlet(np.ones(4), size=n_roots)
+    p = np.einsum("rn,rni->ri", w, np.asarray(xyz, dtype=np.float64)[np.asarray(tets)[k]])
+    t = rng.uniform(t_lo, t_hi, size=n_roots)
+    return k.astype(np.int32), p.astype(np.float32), t.astype(np.float32)
+
+
+def tets_touching(tets: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+    """Indices of the elements with at least one vertex in ``nodes``."""
+    mark = np.zeros(int(np.asarray(tets).max()) + 1, bool)
+    mark[np.asarray(nodes)] = True
+    return np.nonzero(mark[np.asarray(tets)].any(axis=1))[0].astype(np.int32)
 
 
 def smooth_field(xyz: np.ndarray, lo: float, hi: float, seed: int, n_modes: int = 8) -> np.ndarray:

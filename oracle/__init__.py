@@ -14,6 +14,9 @@ Pieces
                                                                   [C, gbp_oracle.c]
 * ``adjoint``          Sec. 2.3: back-propagation along the frozen geodesic parents,
                        Eq. (dto_grad), solved as one sparse linear system
+* ``point_roots`` / ``point_roots_grad`` / ``point_root_adjoint``
+                       roots at points inside elements, Sec. 2.3 Eq. (upwind_xi),
+                       and the chain rule to the point, onset, D and velocity scale
 * ``ecg_forward`` / ``ecg_backward`` / ``ecg_loss``
                        Sec. 2.4: V_l(t) = sum_n B[n,l] U(t - phi_n) with the tanh
                        template, and the objective Eq. (inverse_ecg)
@@ -288,6 +291,97 @@ def adjoint(xyz, tets, D6, vscale, root_node, root_t, T, g, par=None):
     rn = np.atleast_1d(np.asarray(root_node))
     droot = np.where(act, lam[rn], 0.0)
     return dict(lam=lam, dD=dD6, dvscale=dvs, droot_t=droot, par=par)
+
+
+# --------------------------------------------------------------------------
+# roots at points inside elements (Sec. 2.3 Eq. (upwind_xi))
+# --------------------------------------------------------------------------
+def locate_points(xyz, tets, points, tol=1e-12):
+    """Index of an element containing each point (barycentric coordinates all
+    >= -tol; the lowest such index), or -1.  Brute force over all elements."""
+    x = np.asarray(xyz, dtype=np.float64)
+    tets = np.asarray(tets)
+    P = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    v0 = x[tets[:, 0]]
+    E = np.stack([x[tets[:, k]] - v0 for k in (1, 2, 3)], axis=2)      # [n_e,3,3] columns
+    Einv = np.linalg.inv(E)
+    out = np.full(len(P), -1, dtype=np.int64)
+    for r, p in enumerate(P):
+        lam = np.einsum("nij,nj->ni", Einv, p - v0)
+        bary = np.concatenate([1.0 - lam.sum(1, keepdims=True), lam], axis=1)
+        hit = np.nonzero((bary >= -tol).all(axis=1))[0]
+        if len(hit):
+            out[r] = hit[0]
+    return out
+
+
+def point_roots(xyz, tets, D6, vscale, root_tet, root_xyz, root_t):
+    """Eq. (upwind_xi): a root at the point x_i of element E_k with onset t_i
+    gives each vertex v of E_k the value t_i + ||v - x_i|| in the metric of E_k
+    (D_eff^-1 of that element, the step cost of Alg. 2).  Returned as node
+    roots (node ids [4R], onsets [4R]): root i's vertices at 4i..4i+3 in the
+    element's vertex order.  Alg. 2 then keeps the smallest onset of a node."""
+    x = np.asarray(xyz, dtype=np.float64)
+    tets = np.asarray(tets)
+    k = np.asarray(root_tet).reshape(-1)
+    X = np.asarray(root_xyz, dtype=np.float64).reshape(-1, 3)
+    t = np.asarray(root_t, dtype=np.float64).reshape(-1)
+    Minv = unpack_sym(metric_inverse(D6, vscale, tets))[k]            # [R,3,3]
+    e = x[tets[k]] - X[:, None, :]                                     # [R,4,3]
+    h = np.sqrt(np.einsum("rni,rij,rnj->rn", e, Minv, e))
+    return tets[k].reshape(-1), (t[:, None] + h).reshape(-1)
+
+
+def point_roots_grad(xyz, tets, D6, vscale, root_tet, root_xyz, root_t, g_onset):
+    """Chain rule of Eq. (upwind_xi) for a loss with dL/d(onset) = g_onset [4R]
+    on the node roots of ``point_roots``.  With e = v_n - x_i and
+    h = sqrt(e^T D_eff^-1 e) in element k:
+      dL/dt_i  = sum_n g_n,
+      dL/dx_i  = sum_n g_n (-D_eff^-1 e / h)          (the gradient of Sec. 2.3),
+      dL/dD_k += g_n (-sbar^-2 D^-1 e e^T D^-1 / (2h)),
+      dL/dsbar_k += g_n (-h / sbar),  d sbar / d s = 1/4 on the element's nodes.
+    A vertex at the point itself (h = 0) contributes to t_i only.
+    Returns dict(dt [R], dx [R,3], dD [n_e,6] (off-diagonals doubled), dvscale [n_v])."""
+    x = np.asarray(xyz, dtype=np.float64)
+    tets = np.asarray(tets)
+    n_v = len(x)
+    vs = np.ones(n_v) if vscale is None else np.asarray(vscale, dtype=np.float64)
+    k = np.asarray(root_tet).reshape(-1)
+    R = len(k)
+    X = np.asarray(root_xyz, dtype=np.float64).reshape(-1, 3)
+    g = np.asarray(g_onset, dtype=np.float64).reshape(R, 4)
+    D = unpack_sym(D6)
+    Dinv = np.linalg.inv(D[k])                                          # [R,3,3]
+    sbar = mean_scale(vs, tets)[k]                                      # [R]
+    Minv = Dinv / (sbar ** 2)[:, None, None]
+    e = x[tets[k]] - X[:, None, :]                                     # [R,4,3]
+    h = np.sqrt(np.einsum("rni,rij,rnj->rn", e, Minv, e))               # [R,4]
+    pos = h > 0
+    hs = np.where(pos, h, 1.0)
+    dx = -np.einsum("rn,rij,rnj->ri", np.where(pos, g / hs, 0.0), Minv, e)
+    u = np.einsum("rij,rnj->rni", Dinv, e)                              # D^-1 e
+    coef = np.where(pos, g / (sbar[:, None] ** 2 * 2.0 * hs), 0.0)      # [R,4]
+    dD = np.zeros((len(tets), 3, 3))
+    np.add.at(dD, k, -np.einsum("rn,rni,rnj->rij", coef, u, u))
+    dsbar = np.zeros(len(tets))
+    np.add.at(dsbar, k, (g * (-h / sbar[:, None])).sum(axis=1))
+    dvs = np.zeros(n_v)
+    np.add.at(dvs, tets.reshape(-1), np.repeat(dsbar / 4.0, 4))
+    dD6 = pack_sym(dD)
+    dD6[:, 3:] *= 2.0
+    return dict(dt=g.sum(axis=1), dx=dx, dD=dD6, dvscale=dvs)
+
+
+def point_root_adjoint(xyz, tets, D6, vscale, root_tet, root_xyz, root_t, T, g):
+    """Gradients of L = g.T when the roots are points (Eq. (upwind_xi)): the
+    adjoint along the geodesic parents down to the node roots of the containing
+    elements, then the chain rule of ``point_roots_grad``.
+    Returns dict(lam, dD, dvscale, dt, dx)."""
+    nodes, onset = point_roots(xyz, tets, D6, vscale, root_tet, root_xyz, root_t)
+    a = adjoint(xyz, tets, D6, vscale, nodes, onset, T, g)
+    c = point_roots_grad(xyz, tets, D6, vscale, root_tet, root_xyz, root_t, a["droot_t"])
+    return dict(lam=a["lam"], dD=a["dD"] + c["dD"], dvscale=a["dvscale"] + c["dvscale"],
+                dt=c["dt"], dx=c["dx"])
 
 
 # --------------------------------------------------------------------------
