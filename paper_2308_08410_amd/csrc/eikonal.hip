@@ -78,20 +78,24 @@ struct XPushBuf {
 // together, one atomic per sub-queue present among them (a per-lane atomic on one
 // counter serialises the whole wave at L2; fronts of millions of vertices
 // overflow every block).
+// The loop runs over the sub-queues (a wave-uniform bound), one ballot each: a
+// loop that peels lanes by readfirstlane until none is left is not safe here,
+// since the compiler may hoist the readfirstlane and then take the loop to run
+// once for every lane.
 __device__ __forceinline__ void xpush_global(int v, const XcdQueues& xq, int* __restrict__ qout,
                                              int* cnt_next) {
     const int x = xq.nq == 1 ? 0 : xcd_of(v, xq.R);
     const unsigned long long below = (1ull << __lane_id()) - 1ull;
-    for (;;) {
-        const int x0 = __builtin_amdgcn_readfirstlane(x);
-        if (x == x0) {
-            const unsigned long long grp = __ballot(1);
+    for (int xs = 0; xs < xq.nq; ++xs) {
+        const bool mine = x == xs;
+        const unsigned long long grp = __ballot(mine);   // overflowing lanes of sub-queue xs
+        if (grp == 0ull) continue;
+        if (mine) {
             const int rank = __popcll(grp & below);
             int base = 0;
-            if (rank == 0) base = atomicAdd(&cnt_next[x0], __popcll(grp));
+            if (rank == 0) base = atomicAdd(&cnt_next[xs], __popcll(grp));
             base = __shfl(base, __ffsll((unsigned long long)grp) - 1);
-            qout[xq.off[x0] + base + rank] = v;
-            break;
+            qout[xq.off[xs] + base + rank] = v;
         }
     }
 }

@@ -117,3 +117,31 @@ def test_full_forward_parity(full):
 
 def test_full_ecg_and_gradients(full):
     full.ecg_and_backward(calibrate=True)
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_full_forward_with_push_overflow(full, split):
+    """A 64-block grid makes every block's LDS push buffer overflow in the first
+    rounds of a two-sided warm solve (all 500k vertices queued, ~7.8k per
+    block): the overflow path of both queue layouts must keep every vertex it
+    queues, so the warm solve (from a perturbed guess) and the cold solve both
+    reach the stored oracle times."""
+    plan = full.plan
+    saved = B().get_launch(plan)
+    saved_split = B().get_queue_split(plan)
+    B().set_launch(plan, 16, 64, saved["level_blocks"], 16)
+    B().set_queue_split(plan, split)
+    try:
+        r = np.random.Generator(np.random.PCG64(11))
+        guess = t32(full.T_ref * (1.0 + 0.02 * r.uniform(-1.0, 1.0, size=len(full.T_ref))), full.dev)
+        print(f"[overflow] split={split} warm", flush=True)
+        T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt, T_init=guess)
+        assert st["converged"]
+        assert rel_max(T.cpu().numpy(), full.T_ref) <= 1e-4
+        print(f"[overflow] split={split} cold", flush=True)
+        T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt)
+        assert st["converged"]
+        assert rel_max(T.cpu().numpy(), full.T_ref) <= 1e-4
+    finally:
+        B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
+        B().set_queue_split(plan, saved_split)
