@@ -170,6 +170,50 @@ def warm_single_form(st, prob, steps, torch, B, autotune):
                 converged=bool(status["forward_converged"] and status["backward_settled"]), budgets=bud)
 
 
+def point_root_form(st, prob, steps, torch, gi, B, n_points=100, seed=41):
+    """The same 500k iteration with its roots at points inside endocardial
+    elements (Sec. 2.3 Eq. (upwind_xi); the paper fits 100 root points): the
+    points, their onsets and the velocity scale are fitted.  One step: vertex
+    onsets of the points, cold forward, ECG, loss, ECG backward, adjoint, the
+    chain rule to the points, three Adam updates."""
+    import numpy as np
+    dev = st["D"].device
+    plan, D = st["plan"], st["D"]
+    cand = gi.tets_touching(prob.tets, prob.extra["endo"])
+    k, X, t = gi.random_point_roots(prob.xyz, prob.tets, cand, n_points, 0.0, 20.0, seed=seed)
+    f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    s = dict(k=torch.as_tensor(k, device=dev), X=f32(X), t=f32(t), vs=f32(np.ones(prob.n_v)))
+    for name in ("X", "t", "vs"):
+        s["m_" + name] = torch.zeros_like(s[name])
+        s["v_" + name] = torch.zeros_like(s[name])
+
+    def step(kk):
+        node, onset = B.point_roots(plan, D, s["vs"], s["k"], s["X"], s["t"])
+        T, stats = B.eikonal_forward(plan, D, s["vs"], node, onset)
+        ecg = B.ecg_forward(T, st["W"], st["ap"])
+        loss, G = B.ecg_loss(ecg, st["target"])
+        gT = B.ecg_backward(T, st["W"], st["ap"], G)
+        _, dvs, donset = B.eikonal_backward(plan, D, s["vs"], node, onset, T, gT, want_D=False)
+        dt, dx = B.point_roots_backward(plan, D, s["vs"], s["k"], s["X"], donset, dL_dvscale=dvs)
+        B.adam_step(s["vs"], dvs, s["m_vs"], s["v_vs"], kk, lr=0.01, lo=0.2, hi=5.0)
+        B.adam_step(s["t"], dt, s["m_t"], s["v_t"], kk, lr=0.5)
+        B.adam_step(s["X"], dx, s["m_X"], s["v_X"], kk, lr=0.01)
+        return loss, stats
+
+    for kk in range(1, 3):
+        step(kk)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for kk in range(3, 3 + steps):
+        loss, stats = step(kk)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return dict(points=n_points, iters_per_s=1000.0 / ms, ms_per_step=ms, rounds=stats["rounds"],
+                loss=float(loss[0]))
+
+
 def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed=31):
     """Many uneven meshes and parameter sets as one union plan, one HIP-graph
     replay per iteration for all instances (forward -- cold, then warm-started
@@ -377,6 +421,12 @@ def main():
         detail["warm_single_500k"] = ws
         log(f"[bench] warm single form: {ws['iters_per_s']:.1f} iter/s (x{ws['speedup_vs_plain']:.2f}), "
             f"max rel T vs cold {ws['max_rel_T_vs_cold']:.1e} ({time.time() - t:.1f}s)")
+        t = time.time()
+        pf = point_root_form(st, prob, args.form_steps, torch, gi, B)
+        pf["speedup_vs_plain"] = pf["iters_per_s"] / (1000.0 / ms)
+        detail["point_roots_500k"] = pf
+        log(f"[bench] point-root form ({pf['points']} points): {pf['iters_per_s']:.1f} iter/s "
+            f"(x{pf['speedup_vs_plain']:.2f}), {pf['rounds']} rounds ({time.time() - t:.1f}s)")
         t = time.time()
         bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
         for k in ("cold", "warm"):

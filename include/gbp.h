@@ -137,6 +137,60 @@ int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
                          float *dL_dvscale, float *dL_droot_t, void *stream);
 
 /*
+ * gbp_point_roots -- initial conditions at points inside elements (Sec. 2.3
+ * Eq. (upwind_xi)): a root at the point x_r of element E_k with onset t_r
+ * gives each vertex v of E_k the onset t_r + sqrt((v - x_r)^T D_eff,k^-1 (v - x_r))
+ * (the step cost of the forward in that element).  The 4 n_roots results are
+ * vertex roots for gbp_eikonal_forward / gbp_eikonal_backward (a vertex named
+ * by several takes the smallest onset).
+ *   D, vscale  as for the forward (D_eff,k = sbar_k^2 D_k)
+ *   root_tet   device int32 [n_roots]     caller element id holding each point
+ *   root_xyz   device float [n_roots*3]   the points
+ *   root_t     device float [n_roots]     onsets
+ *   node_out   device int32 [4*n_roots]   caller vertex ids, root r at 4r..4r+3 in
+ *                                         the element's vertex order
+ *   t_out      device float [4*n_roots]   their onsets
+ * Asynchronous.  An element id out of range gives vertex ids -1 (the forward
+ * then returns GBP_ERR_ARG); non-finite points or onsets give non-finite
+ * onsets (the forward returns GBP_ERR_NONFINITE).  Errors here: GBP_ERR_ARG
+ * (n_roots < 0, missing pointers), GBP_ERR_HIP.
+ */
+int gbp_point_roots(gbp_plan plan, const float *D, const float *vscale, const int32_t *root_tet,
+                    const float *root_xyz, const float *root_t, int n_roots, int32_t *node_out,
+                    float *t_out, void *stream);
+
+/*
+ * gbp_point_roots_backward -- chain rule of gbp_point_roots (the gradient of
+ * Sec. 2.3: d onset / d x_r = -D_eff^-1 e / |e|, e = v - x_r; d onset / d t_r = 1;
+ * and the metric's dependence on D_k and the nodal scales, as in the backward).
+ *   dL_donset     device float [4*n_roots]  e.g. gbp_eikonal_backward's
+ *                                           dL_droot_t for the vertex roots
+ *   dL_droot_t    device float [n_roots]    or NULL, overwritten
+ *   dL_droot_xyz  device float [n_roots*3]  or NULL, overwritten
+ *   dL_dD         device float [n_e*6]      or NULL, ACCUMULATED (off-diagonals
+ *                                           doubled, as in the backward)
+ *   dL_dvscale    device float [n_v]        or NULL, ACCUMULATED
+ * A vertex at the point itself contributes to dL_droot_t only.  Roots sharing
+ * an element or a vertex accumulate in unspecified order (rounding only).
+ * Elements out of range give zero gradients.  Errors: as gbp_point_roots.
+ */
+int gbp_point_roots_backward(gbp_plan plan, const float *D, const float *vscale,
+                             const int32_t *root_tet, const float *root_xyz, int n_roots,
+                             const float *dL_donset, float *dL_droot_t, float *dL_droot_xyz,
+                             float *dL_dD, float *dL_dvscale, void *stream);
+
+/*
+ * gbp_locate_points -- the element holding each point (for roots given by
+ * position): the lowest caller element id whose barycentric coordinates of the
+ * point are all >= -tol (FP32), or -1 if none.
+ *   points   device float [n_points*3];  tet_out  device int32 [n_points]
+ * Brute force over all elements (n_e x n_points tests).  Errors: GBP_ERR_ARG
+ * (n_points < 0, tol < 0, missing pointers), GBP_ERR_HIP.
+ */
+int gbp_locate_points(gbp_plan plan, const float *points, int n_points, float tol,
+                      int32_t *tet_out, void *stream);
+
+/*
  * gbp_backward_info -- diagnostics of the last gbp_eikonal_backward on this
  * plan.  The adjoint walks the parent graph leaves-first in levels; two vertices
  * that are each other's weighted parents (possible in anisotropic media, where

@@ -4,6 +4,8 @@
 sweep of Alg. 2 (Sec. 2.3, Sec. 2.5): its forward keeps only the inputs and the
 converged activation times; its backward recomputes the geodesic parents from
 them (they are never stored) and solves the adjoint system along those parents.
+``PointRootsFn`` turns roots at points inside elements into vertex roots
+(Sec. 2.3 Eq. (upwind_xi)) and carries their gradient to the points.
 ``EcgFn`` and ``EcgLossFn`` wrap the lead-field ECG (Sec. 2.4) and the misfit of
 Eq. (inverse_ecg).  All arithmetic runs in libgbp's HIP kernels on torch's
 current stream.
@@ -37,6 +39,36 @@ class EikonalFn(torch.autograd.Function):
                                          want_D=need[1], want_vscale=need[2] and vscale is not None,
                                          want_root_t=need[4])
         return None, dD, dvs, None, dt, None
+
+
+class PointRootsFn(torch.autograd.Function):
+    """node, onset = PointRootsFn.apply(plan, D, vscale, root_tet, root_xyz, root_t).
+
+    Roots at points inside elements (Sec. 2.3 Eq. (upwind_xi)) as vertex roots
+    for ``EikonalFn``; differentiable w.r.t. D, vscale, root_xyz and root_t (the
+    gradient w.r.t. the point is the one the paper derives from Eq. (upwind_xi))."""
+
+    @staticmethod
+    def forward(ctx, plan, D, vscale, root_tet, root_xyz, root_t):
+        node, onset = B.point_roots(plan, D, vscale, root_tet, root_xyz, root_t)
+        ctx.plan = plan
+        ctx.save_for_backward(D, vscale, root_tet, root_xyz)
+        ctx.mark_non_differentiable(node)
+        return node, onset
+
+    @staticmethod
+    def backward(ctx, g_node, g_onset):
+        D, vscale, root_tet, root_xyz = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        plan = ctx.plan
+        dD = torch.zeros((plan.n_e, 6), dtype=torch.float32, device=D.device) if need[1] else None
+        dvs = (torch.zeros(plan.n_v, dtype=torch.float32, device=D.device)
+               if need[2] and vscale is not None else None)
+        if g_onset is None:
+            g_onset = torch.zeros(4 * root_tet.numel(), dtype=torch.float32, device=D.device)
+        dt, dx = B.point_roots_backward(plan, D, vscale, root_tet, root_xyz, g_onset.contiguous(), dL_dD=dD,
+                                        dL_dvscale=dvs, want_t=need[5], want_xyz=need[4])
+        return None, dD, dvs, None, dx, dt
 
 
 class EcgFn(torch.autograd.Function):
@@ -73,6 +105,10 @@ class EcgLossFn(torch.autograd.Function):
 
 def eikonal(plan, D, vscale, root_node, root_t, T_init=None):
     return EikonalFn.apply(plan, D, vscale, root_node, root_t, T_init)
+
+
+def point_roots(plan, D, vscale, root_tet, root_xyz, root_t):
+    return PointRootsFn.apply(plan, D, vscale, root_tet, root_xyz, root_t)
 
 
 def ecg(T, W, ap):

@@ -105,6 +105,12 @@ _ecg_loss_b = _sig("gbp_ecg_loss_batched", [c_void_p, c_void_p, c_int, c_int, c_
 _step_create = _sig("gbp_step_create", [c_void_p, ctypes.POINTER(c_void_p)])
 _step_launch = _sig("gbp_step_launch", [c_void_p, c_void_p])
 _step_destroy = _sig("gbp_step_destroy", [c_void_p], None)
+_point_roots = _sig("gbp_point_roots", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                        c_void_p, c_void_p, c_void_p])
+_point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                                     c_void_p])
+_locate = _sig("gbp_locate_points", [c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p])
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -257,6 +263,52 @@ def parent_map(plan: Plan, D, vscale, root_node, root_t, T, stream=None):
                     _ptr(T, torch.float32, (n_v,), "T"), pt.data_ptr(), pn.data_ptr(), pa.data_ptr(),
                     best.data_ptr(), _stream(stream)))
     return pt, pn, pa, best
+
+
+def point_roots(plan: Plan, D, vscale, root_tet, root_xyz, root_t, stream=None):
+    """Vertex roots of roots at points inside elements (Sec. 2.3 Eq. (upwind_xi)).
+    Returns (node int32 [4R] caller vertex ids, onset float32 [4R])."""
+    R = root_tet.numel()
+    dev = root_xyz.device
+    node = torch.empty(4 * R, dtype=torch.int32, device=dev)
+    onset = torch.empty(4 * R, dtype=torch.float32, device=dev)
+    _check(_point_roots(plan.handle, _ptr(D, torch.float32, (plan.n_e, 6), "D"),
+                        _ptr(vscale, torch.float32, (plan.n_v,), "vscale"),
+                        _ptr(root_tet, torch.int32, (R,), "root_tet"),
+                        _ptr(root_xyz, torch.float32, (R, 3), "root_xyz"),
+                        _ptr(root_t, torch.float32, (R,), "root_t"), R,
+                        _ptr(node, torch.int32, (4 * R,), "node_out"),
+                        _ptr(onset, torch.float32, (4 * R,), "t_out"), _stream(stream)))
+    return node, onset
+
+
+def point_roots_backward(plan: Plan, D, vscale, root_tet, root_xyz, dL_donset, dL_dD=None, dL_dvscale=None,
+                         want_t=True, want_xyz=True, stream=None):
+    """Chain rule of ``point_roots``: returns (dL/droot_t [R] or None, dL/droot_xyz [R,3] or None)
+    and ADDS the element-tensor and velocity-scale parts into dL_dD / dL_dvscale if given."""
+    R = root_tet.numel()
+    dev = root_xyz.device
+    dt = torch.empty(R, dtype=torch.float32, device=dev) if want_t else None
+    dx = torch.empty((R, 3), dtype=torch.float32, device=dev) if want_xyz else None
+    _check(_point_roots_bwd(plan.handle, _ptr(D, torch.float32, (plan.n_e, 6), "D"),
+                            _ptr(vscale, torch.float32, (plan.n_v,), "vscale"),
+                            _ptr(root_tet, torch.int32, (R,), "root_tet"),
+                            _ptr(root_xyz, torch.float32, (R, 3), "root_xyz"), R,
+                            _ptr(dL_donset, torch.float32, (4 * R,), "dL_donset"),
+                            _ptr(dt, torch.float32, (R,), "dL_droot_t"),
+                            _ptr(dx, torch.float32, (R, 3), "dL_droot_xyz"),
+                            _ptr(dL_dD, torch.float32, (plan.n_e, 6), "dL_dD"),
+                            _ptr(dL_dvscale, torch.float32, (plan.n_v,), "dL_dvscale"), _stream(stream)))
+    return dt, dx
+
+
+def locate_points(plan: Plan, points, tol=1e-6, stream=None):
+    """Caller element id holding each point (lowest id within barycentric tolerance) or -1."""
+    n = points.shape[0]
+    out = torch.empty(n, dtype=torch.int32, device=points.device)
+    _check(_locate(plan.handle, _ptr(points, torch.float32, (n, 3), "points"), n, float(tol),
+                   _ptr(out, torch.int32, (n,), "tet_out"), _stream(stream)))
+    return out
 
 
 def ecg_forward(T, W, ap: AP, out=None, stream=None):

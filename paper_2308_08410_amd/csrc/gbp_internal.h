@@ -84,6 +84,7 @@ struct gbp_plan_s {
     float4* xyz = nullptr;        // [n_v]  (x, y, z, 0)
     int4* tetv = nullptr;         // [n_e]  internal vertex ids
     int* tet_user = nullptr;      // [n_e]  internal element -> caller element id
+    int* tet_int = nullptr;       // [n_e]  caller element id -> internal element
     int* node_user = nullptr;     // [n_v]  internal node -> caller node id
     int* node_int = nullptr;      // [n_v]  caller node id -> internal node
     int2* nptr = nullptr;         // [n_v]  (first entry, 4 packed 8-bit counts per local slot)

@@ -68,7 +68,7 @@ static int dalloc(T** dst, size_t n) {
 
 static void plan_free(gbp_plan p) {
     if (!p) return;
-    void* ptrs[] = {p->xyz, p->tetv, p->tet_user, p->node_user, p->node_int, p->nptr, p->nent,
+    void* ptrs[] = {p->xyz, p->tetv, p->tet_user, p->tet_int, p->node_user, p->node_int, p->nptr, p->nent,
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
                     p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp,
@@ -208,6 +208,8 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
                      [&](int a, int b) { return tmin[a] < tmin[b]; });
     std::vector<int4> tvs(n_e);
     for (int j = 0; j < n_e; ++j) tvs[j] = tv[tet_user[j]];
+    std::vector<int> tet_int(n_e);
+    for (int j = 0; j < n_e; ++j) tet_int[tet_user[j]] = j;
 
     // ---- incidence CSR by (node, slot, element)
     std::vector<int> cnt((size_t)n_v * 4, 0);
@@ -283,6 +285,7 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(upload(&p->xyz, x4.data(), n_v));
     TRY(upload(&p->tetv, tvs.data(), n_e));
     TRY(upload(&p->tet_user, tet_user.data(), n_e));
+    TRY(upload(&p->tet_int, tet_int.data(), n_e));
     TRY(upload(&p->node_user, node_user.data(), n_v));
     TRY(upload(&p->node_int, node_int.data(), n_v));
     TRY(upload(&p->nptr, nptr.data(), n_v));
