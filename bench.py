@@ -214,6 +214,54 @@ def point_root_form(st, prob, steps, torch, gi, B, n_points=100, seed=41):
                 loss=float(loss[0]))
 
 
+def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
+    """The forward with the paper's own local solver (FISTA, Alg. 1, tightened
+    step constant) against the exact predicated solve on the same 500k problem:
+    forward time and max relative deviation from the exact solve per iteration
+    count, and the cost of one local problem for each solver (a batch of seeded
+    random faces)."""
+    import numpy as np
+    plan, D, vs, rn, rt = st["plan"], st["D"], st["vs"], st["rn"], st["rt"]
+    dev = D.device
+
+    def timed(fn, k=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k, out
+
+    ms_e, (Te, se) = timed(lambda: B.eikonal_forward(plan, D, vs, rn, rt))
+    Te = Te.clone()
+    fin = torch.isfinite(Te)
+    runs = []
+    try:
+        for n_f in (32, 64, 128):
+            B.set_local_solver(plan, "fista", n_f, "tight")
+            ms, (Tf, sf) = timed(lambda: B.eikonal_forward(plan, D, vs, rn, rt))
+            err = float((Tf[fin] - Te[fin]).abs().max() / Te[fin].abs().max())
+            runs.append(dict(n_f=n_f, forward_ms=ms, rel_max_vs_exact=err, rounds=sf["rounds"],
+                             slowdown_vs_exact=ms / ms_e))
+    finally:
+        B.set_local_solver(plan, "exact")
+    r = np.random.Generator(np.random.PCG64(seed))
+    A = r.normal(size=(n_faces, 3, 3)).astype(np.float32)
+    Q = np.einsum("nki,nkj->nij", A, A) + 0.1 * np.eye(3, dtype=np.float32)
+    Q6 = torch.as_tensor(np.stack([Q[:, 0, 0], Q[:, 1, 1], Q[:, 2, 2], Q[:, 0, 1], Q[:, 0, 2], Q[:, 1, 2]], 1),
+                         device=dev).contiguous()
+    Phi = torch.as_tensor(r.uniform(0, 1, size=(n_faces, 3)).astype(np.float32), device=dev)
+    lip = B.local_solve(Q6, Phi, "fista", n_f=1, want_alpha=False, want_lip=True)[2]
+    per_face = {"exact": timed(lambda: B.local_solve(Q6, Phi, "exact", want_alpha=False))[0] * 1e6 / n_faces}
+    for n_f in (16, 32, 64, 128):
+        per_face[f"fista_{n_f}"] = timed(lambda: B.local_solve(Q6, Phi, "fista", n_f=n_f, lip=lip,
+                                                               want_alpha=False))[0] * 1e6 / n_faces
+    return dict(exact_forward_ms=ms_e, exact_rounds=se["rounds"], runs=runs, ns_per_local_problem=per_face)
+
+
 def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed=31):
     """Many uneven meshes and parameter sets as one union plan, one HIP-graph
     replay per iteration for all instances (forward -- cold, then warm-started
@@ -427,6 +475,12 @@ def main():
         detail["point_roots_500k"] = pf
         log(f"[bench] point-root form ({pf['points']} points): {pf['iters_per_s']:.1f} iter/s "
             f"(x{pf['speedup_vs_plain']:.2f}), {pf['rounds']} rounds ({time.time() - t:.1f}s)")
+        t = time.time()
+        fs = fista_form(st, torch, B)
+        detail["fista_500k"] = fs
+        log("[bench] FISTA local solver: " + ", ".join(
+            f"n_f={x['n_f']}: {x['forward_ms']:.1f} ms (x{x['slowdown_vs_exact']:.1f}), dev {x['rel_max_vs_exact']:.1e}"
+            for x in fs["runs"]) + f"; exact {fs['exact_forward_ms']:.2f} ms ({time.time() - t:.1f}s)")
         t = time.time()
         bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
         for k in ("cold", "warm"):

@@ -137,6 +137,42 @@ int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
                          float *dL_dvscale, float *dL_droot_t, void *stream);
 
 /*
+ * gbp_plan_set_local_solver / gbp_plan_get_local_solver -- the local solver of
+ * the forward's relaxation rounds:
+ *   solver          0: exact minimum (all KKT candidates of the local problem,
+ *                      Sec. 2.2 Eq. (upwind_eq_lsqr), predicated; the default)
+ *                   1: n_f iterations of FISTA (Alg. 1) from alpha = 1/3, step
+ *                      1/L per face with L from Eq. (lipschitz_est)
+ *   n_f             FISTA iterations, 1..100000 (solver 1)
+ *   lipschitz_mode  0: the lower bound h_ = sigma_min(A)/(3 sqrt 3) of Eq.
+ *                      (lipschitz_est); 1: the tightened h_ = h(alpha*_0)/1.1 of
+ *                      Sec. 2.5 (default)
+ * FISTA values are feasible points, so they are never below the exact minimum:
+ * the solve converges to activation times at or above the exact scheme's, closer
+ * with more iterations.  The backward always uses the exact parents.
+ * Errors: GBP_ERR_ARG for values outside those ranges, GBP_ERR_NOMEM.
+ */
+int gbp_plan_set_local_solver(gbp_plan plan, int solver, int n_f, int lipschitz_mode);
+int gbp_plan_get_local_solver(gbp_plan plan, int *solver, int *n_f, int *lipschitz_mode);
+
+/*
+ * gbp_local_solve -- n independent local problems (Sec. 2.2 Eq.
+ * (upwind_eq_lsqr)): min over the simplex of <alpha, Phi> + sqrt(alpha^T Q alpha).
+ *   Q6       device float [n*6]  Q = E^T D_eff^-1 E packed (q00, q11, q22, q01, q02, q12)
+ *   Phi      device float [n*3]  face values (+inf: unreached, weight zero)
+ *   solver   0 exact, 1 FISTA (Alg. 1) with n_f iterations
+ *   lip      device float [n] or NULL: FISTA step constants; NULL computes them
+ *            with lipschitz_mode as in gbp_plan_set_local_solver
+ *   value    device float [n]      the minimum (FISTA: the value at alpha_{n_f})
+ *   alpha    device float [n*3] or NULL   the minimiser (FISTA: alpha_{n_f})
+ *   lip_out  device float [n] or NULL     the step constants used (solver 1)
+ * Errors: GBP_ERR_ARG (sizes, solver, n_f, mode, missing pointers), GBP_ERR_HIP.
+ */
+int gbp_local_solve(const float *Q6, const float *Phi, int n, int solver, int n_f,
+                    const float *lip, int lipschitz_mode, float *value, float *alpha,
+                    float *lip_out, void *stream);
+
+/*
  * gbp_point_roots -- initial conditions at points inside elements (Sec. 2.3
  * Eq. (upwind_xi)): a root at the point x_r of element E_k with onset t_r
  * gives each vertex v of E_k the onset t_r + sqrt((v - x_r)^T D_eff,k^-1 (v - x_r))

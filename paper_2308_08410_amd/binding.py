@@ -111,6 +111,10 @@ _point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_
                                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                      c_void_p])
 _locate = _sig("gbp_locate_points", [c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p])
+_set_solver = _sig("gbp_plan_set_local_solver", [c_void_p, c_int, c_int, c_int])
+_get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
+_local_solve = _sig("gbp_local_solve", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p,
+                                        c_void_p, c_void_p, c_void_p])
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -370,6 +374,38 @@ def get_launch(plan: Plan):
 def set_queue_split(plan: Plan, split=True):
     """Relaxation queue split into 8 XCD sub-queues (True) or one queue (False)."""
     _check(_set_split(plan.handle, 1 if split else 0))
+
+
+def set_local_solver(plan: Plan, solver="exact", n_f=32, lipschitz="tight"):
+    """Local solver of the forward: "exact" (predicated KKT) or "fista" (Alg. 1, n_f
+    iterations, step constant from Eq. (lipschitz_est) with the "bound" or the
+    "tight" lower bound of h)."""
+    s = {"exact": 0, "fista": 1}[solver]
+    m = {"bound": 0, "tight": 1}[lipschitz]
+    _check(_set_solver(plan.handle, s, int(n_f), m))
+
+
+def get_local_solver(plan: Plan):
+    v = [c_int() for _ in range(3)]
+    _check(_get_solver(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(solver=("exact", "fista")[v[0].value], n_f=v[1].value,
+                lipschitz=("bound", "tight")[v[2].value])
+
+
+def local_solve(Q6, Phi, solver="exact", n_f=32, lip=None, lipschitz="tight", want_alpha=True,
+                want_lip=False, stream=None):
+    """n independent local problems: returns (value [n], alpha [n,3] or None, lip [n] or None)."""
+    n = Q6.shape[0]
+    dev = Q6.device
+    val = torch.empty(n, dtype=torch.float32, device=dev)
+    al = torch.empty((n, 3), dtype=torch.float32, device=dev) if want_alpha else None
+    lo = torch.empty(n, dtype=torch.float32, device=dev) if want_lip else None
+    _check(_local_solve(_ptr(Q6, torch.float32, (n, 6), "Q6"), _ptr(Phi, torch.float32, (n, 3), "Phi"), n,
+                        {"exact": 0, "fista": 1}[solver], int(n_f), _ptr(lip, torch.float32, (n,), "lip"),
+                        {"bound": 0, "tight": 1}[lipschitz], _ptr(val, torch.float32, (n,), "value"),
+                        _ptr(al, torch.float32, (n, 3), "alpha"), _ptr(lo, torch.float32, (n,), "lip_out"),
+                        _stream(stream)))
+    return val, al, lo
 
 
 def get_queue_split(plan: Plan) -> bool:

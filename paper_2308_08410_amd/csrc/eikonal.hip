@@ -22,6 +22,7 @@
 
 #include "gbp_internal.h"
 #include "local_solve.h"
+#include "fista.h"
 #include "profile.h"
 
 namespace {
@@ -319,6 +320,15 @@ __global__ void k_forward_end(GbpCtl* ctl, int launched) {
     }
 }
 
+// Step constant of Alg. 1 for every face (4 per element, face K of element t at 4t + K).
+__global__ void k_fista_lip(const float4* __restrict__ tetg, int n_e, int mode,
+                            float* __restrict__ lip) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4LL * n_e) return;
+    const long long t = i >> 2;
+    lip[i] = fista_lipschitz(face_q_rt(tetg[2 * t], tetg[2 * t + 1], (int)(i & 3)), mode);
+}
+
 __global__ void k_fill_i(int* __restrict__ x, int v, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
 }
@@ -345,26 +355,30 @@ __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restric
 // 32, autotuned); lane c evaluates local problems c and c+L of the vertex's patch (slot picked at run
 // time, both problems' loads in flight together), a 16-lane min-reduction forms
 // the Hopf-Lax minimum, and on a change the lanes push the unique neighbours.
+// SOLVER 0: the exact predicated solve; 1: n_f iterations of Alg. 1 with the
+// face's step constant lip[4 t + K].
+template <int SOLVER>
 __device__ __forceinline__ float face_value(const int* __restrict__ nent,
                                             const int4* __restrict__ tetv,
                                             const float4* __restrict__ tetg, const float* T,
-                                            int e, int K) {
+                                            int e, int K, const float* __restrict__ lip, int n_f) {
     const int t = nent[e];
     const int4 v = tetv[t];
     const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
     int a, b, cc;
     face_nodes_sel(v, K, a, b, cc);
-    return local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]);
+    if constexpr (SOLVER == 0) return local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]);
+    else return local_fista<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc], lip[4 * (size_t)t + K], n_f);
 }
 
-template <bool TWO_SIDED, int L>
+template <bool TWO_SIDED, int L, int SOLVER>
 __global__ void __launch_bounds__(TPB)
     k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
-            float eps_rel, int n_v, XcdQueues xq) {
+            float eps_rel, int n_v, XcdQueues xq, const float* __restrict__ lip, int n_f) {
     constexpr int PER_BLOCK = TPB / L;
     // blocks are placed on the 8 XCDs round-robin: with the split layout block b
     // serves sub-queue b % 8, else every block serves the one queue
@@ -413,8 +427,9 @@ __global__ void __launch_bounds__(TPB)
             const bool okd = d < tot;
             const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
             const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
-            const float vc = face_value(nent, tetv, tetg, T, p.x + c, Kc);
-            const float vd = face_value(nent, tetv, tetg, T, p.x + (okd ? d : c), okd ? Kd : Kc);
+            const float vc = face_value<SOLVER>(nent, tetv, tetg, T, p.x + c, Kc, lip, n_f);
+            const float vd = face_value<SOLVER>(nent, tetv, tetg, T, p.x + (okd ? d : c),
+                                                okd ? Kd : Kc, lip, n_f);
             best = fminf(best, okd ? fminf(vc, vd) : vc);
             solves += okd ? 2 : 1;
         }
@@ -1226,6 +1241,9 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
         ProfScope ps(GBP_PROF_METRIC, s);
         k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs,
                                                       p->tetg, n_e, p->ctl);
+        if (p->solver == 1 && cold != 2)   // step constants of Alg. 1, per face
+            k_fista_lip<<<gbp_blocks(4LL * n_e, TPB), TPB, 0, s>>>(p->tetg, n_e, p->fista_lmode,
+                                                                   p->lip);
     }
     k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, GBP_INF, n_v);
     if (cold == 1)
@@ -1244,19 +1262,25 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
     int* qout = p->q[(r + 1) & 1];
     const int grid = std::min(p->sweep_blocks, kStatBlocks);
     ProfScope ps(GBP_PROF_FIM_SWEEP, s);
-#define GBP_SWEEP(TS, LN)                                                                       \
-    k_sweep<TS, LN><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, qin, \
-                                         qout, p->adj_ptr, p->adj, p->mark, p->ctl, p->blk, r,   \
-                                         p->eps_rel, p->n_v, p->xq)
-    if (cold) {
-        if (p->lanes == 8) GBP_SWEEP(false, 8);
-        else if (p->lanes == 32) GBP_SWEEP(false, 32);
-        else GBP_SWEEP(false, 16);
+#define GBP_SWEEP(TS, LN, SV)                                                                   \
+    k_sweep<TS, LN, SV><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, \
+                                             qin, qout, p->adj_ptr, p->adj, p->mark, p->ctl,     \
+                                             p->blk, r, p->eps_rel, p->n_v, p->xq, p->lip,       \
+                                             p->fista_iters)
+#define GBP_SWEEP_LANES(TS, SV)                         \
+    do {                                                \
+        if (p->lanes == 8) GBP_SWEEP(TS, 8, SV);        \
+        else if (p->lanes == 32) GBP_SWEEP(TS, 32, SV); \
+        else GBP_SWEEP(TS, 16, SV);                     \
+    } while (0)
+    if (p->solver == 1) {
+        if (cold) GBP_SWEEP_LANES(false, 1);
+        else GBP_SWEEP_LANES(true, 1);
     } else {
-        if (p->lanes == 8) GBP_SWEEP(true, 8);
-        else if (p->lanes == 32) GBP_SWEEP(true, 32);
-        else GBP_SWEEP(true, 16);
+        if (cold) GBP_SWEEP_LANES(false, 0);
+        else GBP_SWEEP_LANES(true, 0);
     }
+#undef GBP_SWEEP_LANES
 #undef GBP_SWEEP
 }
 

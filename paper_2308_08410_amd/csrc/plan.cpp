@@ -71,7 +71,7 @@ static void plan_free(gbp_plan p) {
     void* ptrs[] = {p->xyz, p->tetv, p->tet_user, p->tet_int, p->node_user, p->node_int, p->nptr, p->nent,
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
-                    p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp,
+                    p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp, p->lip,
                     p->pnode, p->partner, p->pairrem};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -377,6 +377,30 @@ extern "C" int gbp_plan_set_queue_split(gbp_plan p, int split) {
         return GBP_ERR_ARG;
     }
     gbp_set_queue_layout(p, split);
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_local_solver(gbp_plan p, int solver, int n_f, int lipschitz_mode) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if ((solver != 0 && solver != 1) || n_f < 1 || n_f > 100000 ||
+        (lipschitz_mode != 0 && lipschitz_mode != 1)) {
+        gbp_set_error("set_local_solver: solver 0 or 1, n_f 1..100000, lipschitz_mode 0 or 1");
+        return GBP_ERR_ARG;
+    }
+    if (solver == 1 && !p->lip && (rc = dalloc(&p->lip, (size_t)4 * p->n_e))) return rc;
+    p->solver = solver;
+    p->fista_iters = n_f;
+    p->fista_lmode = lipschitz_mode;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_local_solver(gbp_plan p, int* solver, int* n_f, int* lipschitz_mode) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (solver) *solver = p->solver;
+    if (n_f) *n_f = p->fista_iters;
+    if (lipschitz_mode) *lipschitz_mode = p->fista_lmode;
     return GBP_OK;
 }
 

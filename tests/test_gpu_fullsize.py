@@ -145,3 +145,22 @@ def test_full_forward_with_push_overflow(full, split):
     finally:
         B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
         B().set_queue_split(plan, saved_split)
+
+
+def test_full_forward_with_fista(full):
+    """The forward with FISTA local solves (Alg. 1, 128 iterations, tightened
+    step constant) at 500k reaches the stored oracle times within 1e-4 and
+    never falls below them by more than the FP32 solve's own error (FISTA
+    values are feasible points of each local problem)."""
+    plan = full.plan
+    B().set_local_solver(plan, "fista", 128, "tight")
+    try:
+        T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt)
+    finally:
+        B().set_local_solver(plan, "exact")
+    assert st["converged"]
+    Tg = T.cpu().numpy().astype(np.float64)
+    err = rel_max(Tg, full.T_ref)
+    print(f"[fista 500k] rel max err {err:.3e} rounds {st['rounds']}", flush=True)
+    assert err <= 1e-4
+    assert np.all(Tg >= full.T_ref * (1 - 1e-5) - 1e-6)
