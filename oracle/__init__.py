@@ -17,6 +17,9 @@ Pieces
 * ``point_roots`` / ``point_roots_grad`` / ``point_root_adjoint``
                        roots at points inside elements, Sec. 2.3 Eq. (upwind_xi),
                        and the chain rule to the point, onset, D and velocity scale
+* ``p1_stiffness`` / ``lead_field``
+                       the lead weights B = K Z of Sec. 2.4 (P1 stiffness times the
+                       point-electrode lead fields)
 * ``ecg_forward`` / ``ecg_backward`` / ``ecg_loss``
                        Sec. 2.4: V_l(t) = sum_n B[n,l] U(t - phi_n) with the tanh
                        template, and the objective Eq. (inverse_ecg)
@@ -382,6 +385,38 @@ def point_root_adjoint(xyz, tets, D6, vscale, root_tet, root_xyz, root_t, T, g):
     c = point_roots_grad(xyz, tets, D6, vscale, root_tet, root_xyz, root_t, a["droot_t"])
     return dict(lam=a["lam"], dD=a["dD"] + c["dD"], dvscale=a["dvscale"] + c["dvscale"],
                 dt=c["dt"], dx=c["dx"])
+
+
+# --------------------------------------------------------------------------
+# lead-field weights (Sec. 2.4)
+# --------------------------------------------------------------------------
+def p1_stiffness(xyz, tets):
+    """P1 stiffness with unit conductivity, K_ab = sum over elements of
+    |E| grad(l_a) . grad(l_b): the barycentric functions of an element are
+    l = C^-1 [1, x, y, z]^T with C the 4x4 matrix whose columns are
+    [1, x_a, y_a, z_a], so their gradients are the last three columns of C^-1."""
+    x = np.asarray(xyz, dtype=np.float64)
+    tets = np.asarray(tets, dtype=np.int64)
+    n_e = len(tets)
+    C = np.ones((n_e, 4, 4))
+    C[:, 1:, :] = np.transpose(x[tets], (0, 2, 1))
+    Ci = np.linalg.inv(C)                       # row a: coefficients of l_a
+    G = Ci[:, :, 1:]                             # [n_e, 4, 3] gradients
+    vol = np.abs(np.linalg.det(C)) / 6.0
+    Ke = vol[:, None, None] * np.einsum("eai,ebi->eab", G, G)
+    rows = np.repeat(tets, 4, axis=1).reshape(-1)
+    cols = np.tile(tets, (1, 4)).reshape(-1)
+    return sp.csr_matrix((Ke.reshape(-1), (rows, cols)), shape=(len(x), len(x)))
+
+
+def lead_field(xyz, tets, electrodes):
+    """Lead weights B = K Z (Sec. 2.4, with G_i = I): Z[n, l] = 1 / |x_n - e_l|, the
+    lead field of a point electrode in an unbounded unit-conductivity medium,
+    and K the P1 stiffness.  Returns float64 [n_v, L]."""
+    x = np.asarray(xyz, dtype=np.float64)
+    e = np.asarray(electrodes, dtype=np.float64).reshape(-1, 3)
+    Z = 1.0 / np.linalg.norm(x[:, None, :] - e[None, :, :], axis=2)
+    return np.asarray(p1_stiffness(x, tets) @ Z)
 
 
 # --------------------------------------------------------------------------
