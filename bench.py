@@ -262,6 +262,25 @@ def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
     return dict(exact_forward_ms=ms_e, exact_rounds=se["rounds"], runs=runs, ns_per_local_problem=per_face)
 
 
+def lead_field_form(st, prob, torch, B, reps=5):
+    """Lead weights W = K Z assembled on the device for the benchmark's 12
+    electrodes (Sec. 2.4): time per assembly and the largest deviation from the
+    weights the benchmark uses (assembled on the host in float64)."""
+    import numpy as np
+    dev = st["D"].device
+    e = torch.as_tensor(np.asarray(prob.extra["electrodes"], np.float32), device=dev)
+    W = B.lead_field(st["plan"], e)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        B.lead_field(st["plan"], e, out=W)
+    e1.record()
+    torch.cuda.synchronize()
+    dev_max = float((W - st["W"]).abs().max() / st["W"].abs().max())
+    return dict(ms=e0.elapsed_time(e1) / reps, n_leads=int(e.shape[0]), rel_max_vs_host=dev_max)
+
+
 def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed=31):
     """Many uneven meshes and parameter sets as one union plan, one HIP-graph
     replay per iteration for all instances (forward -- cold, then warm-started
@@ -475,6 +494,10 @@ def main():
         detail["point_roots_500k"] = pf
         log(f"[bench] point-root form ({pf['points']} points): {pf['iters_per_s']:.1f} iter/s "
             f"(x{pf['speedup_vs_plain']:.2f}), {pf['rounds']} rounds ({time.time() - t:.1f}s)")
+        lf = lead_field_form(st, prob, torch, B)
+        detail["lead_field_500k"] = lf
+        log(f"[bench] lead weights on the device: {lf['ms']:.2f} ms for {lf['n_leads']} leads, "
+            f"max rel dev from the host assembly {lf['rel_max_vs_host']:.1e}")
         t = time.time()
         fs = fista_form(st, torch, B)
         detail["fista_500k"] = fs

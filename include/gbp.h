@@ -173,6 +173,19 @@ int gbp_local_solve(const float *Q6, const float *Phi, int n, int solver, int n_
                     float *lip_out, void *stream);
 
 /*
+ * gbp_lead_field -- lead weights B = K Z on the device (Sec. 2.4 with unit
+ * conductivity, G_i = I): K the P1 stiffness of the plan's mesh,
+ * K_ab = sum over elements of |E| grad(l_a) . grad(l_b), and Z[n, l] =
+ * 1 / |x_n - e_l| the lead field of a point electrode at e_l.  The result is
+ * the W of gbp_ecg_forward.
+ *   electrodes  device float [n_leads*3]
+ *   W           device float [n_v*n_leads]  (caller vertex order, row-major)
+ * FP64 arithmetic, deterministic.  Errors: GBP_ERR_ARG (n_leads outside
+ * 1..256, missing pointers), GBP_ERR_HIP.
+ */
+int gbp_lead_field(gbp_plan plan, const float *electrodes, int n_leads, float *W, void *stream);
+
+/*
  * gbp_point_roots -- initial conditions at points inside elements (Sec. 2.3
  * Eq. (upwind_xi)): a root at the point x_r of element E_k with onset t_r
  * gives each vertex v of E_k the onset t_r + sqrt((v - x_r)^T D_eff,k^-1 (v - x_r))

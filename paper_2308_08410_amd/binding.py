@@ -115,6 +115,7 @@ _set_solver = _sig("gbp_plan_set_local_solver", [c_void_p, c_int, c_int, c_int])
 _get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
 _local_solve = _sig("gbp_local_solve", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p,
                                         c_void_p, c_void_p, c_void_p])
+_lead_field = _sig("gbp_lead_field", [c_void_p, c_void_p, c_int, c_void_p, c_void_p])
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -312,6 +313,16 @@ def locate_points(plan: Plan, points, tol=1e-6, stream=None):
     out = torch.empty(n, dtype=torch.int32, device=points.device)
     _check(_locate(plan.handle, _ptr(points, torch.float32, (n, 3), "points"), n, float(tol),
                    _ptr(out, torch.int32, (n,), "tet_out"), _stream(stream)))
+    return out
+
+
+def lead_field(plan: Plan, electrodes, out=None, stream=None):
+    """Lead weights W = K Z [n_v, L] for point electrodes [L, 3] (Sec. 2.4)."""
+    L = electrodes.shape[0]
+    if out is None:
+        out = torch.empty((plan.n_v, L), dtype=torch.float32, device=electrodes.device)
+    _check(_lead_field(plan.handle, _ptr(electrodes, torch.float32, (L, 3), "electrodes"), L,
+                       _ptr(out, torch.float32, (plan.n_v, L), "W"), _stream(stream)))
     return out
 
 
