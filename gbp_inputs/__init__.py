@@ -34,7 +34,8 @@ __all__ = [
     "kuhn_cube", "shell_mesh", "Shell", "mlp_params", "mlp_rows", "MLP_SIZES", "fibre_tensor", "endocardial_nodes",
     "random_roots", "random_point_roots", "tets_touching", "smooth_field", "sphere_electrodes", "lead_weights",
     "jitter_nodes", "Problem", "cube_problem", "shell_problem", "AP_CUBE",
-    "AP_SHELL", "tet_volumes",
+    "AP_SHELL", "tet_volumes", "square_tri", "jitter_nodes2", "fibre_tensor2", "annulus_mesh",
+    "circle_electrodes", "lead_weights2", "annulus_problem", "AP_SLICE",
 ]
 
 # Action-potential template parameters (U(xi) = K0 + (K1-K0)*sigmoid(4 xi/tau)
@@ -357,6 +358,142 @@ def lead_weights(xyz: np.ndarray, tets: np.ndarray, electrodes: np.ndarray) -> n
     K = stiffness_matrix(x, tets)
     Z = 1.0 / np.linalg.norm(x[:, None, :] - electrodes[None, :, :], axis=2)
     return np.asarray(K @ Z).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# triangle meshes (d = 2)
+# --------------------------------------------------------------------------
+def square_tri(n_cells: int, length: float = 1.0):
+    """Structured triangle mesh of the square [0, length]^2: n_cells^2 cells,
+    each split along its (i, j)-(i+1, j+1) diagonal into two counter-clockwise
+    triangles.  Node id of grid point (i, j) is i + (n+1) j."""
+    n1 = n_cells + 1
+    g = np.arange(n1, dtype=np.float64) * (length / n_cells)
+    j, i = np.meshgrid(g, g, indexing="ij")
+    xy = np.stack([i.ravel(), j.ravel()], axis=1)
+    c = np.arange(n_cells)
+    cj, ci = np.meshgrid(c, c, indexing="ij")
+    a = (ci + n1 * cj).ravel()
+    b, d, e = a + 1, a + 1 + n1, a + n1
+    tris = np.concatenate([np.stack([a, b, d], 1), np.stack([a, d, e], 1)])
+    return xy.astype(np.float32), tris.astype(np.int32)
+
+
+def jitter_nodes2(xy: np.ndarray, h: float, amp: float, seed: int) -> np.ndarray:
+    """Smooth random 2-D displacement of relative amplitude ``amp`` x h (random
+    sine modes), as ``jitter_nodes`` in the plane."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.asarray(xy, dtype=np.float64)
+    disp = np.zeros_like(x)
+    span = np.ptp(x, axis=0).max()
+    for _ in range(6):
+        k = rng.normal(size=2)
+        k *= (2 * np.pi / span) * rng.uniform(2.0, 6.0) / np.linalg.norm(k)
+        ph = rng.uniform(0, 2 * np.pi)
+        d = rng.normal(size=2)
+        d /= np.linalg.norm(d)
+        disp += np.sin(x @ k + ph)[:, None] * d[None, :]
+    disp *= amp * h / 6.0 * 2.0
+    return (x + disp).astype(np.float32)
+
+
+def fibre_tensor2(fibre: np.ndarray, v_fibre: float = 0.6, v_cross: float = 0.3) -> np.ndarray:
+    """2-D velocity tensor per triangle, packed (xx, yy, xy):
+    D = v_cross^2 I + (v_fibre^2 - v_cross^2) f f^T."""
+    f = np.asarray(fibre, dtype=np.float64)
+    d1, d2 = v_fibre ** 2, v_cross ** 2
+    return np.stack([d2 + (d1 - d2) * f[:, 0] ** 2, d2 + (d1 - d2) * f[:, 1] ** 2,
+                     (d1 - d2) * f[:, 0] * f[:, 1]], axis=1).astype(np.float32)
+
+
+def annulus_mesh(target_nodes: int, r_in: float = 20.0, r_out: float = 30.0, seed: int = 5,
+                 jitter: float = 0.1):
+    """Ring r_in <= r <= r_out (mm), a short-axis slice of a left ventricle: a
+    polar grid of n_r x n_theta nodes (periodic in theta, cells of roughly unit
+    aspect) split into triangles, smooth node jitter.  Fibres lie in the plane at
+    an angle to the circumferential direction rotating linearly from +60 deg at
+    the inner (endocardial) to -60 deg at the outer boundary.
+    Returns (xy, tris, inner node ids, fibre per triangle, grid spacing)."""
+    r_mid = 0.5 * (r_in + r_out)
+    ratio = 2 * np.pi * r_mid / (r_out - r_in)
+    n_r = max(2, int(round(np.sqrt(target_nodes / ratio))))
+    n_t = max(8, int(round(target_nodes / n_r)))
+    r = np.linspace(r_in, r_out, n_r)
+    th = np.arange(n_t) * (2 * np.pi / n_t)
+    R, TH = np.meshgrid(r, th, indexing="ij")
+    xy = np.stack([(R * np.cos(TH)).ravel(), (R * np.sin(TH)).ravel()], axis=1)
+    h = min(r[1] - r[0], 2 * np.pi * r_in / n_t)
+    xy = jitter_nodes2(xy, h, jitter, seed).astype(np.float64)
+
+    def nid(ir, it):
+        return ir * n_t + (it % n_t)
+    ir, it = np.meshgrid(np.arange(n_r - 1), np.arange(n_t), indexing="ij")
+    a, b = nid(ir, it).ravel(), nid(ir, it + 1).ravel()
+    c, d = nid(ir + 1, it + 1).ravel(), nid(ir + 1, it).ravel()
+    tris = np.concatenate([np.stack([a, c, b], 1), np.stack([a, d, c], 1)])
+    # orient counter-clockwise
+    P = xy[tris]
+    cr = (P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1]) - (P[:, 1, 1] - P[:, 0, 1]) * (P[:, 2, 0] - P[:, 0, 0])
+    tris[cr < 0] = tris[cr < 0][:, [0, 2, 1]]
+    cen = xy[tris].mean(axis=1)
+    rc = np.linalg.norm(cen, axis=1)
+    w = np.clip((rc - r_in) / (r_out - r_in), 0, 1)
+    ang = np.deg2rad(60.0 - 120.0 * w)
+    e_t = np.stack([-cen[:, 1], cen[:, 0]], 1) / rc[:, None]
+    e_r = cen / rc[:, None]
+    fib = np.cos(ang)[:, None] * e_t + np.sin(ang)[:, None] * e_r
+    return (xy.astype(np.float32), tris.astype(np.int32), np.arange(n_t, dtype=np.int32),
+            fib.astype(np.float32), float(h))
+
+
+def circle_electrodes(centre, radius: float, n: int, seed: int) -> np.ndarray:
+    """n points at uniform random angles on a circle."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.uniform(0, 2 * np.pi, size=n)
+    return np.asarray(centre, dtype=np.float64)[None, :] + radius * np.stack([np.cos(a), np.sin(a)], 1)
+
+
+def lead_weights2(xy: np.ndarray, tris: np.ndarray, electrodes: np.ndarray) -> np.ndarray:
+    """W[:, l] = K Z_l on a triangle mesh (P1 stiffness, unit conductivity,
+    Z_l(x) = 1/|x - e_l|).  Assembled in float64, returned float32."""
+    x = np.asarray(xy, dtype=np.float64)
+    t = np.asarray(tris, dtype=np.int64)
+    P = x[t]
+    E = P[:, 1:, :] - P[:, :1, :]
+    det = E[:, 0, 0] * E[:, 1, 1] - E[:, 0, 1] * E[:, 1, 0]
+    area = np.abs(det) / 2.0
+    Einv = np.linalg.inv(E)
+    g12 = np.transpose(Einv, (0, 2, 1))
+    G = np.concatenate([-g12.sum(axis=1, keepdims=True), g12], axis=1)
+    Ke = area[:, None, None] * np.einsum("eai,ebi->eab", G, G)
+    n = len(x)
+    K = sp.csr_matrix((Ke.ravel(), (np.repeat(t, 3, axis=1).ravel(), np.tile(t, (1, 3)).ravel())), shape=(n, n))
+    Z = 1.0 / np.linalg.norm(x[:, None, :] - np.asarray(electrodes)[None, :, :], axis=2)
+    return np.asarray(K @ Z).astype(np.float32)
+
+
+AP_SLICE = dict(K0=-85.0, K1=30.0, tau=1.0, t0=0.0, dt=1.0, n_steps=120)
+
+
+def annulus_problem(target_nodes: int = 2700, seed: int = 5, n_roots: int = 8, n_leads: int = 7,
+                    vscale_range=None) -> "Problem":
+    """2-D left-ventricular slice (stands in for the paper's 2-D study: ~2,700
+    nodes, 8 roots, 7 leads): ``annulus_mesh``, D = diag(0.6^2, 0.3^2) (mm/ms)^2 in
+    the fibre frame, roots on the inner boundary with onsets U[0, 20] ms,
+    electrodes on a circle of 3x the outer radius, 120 steps of 1 ms."""
+    xy, tris, inner, fib, h = annulus_mesh(target_nodes, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    rn = rng.choice(inner, size=n_roots, replace=False).astype(np.int32)
+    rt = rng.uniform(0.0, 20.0, size=n_roots).astype(np.float32)
+    if vscale_range is None:
+        vs = np.ones(len(xy), dtype=np.float32)
+    else:
+        r2 = np.random.Generator(np.random.PCG64(seed + 2))
+        vs = r2.uniform(vscale_range[0], vscale_range[1], size=len(xy)).astype(np.float32)
+    el = circle_electrodes(np.zeros(2), 90.0, n_leads, seed + 3)
+    return Problem(name=f"annulus{len(xy)}", xyz=xy, tets=tris, D=fibre_tensor2(fib), vscale=vs,
+                   root_node=rn, root_t=rt, W=lead_weights2(xy, tris, el), ap=dict(AP_SLICE), h=h,
+                   extra=dict(electrodes=el, inner=inner, fibre=fib))
 
 
 # --------------------------------------------------------------------------
