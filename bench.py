@@ -281,6 +281,53 @@ def lead_field_form(st, prob, torch, B, reps=5):
     return dict(ms=e0.elapsed_time(e1) / reps, n_leads=int(e.shape[0]), rel_max_vs_host=dev_max)
 
 
+def slice_form(dev, steps, torch, gi, B, sizes=(2_700, 250_000)):
+    """The iteration on triangle meshes (d = 2): the 2-D left-ventricular slice of
+    the paper's 2-D study (~2.7k nodes, 8 roots, 7 leads) and a finer slice.  One
+    step: forward, ECG, loss, ECG backward, adjoint (scale, onsets), two Adam
+    updates, fitting to the ECG of a hidden scale field."""
+    import numpy as np
+    out = []
+    for n in sizes:
+        p = gi.annulus_problem(n)
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+        plan = B.TriPlan(p.xyz, p.tets)
+        D, W = f32(p.D), f32(p.W)
+        rn = torch.as_tensor(p.root_node, device=dev)
+        a = p.ap
+        ap = B.make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])
+        vs_true = f32(np.random.Generator(np.random.PCG64(8)).uniform(0.8, 1.2, size=p.n_v))
+        T_true, _ = B.tri_forward(plan, D, vs_true, rn, f32(p.root_t))
+        target = B.ecg_forward(T_true, W, ap).clone()
+        vs, rt = f32(np.ones(p.n_v)), f32(p.root_t + 2.0)
+        m_vs, v_vs, m_rt, v_rt = (torch.zeros_like(x) for x in (vs, vs, rt, rt))
+
+        def step(k):
+            T, st = B.tri_forward(plan, D, vs, rn, rt)
+            ecg = B.ecg_forward(T, W, ap)
+            loss, G = B.ecg_loss(ecg, target)
+            gT = B.ecg_backward(T, W, ap, G)
+            _, dvs, drt = B.tri_backward(plan, D, vs, rn, rt, T, gT, want_D=False)
+            B.adam_step(vs, dvs, m_vs, v_vs, k, lr=0.01, lo=0.2, hi=5.0)
+            B.adam_step(rt, drt, m_rt, v_rt, k, lr=0.5)
+            return loss, st
+
+        for k in range(1, 3):
+            step(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(3, 3 + steps):
+            loss, st = step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out.append(dict(n_v=p.n_v, n_tri=p.n_e, iters_per_s=1000.0 / ms, ms_per_step=ms, rounds=st["rounds"],
+                        loss=float(loss[0])))
+        plan.close()
+    return out
+
+
 def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed=31):
     """Many uneven meshes and parameter sets as one union plan, one HIP-graph
     replay per iteration for all instances (forward -- cold, then warm-started
@@ -504,6 +551,11 @@ def main():
         log("[bench] FISTA local solver: " + ", ".join(
             f"n_f={x['n_f']}: {x['forward_ms']:.1f} ms (x{x['slowdown_vs_exact']:.1f}), dev {x['rel_max_vs_exact']:.1e}"
             for x in fs["runs"]) + f"; exact {fs['exact_forward_ms']:.2f} ms ({time.time() - t:.1f}s)")
+        t = time.time()
+        sl = slice_form(dev, args.form_steps, torch, gi, B)
+        detail["slice_2d"] = sl
+        log("[bench] 2-D slice (triangles): " + ", ".join(
+            f"{x['n_v']} nodes {x['iters_per_s']:.1f} iter/s" for x in sl) + f" ({time.time() - t:.1f}s)")
         t = time.time()
         bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
         for k in ("cold", "warm"):

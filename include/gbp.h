@@ -186,6 +186,38 @@ int gbp_local_solve(const float *Q6, const float *Phi, int n, int solver, int n_
 int gbp_lead_field(gbp_plan plan, const float *electrodes, int n_leads, float *W, void *stream);
 
 /*
+ * Triangle meshes (d = 2, the setting of the paper's 2-D study, Sec. 3.1): the
+ * forward and backward of the tetrahedral path with a segment as the local
+ * simplex (Sec. 2.2 Eq. (upwind_eq_lsqr) with d = 2).  Mesh arrays are host
+ * pointers, per-call arrays device pointers, as for tetrahedra.
+ *
+ * gbp_tri_plan_create -- xy [n_v*2] coordinates, tris [n_t*3] vertex ids.
+ *   Errors: GBP_ERR_ARG (ids out of range, a repeated vertex), GBP_ERR_NONFINITE,
+ *   GBP_ERR_DEGENERATE_TET (|2 area| below 1e-7 of the longest edge squared),
+ *   GBP_ERR_NOMEM, GBP_ERR_HIP.
+ * gbp_tri_forward -- activation times (Alg. 2, exact local solves in FP32):
+ *   D [n_t*3] velocity tensor per triangle packed (xx, yy, xy), vscale [n_v] or
+ *   NULL (D_eff = sbar^2 D, sbar the mean of the three nodal scales), vertex
+ *   roots and onsets as gbp_eikonal_forward; T_out [n_v].  Synchronous (the
+ *   convergence check reads the queue length every 8 rounds).  Errors: as
+ *   gbp_eikonal_forward.
+ * gbp_tri_backward -- vector-Jacobian product along the FP64 geodesic parents:
+ *   dL_dD [n_t*3] (off-diagonal doubled) / dL_dvscale [n_v] / dL_droot_t
+ *   [n_roots], each may be NULL; the formulas of gbp_eikonal_backward with
+ *   d sbar / d s = 1/3.  The adjoint sweeps to a relative change of 1e-7.
+ *   Errors: as gbp_eikonal_backward.
+ */
+typedef struct gbp_tri_plan_s *gbp_tri_plan;
+int gbp_tri_plan_create(const float *xy, int n_v, const int32_t *tris, int n_t, gbp_tri_plan *out);
+void gbp_tri_plan_destroy(gbp_tri_plan plan);
+int gbp_tri_forward(gbp_tri_plan plan, const float *D, const float *vscale, const int32_t *root_node,
+                    const float *root_t, int n_roots, float *T_out, gbp_stats *stats, void *stream);
+int gbp_tri_backward(gbp_tri_plan plan, const float *D, const float *vscale,
+                     const int32_t *root_node, const float *root_t, int n_roots, const float *T,
+                     const float *dL_dT, float *dL_dD, float *dL_dvscale, float *dL_droot_t,
+                     void *stream);
+
+/*
  * gbp_point_roots -- initial conditions at points inside elements (Sec. 2.3
  * Eq. (upwind_xi)): a root at the point x_r of element E_k with onset t_r
  * gives each vertex v of E_k the onset t_r + sqrt((v - x_r)^T D_eff,k^-1 (v - x_r))

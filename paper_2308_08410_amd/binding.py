@@ -116,6 +116,12 @@ _get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_i
 _local_solve = _sig("gbp_local_solve", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p,
                                         c_void_p, c_void_p, c_void_p])
 _lead_field = _sig("gbp_lead_field", [c_void_p, c_void_p, c_int, c_void_p, c_void_p])
+_tri_create = _sig("gbp_tri_plan_create", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(c_void_p)])
+_tri_destroy = _sig("gbp_tri_plan_destroy", [c_void_p], None)
+_tri_forward = _sig("gbp_tri_forward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                        ctypes.POINTER(Stats), c_void_p])
+_tri_backward = _sig("gbp_tri_backward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -268,6 +274,68 @@ def parent_map(plan: Plan, D, vscale, root_node, root_t, T, stream=None):
                     _ptr(T, torch.float32, (n_v,), "T"), pt.data_ptr(), pn.data_ptr(), pa.data_ptr(),
                     best.data_ptr(), _stream(stream)))
     return pt, pn, pa, best
+
+
+class TriPlan:
+    """Triangle-mesh plan (gbp_tri_plan, d = 2).  xy float32 [n_v,2], tris int32 [n_t,3] on the host."""
+
+    def __init__(self, xy, tris):
+        xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float32))
+        tris = np.ascontiguousarray(np.asarray(tris, dtype=np.int32))
+        if xy.ndim != 2 or xy.shape[1] != 2 or tris.ndim != 2 or tris.shape[1] != 3:
+            raise ValueError("xy must be [n_v,2] and tris [n_t,3]")
+        h = c_void_p()
+        torch.cuda.current_device()
+        _check(_tri_create(xy.ctypes.data, len(xy), tris.ctypes.data, len(tris), ctypes.byref(h)))
+        self._h = h
+        self.n_v, self.n_t = len(xy), len(tris)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _tri_destroy is not None:
+            _tri_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def tri_forward(plan: TriPlan, D, vscale, root_node, root_t, out=None, stream=None):
+    """Activation times on a triangle mesh: (T [n_v], stats)."""
+    R = root_node.numel()
+    if out is None:
+        out = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
+    st = Stats()
+    _check(_tri_forward(plan.handle, _ptr(D, torch.float32, (plan.n_t, 3), "D"),
+                        _ptr(vscale, torch.float32, (plan.n_v,), "vscale"),
+                        _ptr(root_node, torch.int32, (R,), "root_node"), _ptr(root_t, torch.float32, (R,), "root_t"),
+                        R, _ptr(out, torch.float32, (plan.n_v,), "T_out"), ctypes.byref(st), _stream(stream)))
+    return out, st.as_dict()
+
+
+def tri_backward(plan: TriPlan, D, vscale, root_node, root_t, T, dL_dT, want_D=True, want_vscale=True,
+                 want_root_t=True, stream=None):
+    """(dL/dD [n_t,3] or None, dL/dvscale [n_v] or None, dL/droot_t [R] or None) on a triangle mesh."""
+    R = root_node.numel()
+    dev = T.device
+    dD = torch.empty((plan.n_t, 3), dtype=torch.float32, device=dev) if want_D else None
+    dvs = torch.empty(plan.n_v, dtype=torch.float32, device=dev) if want_vscale else None
+    dt = torch.empty(R, dtype=torch.float32, device=dev) if want_root_t else None
+    _check(_tri_backward(plan.handle, _ptr(D, torch.float32, (plan.n_t, 3), "D"),
+                         _ptr(vscale, torch.float32, (plan.n_v,), "vscale"),
+                         _ptr(root_node, torch.int32, (R,), "root_node"), _ptr(root_t, torch.float32, (R,), "root_t"),
+                         R, _ptr(T, torch.float32, (plan.n_v,), "T"), _ptr(dL_dT, torch.float32, (plan.n_v,), "dL_dT"),
+                         _ptr(dD, torch.float32, (plan.n_t, 3), "dL_dD"),
+                         _ptr(dvs, torch.float32, (plan.n_v,), "dL_dvscale"),
+                         _ptr(dt, torch.float32, (R,), "dL_droot_t"), _stream(stream)))
+    return dD, dvs, dt
 
 
 def point_roots(plan: Plan, D, vscale, root_tet, root_xyz, root_t, stream=None):

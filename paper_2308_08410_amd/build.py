@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbp.so")
-SOURCES = ["plan.cpp", "profile.cpp", "eikonal.hip", "ecg.hip", "optim.hip", "step.cpp", "mlp.hip", "points.hip", "local.hip", "leadfield.hip"]
+SOURCES = ["plan.cpp", "profile.cpp", "eikonal.hip", "ecg.hip", "optim.hip", "step.cpp", "mlp.hip", "points.hip", "local.hip", "leadfield.hip", "tri.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
