@@ -101,11 +101,22 @@ __device__ __forceinline__ void xpush_global(int v, const XcdQueues& xq, int* __
     }
 }
 
+// WIDE: fronts that overflow the LDS buffer wholesale (a warm start queues every
+// vertex) take the wave-aggregated reservation; cold fronts overflow rarely and
+// keep the plain per-lane atomic, which needs fewer registers in the round's
+// main loop.
+template <bool WIDE>
 __device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& xq,
                                            int* __restrict__ qout, int* cnt_next) {
     const int pos = atomicAdd(b.n, 1);
-    if (pos < kPushCap) b.q[pos] = v;
-    else xpush_global(v, xq, qout, cnt_next);
+    if (pos < kPushCap) {
+        b.q[pos] = v;
+    } else if constexpr (WIDE) {
+        xpush_global(v, xq, qout, cnt_next);
+    } else {
+        const int x = xcd_of(v, xq.R);
+        qout[xq.off[x] + atomicAdd(&cnt_next[x], 1)] = v;
+    }
 }
 
 // cnt_sh, base_sh: LDS [8] scratch
@@ -452,7 +463,7 @@ __global__ void __launch_bounds__(TPB)
             for (int a = adj0 + lane; a < adj1; a += L) {
                 const int nb = adj[a];
                 if (atomicMax(&mark[nb], stamp_next) < stamp_next)
-                    xpush_node(pb, nb, xq, qout, cnt_next);
+                    xpush_node<TWO_SIDED>(pb, nb, xq, qout, cnt_next);
             }
         }
     }
