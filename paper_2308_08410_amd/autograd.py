@@ -41,6 +41,29 @@ class EikonalFn(torch.autograd.Function):
         return None, dD, dvs, None, dt, None
 
 
+class TriEikonalFn(torch.autograd.Function):
+    """T = TriEikonalFn.apply(plan, D, vscale, root_node, root_t) on a triangle mesh
+    (d = 2, ``binding.TriPlan``); differentiable w.r.t. D [n_t,3] (off-diagonal
+    entries doubled), vscale and root_t, parents recomputed in the backward."""
+
+    @staticmethod
+    def forward(ctx, plan, D, vscale, root_node, root_t):
+        T, stats = B.tri_forward(plan, D, vscale, root_node, root_t)
+        ctx.plan = plan
+        ctx.stats = stats
+        ctx.save_for_backward(D, vscale, root_node, root_t, T)
+        return T
+
+    @staticmethod
+    def backward(ctx, gT):
+        D, vscale, root_node, root_t, T = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        dD, dvs, dt = B.tri_backward(ctx.plan, D, vscale, root_node, root_t, T, gT.contiguous(),
+                                     want_D=need[1], want_vscale=need[2] and vscale is not None,
+                                     want_root_t=need[4])
+        return None, dD, dvs, None, dt
+
+
 class PointRootsFn(torch.autograd.Function):
     """node, onset = PointRootsFn.apply(plan, D, vscale, root_tet, root_xyz, root_t).
 
@@ -105,6 +128,10 @@ class EcgLossFn(torch.autograd.Function):
 
 def eikonal(plan, D, vscale, root_node, root_t, T_init=None):
     return EikonalFn.apply(plan, D, vscale, root_node, root_t, T_init)
+
+
+def tri_eikonal(plan, D, vscale, root_node, root_t):
+    return TriEikonalFn.apply(plan, D, vscale, root_node, root_t)
 
 
 def point_roots(plan, D, vscale, root_tet, root_xyz, root_t):

@@ -125,3 +125,27 @@ def test_tri_input_errors():
                         t32([0.0], dev))
     T, st = B().tri_forward(plan, D3, None, i32([0], dev), t32([0.0], dev))
     assert st["converged"] and float(T[0]) == 0.0
+
+
+def test_slice_through_autograd(slice_case):
+    """A full 2-D iteration through torch autograd (TriEikonalFn + ECG + loss)
+    gives the explicit C ABI chain's gradients."""
+    from paper_2308_08410_amd import autograd as A
+    c, p = slice_case, slice_case["p"]
+    a = p.ap
+    ap = B().make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])
+    W = t32(p.W, c["dev"])
+    target = B().ecg_forward(c["T"], W, ap).clone() * 0.9
+    vs = c["vs"].clone().requires_grad_(True)
+    rt = c["rt"].clone().requires_grad_(True)
+    D = c["D"].clone().requires_grad_(True)
+    T = A.tri_eikonal(c["plan"], D, vs, c["rn"], rt)
+    loss = A.ecg_loss(A.ecg(T, W, ap), target)
+    loss.backward()
+    T2, _ = B().tri_forward(c["plan"], c["D"], c["vs"], c["rn"], c["rt"])
+    ecg = B().ecg_forward(T2, W, ap)
+    _, G = B().ecg_loss(ecg, target)
+    gT = B().ecg_backward(T2, W, ap, G)
+    dD, dvs, drt = B().tri_backward(c["plan"], c["D"], c["vs"], c["rn"], c["rt"], T2, gT)
+    for x, y in ((D.grad, dD), (vs.grad, dvs), (rt.grad, drt)):
+        assert rel_l2(x.cpu().numpy(), y.cpu().numpy()) <= 1e-5
