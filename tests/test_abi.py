@@ -86,3 +86,41 @@ def test_mlp_entry_points_validate_before_gpu():
     norm0 = (ctypes.c_float * 5)(0, 0, 0, 0, 1)
     assert f(fake, fake, None, 10, None, 5, fake, fake, 2, norm0, None, fake, None, None) == -1
     assert f(fake, fake, None, 10, None, 5, fake, fake, 2, norm, fake, fake, None, None) == -1
+
+
+def test_triangle_plan_rejects_bad_meshes_before_gpu():
+    from paper_2308_08410_amd import binding as B
+    xy, tris = gi.square_tri(2)
+
+    def create(x, t):
+        h = ctypes.c_void_p()
+        x = np.ascontiguousarray(x, np.float32)
+        t = np.ascontiguousarray(t, np.int32)
+        return B._tri_create(x.ctypes.data, len(x), t.ctypes.data, len(t), ctypes.byref(h))
+
+    bad = tris.copy()
+    bad[1, 2] = -1
+    assert create(xy, bad) == -1
+    bad = tris.copy()
+    bad[0, 2] = bad[0, 1]
+    assert create(xy, bad) == -1
+    flat = xy.copy()
+    flat[:, 1] = 0.0
+    assert create(flat, tris) == -2
+    nan = xy.copy()
+    nan[3, 0] = np.inf
+    assert create(nan, tris) == -4
+
+
+def test_local_solve_and_lead_field_validate_before_gpu():
+    lib = ctypes.CDLL(LIB)
+    f = lib.gbp_local_solve
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(16)   # never dereferenced: the checks run first
+    assert f(fake, fake, -1, 0, 1, None, 1, fake, None, None, None) == -1        # n < 0
+    assert f(fake, fake, 4, 2, 1, None, 1, fake, None, None, None) == -1         # solver
+    assert f(fake, fake, 4, 1, 0, None, 1, fake, None, None, None) == -1         # n_f
+    assert f(fake, fake, 4, 1, 8, None, 3, fake, None, None, None) == -1         # step-constant mode
+    assert f(None, fake, 4, 0, 1, None, 1, fake, None, None, None) == -1         # missing Q
+    assert f(fake, fake, 0, 0, 1, None, 1, None, None, None, None) == 0          # empty batch
