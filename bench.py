@@ -34,6 +34,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0   # dense bf16 matrix-core peak
 
 
+FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,7 +51,9 @@ def parse():
                     help="use this launch configuration instead of autotuning (e.g. to profile the "
                          "configuration a timed run chose)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the warm-started single and batched forms")
+                    help="skip every form beside the plain iteration")
+    ap.add_argument("--forms", default=",".join(FORMS), metavar="LIST",
+                    help="comma-separated subset of " + ",".join(FORMS) + " (default: all)")
     ap.add_argument("--form-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="MIB",
                     help="run one plain copy of this many MiB first (a known-size kernel for "
@@ -527,35 +532,45 @@ def main():
                                     mfma_busy_pct=m["mfma_busy_pct"])
         detail["kernel_ms_per_step"] = {k: v[1] / nprof for k, v in prof.items() if v[0]}
         detail["kernel_launches_per_step"] = {k: v[0] / nprof for k, v in prof.items() if v[0]}
-    if not args.no_forms:
-        from paper_2308_08410_amd import autotune
+    forms = set() if args.no_forms else {f for f in args.forms.split(",") if f}
+    unknown = forms - set(FORMS)
+    if unknown:
+        print(f"unknown forms {sorted(unknown)}; choose from {','.join(FORMS)}", file=sys.stderr)
+        sys.exit(2)
+    from paper_2308_08410_amd import autotune
+    if "warm" in forms:
         t = time.time()
         ws = warm_single_form(st, prob, args.form_steps, torch, B, autotune)
         ws["speedup_vs_plain"] = ws["iters_per_s"] / (1000.0 / ms)
         detail["warm_single_500k"] = ws
         log(f"[bench] warm single form: {ws['iters_per_s']:.1f} iter/s (x{ws['speedup_vs_plain']:.2f}), "
             f"max rel T vs cold {ws['max_rel_T_vs_cold']:.1e} ({time.time() - t:.1f}s)")
+    if "points" in forms:
         t = time.time()
         pf = point_root_form(st, prob, args.form_steps, torch, gi, B)
         pf["speedup_vs_plain"] = pf["iters_per_s"] / (1000.0 / ms)
         detail["point_roots_500k"] = pf
         log(f"[bench] point-root form ({pf['points']} points): {pf['iters_per_s']:.1f} iter/s "
             f"(x{pf['speedup_vs_plain']:.2f}), {pf['rounds']} rounds ({time.time() - t:.1f}s)")
+    if "leadfield" in forms:
         lf = lead_field_form(st, prob, torch, B)
         detail["lead_field_500k"] = lf
         log(f"[bench] lead weights on the device: {lf['ms']:.2f} ms for {lf['n_leads']} leads, "
             f"max rel dev from the host assembly {lf['rel_max_vs_host']:.1e}")
+    if "fista" in forms:
         t = time.time()
         fs = fista_form(st, torch, B)
         detail["fista_500k"] = fs
         log("[bench] FISTA local solver: " + ", ".join(
             f"n_f={x['n_f']}: {x['forward_ms']:.1f} ms (x{x['slowdown_vs_exact']:.1f}), dev {x['rel_max_vs_exact']:.1e}"
             for x in fs["runs"]) + f"; exact {fs['exact_forward_ms']:.2f} ms ({time.time() - t:.1f}s)")
+    if "slice" in forms:
         t = time.time()
         sl = slice_form(dev, args.form_steps, torch, gi, B)
         detail["slice_2d"] = sl
         log("[bench] 2-D slice (triangles): " + ", ".join(
             f"{x['n_v']} nodes {x['iters_per_s']:.1f} iter/s" for x in sl) + f" ({time.time() - t:.1f}s)")
+    if "batched" in forms:
         t = time.time()
         bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
         for k in ("cold", "warm"):
