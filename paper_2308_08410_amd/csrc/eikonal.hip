@@ -56,8 +56,11 @@ __device__ __forceinline__ float block_max_f(float v) {
     return t;
 }
 
-// Capacity of a block's LDS push buffer (entries, all sub-queue sections).
+// Capacity of a block's LDS push buffer (entries, all sub-queue sections): cold
+// rounds' fronts fit 4096; a two-sided (warm) round queues every vertex, so its
+// blocks get 8192 (32 KB, still within four resident blocks' share of the LDS).
 constexpr int kPushCap = 4096;
+constexpr int kPushCapWide = 8192;
 
 __device__ __forceinline__ int xcd_of(int i, int R) { return (i / R) & 7; }
 // position of vertex i inside its sub-queue when every vertex is queued
@@ -71,8 +74,9 @@ __device__ __forceinline__ int xcd_rank(int i, int R) {
 // room, and the entries are scattered to their sub-queues (overflow goes
 // straight to global).
 struct XPushBuf {
-    int* q;      // LDS [kPushCap]
+    int* q;      // LDS [cap]
     int* n;      // LDS counter
+    int cap;
 };
 
 // Overflow of the LDS buffer: the overflowing lanes of a wave reserve global room
@@ -109,7 +113,7 @@ template <bool WIDE>
 __device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& xq,
                                            int* __restrict__ qout, int* cnt_next) {
     const int pos = atomicAdd(b.n, 1);
-    if (pos < kPushCap) {
+    if (pos < b.cap) {
         b.q[pos] = v;
     } else if constexpr (WIDE) {
         xpush_global(v, xq, qout, cnt_next);
@@ -123,7 +127,7 @@ __device__ __forceinline__ void xpush_node(XPushBuf b, int v, const XcdQueues& x
 __device__ __forceinline__ void xpush_flush(XPushBuf b, const XcdQueues& xq, int* __restrict__ qout,
                                             int* cnt_next, int* cnt_sh, int* base_sh) {
     __syncthreads();
-    const int n = min(*b.n, kPushCap);
+    const int n = min(*b.n, b.cap);
     if (xq.nq == 1) {   // one queue: a single reservation, entries in push order
         if (threadIdx.x == 0) base_sh[0] = n > 0 ? atomicAdd(&cnt_next[0], n) : 0;
         __syncthreads();
@@ -411,11 +415,12 @@ __global__ void __launch_bounds__(TPB)
     }
     if (lb * PER_BLOCK >= n) return;                // no vertex for this block
     int* cnt_next = ctl->qcnt[(s + 1) % 3];
-    __shared__ int push_q[kPushCap];
+    constexpr int CAP = TWO_SIDED ? kPushCapWide : kPushCap;
+    __shared__ int push_q[CAP];
     __shared__ int push_n, push_cnt[8], push_base[8];
     if (threadIdx.x == 0) push_n = 0;
     __syncthreads();
-    const XPushBuf pb{push_q, &push_n};
+    const XPushBuf pb{push_q, &push_n, CAP};
     const int lane = threadIdx.x & (L - 1);
     const int sub = threadIdx.x / L;                // vertex slot of this lane group
     unsigned long long solves = 0, upd = 0;
