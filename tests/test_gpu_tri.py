@@ -149,3 +149,26 @@ def test_slice_through_autograd(slice_case):
     dD, dvs, drt = B().tri_backward(c["plan"], c["D"], c["vs"], c["rn"], c["rt"], T2, gT)
     for x, y in ((D.grad, dD), (vs.grad, dvs), (rt.grad, drt)):
         assert rel_l2(x.cpu().numpy(), y.cpu().numpy()) <= 1e-5
+
+
+def test_fine_slice_identities():
+    """250k-vertex slice (the benchmark's finer 2-D case): every vertex reached,
+    roots hold their onsets, and the GPU's own gradients satisfy the exact
+    identities of the scheme at any size: sum_r dL/dt_r = sum_n g_n and
+    sum_n s_n dL/ds_n - sum_r t_r dL/dt_r = -g.T."""
+    dev = _dev()
+    p = gi.annulus_problem(250_000, vscale_range=(0.7, 1.3))
+    print(f"[case] fine slice n_v={p.n_v} n_t={p.n_e}", flush=True)
+    plan = B().TriPlan(p.xyz, p.tets)
+    D, vs, rn, rt = t32(p.D, dev), t32(p.vscale, dev), i32(p.root_node, dev), t32(p.root_t, dev)
+    T, st = B().tri_forward(plan, D, vs, rn, rt)
+    assert st["converged"] and st["unreached"] == 0
+    Tn = T.cpu().numpy().astype(np.float64)
+    assert np.all(Tn[p.root_node] <= p.root_t + 1e-6)
+    g = np.random.Generator(np.random.PCG64(9)).uniform(0.5, 1.5, size=p.n_v)
+    _, dvs, drt = B().tri_backward(plan, D, vs, rn, rt, T, t32(g, dev), want_D=False)
+    drt = drt.cpu().numpy().astype(np.float64)
+    dvs = dvs.cpu().numpy().astype(np.float64)
+    assert drt.sum() == pytest.approx(g.sum(), rel=1e-4)
+    lhs = p.vscale.astype(np.float64) @ dvs - p.root_t.astype(np.float64) @ drt
+    assert lhs == pytest.approx(-(g @ Tn), rel=1e-3)
