@@ -164,3 +164,28 @@ def test_full_forward_with_fista(full):
     print(f"[fista 500k] rel max err {err:.3e} rounds {st['rounds']}", flush=True)
     assert err <= 1e-4
     assert np.all(Tg >= full.T_ref * (1 - 1e-5) - 1e-6)
+
+
+@pytest.mark.parametrize("launch", [(16, 1024, 32, 2048, True), (8, 512, 16, 512, False), (32, 2048, 64, 1024, True)])
+def test_full_forward_and_gradients_in_launch_configs(full, launch):
+    """The 500k forward against the stored oracle times, and the gradients against
+    those of the default configuration, in the configuration the benchmark's
+    autotuner picks (first) and two others from its search space."""
+    lanes, blocks, batch, lblocks, split = launch
+    plan = full.plan
+    saved = B().get_launch(plan)
+    saved_split = B().get_queue_split(plan)
+    g = t32(np.random.Generator(np.random.PCG64(12)).normal(size=full.p.n_v), full.dev)
+    ref = B().eikonal_backward(plan, full.D, full.vst, full.rn, full.rtt, full.T_ref_dev, g)
+    B().set_launch(plan, lanes, blocks, lblocks, batch)
+    B().set_queue_split(plan, split)
+    try:
+        T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt)
+        assert st["converged"]
+        assert rel_max(T.cpu().numpy(), full.T_ref) <= 1e-4
+        got = B().eikonal_backward(plan, full.D, full.vst, full.rn, full.rtt, full.T_ref_dev, g)
+        for a, b in zip(got, ref):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-5
+    finally:
+        B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
+        B().set_queue_split(plan, saved_split)
