@@ -430,8 +430,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the solve of one mesh runs on "
-              "one MI355X; see DESIGN.md for how it would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the solve of one mesh runs on "
+              "one MI355X). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     import gbp_inputs as gi

@@ -7,7 +7,7 @@ size that ran in the same process (the benchmark's `--calibrate-copy`: a
 `torch.neg` of a float32 buffer, which reads and writes the buffer once).
 
     python -m paper_2308_08410_amd.profiling \\
-        --fetch gpurun_out/pmc_fetch --write gpurun_out/pmc_write \\
+        --fetch out/pmc_fetch --write out/pmc_write \\
         --kernel k_sweep --copy-mib 256 --out profiles/k_sweep_shell500k_traffic.md
 
 The summary written is Markdown with one fenced JSON block; `bench.py` reads it
@@ -157,7 +157,7 @@ def main(argv=None):
             f.write("One rocprofv3 counter run (derived counters MfmaFlopsBF16 = 512 x\n"
                     "SQ_INSTS_VALU_MFMA_MOPS_BF16, MfmaUtil = MFMA-busy cycles over active cycles x SIMDs).\n\n")
             if args.command:
-                f.write("Commands (repository root, GPU box):\n\n")
+                f.write("Commands (repository root, on the MI355X):\n\n")
                 for line in args.command.split(";;"):
                     f.write(f"    {line.strip()}\n")
                 f.write("\n")
@@ -177,7 +177,7 @@ def main(argv=None):
                 "dispatch), each scaled by the same counter on a plain copy of known size\n"
                 f"(`{args.copy}`, {args.copy_mib:g} MiB read and written) in the same process.\n\n")
         if args.command:
-            f.write("Commands (repository root, GPU box):\n\n")
+            f.write("Commands (repository root, on the MI355X):\n\n")
             for line in args.command.split(";;"):
                 f.write(f"    {line.strip()}\n")
             f.write("\n")
