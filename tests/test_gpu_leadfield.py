@@ -61,6 +61,20 @@ def test_lead_field_errors():
         B().lead_field(plan, t32(np.zeros((300, 3)), dev))
 
 
+def test_lead_field_max_leads():
+    """256 electrodes (the most one call takes: 32 chunks of 8) on a jittered cube."""
+    dev = _dev()
+    xyz, tets = gi.kuhn_cube(5)
+    x = gi.jitter_nodes(xyz, 1.0 / 5, 0.15, 8)
+    e = gi.sphere_electrodes(np.full(3, 0.5), 2.5, 256, seed=9).astype(np.float32)
+    plan = B().Plan(x, tets)
+    W = B().lead_field(plan, t32(e, dev)).cpu().numpy()
+    assert W.shape == (len(x), 256)
+    _check(W, O.lead_field(x.astype(np.float32), tets, e))
+    with pytest.raises(B().GbpError):
+        B().lead_field(plan, t32(np.zeros((257, 3)), dev))
+
+
 def test_lead_field_full_size():
     """500k-vertex shell, 12 electrodes: element by element against the oracle."""
     dev = _dev()

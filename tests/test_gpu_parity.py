@@ -333,6 +333,34 @@ def test_ecg_unreached_and_ragged():
         assert np.all(d[~np.isfinite(T)] == 0)
 
 
+def test_ecg_size_limits():
+    """The largest ECG the kernels take (16 leads, 992 time steps, a window that
+    spans every step) and the smallest (1 lead, 1 step) against the oracle; one
+    past either limit is refused before any launch."""
+    dev = _dev()
+    r = np.random.Generator(np.random.PCG64(12))
+    n_v = 3000
+    T = r.uniform(0, 60, size=n_v)
+    for L, S, dt in ((16, 992, 0.07), (1, 1, 0.5), (16, 1, 0.5), (1, 992, 0.07)):
+        W = r.normal(size=(n_v, L)).astype(np.float32)
+        ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-2.0, dt=dt, n_steps=S)
+        print(f"[case] ecg limits L={L} S={S}", flush=True)
+        e = B().ecg_forward(t32(T, dev), t32(W, dev), B().make_ap(**ap)).cpu().numpy()
+        eo = O.ecg_forward(T.astype(np.float32), W, ap)
+        assert e.shape == eo.shape == (S, L)
+        assert np.abs(e - eo).max() / max(np.abs(eo).max(), 1e-6) <= 1e-3
+        G = r.normal(size=eo.shape).astype(np.float32)
+        d = B().ecg_backward(t32(T, dev), t32(W, dev), B().make_ap(**ap), t32(G, dev)).cpu().numpy()
+        do = O.ecg_backward(T.astype(np.float32), W, ap, G)
+        assert rel_l2(d, do) <= 1e-3
+    ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-2.0, dt=0.1, n_steps=993)
+    with pytest.raises(B().GbpError):
+        B().ecg_forward(t32(T, dev), t32(np.zeros((n_v, 4)), dev), B().make_ap(**ap))
+    ap["n_steps"] = 10
+    with pytest.raises(B().GbpError):
+        B().ecg_forward(t32(T, dev), t32(np.zeros((n_v, 17)), dev), B().make_ap(**ap))
+
+
 def test_adam_matches_oracle():
     dev = _dev()
     r = np.random.Generator(np.random.PCG64(2))
