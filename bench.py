@@ -74,6 +74,17 @@ def stored_mfma(kernel):
     return t
 
 
+def stored_valu(kernel):
+    """Vector-ALU figures of an ECG kernel (VALU and transcendental instructions
+    per launch) from the committed counter summary, while its source is unchanged
+    (else None)."""
+    from paper_2308_08410_amd import profiling
+    t = profiling.read_summary(os.path.join(PROFILES, f"{kernel}_shell500k_valu.md"))
+    if not t or t.get("source_hash") != profiling.source_hash(kernel, "ecg.hip"):
+        return None
+    return t
+
+
 def stored_traffic(kernel="k_sweep"):
     """Measured HBM bytes per launch of a kernel on this workload, from the
     committed counter summary, while the kernel's source is unchanged since the
@@ -530,6 +541,16 @@ def main():
                 detail[kern] = dict(avg_launch_ms=avg, mfma_flops_per_launch=m["mfma_flops_per_launch"],
                                     mfma_tflops=tf, peak_tflops=PEAK_BF16_TFLOPS, frac=tf / PEAK_BF16_TFLOPS,
                                     mfma_busy_pct=m["mfma_busy_pct"])
+                # the template's exp2/rcp on the VALU: transcendental operations
+                # (counters) over the launch time measured here, against the
+                # quarter-rate peak
+                v = stored_valu(kern)
+                if v:
+                    rate = v["trans_ops_per_launch"] / (avg * 1e-3)
+                    detail[kern].update(valu_insts_per_launch=v["valu_insts_per_launch"],
+                                        trans_ops_per_launch=v["trans_ops_per_launch"],
+                                        trans_ops_per_s=rate, trans_frac=rate / v["trans_peak_ops_per_s"],
+                                        valu_busy_pct=v["valu_busy_pct"])
         detail["kernel_ms_per_step"] = {k: v[1] / nprof for k, v in prof.items() if v[0]}
         detail["kernel_launches_per_step"] = {k: v[0] / nprof for k, v in prof.items() if v[0]}
     forms = set() if args.no_forms else {f for f in args.forms.split(",") if f}

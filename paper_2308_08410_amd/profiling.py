@@ -1,4 +1,5 @@
-"""HBM traffic of a kernel from rocprofv3 counter runs.
+"""HBM traffic (and matrix-core / vector-ALU use) of a kernel from rocprofv3
+counter runs.
 
 Two separate `rocprofv3 --pmc` runs of the same command (FETCH_SIZE, then
 WRITE_SIZE; both in KiB per dispatch) are reduced to bytes per launch of one
@@ -128,6 +129,43 @@ def mfma(path, kernel, source="ecg.hip", peak_tflops=2500.0):
                 source_hash=source_hash(kernel, source))
 
 
+# Quarter-rate transcendental peak of the VALU (exp2, rcp, ...): 256 CUs x 4 SIMDs
+# x 4 lanes per clock x 2.4 GHz.
+PEAK_TRANS_OPS = 256 * 4 * 4 * 2.4e9
+
+
+def valu(path, kernel, source="ecg.hip"):
+    """Vector-ALU use of one kernel from a `--pmc SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32
+    VALUBusy` run: VALU and FP32 transcendental instructions per dispatch (wave
+    instructions; x64 lanes for operations), the transcendental rate over the
+    dispatch's duration against the quarter-rate peak, and VALUBusy (percent of
+    the dispatch's GPU time the CUs' vector ALUs issue)."""
+    cnt = {"SQ_INSTS_VALU": {}, "SQ_INSTS_VALU_TRANS_F32": {}, "VALUBusy": {}}
+    dur = {}
+    with open(_counter_csv(path), newline="") as f:
+        for r in csv.DictReader(f):
+            if kernel not in r["Kernel_Name"] or r["Counter_Name"] not in cnt:
+                continue
+            d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            c = cnt[r["Counter_Name"]]
+            c[d] = c.get(d, 0.0) + float(r["Counter_Value"])
+            dur[d] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    ds = sorted(set(cnt["SQ_INSTS_VALU"]) & set(cnt["SQ_INSTS_VALU_TRANS_F32"]))
+    if not ds:
+        raise KeyError(f"no VALU counter rows for {kernel!r}")
+    n = len(ds)
+    v = sum(cnt["SQ_INSTS_VALU"][d] for d in ds) / n
+    tr = sum(cnt["SQ_INSTS_VALU_TRANS_F32"][d] for d in ds) / n
+    t = sum(dur[d] for d in ds) / n
+    busy = [cnt["VALUBusy"][d] for d in ds if d in cnt["VALUBusy"]]
+    rate = 64.0 * tr / t
+    return dict(kernel=kernel, dispatches=n, valu_insts_per_launch=v, trans_insts_per_launch=tr,
+                trans_ops_per_launch=64.0 * tr, avg_duration_s_under_counters=t,
+                trans_ops_per_s=rate, trans_peak_ops_per_s=PEAK_TRANS_OPS, trans_frac=rate / PEAK_TRANS_OPS,
+                valu_busy_pct=sum(busy) / len(busy) if busy else None,
+                source_hash=source_hash(kernel, source))
+
+
 def read_summary(path):
     """The JSON block of a summary written by this module, or None."""
     try:
@@ -144,6 +182,7 @@ def main(argv=None):
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--mfma", help="a --pmc MfmaFlopsBF16 MfmaUtil run (instead of --fetch/--write)")
+    ap.add_argument("--valu", help="a --pmc SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 VALUBusy run")
     ap.add_argument("--kernel", default="k_sweep")
     ap.add_argument("--copy", default="neg")
     ap.add_argument("--copy-mib", type=float, default=256)
@@ -168,8 +207,29 @@ def main(argv=None):
             f.write("```json\n" + json.dumps(t, indent=1) + "\n```\n")
         print(json.dumps(t))
         return
+    if args.valu:
+        t = valu(args.valu, args.kernel)
+        with open(args.out, "w") as f:
+            f.write(f"# Vector-ALU use: {args.kernel}\n\n")
+            f.write("One rocprofv3 counter run (SQ_INSTS_VALU and SQ_INSTS_VALU_TRANS_F32 in wave\n"
+                    "instructions; VALUBusy = percent of GPU time the vector ALUs issue).  The\n"
+                    "transcendental peak is quarter rate: 256 CUs x 4 SIMDs x 4 lanes x 2.4 GHz.\n\n")
+            if args.command:
+                f.write("Commands (repository root, on the MI355X):\n\n")
+                for line in args.command.split(";;"):
+                    f.write(f"    {line.strip()}\n")
+                f.write("\n")
+            busy = t["valu_busy_pct"]
+            f.write(f"Per launch: {t['valu_insts_per_launch'] / 1e6:.2f}M VALU wave instructions, "
+                    f"{t['trans_insts_per_launch'] / 1e6:.3f}M of them FP32 transcendental "
+                    f"({t['trans_ops_per_launch'] / 1e9:.3f} G lane operations, "
+                    f"{100 * t['trans_frac']:.1f}% of the transcendental peak over the counted dispatch time); "
+                    f"VALUBusy {'n/a' if busy is None else f'{busy:.1f}%'}.\n\n")
+            f.write("```json\n" + json.dumps(t, indent=1) + "\n```\n")
+        print(json.dumps(t))
+        return
     if not (args.fetch and args.write):
-        ap.error("--fetch and --write are required without --mfma")
+        ap.error("--fetch and --write are required without --mfma or --valu")
     t = traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_mib)
     with open(args.out, "w") as f:
         f.write(f"# HBM traffic per launch: {args.kernel}\n\n")
