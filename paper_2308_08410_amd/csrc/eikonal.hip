@@ -546,6 +546,14 @@ __device__ __forceinline__ double parent_face64(int t, int K, int self, const in
 // the FP32 minimum -- a margin about a hundred times the FP32 error -- are
 // solved again in FP64, and the FP64 values decide the argmin (ties: first
 // entry in (slot, element) order).
+// The FP64 candidates are few per vertex (the minimum and its near-ties), so they
+// are gathered per block in LDS and solved densely, one per thread: solved in the
+// lane that found them, one candidate anywhere in a wave would hold all 64 lanes
+// for the whole FP64 solve.  A candidate that finds the list full is solved in
+// its own lane.  Same values, same tie rule: the result does not depend on where
+// a candidate was solved.
+constexpr int kParCands = 512;   // FP64 candidates per block held in LDS
+
 template <int L>
 __global__ void __launch_bounds__(TPB)
     k_parent(const int2* __restrict__ nptr, const int* __restrict__ nent,
@@ -554,8 +562,16 @@ __global__ void __launch_bounds__(TPB)
              const float* __restrict__ vs, const float4* __restrict__ xyz,
              const float* __restrict__ T, const float* __restrict__ troot, int n_v,
              int* __restrict__ par, float4* __restrict__ pa) {
+    constexpr int VPB = TPB / L;                    // vertices per block
+    __shared__ int cand_key[kParCands];             // vertex slot << 16 | entry position
+    __shared__ double cand_val[kParCands];
+    __shared__ float cand_w[kParCands][3];
+    __shared__ int n_cand;
+    if (threadIdx.x == 0) n_cand = 0;
+    __syncthreads();
     const int lane = threadIdx.x & (L - 1);
-    const int i0 = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const int slot = threadIdx.x / L;
+    const int i0 = blockIdx.x * VPB + slot;
     const bool act = i0 < n_v;                      // uniform over the lane group
     const int i = act ? i0 : 0;
     const bool reached = act && T[i] < GBP_INF;
@@ -579,15 +595,15 @@ __global__ void __launch_bounds__(TPB)
     }
     for (int o = L / 2; o > 0; o >>= 1) b32 = fminf(b32, __shfl_xor(b32, o));
     const float cut = b32 + 1e-4f * fmaxf(1.f, fabsf(b32));
-    // FP64 decision among the candidates
+    // candidates of the FP64 decision: into the block's list, or (list full) solved here
     double best = __builtin_huge_val(), b0 = 0, b1 = 0, b2 = 0;
     int bpos = 0x7fffffff;
     for (int c = lane, k = 0; c < tot && b32 < GBP_INF; c += L, ++k) {
-        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
         float v32;
         if (k < kKeep) {
             v32 = keep[k];
         } else {
+            const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
             const int t = nent[p.x + c];
             const int4 v = tetv[t];
             int a, b, cc;
@@ -596,15 +612,50 @@ __global__ void __launch_bounds__(TPB)
                                    T[a], T[b], T[cc]);
         }
         if (!(v32 <= cut)) continue;
-        const int t = nent[p.x + c];
+        const int q = atomicAdd(&n_cand, 1);
+        if (q < kParCands) {
+            cand_key[q] = (slot << 16) | c;
+            continue;
+        }
+        const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
         double x0, x1, x2;
-        const double val = parent_face64(t, K, i, tetv, tet_user, D, vs, xyz, T, x0, x1, x2);
+        const double val = parent_face64(nent[p.x + c], K, i, tetv, tet_user, D, vs, xyz, T, x0, x1, x2);
         if (val < best) {
             best = val;
             bpos = c;
-            b0 = x0;
-            b1 = x1;
-            b2 = x2;
+            b0 = (float)x0;
+            b1 = (float)x1;
+            b2 = (float)x2;
+        }
+    }
+    __syncthreads();
+    const int nc = min(n_cand, kParCands);
+    // dense FP64 solves of the listed candidates
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+        const int key = cand_key[q];
+        const int vi = blockIdx.x * VPB + (key >> 16), c = key & 0xffff;
+        const int2 pq = nptr[vi];
+        const int q0 = pq.y & 255, q01 = q0 + ((pq.y >> 8) & 255), q012 = q01 + ((pq.y >> 16) & 255);
+        const int K = (c < q0) ? 0 : (c < q01) ? 1 : (c < q012) ? 2 : 3;
+        double x0, x1, x2;
+        cand_val[q] = parent_face64(nent[pq.x + c], K, vi, tetv, tet_user, D, vs, xyz, T, x0, x1, x2);
+        cand_w[q][0] = (float)x0;
+        cand_w[q][1] = (float)x1;
+        cand_w[q][2] = (float)x2;
+    }
+    __syncthreads();
+    // each lane group takes its own vertex's listed candidates
+    for (int q = lane; q < nc; q += L) {
+        const int key = cand_key[q];
+        if ((key >> 16) != slot) continue;
+        const int c = key & 0xffff;
+        const double val = cand_val[q];
+        if (val < best || (val == best && c < bpos)) {
+            best = val;
+            bpos = c;
+            b0 = cand_w[q][0];
+            b1 = cand_w[q][1];
+            b2 = cand_w[q][2];
         }
     }
     // group argmin of (value, entry position)
