@@ -841,22 +841,22 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
 
 // A finished vertex hands alpha * lambda to its entries in its parents' child
 // lists (read only in later launches, after this one has ended).
-__device__ __forceinline__ void publish(int x, float l, const float4* __restrict__ pa,
-                                        const int4* __restrict__ cslot, float* __restrict__ contrib) {
-    const int4 cs = cslot[x];
-    const float4 w = pa[x];
+__device__ __forceinline__ void publish_to(float l, int4 cs, float4 w, float* __restrict__ contrib) {
     if (cs.x >= 0) contrib[cs.x] = w.x * l;
     if (cs.y >= 0) contrib[cs.y] = w.y * l;
     if (cs.z >= 0) contrib[cs.z] = w.z * l;
 }
 
+__device__ __forceinline__ void publish(int x, float l, const float4* __restrict__ pa,
+                                        const int4* __restrict__ cslot, float* __restrict__ contrib) {
+    publish_to(l, cslot[x], pa[x], contrib);
+}
+
 // A finished vertex releases its parents; a parent whose last child this was
 // becomes ready for the next launch (stamped with a plain store: it is only
 // read after this launch ends).
-__device__ __forceinline__ bool release_parents(int x, int skip, const int4* __restrict__ pnode,
-                                                int* __restrict__ rem, int* __restrict__ rdy,
-                                                int next) {
-    const int4 pn = pnode[x];
+__device__ __forceinline__ bool release_from(int4 pn, int skip, int* __restrict__ rem,
+                                             int* __restrict__ rdy, int next) {
     const int f[3] = {pn.x, pn.y, pn.z};
     bool any = false;
     for (int k = 0; k < 3; ++k)
@@ -865,6 +865,12 @@ __device__ __forceinline__ bool release_parents(int x, int skip, const int4* __r
             any = true;
         }
     return any;
+}
+
+__device__ __forceinline__ bool release_parents(int x, int skip, const int4* __restrict__ pnode,
+                                                int* __restrict__ rem, int* __restrict__ rdy,
+                                                int next) {
+    return release_from(pnode[x], skip, rem, rdy, next);
 }
 
 // One leaves-first level, as a scan over all vertices (one thread per vertex):
@@ -907,15 +913,22 @@ __global__ void __launch_bounds__(TPB)
     for (int k = 0; k < kLevelPer; ++k) {
         if (rv[k] > s) continue;                    // not ready yet, waiting or finished
         const int x = xb + k * stride;
+        // everything this vertex needs besides its child entries, loaded together:
+        // one memory round trip before the entries instead of a chain of them
         const int q = partner[x];
+        const float gx = g[x];
+        const int cb = cptr[x], ce = cptr[x + 1];
+        const int4 csx = cslot[x];
+        const float4 wx = pa[x];
+        const int4 pnx = pnode[x];
         if (q < 0) {
-            float l = g[x];
-            for (int k = cptr[x]; k < cptr[x + 1]; ++k) l += contrib[k];
+            float l = gx;
+            for (int k = cb; k < ce; ++k) l += contrib[k];
             lam[x] = l;
             done[x] = 1;
             rdy[x] = kRdyDone;
-            publish(x, l, pa, cslot, contrib);
-            any |= release_parents(x, -1, pnode, rem, rdy, s + 1);
+            publish_to(l, csx, wx, contrib);
+            any |= release_from(pnx, -1, rem, rdy, s + 1);
             continue;
         }
         if (atomicSub(&pairrem[min(x, q)], 1) != 1) {   // partner not ready yet
@@ -943,9 +956,9 @@ __global__ void __launch_bounds__(TPB)
         done[q] = 1;
         rdy[x] = kRdyDone;
         rdy[q] = kRdyDone;
-        publish(x, lx, pa, cslot, contrib);
+        publish_to(lx, csx, wx, contrib);
         publish(q, lq, pa, cslot, contrib);
-        any |= release_parents(x, q, pnode, rem, rdy, s + 1);
+        any |= release_from(pnx, q, rem, rdy, s + 1);
         any |= release_parents(q, x, pnode, rem, rdy, s + 1);
     }
     if (any) any_sh = 1;
