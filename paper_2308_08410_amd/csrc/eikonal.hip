@@ -798,6 +798,11 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
     }
 }
 
+// Position of entry k (rank r in x's sorted child list) in the entry array.
+__device__ __forceinline__ int centry(int x, int r, int k, int n_v) {
+    return r < kChildSlots ? x * kChildSlots + r : n_v * kChildSlots + k;
+}
+
 // Where each vertex sits in its weighted parents' (sorted) child lists, so that a
 // finished vertex can hand alpha * lambda to its parents' entries directly.
 __global__ void k_child_slots(const int4* __restrict__ pnode, const int* __restrict__ cptr,
@@ -809,8 +814,9 @@ __global__ void k_child_slots(const int4* __restrict__ pnode, const int* __restr
     int pos[3] = {-1, -1, -1};
     for (int k = 0; k < 3; ++k) {
         if (f[k] < 0) continue;
-        for (int e = cptr[f[k]]; e < cptr[f[k] + 1]; ++e)
-            if (cchild[e] == c) pos[k] = e;
+        const int b = cptr[f[k]];
+        for (int e = b; e < cptr[f[k] + 1]; ++e)
+            if (cchild[e] == c) pos[k] = centry(f[k], e - b, e, n_v);
     }
     cslot[c] = make_int4(pos[0], pos[1], pos[2], -1);
 }
@@ -825,9 +831,13 @@ constexpr int kLevelPer = 8;            // vertices per thread in a level scan (
 __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __restrict__ node_user,
                            const float* __restrict__ T, const int* __restrict__ rem, int n_v,
                            float* __restrict__ g, float* __restrict__ lam, int* __restrict__ done,
-                           int* __restrict__ rdy, GbpCtl* ctl) {
+                           int* __restrict__ rdy, float* __restrict__ contrib, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
+    // fixed entry slots start at zero: a vertex sums all of them, used or not
+    float4* z = reinterpret_cast<float4*>(contrib + (size_t)i * kChildSlots);
+#pragma unroll
+    for (int k = 0; k < kChildSlots / 4; ++k) z[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     const bool reached = T[i] < GBP_INF;
     float gi = reached ? dLdT_user[node_user[i]] : 0.f;
     if (gi != gi) gi = 0.f;
@@ -921,9 +931,15 @@ __global__ void __launch_bounds__(TPB)
         const int4 csx = cslot[x];
         const float4 wx = pa[x];
         const int4 pnx = pnode[x];
+        const float4* sl = reinterpret_cast<const float4*>(contrib + (size_t)x * kChildSlots);
+        const float4 s0 = sl[0], s1 = sl[1];
+        static_assert(kChildSlots == 8, "two float4 slot loads");
         if (q < 0) {
+            // entries in child order: the fixed slots (zero where unused), then the rest
             float l = gx;
-            for (int k = cb; k < ce; ++k) l += contrib[k];
+            l += s0.x; l += s0.y; l += s0.z; l += s0.w;
+            l += s1.x; l += s1.y; l += s1.z; l += s1.w;
+            for (int k = cb + kChildSlots; k < ce; ++k) l += contrib[n_v * kChildSlots + k];
             lam[x] = l;
             done[x] = 1;
             rdy[x] = kRdyDone;
@@ -940,10 +956,11 @@ __global__ void __launch_bounds__(TPB)
         for (int m = 0; m < 2; ++m) {
             const int a = pr[m], o = pr[1 - m];
             float l = g[a], wo = 0.f;
-            for (int k = cptr[a]; k < cptr[a + 1]; ++k) {
+            const int b = cptr[a];
+            for (int k = b; k < cptr[a + 1]; ++k) {
                 const int ch = cchild[k];
                 if (ch == o) wo = calpha[k];
-                else l += contrib[k];
+                else l += contrib[centry(a, k - b, k, n_v)];
             }
             S[m] = l;
             w[m] = wo;     // weight of a in o's parent face
@@ -1533,7 +1550,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     // leaves-first level walk
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 2);
     k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
-                                                    p->lam, p->done, p->rdy, p->ctl);
+                                                    p->lam, p->done, p->rdy, p->contrib, p->ctl);
     GBP_LAUNCH_CHECK();
     int level = 0;
     if (!sync) {

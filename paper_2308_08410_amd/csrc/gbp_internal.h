@@ -126,7 +126,7 @@ struct gbp_plan_s {
     int* cchild = nullptr;        // [3 n_v]
     float* calpha = nullptr;      // [3 n_v]
     float* lam = nullptr;         // [n_v]
-    float* contrib = nullptr;     // [3 n_v] alpha * lambda of each child entry, written by the child
+    float* contrib = nullptr;     // [(kChildSlots + 3) n_v] alpha * lambda of each child entry, written by the child
     int4* cslot = nullptr;        // [n_v] position of a vertex in each weighted parent's child list
     float* g = nullptr;           // [n_v]
     float* dsbar = nullptr;       // [n_e]
@@ -139,6 +139,11 @@ struct gbp_plan_s {
 };
 
 constexpr int kStatBlocks = 2048;   // max grid of the relaxation kernels
+// Adjoint entries: the first kChildSlots children of vertex x hand over their
+// alpha * lambda in fixed slots contrib[x * kChildSlots + r] (rank r in the
+// sorted child list), further ones at contrib[n_v * kChildSlots + k] (k = the
+// CSR index), so a finished vertex reads its first entries without its CSR range.
+constexpr int kChildSlots = 8;
 
 int gbp_plan_check(gbp_plan p);
 int gbp_err_from_bits(int bits);

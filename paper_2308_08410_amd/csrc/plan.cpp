@@ -17,6 +17,8 @@
 #include <numeric>
 #include <vector>
 
+#include <climits>
+
 #include "gbp_internal.h"
 
 static thread_local std::string g_last_error;
@@ -326,12 +328,17 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
 int gbp_alloc_backward(gbp_plan p) {
     if (p->bwd_ready) return GBP_OK;
     const int n_v = p->n_v, n_e = p->n_e;
+    if ((long long)(kChildSlots + 3) * n_v > INT_MAX) {
+        gbp_set_error("adjoint: %d vertices exceed the entry layout (at most %d)", n_v,
+                      INT_MAX / (kChildSlots + 3));
+        return GBP_ERR_ARG;
+    }
     int rc;
     if ((rc = dalloc(&p->par, n_v)) || (rc = dalloc(&p->pa, n_v)) ||
         (rc = dalloc(&p->ccnt, n_v + 1)) || (rc = dalloc(&p->cfill, n_v)) ||
         (rc = dalloc(&p->rem, n_v)) || (rc = dalloc(&p->cchild, (size_t)3 * n_v)) ||
         (rc = dalloc(&p->calpha, (size_t)3 * n_v)) || (rc = dalloc(&p->lam, n_v)) ||
-        (rc = dalloc(&p->contrib, (size_t)3 * n_v)) || (rc = dalloc(&p->cslot, n_v)) ||
+        (rc = dalloc(&p->contrib, (size_t)(kChildSlots + 3) * n_v)) || (rc = dalloc(&p->cslot, n_v)) ||
         (rc = dalloc(&p->g, n_v)) ||
         (rc = dalloc(&p->dsbar, n_e)) || (rc = dalloc(&p->done, n_v)) || (rc = dalloc(&p->rdy, n_v)) ||
         (rc = dalloc(&p->pnode, n_v)) || (rc = dalloc(&p->partner, n_v)) ||
