@@ -393,7 +393,8 @@ __global__ void __launch_bounds__(TPB)
             const float* __restrict__ troot, float* T, const int* __restrict__ qin,
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
-            float eps_rel, int n_v, XcdQueues xq, const float* __restrict__ lip, int n_f) {
+            float eps_rel, int n_v, XcdQueues xq, const float* __restrict__ lip, int n_f,
+            int* __restrict__ st) {
     constexpr int PER_BLOCK = TPB / L;
     // blocks are placed on the 8 XCDs round-robin: with the split layout block b
     // serves sub-queue b % 8, else every block serves the one queue
@@ -410,8 +411,16 @@ __global__ void __launch_bounds__(TPB)
     const int n = ctl->qcnt[s % 3][x];
     const int stamp_next = ctl->stamp + s + 1;
     if (blockIdx.x == 0 && threadIdx.x < 8) {
+        const int left = ctl->qcnt[s % 3][threadIdx.x];
         ctl->qcnt[(s + 2) % 3][threadIdx.x] = 0;
-        if (ctl->qcnt[s % 3][threadIdx.x] > 0) atomicMax(&ctl->rounds, s + 1);
+        if (left > 0) atomicMax(&ctl->rounds, s + 1);
+        if (st) {   // status for the host: this round's work, error bits, round index
+            st[threadIdx.x] = left;
+            if (threadIdx.x == 0) {
+                st[8] = ctl->err;
+                st[9] = s;
+            }
+        }
     }
     if (lb * PER_BLOCK >= n) return;                // no vertex for this block
     int* cnt_next = ctl->qcnt[(s + 1) % 3];
@@ -898,7 +907,7 @@ __global__ void __launch_bounds__(TPB)
                 const int4* __restrict__ pnode, const float4* __restrict__ pa,
                 const int4* __restrict__ cslot, float* __restrict__ contrib,
                 const int* __restrict__ partner, int* __restrict__ pairrem, int* __restrict__ rem,
-                int n_v, GbpCtl* ctl, int s) {
+                int n_v, GbpCtl* ctl, int s, int* __restrict__ st) {
     // up to kLevelPer vertices per thread: their stamps are loaded together, and
     // before the work flag, so that all these loads are in flight at once
     const int stride = gridDim.x * blockDim.x;
@@ -913,6 +922,11 @@ __global__ void __launch_bounds__(TPB)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->count[(s + 2) % 3] = 0;
         if (flag != 0) atomicMax(&ctl->levels, s + 1);
+        if (st) {   // status for the host: this level's work flag, error bits, level index
+            st[0] = flag;
+            st[8] = ctl->err;
+            st[9] = s;
+        }
     }
     if (flag == 0) return;
     __shared__ int any_sh;
@@ -923,8 +937,8 @@ __global__ void __launch_bounds__(TPB)
     for (int k = 0; k < kLevelPer; ++k) {
         if (rv[k] > s) continue;                    // not ready yet, waiting or finished
         const int x = xb + k * stride;
-        // everything this vertex needs besides its child entries, loaded together:
-        // one memory round trip before the entries instead of a chain of them
+        // everything this vertex needs, its first child entries included, loaded together:
+        // one memory round trip instead of a chain (partner, entry range, entries)
         const int q = partner[x];
         const float gx = g[x];
         const int cb = cptr[x], ce = cptr[x + 1];
@@ -1233,11 +1247,12 @@ static int read_ctl(gbp_plan p, hipStream_t s) {
     return GBP_OK;
 }
 
-// Pipelined convergence checks of the synchronous loops: after each batch of
-// launches an asynchronous copy of the control block is queued (pinned slot 1 or
-// 2, with an event); the host waits for batch k's copy only after batch k+1 is
-// queued, so the device never idles on the check.  A finished loop costs at most
-// one batch of empty launches (each returns at once).
+// Pipelined convergence checks of the synchronous loops: the host waits for
+// batch k's status only after batch k+1 is queued, so the device never idles on
+// the check.  A finished loop costs at most one batch of empty launches (each
+// returns at once).  The status comes from the first launch of the next batch
+// (no copy in the stream); status_post, an asynchronous copy of the control block
+// into pinned slot 1 or 2 with an event, serves when no launch is left.
 static int status_post(gbp_plan p, int slot, hipStream_t s) {
     GBP_HIP(hipMemcpyAsync(p->ctl_host + 1 + slot, p->ctl, sizeof(GbpCtl), hipMemcpyDeviceToHost, s));
     GBP_HIP(hipEventRecord(p->ev[slot], s));
@@ -1249,42 +1264,63 @@ static int status_wait(gbp_plan p, int slot) {
     return GBP_OK;
 }
 
-// Runs launch(k) for k = 0, 1, ... in growing batches until done(ctl, k_end)
-// holds for the status taken after a batch ending at k_end, or `cap` launches.
-// Returns GBP_OK, or the device error bits' code; `launched` and `finished` out.
-template <class Launch, class Done>
-static int run_pipelined(gbp_plan p, hipStream_t s, int cap, Launch launch, Done done,
+// Runs launch(k, st) for k = 0, 1, ... in growing batches until the status
+// after a batch ending at k_end shows no work left, or `cap` launches.  The
+// first launch of the next batch (launch k_end) writes that status into the
+// pinned words st (the work it finds, the error bits, its index) and an event
+// follows it; the host waits for that event while the rest of the batch is
+// queued.  Only when no launch is left (cap) is the control block copied.
+// fwd: the status counts are the 8 sub-queue lengths (forward), else one work
+// flag (adjoint level).  Returns GBP_OK, or the device error bits' code;
+// `launched` and `finished` out.
+template <class Launch>
+static int run_pipelined(gbp_plan p, hipStream_t s, int cap, bool fwd, Launch launch,
                          int& launched, bool& finished) {
-    int r = 0, slot = 0, batch = 4;
-    int pend[2] = {0, 0};
+    int r = 0, slot = 0, batch = 4, rc;
     finished = false;
-    int nb = std::min(batch, cap);
-    for (int b = 0; b < nb; ++b, ++r) launch(r);
+    const int nb = std::min(batch, cap);
+    for (int b = 0; b < nb; ++b, ++r) launch(r, nullptr);
     launched = r;
     GBP_LAUNCH_CHECK();
-    int rc = status_post(p, slot, s);
-    if (rc) return rc;
-    pend[slot] = r;
     while (true) {
-        const int other = slot ^ 1;
+        const int k_end = r;                      // status wanted: after k_end launches
         batch = std::min(batch * 2, p->sync_batch);
         const int nb2 = std::min(batch, cap - r);
         if (nb2 > 0) {
-            for (int b = 0; b < nb2; ++b, ++r) launch(r);
+            launch(r, p->st_dev + slot * kStWords);
+            GBP_HIP(hipEventRecord(p->ev[slot], s));
+            ++r;
+            for (int b = 1; b < nb2; ++b, ++r) launch(r, nullptr);
             launched = r;
             GBP_LAUNCH_CHECK();
-            if ((rc = status_post(p, other, s))) return rc;
-            pend[other] = r;
+        } else if ((rc = status_post(p, slot, s))) {
+            return rc;
         }
         if ((rc = status_wait(p, slot))) return rc;
-        const GbpCtl& c = p->ctl_host[1 + slot];
-        if (c.err) return gbp_err_from_bits(c.err);
-        if (done(c, pend[slot])) {
+        int left = 0, err;
+        if (nb2 > 0) {
+            const volatile int* w = p->st_host + slot * kStWords;
+            if (w[9] != k_end) {
+                gbp_set_error("loop status out of order (launch %d reported, %d expected)", w[9], k_end);
+                return GBP_ERR_HIP;
+            }
+            for (int x = 0; x < (fwd ? 8 : 1); ++x) left += w[x];
+            err = w[8];
+        } else {
+            const GbpCtl& c = p->ctl_host[1 + slot];
+            if (fwd)
+                for (int x = 0; x < 8; ++x) left += c.qcnt[k_end % 3][x];
+            else
+                left = c.count[k_end % 3];
+            err = c.err;
+        }
+        if (err) return gbp_err_from_bits(err);
+        if (left == 0) {
             finished = true;
             return GBP_OK;
         }
         if (nb2 <= 0) return GBP_OK;              // cap reached
-        slot = other;
+        slot ^= 1;
     }
 }
 
@@ -1354,7 +1390,7 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     return GBP_OK;
 }
 
-static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
+static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s, int* st = nullptr) {
     const int* qin = p->q[r & 1];
     int* qout = p->q[(r + 1) & 1];
     const int grid = std::min(p->sweep_blocks, kStatBlocks);
@@ -1363,7 +1399,7 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s) {
     k_sweep<TS, LN, SV><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, \
                                              qin, qout, p->adj_ptr, p->adj, p->mark, p->ctl,     \
                                              p->blk, r, p->eps_rel, p->n_v, p->xq, p->lip,       \
-                                             p->fista_iters)
+                                             p->fista_iters, st)
 #define GBP_SWEEP_LANES(TS, SV)                         \
     do {                                                \
         if (p->lanes == 8) GBP_SWEEP(TS, 8, SV);        \
@@ -1403,12 +1439,7 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
         for (; r < budget; ++r) launch_round(p, cold, r, s);
     } else {
         rc = run_pipelined(
-            p, s, p->max_rounds, [&](int k) { launch_round(p, cold, k, s); },
-            [](const GbpCtl& c, int k_end) {
-                int left = 0;
-                for (int x = 0; x < 8; ++x) left += c.qcnt[k_end % 3][x];
-                return left == 0;
-            },
+            p, s, p->max_rounds, true, [&](int k, int* st) { launch_round(p, cold, k, s, st); },
             r, converged);
         if (rc) {
             k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);   // stamps used so far stay retired
@@ -1496,14 +1527,14 @@ extern "C" int gbp_backward_info(gbp_plan p, int* levels, int* cyclic, int* gs_s
     return GBP_OK;
 }
 
-static void launch_level(gbp_plan p, int level, hipStream_t s) {
+static void launch_level(gbp_plan p, int level, hipStream_t s, int* st = nullptr) {
     ProfScope ps(GBP_PROF_ADJ_LEVEL, s);
     const int need = gbp_blocks(p->n_v, TPB);
     const int grid = std::max(std::max(1, gbp_blocks(p->n_v, (long long)TPB * kLevelPer)),
                               std::min(need, p->level_blocks));
     k_adj_level<<<grid, TPB, 0, s>>>(
         p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam, p->done, p->pnode, p->pa, p->cslot,
-        p->contrib, p->partner, p->pairrem, p->rem, p->n_v, p->ctl, level);
+        p->contrib, p->partner, p->pairrem, p->rem, p->n_v, p->ctl, level, st);
 }
 
 static void launch_gs(gbp_plan p, int it, hipStream_t s) {
@@ -1558,8 +1589,8 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     } else {
         bool empty = false;
         rc = run_pipelined(
-            p, s, p->max_rounds + n_v, [&](int k) { launch_level(p, k, s); },
-            [](const GbpCtl& c, int k_end) { return c.count[k_end % 3] == 0; }, level, empty);
+            p, s, p->max_rounds + n_v, false, [&](int k, int* st) { launch_level(p, k, s, st); },
+            level, empty);
         if (rc) return rc;
     }
     // vertices on or above cycles longer than two: Gauss-Seidel on the remainder

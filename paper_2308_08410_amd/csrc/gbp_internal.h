@@ -113,6 +113,8 @@ struct gbp_plan_s {
     GbpCtl* ctl = nullptr;        // device control block
     unsigned long long* blk = nullptr;  // [2 * kStatBlocks] per-block (solves, updates)
     GbpCtl* ctl_host = nullptr;   // pinned mirror [3]: [0] status reads, [1..2] pipelined checks
+    int* st_host = nullptr;       // pinned, device-mapped [2][kStWords]: loop status written by
+    int* st_dev = nullptr;        //   the first launch of a batch (st_dev: its device address)
     hipEvent_t ev[2] = {nullptr, nullptr};   // completion of the pipelined status copies
 
     // backward workspace (allocated on first use)
@@ -139,6 +141,12 @@ struct gbp_plan_s {
 };
 
 constexpr int kStatBlocks = 2048;   // max grid of the relaxation kernels
+// Loop status words a relaxation round or adjoint level writes for the host when
+// asked: [0..7] work left (the round's sub-queue lengths; a level: [0] its work
+// flag), [8] device error bits, [9] the launch index that wrote them.  They live
+// in coherent pinned host memory: the host reads them after an event that follows
+// the writing launch, when the launch's writes have completed.
+constexpr int kStWords = 16;
 // Adjoint entries: the first kChildSlots children of vertex x hand over their
 // alpha * lambda in fixed slots contrib[x * kChildSlots + r] (rank r in the
 // sorted child list), further ones at contrib[n_v * kChildSlots + k] (k = the

@@ -78,6 +78,7 @@ static void plan_free(gbp_plan p) {
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+    if (p->st_host) (void)hipHostFree(p->st_host);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
     delete p;
@@ -314,13 +315,21 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
         return GBP_ERR_HIP;
     }
     if (hipHostMalloc((void**)&p->ctl_host, 3 * sizeof(GbpCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&p->st_host, 2 * kStWords * sizeof(int),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev[1], hipEventDisableTiming) != hipSuccess) {
         gbp_set_error("hipHostMalloc failed");
         plan_free(p);
         return GBP_ERR_NOMEM;
     }
+    if (hipHostGetDevicePointer((void**)&p->st_dev, p->st_host, 0) != hipSuccess || !p->st_dev) {
+        gbp_set_error("hipHostGetDevicePointer failed");
+        plan_free(p);
+        return GBP_ERR_HIP;
+    }
     memset(p->ctl_host, 0, 3 * sizeof(GbpCtl));
+    memset(p->st_host, 0xff, 2 * kStWords * sizeof(int));
     *out = p;
     return GBP_OK;
 }
