@@ -562,6 +562,7 @@ __device__ __forceinline__ double parent_face64(int t, int K, int self, const in
 // its own lane.  Same values, same tie rule: the result does not depend on where
 // a candidate was solved.
 constexpr int kParCands = 512;   // FP64 candidates per block held in LDS
+constexpr int kParLanes = 8;     // lanes per vertex: 3 passes cover a 24-element patch
 
 template <int L>
 __global__ void __launch_bounds__(TPB)
@@ -1487,9 +1488,9 @@ extern "C" int gbp_eikonal_forward(gbp_plan p, const float* D, const float* vsca
 static int run_parents(gbp_plan p, const float* D_in, hipStream_t s) {
     const int n_v = p->n_v;
     ProfScope ps(GBP_PROF_PARENT, s);
-    k_parent<16><<<gbp_blocks(16LL * n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg,
-                                                             p->tet_user, D_in, p->vs, p->xyz, p->T,
-                                                             p->troot, n_v, p->par, p->pa);
+    k_parent<kParLanes><<<gbp_blocks((long long)kParLanes * n_v, TPB), TPB, 0, s>>>(
+        p->nptr, p->nent, p->tetv, p->tetg, p->tet_user, D_in, p->vs, p->xyz, p->T, p->troot, n_v,
+        p->par, p->pa);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
