@@ -172,19 +172,31 @@ __global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCt
 }
 
 // ------------------------------------------------------------------ preparation
-__global__ void k_vscale_in(const float* __restrict__ vs_user, const int* __restrict__ node_user,
-                            float* __restrict__ vs, int n_v, GbpCtl* ctl) {
+// Per-vertex inputs of a call, internal order: the velocity scale (1 without
+// one; a scale that is not finite and > 0 flags an error), the onsets reset to
+// +inf, and T: +inf (T_init null, a cold start) or T_init (NaN read as +inf).
+__global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __restrict__ T_init,
+                            const int* __restrict__ node_user, float* __restrict__ vs,
+                            float* __restrict__ troot, float* __restrict__ T, int n_v, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
+    const int u = node_user[i];
     float s = 1.f;
     if (vs_user) {
-        s = vs_user[node_user[i]];
+        s = vs_user[u];
         if (!(s > 0.f) || !finitef(s)) {
             atomicOr(&ctl->err, ERRBIT_VSCALE);
             s = 1.f;
         }
     }
     vs[i] = s;
+    troot[i] = GBP_INF;
+    float t = GBP_INF;
+    if (T_init) {
+        t = T_init[u];
+        if (t != t) t = GBP_INF;
+    }
+    T[i] = t;
 }
 
 // Per element: M = D_eff^{-1} = D^{-1} / sbar^2 and G = F^T M F (F: edges from v0).
@@ -227,20 +239,6 @@ __global__ void k_metric(const float* __restrict__ D, const int* __restrict__ te
     const float G23 = F2x * M3x + F2y * M3y + F2z * M3z;
     tetg[2 * (size_t)j] = make_float4(G11, G22, G33, G12);
     tetg[2 * (size_t)j + 1] = make_float4(G13, G23, sbar, 0.f);
-}
-
-__global__ void k_fill(float* __restrict__ x, float v, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = v;
-}
-
-__global__ void k_gather_in(const float* __restrict__ src_user, const int* __restrict__ node_user,
-                            float* __restrict__ dst, int n_v) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_v) return;
-    float x = src_user[node_user[i]];
-    if (x != x) x = GBP_INF;
-    dst[i] = x;
 }
 
 __global__ void k_scatter_out(const float* __restrict__ src, const int* __restrict__ node_int,
@@ -1104,22 +1102,20 @@ __global__ void k_grad_tet(const int4* __restrict__ tetv, const float4* __restri
     dsbar[j] = gs;
 }
 
-// dL/ds_n = 1/4 sum over the elements of n of dL/dsbar_j; 16 lanes per vertex,
-// fixed reduction order.
+// dL/ds_n = 1/4 sum over the elements of n of dL/dsbar_j; L lanes per vertex (8: three
+// passes over a 24-element patch), fixed reduction order.
+template <int L>
 __global__ void k_grad_node(const int2* __restrict__ nptr, const int* __restrict__ nent,
                             const float* __restrict__ dsbar, const int* __restrict__ node_user,
                             int n_v, float* __restrict__ dvs_user) {
-    const int lane = threadIdx.x & 15;
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (i >= n_v) return;                           // uniform over the 16-lane group
+    const int lane = threadIdx.x & (L - 1);
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    if (i >= n_v) return;                           // uniform over the L-lane group
     const int2 p = nptr[i];
     const int tot = (p.y & 255) + ((p.y >> 8) & 255) + ((p.y >> 16) & 255) + ((p.y >> 24) & 255);
     float s = 0.f;
-    for (int c = lane; c < tot; c += 16) s += dsbar[nent[p.x + c]];
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
+    for (int c = lane; c < tot; c += L) s += dsbar[nent[p.x + c]];
+    for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) dvs_user[node_user[i]] = 0.25f * s;
 }
 
@@ -1370,7 +1366,9 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     const int n_v = p->n_v, n_e = p->n_e;
     k_mark_reset_if<<<std::min(gbp_blocks(n_v, TPB), 1024), TPB, 0, s>>>(p->mark, n_v, p->ctl);
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, cold == 2 ? 1 : 0);
-    k_vscale_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, p->node_user, p->vs, n_v, p->ctl);
+    k_vertex_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, cold == 1 ? nullptr : T_init,
+                                                     p->node_user, p->vs, p->troot, p->T, n_v,
+                                                     p->ctl);
     {
         ProfScope ps(GBP_PROF_METRIC, s);
         k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs,
@@ -1379,11 +1377,6 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
             k_fista_lip<<<gbp_blocks(4LL * n_e, TPB), TPB, 0, s>>>(p->tetg, n_e, p->fista_lmode,
                                                                    p->lip);
     }
-    k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, GBP_INF, n_v);
-    if (cold == 1)
-        k_fill<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, GBP_INF, n_v);
-    else   // 0: warm start from T_init; 2: T given (backward, parent map)
-        k_gather_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(T_init, p->node_user, p->T, n_v);
     k_roots<<<1, TPB, 0, s>>>(root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T,
                               cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl,
                               p->xq);
@@ -1630,8 +1623,8 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     k_grad_tet<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(p->tetv, p->tetg, p->xyz, D, p->tet_user,
                                                     p->par, p->pa, p->lam, n_e, dL_dD, p->dsbar);
     if (dL_dvscale)
-        k_grad_node<<<gbp_blocks(16LL * n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->dsbar,
-                                                                p->node_user, n_v, dL_dvscale);
+        k_grad_node<8><<<gbp_blocks(8LL * n_v, TPB), TPB, 0, s>>>(p->nptr, p->nent, p->dsbar,
+                                                                  p->node_user, n_v, dL_dvscale);
     if (dL_droot_t && n_roots > 0)
         k_grad_root<<<gbp_blocks(n_roots, TPB), TPB, 0, s>>>(root_node, root_t, n_roots,
                                                              p->node_int, n_v, p->par, p->troot,
