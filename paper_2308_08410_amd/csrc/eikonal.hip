@@ -704,10 +704,14 @@ __device__ __forceinline__ void face_nodes_rt(const int4 v, int K, int& a, int& 
 // partners when each is a weighted parent of the other (the anisotropic scheme
 // is not causal).  The mutual edges are left out of the readiness counts; the
 // pair is solved jointly once both members' other children are finished.
+// (Also clears the child counters and fill cursors the next kernels accumulate into.)
 __global__ void k_pnodes(const int* __restrict__ par, const float4* __restrict__ pa,
-                         const int4* __restrict__ tetv, int n_v, int4* __restrict__ pnode) {
+                         const int4* __restrict__ tetv, int n_v, int4* __restrict__ pnode,
+                         int* __restrict__ cnt, int* __restrict__ cfill) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_v) return;
+    cnt[c] = 0;
+    cfill[c] = 0;
     const int pr = par[c];
     int4 out = make_int4(-1, -1, -1, -1);
     if (pr >= 0) {
@@ -755,18 +759,15 @@ __global__ void k_partner_fix(int* __restrict__ partner, int* __restrict__ pairr
     if (r < 0) pairrem[a] = 0;
 }
 
-__global__ void k_child_count(const int4* __restrict__ pnode, const int* __restrict__ partner,
-                              int n_v, int* __restrict__ cnt_all, int* __restrict__ cnt_wait) {
+// Children per vertex.  (A vertex waits for all of them but its two-cycle
+// partner, which is always among them: see k_adj_init.)
+__global__ void k_child_count(const int4* __restrict__ pnode, int n_v, int* __restrict__ cnt) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_v) return;
     const int4 pn = pnode[c];
     const int f[3] = {pn.x, pn.y, pn.z};
-    const int q = partner[c];
     for (int k = 0; k < 3; ++k)
-        if (f[k] >= 0) {
-            atomicAdd(&cnt_all[f[k]], 1);
-            if (f[k] != q) atomicAdd(&cnt_wait[f[k]], 1);
-        }
+        if (f[k] >= 0) atomicAdd(&cnt[f[k]], 1);
 }
 
 __global__ void k_child_fill(const int4* __restrict__ pnode, const float4* __restrict__ pa,
@@ -836,8 +837,11 @@ constexpr int kRdyWait = 0x7ffffffe;    // first member of a two-cycle, partner 
 constexpr int kRdyDone = 0x7ffffffd;    // finished
 constexpr int kLevelPer = 8;            // vertices per thread in a level scan (grid >= n_v / (8 TPB))
 
+// rem: the children a vertex waits for, all of them (the CSR range) but its
+// two-cycle partner, which is one of them (partners are parents of each other).
 __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __restrict__ node_user,
-                           const float* __restrict__ T, const int* __restrict__ rem, int n_v,
+                           const float* __restrict__ T, const int* __restrict__ cptr,
+                           const int* __restrict__ partner, int* __restrict__ rem, int n_v,
                            float* __restrict__ g, float* __restrict__ lam, int* __restrict__ done,
                            int* __restrict__ rdy, float* __restrict__ contrib, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -852,7 +856,9 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
     g[i] = gi;
     lam[i] = gi;
     done[i] = reached ? 0 : 1;
-    const bool leaf = reached && rem[i] == 0;
+    const int wait = cptr[i + 1] - cptr[i] - (partner[i] >= 0 ? 1 : 0);
+    rem[i] = wait;
+    const bool leaf = reached && wait == 0;
     rdy[i] = leaf ? 0 : kRdyNever;
     if (leaf) ctl->count[0] = 1;   // flag: the first launch has work
 }
@@ -1556,14 +1562,12 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     {
         ProfScope ps_child(GBP_PROF_CHILD, s);
         const int nb = gbp_blocks(n_v, TPB);
-        k_fill_i<<<nb, TPB, 0, s>>>(p->rem, 0, n_v);
-        k_fill_i<<<nb, TPB, 0, s>>>(p->done, 0, n_v);   // all-children counts
-        k_fill_i<<<nb, TPB, 0, s>>>(p->cfill, 0, n_v);
-        k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode);
+        // p->done holds the child counts until the scan
+        k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode, p->done, p->cfill);
         k_partner<<<nb, TPB, 0, s>>>(p->pnode, n_v, p->partner);
         k_partner_sym<<<nb, TPB, 0, s>>>(p->partner, n_v, p->pairrem);
         k_partner_fix<<<nb, TPB, 0, s>>>(p->partner, p->pairrem, n_v);
-        k_child_count<<<nb, TPB, 0, s>>>(p->pnode, p->partner, n_v, p->done, p->rem);
+        k_child_count<<<nb, TPB, 0, s>>>(p->pnode, n_v, p->done);
         GBP_LAUNCH_CHECK();
         if ((rc = gbp_scan_exclusive(p->done, p->ccnt, n_v, p->scan_tmp, s))) return rc;
         k_child_fill<<<nb, TPB, 0, s>>>(p->pnode, p->pa, n_v, p->ccnt, p->cfill, p->cchild,
@@ -1574,8 +1578,9 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
     }
     // leaves-first level walk
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, 2);
-    k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->rem, n_v, p->g,
-                                                    p->lam, p->done, p->rdy, p->contrib, p->ctl);
+    k_adj_init<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(dL_dT, p->node_user, p->T, p->ccnt, p->partner,
+                                                    p->rem, n_v, p->g, p->lam, p->done, p->rdy,
+                                                    p->contrib, p->ctl);
     GBP_LAUNCH_CHECK();
     int level = 0;
     if (!sync) {
