@@ -174,12 +174,15 @@ __global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCt
 // ------------------------------------------------------------------ preparation
 // Per-vertex inputs of a call, internal order: the velocity scale (1 without
 // one; a scale that is not finite and > 0 flags an error), the onsets reset to
-// +inf, and T: +inf (T_init null, a cold start) or T_init (NaN read as +inf).
+// +inf, and T: +inf (T_init null, a cold start) or T_init (NaN read as +inf);
+// the queue marks are cleared when the control reset restarted the stamps.
 __global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __restrict__ T_init,
                             const int* __restrict__ node_user, float* __restrict__ vs,
-                            float* __restrict__ troot, float* __restrict__ T, int n_v, GbpCtl* ctl) {
+                            float* __restrict__ troot, float* __restrict__ T,
+                            int* __restrict__ mark, int n_v, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
+    if (ctl->marks_stale) mark[i] = 0;   // the stamps restarted from 1
     const int u = node_user[i];
     float s = 1.f;
     if (vs_user) {
@@ -247,8 +250,18 @@ __global__ void k_scatter_out(const float* __restrict__ src, const int* __restri
     if (u < n_v) dst_user[u] = src[node_int[u]];
 }
 
-// Roots: sequential min (deterministic for duplicates), then (cold start) push
-// the neighbours of every root into the first queue.
+// min(*a, v) for a finite v, as one atomic: floats with the sign bit clear order
+// like their bits as signed ints, those with it set (-0 included) in reverse like
+// their bits as unsigned ints, and every sign-set pattern is above every
+// sign-clear one as unsigned, below it as signed.
+__device__ __forceinline__ void atomic_min_float(float* a, float v) {
+    if (__float_as_int(v) >= 0) atomicMin(reinterpret_cast<int*>(a), __float_as_int(v));
+    else atomicMax(reinterpret_cast<unsigned*>(a), __float_as_uint(v));
+}
+
+// Roots: the smallest onset per vertex (one thread per root; a minimum, so
+// duplicates resolve the same in any order), then (cold start) push the
+// neighbours of every root into the first queue.
 __global__ void k_roots(const int* __restrict__ root_node, const float* __restrict__ root_t,
                         int n_roots, const int* __restrict__ node_int, int n_v,
                         float* __restrict__ troot, float* __restrict__ T, int cold,
@@ -256,22 +269,20 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
                         int* __restrict__ qout, int* __restrict__ mark, GbpCtl* ctl,
                         XcdQueues xq) {
     const int stamp = ctl->stamp;
-    if (threadIdx.x == 0) {
-        for (int r = 0; r < n_roots; ++r) {
-            const int u = root_node[r];
-            const float t = root_t[r];
-            if (u < 0 || u >= n_v) {
-                atomicOr(&ctl->err, ERRBIT_ROOT_RANGE);
-                continue;
-            }
-            if (!finitef(t)) {
-                atomicOr(&ctl->err, ERRBIT_ROOT_NONFINITE);
-                continue;
-            }
-            const int i = node_int[u];
-            troot[i] = fminf(troot[i], t);
-            if (cold) T[i] = fminf(T[i], t);
+    for (int r = threadIdx.x; r < n_roots; r += blockDim.x) {
+        const int u = root_node[r];
+        const float t = root_t[r];
+        if (u < 0 || u >= n_v) {
+            atomicOr(&ctl->err, ERRBIT_ROOT_RANGE);
+            continue;
         }
+        if (!finitef(t)) {
+            atomicOr(&ctl->err, ERRBIT_ROOT_NONFINITE);
+            continue;
+        }
+        const int i = node_int[u];
+        atomic_min_float(&troot[i], t);
+        if (cold) atomic_min_float(&T[i], t);
     }
     __syncthreads();
     if (!cold) return;
@@ -308,18 +319,12 @@ __global__ void k_ctl_reset(GbpCtl* ctl, int keep_fwd) {
         const int st = keep_fwd ? (ctl->status & 1) : 0;
         const int err = keep_fwd == 2 ? ctl->err : 0;   // 2: mid-call reset, keep input errors
         GbpCtl z{};
-        z.stamp = stamp > (1 << 30) ? 1 : stamp;
+        z.marks_stale = stamp > (1 << 30) ? 1 : 0;
+        z.stamp = z.marks_stale ? 1 : stamp;
         z.status = st;
         z.err = err;
         *ctl = z;
     }
-}
-
-// Stamps restart from 1 before they could overflow: clear the marks first.
-__global__ void k_mark_reset_if(int* __restrict__ mark, int n_v, const GbpCtl* ctl) {
-    if (ctl->stamp <= (1 << 30)) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_v; i += gridDim.x * blockDim.x)
-        mark[i] = 0;
 }
 
 // After `launched` relaxation rounds: advance the stamp base past every stamp
@@ -1370,11 +1375,10 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
                    const float* root_t, int n_roots, int cold, const float* T_init,
                    hipStream_t s) {
     const int n_v = p->n_v, n_e = p->n_e;
-    k_mark_reset_if<<<std::min(gbp_blocks(n_v, TPB), 1024), TPB, 0, s>>>(p->mark, n_v, p->ctl);
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, cold == 2 ? 1 : 0);
     k_vertex_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, cold == 1 ? nullptr : T_init,
-                                                     p->node_user, p->vs, p->troot, p->T, n_v,
-                                                     p->ctl);
+                                                     p->node_user, p->vs, p->troot, p->T, p->mark,
+                                                     n_v, p->ctl);
     {
         ProfScope ps(GBP_PROF_METRIC, s);
         k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs,

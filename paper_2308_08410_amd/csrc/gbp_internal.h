@@ -56,7 +56,7 @@ struct GbpCtl {
     int stamp;                     // queue stamp base, kept across calls
     int status;                    // bit 0: forward not converged, bit 1: adjoint not settled
     int levels;                    // adjoint: last level with work + 1
-    int pad;
+    int marks_stale;               // set by a reset that restarted the stamps: clear the marks
     int qcnt[3][8];                // forward: rotating lengths of the 8 sub-queues
 };
 

@@ -162,6 +162,24 @@ def test_duplicate_roots_and_unreached_component():
     assert Tg[0] == pytest.approx(0.1)
 
 
+def test_duplicate_roots_with_negative_and_signed_zero_onsets():
+    """Several roots per vertex with onsets of both signs (and -0): each vertex takes
+    its smallest onset, whatever order the roots are applied in."""
+    dev = _dev()
+    xyz, tets = gi.kuhn_cube(5)
+    D = np.tile(np.array([[1, 1, 1, 0, 0, 0]], np.float32), (len(tets), 1))
+    rn = np.array([0, 0, 0, 40, 40, 40, 100, 100, 7], np.int32)
+    rt = np.array([0.2, -0.3, 0.1, -0.0, 0.5, 0.0, -0.05, -0.5, 0.0], np.float32)
+    plan = B().Plan(xyz, tets)
+    for perm in (np.arange(len(rn)), np.arange(len(rn))[::-1].copy()):
+        T, st = B().eikonal_forward(plan, t32(D, dev), None, i32(rn[perm], dev), t32(rt[perm], dev))
+        Tg = T.cpu().numpy()
+        To, _ = O.solve(xyz, tets, D, None, rn, rt)
+        assert st["converged"]
+        assert Tg[0] == np.float32(-0.3) and Tg[100] == np.float32(-0.5) and Tg[40] == 0.0
+        assert np.abs(Tg - To).max() <= 1e-4 * np.abs(To).max()
+
+
 def test_no_roots_all_unreached():
     dev = _dev()
     xyz, tets = gi.kuhn_cube(2)
