@@ -180,6 +180,36 @@ def test_duplicate_roots_with_negative_and_signed_zero_onsets():
         assert np.abs(Tg - To).max() <= 1e-4 * np.abs(To).max()
 
 
+def test_round_cap_reports_not_converged(shell):
+    """A plan capped well below the rounds a solve needs stops at the cap (in the
+    first batch of launches, at the end of one, or inside one), reports
+    GBP_ERR_NOT_CONVERGED and still writes T: an upper bound on the converged
+    times, since the relaxation descends from +inf.  With room to spare it
+    converges.  (The exact round count varies by a round or two between runs: the
+    order of updates inside a round is not fixed.)"""
+    c = shell
+    R = c.stats["rounds"]
+    assert R > 16
+    T_ref = c.T_gpu.astype(np.float64)
+    for cap in (1, 3, 4, 5, 12, 13, R // 2, R + 8):
+        plan = B().Plan(c.p.xyz, c.p.tets, max_rounds=cap)
+        out = torch.full((c.p.n_v,), float("nan"), device=c.dev)
+        print(f"[case] round cap {cap} of {R}", flush=True)
+        if cap < R:
+            with pytest.raises(B().GbpError) as e:
+                B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt, out=out)
+            assert e.value.name == "GBP_ERR_NOT_CONVERGED"
+            Tc = out.cpu().numpy().astype(np.float64)
+            assert not np.isnan(Tc).any()
+            fin = np.isfinite(Tc)
+            assert np.all(Tc[fin] >= T_ref[fin] - 1e-5 * np.abs(T_ref).max())
+            assert fin.sum() < len(Tc) or np.abs(Tc - T_ref).max() > 0
+        else:
+            T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt, out=out)
+            assert st["converged"]
+            assert np.abs(T.cpu().numpy() - c.T_gpu).max() <= 1e-5 * np.abs(c.T_gpu).max()
+
+
 def test_no_roots_all_unreached():
     dev = _dev()
     xyz, tets = gi.kuhn_cube(2)
