@@ -156,6 +156,34 @@ int gbp_plan_set_local_solver(gbp_plan plan, int solver, int n_f, int lipschitz_
 int gbp_plan_get_local_solver(gbp_plan plan, int *solver, int *n_f, int *lipschitz_mode);
 
 /*
+ * gbp_plan_set_fista_tolerance / gbp_plan_get_fista_tolerance -- iterations per
+ * face for the FISTA solver from its rate, Eq. (fista_convergence), as Sec. 2.5
+ * proposes (n_f per element): after k iterations from alpha = 1/3 the value is
+ * at most 2 L ||alpha_0 - alpha*||^2 / (k+1)^2 above the minimum, and
+ * ||alpha_0 - alpha*||^2 <= 2/3 on the simplex, so a face with step constant L
+ * runs the least k with k + 1 >= sqrt(4 L / (3 tau)), at least 1 and at most the
+ * n_f of gbp_plan_set_local_solver (FP32: product, quotient, root, each rounded).
+ *   tau  value tolerance of a local problem (time units); 0 (the default): every
+ *        face runs n_f iterations
+ * The error bound holds with the step constant of Eq. (lipschitz_est)
+ * (lipschitz_mode 0); with the tightened one it is the same rule on a smaller L.
+ * Errors: GBP_ERR_ARG for a negative or non-finite tau.
+ */
+int gbp_plan_set_fista_tolerance(gbp_plan plan, float tau);
+int gbp_plan_get_fista_tolerance(gbp_plan plan, float *tau);
+
+/*
+ * gbp_fista_iterations -- the per-face counts of gbp_plan_set_fista_tolerance
+ * for n step constants (Eq. (fista_convergence)).
+ *   lip    device float [n]  step constants L
+ *   tau    tolerance (>= 0; 0 gives n_max everywhere)
+ *   n_max  cap, 1..100000
+ *   n_f    device int [n]    the counts
+ * Errors: GBP_ERR_ARG (sizes, tau, n_max, missing pointers), GBP_ERR_HIP.
+ */
+int gbp_fista_iterations(const float *lip, int n, float tau, int n_max, int *n_f, void *stream);
+
+/*
  * gbp_local_solve -- n independent local problems (Sec. 2.2 Eq.
  * (upwind_eq_lsqr)): min over the simplex of <alpha, Phi> + sqrt(alpha^T Q alpha).
  *   Q6       device float [n*6]  Q = E^T D_eff^-1 E packed (q00, q11, q22, q01, q02, q12)

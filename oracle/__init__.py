@@ -25,6 +25,7 @@ Pieces
                        template, and the objective Eq. (inverse_ecg)
 * ``fista_local``      Alg. 1 (FISTA on the local problem) with the Lipschitz
                        bound Eq. (lipschitz_est) and its tightened variant (Sec. 2.5)
+* ``fista_iterations`` per-face iteration counts from the rate Eq. (fista_convergence)
 * ``adam_step``        the optimiser used for the inverse problem (Sec. 2.4)
 
 All arithmetic is float64.  Inputs may be float32 arrays (they are upcast).
@@ -526,6 +527,29 @@ def fista_local(Q, Phi, L, n_f):
         a_prev = a_k
         hist.append(a_k @ Phi + np.sqrt(a_k @ Q @ a_k))
     return a_k, float(a_k @ Phi + np.sqrt(a_k @ Q @ a_k)), np.asarray(hist)
+
+
+def fista_iterations(L, tau, n_max, d=3):
+    """Per-face iteration count from the rate Eq. (fista_convergence), as Sec. 2.5
+    suggests (n_f on an element basis): after k iterations from alpha_0 = 1/d the
+    error is at most 2 L ||alpha_0 - alpha*||^2 / (k+1)^2, and ||alpha_0 - alpha||^2
+    <= (d-1)/d over the simplex (its farthest points from the barycentre are the
+    vertices), so k + 1 >= sqrt(2 (d-1)/d L / tau) guarantees an error <= tau
+    whenever L is a Lipschitz constant of grad h.  At least 1, at most n_max;
+    n_max for tau <= 0 or a non-finite bound.  The integer is decided in float32,
+    the precision of the device (products and quotient rounded in that order):
+    x = sqrt((c * L) / tau), c = 2 (d-1)/d, k = ceil(x) - 1."""
+    L = np.asarray(L, dtype=np.float32)
+    out = np.full(L.shape, int(n_max), dtype=np.int64)
+    if not tau > 0:
+        return out
+    c = np.float32(2.0 * (d - 1) / d)
+    with np.errstate(all="ignore"):
+        x = np.sqrt((c * L) / np.float32(tau))
+    ok = x < np.float32(n_max + 1)                     # False for NaN and +inf
+    k = np.ceil(x[ok]).astype(np.int64) - 1
+    out[ok] = np.maximum(k, 1)
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -113,6 +113,9 @@ _point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_
 _locate = _sig("gbp_locate_points", [c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p])
 _set_solver = _sig("gbp_plan_set_local_solver", [c_void_p, c_int, c_int, c_int])
 _get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
+_set_fista_tol = _sig("gbp_plan_set_fista_tolerance", [c_void_p, c_float])
+_get_fista_tol = _sig("gbp_plan_get_fista_tolerance", [c_void_p, ctypes.POINTER(c_float)])
+_fista_iters = _sig("gbp_fista_iterations", [c_void_p, c_int, c_float, c_int, c_void_p, c_void_p])
 _local_solve = _sig("gbp_local_solve", [c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p,
                                         c_void_p, c_void_p, c_void_p])
 _lead_field = _sig("gbp_lead_field", [c_void_p, c_void_p, c_int, c_void_p, c_void_p])
@@ -462,6 +465,28 @@ def set_local_solver(plan: Plan, solver="exact", n_f=32, lipschitz="tight"):
     s = {"exact": 0, "fista": 1}[solver]
     m = {"bound": 0, "tight": 1}[lipschitz]
     _check(_set_solver(plan.handle, s, int(n_f), m))
+
+
+def set_fista_tolerance(plan: Plan, tau: float):
+    """Per-face FISTA iterations from the rate Eq. (fista_convergence) for value
+    tolerance tau (capped by the n_f of set_local_solver); 0 turns it off."""
+    _check(_set_fista_tol(plan.handle, float(tau)))
+
+
+def get_fista_tolerance(plan: Plan) -> float:
+    v = c_float()
+    _check(_get_fista_tol(plan.handle, ctypes.byref(v)))
+    return v.value
+
+
+def fista_iterations(lip, tau: float, n_max: int, out=None, stream=None):
+    """Per-face FISTA iteration counts for step constants lip [n] (int32 [n])."""
+    n = lip.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=lip.device)
+    _check(_fista_iters(_ptr(lip, torch.float32, (n,), "lip"), n, float(tau), int(n_max),
+                        _ptr(out, torch.int32, (n,), "n_f"), _stream(stream)))
+    return out
 
 
 def get_local_solver(plan: Plan):

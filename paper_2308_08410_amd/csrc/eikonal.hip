@@ -373,20 +373,24 @@ __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restric
 // 32, autotuned); lane c evaluates local problems c and c+L of the vertex's patch (slot picked at run
 // time, both problems' loads in flight together), a 16-lane min-reduction forms
 // the Hopf-Lax minimum, and on a change the lanes push the unique neighbours.
-// SOLVER 0: the exact predicated solve; 1: n_f iterations of Alg. 1 with the
-// face's step constant lip[4 t + K].
+// SOLVER 0: the exact predicated solve; 1: Alg. 1 with the face's step constant
+// lip[4 t + K], n_f iterations (tau = 0) or the face's count for tolerance tau.
 template <int SOLVER>
 __device__ __forceinline__ float face_value(const int* __restrict__ nent,
                                             const int4* __restrict__ tetv,
                                             const float4* __restrict__ tetg, const float* T,
-                                            int e, int K, const float* __restrict__ lip, int n_f) {
+                                            int e, int K, const float* __restrict__ lip, int n_f,
+                                            float tau) {
     const int t = nent[e];
     const int4 v = tetv[t];
     const float4 g0 = tetg[2 * (size_t)t], g1 = tetg[2 * (size_t)t + 1];
     int a, b, cc;
     face_nodes_sel(v, K, a, b, cc);
     if constexpr (SOLVER == 0) return local_min<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc]);
-    else return local_fista<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc], lip[4 * (size_t)t + K], n_f);
+    else {
+        const float L = lip[4 * (size_t)t + K];
+        return local_fista<false>(face_q_rt(g0, g1, K), T[a], T[b], T[cc], L, fista_iters(L, tau, n_f));
+    }
 }
 
 template <bool TWO_SIDED, int L, int SOLVER>
@@ -397,7 +401,7 @@ __global__ void __launch_bounds__(TPB)
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
             float eps_rel, int n_v, XcdQueues xq, const float* __restrict__ lip, int n_f,
-            int* __restrict__ st) {
+            float tau, int* __restrict__ st) {
     constexpr int PER_BLOCK = TPB / L;
     // blocks are placed on the 8 XCDs round-robin: with the split layout block b
     // serves sub-queue b % 8, else every block serves the one queue
@@ -455,9 +459,9 @@ __global__ void __launch_bounds__(TPB)
             const bool okd = d < tot;
             const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
             const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
-            const float vc = face_value<SOLVER>(nent, tetv, tetg, T, p.x + c, Kc, lip, n_f);
+            const float vc = face_value<SOLVER>(nent, tetv, tetg, T, p.x + c, Kc, lip, n_f, tau);
             const float vd = face_value<SOLVER>(nent, tetv, tetg, T, p.x + (okd ? d : c),
-                                                okd ? Kd : Kc, lip, n_f);
+                                                okd ? Kd : Kc, lip, n_f, tau);
             best = fminf(best, okd ? fminf(vc, vd) : vc);
             solves += okd ? 2 : 1;
         }
@@ -1403,7 +1407,7 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s, int* st = 
     k_sweep<TS, LN, SV><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, \
                                              qin, qout, p->adj_ptr, p->adj, p->mark, p->ctl,     \
                                              p->blk, r, p->eps_rel, p->n_v, p->xq, p->lip,       \
-                                             p->fista_iters, st)
+                                             p->fista_iters, p->fista_tau, st)
 #define GBP_SWEEP_LANES(TS, SV)                         \
     do {                                                \
         if (p->lanes == 8) GBP_SWEEP(TS, 8, SV);        \

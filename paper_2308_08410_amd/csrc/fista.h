@@ -38,6 +38,21 @@ __device__ __forceinline__ void simplex_proj3(float y0, float y1, float y2, floa
     a2 = fmaxf(y2 - theta, 0.f);
 }
 
+// Iterations for a face with step constant L and value tolerance tau, from the
+// rate Eq. (fista_convergence): 2 L ||alpha_0 - alpha*||^2 / (k+1)^2 <= tau with
+// ||alpha_0 - alpha*||^2 <= 2/3 on the simplex (alpha_0 = 1/3), i.e. the least
+// k with k + 1 >= sqrt(4 L / (3 tau)); at least 1, at most n_max (also for
+// tau <= 0 or a non-finite bound).  Guaranteed with the bound of Eq.
+// (lipschitz_est); with the tightened constant it is the same rule on a
+// heuristic L.  FP32, rounded product then quotient then root.
+__device__ __forceinline__ int fista_iters(float L, float tau, int n_max) {
+    if (!(tau > 0.f)) return n_max;
+    const float x = sqrtf(((4.0f / 3.0f) * L) / tau);
+    if (!(x < (float)(n_max + 1))) return n_max;
+    const int k = (int)ceilf(x) - 1;
+    return k < 1 ? 1 : k;
+}
+
 // n_f FISTA iterations; returns F(alpha_{n_f}) (+inf if no vertex is reached),
 // optionally alpha_{n_f}.
 template <bool WANT_ALPHA>

@@ -106,6 +106,7 @@ struct gbp_plan_s {
     int solver = 0;               // local solver: 0 exact (predicated KKT), 1 FISTA (Alg. 1)
     int fista_iters = 32;         // FISTA iterations per local problem
     int fista_lmode = 1;          // FISTA step constant: 0 Eq. (lipschitz_est), 1 tightened
+    float fista_tau = 0.f;        // > 0: per-face iterations from the rate bound, capped by fista_iters
     float* lip = nullptr;         // [4 n_e] FISTA step constant per face (allocated on use)
     int level_blocks = 2048;      // grid of an adjoint level (scan; at least n_v / (8 * 256))
     int sync_batch = 16;          // launches between convergence checks (synchronous mode)

@@ -2,6 +2,8 @@
 // with either local solver: the exact predicated KKT solve or n_f iterations of
 // FISTA (Alg. 1).  Used to compare the two solvers face by face and to time them
 // per local problem.
+#include <cmath>
+
 #include "fista.h"
 #include "gbp_internal.h"
 
@@ -34,7 +36,29 @@ __global__ void k_local_batch(const float* __restrict__ Q6, const float* __restr
     }
 }
 
+__global__ void k_fista_iters(const float* __restrict__ lip, int n, float tau, int n_max,
+                              int* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = fista_iters(lip[i], tau, n_max);
+}
+
 }  // namespace
+
+extern "C" int gbp_fista_iterations(const float* lip, int n, float tau, int n_max, int* n_f,
+                                    void* stream) {
+    if (n < 0 || n_max < 1 || n_max > 100000 || !(tau >= 0.f) || !std::isfinite(tau)) {
+        gbp_set_error("fista_iterations: n >= 0, n_max 1..100000, tau finite and >= 0");
+        return GBP_ERR_ARG;
+    }
+    if (n == 0) return GBP_OK;
+    if (!lip || !n_f) {
+        gbp_set_error("fista_iterations: lip and n_f are required");
+        return GBP_ERR_ARG;
+    }
+    k_fista_iters<<<gbp_blocks(n, TPB), TPB, 0, (hipStream_t)stream>>>(lip, n, tau, n_max, n_f);
+    GBP_LAUNCH_CHECK();
+    return GBP_OK;
+}
 
 extern "C" int gbp_local_solve(const float* Q6, const float* Phi, int n, int solver, int n_f,
                                const float* lip, int lipschitz_mode, float* value, float* alpha,

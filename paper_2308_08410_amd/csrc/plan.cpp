@@ -18,6 +18,7 @@
 #include <vector>
 
 #include <climits>
+#include <cmath>
 
 #include "gbp_internal.h"
 
@@ -417,6 +418,28 @@ extern "C" int gbp_plan_get_local_solver(gbp_plan p, int* solver, int* n_f, int*
     if (solver) *solver = p->solver;
     if (n_f) *n_f = p->fista_iters;
     if (lipschitz_mode) *lipschitz_mode = p->fista_lmode;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_fista_tolerance(gbp_plan p, float tau) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!(tau >= 0.f) || !std::isfinite(tau)) {
+        gbp_set_error("set_fista_tolerance: tau must be finite and >= 0");
+        return GBP_ERR_ARG;
+    }
+    p->fista_tau = tau;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_fista_tolerance(gbp_plan p, float* tau) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!tau) {
+        gbp_set_error("get_fista_tolerance: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    *tau = p->fista_tau;
     return GBP_OK;
 }
 

@@ -124,3 +124,23 @@ def test_local_solve_and_lead_field_validate_before_gpu():
     assert f(fake, fake, 4, 1, 8, None, 3, fake, None, None, None) == -1         # step-constant mode
     assert f(None, fake, 4, 0, 1, None, 1, fake, None, None, None) == -1         # missing Q
     assert f(fake, fake, 0, 0, 1, None, 1, None, None, None, None) == 0          # empty batch
+
+
+def test_fista_iterations_validate_before_gpu():
+    lib = ctypes.CDLL(LIB)
+    f = lib.gbp_fista_iterations
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_void_p]
+    fake = ctypes.c_void_p(16)   # never dereferenced: the checks run first
+    assert f(fake, -1, 1e-3, 32, fake, None) == -1               # n < 0
+    assert f(fake, 4, -1e-3, 32, fake, None) == -1               # negative tolerance
+    assert f(fake, 4, float("nan"), 32, fake, None) == -1        # NaN tolerance
+    assert f(fake, 4, float("inf"), 32, fake, None) == -1        # infinite tolerance
+    assert f(fake, 4, 1e-3, 0, fake, None) == -1                 # n_max < 1
+    assert f(fake, 4, 1e-3, 100001, fake, None) == -1            # n_max too large
+    assert f(None, 4, 1e-3, 32, fake, None) == -1                # missing lip
+    assert f(fake, 4, 1e-3, 32, None, None) == -1                # missing output
+    assert f(None, 0, 0.0, 1, None, None) == 0                   # empty batch
+    plan_set = lib.gbp_plan_set_fista_tolerance
+    plan_set.argtypes = [ctypes.c_void_p, ctypes.c_float]
+    assert plan_set(None, 1e-3) != 0                             # no plan

@@ -142,3 +142,87 @@ def test_fista_forward_converges_to_exact():
     B().set_local_solver(plan, "exact")
     T, _ = B().eikonal_forward(plan, D, vs, rn, rt)
     assert rel_max(T.cpu().numpy(), To) <= 1e-4
+
+
+@pytest.mark.parametrize("mode", ["bound", "tight"])
+def test_fista_iterations_match_oracle(faces, mode):
+    """Per-face counts from Eq. (fista_convergence): the same integers as the
+    oracle's rule on the same step constants (both decide in FP32), capped and
+    uncapped."""
+    Q, Phi, Q6, scale = faces
+    dev = _dev()
+    _, _, lip = B().local_solve(t32(Q6, dev), t32(Phi, dev), "fista", n_f=1, lipschitz=mode,
+                                want_alpha=False, want_lip=True)
+    L = lip.cpu().numpy()
+    for tau in (1e-1, 1e-3, 1e-5):
+        for n_max in (100000, 64):
+            n = B().fista_iterations(lip, tau, n_max).cpu().numpy()
+            no = O.fista_iterations(L, tau, n_max)
+            assert np.array_equal(n, no), (tau, n_max, np.flatnonzero(n != no)[:5])
+    assert np.all(B().fista_iterations(lip, 0.0, 17).cpu().numpy() == 17)
+
+
+def test_fista_per_face_counts_meet_tolerance(faces):
+    """With the step constant of Eq. (lipschitz_est) (a true Lipschitz constant)
+    each face's count keeps its value within tau of the exact minimum, up to the
+    FP32 solve's own error; faces with up to 100 iterations match the oracle's
+    iterates at the same count."""
+    Q, Phi, Q6, scale = faces
+    dev = _dev()
+    m = 400
+    Qd, Pd = t32(Q6[:m], dev), t32(Phi[:m], dev)
+    _, _, lip = B().local_solve(Qd, Pd, "fista", n_f=1, lipschitz="bound", want_alpha=False,
+                                want_lip=True)
+    L = lip.cpu().numpy().astype(np.float64)
+    exact = np.array([O.local_solve(Q[i], Phi[i])[0] for i in range(m)])
+    n_parity = 0
+    for tau_rel in (1e-1, 1e-2, 1e-3):
+        tau = float(tau_rel * np.median(scale))
+        n = B().fista_iterations(lip, tau, 100000).cpu().numpy()
+        v = np.empty(m)
+        for k in np.unique(n):
+            idx = np.flatnonzero(n == k)
+            vk, _, _ = B().local_solve(t32(Q6[idx], dev), t32(Phi[idx], dev), "fista", n_f=int(k),
+                                       lip=lip[torch.as_tensor(idx, device=dev)], want_alpha=False)
+            v[idx] = vk.cpu().numpy()
+        slack = 1e-5 * scale[:m]
+        assert np.all(v >= exact - slack)
+        assert np.all(v - exact <= tau + slack), np.max(v - exact - tau)
+        few = np.flatnonzero(n <= 100)
+        n_parity += len(few)
+        vo = np.array([O.fista_local(Q[i], Phi[i], L[i], int(n[i]))[1] for i in few])
+        assert np.all(np.abs(v[few] - vo) <= 1e-4 * scale[few])
+    assert n_parity >= 20
+
+
+def test_fista_tolerance_setting_and_forward():
+    """12k shell: the forward with per-face counts for tolerance tau (step
+    constant of Eq. (lipschitz_est)) converges to times at or above the exact
+    scheme's, at most tau per local problem along the longest chain of rounds
+    above them, and closer with a smaller tau."""
+    dev = _dev()
+    p = gi.shell_problem(12_000, seed=81, n_roots=3, vscale_range=(0.7, 1.3))
+    To, _ = O.solve(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t, eps_abs=0.0, eps_rel=1e-12)
+    plan = B().Plan(p.xyz, p.tets)
+    assert B().get_fista_tolerance(plan) == 0.0
+    with pytest.raises(B().GbpError):
+        B().set_fista_tolerance(plan, -1.0)
+    with pytest.raises(B().GbpError):
+        B().set_fista_tolerance(plan, float("nan"))
+    D, vs, rn, rt = t32(p.D, dev), t32(p.vscale, dev), i32(p.root_node, dev), t32(p.root_t, dev)
+    B().set_local_solver(plan, "fista", 100000, "bound")
+    errs = []
+    for tau in (1e-2, 1e-3):
+        B().set_fista_tolerance(plan, tau)
+        assert B().get_fista_tolerance(plan) == pytest.approx(tau)
+        print(f"[case] fista tolerance {tau}", flush=True)
+        T, st = B().eikonal_forward(plan, D, vs, rn, rt)
+        assert st["converged"]
+        Tg = T.cpu().numpy().astype(np.float64)
+        assert np.all(Tg >= To * (1 - 1e-5) - 1e-6)
+        assert np.max(Tg - To) <= tau * st["rounds"] + 1e-5 * To.max()
+        errs.append(np.max(Tg - To))
+    print(f"[fista tolerance] max err tau=1e-2 {errs[0]:.2e}, tau=1e-3 {errs[1]:.2e}", flush=True)
+    assert errs[1] < errs[0]
+    B().set_fista_tolerance(plan, 0.0)
+    B().set_local_solver(plan, "exact")

@@ -63,3 +63,37 @@ def test_fista_tight_converges_to_exact(seed):
     assert Lt <= O.lipschitz_bound(Q)
     a, v, _ = O.fista_local(Q, Phi, Lt, 3000)
     assert v == pytest.approx(val, rel=1e-6, abs=1e-8)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_fista_iterations_meet_tolerance(seed):
+    """Per-face counts from Eq. (fista_convergence): with the Lipschitz bound of
+    Eq. (lipschitz_est) the value after that many iterations is within tau of the
+    exact minimum, for tolerances from loose to tight; one iteration fewer is not
+    always enough for the bound (the count is the smallest the bound allows)."""
+    r = rng(80 + seed)
+    Q = random_face(r)
+    Phi = r.uniform(-0.5, 0.5, size=3) * np.sqrt(np.trace(Q) / 3)
+    val, astar, _ = O.local_solve(Q, Phi)
+    L = O.lipschitz_bound(Q)
+    for tau in (1e-1, 1e-2, 1e-3, 1e-4):
+        n = int(O.fista_iterations(L, tau, 10 ** 6))
+        _, v, _ = O.fista_local(Q, Phi, L, n)
+        assert v - val <= tau * (1 + 1e-9)
+        # the count is the least k with 2 L (2/3) / (k+1)^2 <= tau (up to float32 rounding)
+        assert 2 * L * (2 / 3) / (n + 1) ** 2 <= tau * (1 + 1e-6)
+        if n > 1:
+            assert 2 * L * (2 / 3) / n ** 2 > tau * (1 - 1e-6)
+
+
+def test_fista_iterations_limits():
+    L = np.array([1.0, 3.0, 1e8, np.inf, np.nan, 0.0], np.float32)
+    assert list(O.fista_iterations(L, 0.0, 50)) == [50] * 6
+    n = O.fista_iterations(L, 1.0, 50)
+    # sqrt(4/3) = 1.15 -> 1 iteration; sqrt(4) = 2 -> 1; capped; non-finite -> cap; L = 0 -> 1
+    assert list(n) == [1, 1, 50, 50, 50, 1]
+    assert list(O.fista_iterations(np.float32(300.0), 1e-2, 10 ** 6)[None]) == [199]
+    # counts never grow as the tolerance loosens
+    taus = np.logspace(-6, 1, 40)
+    c = [int(O.fista_iterations(np.float32(123.4), t, 10 ** 7)) for t in taus]
+    assert all(a >= b for a, b in zip(c, c[1:]))
