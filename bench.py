@@ -104,6 +104,9 @@ def make_state(prob, dev, torch, gi, B):
     """Plan, device inputs, a target ECG from hidden parameters, and the
     parameters being fitted (velocity scale, root onsets) with Adam moments."""
     plan = B.Plan(prob.xyz, prob.tets)
+    # the backward of a step gets the same, unchanged D, scales and onsets as the
+    # forward before it: it may keep the element metric that forward built
+    B.set_input_reuse(plan, True)
     f32 = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev).contiguous()
     st = dict(plan=plan, D=f32(prob.D), W=f32(prob.W), rn=torch.as_tensor(prob.root_node, device=dev))
     ap = prob.ap

@@ -169,6 +169,20 @@ int gbp_plan_get_local_solver(gbp_plan plan, int *solver, int *n_f, int *lipschi
  * (lipschitz_mode 0); with the tightened one it is the same rule on a smaller L.
  * Errors: GBP_ERR_ARG for a negative or non-finite tau.
  */
+/*
+ * gbp_plan_set_input_reuse -- lets gbp_eikonal_backward and gbp_parent_map keep
+ * what the last forward (or other call) on this plan built from its inputs: the
+ * element metric D_eff^-1 per element, the nodal scales and the root onsets.
+ * They are kept when the call passes the same D, vscale, root_node and root_t
+ * pointers and root count as that call; otherwise they are rebuilt as always.
+ * The caller promises that the arrays behind those pointers have not changed in
+ * between (as with tensors saved for a backward pass).  Input errors of the
+ * call that built them are still reported.
+ *   on  1: allow, 0: always rebuild (the default)
+ * Errors: GBP_ERR_ARG for on outside {0, 1}.
+ */
+int gbp_plan_set_input_reuse(gbp_plan plan, int on);
+
 int gbp_plan_set_fista_tolerance(gbp_plan plan, float tau);
 int gbp_plan_get_fista_tolerance(gbp_plan plan, float *tau);
 

@@ -113,6 +113,7 @@ _point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_
 _locate = _sig("gbp_locate_points", [c_void_p, c_void_p, c_int, c_float, c_void_p, c_void_p])
 _set_solver = _sig("gbp_plan_set_local_solver", [c_void_p, c_int, c_int, c_int])
 _get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
+_set_reuse = _sig("gbp_plan_set_input_reuse", [c_void_p, c_int])
 _set_fista_tol = _sig("gbp_plan_set_fista_tolerance", [c_void_p, c_float])
 _get_fista_tol = _sig("gbp_plan_get_fista_tolerance", [c_void_p, ctypes.POINTER(c_float)])
 _fista_iters = _sig("gbp_fista_iterations", [c_void_p, c_int, c_float, c_int, c_void_p, c_void_p])
@@ -465,6 +466,13 @@ def set_local_solver(plan: Plan, solver="exact", n_f=32, lipschitz="tight"):
     s = {"exact": 0, "fista": 1}[solver]
     m = {"bound": 0, "tight": 1}[lipschitz]
     _check(_set_solver(plan.handle, s, int(n_f), m))
+
+
+def set_input_reuse(plan: Plan, on=True):
+    """Allow backward / parent-map calls to keep the element metric, scales and
+    onsets built from the same D, vscale, root_node, root_t tensors by the last
+    call on this plan; the caller promises those tensors are unchanged since."""
+    _check(_set_reuse(plan.handle, 1 if on else 0))
 
 
 def set_fista_tolerance(plan: Plan, tau: float):

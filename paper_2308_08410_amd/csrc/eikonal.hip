@@ -176,24 +176,27 @@ __global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCt
 // one; a scale that is not finite and > 0 flags an error), the onsets reset to
 // +inf, and T: +inf (T_init null, a cold start) or T_init (NaN read as +inf);
 // the queue marks are cleared when the control reset restarted the stamps.
+// only_T: T alone (the scales and onsets of the last preparation are kept).
 __global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __restrict__ T_init,
                             const int* __restrict__ node_user, float* __restrict__ vs,
                             float* __restrict__ troot, float* __restrict__ T,
-                            int* __restrict__ mark, int n_v, GbpCtl* ctl) {
+                            int* __restrict__ mark, int n_v, int only_T, GbpCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
     if (ctl->marks_stale) mark[i] = 0;   // the stamps restarted from 1
     const int u = node_user[i];
-    float s = 1.f;
-    if (vs_user) {
-        s = vs_user[u];
-        if (!(s > 0.f) || !finitef(s)) {
-            atomicOr(&ctl->err, ERRBIT_VSCALE);
-            s = 1.f;
+    if (!only_T) {
+        float s = 1.f;
+        if (vs_user) {
+            s = vs_user[u];
+            if (!(s > 0.f) || !finitef(s)) {
+                atomicOr(&ctl->err, ERRBIT_VSCALE);
+                s = 1.f;
+            }
         }
+        vs[i] = s;
+        troot[i] = GBP_INF;
     }
-    vs[i] = s;
-    troot[i] = GBP_INF;
     float t = GBP_INF;
     if (T_init) {
         t = T_init[u];
@@ -1379,10 +1382,21 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
                    const float* root_t, int n_roots, int cold, const float* T_init,
                    hipStream_t s) {
     const int n_v = p->n_v, n_e = p->n_e;
-    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, cold == 2 ? 1 : 0);
+    // A backward (cold == 2) may keep the element metric, scales and onsets of the
+    // last full preparation when the caller allows it (gbp_plan_set_input_reuse)
+    // and passes the same arrays; the control reset then keeps the error bits that
+    // preparation raised.
+    const bool keep = cold == 2 && p->reuse_inputs && p->prep_valid && p->prep_D == D &&
+                      p->prep_vs == vscale && p->prep_rn == root_node && p->prep_rt == root_t &&
+                      p->prep_nroots == n_roots;
+    k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, keep ? 2 : (cold == 2 ? 1 : 0));
     k_vertex_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, cold == 1 ? nullptr : T_init,
                                                      p->node_user, p->vs, p->troot, p->T, p->mark,
-                                                     n_v, p->ctl);
+                                                     n_v, keep ? 1 : 0, p->ctl);
+    if (keep) {
+        GBP_LAUNCH_CHECK();
+        return GBP_OK;
+    }
     {
         ProfScope ps(GBP_PROF_METRIC, s);
         k_metric<<<gbp_blocks(n_e, TPB), TPB, 0, s>>>(D, p->tet_user, p->tetv, p->xyz, p->vs,
@@ -1395,6 +1409,12 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
                               cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl,
                               p->xq);
     GBP_LAUNCH_CHECK();
+    p->prep_valid = true;
+    p->prep_D = D;
+    p->prep_vs = vscale;
+    p->prep_rn = root_node;
+    p->prep_rt = root_t;
+    p->prep_nroots = n_roots;
     return GBP_OK;
 }
 

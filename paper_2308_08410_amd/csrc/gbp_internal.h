@@ -107,6 +107,12 @@ struct gbp_plan_s {
     int fista_iters = 32;         // FISTA iterations per local problem
     int fista_lmode = 1;          // FISTA step constant: 0 Eq. (lipschitz_est), 1 tightened
     float fista_tau = 0.f;        // > 0: per-face iterations from the rate bound, capped by fista_iters
+    // inputs of the last full preparation (element metric, scales, onsets): a
+    // backward may reuse them when the caller allows it and passes the same arrays
+    int reuse_inputs = 0;
+    bool prep_valid = false;
+    const void *prep_D = nullptr, *prep_vs = nullptr, *prep_rn = nullptr, *prep_rt = nullptr;
+    int prep_nroots = 0;
     float* lip = nullptr;         // [4 n_e] FISTA step constant per face (allocated on use)
     int level_blocks = 2048;      // grid of an adjoint level (scan; at least n_v / (8 * 256))
     int sync_batch = 16;          // launches between convergence checks (synchronous mode)

@@ -443,6 +443,17 @@ extern "C" int gbp_plan_get_fista_tolerance(gbp_plan p, float* tau) {
     return GBP_OK;
 }
 
+extern "C" int gbp_plan_set_input_reuse(gbp_plan p, int on) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (on != 0 && on != 1) {
+        gbp_set_error("set_input_reuse: on must be 0 or 1");
+        return GBP_ERR_ARG;
+    }
+    p->reuse_inputs = on;
+    return GBP_OK;
+}
+
 extern "C" int gbp_plan_get_queue_split(gbp_plan p, int* split) {
     if (!p || !split) {
         gbp_set_error("get_queue_split: NULL argument");

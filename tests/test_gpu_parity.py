@@ -330,6 +330,31 @@ def test_shell_backward(shell):
     assert lhs == pytest.approx(-0.5 * gT, rel=1e-3)
 
 
+def test_backward_input_reuse_matches_rebuild(shell):
+    """With input reuse allowed, a backward with the forward's own D, scales and
+    onsets keeps that forward's metric and gives bit-identical gradients to a
+    rebuild; other arrays (a copy of D, or a forward with other scales in between)
+    rebuild, with the same result."""
+    c = shell
+    g = t32(np.random.Generator(np.random.PCG64(31)).normal(size=c.p.n_v), c.dev)
+    plan = B().Plan(c.p.xyz, c.p.tets)
+    B().set_input_reuse(plan, True)
+    T, _ = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+    ref = B().eikonal_backward(c.plan, c.D, c.vs, c.rn, c.rt, T, g)     # rebuilds (default plan)
+    got = B().eikonal_backward(plan, c.D, c.vs, c.rn, c.rt, T, g)       # keeps
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    got = B().eikonal_backward(plan, c.D.clone(), c.vs, c.rn, c.rt, T, g)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    B().eikonal_forward(plan, c.D, c.vs * 1.1, c.rn, c.rt)
+    got = B().eikonal_backward(plan, c.D, c.vs, c.rn, c.rt, T, g)
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+    with pytest.raises(B().GbpError):
+        B()._check(B()._set_reuse(plan.handle, 2))
+
+
 # ---------------------------------------------------------------- ECG
 def test_cube_ecg(cube):
     ap = cube.ap()
