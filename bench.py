@@ -385,6 +385,7 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
     rt = f32(concat(rts) + rng.uniform(-3, 3, size=len(rn)).astype(np.float32))
     vs = f32(concat(vs0))
     plan = B.Plan(xyz, tets)
+    B.set_input_reuse(plan, True)   # each step's backward gets its forward's inputs
     ap = inst[0].ap
     S, L = ap["n_steps"], W.shape[1]
     apc = B.make_ap(ap["K0"], ap["K1"], ap["tau"], ap["t0"], ap["dt"], S)

@@ -36,6 +36,8 @@ class MultiStartFit:
         uxyz, utets, voff, _ = union_mesh([xyz] * S, [tets] * S)
         self.n_v, self.S, self.voff = n_v, S, voff
         self.plan = B.Plan(uxyz, utets)
+        # the captured step's backward gets the same, unchanged inputs as its forward
+        B.set_input_reuse(self.plan, True)
         self.batch = B.Batch(voff, ap["n_steps"])
         self.ap = B.make_ap(ap["K0"], ap["K1"], ap["tau"], ap["t0"], ap["dt"], ap["n_steps"])
         f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
