@@ -129,6 +129,8 @@ int gbp_eikonal_forward(gbp_plan plan, const float *D, const float *vscale,
  *   dL_dD      device float [n_e*6] or NULL   (off-diagonals doubled)
  *   dL_dvscale device float [n_v]   or NULL
  *   dL_droot_t device float [n_roots] or NULL
+ * The element metric, scales and onsets are rebuilt from D, vscale and the roots,
+ * or kept from the previous call on the plan (see gbp_plan_set_input_reuse).
  * Errors: as the forward; GBP_ERR_NOT_CONVERGED if the adjoint did not settle.
  */
 int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
