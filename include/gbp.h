@@ -446,6 +446,15 @@ int gbp_plan_get_queue_split(gbp_plan plan, int *split);
 int gbp_plan_last_counts(gbp_plan plan, int *rounds, int *levels);
 
 /*
+ * gbp_plan_set_stamp_base -- sets the base of the forward's queue stamps (each
+ * relaxation round marks queued vertices with the base plus its round index; the
+ * base restarts from 1, clearing every mark, once it exceeds 2^30).  For tests of
+ * that restart, which otherwise comes after some ten million solves.
+ * Synchronises the device.  Errors: GBP_ERR_ARG for stamp < 1, GBP_ERR_HIP.
+ */
+int gbp_plan_set_stamp_base(gbp_plan plan, int stamp);
+
+/*
  * Batches.  Many meshes solve together as one plan over their disjoint union
  * (the instances are its connected components, vertices numbered instance by
  * instance); a batch descriptor records where each instance's vertices start

@@ -114,6 +114,7 @@ _locate = _sig("gbp_locate_points", [c_void_p, c_void_p, c_int, c_float, c_void_
 _set_solver = _sig("gbp_plan_set_local_solver", [c_void_p, c_int, c_int, c_int])
 _get_solver = _sig("gbp_plan_get_local_solver", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
 _set_reuse = _sig("gbp_plan_set_input_reuse", [c_void_p, c_int])
+_set_stamp = _sig("gbp_plan_set_stamp_base", [c_void_p, c_int])
 _set_fista_tol = _sig("gbp_plan_set_fista_tolerance", [c_void_p, c_float])
 _get_fista_tol = _sig("gbp_plan_get_fista_tolerance", [c_void_p, ctypes.POINTER(c_float)])
 _fista_iters = _sig("gbp_fista_iterations", [c_void_p, c_int, c_float, c_int, c_void_p, c_void_p])
@@ -466,6 +467,11 @@ def set_local_solver(plan: Plan, solver="exact", n_f=32, lipschitz="tight"):
     s = {"exact": 0, "fista": 1}[solver]
     m = {"bound": 0, "tight": 1}[lipschitz]
     _check(_set_solver(plan.handle, s, int(n_f), m))
+
+
+def set_stamp_base(plan: Plan, stamp: int):
+    """Queue stamp base of the forward (for tests of its restart past 2^30)."""
+    _check(_set_stamp(plan.handle, int(stamp)))
 
 
 def set_input_reuse(plan: Plan, on=True):

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include <climits>
+#include <cstddef>
 #include <cmath>
 
 #include "gbp_internal.h"
@@ -451,6 +452,19 @@ extern "C" int gbp_plan_set_input_reuse(gbp_plan p, int on) {
         return GBP_ERR_ARG;
     }
     p->reuse_inputs = on;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_stamp_base(gbp_plan p, int stamp) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (stamp < 1) {
+        gbp_set_error("set_stamp_base: stamp must be >= 1");
+        return GBP_ERR_ARG;
+    }
+    GBP_HIP(hipDeviceSynchronize());
+    GBP_HIP(hipMemcpy(reinterpret_cast<char*>(p->ctl) + offsetof(GbpCtl, stamp), &stamp, sizeof(int),
+                      hipMemcpyHostToDevice));
     return GBP_OK;
 }
 

@@ -210,6 +210,25 @@ def test_round_cap_reports_not_converged(shell):
             assert np.abs(T.cpu().numpy() - c.T_gpu).max() <= 1e-5 * np.abs(c.T_gpu).max()
 
 
+def test_stamp_restart_keeps_results(shell):
+    """The queue stamps restart from 1 (every mark cleared) once their base passes
+    2^30: forwards across the restart, cold and warm, give the times of a fresh
+    plan."""
+    c = shell
+    plan = B().Plan(c.p.xyz, c.p.tets)
+    B().set_stamp_base(plan, (1 << 30) - 40)
+    ref = c.T_gpu
+    for k in range(4):
+        T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+        assert st["converged"], k
+        assert np.abs(T.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max(), k
+    B().set_stamp_base(plan, (1 << 30) - 3)
+    Tw, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt, T_init=T.clone())
+    assert st["converged"] and np.abs(Tw.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+    with pytest.raises(B().GbpError):
+        B().set_stamp_base(plan, 0)
+
+
 def test_no_roots_all_unreached():
     dev = _dev()
     xyz, tets = gi.kuhn_cube(2)
