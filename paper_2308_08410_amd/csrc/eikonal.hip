@@ -289,11 +289,13 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
     }
     __syncthreads();
     if (!cold) return;
-    for (int r = threadIdx.x; r < n_roots; r += blockDim.x) {
+    // one wave per root, its lanes over the root's neighbours
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int r = wave; r < n_roots; r += nw) {
         const int u = root_node[r];
         if (u < 0 || u >= n_v) continue;
         const int i = node_int[u];
-        for (int a = adj_ptr[i]; a < adj_ptr[i + 1]; ++a) {
+        for (int a = adj_ptr[i] + lane; a < adj_ptr[i + 1]; a += 64) {
             const int nb = adj[a];
             if (atomicMax(&mark[nb], stamp) < stamp) {
                 const int x = xcd_of(nb, xq.R);
@@ -716,14 +718,16 @@ __device__ __forceinline__ void face_nodes_rt(const int4 v, int K, int& a, int& 
 // partners when each is a weighted parent of the other (the anisotropic scheme
 // is not causal).  The mutual edges are left out of the readiness counts; the
 // pair is solved jointly once both members' other children are finished.
-// (Also clears the child counters and fill cursors the next kernels accumulate into.)
+// (Also clears the child counters and fill cursors the next kernels accumulate into,
+// and the entry slots k_child_sort fills.)
 __global__ void k_pnodes(const int* __restrict__ par, const float4* __restrict__ pa,
                          const int4* __restrict__ tetv, int n_v, int4* __restrict__ pnode,
-                         int* __restrict__ cnt, int* __restrict__ cfill) {
+                         int* __restrict__ cnt, int* __restrict__ cfill, int4* __restrict__ cslot) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_v) return;
     cnt[c] = 0;
     cfill[c] = 0;
+    cslot[c] = make_int4(-1, -1, -1, -1);
     const int pr = par[c];
     int4 out = make_int4(-1, -1, -1, -1);
     if (pr >= 0) {
@@ -799,9 +803,16 @@ __global__ void k_child_fill(const int4* __restrict__ pnode, const float4* __res
         }
 }
 
-// Sort each child list by child id (fixed summation order -> deterministic).
+// Position of entry k (rank r in x's sorted child list) in the entry array.
+__device__ __forceinline__ int centry(int x, int r, int k, int n_v) {
+    return r < kChildSlots ? x * kChildSlots + r : n_v * kChildSlots + k;
+}
+
+// Sort each child list by child id (fixed summation order -> deterministic), then
+// tell each child where its entry sits (the component of its cslot for this parent).
 __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cchild,
-                             float* __restrict__ calpha, int n_v) {
+                             float* __restrict__ calpha, const int4* __restrict__ pnode, int n_v,
+                             int4* __restrict__ cslot) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_v) return;
     const int b = cptr[p], e = cptr[p + 1];
@@ -817,29 +828,12 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
         cchild[y + 1] = kc;
         calpha[y + 1] = ka;
     }
-}
-
-// Position of entry k (rank r in x's sorted child list) in the entry array.
-__device__ __forceinline__ int centry(int x, int r, int k, int n_v) {
-    return r < kChildSlots ? x * kChildSlots + r : n_v * kChildSlots + k;
-}
-
-// Where each vertex sits in its weighted parents' (sorted) child lists, so that a
-// finished vertex can hand alpha * lambda to its parents' entries directly.
-__global__ void k_child_slots(const int4* __restrict__ pnode, const int* __restrict__ cptr,
-                              const int* __restrict__ cchild, int n_v, int4* __restrict__ cslot) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_v) return;
-    const int4 pn = pnode[c];
-    const int f[3] = {pn.x, pn.y, pn.z};
-    int pos[3] = {-1, -1, -1};
-    for (int k = 0; k < 3; ++k) {
-        if (f[k] < 0) continue;
-        const int b = cptr[f[k]];
-        for (int e = b; e < cptr[f[k] + 1]; ++e)
-            if (cchild[e] == c) pos[k] = centry(f[k], e - b, e, n_v);
+    for (int x = b; x < e; ++x) {
+        const int c = cchild[x];
+        const int4 pn = pnode[c];
+        const int k = pn.x == p ? 0 : (pn.y == p ? 1 : 2);
+        reinterpret_cast<int*>(&cslot[c])[k] = centry(p, x - b, x, n_v);
     }
-    cslot[c] = make_int4(pos[0], pos[1], pos[2], -1);
 }
 
 // Readiness stamps of the level walk: the launch from which a vertex may be
@@ -1591,7 +1585,8 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
         ProfScope ps_child(GBP_PROF_CHILD, s);
         const int nb = gbp_blocks(n_v, TPB);
         // p->done holds the child counts until the scan
-        k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode, p->done, p->cfill);
+        k_pnodes<<<nb, TPB, 0, s>>>(p->par, p->pa, p->tetv, n_v, p->pnode, p->done, p->cfill,
+                                    p->cslot);
         k_partner<<<nb, TPB, 0, s>>>(p->pnode, n_v, p->partner);
         k_partner_sym<<<nb, TPB, 0, s>>>(p->partner, n_v, p->pairrem);
         k_partner_fix<<<nb, TPB, 0, s>>>(p->partner, p->pairrem, n_v);
@@ -1600,8 +1595,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
         if ((rc = gbp_scan_exclusive(p->done, p->ccnt, n_v, p->scan_tmp, s))) return rc;
         k_child_fill<<<nb, TPB, 0, s>>>(p->pnode, p->pa, n_v, p->ccnt, p->cfill, p->cchild,
                                         p->calpha);
-        k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
-        k_child_slots<<<nb, TPB, 0, s>>>(p->pnode, p->ccnt, p->cchild, n_v, p->cslot);
+        k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->pnode, n_v, p->cslot);
         GBP_LAUNCH_CHECK();
     }
     // leaves-first level walk
