@@ -14,7 +14,7 @@
 // is walked leaves-first in levels (Kahn order): a vertex is finished once all of
 // its children are, and then pulls their contributions in a fixed order, so the
 // result is deterministic.  Vertices left over by a cycle in the (non-causal)
-// anisotropic parent graph are finished with Jacobi sweeps.
+// anisotropic parent graph are finished with in-place (Gauss-Seidel) sweeps.
 #include <math.h>
 
 #include <algorithm>
