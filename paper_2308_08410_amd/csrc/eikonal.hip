@@ -262,45 +262,43 @@ __device__ __forceinline__ void atomic_min_float(float* a, float v) {
     else atomicMax(reinterpret_cast<unsigned*>(a), __float_as_uint(v));
 }
 
-// Roots: the smallest onset per vertex (one thread per root; a minimum, so
-// duplicates resolve the same in any order), then (cold start) push the
-// neighbours of every root into the first queue.
+// Roots: the smallest onset per vertex (a minimum, so duplicates resolve the same
+// in any order), then (cold start) push the neighbours of every root into the
+// first queue.  16 lanes per root: the first applies the onset, all of them push
+// the root's neighbours.
+constexpr int kRootLanes = 16;
+
 __global__ void k_roots(const int* __restrict__ root_node, const float* __restrict__ root_t,
                         int n_roots, const int* __restrict__ node_int, int n_v,
                         float* __restrict__ troot, float* __restrict__ T, int cold,
                         const int* __restrict__ adj_ptr, const int* __restrict__ adj,
                         int* __restrict__ qout, int* __restrict__ mark, GbpCtl* ctl,
                         XcdQueues xq) {
-    const int stamp = ctl->stamp;
-    for (int r = threadIdx.x; r < n_roots; r += blockDim.x) {
-        const int u = root_node[r];
-        const float t = root_t[r];
-        if (u < 0 || u >= n_v) {
-            atomicOr(&ctl->err, ERRBIT_ROOT_RANGE);
-            continue;
-        }
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = gid / kRootLanes, lane = gid % kRootLanes;
+    if (r >= n_roots) return;
+    const int u = root_node[r];
+    const float t = root_t[r];
+    if (u < 0 || u >= n_v) {
+        if (lane == 0) atomicOr(&ctl->err, ERRBIT_ROOT_RANGE);
+        return;
+    }
+    const int i = node_int[u];
+    if (lane == 0) {
         if (!finitef(t)) {
             atomicOr(&ctl->err, ERRBIT_ROOT_NONFINITE);
-            continue;
+        } else {
+            atomic_min_float(&troot[i], t);
+            if (cold) atomic_min_float(&T[i], t);
         }
-        const int i = node_int[u];
-        atomic_min_float(&troot[i], t);
-        if (cold) atomic_min_float(&T[i], t);
     }
-    __syncthreads();
     if (!cold) return;
-    // one wave per root, its lanes over the root's neighbours
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int r = wave; r < n_roots; r += nw) {
-        const int u = root_node[r];
-        if (u < 0 || u >= n_v) continue;
-        const int i = node_int[u];
-        for (int a = adj_ptr[i] + lane; a < adj_ptr[i + 1]; a += 64) {
-            const int nb = adj[a];
-            if (atomicMax(&mark[nb], stamp) < stamp) {
-                const int x = xcd_of(nb, xq.R);
-                qout[xq.off[x] + atomicAdd(&ctl->qcnt[0][x], 1)] = nb;
-            }
+    const int stamp = ctl->stamp;
+    for (int a = adj_ptr[i] + lane; a < adj_ptr[i + 1]; a += kRootLanes) {
+        const int nb = adj[a];
+        if (atomicMax(&mark[nb], stamp) < stamp) {
+            const int x = xcd_of(nb, xq.R);
+            qout[xq.off[x] + atomicAdd(&ctl->qcnt[0][x], 1)] = nb;
         }
     }
 }
@@ -1399,9 +1397,9 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
             k_fista_lip<<<gbp_blocks(4LL * n_e, TPB), TPB, 0, s>>>(p->tetg, n_e, p->fista_lmode,
                                                                    p->lip);
     }
-    k_roots<<<1, TPB, 0, s>>>(root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T,
-                              cold == 1 ? 1 : 0, p->adj_ptr, p->adj, p->q[0], p->mark, p->ctl,
-                              p->xq);
+    k_roots<<<std::max(1, gbp_blocks((long long)kRootLanes * n_roots, TPB)), TPB, 0, s>>>(
+        root_node, root_t, n_roots, p->node_int, n_v, p->troot, p->T, cold == 1 ? 1 : 0, p->adj_ptr,
+        p->adj, p->q[0], p->mark, p->ctl, p->xq);
     GBP_LAUNCH_CHECK();
     p->prep_valid = true;
     p->prep_D = D;
