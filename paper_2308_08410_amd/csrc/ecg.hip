@@ -381,7 +381,7 @@ int ecg_forward_launch(const EcgLaunch& el, const float* T, int n_v, const float
     const int total = el.n_inst * (2 * S_pad * 16 + 16);
     k_ecg_zero<<<std::min((total + 255) / 256, 1024), 256, 0, s>>>(el.work, total);
     const int groups = (el.max_verts + 63) / 64;
-    const int gpb = 16;   // 64-vertex groups per block (4 per wave)
+    const int gpb = 8;    // 64-vertex groups per block (2 per wave; 16 measured slower: fewer resident waves)
     const dim3 grid((groups + gpb - 1) / gpb, el.n_inst);
     const size_t lds = (size_t)S_pad * 16 * sizeof(float);
     {
