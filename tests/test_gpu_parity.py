@@ -349,6 +349,47 @@ def test_shell_backward(shell):
     assert lhs == pytest.approx(-0.5 * gT, rel=1e-3)
 
 
+def test_backward_and_ecg_are_deterministic(shell):
+    """Given the same T, the adjoint (fixed-order sums over child entries, no float
+    atomics) and the ECG backward give bitwise the same results run after run; the
+    ECG forward accumulates its windows with float atomics, so it agrees to FP32
+    reassociation only."""
+    c = shell
+    g = t32(np.random.Generator(np.random.PCG64(41)).normal(size=c.p.n_v), c.dev)
+    first = B().eikonal_backward(c.plan, c.D, c.vs, c.rn, c.rt, c.T, g)
+    ap = c.ap()
+    e1 = B().ecg_forward(c.T, c.W, ap).clone()
+    G = t32(np.random.Generator(np.random.PCG64(42)).normal(size=tuple(e1.shape)), c.dev)
+    d1 = B().ecg_backward(c.T, c.W, ap, G).clone()
+    for _ in range(3):
+        again = B().eikonal_backward(c.plan, c.D, c.vs, c.rn, c.rt, c.T, g)
+        for a, b in zip(first, again):
+            assert torch.equal(a, b)
+        e = B().ecg_forward(c.T, c.W, ap)
+        assert float((e - e1).abs().max()) <= 1e-5 * float(e1.abs().max())
+        assert torch.equal(B().ecg_backward(c.T, c.W, ap, G), d1)
+
+
+def test_overshadowed_root_has_zero_gradient():
+    """Sec. 2.5: a root whose onset is beaten by the wave from another root is not
+    its own parent, so its onset gets exactly zero gradient; the active root gets
+    the whole sum of dL/dT."""
+    dev = _dev()
+    xyz, tets = gi.kuhn_cube(6)
+    D = np.tile(np.array([[1, 1, 1, 0, 0, 0]], np.float32), (len(tets), 1))
+    far = len(xyz) - 1                              # opposite corner
+    rn = np.array([0, far], np.int32)
+    rt = np.array([0.0, 100.0], np.float32)         # the second root is overshadowed
+    plan = B().Plan(xyz, tets)
+    T, _ = B().eikonal_forward(plan, t32(D, dev), None, i32(rn, dev), t32(rt, dev))
+    assert float(T[far]) < 100.0
+    g = np.random.Generator(np.random.PCG64(5)).uniform(0.5, 1.5, size=len(xyz))
+    _, _, drt = B().eikonal_backward(plan, t32(D, dev), None, i32(rn, dev), t32(rt, dev), T, t32(g, dev))
+    drt = drt.cpu().numpy()
+    assert drt[1] == 0.0
+    assert drt[0] == pytest.approx(g.sum(), rel=1e-4)
+
+
 def test_backward_input_reuse_matches_rebuild(shell):
     """With input reuse allowed, a backward with the forward's own D, scales and
     onsets keeps that forward's metric and gives bit-identical gradients to a
