@@ -350,10 +350,6 @@ __global__ void k_fista_lip(const float4* __restrict__ tetg, int n_e, int mode,
     lip[i] = fista_lipschitz(face_q_rt(tetg[2 * t], tetg[2 * t + 1], (int)(i & 3)), mode);
 }
 
-__global__ void k_fill_i(int* __restrict__ x, int v, int n) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
-}
-
 // ------------------------------------------------------------------ relaxation
 template <int K>
 __device__ __forceinline__ void relax_slot(int& e, int cnt, const int* __restrict__ nent,
