@@ -258,7 +258,11 @@ def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
     Te = Te.clone()
     fin = torch.isfinite(Te)
     runs = []
+    tuned = B.get_launch(plan)
     try:
+        # FISTA rounds are arithmetic-bound: 8 lanes per vertex (three local problems
+        # per lane) and a full grid of 2048 blocks
+        B.set_launch(plan, 8, 2048, tuned["level_blocks"], tuned["sync_batch"])
         for n_f in (32, 64, 128):
             B.set_local_solver(plan, "fista", n_f, "tight")
             ms, (Tf, sf) = timed(lambda: B.eikonal_forward(plan, D, vs, rn, rt))
@@ -277,6 +281,7 @@ def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
     finally:
         B.set_fista_tolerance(plan, 0.0)
         B.set_local_solver(plan, "exact")
+        B.set_launch(plan, tuned["lanes"], tuned["sweep_blocks"], tuned["level_blocks"], tuned["sync_batch"])
     r = np.random.Generator(np.random.PCG64(seed))
     A = r.normal(size=(n_faces, 3, 3)).astype(np.float32)
     Q = np.einsum("nki,nkj->nij", A, A) + 0.1 * np.eye(3, dtype=np.float32)
@@ -288,7 +293,8 @@ def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
     for n_f in (16, 32, 64, 128):
         per_face[f"fista_{n_f}"] = timed(lambda: B.local_solve(Q6, Phi, "fista", n_f=n_f, lip=lip,
                                                                want_alpha=False))[0] * 1e6 / n_faces
-    return dict(exact_forward_ms=ms_e, exact_rounds=se["rounds"], runs=runs, ns_per_local_problem=per_face)
+    return dict(exact_forward_ms=ms_e, exact_rounds=se["rounds"], fista_launch=dict(lanes=8, sweep_blocks=2048),
+                runs=runs, ns_per_local_problem=per_face)
 
 
 def lead_field_form(st, prob, torch, B, reps=5):

@@ -453,16 +453,39 @@ __global__ void __launch_bounds__(TPB)
         const int e01 = c0 + c1, e012 = e01 + c2;
         const int tot = e012 + c3;
         float best = GBP_INF;
-        for (int c = lane; c < tot; c += 2 * L) {
-            const int d = c + L;       // second local problem of this lane
-            const bool okd = d < tot;
-            const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
-            const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
-            const float vc = face_value<SOLVER>(nent, tetv, tetg, T, p.x + c, Kc, lip, n_f, tau);
-            const float vd = face_value<SOLVER>(nent, tetv, tetg, T, p.x + (okd ? d : c),
-                                                okd ? Kd : Kc, lip, n_f, tau);
-            best = fminf(best, okd ? fminf(vc, vd) : vc);
-            solves += okd ? 2 : 1;
+        if constexpr (SOLVER == 1 && L == 8) {
+            // FISTA rounds are bound by arithmetic: at 8 lanes each lane takes local
+            // problems c, c + 8 and c + 16, so a 24-element patch fills three
+            // passes with no idle slot (two passes of 16 lanes leave 8 of 32 idle)
+            for (int c = lane; c < tot; c += 3 * L) {
+                float v3[3];
+                bool ok3[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int d = c + k * L;
+                    ok3[k] = k == 0 || d < tot;
+                    const int dd = ok3[k] ? d : c;
+                    const int Kd = (dd < c0) ? 0 : (dd < e01) ? 1 : (dd < e012) ? 2 : 3;
+                    v3[k] = face_value<SOLVER>(nent, tetv, tetg, T, p.x + dd, Kd, lip, n_f, tau);
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    best = fminf(best, ok3[k] ? v3[k] : GBP_INF);
+                    solves += ok3[k] ? 1 : 0;
+                }
+            }
+        } else {
+            for (int c = lane; c < tot; c += 2 * L) {
+                const int d = c + L;       // second local problem of this lane
+                const bool okd = d < tot;
+                const int Kc = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
+                const int Kd = (d < c0) ? 0 : (d < e01) ? 1 : (d < e012) ? 2 : 3;
+                const float vc = face_value<SOLVER>(nent, tetv, tetg, T, p.x + c, Kc, lip, n_f, tau);
+                const float vd = face_value<SOLVER>(nent, tetv, tetg, T, p.x + (okd ? d : c),
+                                                    okd ? Kd : Kc, lip, n_f, tau);
+                best = fminf(best, okd ? fminf(vc, vd) : vc);
+                solves += okd ? 2 : 1;
+            }
         }
         for (int o = L / 2; o > 0; o >>= 1) best = fminf(best, __shfl_xor(best, o));
         if (!act) continue;
