@@ -370,26 +370,18 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
     launch configuration from the autotuner."""
     import numpy as np
     from paper_2308_08410_amd.batch import concat, shift_roots, union_mesh
-    rng = np.random.Generator(np.random.PCG64(seed))
-    sizes = np.sort(rng.integers(10_000, 200_001, size=n_meshes))
     t0 = time.time()
-    meshes = [gi.shell_problem(int(n), seed=seed + 7 * k, n_roots=1, n_leads=12) for k, n in enumerate(sizes)]
-    inst = [meshes[i % n_meshes] for i in range(n_inst)]
+    wl = gi.batched_workload(n_inst=n_inst, n_meshes=n_meshes, seed=seed)
+    meshes = wl.meshes
+    inst = [meshes[k] for k in wl.mesh_of]
     xyz, tets, voff, _ = union_mesh([m.xyz for m in inst], [m.tets for m in inst])
-    rns, rts, vs_true, vs0 = [], [], [], []
-    for i, m in enumerate(inst):
-        R = int(rng.integers(1, 9))
-        rn, rt = gi.random_roots(m.extra["endo"], R, 0.0, 20.0, seed=seed + 1000 + i)
-        rns.append(rn)
-        rts.append(rt)
-        vs_true.append(gi.smooth_field(m.xyz, 0.5, 1.5, seed=seed + 2000 + i))
-        vs0.append(np.ones(m.n_v, np.float32))
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
     D, W = f32(concat([m.D for m in inst])), f32(concat([m.W for m in inst]))
-    rn = torch.as_tensor(shift_roots(rns, voff), device=dev)
-    rt_true = f32(concat(rts))
-    rt = f32(concat(rts) + rng.uniform(-3, 3, size=len(rn)).astype(np.float32))
-    vs = f32(concat(vs0))
+    rn = torch.as_tensor(shift_roots(wl.root_node, voff), device=dev)
+    rt_true = f32(concat(wl.root_t_true))
+    rt = f32(concat(wl.root_t_start))
+    vs = f32(np.ones(int(voff[-1])))
+    vs_true = wl.vscale_true
     plan = B.Plan(xyz, tets)
     B.set_input_reuse(plan, True)   # each step's backward gets its forward's inputs
     ap = inst[0].ap

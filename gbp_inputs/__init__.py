@@ -35,7 +35,8 @@ __all__ = [
     "random_roots", "random_point_roots", "tets_touching", "smooth_field", "sphere_electrodes", "lead_weights",
     "jitter_nodes", "Problem", "cube_problem", "shell_problem", "AP_CUBE",
     "AP_SHELL", "tet_volumes", "square_tri", "jitter_nodes2", "fibre_tensor2", "annulus_mesh",
-    "circle_electrodes", "lead_weights2", "annulus_problem", "AP_SLICE",
+    "circle_electrodes", "lead_weights2", "annulus_problem", "AP_SLICE", "batched_workload",
+    "multistart_workload",
 ]
 
 # Action-potential template parameters (U(xi) = K0 + (K1-K0)*sigmoid(4 xi/tau)
@@ -561,6 +562,59 @@ def shell_problem(target_nodes: int = 500_000, seed: int = 2, n_roots: int = 5, 
     W = lead_weights(sh.xyz, sh.tets, el)
     return Problem("shell", sh.xyz, sh.tets, D, vs, rn, rt, W, dict(AP_SHELL), sh.h,
                    extra=dict(electrodes=el, endo=sh.endo, fibre=sh.fibre, node_fibre=sh.node_fibre))
+
+
+@dataclasses.dataclass
+class BatchedWorkload:
+    """Many uneven meshes and parameter sets solved together.  Instance i uses
+    mesh ``meshes[mesh_of[i]]`` with roots ``root_node[i]`` (local vertex ids), a
+    hidden velocity scale ``vscale_true[i]`` and onsets ``root_t_true[i]`` that
+    make its target ECG, and fit start values ``root_t_start[i]`` (the velocity
+    scale starts at 1)."""
+    meshes: list
+    mesh_of: list
+    root_node: list
+    root_t_true: list
+    root_t_start: list
+    vscale_true: list
+
+
+def batched_workload(n_inst: int = 64, n_meshes: int = 8, seed: int = 31) -> BatchedWorkload:
+    """The batched form: ``n_meshes`` shells of seeded sizes in [10k, 200k]
+    vertices, each used by n_inst / n_meshes instances (instance i on mesh
+    i % n_meshes); per instance 1-8 endocardial roots with onsets U[0, 20] ms, a
+    hidden smooth velocity scale in [0.5, 1.5], and start onsets perturbed by
+    U[-3, 3] ms."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.sort(rng.integers(10_000, 200_001, size=n_meshes))
+    meshes = [shell_problem(int(n), seed=seed + 7 * k, n_roots=1, n_leads=12) for k, n in enumerate(sizes)]
+    mesh_of = [i % n_meshes for i in range(n_inst)]
+    rns, rts, vst = [], [], []
+    for i in range(n_inst):
+        m = meshes[mesh_of[i]]
+        R = int(rng.integers(1, 9))
+        rn, rt = random_roots(m.extra["endo"], R, 0.0, 20.0, seed=seed + 1000 + i)
+        rns.append(rn)
+        rts.append(rt)
+        vst.append(smooth_field(m.xyz, 0.5, 1.5, seed=seed + 2000 + i))
+    pert = rng.uniform(-3, 3, size=sum(len(r) for r in rns)).astype(np.float32)
+    starts, o = [], 0
+    for rt in rts:
+        starts.append((rt + pert[o:o + len(rt)]).astype(np.float32))
+        o += len(rt)
+    return BatchedWorkload(meshes, mesh_of, rns, rts, starts, vst)
+
+
+def multistart_workload(n_nodes: int = 1_000_000, n_starts: int = 16, n_roots: int = 8, seed: int = 5):
+    """The inverse problem: a shell with hidden parameters (a smooth velocity
+    scale in [0.5, 1.5] and ``n_roots`` endocardial onsets) whose ECG is the
+    target, and ``n_starts`` fit starts (velocity scale 1, onsets U[0, 20] ms).
+    Returns (problem, vscale_true, [start onsets])."""
+    p = shell_problem(n_nodes, seed=seed, n_roots=n_roots, n_leads=12)
+    vs_true = smooth_field(p.xyz, 0.5, 1.5, seed=seed + 10)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    rt0 = [rng.uniform(0.0, 20.0, size=n_roots).astype(np.float32) for _ in range(n_starts)]
+    return p, vs_true, rt0
 
 
 # ---------------------------------------------------------------- warm-start network

@@ -13,9 +13,14 @@
  *     "host" means ordinary CPU memory.  Nothing passed in is retained after
  *     the call returns, except that a plan keeps its own copies of the mesh.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
- *     is enqueued on it; the eikonal forward and backward synchronise with it
- *     internally (their iteration counts are decided on the device); the ECG,
- *     loss and Adam calls are fully asynchronous.
+ *     is enqueued on it.  gbp_eikonal_forward and gbp_eikonal_backward wait for
+ *     it: how many relaxation rounds and adjoint levels a solve needs is known
+ *     only on the device, so the host reads the device's convergence flag (one
+ *     batch of launches behind, so that the device does not idle) and returns
+ *     when the solve is done, with its statistics and error code.  Their _async
+ *     variants enqueue a fixed budget of launches and return at once (for graph
+ *     capture and streams the caller does not want to block on); the ECG, loss
+ *     and Adam calls are fully asynchronous.
  *   - Outputs are overwritten, never accumulated into.
  *   - Return value: GBP_OK (0) or a negative GBP_ERR_* code; gbp_last_error()
  *     then returns a message (thread-local, valid until the next call).
@@ -137,6 +142,29 @@ int gbp_eikonal_backward(gbp_plan plan, const float *D, const float *vscale,
                          const int32_t *root_node, const float *root_t, int n_roots,
                          const float *T, const float *dL_dT, float *dL_dD,
                          float *dL_dvscale, float *dL_droot_t, void *stream);
+
+/*
+ * gbp_eikonal_forward_async / gbp_eikonal_backward_async -- gbp_eikonal_forward
+ * and gbp_eikonal_backward enqueued on `stream` with fixed launch budgets and no
+ * host synchronisation (graph-capturable; the same kernels and results):
+ *   round_budget  relaxation rounds (>= 1); rounds after convergence return at once
+ *   level_budget  adjoint levels (>= 1); gs_budget Gauss-Seidel sweeps (>= 0) for
+ *                 vertices on or above parent-graph cycles
+ * Whether the budgets sufficed and the input errors the kernels found (root ids
+ * out of range, non-finite inputs, D not positive definite) are kept on the
+ * device: gbp_plan_status reads them (it synchronises), gbp_plan_forward_work the
+ * work done.  Budgets come from a synchronous call on similar inputs
+ * (gbp_plan_last_counts, gbp_backward_info) with a margin.  Errors returned here:
+ * GBP_ERR_ARG (sizes, pointers, budgets), GBP_ERR_NOMEM, GBP_ERR_HIP.
+ */
+int gbp_eikonal_forward_async(gbp_plan plan, const float *D, const float *vscale,
+                              const int32_t *root_node, const float *root_t, int n_roots,
+                              const float *T_init, float *T_out, int round_budget, void *stream);
+int gbp_eikonal_backward_async(gbp_plan plan, const float *D, const float *vscale,
+                               const int32_t *root_node, const float *root_t, int n_roots,
+                               const float *T, const float *dL_dT, float *dL_dD,
+                               float *dL_dvscale, float *dL_droot_t, int level_budget,
+                               int gs_budget, void *stream);
 
 /*
  * gbp_plan_set_local_solver / gbp_plan_get_local_solver -- the local solver of
@@ -357,9 +385,13 @@ typedef struct {
  *   sum_n W[n*L + l] * U(t_s - T[n]).  W is the discretised lead-field operator
  *   B (one column per lead).  Vertices with T = +inf stay at rest (U = K0).
  *   T   device float [n_v];  W device float [n_v*L];  ecg device float [n_steps*L]
- *   1 <= L <= 16.  Uses a library-owned scratch buffer per device (grown on
- *   demand): forward calls that overlap on one device, on different streams or
- *   host threads, race on it.
+ *   1 <= L <= 256, 1 <= n_steps <= 2^20 (the kernels take tiles of 16 leads and
+ *   chunks of 992 steps; the paper's 31 leads are two tiles).  Uses a
+ *   library-owned scratch buffer per device (grown on demand, which frees the old
+ *   one): forward calls that overlap on one device, on different streams or host
+ *   threads, race on it, and a captured graph would keep a buffer that a later,
+ *   larger call frees.  For either, use gbp_ecg_forward_batched with a batch of
+ *   one instance (the batch owns its scratch).
  */
 int gbp_ecg_forward(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
                     float *ecg, void *stream);
@@ -368,6 +400,8 @@ int gbp_ecg_forward(const float *T, int n_v, const float *W, int L, const gbp_ap
  * gbp_ecg_backward -- dL_dT[n] = -sum_s U'(t_s - T[n]) sum_l dL_decg[s*L+l] W[n*L+l]
  * (Sec. 2.4: the gradient of V_l is -B^T U' times the gradient of phi).
  *   dL_decg device float [n_steps*L];  dL_dT device float [n_v] (overwritten)
+ * Limits as gbp_ecg_forward; no scratch (the tiles and chunks add into dL_dT in
+ * launch order, so the result is deterministic).
  */
 int gbp_ecg_backward(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
                      const float *dL_decg, float *dL_dT, void *stream);
@@ -417,6 +451,15 @@ int gbp_plan_status(gbp_plan plan, int *err_code, int *forward_converged,
                     int *backward_settled, int *rounds, int *levels, void *stream);
 
 /*
+ * gbp_plan_forward_work -- synchronises `stream` and returns the work of the last
+ * forward on the plan, synchronous or budgeted (e.g. inside a replayed step):
+ * local problems evaluated and vertex value changes beyond the threshold.
+ * Either pointer may be NULL.
+ */
+int gbp_plan_forward_work(gbp_plan plan, int64_t *face_solves, int64_t *node_updates,
+                          void *stream);
+
+/*
  * gbp_plan_set_launch / gbp_plan_get_launch -- launch configuration of the
  * relaxation rounds and adjoint levels (chosen by an autotuner):
  *   lanes        lanes per vertex in a relaxation round: 8, 16 or 32
@@ -446,22 +489,15 @@ int gbp_plan_get_queue_split(gbp_plan plan, int *split);
 int gbp_plan_last_counts(gbp_plan plan, int *rounds, int *levels);
 
 /*
- * gbp_plan_set_stamp_base -- sets the base of the forward's queue stamps (each
- * relaxation round marks queued vertices with the base plus its round index; the
- * base restarts from 1, clearing every mark, once it exceeds 2^30).  For tests of
- * that restart, which otherwise comes after some ten million solves.
- * Synchronises the device.  Errors: GBP_ERR_ARG for stamp < 1, GBP_ERR_HIP.
- */
-int gbp_plan_set_stamp_base(gbp_plan plan, int stamp);
-
-/*
  * Batches.  Many meshes solve together as one plan over their disjoint union
  * (the instances are its connected components, vertices numbered instance by
  * instance); a batch descriptor records where each instance's vertices start
- * so that the ECG and the misfit are evaluated per instance.
+ * so that the ECG and the misfit are evaluated per instance.  The batch owns the
+ * ECG forward's scratch (n_inst * ~130 KB at most), so batched ECG calls are
+ * graph-capturable; calls with one batch must not overlap.
  *   offsets  host int32 [n_inst+1], offsets[0] = 0, non-decreasing; instance i
  *            owns vertices [offsets[i], offsets[i+1]) of the union
- *   max_steps largest n_steps the batch will be used with (<= 992)
+ *   max_steps largest n_steps the batch will be used with (<= 2^20)
  * Errors: GBP_ERR_ARG, GBP_ERR_NOMEM, GBP_ERR_HIP.
  */
 typedef struct gbp_batch_s *gbp_batch;
@@ -535,6 +571,15 @@ typedef struct gbp_step_s *gbp_step;
 int gbp_step_create(const gbp_step_desc *desc, gbp_step *out);
 int gbp_step_launch(gbp_step step, void *stream);
 void gbp_step_destroy(gbp_step step);
+/*
+ * gbp_step_gradients -- copies, on `stream`, the gradients the last replay of the
+ * step computed before its Adam updates (at the parameters that replay started
+ * from): dL_dT [n_v] (ECG backward), dL_dvscale [n_v] and dL_droot_t [n_roots]
+ * (eikonal backward), L the sum of the instances' misfits.  Device buffers, each
+ * may be NULL.  Errors: GBP_ERR_ARG (no step), GBP_ERR_HIP.
+ */
+int gbp_step_gradients(gbp_step step, float *dL_dT, float *dL_dvscale, float *dL_droot_t,
+                       void *stream);
 
 /*
  * Learned warm start (an extension beyond the paper, which solves every

@@ -47,12 +47,21 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the C part of the oracle with gcc (plain -O2, IEEE semantics)."""
+    """Compile the C part of the oracle with gcc (plain -O2, IEEE semantics;
+    OpenMP only spreads independent elements or nodes over threads)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-shared", "-fPIC", "-o", tmp,
+                               _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def set_threads(n: int) -> int:
+    """Host threads for the C loops of Alg. 2 (Jacobi and warm modes) and the
+    parent map; 1 by default.  The results are the same for any count (the
+    scatter-min is order-independent); only the time changes."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _load():
@@ -71,6 +80,8 @@ def _load():
         lib.orc_parent_map.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp, ctypes.c_int, ip, dp,
                                        dp, ip, ip, dp, dp, dp, ip]
         lib.orc_parent_map.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -534,21 +545,31 @@ def fista_iterations(L, tau, n_max, d=3):
     suggests (n_f on an element basis): after k iterations from alpha_0 = 1/d the
     error is at most 2 L ||alpha_0 - alpha*||^2 / (k+1)^2, and ||alpha_0 - alpha||^2
     <= (d-1)/d over the simplex (its farthest points from the barycentre are the
-    vertices), so k + 1 >= sqrt(2 (d-1)/d L / tau) guarantees an error <= tau
-    whenever L is a Lipschitz constant of grad h.  At least 1, at most n_max;
-    n_max for tau <= 0 or a non-finite bound.  The integer is decided in float32,
-    the precision of the device (products and quotient rounded in that order):
-    x = sqrt((c * L) / tau), c = 2 (d-1)/d, k = ceil(x) - 1."""
-    L = np.asarray(L, dtype=np.float32)
+    vertices), so the least k >= 1 with (k+1)^2 >= 2 (d-1)/d L / tau guarantees an
+    error <= tau whenever L is a Lipschitz constant of grad h.  At most n_max;
+    n_max for tau <= 0 or a non-finite bound.  Float64 throughout: the square
+    root gives a first guess, then the defining inequality, d tau (k+1)^2 >=
+    2 (d-1) L, is checked on the neighbouring integers."""
+    L = np.asarray(L, dtype=np.float64)
     out = np.full(L.shape, int(n_max), dtype=np.int64)
+    tau = float(tau)
     if not tau > 0:
         return out
-    c = np.float32(2.0 * (d - 1) / d)
-    with np.errstate(all="ignore"):
-        x = np.sqrt((c * L) / np.float32(tau))
-    ok = x < np.float32(n_max + 1)                     # False for NaN and +inf
-    k = np.ceil(x[ok]).astype(np.int64) - 1
-    out[ok] = np.maximum(k, 1)
+    flat_L = L.reshape(-1)
+    flat = out.reshape(-1)
+    for i, Li in enumerate(flat_L):
+        if not np.isfinite(Li):
+            continue
+        need = 2.0 * (d - 1) * Li               # the bound holds iff d tau (k+1)^2 >= need
+        x = np.sqrt(need / (d * tau))
+        if not x < n_max + 2:
+            continue                           # capped
+        k = max(int(np.ceil(x)) - 1, 1)
+        while k > 1 and d * tau * float(k) ** 2 >= need:        # k - 1 iterations suffice
+            k -= 1
+        while d * tau * float(k + 1) ** 2 < need:               # k iterations do not
+            k += 1
+        flat[i] = min(k, int(n_max))
     return out
 
 

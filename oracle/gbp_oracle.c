@@ -37,8 +37,41 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_INF (1.0 / 0.0)
+
+/* Threads for the loops below that are independent per element or per node (1
+ * unless a caller asks for more, e.g. to time the oracle on every host core).
+ * Results do not depend on the count: the only shared update is the scatter-min
+ * of Alg. 2, and a minimum does not depend on the order of its operands. */
+static int orc_threads = 1;
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    orc_threads = n < 1 ? 1 : n;
+#else
+    (void)n;
+    orc_threads = 1;
+#endif
+    return orc_threads;
+}
+
+/* *addr = min(*addr, val), safe when several threads update one node */
+static void orc_min_update(double *addr, double val) {
+    unsigned long long *a = (unsigned long long *)addr;
+    unsigned long long old = __atomic_load_n(a, __ATOMIC_RELAXED);
+    for (;;) {
+        double cur;
+        memcpy(&cur, &old, sizeof cur);
+        if (!(val < cur)) return;
+        unsigned long long nv;
+        memcpy(&nv, &val, sizeof nv);
+        if (__atomic_compare_exchange_n(a, &old, nv, 0, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) return;
+    }
+}
 
 /* ---- small dense linear algebra (Gaussian elimination, partial pivoting) */
 static int orc_solve(int m, const double *A_in, const double *b_in, double *x) {
@@ -239,6 +272,9 @@ int orc_fim(int n_v, const double *xyz, int n_e, const int *tets, const double *
             memcpy(k0, km1, sizeof(double) * n_v);
         }
         const double *src = (mode == 1) ? k0 : km1;
+        /* Gauss-Seidel (mode 1) reads the array it writes: sequential */
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : solves) \
+    num_threads(mode == 1 ? 1 : orc_threads)
         for (int j = 0; j < n_e; ++j) {
             const int *tet = tets + 4 * j;
             for (int kk = 0; kk < 4; ++kk) {
@@ -256,7 +292,7 @@ int orc_fim(int n_v, const double *xyz, int n_e, const int *tets, const double *
                 for (int n = 0; n < 3; ++n) Phi[n] = src[fv[n]];
                 orc_local_solve(Q, Phi, &val, a);
                 ++solves;
-                if (val < k0[tet[kk]]) k0[tet[kk]] = val;
+                orc_min_update(&k0[tet[kk]], val);
             }
         }
         int any = 0;
@@ -331,6 +367,7 @@ int orc_parent_map(int n_v, const double *xyz, int n_e, const int *tets, const d
     for (int j = 0; j < n_e; ++j)
         for (int k = 0; k < 4; ++k) inc[fill[tets[4 * j + k]]++] = 4 * j + k;
 
+#pragma omp parallel for schedule(dynamic, 256) num_threads(orc_threads)
     for (int i = 0; i < n_v; ++i) {
         int nc = cnt[i + 1] - cnt[i];
         double *vals = (double *)malloc(sizeof(double) * (nc > 0 ? nc : 1));

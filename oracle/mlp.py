@@ -7,13 +7,20 @@ The network is not part of the paper (which solves every forward from scratch);
 it maps per-vertex features to a guess of the activation time that seeds the
 two-sided warm-started solve.  Parity is pinned by the tests in
 ``tests/test_oracle_mlp.py``: the forward equals ``torch.nn`` Linear/ReLU layers
-in float64, the gradient equals autograd and central differences, and the bf16
-rounding equals torch's float32 -> bfloat16 conversion.
+in float64, the gradient equals autograd and central differences, and the
+features equal hand-computed rows.
 
 Network: 16 -> 256 -> 256 -> 256 -> 256 -> 1, ReLU after each hidden layer.
-With ``bf16=True`` the same quantities are rounded to bfloat16 as in the
-library: the hidden weights W1..W4, each hidden activation H_l, and each
-back-propagated pre-activation gradient dZ_l; everything else is float64.
+Everything here is float64 and nothing is rounded to a narrower format: the
+library's bf16 storage of weights, features and activations is an error that
+the GPU tests bound from the rounding unit of bf16, not something this
+reference imitates.  ``forward(..., cache=True)`` and ``loss_and_gradient(...,
+cache=True)`` also return the intermediate arrays those bounds are built from,
+and the optional ``perturb`` callable lets a test sample the standard model of
+rounding error (every stored value times 1 + delta with |delta| <= u): it is
+applied to the hidden weights W1..W4 where they are used, to each hidden
+activation H_l and to each back-propagated dZ_l.  With ``perturb=None`` (the
+default) the network is evaluated exactly in float64.
 """
 from __future__ import annotations
 
@@ -23,15 +30,6 @@ SIZES = (("W1", (256, 16)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
          ("W3", (256, 256)), ("b3", (256,)), ("W4", (256, 256)), ("b4", (256,)),
          ("w5", (256,)), ("b5", (1,)))
 N_PARAMS = sum(int(np.prod(s)) for _, s in SIZES)
-
-
-def bf16_round(x):
-    """Round float64 values to the nearest bfloat16 value (8 significant bits,
-    ties to even); the result is returned as float64.  Subnormal and overflow
-    ranges are not handled (no value here comes near them)."""
-    x = np.asarray(x, dtype=np.float64)
-    m, e = np.frexp(x)                      # x = m 2^e, 0.5 <= |m| < 1
-    return np.ldexp(np.round(m * 256.0), e - 8)   # np.round: half to even
 
 
 def unpack(params):
@@ -51,7 +49,7 @@ def pack(d):
     return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SIZES])
 
 
-def features(xyz, fibre, vscale, rows, root_xyz, root_t, norm, T=None, bf16=True):
+def features(xyz, fibre, vscale, rows, root_xyz, root_t, norm, T=None):
     """Feature rows: (x - c)/len_scale, fibre, the per-root values
     |x - x_r|/len_scale + t_r/time_scale over 8 roots (fewer roots: root 0
     repeated) sorted ascending, vscale, 0.  Returns X [m,16] (and T[rows] /
@@ -74,52 +72,58 @@ def features(xyz, fibre, vscale, rows, root_xyz, root_t, norm, T=None, bf16=True
     X[:, 3:6] = np.asarray(fibre, np.float64)[rows]
     X[:, 6:14] = a
     X[:, 14] = vs
-    if bf16:
-        X = bf16_round(X)
     if T is None:
         return X
     return X, np.asarray(T, np.float64)[rows] / ts
 
 
-def forward(params, X, bf16=True, cache=False):
-    """y = w5 . H4 + b5 with H_l = relu(W_l H_{l-1} + b_l), H_0 = X."""
+def _keep(name, a):
+    return a
+
+
+def forward(params, X, cache=False, perturb=None):
+    """y = w5 . H4 + b5 with H_l = relu(Z_l), Z_l = W_l H_{l-1} + b_l, H_0 = X.
+    cache=True returns (y, Z [Z_1..Z_4], H [H_0..H_4])."""
+    pt = _keep if perturb is None else perturb
     P = unpack(params)
     H = np.asarray(X, np.float64)
-    hs = [H]
+    hs, zs = [H], []
     for l in range(1, 5):
-        W = P[f"W{l}"]
-        if bf16:
-            W = bf16_round(W)
-        H = np.maximum(H @ W.T + P[f"b{l}"], 0.0)
-        if bf16:
-            H = bf16_round(H)
+        Z = H @ pt(f"W{l}", P[f"W{l}"]).T + P[f"b{l}"]
+        H = pt(f"H{l}", np.maximum(Z, 0.0))
+        zs.append(Z)
         hs.append(H)
     y = H @ P["w5"] + P["b5"][0]
-    return (y, hs) if cache else y
+    return (y, zs, hs) if cache else y
 
 
-def loss_and_gradient(params, X, target, bf16=True):
+def loss_and_gradient(params, X, target, cache=False, perturb=None):
     """Mean squared error and its gradient with respect to the flat parameter
-    vector (back-propagation through the layers above)."""
+    vector (back-propagation through the layers above).  cache=True also
+    returns dict(y, Z, H, dy, dZ) with dZ[l-1] the gradient of the loss with
+    respect to Z_l."""
+    pt = _keep if perturb is None else perturb
     P = unpack(params)
-    y, hs = forward(params, X, bf16=bf16, cache=True)
+    Wq = {l: pt(f"W{l}", P[f"W{l}"]) for l in range(1, 5)}
+
+    def same_weights(name, a):      # the forward and the backward use one set of weights
+        return Wq[int(name[1])] if name.startswith("W") else pt(name, a)
+
+    y, zs, hs = forward(params, X, cache=True, perturb=same_weights)
     t = np.asarray(target, np.float64)
     m = len(t)
     d = y - t
     loss = float(np.mean(d * d))
     dy = 2.0 * d / m
     G = {"w5": hs[4].T @ dy, "b5": np.array([dy.sum()])}
-    dZ = np.outer(dy, P["w5"]) * (hs[4] > 0)
-    if bf16:
-        dZ = bf16_round(dZ)
+    dZ = pt("dZ4", np.outer(dy, P["w5"]) * (zs[3] > 0))
+    dzs = [None] * 4
     for l in range(4, 0, -1):
+        dzs[l - 1] = dZ
         G[f"W{l}"] = dZ.T @ hs[l - 1]
         G[f"b{l}"] = dZ.sum(axis=0)
         if l > 1:
-            W = P[f"W{l}"]
-            if bf16:
-                W = bf16_round(W)
-            dZ = (dZ @ W) * (hs[l - 1] > 0)
-            if bf16:
-                dZ = bf16_round(dZ)
+            dZ = pt(f"dZ{l - 1}", (dZ @ Wq[l]) * (zs[l - 2] > 0))
+    if cache:
+        return loss, pack(G), dict(y=y, Z=zs, H=hs, dy=dy, dZ=dzs)
     return loss, pack(G)

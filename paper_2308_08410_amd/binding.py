@@ -73,6 +73,11 @@ _backward = _sig("gbp_eikonal_backward", [c_void_p, c_void_p, c_void_p, c_void_p
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _parents = _sig("gbp_parent_map", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_forward_async = _sig("gbp_eikonal_forward_async", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                                    c_void_p, c_void_p, c_int, c_void_p])
+_backward_async = _sig("gbp_eikonal_backward_async", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                                      c_int, c_void_p])
 _ecg_fwd = _sig("gbp_ecg_forward", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(AP), c_void_p,
                                     c_void_p])
 _ecg_bwd = _sig("gbp_ecg_backward", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(AP), c_void_p,
@@ -89,6 +94,7 @@ _prof_read = _sig("gbp_profile_read", [ctypes.c_char_p, ctypes.POINTER(ctypes.c_
 _plan_status = _sig("gbp_plan_status", [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                         ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                         ctypes.POINTER(c_int), c_void_p])
+_forward_work = _sig("gbp_plan_forward_work", [c_void_p, c_void_p, c_void_p, c_void_p])
 _set_launch = _sig("gbp_plan_set_launch", [c_void_p, c_int, c_int, c_int, c_int])
 _get_launch = _sig("gbp_plan_get_launch", [c_void_p] + [ctypes.POINTER(c_int)] * 4)
 _set_split = _sig("gbp_plan_set_queue_split", [c_void_p, c_int])
@@ -105,6 +111,7 @@ _ecg_loss_b = _sig("gbp_ecg_loss_batched", [c_void_p, c_void_p, c_int, c_int, c_
 _step_create = _sig("gbp_step_create", [c_void_p, ctypes.POINTER(c_void_p)])
 _step_launch = _sig("gbp_step_launch", [c_void_p, c_void_p])
 _step_destroy = _sig("gbp_step_destroy", [c_void_p], None)
+_step_gradients = _sig("gbp_step_gradients", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
 _point_roots = _sig("gbp_point_roots", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                         c_void_p, c_void_p, c_void_p])
 _point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
@@ -253,6 +260,45 @@ def eikonal_backward(plan: Plan, D, vscale, root_node, root_t, T, dL_dT, want_D=
                      _ptr(dD, torch.float32, (n_e, 6), "dL_dD"),
                      _ptr(dvs, torch.float32, (n_v,), "dL_dvscale"),
                      _ptr(dt, torch.float32, (R,), "dL_droot_t"), _stream(stream)))
+    return dD, dvs, dt
+
+
+def eikonal_forward_async(plan: Plan, D, vscale, root_node, root_t, round_budget, T_init=None, out=None,
+                          stream=None):
+    """gbp_eikonal_forward_async: enqueue `round_budget` relaxation rounds, no
+    synchronisation; read convergence and input errors with plan_status."""
+    n_v, n_e = plan.n_v, plan.n_e
+    R = root_node.numel()
+    if out is None:
+        out = torch.empty(n_v, dtype=torch.float32, device=D.device)
+    _check(_forward_async(plan.handle, _ptr(D, torch.float32, (n_e, 6), "D"),
+                          _ptr(vscale, torch.float32, (n_v,), "vscale"),
+                          _ptr(root_node, torch.int32, (R,), "root_node"),
+                          _ptr(root_t, torch.float32, (R,), "root_t"), R,
+                          _ptr(T_init, torch.float32, (n_v,), "T_init"),
+                          _ptr(out, torch.float32, (n_v,), "T_out"), int(round_budget), _stream(stream)))
+    return out
+
+
+def eikonal_backward_async(plan: Plan, D, vscale, root_node, root_t, T, dL_dT, level_budget, gs_budget=32,
+                           want_D=True, want_vscale=True, want_root_t=True, stream=None):
+    """gbp_eikonal_backward_async: enqueue the adjoint with fixed budgets, no
+    synchronisation.  Returns (dL/dD, dL/dvscale, dL/droot_t) tensors."""
+    n_v, n_e = plan.n_v, plan.n_e
+    R = root_node.numel()
+    dev = T.device
+    dD = torch.empty((n_e, 6), dtype=torch.float32, device=dev) if want_D else None
+    dvs = torch.empty(n_v, dtype=torch.float32, device=dev) if want_vscale else None
+    dt = torch.empty(R, dtype=torch.float32, device=dev) if want_root_t else None
+    _check(_backward_async(plan.handle, _ptr(D, torch.float32, (n_e, 6), "D"),
+                           _ptr(vscale, torch.float32, (n_v,), "vscale"),
+                           _ptr(root_node, torch.int32, (R,), "root_node"),
+                           _ptr(root_t, torch.float32, (R,), "root_t"), R,
+                           _ptr(T, torch.float32, (n_v,), "T"), _ptr(dL_dT, torch.float32, (n_v,), "dL_dT"),
+                           _ptr(dD, torch.float32, (n_e, 6), "dL_dD"),
+                           _ptr(dvs, torch.float32, (n_v,), "dL_dvscale"),
+                           _ptr(dt, torch.float32, (R,), "dL_droot_t"), int(level_budget), int(gs_budget),
+                           _stream(stream)))
     return dD, dvs, dt
 
 
@@ -443,6 +489,14 @@ def plan_status(plan: Plan, stream=None):
                         ctypes.byref(l), _stream(stream)))
     return dict(err=e.value, forward_converged=bool(f.value), backward_settled=bool(b.value),
                 rounds=r.value, levels=l.value)
+
+
+def forward_work(plan: Plan, stream=None):
+    """Synchronises and returns the last forward's work (gbp_plan_forward_work):
+    local problems evaluated and vertex value changes."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_forward_work(plan.handle, ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+    return dict(face_solves=a.value, node_updates=b.value)
 
 
 def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=2048, sync_batch=16):
@@ -636,9 +690,19 @@ class Step:
         h = c_void_p()
         _check(_step_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
+        self._n_v, self._R, self._dev = n_v, R, T.device
 
     def launch(self, stream=None):
         _check(_step_launch(self._h, _stream(stream)))
+
+    def gradients(self, stream=None):
+        """(dL/dT, dL/dvscale, dL/droot_t) of the last replay, before its Adam
+        updates (gbp_step_gradients)."""
+        gT = torch.empty(self._n_v, dtype=torch.float32, device=self._dev)
+        gv = torch.empty(self._n_v, dtype=torch.float32, device=self._dev)
+        gr = torch.empty(max(self._R, 1), dtype=torch.float32, device=self._dev)
+        _check(_step_gradients(self._h, gT.data_ptr(), gv.data_ptr(), gr.data_ptr(), _stream(stream)))
+        return gT, gv, gr[: self._R]
 
     def close(self):
         h = getattr(self, "_h", None)

@@ -8,7 +8,7 @@
 // span [Tmin, Tmax], so for t_s < Tmin - 6 tau every term is at rest and for
 // t_s > Tmax + 6 tau every term is at K1.  Only the window in between needs the
 // template; there the contraction (time x vertices) . (vertices x leads) runs on
-// MFMA 16x16x16 bf16 tiles whose A operand is generated in registers from T.
+// v_mfma_f32_16x16x32_bf16 tiles whose A operand is generated in registers from T.
 // Both operands are split into bf16 hi + lo parts (three products, FP32
 // accumulation), since the lead weights sum to ~0 and the ECG is a cancellation.
 // The saturated part is a step function: the window's weight sum is added once at
@@ -17,6 +17,14 @@
 // Backward:  dT_n = -sum_s U'(t_s - T_n) sum_l G[s,l] W[n,l], with U' zero outside
 // the same window; R = U' G runs on MFMA (vertices x time) . (time x leads) and the
 // row-wise dot with W finishes in registers.  No atomics: deterministic.
+//
+// One launch covers a tile of at most 16 leads and a chunk of at most kMaxChunk
+// time steps (the window and G tiles live in LDS); the host walks the tiles and
+// chunks.  A chunk is an independent ECG on its own time grid; the backward adds
+// the contributions of later tiles and chunks to dT in launch order.
+//
+// MFMA 16x16x32 lane layout (checked on the device): lane l holds A[l % 16][8 (l / 16) + q]
+// and B[8 (l / 16) + q][l % 16], q = 0..7, and returns D[4 (l / 16) + r][l % 16], r = 0..3.
 #include <math.h>
 #include <mutex>
 
@@ -25,12 +33,15 @@
 
 namespace {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr float kSat = 24.f;          // |4 xi / tau| beyond which sigma is saturated
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr int kMaxSteps = 992;      // keeps the LDS of both kernels within 64 KB
+constexpr int kMaxChunk = 992;        // time steps per launch: keeps the LDS of both kernels within 64 KB
+constexpr int kMaxSteps = 1 << 20;    // time steps per call
+constexpr int kMaxLeads = 256;
 
 __device__ __forceinline__ unsigned bf16_rne(float x) {
     const unsigned u = __float_as_uint(x);
@@ -43,11 +54,12 @@ __device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
     lo = (short)bf16_rne(x - __uint_as_float(h << 16));
 }
 
-__device__ __forceinline__ floatx4 mfma3(bf16x4_t ah, bf16x4_t al, bf16x4_t bh, bf16x4_t bl,
-                                         floatx4 acc) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+__device__ __forceinline__ floatx4 mfma3(short8 ah, short8 al, short8 bh, short8 bl, floatx4 acc) {
+    const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah), Al = __builtin_bit_cast(bf16x8_t, al);
+    const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh), Bl = __builtin_bit_cast(bf16x8_t, bl);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc, 0, 0, 0);
     return acc;
 }
 
@@ -62,7 +74,15 @@ __device__ __forceinline__ float wave_max(float v) {
 
 struct ApDev {
     float K0, amp, c4, dudx, t0, dt, halfw;  // c4 = 4 log2(e)/tau, dudx = amp*4/tau, halfw = 6 tau
-    int S;
+    int S;                                    // time steps of this chunk
+};
+
+// Tile of the lead and time axes a launch works on: columns [0, Lt) of arrays
+// whose rows are Ls floats long (W, and ecg / G per time step), the latter
+// `istride` floats apart from one instance to the next.
+struct LeadTile {
+    int Ls, Lt;
+    long long istride;
 };
 
 // window [s_lo, s_hi) of a wave's finite activation times; empty if none finite
@@ -84,19 +104,21 @@ __device__ __forceinline__ void wave_window(float Tv, const ApDev& ap, int& s_lo
 }
 
 // ------------------------------------------------------------------ forward
-// Block: 4 waves; each wave takes 64-vertex groups of the block's range.
+// Block: 4 waves; each wave takes 64-vertex groups of the block's range (two
+// K-steps of 32 vertices: lane (col, kq) holds vertices 8 kq .. 8 kq + 7).
 // Dynamic LDS: win[S_pad*16] floats.  The step histogram goes to global memory
 // directly (one 16-wide add per 64-vertex group).
 // Grid (blocks per instance, instances); instance i owns vertices
 // [off[i], off[i+1]) (off == nullptr: one instance of n_v vertices).
 __global__ void __launch_bounds__(256)
-    k_ecg_fwd(const float* __restrict__ T, const float* __restrict__ W, int n_v, int L,
+    k_ecg_fwd(const float* __restrict__ T, const float* __restrict__ W, int n_v, LeadTile lt,
               ApDev ap, int S_pad, int groups_per_block, const int* __restrict__ off,
               float* __restrict__ g_win_all, float* __restrict__ g_hist_all,
               float* __restrict__ g_wsum_all) {
     extern __shared__ float win[];
     const int inst = blockIdx.y;
     const int vbeg = off ? off[inst] : 0, vend = off ? off[inst + 1] : n_v;
+    const int Ls = lt.Ls, Lt = lt.Lt;
     float* g_win = g_win_all + (size_t)inst * S_pad * 16;
     float* g_hist = g_hist_all + (size_t)inst * S_pad * 16;
     float* g_wsum = g_wsum_all + (size_t)inst * 16;
@@ -110,7 +132,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
-    float wsum_all = 0.f;   // lane: lead col, vertices 4kq+r of each K-step
+    float wsum_all = 0.f;   // lane: lead col, vertices 8kq+q of each K-step
     for (int gi = wave; gi < groups_per_block; gi += 4) {
         const int g0 = vbeg + (blockIdx.x * groups_per_block + gi) * 64;
         if (g0 >= vend) break;
@@ -120,11 +142,11 @@ __global__ void __launch_bounds__(256)
         bool any;
         wave_window(Tl, ap, s_lo, s_hi, any);
         float wsum_fin = 0.f;
-        // W fragments and sums (4 K-steps of 16 vertices)
-        for (int ks = 0; ks < 4; ++ks) {
-            for (int r = 0; r < 4; ++r) {
-                const int n = g0 + ks * 16 + kq * 4 + r;
-                const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
+        // weight sums (2 K-steps of 32 vertices)
+        for (int ks = 0; ks < 2; ++ks) {
+            for (int q = 0; q < 8; ++q) {
+                const int n = g0 + ks * 32 + kq * 8 + q;
+                const float w = (n < vend && col < Lt) ? W[(size_t)n * Ls + col] : 0.f;
                 const float t = n < vend ? T[n] : __builtin_huge_valf();
                 wsum_all += w;
                 if (t < __builtin_huge_valf()) wsum_fin += w;
@@ -136,29 +158,29 @@ __global__ void __launch_bounds__(256)
             floatx4 acc[4];
             for (int m = 0; m < 4; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
             const int ntile = min(4, (s_hi - s0 + 15) / 16);
-            for (int ks = 0; ks < 4; ++ks) {
-                float tv[4];
-                bf16x4_t bh, bl;
-                for (int r = 0; r < 4; ++r) {
-                    const int n = g0 + ks * 16 + kq * 4 + r;
-                    const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
-                    tv[r] = n < vend ? T[n] : __builtin_huge_valf();
+            for (int ks = 0; ks < 2; ++ks) {
+                float tv[8];
+                short8 bh, bl;
+                for (int q = 0; q < 8; ++q) {
+                    const int n = g0 + ks * 32 + kq * 8 + q;
+                    const float w = (n < vend && col < Lt) ? W[(size_t)n * Ls + col] : 0.f;
+                    tv[q] = n < vend ? T[n] : __builtin_huge_valf();
                     short h, l;
                     split_bf16(w, h, l);
-                    bh[r] = h;
-                    bl[r] = l;
+                    bh[q] = h;
+                    bl[q] = l;
                 }
                 for (int m = 0; m < 4; ++m) {
                     if (m >= ntile) break;
                     const float t = ap.t0 + (float)(s0 + 16 * m + col) * ap.dt;
-                    bf16x4_t ah, al;
-                    for (int r = 0; r < 4; ++r) {
-                        const float e = __builtin_amdgcn_exp2f((tv[r] - t) * ap.c4);
+                    short8 ah, al;
+                    for (int q = 0; q < 8; ++q) {
+                        const float e = __builtin_amdgcn_exp2f((tv[q] - t) * ap.c4);
                         const float a = ap.amp * __builtin_amdgcn_rcpf(1.f + e);
                         short h, l;
                         split_bf16(a, h, l);
-                        ah[r] = h;
-                        al[r] = l;
+                        ah[q] = h;
+                        al[q] = l;
                     }
                     acc[m] = mfma3(ah, al, bh, bl, acc[m]);
                 }
@@ -166,14 +188,14 @@ __global__ void __launch_bounds__(256)
             for (int m = 0; m < ntile; ++m)
                 for (int r = 0; r < 4; ++r) {
                     const int s = s0 + 16 * m + kq * 4 + r;
-                    if (s < s_hi && col < L) atomicAdd(&win[s * 16 + col], acc[m][r]);
+                    if (s < s_hi && col < Lt) atomicAdd(&win[s * 16 + col], acc[m][r]);
                 }
         }
         // saturated part: step at s_hi
         float hsum = wsum_fin;
         hsum += __shfl_xor(hsum, 16);
         hsum += __shfl_xor(hsum, 32);
-        if (s_hi < ap.S && kq == 0 && col < L) atomicAdd(&g_hist[s_hi * 16 + col], ap.amp * hsum);
+        if (s_hi < ap.S && kq == 0 && col < Lt) atomicAdd(&g_hist[s_hi * 16 + col], ap.amp * hsum);
         if (lane == 0) {
             atomicMin(&blo, s_lo);
             atomicMax(&bhi, s_hi);
@@ -183,14 +205,14 @@ __global__ void __launch_bounds__(256)
     wsum_all += __shfl_xor(wsum_all, 32);
     if (kq == 0) wsum_sh[wave][col] = wsum_all;
     __syncthreads();
-    if (threadIdx.x < 16 && (int)threadIdx.x < L) {
+    if (threadIdx.x < 16 && (int)threadIdx.x < Lt) {
         const float v = wsum_sh[0][threadIdx.x] + wsum_sh[1][threadIdx.x] +
                         wsum_sh[2][threadIdx.x] + wsum_sh[3][threadIdx.x];
         atomicAdd(&g_wsum[threadIdx.x], v);
     }
     const int lo = blo, hi = min(bhi, ap.S);
     for (int x = lo * 16 + threadIdx.x; x < hi * 16; x += blockDim.x) {
-        if ((x & 15) >= L) continue;
+        if ((x & 15) >= Lt) continue;
         const float a = win[x];
         if (a != 0.f) atomicAdd(&g_win[x], a);
     }
@@ -205,14 +227,14 @@ __global__ void k_ecg_zero(float* __restrict__ p, int n) {
 // thread (c, l) owns lead l and the c-th of 64 contiguous chunks of time steps.
 __global__ void __launch_bounds__(1024)
     k_ecg_finish(const float* __restrict__ g_win_all, const float* __restrict__ g_hist_all,
-                 const float* __restrict__ g_wsum_all, int S, int S_pad, int L, float K0,
+                 const float* __restrict__ g_wsum_all, int S, int S_pad, LeadTile lt, float K0,
                  float* __restrict__ ecg_all) {
     __shared__ float part[64][17];
     const int inst = blockIdx.x;
     const float* g_win = g_win_all + (size_t)inst * S_pad * 16;
     const float* g_hist = g_hist_all + (size_t)inst * S_pad * 16;
     const float* g_wsum = g_wsum_all + (size_t)inst * 16;
-    float* ecg = ecg_all + (size_t)inst * S * L;
+    float* ecg = ecg_all + (size_t)inst * lt.istride;
     const int l = threadIdx.x & 15, c = threadIdx.x >> 4;
     const int len = (S + 63) / 64;
     const int s0 = c * len, s1 = min(S, s0 + len);
@@ -222,30 +244,32 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     float off = 0.f;
     for (int k = 0; k < c; ++k) off += part[k][l];
-    if (l < L) {
+    if (l < lt.Lt) {
         const float base = K0 * g_wsum[l];
         float r = off;
         for (int s = s0; s < s1; ++s) {
             r += g_hist[s * 16 + l];
-            ecg[(size_t)s * L + l] = base + r + g_win[s * 16 + l];
+            ecg[(size_t)s * lt.Ls + l] = base + r + g_win[s * 16 + l];
         }
     }
 }
 
 // ------------------------------------------------------------------ backward
+// accumulate: add this tile's / chunk's contribution to dT instead of writing it.
 __global__ void __launch_bounds__(256)
     k_ecg_bwd(const float* __restrict__ T, const float* __restrict__ W,
-              const float* __restrict__ G_all, int n_v, int L, ApDev ap, int S_pad,
-              const int* __restrict__ off, float* __restrict__ dT) {
+              const float* __restrict__ G_all, int n_v, LeadTile lt, ApDev ap, int S_pad,
+              const int* __restrict__ off, int accumulate, float* __restrict__ dT) {
     extern __shared__ short gl[];  // [S_pad*16] hi, then [S_pad*16] lo
     const int inst = blockIdx.y;
     const int vbeg = off ? off[inst] : 0, vend = off ? off[inst + 1] : n_v;
-    const float* G = G_all + (size_t)inst * ap.S * L;
+    const int Ls = lt.Ls, Lt = lt.Lt;
+    const float* G = G_all + (size_t)inst * lt.istride;
     short* gh = gl;
     short* glo = gl + S_pad * 16;
     for (int x = threadIdx.x; x < S_pad * 16; x += blockDim.x) {
         const int s = x >> 4, l = x & 15;
-        const float v = (s < ap.S && l < L) ? G[(size_t)s * L + l] : 0.f;
+        const float v = (s < ap.S && l < Lt) ? G[(size_t)s * Ls + l] : 0.f;
         short h, lo;
         split_bf16(v, h, lo);
         gh[x] = h;
@@ -268,22 +292,22 @@ __global__ void __launch_bounds__(256)
             const float tn = nrow < vend ? T[nrow] : __builtin_huge_valf();
             floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
             if (any) {
-                for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
-                    bf16x4_t ah, al, bh, bl;
-                    for (int r = 0; r < 4; ++r) {
-                        const int s = s0 + kq * 4 + r;
+                for (int s0 = s_lo; s0 < s_hi; s0 += 32) {   // K-steps of 32 time steps
+                    short8 ah, al, bh, bl;
+                    for (int q = 0; q < 8; ++q) {
+                        const int s = s0 + kq * 8 + q;
                         const float t = ap.t0 + (float)s * ap.dt;
                         const float e = __builtin_amdgcn_exp2f((tn - t) * ap.c4);
-                        const float q = __builtin_amdgcn_rcpf(1.f + e);
-                        const float omq = e < 1.f ? e * q : 1.f - q;
-                        const float a = (s < ap.S) ? ap.dudx * q * omq : 0.f;
+                        const float qq = __builtin_amdgcn_rcpf(1.f + e);
+                        const float omq = e < 1.f ? e * qq : 1.f - qq;
+                        const float a = (s < ap.S) ? ap.dudx * qq * omq : 0.f;
                         short h, l;
                         split_bf16(a, h, l);
-                        ah[r] = h;
-                        al[r] = l;
+                        ah[q] = h;
+                        al[q] = l;
                         const int sc = s < S_pad ? s : S_pad - 1;
-                        bh[r] = (s < ap.S) ? gh[sc * 16 + col] : (short)0;
-                        bl[r] = (s < ap.S) ? glo[sc * 16 + col] : (short)0;
+                        bh[q] = (s < ap.S) ? gh[sc * 16 + col] : (short)0;
+                        bl[q] = (s < ap.S) ? glo[sc * 16 + col] : (short)0;
                     }
                     acc = mfma3(ah, al, bh, bl, acc);
                 }
@@ -292,7 +316,7 @@ __global__ void __launch_bounds__(256)
             float out[4];
             for (int r = 0; r < 4; ++r) {
                 const int n = g0 + mt * 16 + kq * 4 + r;
-                const float w = (n < vend && col < L) ? W[(size_t)n * L + col] : 0.f;
+                const float w = (n < vend && col < Lt) ? W[(size_t)n * Ls + col] : 0.f;
                 float v = acc[r] * w;
                 v += __shfl_xor(v, 1);
                 v += __shfl_xor(v, 2);
@@ -303,7 +327,7 @@ __global__ void __launch_bounds__(256)
             if (col == 0)
                 for (int r = 0; r < 4; ++r) {
                     const int n = g0 + mt * 16 + kq * 4 + r;
-                    if (n < vend) dT[n] = -out[r];
+                    if (n < vend) dT[n] = accumulate ? dT[n] - out[r] : -out[r];
                 }
         }
     }
@@ -340,8 +364,8 @@ int ecg_workspace(size_t nfloat, float** out) {
 }
 
 int check_ap(const float* T, int n_v, const float* W, int L, const gbp_ap* ap) {
-    if (!T || !W || !ap || n_v <= 0 || L < 1 || L > 16) {
-        gbp_set_error("ECG: need T, W, ap, n_v > 0 and 1 <= L <= 16 (L=%d)", L);
+    if (!T || !W || !ap || n_v <= 0 || L < 1 || L > kMaxLeads) {
+        gbp_set_error("ECG: need T, W, ap, n_v > 0 and 1 <= L <= %d (L=%d)", kMaxLeads, L);
         return GBP_ERR_ARG;
     }
     if (ap->n_steps < 1 || ap->n_steps > kMaxSteps || !(ap->dt > 0.f) || !(ap->tau > 0.f) ||
@@ -352,57 +376,89 @@ int check_ap(const float* T, int n_v, const float* W, int L, const gbp_ap* ap) {
     return GBP_OK;
 }
 
-ApDev make_ap(const gbp_ap* a) {
+// the template constants for the chunk of `len` steps starting at step s0
+ApDev make_ap(const gbp_ap* a, int s0, int len) {
     ApDev d;
     d.K0 = a->K0;
     d.amp = a->K1 - a->K0;
     d.c4 = 4.f * kLog2e / a->tau;
     d.dudx = (a->K1 - a->K0) * 4.f / a->tau;
-    d.t0 = a->t0;
+    d.t0 = a->t0 + (float)s0 * a->dt;
     d.dt = a->dt;
     d.halfw = kSat * a->tau / 4.f;
-    d.S = a->n_steps;
+    d.S = len;
     return d;
+}
+
+int chunk_pad(int len) { return (len + 15) / 16 * 16 + 16; }
+
+// floats of forward scratch per instance: window and histogram of one chunk, weight sums
+size_t ecg_work_floats(int n_steps) {
+    const int S_pad = chunk_pad(std::min(n_steps, kMaxChunk));
+    return (size_t)2 * S_pad * 16 + 16;
 }
 
 struct EcgLaunch {
     const int* off;       // device offsets or nullptr
     int n_inst;
     int max_verts;        // largest instance
-    float* work;          // n_inst * (2*S_pad*16 + 16) floats
+    float* work;          // n_inst * ecg_work_floats(n_steps) floats
 };
 
+// Every (lead tile, time chunk) of the call: a forward chunk is an ECG on its own
+// time grid (the instance's rows of ecg are n_steps * L floats apart).
 int ecg_forward_launch(const EcgLaunch& el, const float* T, int n_v, const float* W, int L,
-                       const ApDev& d, float* ecg, hipStream_t s) {
-    const int S_pad = (d.S + 15) / 16 * 16 + 16;
-    float* g_win = el.work;
-    float* g_hist = el.work + (size_t)el.n_inst * S_pad * 16;
-    float* g_wsum = el.work + (size_t)2 * el.n_inst * S_pad * 16;
-    const int total = el.n_inst * (2 * S_pad * 16 + 16);
-    k_ecg_zero<<<std::min((total + 255) / 256, 1024), 256, 0, s>>>(el.work, total);
-    const int groups = (el.max_verts + 63) / 64;
-    const int gpb = 8;    // 64-vertex groups per block (2 per wave; 16 measured slower: fewer resident waves)
-    const dim3 grid((groups + gpb - 1) / gpb, el.n_inst);
-    const size_t lds = (size_t)S_pad * 16 * sizeof(float);
-    {
-        ProfScope ps(GBP_PROF_ECG_FWD, s);
-        k_ecg_fwd<<<grid, 256, lds, s>>>(T, W, n_v, L, d, S_pad, gpb, el.off, g_win, g_hist, g_wsum);
+                       const gbp_ap* ap, float* ecg, hipStream_t s) {
+    const int S = ap->n_steps;
+    for (int c0 = 0; c0 < L; c0 += 16) {
+        for (int s0 = 0; s0 < S; s0 += kMaxChunk) {
+            const int len = std::min(kMaxChunk, S - s0);
+            const ApDev d = make_ap(ap, s0, len);
+            const LeadTile lt{L, std::min(16, L - c0), (long long)S * L};
+            const int S_pad = chunk_pad(len);
+            float* g_win = el.work;
+            float* g_hist = el.work + (size_t)el.n_inst * S_pad * 16;
+            float* g_wsum = el.work + (size_t)2 * el.n_inst * S_pad * 16;
+            const int total = el.n_inst * (2 * S_pad * 16 + 16);
+            k_ecg_zero<<<std::min((total + 255) / 256, 1024), 256, 0, s>>>(el.work, total);
+            const int groups = (el.max_verts + 63) / 64;
+            const int gpb = 8;    // 64-vertex groups per block (2 per wave; 16 measured slower: fewer resident waves)
+            const dim3 grid((groups + gpb - 1) / gpb, el.n_inst);
+            const size_t lds = (size_t)S_pad * 16 * sizeof(float);
+            {
+                ProfScope ps(GBP_PROF_ECG_FWD, s);
+                k_ecg_fwd<<<grid, 256, lds, s>>>(T, W + c0, n_v, lt, d, S_pad, gpb, el.off, g_win,
+                                                 g_hist, g_wsum);
+            }
+            k_ecg_finish<<<el.n_inst, 1024, 0, s>>>(g_win, g_hist, g_wsum, len, S_pad, lt, d.K0,
+                                                    ecg + (size_t)s0 * L + c0);
+            GBP_LAUNCH_CHECK();
+        }
     }
-    k_ecg_finish<<<el.n_inst, 1024, 0, s>>>(g_win, g_hist, g_wsum, d.S, S_pad, L, d.K0, ecg);
-    GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
 
 int ecg_backward_launch(const EcgLaunch& el, const float* T, int n_v, const float* W, int L,
-                        const ApDev& d, const float* G, float* dT, hipStream_t s) {
-    const int S_pad = (d.S + 15) / 16 * 16 + 16;
-    const int groups = (el.max_verts + 63) / 64;
-    const dim3 grid(std::max(1, std::min((groups + 3) / 4, 2048 / std::max(1, el.n_inst) + 1)),
-                    el.n_inst);
-    const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
-    ProfScope ps(GBP_PROF_ECG_BWD, s);
-    k_ecg_bwd<<<grid, 256, lds, s>>>(T, W, G, n_v, L, d, S_pad, el.off, dT);
-    GBP_LAUNCH_CHECK();
+                        const gbp_ap* ap, const float* G, float* dT, hipStream_t s) {
+    const int S = ap->n_steps;
+    int first = 1;
+    for (int c0 = 0; c0 < L; c0 += 16) {
+        for (int s0 = 0; s0 < S; s0 += kMaxChunk) {
+            const int len = std::min(kMaxChunk, S - s0);
+            const ApDev d = make_ap(ap, s0, len);
+            const LeadTile lt{L, std::min(16, L - c0), (long long)S * L};
+            const int S_pad = chunk_pad(len);
+            const int groups = (el.max_verts + 63) / 64;
+            const dim3 grid(std::max(1, std::min((groups + 3) / 4, 2048 / std::max(1, el.n_inst) + 1)),
+                            el.n_inst);
+            const size_t lds = (size_t)2 * S_pad * 16 * sizeof(short);
+            ProfScope ps(GBP_PROF_ECG_BWD, s);
+            k_ecg_bwd<<<grid, 256, lds, s>>>(T, W + c0, G + (size_t)s0 * L + c0, n_v, lt, d, S_pad,
+                                             el.off, first ? 0 : 1, dT);
+            GBP_LAUNCH_CHECK();
+            first = 0;
+        }
+    }
     return GBP_OK;
 }
 
@@ -439,8 +495,7 @@ extern "C" int gbp_batch_create(const int32_t* offsets, int n_inst, int max_step
     b->max_verts = std::max(mx, 1);
     b->total = offsets[n_inst];
     b->max_steps = max_steps;
-    const int S_pad = (max_steps + 15) / 16 * 16 + 16;
-    const size_t nwork = (size_t)n_inst * (2 * S_pad * 16 + 16);
+    const size_t nwork = (size_t)n_inst * ecg_work_floats(max_steps);
     if (hipMalloc((void**)&b->off, sizeof(int) * (n_inst + 1)) != hipSuccess ||
         hipMalloc((void**)&b->work, sizeof(float) * nwork) != hipSuccess) {
         gbp_set_error("batch: allocation failed");
@@ -493,11 +548,9 @@ extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, c
         gbp_set_error("ecg is NULL");
         return GBP_ERR_ARG;
     }
-    const ApDev d = make_ap(ap);
-    const int S_pad = (d.S + 15) / 16 * 16 + 16;
     float* work;
-    if ((rc = ecg_workspace((size_t)2 * S_pad * 16 + 16, &work))) return rc;
-    return ecg_forward_launch(EcgLaunch{nullptr, 1, n_v, work}, T, n_v, W, L, d, ecg,
+    if ((rc = ecg_workspace(ecg_work_floats(ap->n_steps), &work))) return rc;
+    return ecg_forward_launch(EcgLaunch{nullptr, 1, n_v, work}, T, n_v, W, L, ap, ecg,
                               (hipStream_t)stream);
 }
 
@@ -509,8 +562,8 @@ extern "C" int gbp_ecg_backward(const float* T, int n_v, const float* W, int L, 
         gbp_set_error("dL_decg and dL_dT are required");
         return GBP_ERR_ARG;
     }
-    return ecg_backward_launch(EcgLaunch{nullptr, 1, n_v, nullptr}, T, n_v, W, L, make_ap(ap),
-                               dL_decg, dL_dT, (hipStream_t)stream);
+    return ecg_backward_launch(EcgLaunch{nullptr, 1, n_v, nullptr}, T, n_v, W, L, ap, dL_decg, dL_dT,
+                               (hipStream_t)stream);
 }
 
 extern "C" int gbp_ecg_forward_batched(gbp_batch b, const float* T, const float* W, int L,
@@ -523,7 +576,7 @@ extern "C" int gbp_ecg_forward_batched(gbp_batch b, const float* T, const float*
         return GBP_ERR_ARG;
     }
     return ecg_forward_launch(EcgLaunch{b->off, b->n_inst, b->max_verts, b->work}, T, b->total, W,
-                              L, make_ap(ap), ecg, (hipStream_t)stream);
+                              L, ap, ecg, (hipStream_t)stream);
 }
 
 extern "C" int gbp_ecg_backward_batched(gbp_batch b, const float* T, const float* W, int L,
@@ -537,5 +590,5 @@ extern "C" int gbp_ecg_backward_batched(gbp_batch b, const float* T, const float
         return GBP_ERR_ARG;
     }
     return ecg_backward_launch(EcgLaunch{b->off, b->n_inst, b->max_verts, nullptr}, T, b->total, W,
-                               L, make_ap(ap), dL_decg, dL_dT, (hipStream_t)stream);
+                               L, ap, dL_decg, dL_dT, (hipStream_t)stream);
 }

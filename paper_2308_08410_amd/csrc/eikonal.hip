@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <vector>
+
 #include "gbp_internal.h"
 #include "local_solve.h"
 #include "fista.h"
@@ -1689,6 +1691,54 @@ extern "C" int gbp_eikonal_backward(gbp_plan p, const float* D, const float* vsc
     }
     return gbp_backward_impl(p, D, vscale, root_node, root_t, n_roots, T, dL_dT, dL_dD, dL_dvscale,
                              dL_droot_t, (hipStream_t)stream, 0, 0);
+}
+
+extern "C" int gbp_eikonal_forward_async(gbp_plan p, const float* D, const float* vscale,
+                                         const int32_t* root_node, const float* root_t,
+                                         int n_roots, const float* T_init, float* T_out,
+                                         int round_budget, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T_out || round_budget < 1) {
+        gbp_set_error("forward_async: T_out is required and round_budget >= 1 (%d)", round_budget);
+        return GBP_ERR_ARG;
+    }
+    return gbp_forward_impl(p, D, vscale, root_node, root_t, n_roots, T_init, T_out, nullptr,
+                            (hipStream_t)stream, round_budget);
+}
+
+extern "C" int gbp_eikonal_backward_async(gbp_plan p, const float* D, const float* vscale,
+                                          const int32_t* root_node, const float* root_t,
+                                          int n_roots, const float* T, const float* dL_dT,
+                                          float* dL_dD, float* dL_dvscale, float* dL_droot_t,
+                                          int level_budget, int gs_budget, void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!T || !dL_dT || level_budget < 1 || gs_budget < 0) {
+        gbp_set_error("backward_async: T and dL_dT are required, level_budget >= 1, gs_budget >= 0");
+        return GBP_ERR_ARG;
+    }
+    return gbp_backward_impl(p, D, vscale, root_node, root_t, n_roots, T, dL_dT, dL_dD, dL_dvscale,
+                             dL_droot_t, (hipStream_t)stream, level_budget, gs_budget);
+}
+
+extern "C" int gbp_plan_forward_work(gbp_plan p, int64_t* face_solves, int64_t* node_updates,
+                                     void* stream) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    std::vector<unsigned long long> b(2 * (size_t)kStatBlocks);
+    hipStream_t s = (hipStream_t)stream;
+    GBP_HIP(hipMemcpyAsync(b.data(), p->blk, b.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    unsigned long long a = 0, u = 0;
+    for (int i = 0; i < kStatBlocks; ++i) {
+        a += b[2 * i];
+        u += b[2 * i + 1];
+    }
+    if (face_solves) *face_solves = (int64_t)a;
+    if (node_updates) *node_updates = (int64_t)u;
+    return GBP_OK;
 }
 
 extern "C" int gbp_plan_status(gbp_plan p, int* err_code, int* forward_converged,

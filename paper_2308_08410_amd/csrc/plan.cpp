@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "gbp_internal.h"
+#include "gbp_test_hooks.h"
 
 static thread_local std::string g_last_error;
 

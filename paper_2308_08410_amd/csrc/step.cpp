@@ -75,7 +75,7 @@ extern "C" int gbp_step_create(const gbp_step_desc* desc, gbp_step* out) {
     gbp_plan_sizes(d.plan, &n_v, nullptr);
     if (!d.batch || !d.D || !d.vscale || !d.W || !d.target || !d.T || !d.ecg || !d.loss ||
         d.n_roots < 0 || (d.n_roots > 0 && (!d.root_node || !d.root_t)) || d.round_budget < 1 ||
-        d.level_budget < 1 || d.gs_budget < 0 || d.L < 1 || d.L > 16) {
+        d.level_budget < 1 || d.gs_budget < 0 || d.L < 1 || d.L > 256) {
         gbp_set_error("step: missing buffer or bad budget/size");
         return GBP_ERR_ARG;
     }
@@ -137,6 +137,22 @@ extern "C" int gbp_step_create(const gbp_step_desc* desc, gbp_step* out) {
         return GBP_ERR_HIP;
     }
     *out = st;
+    return GBP_OK;
+}
+
+extern "C" int gbp_step_gradients(gbp_step st, float* dL_dT, float* dL_dvscale, float* dL_droot_t,
+                                  void* stream) {
+    if (!st || !st->exec) {
+        gbp_set_error("step: not created");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (dL_dT) GBP_HIP(hipMemcpyAsync(dL_dT, st->gT, st->n_v * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (dL_dvscale)
+        GBP_HIP(hipMemcpyAsync(dL_dvscale, st->dvs, st->n_v * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (dL_droot_t && st->d.n_roots > 0)
+        GBP_HIP(hipMemcpyAsync(dL_droot_t, st->drt, st->d.n_roots * sizeof(float), hipMemcpyDeviceToDevice,
+                               s));
     return GBP_OK;
 }
 

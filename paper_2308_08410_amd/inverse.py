@@ -83,12 +83,12 @@ class MultiStartFit:
         return self.vs[sl], self.rt[i * R:(i + 1) * R], self.T[sl]
 
 
-def synthetic_problem(n_nodes, n_roots=8, seed=5):
-    """Hidden parameters (smooth scale in [0.5, 1.5], 8 onsets) and their ECG."""
+def synthetic_problem(n_nodes, n_roots=8, seed=5, n_starts=4):
+    """Hidden parameters (smooth scale in [0.5, 1.5], 8 onsets) and the fit
+    starts (scale 1, onsets U[0, 20] ms).  Returns (problem, vscale_true, [start
+    onsets])."""
     import gbp_inputs as gi
-    p = gi.shell_problem(n_nodes, seed=seed, n_roots=n_roots, n_leads=12)
-    vs_true = gi.smooth_field(p.xyz, 0.5, 1.5, seed=seed + 10)
-    return p, vs_true
+    return gi.multistart_workload(n_nodes, n_starts, n_roots, seed)
 
 
 def main(argv=None):
@@ -102,7 +102,7 @@ def main(argv=None):
                     help="start each forward from the previous iteration's activation times")
     args = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
-    p, vs_true = synthetic_problem(args.nodes, args.roots, args.seed)
+    p, vs_true, rt0 = synthetic_problem(args.nodes, args.roots, args.seed, args.starts)
     a = p.ap
     # target ECG of the hidden parameters
     plan1 = B.Plan(p.xyz, p.tets)
@@ -110,9 +110,7 @@ def main(argv=None):
                                   torch.as_tensor(p.root_node, device=dev), torch.as_tensor(p.root_t, device=dev))
     target = B.ecg_forward(T_true, torch.as_tensor(p.W, device=dev),
                            B.make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])).cpu().numpy()
-    rng = np.random.Generator(np.random.PCG64(args.seed + 1))
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(args.starts)]
-    rt0 = [rng.uniform(0.0, 20.0, size=args.roots).astype(np.float32) for _ in range(args.starts)]
     fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=args.warm)
     out = fit.run(args.iters, log_every=max(1, args.iters // 10))
     final = out["history"][-1][1]

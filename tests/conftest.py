@@ -12,6 +12,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+    # the oracle's element and vertex loops on the host cores (same results for any count)
+    import oracle
+    oracle.set_threads(min(16, os.cpu_count() or 1))
 
 
 def rng(seed):

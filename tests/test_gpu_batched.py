@@ -68,6 +68,28 @@ def test_batched_ecg_and_loss_equal_per_instance(batch):
         assert rel_l2(dT[sl], do) <= 1e-3
 
 
+def test_batched_ecg_many_leads_and_steps(batch):
+    """The batched ECG with 31 leads and 2000 steps (two lead tiles, three time
+    chunks per instance) against the oracle per instance."""
+    dev = _dev()
+    probs, xyz, tets, voff, D, vs, W, rn, rt = batch
+    ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-5.0, dt=0.07, n_steps=2000)
+    bt = B().Batch(voff, ap["n_steps"])
+    r = np.random.Generator(np.random.PCG64(3))
+    T = np.concatenate([r.uniform(0, 130, size=len(p.xyz)) for p in probs]).astype(np.float32)
+    W31 = r.normal(size=(len(T), 31)).astype(np.float32)
+    apb = B().make_ap(**ap)
+    e = B().ecg_forward_batched(bt, t32(T, dev), t32(W31, dev), apb).cpu().numpy()
+    G = r.normal(size=e.shape).astype(np.float32)
+    dT = B().ecg_backward_batched(bt, t32(T, dev), t32(W31, dev), apb, t32(G, dev)).cpu().numpy()
+    for k, p in enumerate(probs):
+        sl = slice(voff[k], voff[k + 1])
+        eo = O.ecg_forward(T[sl], W31[sl], ap)
+        assert np.abs(e[k] - eo).max() / np.abs(eo).max() <= 1e-3, k
+        do = O.ecg_backward(T[sl], W31[sl], ap, G[k])
+        assert rel_l2(dT[sl], do) <= 1e-3, k
+
+
 def _eager_iteration(plan, bt, D, vs, rn, rt, W, ap, tgt, st, lr_vs=0.01, lr_rt=0.5, warm_T=None):
     T, _ = B().eikonal_forward(plan, D, vs, rn, rt, T_init=warm_T)
     e = B().ecg_forward_batched(bt, T, W, ap)

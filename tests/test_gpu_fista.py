@@ -146,19 +146,33 @@ def test_fista_forward_converges_to_exact():
 
 @pytest.mark.parametrize("mode", ["bound", "tight"])
 def test_fista_iterations_match_oracle(faces, mode):
-    """Per-face counts from Eq. (fista_convergence): the same integers as the
-    oracle's rule on the same step constants (both decide in FP32), capped and
-    uncapped."""
+    """Per-face counts from Eq. (fista_convergence): the device decides them in
+    FP32, the oracle in FP64 on the same step constants and the same (FP32)
+    tolerance.  The FP32 evaluation of x = sqrt(4 L / (3 tau)) rounds the
+    constant 4/3, the product, the quotient and the root, each within one FP32
+    ulp, so it is within 8 * 2^-24 * x of the exact x; the counts may then
+    differ (by one) only where x lies that close to an integer.  Those faces
+    are counted and must be rare; every other face must agree exactly."""
     Q, Phi, Q6, scale = faces
     dev = _dev()
     _, _, lip = B().local_solve(t32(Q6, dev), t32(Phi, dev), "fista", n_f=1, lipschitz=mode,
                                 want_alpha=False, want_lip=True)
-    L = lip.cpu().numpy()
+    L = lip.cpu().numpy().astype(np.float64)
+    n_near = 0
     for tau in (1e-1, 1e-3, 1e-5):
+        tau32 = float(np.float32(tau))
+        x = np.sqrt(4.0 * L / (3.0 * tau32))
+        near = np.abs(x - np.round(x)) <= 8.0 * 2.0 ** -24 * x
         for n_max in (100000, 64):
             n = B().fista_iterations(lip, tau, n_max).cpu().numpy()
-            no = O.fista_iterations(L, tau, n_max)
-            assert np.array_equal(n, no), (tau, n_max, np.flatnonzero(n != no)[:5])
+            no = O.fista_iterations(L, tau32, n_max)
+            diff = n != no
+            assert not np.any(diff & ~near), (tau, n_max, np.flatnonzero(diff & ~near)[:5])
+            assert np.all(np.abs(n[diff] - no[diff]) == 1)
+            n_near += int(np.sum(diff))
+    print(f"[fista counts] {len(L)} faces x 6 settings: {n_near} differ by one at a "
+          f"near-integer bound", flush=True)
+    assert n_near <= 1e-3 * 6 * len(L)
     assert np.all(B().fista_iterations(lip, 0.0, 17).cpu().numpy() == 17)
 
 

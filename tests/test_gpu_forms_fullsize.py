@@ -1,0 +1,187 @@
+"""The batched form and the inverse problem at their full sizes against the oracle.
+
+* Batched: the 64-instance workload (8 shells of 23k-183k vertices, 6.5M vertices
+  in one union plan) in the launch configuration the benchmark's autotuner picks;
+  one replay of the captured iteration (cold, and warm-started from a far guess)
+  from the fit's start parameters.  For four instances (the smallest mesh, the
+  largest and two others) the activation times, the misfit and the gradients the
+  step computed before its Adam update are compared with the oracle's values,
+  written by tests/golden/make_forms_reference.py (oracle only).
+* Inverse problem: 16 multi-starts on the 1M-vertex shell (16M vertices), one
+  captured iteration; start 0 against the oracle the same way.
+
+The golden files hold the oracle's values at a seeded sample of 20k vertices per
+instance (all vertices of smaller meshes) and the exact norms of the full
+gradients; the comparisons are element by element on that sample.  Bars:
+activation times 1e-4 (max norm relative to the largest time), misfit, ECG
+gradient, velocity-scale and onset gradients 1e-3 (max norm relative to the
+largest entry, and relative L2 on the sample).
+
+The step differentiates at its own FP32 times.  Where a vertex's two best parents
+are within rounding of each other, either is a valid parent and the velocity-scale
+gradient jumps between them: rounding the oracle's own times to FP32 already
+moves its gradient by ~1e-3 on the smallest mesh.  Per vertex, the bar for that
+gradient therefore adds the oracle's tie envelope (the largest change of its own
+gradient under six FP32-level perturbations of its times, stored with the golden
+values) to 1e-3 of the largest entry; the other quantities have no such jumps.
+The identities of Sec. 2.3 that hold for any valid choice of parents (the onset
+gradients sum to the ECG gradient's sum over the instance's reached vertices;
+velocity homogeneity) are checked on the step's full gradients."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gbp_inputs as gi
+from test_gpu_parity import B, _dev, rel_l2, t32
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+from make_forms_reference import BATCHED_OUT, MULTISTART_OUT, input_hash  # noqa: E402
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _load(path):
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run tests/golden/make_forms_reference.py")
+    return np.load(path)
+
+
+def check_instance(ref, pre, T, gT, gv, gr, loss, label, vscale=None, root_t=None):
+    """One instance's step outputs (device tensors over its own vertices) against
+    the stored oracle values with prefix `pre`.  Returns the failures."""
+    ids = torch.as_tensor(ref[pre + "ids"].astype(np.int64), device=T.device)
+    T_s = T[ids].cpu().numpy().astype(np.float64)
+    T_o = ref[pre + "T0"].astype(np.float64)
+    out = dict(T=np.abs(T_s - T_o).max() / np.abs(T_o).max(),
+               loss=abs(float(loss) - float(ref[pre + "loss"])) / float(ref[pre + "loss"]))
+    g = gT[ids].cpu().numpy().astype(np.float64)
+    out["gT"] = np.abs(g - ref[pre + "gT"]).max() / float(ref[pre + "gT_max"])
+    out["gT_l2"] = rel_l2(g, ref[pre + "gT"])
+    g = gv[ids].cpu().numpy().astype(np.float64)
+    o = ref[pre + "dvscale"].astype(np.float64)
+    env = ref[pre + "dvscale_env"].astype(np.float64)
+    gmax = float(ref[pre + "dvscale_max"])
+    out["dvscale_raw"] = np.abs(g - o).max() / gmax
+    out["dvscale"] = np.max(np.maximum(np.abs(g - o) - env, 0.0)) / gmax      # beyond the tie envelope
+    out["dvscale_l2"] = max(np.linalg.norm(g - o) - np.linalg.norm(env), 0.0) / np.linalg.norm(o)
+    out["droot_t"] = rel_l2(gr.cpu().numpy(), ref[pre + "droot_t"])
+    Tf = T.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(Tf)
+    gTf = gT.cpu().numpy().astype(np.float64)
+    grf = gr.cpu().numpy().astype(np.float64)
+    # shift identity: sum_r dL/dt_r = sum over reached vertices of dL/dT
+    out["shift_identity"] = abs(grf.sum() - gTf[fin].sum()) / max(np.abs(gTf[fin]).sum(), 1e-30)
+    if vscale is not None:
+        # velocity homogeneity: sum_n s_n dL/ds_n - sum_r t_r dL/dt_r = -sum_n dL/dT_n T_n
+        lhs = vscale.cpu().numpy().astype(np.float64) @ gv.cpu().numpy() - root_t @ grf
+        rhs = -(gTf[fin] @ Tf[fin])
+        out["homogeneity_identity"] = abs(lhs - rhs) / max(np.abs(gTf[fin] * Tf[fin]).sum(), 1e-30)
+    print(f"[{label}] " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()), flush=True)
+    bad = []
+    if out["T"] > 1e-4:
+        bad.append((label, "T", out["T"]))
+    for k, v in out.items():
+        if k not in ("T", "dvscale_raw") and v > 1e-3:
+            bad.append((label, k, v))
+    return bad
+
+
+@pytest.fixture(scope="module")
+def batched():
+    dev = _dev()
+    from paper_2308_08410_amd import autotune
+    from paper_2308_08410_amd.batch import concat, shift_roots, union_mesh
+    ref = _load(BATCHED_OUT)
+    wl = gi.batched_workload()
+    for i in ref["instances"]:
+        m = wl.meshes[wl.mesh_of[i]]
+        if str(ref[f"i{i}_hash"]) != input_hash(m.xyz, m.tets, m.D, wl.root_node[i], wl.root_t_true[i],
+                                                  wl.root_t_start[i], wl.vscale_true[i]):
+            pytest.fail("stored batched reference does not match the generated inputs: rerun the script")
+    inst = [wl.meshes[k] for k in wl.mesh_of]
+    xyz, tets, voff, _ = union_mesh([m.xyz for m in inst], [m.tets for m in inst])
+    print(f"[case] batched union n_v={voff[-1]} n_e={len(tets)}", flush=True)
+    plan = B().Plan(xyz, tets)
+    B().set_input_reuse(plan, True)
+    f32 = lambda a: t32(a, dev)
+    D, W = f32(concat([m.D for m in inst])), f32(concat([m.W for m in inst]))
+    rn = torch.as_tensor(shift_roots(wl.root_node, voff), device=dev)
+    ap = inst[0].ap
+    S, L = ap["n_steps"], W.shape[1]
+    # the compared instances get the oracle's target; the others a zero target
+    # (instances are disconnected components: they do not influence each other)
+    target = np.zeros((len(inst), S, L), np.float32)
+    for i in ref["instances"]:
+        target[i] = ref[f"i{i}_target"]
+    st = dict(ref=ref, wl=wl, plan=plan, voff=voff, D=D, W=W, rn=rn, n_v=int(voff[-1]),
+              rt_start=concat(wl.root_t_start), ap=B().make_ap(ap["K0"], ap["K1"], ap["tau"], ap["t0"],
+                                                               ap["dt"], S),
+              batch=B().Batch(voff, S), target=f32(target), S=S, L=L, dev=dev)
+    vs, rt = f32(np.ones(st["n_v"])), f32(st["rt_start"])
+    tune = autotune.tune(plan, D, vs, rn, rt, use_cache=False, save=False, repeats=1)
+    print(f"[case] autotuned launch {tune}", flush=True)
+    st["vs_true"] = f32(concat(wl.vscale_true))
+    st["rt_true"] = f32(concat(wl.root_t_true))
+    return st
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_batched_step_matches_oracle(batched, warm):
+    from paper_2308_08410_amd import autotune
+    b = batched
+    plan, D, W, rn, dev = b["plan"], b["D"], b["W"], b["rn"], b["dev"]
+    vs = t32(np.ones(b["n_v"]), dev)
+    rt = t32(b["rt_start"], dev)
+    T = torch.empty(b["n_v"], dtype=torch.float32, device=dev)
+    B().eikonal_forward(plan, D, vs, rn, rt, out=T)
+    B().eikonal_backward(plan, D, vs, rn, rt, T, torch.ones_like(T), want_D=False)
+    bud = autotune.budgets(plan, margin=2.0 if warm else 1.5, extra=64 if warm else 32)
+    if warm:
+        # a far guess: the times of the hidden parameters
+        B().eikonal_forward(plan, D, b["vs_true"], rn, b["rt_true"], out=T)
+    ecg = torch.empty((len(b["wl"].mesh_of), b["S"], b["L"]), dtype=torch.float32, device=dev)
+    loss = torch.empty(len(b["wl"].mesh_of), dtype=torch.float32, device=dev)
+    print(f"[case] batched step warm={warm} budgets {bud}", flush=True)
+    step = B().Step(plan, b["batch"], D, vs, rn, rt, W, b["ap"], b["target"], T, ecg, loss, warm=warm, **bud)
+    step.launch()
+    status = B().plan_status(plan)
+    assert status["err"] == 0 and status["forward_converged"] and status["backward_settled"], status
+    gT, gv, gr = step.gradients()
+    torch.cuda.synchronize()
+    voff, R = b["voff"], [len(r) for r in b["wl"].root_node]
+    roff = np.concatenate([[0], np.cumsum(R)])
+    bad = []
+    for i in b["ref"]["instances"]:
+        sl = slice(int(voff[i]), int(voff[i + 1]))
+        bad += check_instance(b["ref"], f"i{i}_", T[sl], gT[sl], gv[sl], gr[roff[i]:roff[i + 1]], loss[i],
+                              f"batched warm={warm} instance {i}", vscale=torch.ones_like(T[sl]),
+                              root_t=b["rt_start"][roff[i]:roff[i + 1]].astype(np.float64))
+    step.close()
+    assert not bad, bad
+
+
+def test_multistart_iteration_matches_oracle():
+    dev = _dev()
+    from paper_2308_08410_amd.inverse import MultiStartFit
+    ref = _load(MULTISTART_OUT)
+    p, vs_true, rt0 = gi.multistart_workload()
+    if str(ref["hash"]) != input_hash(p.xyz, p.tets, p.D, p.root_node, p.root_t, vs_true, rt0[0]):
+        pytest.fail("stored multi-start reference does not match the generated inputs: rerun the script")
+    print(f"[case] multi-start fit: {len(rt0)} starts x n_v={p.n_v}", flush=True)
+    vs0 = [np.ones(p.n_v, np.float32) for _ in rt0]
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, ref["s0_target"], p.ap, vs0, rt0)
+    fit.step.launch()
+    status = B().plan_status(fit.plan)
+    assert status["err"] == 0 and status["forward_converged"] and status["backward_settled"], status
+    gT, gv, gr = fit.step.gradients()
+    torch.cuda.synchronize()
+    sl = slice(int(fit.voff[0]), int(fit.voff[1]))
+    R = len(p.root_node)
+    bad = check_instance(ref, "s0_", fit.T[sl], gT[sl], gv[sl], gr[:R], fit.loss[0], "multi-start 1M start 0",
+                         vscale=torch.ones_like(fit.T[sl]), root_t=rt0[0].astype(np.float64))
+    assert not bad, bad
+    # every start took a finite, positive misfit
+    assert torch.all(torch.isfinite(fit.loss)) and torch.all(fit.loss > 0)

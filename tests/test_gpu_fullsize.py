@@ -44,7 +44,7 @@ class Big:
         a = p.ap
         self.ap = B().make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])
 
-    def ecg_and_backward(self, calibrate=False):
+    def ecg_and_backward(self):
         p = self.p
         T64 = self.T_ref.astype(np.float64)
         ecg = B().ecg_forward(self.T_ref_dev, self.W, self.ap)
@@ -60,26 +60,15 @@ class Big:
                                             self.T_ref_dev, t32(go, self.dev))
         info = B().backward_info(self.plan)
         res = O.adjoint(p.xyz, p.tets, p.D, self.vs, p.root_node, self.rt, T64, go)
-        errs = dict(vscale=rel_l2(dvs.cpu().numpy(), res["dvscale"]),
-                    root_t=rel_l2(drt.cpu().numpy(), res["droot_t"]),
-                    D=rel_l2(dD.cpu().numpy(), res["dD"]))
-        tol = dict(vscale=1e-3, root_t=1e-3, D=1e-3)
-        if calibrate:
-            # The gradient jumps where a vertex switches between near-tied parents,
-            # so it cannot be more stable than the oracle itself under FP32
-            # rounding: perturb T by one float32 ulp (seeded signs) and take the
-            # oracle's own change as the yardstick (oracle-only computation).
-            sgn = np.random.Generator(np.random.PCG64(1)).choice([-1.0, 0.0, 1.0], size=len(T64))
-            res2 = O.adjoint(p.xyz, p.tets, p.D, self.vs, p.root_node, self.rt,
-                             T64 * (1 + sgn * 2.0 ** -23), go)
-            sens = dict(vscale=rel_l2(res2["dvscale"], res["dvscale"]),
-                        root_t=rel_l2(res2["droot_t"], res["droot_t"]),
-                        D=rel_l2(res2["dD"], res["dD"]))
-            tol = {k: max(1e-3, 3.0 * sens[k]) for k in tol}
-            print(f"[backward] oracle one-ulp sensitivity {sens}", flush=True)
-        print(f"[backward] {info} rel L2 errors {errs} tolerances {tol}", flush=True)
-        for k, v in errs.items():
-            assert v <= tol[k], (k, v, tol[k])
+        got = dict(vscale=dvs.cpu().numpy(), root_t=drt.cpu().numpy(), D=dD.cpu().numpy())
+        ref = dict(vscale=res["dvscale"], root_t=res["droot_t"], D=res["dD"])
+        errs = {k: rel_l2(got[k], ref[k]) for k in got}
+        # element by element, relative to the block's largest entry
+        emax = {k: float(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in got}
+        print(f"[backward] {info} rel L2 errors {errs}, max-norm errors {emax}", flush=True)
+        for k in got:
+            assert errs[k] <= 1e-3, (k, errs[k])
+            assert emax[k] <= 1e-3, (k, emax[k])
         return info
 
 
@@ -116,7 +105,7 @@ def test_full_forward_parity(full):
 
 
 def test_full_ecg_and_gradients(full):
-    full.ecg_and_backward(calibrate=True)
+    full.ecg_and_backward()
 
 
 @pytest.mark.parametrize("split", [True, False])
@@ -147,21 +136,29 @@ def test_full_forward_with_push_overflow(full, split):
         B().set_queue_split(plan, saved_split)
 
 
-def test_full_forward_with_fista(full):
+@pytest.mark.parametrize("launch", [(16, 1024), (8, 2048)])
+def test_full_forward_with_fista(full, launch):
     """The forward with FISTA local solves (Alg. 1, 128 iterations, tightened
     step constant) at 500k reaches the stored oracle times within 1e-4 and
     never falls below them by more than the FP32 solve's own error (FISTA
-    values are feasible points of each local problem)."""
+    values are feasible points of each local problem), in the default launch
+    (16 lanes per vertex, two local problems per lane) and in the one the
+    benchmark's FISTA figures use (8 lanes, three per lane, 2048 blocks)."""
     plan = full.plan
+    lanes, blocks = launch
+    saved = B().get_launch(plan)
     B().set_local_solver(plan, "fista", 128, "tight")
+    B().set_launch(plan, lanes, blocks, saved["level_blocks"], saved["sync_batch"])
     try:
         T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt)
     finally:
         B().set_local_solver(plan, "exact")
+        B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
     assert st["converged"]
     Tg = T.cpu().numpy().astype(np.float64)
     err = rel_max(Tg, full.T_ref)
-    print(f"[fista 500k] rel max err {err:.3e} rounds {st['rounds']}", flush=True)
+    print(f"[fista 500k] lanes {lanes} blocks {blocks}: rel max err {err:.3e} rounds {st['rounds']}",
+          flush=True)
     assert err <= 1e-4
     assert np.all(Tg >= full.T_ref * (1 - 1e-5) - 1e-6)
 

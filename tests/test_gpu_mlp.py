@@ -1,16 +1,24 @@
 """Learned warm start: the bf16 matrix-core network kernels (features, forward,
-gradient, Adam step) against the FP64 reference that rounds to bf16 at the same
-points, and the warm-started solve against the oracle's cold solution.
+gradient, Adam step) against the exact FP64 network of ``oracle/mlp.py``, and the
+warm-started solve against the oracle's cold solution.
 
-Tolerances.  Both sides round the same quantities to bf16, but the library
-accumulates in fp32 (relative error about 1e-6) and the reference in fp64, so a
-value that lies within that distance of a bf16 rounding boundary can round to
-neighbouring bf16 numbers on the two sides (probability ~1e-6 / 2^-8 per
-element).  A flip moves one hidden activation by one bf16 ulp (2^-8 relative),
-which moves the output by about 2^-8 / 16 of its size; features may differ by
-one bf16 ulp.  Bars: features within one bf16 ulp elementwise, outputs 1e-3
-(relative L2) and 5e-3 (max, relative to max |y|), gradients 5e-3 (relative L2
-per parameter block)."""
+Bounds, from the rounding unit of bf16 (8 significant bits, u = 2^-8: a rounded
+value is x (1 + delta) with |delta| <= u).  The library stores the features, the
+hidden weights, the hidden activations and the back-propagated dZ in bf16 and
+accumulates in fp32 (2^-24, negligible beside u).
+* Features: one rounding of a value computed in fp32, so |X - X64| <= u |X64|
+  plus fp32 error (1e-6 absolute for the centred coordinates).
+* Forward: the standard probabilistic model of rounding error (independent,
+  mean-zero delta; variance at most u^2 for any distribution on [-u, u]) and a
+  first-order expansion give, per output, Var(y - y64) <= u^2 sum over rounding
+  events of (dy/d(value) * value)^2, with the sensitivities dy/dZ_l, dy/dH_l of
+  the FP64 network itself.  Each output must lie within 6 such standard
+  deviations.
+* Gradients: the same model sampled (16 draws of delta ~ U[-u, u] at every
+  rounding point of the FP64 network, ``oracle.mlp``'s ``perturb``) gives the
+  spread of the gradient under bf16 storage; each parameter block's relative L2
+  error must stay within 3 times the sampled root-mean-square error (the
+  uniform draws have twice the variance of round-to-nearest errors)."""
 import numpy as np
 import pytest
 
@@ -21,6 +29,43 @@ from test_gpu_parity import B, _dev, i32, rel_l2, rel_max, t32
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+
+U_BF16 = 2.0 ** -8
+
+
+def forward_sigma(params, X):
+    """Per-row standard deviation bound of the bf16 forward's error (first order,
+    independent rounding errors of variance <= u^2): weight rounding of W_l
+    (each product W_jk H_k), activation rounding of H_1..H_4."""
+    y, zs, hs = M.forward(params, X, cache=True)
+    P = M.unpack(params)
+    var = ((P["w5"][None, :] * hs[4]) ** 2).sum(1)          # rounding of H4
+    s = P["w5"][None, :] * (zs[3] > 0)                        # dy/dZ4
+    for l in range(4, 0, -1):
+        W = P[f"W{l}"]
+        var += (s ** 2 * ((hs[l - 1] ** 2) @ (W ** 2).T)).sum(1)   # rounding of W_l
+        if l > 1:
+            g = s @ W                                        # dy/dH_{l-1}
+            var += ((g * hs[l - 1]) ** 2).sum(1)              # rounding of H_{l-1}
+            s = g * (zs[l - 2] > 0)
+    return y, U_BF16 * np.sqrt(var)
+
+
+def gradient_spread(params, X, t, draws=16, seed=0):
+    """Root-mean-square error of the FP64 gradient under the rounding model
+    (delta ~ U[-u, u] wherever the library stores bf16), per element."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    _, g64 = M.loss_and_gradient(params, X, t)
+    acc = np.zeros_like(g64)
+
+    def perturb(name, a):
+        return a * (1.0 + r.uniform(-U_BF16, U_BF16, size=a.shape))
+
+    for _ in range(draws):
+        _, gk = M.loss_and_gradient(params, X, t, perturb=perturb)
+        acc += (gk - g64) ** 2
+    return g64, np.sqrt(acc / draws)
 
 
 def bits_to_f64(X):
@@ -63,12 +108,12 @@ def test_features_match_oracle(shell):
     Xo, to = M.features(p.xyz, nf, p.vscale, rows[:-1], rx, p.root_t, norm, T=T)
     Xg = bits_to_f64(X)
     assert np.all(Xg[-1] == 0) and np.isnan(tg[-1].item())
-    assert np.all(np.abs(Xg[:-1] - Xo) <= 2.0 ** -7 * np.abs(Xo))
+    assert np.all(np.abs(Xg[:-1] - Xo) <= U_BF16 * np.abs(Xo) + 1e-6)
     np.testing.assert_allclose(tg[:-1].cpu().numpy(), to, rtol=1e-6)
     # all rows, no vscale (ones), a single root
     X1 = B().mlp_features(t32(p.xyz, dev), t32(nf, dev), t32(rx[:1], dev), t32(p.root_t[:1], dev), norm)
     Xo1 = M.features(p.xyz, nf, None, None, rx[:1], p.root_t[:1], norm)
-    assert np.all(np.abs(bits_to_f64(X1) - Xo1) <= 2.0 ** -7 * np.abs(Xo1))
+    assert np.all(np.abs(bits_to_f64(X1) - Xo1) <= U_BF16 * np.abs(Xo1) + 1e-6)
 
 
 @pytest.mark.parametrize("m", [1, 63, 3000])
@@ -80,9 +125,11 @@ def test_forward_matches_oracle(m):
     net.set_params(params)
     Xd = torch.as_tensor(bits, device="cuda")
     y = net.forward(Xd).cpu().numpy()
-    yo = M.forward(params, vals)
-    assert rel_l2(y, yo) <= 1e-3
-    assert np.abs(y - yo).max() <= 5e-3 * np.abs(yo).max()
+    yo, sig = forward_sigma(params, vals)
+    ratio = np.abs(y - yo) / (sig + 1e-6 * np.abs(yo))
+    print(f"[mlp forward] m={m} rel L2 err {rel_l2(y, yo):.2e}, max |err|/sigma {ratio.max():.2f}",
+          flush=True)
+    assert ratio.max() <= 6.0
     y2 = net.forward(Xd, out_scale=2.5).cpu().numpy()
     np.testing.assert_allclose(y2, 2.5 * y, rtol=1e-6)
     assert np.array_equal(net.get_params(), params)
@@ -99,11 +146,18 @@ def test_gradient_matches_oracle(m):
     net.set_params(params)
     loss = net.gradient(torch.as_tensor(bits, device="cuda"), t32(t, "cuda"))
     _, g = net.get_params(grads=True)
-    lo, go = M.loss_and_gradient(params, vals, t)
-    assert float(loss) == pytest.approx(lo, rel=1e-4)
-    gb, gob = blocks(g), blocks(go)
+    lo, _, c = M.loss_and_gradient(params, vals, t, cache=True)
+    _, sig = forward_sigma(params, vals)
+    # loss = mean (y - t)^2 moves by at most 2 rms(y - t) rms(dy) (Cauchy-Schwarz)
+    dl = 2.0 * np.sqrt(lo) * np.sqrt(np.mean((6.0 * sig) ** 2))
+    assert abs(float(loss) - lo) <= dl + 1e-6 * lo
+    go, spread = gradient_spread(params, vals, t)
+    gb, gob, sb = blocks(g), blocks(go), blocks(spread)
     for name, _ in M.SIZES:
-        assert rel_l2(gb[name], gob[name]) <= 5e-3, name
+        err = rel_l2(gb[name], gob[name])
+        bar = 3.0 * np.linalg.norm(sb[name]) / np.linalg.norm(gob[name])
+        print(f"[mlp gradient] m={m} {name}: rel L2 err {err:.2e}, bar {bar:.2e}", flush=True)
+        assert err <= bar + 1e-6, name
     assert np.all(gb["W1"].reshape(256, 16)[:, 15] == 0)
 
 
@@ -118,16 +172,25 @@ def test_train_step_is_adam_on_the_gradient():
     loss = torch.empty(1, device="cuda")
     net.train_step(torch.as_tensor(bits, device="cuda"), t32(t, "cuda"), lr, loss=loss)
     p1 = net.get_params()
-    _, go = M.loss_and_gradient(params, vals, t)
+    go, spread = gradient_spread(params, vals, t)
     dp = p1.astype(np.float64) - params.astype(np.float64)
-    # first Adam step: m_hat = g, v_hat = g^2, so the update is -lr g / (|g| + 1e-8)
+    # first Adam step: m_hat = g, v_hat = g^2, so the update is -lr g / (|g| + 1e-8); the
+    # device's gradient has the FP64 sign wherever |g| is far outside its rounding spread
+    # (per element, and at least the block's RMS spread, since 16 draws estimate a single
+    # element's spread loosely).  A ReLU mask that flips where a pre-activation lies within
+    # rounding of zero moves a row's contribution discretely, so a few elements in 10^4
+    # may still differ.
     for name, sl in blocks(np.arange(M.N_PARAMS)).items():
         g = go[sl]
-        big = np.abs(g) > max(1e-2 * np.sqrt(np.mean(g * g)), 1e-6)
-        assert big.sum() > 0.5 * len(g) or name == "W1", name
-        np.testing.assert_allclose(dp[sl][big], -lr * np.sign(g[big]), atol=0.02 * lr, err_msg=name)
+        sp = np.maximum(spread[sl], np.sqrt(np.mean(spread[sl] ** 2)))
+        big = (np.abs(g) > 12.0 * sp) & (np.abs(g) > 1e-6)
+        assert big.sum() > 0.25 * len(g) or name == "W1", (name, big.sum())
+        ok = np.abs(dp[sl][big] + lr * np.sign(g[big])) <= 0.02 * lr
+        assert np.sum(~ok) <= max(1, 1e-4 * big.sum()), (name, int(np.sum(~ok)), int(big.sum()))
     assert np.all(dp[:4096].reshape(256, 16)[:, 15] == 0)
-    assert float(loss) == pytest.approx(M.loss_and_gradient(params, vals, t)[0], rel=1e-4)
+    lo = M.loss_and_gradient(params, vals, t)[0]
+    _, sig = forward_sigma(params, vals)
+    assert abs(float(loss) - lo) <= 2.0 * np.sqrt(lo) * np.sqrt(np.mean((6.0 * sig) ** 2)) + 1e-6 * lo
 
 
 def test_bad_sizes_rejected():

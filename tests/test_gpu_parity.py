@@ -281,60 +281,108 @@ def test_error_codes():
 
 
 # ---------------------------------------------------------------- parents
+def gpu_parents(case):
+    """The GPU's parent map at the oracle's times, in the oracle's dict layout."""
+    pt, pn, pa, best = B().parent_map(case.plan, case.D, case.vs, case.rn, case.rt, case.T_in_dev)
+    pt, pn, pa = pt.cpu().numpy(), pn.cpu().numpy(), pa.cpu().numpy().astype(np.float64)
+    Tg = case.T_in.astype(np.float64)
+    return dict(par_tet=pt, par_node=pn, par_alpha=pa, root_self=(pt < 0) & np.isfinite(Tg))
+
+
 def compare_parents(case, tol_gap=1e-6):
+    """Where the oracle's best candidate beats every other support by more than
+    tol_gap * max(1, |T|), the GPU must pick the same support and weights (within
+    1e-3).  Where candidates tie that closely, several parents are correct: the
+    GPU's choice must then be one of them, i.e. its element's local minimum
+    (solved by the oracle at the same times) and the value of its own weights on
+    that face must both be within the tie tolerance of the oracle's best value
+    (or, for a vertex the GPU makes its own parent, the onset must be)."""
     p = case.p
     Minv = O.metric_inverse(p.D, p.vscale, p.tets)
     Tg = case.T_in.astype(np.float64)
     par_o = O.parent_map(p.xyz, p.tets, Minv, p.root_node, p.root_t, Tg)
-    pt, pn, pa, best = B().parent_map(case.plan, case.D, case.vs, case.rn, case.rt, case.T_in_dev)
-    pt, pn, pa = pt.cpu().numpy(), pn.cpu().numpy(), pa.cpu().numpy()
+    par_g = gpu_parents(case)
+    pt, pn, pa = par_g["par_tet"], par_g["par_node"], par_g["par_alpha"]
+    troot = np.full(p.n_v, np.inf)
+    for n_, t_ in zip(p.root_node, p.root_t.astype(np.float64)):
+        troot[n_] = min(troot[n_], t_)
+    x64 = p.xyz.astype(np.float64)
     scale = np.maximum(1.0, np.abs(Tg))
     clear = par_o["gap"] > tol_gap * scale
-    n_cmp = 0
-    for i in np.nonzero(clear & np.isfinite(Tg))[0]:
-        so = {int(n): a for n, a in zip(par_o["par_node"][i], par_o["par_alpha"][i]) if a > 0}
-        sg = {int(n): a for n, a in zip(pn[i], pa[i]) if n >= 0 and a > 0}
-        if par_o["par_tet"][i] < 0:
-            assert pt[i] < 0, i
+    n_cmp = n_tie = 0
+    for i in np.nonzero(np.isfinite(Tg))[0]:
+        if clear[i]:
+            so = {int(n): a for n, a in zip(par_o["par_node"][i], par_o["par_alpha"][i]) if a > 0}
+            sg = {int(n): a for n, a in zip(pn[i], pa[i]) if n >= 0 and a > 0}
+            if par_o["par_tet"][i] < 0:
+                assert pt[i] < 0, i
+                continue
+            for n in set(so) | set(sg):
+                assert abs(so.get(n, 0.0) - sg.get(n, 0.0)) <= 1e-3, (i, so, sg)
+            n_cmp += 1
             continue
-        for n in set(so) | set(sg):
-            assert abs(so.get(n, 0.0) - sg.get(n, 0.0)) <= 1e-3, (i, so, sg)
-        n_cmp += 1
-    return n_cmp, clear.mean()
+        n_tie += 1
+        best = min(par_o["best"][i], troot[i])
+        tol = tol_gap * scale[i]
+        if pt[i] < 0:
+            assert troot[i] <= best + tol, (i, troot[i], best)
+            continue
+        tet = p.tets[pt[i]]
+        k = int(np.nonzero(tet == i)[0][0])
+        Q, fv = O.face_Q(x64, tet, Minv[pt[i]], k)
+        val, _, _ = O.local_solve(Q, Tg[fv])
+        assert val <= best + tol, (i, val, best)
+        a = np.array([pa[i][list(pn[i]).index(n)] if n in list(pn[i]) else 0.0 for n in fv])
+        fin = a > 0
+        own = a[fin] @ Tg[np.array(fv)[fin]] + np.sqrt(a @ Q @ a)
+        assert own <= best + tol + 1e-5 * scale[i], (i, own, best)
+    return n_cmp, n_tie, clear.mean()
 
 
 def test_cube_parents(cube):
-    n, frac = compare_parents(cube)
+    n, n_tie, frac = compare_parents(cube)
+    print(f"[parents] cube: {n} clear parents identical, {n_tie} tied parents valid", flush=True)
     assert n > 0.5 * len(cube.T_gpu)
 
 
 def test_shell_parents(shell):
-    n, frac = compare_parents(shell)
+    n, n_tie, frac = compare_parents(shell)
+    print(f"[parents] shell: {n} clear parents identical, {n_tie} tied parents valid", flush=True)
     assert frac > 0.95 and n > 0.9 * len(shell.T_gpu)
 
 
 # ---------------------------------------------------------------- backward
-def check_backward(case, tet_level=True):
+def check_backward(case, exact_ties=False):
+    """Gradients against the oracle's adjoint at the same times.  With
+    exact_ties (a homogeneous medium, where several elements give a vertex the
+    same edge path), the parent is not unique: compare_parents checks that the
+    GPU's choice is one of the minimisers, and the oracle's adjoint is then
+    evaluated along that same (valid) choice, element by element."""
     p = case.p
     r = np.random.Generator(np.random.PCG64(11))
     g = r.normal(size=p.n_v).astype(np.float32)
     dD, dvs, dt = B().eikonal_backward(case.plan, case.D, case.vs, case.rn, case.rt, case.T_in_dev,
                                        t32(g, case.dev))
+    par = None
+    if exact_ties:
+        compare_parents(case)
+        par = gpu_parents(case)
     res = O.adjoint(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t,
-                    case.T_in.astype(np.float64), g)
+                    case.T_in.astype(np.float64), g, par=par)
     assert rel_l2(dvs.cpu().numpy(), res["dvscale"]) <= 1e-3
     assert rel_l2(dt.cpu().numpy(), res["droot_t"]) <= 1e-3
-    if tet_level:
-        assert rel_l2(dD.cpu().numpy(), res["dD"]) <= 1e-3
-    else:
-        assert rel_l2(dD.cpu().numpy().sum(0), res["dD"].sum(0)) <= 1e-3
+    assert rel_l2(dD.cpu().numpy(), res["dD"]) <= 1e-3
+    assert np.abs(dD.cpu().numpy() - res["dD"]).max() <= 1e-3 * np.abs(res["dD"]).max()
+    if exact_ties:
+        # what is unique whatever the tie choice: the gradients summed over elements
+        ref = O.adjoint(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t,
+                        case.T_in.astype(np.float64), g)
+        assert rel_l2(dD.cpu().numpy().sum(0), ref["dD"].sum(0)) <= 1e-3
     return dD.cpu().numpy(), dvs.cpu().numpy(), dt.cpu().numpy(), g
 
 
 def test_cube_backward(cube):
-    # homogeneous D: elements sharing an edge path tie exactly, so the tensor
-    # gradient is compared summed over elements
-    check_backward(cube, tet_level=False)
+    check_backward(cube, exact_ties=True)
 
 
 def test_shell_backward(shell):
@@ -466,32 +514,70 @@ def test_ecg_unreached_and_ragged():
         assert np.all(d[~np.isfinite(T)] == 0)
 
 
+def test_async_forward_and_backward(shell):
+    """The enqueue-only forward and backward (fixed budgets, no synchronisation)
+    give the synchronous calls' results; a budget that is too small and an input
+    error are reported by the device-side status, not by the call."""
+    c = shell
+    plan = c.plan
+    T_sync, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+    g = t32(np.random.Generator(np.random.PCG64(5)).normal(size=c.p.n_v), c.dev)
+    ref = B().eikonal_backward(plan, c.D, c.vs, c.rn, c.rt, T_sync, g)
+    info = B().backward_info(plan)
+    T = B().eikonal_forward_async(plan, c.D, c.vs, c.rn, c.rt, st["rounds"] + 16)
+    s1 = B().plan_status(plan)
+    assert s1["err"] == 0 and s1["forward_converged"]
+    assert B().forward_work(plan)["face_solves"] > 0
+    assert rel_max(T.cpu().numpy(), c.T_orc) <= 1e-4
+    got = B().eikonal_backward_async(plan, c.D, c.vs, c.rn, c.rt, T_sync, g, info["levels"] + 16,
+                                     max(32, 2 * info["gs_sweeps"]))
+    s2 = B().plan_status(plan)
+    assert s2["err"] == 0 and s2["backward_settled"]
+    for a, b in zip(got, ref):
+        assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-6
+    B().eikonal_forward_async(plan, c.D, c.vs, c.rn, c.rt, 2)
+    assert not B().plan_status(plan)["forward_converged"]
+    bad = c.rn.clone()
+    bad[0] = c.p.n_v + 3
+    B().eikonal_forward_async(plan, c.D, c.vs, bad, c.rt, 4)
+    assert B().plan_status(plan)["err"] == -1
+    with pytest.raises(B().GbpError):
+        B().eikonal_forward_async(plan, c.D, c.vs, c.rn, c.rt, 0)
+
+
 def test_ecg_size_limits():
-    """The largest ECG the kernels take (16 leads, 992 time steps, a window that
-    spans every step) and the smallest (1 lead, 1 step) against the oracle; one
-    past either limit is refused before any launch."""
+    """ECGs across the kernels' tiling: one launch covers at most 16 leads and 992
+    time steps, so lead counts of 16/17/31/256 (the paper fits 31 leads, Sec. 3.2)
+    and step counts of 992/993/2000 exercise the tiles and chunks and their
+    ragged ends, with a window that spans every step; the smallest case is 1 lead
+    x 1 step.  All against the oracle; one past either limit (256 leads, 2^20
+    steps) is refused before any launch."""
     dev = _dev()
     r = np.random.Generator(np.random.PCG64(12))
     n_v = 3000
     T = r.uniform(0, 60, size=n_v)
-    for L, S, dt in ((16, 992, 0.07), (1, 1, 0.5), (16, 1, 0.5), (1, 992, 0.07)):
+    T[::97] = np.inf                                   # unreached vertices stay at rest
+    cases = ((16, 992, 0.07), (1, 1, 0.5), (16, 1, 0.5), (1, 992, 0.07), (17, 993, 0.07),
+             (31, 2000, 0.035), (256, 12, 5.0), (33, 1, 0.5))
+    for L, S, dt in cases:
         W = r.normal(size=(n_v, L)).astype(np.float32)
         ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-2.0, dt=dt, n_steps=S)
         print(f"[case] ecg limits L={L} S={S}", flush=True)
         e = B().ecg_forward(t32(T, dev), t32(W, dev), B().make_ap(**ap)).cpu().numpy()
         eo = O.ecg_forward(T.astype(np.float32), W, ap)
         assert e.shape == eo.shape == (S, L)
-        assert np.abs(e - eo).max() / max(np.abs(eo).max(), 1e-6) <= 1e-3
+        assert np.abs(e - eo).max() / max(np.abs(eo).max(), 1e-6) <= 1e-3, (L, S)
         G = r.normal(size=eo.shape).astype(np.float32)
         d = B().ecg_backward(t32(T, dev), t32(W, dev), B().make_ap(**ap), t32(G, dev)).cpu().numpy()
         do = O.ecg_backward(T.astype(np.float32), W, ap, G)
-        assert rel_l2(d, do) <= 1e-3
-    ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-2.0, dt=0.1, n_steps=993)
+        assert rel_l2(d, do) <= 1e-3, (L, S)
+        assert np.all(d[~np.isfinite(T)] == 0)
+    ap = dict(K0=-85.0, K1=30.0, tau=1.0, t0=-2.0, dt=0.1, n_steps=(1 << 20) + 1)
     with pytest.raises(B().GbpError):
         B().ecg_forward(t32(T, dev), t32(np.zeros((n_v, 4)), dev), B().make_ap(**ap))
     ap["n_steps"] = 10
     with pytest.raises(B().GbpError):
-        B().ecg_forward(t32(T, dev), t32(np.zeros((n_v, 17)), dev), B().make_ap(**ap))
+        B().ecg_forward(t32(T, dev), t32(np.zeros((n_v, 257)), dev), B().make_ap(**ap))
 
 
 def test_adam_matches_oracle():

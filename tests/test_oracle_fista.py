@@ -80,10 +80,10 @@ def test_fista_iterations_meet_tolerance(seed):
         n = int(O.fista_iterations(L, tau, 10 ** 6))
         _, v, _ = O.fista_local(Q, Phi, L, n)
         assert v - val <= tau * (1 + 1e-9)
-        # the count is the least k with 2 L (2/3) / (k+1)^2 <= tau (up to float32 rounding)
-        assert 2 * L * (2 / 3) / (n + 1) ** 2 <= tau * (1 + 1e-6)
+        # the count is the least k with 2 L (2/3) / (k+1)^2 <= tau (float64 rounding only)
+        assert 2 * L * (2 / 3) / (n + 1) ** 2 <= tau * (1 + 1e-12)
         if n > 1:
-            assert 2 * L * (2 / 3) / n ** 2 > tau * (1 - 1e-6)
+            assert 2 * L * (2 / 3) / n ** 2 > tau * (1 - 1e-12)
 
 
 def test_fista_iterations_limits():

@@ -1,6 +1,6 @@
 """Pins of the FP64 warm-start network reference against library routines
-(torch.nn layers, autograd, torch's bfloat16 conversion), central differences
-and hand-computed feature rows."""
+(torch.nn layers, autograd), central differences and hand-computed feature
+rows."""
 import numpy as np
 import pytest
 
@@ -36,21 +36,10 @@ def test_layout_matches_generator():
     assert M.N_PARAMS == 256 * 16 + 3 * 256 * 256 + 4 * 256 + 256 + 1
 
 
-def test_bf16_round_equals_torch_conversion(rng):
-    x = (rng.normal(size=20000) * 10.0 ** rng.uniform(-6, 6, size=20000)).astype(np.float32)
-    # exact ties: low 16 bits 0x8000, both parities of the kept bit
-    mant = rng.integers(0, 2 ** 7, size=2000, dtype=np.uint32) << 16
-    expo = rng.integers(100, 150, size=2000, dtype=np.uint32) << 23
-    ties = (expo | mant | np.uint32(0x8000)).view(np.float32)
-    for v in (x, ties, -ties):
-        ref = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
-        assert np.array_equal(M.bf16_round(v.astype(np.float64)), ref)
-
-
 def test_forward_equals_torch_layers(rng):
     p = gi.mlp_params(3)
     X = rng.normal(size=(300, 16))
-    y = M.forward(p, X, bf16=False)
+    y = M.forward(p, X)
     with torch.no_grad():
         yt = _torch_net(p)(torch.from_numpy(X)).numpy()[:, 0]
     np.testing.assert_allclose(y, yt, rtol=1e-12, atol=1e-12)
@@ -60,7 +49,7 @@ def test_gradient_equals_autograd(rng):
     p = gi.mlp_params(4)
     X = rng.normal(size=(200, 16))
     t = rng.normal(size=200)
-    loss, g = M.loss_and_gradient(p, X, t, bf16=False)
+    loss, g = M.loss_and_gradient(p, X, t)
     net = _torch_net(p)
     lt = ((net(torch.from_numpy(X))[:, 0] - torch.from_numpy(t)) ** 2).mean()
     lt.backward()
@@ -78,32 +67,16 @@ def test_gradient_central_differences(rng):
     p = gi.mlp_params(5).astype(np.float64)
     X = rng.normal(size=(64, 16))
     t = rng.normal(size=64)
-    _, g = M.loss_and_gradient(p, X, t, bf16=False)
+    _, g = M.loss_and_gradient(p, X, t)
     idx = rng.choice(M.N_PARAMS, size=40, replace=False)
     idx = np.concatenate([idx, [0, 256 * 16, M.N_PARAMS - 1, M.N_PARAMS - 2]])
     h = 1e-6
     for i in idx:
         e = np.zeros(M.N_PARAMS)
         e[i] = h
-        fd = (M.loss_and_gradient(p + e, X, t, bf16=False)[0]
-              - M.loss_and_gradient(p - e, X, t, bf16=False)[0]) / (2 * h)
+        fd = (M.loss_and_gradient(p + e, X, t)[0]
+              - M.loss_and_gradient(p - e, X, t)[0]) / (2 * h)
         assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9), i
-
-
-def test_bf16_rounding_points_stay_close_to_fp64(rng):
-    p = gi.mlp_params(6)
-    X = M.bf16_round(rng.normal(size=(500, 16)))
-    t = rng.normal(size=500)
-    y64 = M.forward(p, X, bf16=False)
-    y16 = M.forward(p, X, bf16=True)
-    assert np.abs(y16 - y64).max() <= 0.05 * np.abs(y64).max()
-    _, g64 = M.loss_and_gradient(p, X, t, bf16=False)
-    _, g16 = M.loss_and_gradient(p, X, t, bf16=True)
-    assert np.linalg.norm(g16 - g64) <= 0.05 * np.linalg.norm(g64)
-    # rounding is applied: bf16 forward values of H are bf16 numbers
-    _, hs = M.forward(p, X, bf16=True, cache=True)
-    for H in hs[1:]:
-        assert np.array_equal(M.bf16_round(H), H)
 
 
 def test_features_by_hand():
@@ -114,7 +87,7 @@ def test_features_by_hand():
     root_t = np.array([0.0, 2.0])
     norm = (1.0, 0.0, 0.0, 2.0, 4.0)        # centre (1,0,0), len 2, time 4
     T = np.array([8.0, 0.0, 2.0])
-    X, tgt = M.features(xyz, fib, vs, None, root_xyz, root_t, norm, T=T, bf16=False)
+    X, tgt = M.features(xyz, fib, vs, None, root_xyz, root_t, norm, T=T)
     # vertex 0: |x - r0| = 3, |x - r1| = sqrt(9+4+4) = sqrt(17)
     a0, a1 = 3 / 2 + 0 / 4, np.sqrt(17) / 2 + 2 / 4
     np.testing.assert_allclose(X[0, 0:3], [0.0, 1.0, 1.0])
@@ -125,8 +98,8 @@ def test_features_by_hand():
     np.testing.assert_allclose(X[1, 6:14], [0.0] * 7 + [2.5])
     np.testing.assert_allclose(tgt, T / 4.0)
     # the root order does not matter
-    X2 = M.features(xyz, fib, vs, None, root_xyz[::-1], root_t[::-1], norm, bf16=False)
+    X2 = M.features(xyz, fib, vs, None, root_xyz[::-1], root_t[::-1], norm)
     X3 = M.features(xyz, fib, vs, None, np.repeat(root_xyz, [7, 1], axis=0),
-                    np.repeat(root_t, [7, 1]), norm, bf16=False)
+                    np.repeat(root_t, [7, 1]), norm)
     assert not np.array_equal(X2, X)        # padding repeats a different root 0
     np.testing.assert_allclose(X3, X)
