@@ -397,6 +397,20 @@ int gbp_ecg_forward(const float *T, int n_v, const float *W, int L, const gbp_ap
                     float *ecg, void *stream);
 
 /*
+ * gbp_ecg_forward_noalloc -- gbp_ecg_forward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, with the scratch in a
+ * fixed-size array that the library holds in each GPU's memory (129 KB, for any
+ * call within gbp_ecg_forward's limits: the lead tiles and time chunks reuse it
+ * in stream order).  The call allocates and frees nothing.  Every call on one GPU
+ * shares that GPU's array (the kernels clear it first): calls that overlap on one
+ * GPU, on different streams or host threads, race on it.  Arguments, limits and
+ * errors as gbp_ecg_forward; GBP_ERR_HIP if the array's address cannot be found.
+ */
+int gbp_ecg_forward_noalloc(const float *T, int n_v, const float *W, int L, const gbp_ap *ap,
+                            float *ecg, void *stream);
+
+/*
  * gbp_ecg_backward -- dL_dT[n] = -sum_s U'(t_s - T[n]) sum_l dL_decg[s*L+l] W[n*L+l]
  * (Sec. 2.4: the gradient of V_l is -B^T U' times the gradient of phi).
  *   dL_decg device float [n_steps*L];  dL_dT device float [n_v] (overwritten)

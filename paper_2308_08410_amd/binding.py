@@ -80,6 +80,8 @@ _backward_async = _sig("gbp_eikonal_backward_async", [c_void_p, c_void_p, c_void
                                                       c_int, c_void_p])
 _ecg_fwd = _sig("gbp_ecg_forward", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(AP), c_void_p,
                                     c_void_p])
+_ecg_fwd_noalloc = _sig("gbp_ecg_forward_noalloc", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(AP),
+                                                      c_void_p, c_void_p])
 _ecg_bwd = _sig("gbp_ecg_backward", [c_void_p, c_int, c_void_p, c_int, ctypes.POINTER(AP), c_void_p,
                                      c_void_p, c_void_p])
 _ecg_loss = _sig("gbp_ecg_loss", [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p])
@@ -451,6 +453,16 @@ def ecg_forward(T, W, ap: AP, out=None, stream=None):
         out = torch.empty((ap.n_steps, L), dtype=torch.float32, device=T.device)
     _check(_ecg_fwd(_ptr(T, torch.float32, (n_v,), "T"), n_v, _ptr(W, torch.float32, (n_v, L), "W"), L,
                     ctypes.byref(ap), _ptr(out, torch.float32, (ap.n_steps, L), "ecg"), _stream(stream)))
+    return out
+
+
+def ecg_forward_noalloc(T, W, ap: AP, out, stream=None):
+    """gbp_ecg_forward_noalloc: the ECG into the caller's `out` [n_steps, L], the
+    library allocating nothing (its scratch is a fixed array per GPU)."""
+    n_v, L = W.shape
+    _check(_ecg_fwd_noalloc(_ptr(T, torch.float32, (n_v,), "T"), n_v, _ptr(W, torch.float32, (n_v, L), "W"), L,
+                            ctypes.byref(ap), _ptr(out, torch.float32, (ap.n_steps, L), "ecg"),
+                            _stream(stream)))
     return out
 
 

@@ -334,6 +334,36 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------------ workspace
+// Scratch of gbp_ecg_forward_noalloc: one chunk's window, histogram and weight
+// sums for one instance (every chunk and lead tile reuses it in stream order),
+// file-scope device memory that each GPU holds until the process ends.
+constexpr int kNoAllocFloats = 2 * ((kMaxChunk + 15) / 16 * 16 + 16) * 16 + 16;
+__device__ __align__(256) float scratch[kNoAllocFloats];
+
+// The array's device address on the current device, looked up once per device
+// (in host code the symbol's name is a host-side stand-in, not this address).
+int noalloc_scratch(float** out) {
+    static std::mutex mu;
+    static float* addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        gbp_set_error("no HIP device");
+        return GBP_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            gbp_set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return GBP_ERR_HIP;
+        }
+        addr[dev] = (float*)p;
+    }
+    *out = addr[dev];
+    return GBP_OK;
+}
+
 struct EcgWork {
     float* buf = nullptr;
     size_t cap = 0;
@@ -550,6 +580,26 @@ extern "C" int gbp_ecg_forward(const float* T, int n_v, const float* W, int L, c
     }
     float* work;
     if ((rc = ecg_workspace(ecg_work_floats(ap->n_steps), &work))) return rc;
+    return ecg_forward_launch(EcgLaunch{nullptr, 1, n_v, work}, T, n_v, W, L, ap, ecg,
+                              (hipStream_t)stream);
+}
+
+extern "C" int gbp_ecg_forward_noalloc(const float* T, int n_v, const float* W, int L,
+                                       const gbp_ap* ap, float* ecg, void* stream) {
+    int rc = check_ap(T, n_v, W, L, ap);
+    if (rc) return rc;
+    if (!ecg) {
+        gbp_set_error("ecg is NULL");
+        return GBP_ERR_ARG;
+    }
+    const size_t need = ecg_work_floats(ap->n_steps);
+    if (need > (size_t)kNoAllocFloats) {
+        gbp_set_error("ECG (no allocation): needs %zu scratch floats, the library holds %d", need,
+                      kNoAllocFloats);
+        return GBP_ERR_ARG;
+    }
+    float* work;
+    if ((rc = noalloc_scratch(&work))) return rc;
     return ecg_forward_launch(EcgLaunch{nullptr, 1, n_v, work}, T, n_v, W, L, ap, ecg,
                               (hipStream_t)stream);
 }
