@@ -23,10 +23,40 @@ METRIC = "Geodesic-BP iters/s (FIM+adjoint+ECG) at 500k nodes; speedup vs plain"
 # Nominal FP32 operations of one closed-form local solve (vertex, edge and
 # interior KKT candidates, see local_solve.h; an FMA counts as two operations).
 FLOP_PER_FACE = 185.0
-# Algorithmic bytes of one local solve in a relaxation round: the incidence entry
-# (4 B), the element's vertex ids (16 B) and Gram record (32 B), and the three
-# face values (12 B).
-BYTES_PER_FACE = 64.0
+# Bytes a relaxation round gathers per local problem (not the algorithmic count):
+# the incidence entry (4 B), the element's vertex ids (16 B) and Gram record
+# (32 B), and the three face values (12 B).
+GATHERED_BYTES_PER_FACE = 64.0
+
+
+def sweep_bytes(n_v, n_e):
+    """Algorithmic bytes of one full relaxation sweep over every local problem:
+    per element its 4 vertex ids (16 B) and the 6 entries of its metric (24 B),
+    4 incidence entries (16 B); per vertex the coordinates (12 B), the time read
+    and written (8 B) and the incidence pointer (4 B).  Each element's data counts
+    once per sweep although 4 local problems use it."""
+    return n_e * (16 + 24) + 4 * n_e * 4 + n_v * (12 + 4 + 4 + 4)
+
+
+def bytes_per_local_problem(n_v, n_e):
+    """A solve's algorithmic bytes per local problem evaluated: the full-sweep
+    bytes spread over the sweep's 4 n_e local problems (a solve that evaluates k
+    local problems moves k / (4 n_e) full sweeps)."""
+    return sweep_bytes(n_v, n_e) / (4.0 * n_e)
+
+
+def adjoint_bytes(n_v, n_e, want_D=False):
+    """Algorithmic bytes of one backward: the parent recompute (one full sweep),
+    the lambda pass (per vertex 3 parent ids, 3 weights, lambda and the incoming
+    gradient: 32 B), the velocity-scale gradient (4 B per vertex) and, if asked
+    for, the tensor gradient (24 B per element)."""
+    return sweep_bytes(n_v, n_e) + 32 * n_v + 4 * n_v + (24 * n_e if want_D else 0)
+
+
+def ecg_bytes(n_v, L):
+    """Algorithmic bytes of the ECG forward and backward: T and the lead weights
+    read by each (4 + 4 L B per vertex), the gradient written by the backward."""
+    return 2 * n_v * (4 + 4 * L) + 4 * n_v
 # MI355X peaks: FP32 vector without packed math (256 CU x 64 lanes x 2 x 2.4 GHz)
 # and HBM3E bandwidth.
 PEAK_FP32_TFLOPS = 78.6
@@ -45,11 +75,17 @@ def parse():
     ap.add_argument("--nodes", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
-    ap.add_argument("--cpu-sample-nodes", type=int, default=125_000)
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the CPU baseline (0: min(16, cores))")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="time only the CPU baseline on this host (no GPU) and print it")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS,SPLIT",
                     help="use this launch configuration instead of autotuning (e.g. to profile the "
                          "configuration a timed run chose)")
+    ap.add_argument("--hold", default="", metavar="DELTA,WINDOW,OPEN_BELOW",
+                    help="with --launch: the cold forward's hold-back (bucket width in ms, window, "
+                         "opening threshold)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip every form beside the plain iteration")
     ap.add_argument("--forms", default=",".join(FORMS), metavar="LIST",
@@ -119,8 +155,10 @@ def make_state(prob, dev, torch, gi, B):
     # initial guess of the fit
     import numpy as np
     rng = np.random.Generator(np.random.PCG64(21))
-    st["vs"] = f32(np.ones(prob.n_v))
-    st["rt"] = f32(prob.root_t + rng.uniform(-5, 5, size=len(prob.root_t)))
+    st["vs_start"] = np.ones(prob.n_v, np.float32)
+    st["rt_start"] = (prob.root_t + rng.uniform(-5, 5, size=len(prob.root_t))).astype(np.float32)
+    st["vs"] = f32(st["vs_start"])
+    st["rt"] = f32(st["rt_start"])
     for k in ("vs", "rt"):
         st["m_" + k] = torch.zeros_like(st[k])
         st["v_" + k] = torch.zeros_like(st[k])
@@ -408,49 +446,96 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
         loss = torch.empty(n_inst, dtype=torch.float32, device=dev)
         step = B.Step(plan, bt, D, vs, rn, rt, W, apc, target, T, ecg, loss, warm=warm, **bud)
         ms = _replay_timed(step, steps, torch)
+        work = B.forward_work(plan)          # the last replay's forward
         err, status = _warm_accuracy(step, plan, D, vs, rn, rt, T, B, torch)
         step.close()
+        # algorithmic bytes of one replayed iteration: the forward's local problems,
+        # the backward, the ECG forward and backward (the small misfit and Adam aside)
+        nv, ne = int(voff[-1]), int(len(tets))
+        alg = (work["face_solves"] * bytes_per_local_problem(nv, ne) + adjoint_bytes(nv, ne)
+               + ecg_bytes(nv, L))
         out["warm" if warm else "cold"] = dict(
             ms_per_step=ms, instance_iters_per_s=n_inst * 1000.0 / ms,
             vertex_iters_per_s=int(voff[-1]) * 1000.0 / ms, max_rel_T_vs_cold=err,
             converged=bool(status["forward_converged"] and status["backward_settled"]), status=status,
-            budgets=bud, backward=B.backward_info(plan))
+            budgets=bud, backward=B.backward_info(plan), local_problems_per_step=work["face_solves"],
+            roofline=dict(bound="hbm", algorithmic_bytes_per_step=alg,
+                          achieved=alg / (ms * 1e-3) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s",
+                          frac=alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS))
     return out
 
 
-def cpu_baseline(n_sample, n_full):
-    """The FP64 oracle, as it stands, timed on the host for one complete
-    iteration on a smaller member of the same shell family, scaled to the
-    full workload: the eikonal part by (n_full/n_sample)^(4/3) (work ~ vertices x
-    sweeps, sweeps ~ vertices^(1/3)), the rest linearly."""
+def host_info():
+    """CPU model and logical core count of the host this runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count())
+
+
+def cpu_baseline(prob, vs, rt, threads):
+    """The FP64 oracle, as it stands, timed on this host for one complete
+    iteration of the benchmark workload itself (same mesh, inputs and seeds): Alg. 2
+    (Jacobi), the parent map, the ECG forward, misfit and backward, the sparse
+    adjoint and the Adam step.  The oracle's element and vertex loops run on
+    `threads` host threads (OpenMP; the results do not depend on the count), numpy
+    and scipy with as many BLAS threads."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    O.set_threads(threads)
+    target = np.zeros((prob.ap["n_steps"], prob.W.shape[1]))
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        Minv = O.metric_inverse(prob.D, vs, prob.tets)
+        T, st = O.fim(prob.xyz, prob.tets, Minv, prob.root_node, rt)
+        t1 = time.perf_counter()
+        par = O.parent_map(prob.xyz, prob.tets, Minv, prob.root_node, rt, T)
+        t2 = time.perf_counter()
+        e = O.ecg_forward(T, prob.W, prob.ap)
+        _, G = O.ecg_loss(e, target)
+        g = O.ecg_backward(T, prob.W, prob.ap, G)
+        t3 = time.perf_counter()
+        res = O.adjoint(prob.xyz, prob.tets, prob.D, vs, prob.root_node, rt, T, g, par=par)
+        O.adam_step(vs, res["dvscale"], np.zeros_like(vs), np.zeros_like(vs), 1, lr=0.01)
+        t4 = time.perf_counter()
+    O.set_threads(1)
+    total = t4 - t0
+    return dict(value=1.0 / total, unit="iter/s", cores=threads, kind="oracle", **host_info(),
+                seconds=dict(eikonal=t1 - t0, parents=t2 - t1, ecg=t3 - t2, adjoint_adam=t4 - t3, total=total),
+                sample=(f"one full FP64 oracle iteration on the benchmark workload itself ({prob.n_v} vertices, "
+                        f"{prob.n_e} tets, same inputs): Alg. 2 Jacobi ({st['sweeps']} sweeps, "
+                        f"{st['solves']} local problems), parents, ECG fwd/bwd, sparse adjoint, Adam; "
+                        f"{threads} host threads; measured, not scaled"))
+
+
+def cpu_threads(args):
+    return args.cpu_threads if args.cpu_threads > 0 else min(16, os.cpu_count() or 1)
+
+
+def cpu_only(args):
+    """The CPU baseline alone (no GPU): the benchmark workload's inputs, the oracle."""
     import numpy as np
     import gbp_inputs as gi
-    import oracle as O
-    p = gi.shell_problem(n_sample, seed=2, n_roots=5, n_leads=12)
-    vs = np.ones(p.n_v)
-    t0 = time.perf_counter()
-    Minv = O.metric_inverse(p.D, vs, p.tets)
-    T, st = O.fim(p.xyz, p.tets, Minv, p.root_node, p.root_t)
-    t1 = time.perf_counter()
-    par = O.parent_map(p.xyz, p.tets, Minv, p.root_node, p.root_t, T)
-    e = O.ecg_forward(T, p.W, p.ap)
-    _, G = O.ecg_loss(e, 0.9 * e)
-    g = O.ecg_backward(T, p.W, p.ap, G)
-    res = O.adjoint(p.xyz, p.tets, p.D, vs, p.root_node, p.root_t, T, g, par=par)
-    O.adam_step(vs, res["dvscale"], np.zeros_like(vs), np.zeros_like(vs), 1, lr=0.01)
-    t2 = time.perf_counter()
-    ratio = n_full / p.n_v
-    t_est = (t1 - t0) * ratio ** (4.0 / 3.0) + (t2 - t1) * ratio
-    return dict(value=1.0 / t_est, unit="iter/s", cores=1, kind="oracle",
-                sample=(f"one full FP64 oracle iteration (Alg. 2 Jacobi, parents, sparse adjoint, ECG fwd/bwd, "
-                        f"Adam) on the {p.n_v}-vertex member of the same shell family took "
-                        f"{t2 - t0:.2f} s ({t1 - t0:.2f} s eikonal, {st['sweeps']} sweeps); scaled to "
-                        f"{n_full} vertices: eikonal x{ratio:.2f}^(4/3), rest x{ratio:.2f} -> {t_est:.1f} s/iter; "
-                        f"single thread"))
+    prob = gi.shell_problem(args.nodes, seed=2, n_roots=5, n_leads=12)
+    rng = np.random.Generator(np.random.PCG64(21))
+    rt = (prob.root_t + rng.uniform(-5, 5, size=len(prob.root_t))).astype(np.float32)
+    cpu = cpu_baseline(prob, np.ones(prob.n_v, np.float32), rt, cpu_threads(args))
+    print(json.dumps(dict(cpu_baseline=cpu, workload=f"shell {prob.n_v} vertices / {prob.n_e} tets")),
+          flush=True)
 
 
 def main():
     args = parse()
+    if args.cpu_only:
+        cpu_only(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (the solve of one mesh runs on "
@@ -467,16 +552,20 @@ def main():
     st = make_state(prob, dev, torch, gi, B)
     tuned = None
     if args.launch:
-        lanes, blocks, batch, lblocks, split = (int(x) for x in args.launch.split(","))
+        lanes, blocks, batch, lblocks, split = (int(x) for x in args.launch.split(",")[:5])
         B.set_launch(st["plan"], lanes, blocks, lblocks, batch)
         B.set_queue_split(st["plan"], split)
+        if args.hold:
+            d, w, o = args.hold.split(",")
+            B.set_hold(st["plan"], float(d), int(w), int(o))
     elif not args.no_tune:
         from paper_2308_08410_amd import autotune
         t = time.time()
         tuned = autotune.tune(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], use_cache=False, save=False)
         log(f"[bench] autotuned launch: lanes={tuned['lanes']} sweep_blocks={tuned['sweep_blocks']} "
             f"sync_batch={tuned['sync_batch']} level_blocks={tuned['level_blocks']} split={tuned['split']} "
-            f"({time.time() - t:.1f}s)")
+            f"hold=({tuned['hold_delta']:.3g} ms, window {tuned['hold_window']}, open below "
+            f"{tuned['hold_open']}) ({time.time() - t:.1f}s)")
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 20)) // 4
         x = torch.ones(n, dtype=torch.float32, device=dev)
@@ -504,7 +593,9 @@ def main():
         f"loss={float(loss[0]):.4g}")
 
     roofline = None
-    detail = dict(launch=dict(B.get_launch(st["plan"]), split=int(B.get_queue_split(st["plan"]))),
+    hd, hw, ho = B.get_hold(st["plan"])
+    detail = dict(launch=dict(B.get_launch(st["plan"]), split=int(B.get_queue_split(st["plan"])),
+                              hold_delta_ms=hd, hold_window=hw, hold_open_below=ho),
                   fim_rounds=stats["rounds"],
                   face_solves_per_step=face_solves // args.steps,
                   node_updates=stats["node_updates"], wall_ms_per_step=1e3 * t_wall / args.steps)
@@ -523,25 +614,38 @@ def main():
         n_sw, ms_sw = prof["fim_sweep"]
         avg_ms = ms_sw / max(n_sw, 1)
         faces_per_launch = fs / max(n_sw, 1)
+        bpl = bytes_per_local_problem(prob.n_v, prob.n_e)
         # The relaxation round is bound by its gathers (memory), not by its arithmetic:
-        # report it against HBM bandwidth with the algorithmic bytes per launch, and
-        # keep the arithmetic rate beside it.
-        achieved = faces_per_launch * BYTES_PER_FACE / (avg_ms * 1e-3) / 1e9
+        # report it against HBM bandwidth with the algorithmic bytes per launch (the
+        # full-sweep bytes times the fraction of the sweep's local problems the launch
+        # evaluates), and keep the arithmetic rate beside it.
+        alg = faces_per_launch * bpl
+        achieved = alg / (avg_ms * 1e-3) / 1e9
         tflops = faces_per_launch * FLOP_PER_FACE / (avg_ms * 1e-3) / 1e12
+        traffic = stored_traffic("k_sweep")
         roofline = dict(kernel="k_sweep (eikonal relaxation round)", bound="hbm", achieved=achieved,
-                        peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                        traffic=stored_traffic("k_sweep"), algorithmic_bytes_per_launch=faces_per_launch * BYTES_PER_FACE,
+                        peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS, traffic=traffic,
+                        algorithmic_bytes_per_launch=alg, bytes_per_local_problem=bpl,
+                        full_sweep_bytes=sweep_bytes(prob.n_v, prob.n_e),
+                        local_problems_per_launch=faces_per_launch,
+                        gathered_bytes_per_launch=faces_per_launch * GATHERED_BYTES_PER_FACE,
+                        traffic_over_algorithmic=None if traffic is None else traffic / alg,
                         avg_launch_ms=avg_ms, launches_per_step=n_sw / nprof,
                         alu_tflops=tflops, alu_frac=tflops / PEAK_FP32_TFLOPS)
-        # adjoint levels: latency-bound; measured traffic against HBM peak
+        # the whole backward (parent recompute, child lists, level walk, gradients)
+        # against its algorithmic bytes; the level launches are latency-bound
+        bwd_fams = ("parent", "child_lists", "adj_level", "grad")
+        bwd_ms = sum(prof[f][1] for f in bwd_fams if f in prof) / nprof
+        ab = adjoint_bytes(prob.n_v, prob.n_e)
         n_lv, ms_lv = prof["adj_level"]
         lv_ms = ms_lv / max(n_lv, 1)
         lv_bytes = stored_traffic("k_adj_level")
-        detail["adjoint_level"] = dict(
-            kernel="k_adj_level", avg_launch_ms=lv_ms, launches_per_step=n_lv / nprof,
-            traffic=lv_bytes,
-            achieved_GBps=None if lv_bytes is None else lv_bytes / (lv_ms * 1e-3) / 1e9,
-            frac_of_hbm_peak=None if lv_bytes is None else lv_bytes / (lv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+        detail["adjoint"] = dict(
+            kernels="+".join(bwd_fams), ms_per_step=bwd_ms, algorithmic_bytes=ab,
+            achieved_GBps=ab / (bwd_ms * 1e-3) / 1e9, frac=ab / (bwd_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            level_kernel="k_adj_level", level_avg_launch_ms=lv_ms, level_launches_per_step=n_lv / nprof,
+            level_traffic_per_launch=lv_bytes,
+            level_traffic_per_backward=None if lv_bytes is None else lv_bytes * n_lv / nprof)
         # ECG contraction on the matrix cores: executed bf16 MFMA flops (counters)
         # over the launch time measured here
         for fam, kern in (("ecg_fwd", "k_ecg_fwd"), ("ecg_bwd", "k_ecg_bwd")):
@@ -619,8 +723,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
-        cpu = cpu_baseline(args.cpu_sample_nodes, prob.n_v)
-        log(f"[bench] cpu baseline {time.time() - t:.1f}s: {cpu['value']:.4g} iter/s (estimated)")
+        cpu = cpu_baseline(prob, st["vs_start"], st["rt_start"], cpu_threads(args))
+        log(f"[bench] cpu baseline {time.time() - t:.1f}s: {cpu['value']:.4g} iter/s on {cpu['cores']} threads")
     out = {
         "metric": METRIC, "value": 1000.0 / ms, "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

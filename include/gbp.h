@@ -200,6 +200,25 @@ int gbp_plan_get_local_solver(gbp_plan plan, int *solver, int *n_f, int *lipschi
  * Errors: GBP_ERR_ARG for a negative or non-finite tau.
  */
 /*
+ * gbp_plan_set_hold / gbp_plan_get_hold -- bucketed hold-back of the cold forward
+ * (Delta-stepping on the active list of Alg. 2).  Bucket b holds the values in
+ * [t_min + b delta, t_min + (b+1) delta), t_min the smallest onset.  A vertex whose
+ * value drops beyond the current bucket plus `window` buckets does not propagate
+ * yet; it waits in its bucket's list.  The buckets open in increasing order: one
+ * per round whenever the active list is shorter than open_below vertices (0: half
+ * of what one round's grid takes at once), and the next non-empty one whenever the
+ * list is empty.  Only the order of the relaxation changes: the solve reaches the
+ * same fixed point, with fewer re-evaluations of vertices whose first values were
+ * too high, in more rounds.  delta = 0 (the default) turns it off.  Warm
+ * (two-sided) solves do not hold.  Allocates 5 n_v / 4 ints of device memory on
+ * first use (per plan).
+ * Errors: GBP_ERR_ARG (delta negative or non-finite, window outside 0..32,
+ * open_below < 0), GBP_ERR_NOMEM.
+ */
+int gbp_plan_set_hold(gbp_plan plan, float delta, int window, int open_below);
+int gbp_plan_get_hold(gbp_plan plan, float *delta, int *window, int *open_below);
+
+/*
  * gbp_plan_set_input_reuse -- lets gbp_eikonal_backward and gbp_parent_map keep
  * what the last forward (or other call) on this plan built from its inputs: the
  * element metric D_eff^-1 per element, the nodal scales and the root onsets.

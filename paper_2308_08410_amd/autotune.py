@@ -3,9 +3,10 @@
 For a plan and a representative problem it times the eikonal forward (and
 optionally the adjoint) under each candidate configuration -- lanes per vertex
 in a relaxation round, grid of a round, launches between convergence checks,
-queue split over the XCDs or not -- keeps the
-fastest, and records the rounds/levels that carried work so that graph-captured
-iterations can be given launch budgets.  Results are cached in a JSON file
+queue split over the XCDs or not, then the cold forward's hold-back (bucket
+width in units of the front's mean advance per round, and when the next bucket
+opens) -- keeps the fastest, and records the rounds/levels that carried work so
+that graph-captured iterations can be given launch budgets.  Results are cached in a JSON file
 keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
 """
 from __future__ import annotations
@@ -22,6 +23,10 @@ SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt, sp
          for sp in (1, 0) for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048)
          for bt in (16, 32, 64)]
 LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
+# hold-back candidates, searched last: (bucket width / mean front advance per round,
+# buckets past the current one that propagate, opening threshold / vertices one
+# round's grid takes at once); (0, 0, 0) is off
+HOLD_SPACE = ((0, 0, 0.0), (4, 0, 2.0), (8, 0, 0.5), (4, 0, 0.5), (8, 0, 2.0))
 
 
 def cache_path() -> str:
@@ -74,6 +79,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
         rec = db[key]
         B.set_launch(plan, rec["lanes"], rec["sweep_blocks"], rec["level_blocks"], rec.get("sync_batch", 16))
         B.set_queue_split(plan, rec.get("split", 1))
+        B.set_hold(plan, rec.get("hold_delta", 0.0), rec.get("hold_window", 0), rec.get("hold_open", 0))
         return dict(rec, cached=True)
     gT = torch.ones(plan.n_v, dtype=torch.float32, device=D.device)
     T = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
@@ -102,6 +108,27 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
                 best = dict(cfg, ms=ms)
     B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"], best["sync_batch"])
     B.set_queue_split(plan, best["split"])
+    best.update(hold_delta=0.0, hold_window=0, hold_open=0)
+    if space is None:
+        B.set_hold(plan, 0.0)
+        run()
+        fin = torch.isfinite(T)
+        rounds = max(B.last_counts(plan)["rounds"], 1)
+        span = float(T[fin].max() - T[fin].min()) if bool(fin.any()) else 0.0
+        unit = span / rounds                    # mean advance of the front per round
+        cap = best["sweep_blocks"] * (256 // best["lanes"])
+        for mult, window, frac in HOLD_SPACE:
+            if mult and not unit > 0:
+                continue
+            cfg = dict(hold_delta=mult * unit, hold_window=window, hold_open=int(frac * cap))
+            B.set_hold(plan, cfg["hold_delta"], window, cfg["hold_open"])
+            run()
+            ms = _time(run, repeats)
+            if mult == 0:
+                best["ms"] = ms                 # the same configuration, timed again
+            elif ms < best["ms"]:
+                best.update(cfg, ms=ms)
+        B.set_hold(plan, best["hold_delta"], best["hold_window"], best["hold_open"])
     run()
     best.update(B.last_counts(plan))
     if save:

@@ -97,6 +97,9 @@ _plan_status = _sig("gbp_plan_status", [c_void_p, ctypes.POINTER(c_int), ctypes.
                                         ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                         ctypes.POINTER(c_int), c_void_p])
 _forward_work = _sig("gbp_plan_forward_work", [c_void_p, c_void_p, c_void_p, c_void_p])
+_set_hold = _sig("gbp_plan_set_hold", [c_void_p, c_float, c_int, c_int])
+_get_hold = _sig("gbp_plan_get_hold", [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_int)])
 _set_launch = _sig("gbp_plan_set_launch", [c_void_p, c_int, c_int, c_int, c_int])
 _get_launch = _sig("gbp_plan_get_launch", [c_void_p] + [ctypes.POINTER(c_int)] * 4)
 _set_split = _sig("gbp_plan_set_queue_split", [c_void_p, c_int])
@@ -509,6 +512,20 @@ def forward_work(plan: Plan, stream=None):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     _check(_forward_work(plan.handle, ctypes.byref(a), ctypes.byref(b), _stream(stream)))
     return dict(face_solves=a.value, node_updates=b.value)
+
+
+def set_hold(plan: Plan, delta: float, window: int = 0, open_below: int = 0):
+    """The cold forward's hold-back (gbp_plan_set_hold): bucket width, buckets past
+    the current one that propagate at once, and the queue length below which a
+    round opens the next bucket; delta 0 turns it off."""
+    _check(_set_hold(plan.handle, float(delta), int(window), int(open_below)))
+
+
+def get_hold(plan: Plan):
+    """(delta, window, open_below)."""
+    d, w, o = c_float(), c_int(), c_int()
+    _check(_get_hold(plan.handle, ctypes.byref(d), ctypes.byref(w), ctypes.byref(o)))
+    return d.value, w.value, o.value
 
 
 def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=2048, sync_batch=16):

@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 #include <vector>
@@ -182,10 +183,12 @@ __global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCt
 __global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __restrict__ T_init,
                             const int* __restrict__ node_user, float* __restrict__ vs,
                             float* __restrict__ troot, float* __restrict__ T,
-                            int* __restrict__ mark, int n_v, int only_T, GbpCtl* ctl) {
+                            int* __restrict__ mark, int n_v, int only_T, GbpCtl* ctl,
+                            int* __restrict__ hold) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
     if (ctl->marks_stale) mark[i] = 0;   // the stamps restarted from 1
+    if (hold) hold[i] = INT_MIN;          // held in no bucket
     const int u = node_user[i];
     if (!only_T) {
         float s = 1.f;
@@ -291,7 +294,10 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
             atomicOr(&ctl->err, ERRBIT_ROOT_NONFINITE);
         } else {
             atomic_min_float(&troot[i], t);
-            if (cold) atomic_min_float(&T[i], t);
+            if (cold) {
+                atomic_min_float(&T[i], t);
+                atomic_min_float(&ctl->tmin, t);
+            }
         }
     }
     if (!cold) return;
@@ -324,6 +330,7 @@ __global__ void k_ctl_reset(GbpCtl* ctl, int keep_fwd) {
         const int st = keep_fwd ? (ctl->status & 1) : 0;
         const int err = keep_fwd == 2 ? ctl->err : 0;   // 2: mid-call reset, keep input errors
         GbpCtl z{};
+        z.tmin = GBP_INF;
         z.marks_stale = stamp > (1 << 30) ? 1 : 0;
         z.stamp = z.marks_stale ? 1 : stamp;
         z.status = st;
@@ -339,6 +346,9 @@ __global__ void k_forward_end(GbpCtl* ctl, int launched) {
         ctl->stamp += launched + 2;
         int left = 0;
         for (int x = 0; x < 8; ++x) left += ctl->qcnt[launched % 3][x];
+        // vertices still held in buckets beyond the current one (hold-back)
+        const int bc = ctl->bcur[launched % 3];
+        for (int k = 1; k < kHoldBuckets; ++k) left += ctl->bcnt[(bc + k) & (kHoldBuckets - 1)];
         if (left != 0) ctl->status |= 1;
     }
 }
@@ -394,7 +404,31 @@ __device__ __forceinline__ float face_value(const int* __restrict__ nent,
     }
 }
 
-template <bool TWO_SIDED, int L, int SOLVER>
+// Hold-back (HOLD, cold rounds only): Delta-stepping on the active list.  Bucket b
+// holds values in [tmin + b Delta, tmin + (b+1) Delta).  A vertex whose value drops
+// into a bucket beyond the current one does not push its neighbours yet: it is
+// appended to that bucket's list (once per bucket) and waits.  A round that finds
+// the queue shorter than open_below (the rest of the current bucket's tail, too
+// short to fill the grid) also opens the next non-empty bucket: every listed vertex
+// whose value has not dropped below that bucket pushes its neighbours (values
+// beyond the ring's last bucket wait there).  Only the order
+// of the relaxation changes (every held vertex is released before the solve
+// ends), so the fixed point is the same; a vertex that finds its bucket's list
+// full pushes at once.
+struct HoldArgs {
+    int* hold;          // [n_v] bucket a vertex was last appended to
+    int* blist;         // [kHoldBuckets * bcap]
+    int bcap;
+    float inv_delta;
+    int open_below;     // open the next bucket once the queue is shorter than this
+    int window;         // buckets past the current one that propagate at once (>= 0)
+};
+
+__device__ __forceinline__ int bucket_of(float t, float tmin, float inv_delta) {
+    return (int)fminf(floorf((t - tmin) * inv_delta), (float)(1 << 30));
+}
+
+template <bool TWO_SIDED, int L, int SOLVER, bool HOLD>
 __global__ void __launch_bounds__(TPB)
     k_sweep(const int2* __restrict__ nptr, const int* __restrict__ nent,
             const int4* __restrict__ tetv, const float4* __restrict__ tetg,
@@ -402,7 +436,8 @@ __global__ void __launch_bounds__(TPB)
             int* __restrict__ qout, const int* __restrict__ adj_ptr, const int* __restrict__ adj,
             int* __restrict__ mark, GbpCtl* ctl, unsigned long long* __restrict__ blk, int s,
             float eps_rel, int n_v, XcdQueues xq, const float* __restrict__ lip, int n_f,
-            float tau, int* __restrict__ st) {
+            float tau, int* __restrict__ st, HoldArgs ha) {
+    static_assert(!(HOLD && TWO_SIDED), "hold-back is a cold-start ordering");
     constexpr int PER_BLOCK = TPB / L;
     // blocks are placed on the 8 XCDs round-robin: with the split layout block b
     // serves sub-queue b % 8, else every block serves the one queue
@@ -418,9 +453,40 @@ __global__ void __launch_bounds__(TPB)
     const int pre = qi0 < xq.off[x + 1] - xq.off[x] ? qx[qi0] : 0;
     const int n = ctl->qcnt[s % 3][x];
     const int stamp_next = ctl->stamp + s + 1;
+    // hold-back: the current bucket, and whether this round opens the next one
+    int bc = 0, bopen = -1, nopen = 0;
+    float tmin = 0.f;
+    if constexpr (HOLD) {
+        bc = ctl->bcur[s % 3];
+        tmin = ctl->tmin;
+        int tot = 0;
+        for (int xs = 0; xs < 8; ++xs) tot += ctl->qcnt[s % 3][xs];
+        if (tot == 0) {
+            // nothing is evaluated, so no list grows: skip to the next non-empty bucket
+            for (int k = 1; k < kHoldBuckets; ++k) {
+                const int c = ctl->bcnt[(bc + k) & (kHoldBuckets - 1)];
+                if (c > 0) {
+                    bopen = bc + k;
+                    nopen = min(c, ha.bcap);
+                    break;
+                }
+            }
+        } else if (tot < ha.open_below) {
+            // the tail of the current bucket: open the next one beside it; this
+            // round holds nothing in it (its list stays as counted here)
+            bopen = bc + 1;
+            nopen = min(ctl->bcnt[bopen & (kHoldBuckets - 1)], ha.bcap);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            // the bucket the last round opened has been consumed: its slot is free
+            if (bc != ctl->bcur[(s + 2) % 3]) ctl->bcnt[bc & (kHoldBuckets - 1)] = 0;
+            ctl->bcur[(s + 1) % 3] = bopen >= 0 ? bopen : bc;
+        }
+    }
     if (blockIdx.x == 0 && threadIdx.x < 8) {
-        const int left = ctl->qcnt[s % 3][threadIdx.x];
+        int left = ctl->qcnt[s % 3][threadIdx.x];
         ctl->qcnt[(s + 2) % 3][threadIdx.x] = 0;
+        if (HOLD && threadIdx.x == 0 && nopen > 0) left = max(left, 1);
         if (left > 0) atomicMax(&ctl->rounds, s + 1);
         if (st) {   // status for the host: this round's work, error bits, round index
             st[threadIdx.x] = left;
@@ -430,11 +496,12 @@ __global__ void __launch_bounds__(TPB)
             }
         }
     }
-    if (lb * PER_BLOCK >= n) return;                // no vertex for this block
     int* cnt_next = ctl->qcnt[(s + 1) % 3];
     constexpr int CAP = TWO_SIDED ? kPushCapWide : kPushCap;
     __shared__ int push_q[CAP];
     __shared__ int push_n, push_cnt[8], push_base[8];
+    const bool have_open = HOLD && bopen >= 0 && (int)blockIdx.x * PER_BLOCK < nopen;
+    if (lb * PER_BLOCK >= n && !have_open) return;   // no vertex for this block
     if (threadIdx.x == 0) push_n = 0;
     __syncthreads();
     const XPushBuf pb{push_q, &push_n, CAP};
@@ -505,10 +572,51 @@ __global__ void __launch_bounds__(TPB)
         }
         if (changed) {
             if (lane == 0) ++upd;
+            if constexpr (HOLD) {
+                // the bucket opened by this round, if any, counts as current; the
+                // ring's slot of the old current bucket is being cleared: skip it
+                const int bce = (bopen >= 0 ? bopen : bc) + ha.window;
+                int b = bucket_of(best, tmin, ha.inv_delta);
+                if (b > bce) {   // beyond the window: wait in b's list
+                    b = min(b, bc + kHoldBuckets - 1);
+                    int ok = 0;
+                    if (lane == 0) {
+                        if (ha.hold[i] == b) {
+                            ok = 1;
+                        } else {
+                            const int slot = b & (kHoldBuckets - 1);
+                            const int pos = atomicAdd(&ctl->bcnt[slot], 1);
+                            if (pos < ha.bcap) {
+                                ha.blist[(size_t)slot * ha.bcap + pos] = i;
+                                ha.hold[i] = b;
+                                ok = 1;
+                            }
+                        }
+                    }
+                    if (__shfl(ok, (threadIdx.x & 63) & ~(L - 1))) continue;
+                }
+            }
             for (int a = adj0 + lane; a < adj1; a += L) {
                 const int nb = adj[a];
                 if (atomicMax(&mark[nb], stamp_next) < stamp_next)
                     xpush_node<TWO_SIDED>(pb, nb, xq, qout, cnt_next);
+            }
+        }
+    }
+    if constexpr (HOLD) {
+        if (have_open) {
+            // open bucket bopen: every listed vertex not below it pushes its neighbours
+            const int* lst = ha.blist + (size_t)(bopen & (kHoldBuckets - 1)) * ha.bcap;
+            for (int qi = blockIdx.x * PER_BLOCK + sub; qi < nopen; qi += gridDim.x * PER_BLOCK) {
+                const int v = lst[qi];
+                // stale: re-held in a lower bucket, or pushed already from the current
+                // one; a value beyond bopen was clamped into the ring's last bucket
+                if (ha.hold[v] != bopen || bucket_of(T[v], tmin, ha.inv_delta) < bopen) continue;
+                for (int a = adj_ptr[v] + lane; a < adj_ptr[v + 1]; a += L) {
+                    const int nb = adj[a];
+                    if (atomicMax(&mark[nb], stamp_next) < stamp_next)
+                        xpush_node<false>(pb, nb, xq, qout, cnt_next);
+                }
             }
         }
     }
@@ -1405,7 +1513,9 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     k_ctl_reset<<<1, 64, 0, s>>>(p->ctl, keep ? 2 : (cold == 2 ? 1 : 0));
     k_vertex_in<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(vscale, cold == 1 ? nullptr : T_init,
                                                      p->node_user, p->vs, p->troot, p->T, p->mark,
-                                                     n_v, keep ? 1 : 0, p->ctl);
+                                                     n_v, keep ? 1 : 0, p->ctl,
+                                                     cold == 1 && p->hold_delta > 0.f ? p->hold
+                                                                                      : nullptr);
     if (keep) {
         GBP_LAUNCH_CHECK();
         return GBP_OK;
@@ -1436,23 +1546,29 @@ static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s, int* st = 
     int* qout = p->q[(r + 1) & 1];
     const int grid = std::min(p->sweep_blocks, kStatBlocks);
     ProfScope ps(GBP_PROF_FIM_SWEEP, s);
-#define GBP_SWEEP(TS, LN, SV)                                                                   \
-    k_sweep<TS, LN, SV><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot, p->T, \
-                                             qin, qout, p->adj_ptr, p->adj, p->mark, p->ctl,     \
-                                             p->blk, r, p->eps_rel, p->n_v, p->xq, p->lip,       \
-                                             p->fista_iters, p->fista_tau, st)
-#define GBP_SWEEP_LANES(TS, SV)                         \
-    do {                                                \
-        if (p->lanes == 8) GBP_SWEEP(TS, 8, SV);        \
-        else if (p->lanes == 32) GBP_SWEEP(TS, 32, SV); \
-        else GBP_SWEEP(TS, 16, SV);                     \
+    const int open_below = p->hold_open > 0 ? p->hold_open : grid * (TPB / p->lanes) / 2;
+    const HoldArgs ha{p->hold, p->blist, p->bcap, p->hold_delta > 0.f ? 1.f / p->hold_delta : 0.f,
+                      open_below, p->hold_window};
+    const bool hold = cold && p->hold_delta > 0.f;
+#define GBP_SWEEP(TS, LN, SV, HD)                                                                  \
+    k_sweep<TS, LN, SV, HD><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,    \
+                                                 p->T, qin, qout, p->adj_ptr, p->adj, p->mark,    \
+                                                 p->ctl, p->blk, r, p->eps_rel, p->n_v, p->xq,    \
+                                                 p->lip, p->fista_iters, p->fista_tau, st, ha)
+#define GBP_SWEEP_LANES(TS, SV, HD)                         \
+    do {                                                    \
+        if (p->lanes == 8) GBP_SWEEP(TS, 8, SV, HD);        \
+        else if (p->lanes == 32) GBP_SWEEP(TS, 32, SV, HD); \
+        else GBP_SWEEP(TS, 16, SV, HD);                     \
     } while (0)
     if (p->solver == 1) {
-        if (cold) GBP_SWEEP_LANES(false, 1);
-        else GBP_SWEEP_LANES(true, 1);
+        if (hold) GBP_SWEEP_LANES(false, 1, true);
+        else if (cold) GBP_SWEEP_LANES(false, 1, false);
+        else GBP_SWEEP_LANES(true, 1, false);
     } else {
-        if (cold) GBP_SWEEP_LANES(false, 0);
-        else GBP_SWEEP_LANES(true, 0);
+        if (hold) GBP_SWEEP_LANES(false, 0, true);
+        else if (cold) GBP_SWEEP_LANES(false, 0, false);
+        else GBP_SWEEP_LANES(true, 0, false);
     }
 #undef GBP_SWEEP_LANES
 #undef GBP_SWEEP

@@ -58,7 +58,13 @@ struct GbpCtl {
     int levels;                    // adjoint: last level with work + 1
     int marks_stale;               // set by a reset that restarted the stamps: clear the marks
     int qcnt[3][8];                // forward: rotating lengths of the 8 sub-queues
+    // bucketed hold-back of the cold forward (Delta-stepping): changed vertices whose
+    // value lies beyond the current bucket wait in per-bucket lists (a ring)
+    float tmin;                    // smallest root onset: bucket 0 starts there
+    int bcur[3];                   // rotating current bucket
+    int bcnt[64];                  // entries per ring slot (slot = bucket % 64)
 };
+constexpr int kHoldBuckets = 64;   // ring size (bcnt)
 
 // The forward's work queue is split into 8 sub-queues, one per XCD: the vertex
 // range (Morton order) is cut into kXcdRegions contiguous regions, region r
@@ -107,6 +113,12 @@ struct gbp_plan_s {
     int fista_iters = 32;         // FISTA iterations per local problem
     int fista_lmode = 1;          // FISTA step constant: 0 Eq. (lipschitz_est), 1 tightened
     float fista_tau = 0.f;        // > 0: per-face iterations from the rate bound, capped by fista_iters
+    float hold_delta = 0.f;       // bucket width of the cold forward's hold-back (0: off)
+    int hold_open = 0;            // queue length below which a round opens the next bucket (0: half the grid)
+    int hold_window = 0;          // buckets past the current one that propagate at once
+    int* hold = nullptr;          // [n_v] bucket a vertex was last held in (allocated on use)
+    int* blist = nullptr;         // [kHoldBuckets * bcap] held vertices per ring slot
+    int bcap = 0;                 // entries per ring slot
     // inputs of the last full preparation (element metric, scales, onsets): a
     // backward may reuse them when the caller allows it and passes the same arrays
     int reuse_inputs = 0;

@@ -77,7 +77,7 @@ static void plan_free(gbp_plan p) {
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
                     p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp, p->lip,
-                    p->pnode, p->partner, p->pairrem};
+                    p->pnode, p->partner, p->pairrem, p->hold, p->blist};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -431,6 +431,36 @@ extern "C" int gbp_plan_set_fista_tolerance(gbp_plan p, float tau) {
         return GBP_ERR_ARG;
     }
     p->fista_tau = tau;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_hold(gbp_plan p, float delta, int window, int open_below) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (!(delta >= 0.f) || !std::isfinite(delta) || open_below < 0 || window < 0 ||
+        window > kHoldBuckets / 2) {
+        gbp_set_error("set_hold: delta finite and >= 0, window 0..%d, open_below >= 0",
+                      kHoldBuckets / 2);
+        return GBP_ERR_ARG;
+    }
+    p->hold_open = open_below;
+    p->hold_window = window;
+    if (delta > 0.f && !p->hold) {
+        p->bcap = std::max(4096, p->n_v / 16);
+        if ((rc = dalloc(&p->hold, (size_t)p->n_v)) ||
+            (rc = dalloc(&p->blist, (size_t)kHoldBuckets * p->bcap)))
+            return rc;
+    }
+    p->hold_delta = delta;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_hold(gbp_plan p, float* delta, int* window, int* open_below) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (delta) *delta = p->hold_delta;
+    if (window) *window = p->hold_window;
+    if (open_below) *open_below = p->hold_open;
     return GBP_OK;
 }
 

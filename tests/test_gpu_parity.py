@@ -514,6 +514,67 @@ def test_ecg_unreached_and_ragged():
         assert np.all(d[~np.isfinite(T)] == 0)
 
 
+@pytest.mark.parametrize("lanes,split", [(16, True), (8, False), (32, True)])
+def test_hold_back_reaches_the_oracle(shell, lanes, split):
+    """The cold forward with bucketed hold-back (Delta-stepping order) reaches the
+    oracle's fixed point for bucket widths from a fraction of an edge's travel
+    time to many, in every lane count and queue layout; the bucket ring (64
+    buckets) wraps when the width is small.  Turning it off restores the plain
+    order."""
+    c = shell
+    plan = c.plan
+    saved = B().get_launch(plan)
+    B().set_launch(plan, lanes, 1024, saved["level_blocks"], 16)
+    B().set_queue_split(plan, split)
+    try:
+        T0, st0 = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+        for delta, window, open_below in ((0.05, 0, 0), (0.5, 0, 0), (2.0, 0, 0), (20.0, 0, 0), (1.0, 0, 1),
+                                          (1.0, 0, 1 << 30), (0.5, 4, 1 << 30), (0.25, 32, 0)):
+            B().set_hold(plan, delta, window, open_below)
+            assert B().get_hold(plan) == (pytest.approx(delta), window, open_below)
+            print(f"[case] hold delta={delta} window={window} open_below={open_below} lanes={lanes} "
+                  f"split={split}", flush=True)
+            T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+            assert st["converged"] and st["unreached"] == 0
+            assert rel_max(T.cpu().numpy(), c.T_orc) <= 1e-4
+            print(f"[hold] delta={delta}: {st['rounds']} rounds, {st['face_solves']} local problems "
+                  f"(plain order {st0['rounds']}, {st0['face_solves']})", flush=True)
+        B().set_hold(plan, 0.0)
+        T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+        assert st["face_solves"] == st0["face_solves"] or rel_max(T.cpu().numpy(), c.T_orc) <= 1e-4
+        with pytest.raises(B().GbpError):
+            B().set_hold(plan, -1.0)
+        with pytest.raises(B().GbpError):
+            B().set_hold(plan, 1.0, 33)
+    finally:
+        B().set_hold(plan, 0.0)
+        B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
+        B().set_queue_split(plan, True)
+
+
+def test_hold_back_async_and_duplicate_roots():
+    """Hold-back in the enqueue-only forward (budget from a synchronous run) and
+    with roots of staggered, duplicated and negative onsets (bucket 0 starts at
+    the smallest onset): the oracle's fixed point."""
+    dev = _dev()
+    p = gi.shell_problem(9_000, seed=17, n_roots=6, vscale_range=(0.6, 1.4))
+    rn = np.concatenate([p.root_node, p.root_node[:2]]).astype(np.int32)
+    rt = np.concatenate([p.root_t - 7.0, p.root_t[:2] - 12.0]).astype(np.float32)
+    To, _ = O.solve(p.xyz, p.tets, p.D, p.vscale, rn, rt)
+    plan = B().Plan(p.xyz, p.tets)
+    D, vs, rnd, rtd = t32(p.D, dev), t32(p.vscale, dev), i32(rn, dev), t32(rt, dev)
+    B().set_hold(plan, 1.0)
+    T, st = B().eikonal_forward(plan, D, vs, rnd, rtd)
+    assert st["converged"] and rel_max(T.cpu().numpy(), To) <= 1e-4
+    Ta = B().eikonal_forward_async(plan, D, vs, rnd, rtd, st["rounds"] + 8)
+    s1 = B().plan_status(plan)
+    assert s1["err"] == 0 and s1["forward_converged"], s1
+    assert rel_max(Ta.cpu().numpy(), To) <= 1e-4
+    # too small a budget leaves held vertices: reported as not converged
+    B().eikonal_forward_async(plan, D, vs, rnd, rtd, max(1, st["rounds"] // 3))
+    assert not B().plan_status(plan)["forward_converged"]
+
+
 def test_async_forward_and_backward(shell):
     """The enqueue-only forward and backward (fixed budgets, no synchronisation)
     give the synchronous calls' results; a budget that is too small and an input
