@@ -25,8 +25,8 @@ SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt, sp
 LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
 # hold-back candidates, searched last: (bucket width / mean front advance per round,
 # buckets past the current one that propagate, opening threshold / vertices one
-# round's grid takes at once); (0, 0, 0) is off
-HOLD_SPACE = ((0, 0, 0.0), (4, 0, 2.0), (8, 0, 0.5), (4, 0, 0.5), (8, 0, 2.0))
+# round's grid takes at once, None: open a bucket every round); (0, 0, 0) is off
+HOLD_SPACE = ((0, 0, 0.0), (1, 2, None), (1, 4, None), (4, 0, 2.0), (8, 0, 0.5))
 
 
 def cache_path() -> str:
@@ -120,7 +120,8 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
         for mult, window, frac in HOLD_SPACE:
             if mult and not unit > 0:
                 continue
-            cfg = dict(hold_delta=mult * unit, hold_window=window, hold_open=int(frac * cap))
+            cfg = dict(hold_delta=mult * unit, hold_window=window,
+                       hold_open=(1 << 30) if frac is None else int(frac * cap))
             B.set_hold(plan, cfg["hold_delta"], window, cfg["hold_open"])
             run()
             ms = _time(run, repeats)

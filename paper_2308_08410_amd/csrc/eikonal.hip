@@ -500,9 +500,17 @@ __global__ void __launch_bounds__(TPB)
     constexpr int CAP = TWO_SIDED ? kPushCapWide : kPushCap;
     __shared__ int push_q[CAP];
     __shared__ int push_n, push_cnt[8], push_base[8];
+    // held vertices staged per block (HOLD): vertex, ring slot
+    constexpr int kHoldStage = HOLD ? 1024 : 1;
+    __shared__ int hold_v[kHoldStage];
+    __shared__ unsigned char hold_s[kHoldStage];
+    __shared__ int hold_n, hold_cnt[HOLD ? kHoldBuckets : 1], hold_base[HOLD ? kHoldBuckets : 1];
     const bool have_open = HOLD && bopen >= 0 && (int)blockIdx.x * PER_BLOCK < nopen;
     if (lb * PER_BLOCK >= n && !have_open) return;   // no vertex for this block
-    if (threadIdx.x == 0) push_n = 0;
+    if (threadIdx.x == 0) {
+        push_n = 0;
+        hold_n = 0;
+    }
     __syncthreads();
     const XPushBuf pb{push_q, &push_n, CAP};
     const int lane = threadIdx.x & (L - 1);
@@ -584,12 +592,22 @@ __global__ void __launch_bounds__(TPB)
                         if (ha.hold[i] == b) {
                             ok = 1;
                         } else {
-                            const int slot = b & (kHoldBuckets - 1);
-                            const int pos = atomicAdd(&ctl->bcnt[slot], 1);
-                            if (pos < ha.bcap) {
-                                ha.blist[(size_t)slot * ha.bcap + pos] = i;
+                            // staged in LDS; the block reserves list room per bucket at
+                            // the end (one global atomic per bucket, not per vertex)
+                            const int hp = atomicAdd(&hold_n, 1);
+                            if (hp < kHoldStage) {
+                                hold_v[hp] = i;
+                                hold_s[hp] = (unsigned char)(b & (kHoldBuckets - 1));
                                 ha.hold[i] = b;
                                 ok = 1;
+                            } else {
+                                const int slot = b & (kHoldBuckets - 1);
+                                const int pos = atomicAdd(&ctl->bcnt[slot], 1);
+                                if (pos < ha.bcap) {
+                                    ha.blist[(size_t)slot * ha.bcap + pos] = i;
+                                    ha.hold[i] = b;
+                                    ok = 1;
+                                }
                             }
                         }
                     }
@@ -616,6 +634,36 @@ __global__ void __launch_bounds__(TPB)
                     const int nb = adj[a];
                     if (atomicMax(&mark[nb], stamp_next) < stamp_next)
                         xpush_node<false>(pb, nb, xq, qout, cnt_next);
+                }
+            }
+        }
+    }
+    if constexpr (HOLD) {
+        // the staged holds: count per ring slot, reserve room with one atomic per
+        // slot, scatter; a vertex that finds its list full pushes its neighbours now
+        __syncthreads();
+        const int nh = min(hold_n, kHoldStage);
+        if (threadIdx.x < kHoldBuckets) hold_cnt[threadIdx.x] = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < nh; k += blockDim.x) atomicAdd(&hold_cnt[hold_s[k]], 1);
+        __syncthreads();
+        if (threadIdx.x < kHoldBuckets) {
+            const int m = hold_cnt[threadIdx.x];
+            hold_base[threadIdx.x] = m > 0 ? atomicAdd(&ctl->bcnt[threadIdx.x], m) : 0;
+            hold_cnt[threadIdx.x] = 0;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nh; k += blockDim.x) {
+            const int v = hold_v[k], sl = hold_s[k];
+            const int pos = hold_base[sl] + atomicAdd(&hold_cnt[sl], 1);
+            if (pos < ha.bcap) {
+                ha.blist[(size_t)sl * ha.bcap + pos] = v;
+            } else {
+                ha.hold[v] = INT_MIN;
+                for (int a = adj_ptr[v]; a < adj_ptr[v + 1]; ++a) {
+                    const int nb = adj[a];
+                    if (atomicMax(&mark[nb], stamp_next) < stamp_next)
+                        xpush_node<TWO_SIDED>(pb, nb, xq, qout, cnt_next);
                 }
             }
         }
