@@ -64,7 +64,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0   # dense bf16 matrix-core peak
 
 
-FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched")
+FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched", "learned")
 
 
 def parse():
@@ -341,6 +341,42 @@ def fista_form(st, torch, B, n_faces=4_000_000, seed=43):
                                                                want_alpha=False))[0] * 1e6 / n_faces
     return dict(exact_forward_ms=ms_e, exact_rounds=se["rounds"], fista_launch=dict(lanes=8, sweep_blocks=2048),
                 runs=runs, ns_per_local_problem=per_face)
+
+
+def learned_form(st, prob, torch, B, n_train=128, steps=1500, batch=16384, n_test=3, seed=5):
+    """The learned warm start on the benchmark mesh: the network (bf16 matrix-core
+    kernels) trained on n_train cold solves with random roots (1-8), onsets and
+    smooth velocity scales (beyond 128 solves the held-out guess error stops
+    improving: 13.3% at 128 and 512 solves, 13.0% at 2048), then on held-out
+    cases: the guess error, and the cold solve against the solve warm-started
+    from the guess (local problems, rounds, time, agreement)."""
+    import numpy as np
+    from paper_2308_08410_amd import warmstart as WS
+    plan, D = st["plan"], st["D"]
+    t0 = time.perf_counter()
+    data = WS.make_dataset(plan, prob.xyz, D, prob.extra["endo"], n_train, seed=1000 * seed, scale_bank=32)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    ws = WS.WarmStart(prob.xyz, prob.extra["node_fibre"], max_rows=max(batch, 1 << 16), seed=seed)
+    t0 = time.perf_counter()
+    hist = WS.train(ws, data, steps, batch=batch, lr=1e-3, log_every=max(1, steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del data
+    test = WS.make_dataset(plan, prob.xyz, D, prob.extra["endo"], n_test, seed=7_000_000 + seed)
+    rows = WS.evaluate(ws, plan, D, test, repeats=2)
+    mean = lambda f: float(np.mean([f(r) for r in rows]))
+    return dict(
+        train_solves=n_train, train_steps=steps, batch=batch, data_seconds=t_data, train_seconds=t_train,
+        loss_first=hist[0][1], loss_last=hist[-1][1], held_out=n_test,
+        guess_rel_l2=dict(mlp=mean(lambda r: r["guess_rel_l2"]["mlp"]), geo=mean(lambda r: r["guess_rel_l2"]["geo"])),
+        local_problems=dict(cold=mean(lambda r: r["cold"]["face_solves"]),
+                            warm_mlp=mean(lambda r: r["warm_mlp"]["face_solves"])),
+        rounds=dict(cold=mean(lambda r: r["cold"]["rounds"]), warm_mlp=mean(lambda r: r["warm_mlp"]["rounds"])),
+        ms=dict(cold=mean(lambda r: r["cold_ms"]), warm_mlp_incl_prediction=mean(lambda r: r["warm_ms"]),
+                predict=mean(lambda r: r["predict_ms"])),
+        fallbacks=int(sum(r["warm_mlp"]["fallback"] for r in rows)),
+        max_rel_T_warm_vs_cold=max(r["warm_vs_cold_rel_max"]["mlp"] for r in rows))
 
 
 def lead_field_form(st, prob, torch, B, reps=5):
@@ -728,6 +764,15 @@ def main():
                 f"within budgets {f['converged']}")
         detail["batched"] = bw
         log(f"[bench] batched forms done ({time.time() - t:.1f}s)")
+    if "learned" in forms:
+        t = time.time()
+        lf = learned_form(st, prob, torch, B)
+        detail["learned_warm_start_500k"] = lf
+        log(f"[bench] learned warm start ({lf['train_solves']} solves, {lf['train_steps']} steps, "
+            f"{lf['train_seconds']:.1f}s training): guess error {lf['guess_rel_l2']['mlp']:.3f} (geometric "
+            f"{lf['guess_rel_l2']['geo']:.3f}); warm {lf['ms']['warm_mlp_incl_prediction']:.2f} ms vs cold "
+            f"{lf['ms']['cold']:.2f} ms, local problems x{lf['local_problems']['warm_mlp'] / lf['local_problems']['cold']:.2f}, "
+            f"rounds {lf['rounds']['warm_mlp']:.0f} vs {lf['rounds']['cold']:.0f} ({time.time() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()

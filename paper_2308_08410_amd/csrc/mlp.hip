@@ -1,6 +1,6 @@
 // Learned warm start: a small MLP (16 inputs -> 4 x 256 ReLU -> 1) that predicts
 // activation times from per-vertex features, trained and evaluated with BF16
-// matrix-core kernels (v_mfma_f32_16x16x16_bf16, FP32 accumulation).
+// matrix-core kernels (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
 //
 // Precision policy (mirrored by the reference):
 //   features X and the hidden-layer weights W1..W4 are rounded to bf16;
@@ -11,6 +11,8 @@
 //   dZ_{l-1} = bf16((dZ_l W_l) [H_{l-1} > 0]);  Adam on fp32 master weights.
 #include <math.h>
 
+#include <algorithm>
+
 #include <cstring>
 #include <random>
 #include <vector>
@@ -19,7 +21,7 @@
 
 namespace {
 
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;
 
@@ -35,17 +37,22 @@ __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((uns
 
 // ---------------------------------------------------------------- GEMM
 // C[i][j] = sum_k A(i,k) B(k,j) with A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc]
-// (bf16), 64x64 tile per block of 4 waves, each wave 32x32 = 2x2 MFMA tiles, K in
-// steps of 16 staged through LDS (B stored transposed so fragments are contiguous).
+// (bf16), 64x64 tile per block of 4 waves, each wave 32x32 = 2x2 tiles of
+// v_mfma_f32_16x16x32_bf16, K in steps of 32 staged through LDS (B stored
+// transposed so that a lane's 8 consecutive K values are one 16-byte read).
+// MFMA 16x16x32 lane layout: lane l holds A[l % 16][8 (l / 16) + q] and
+// B[8 (l / 16) + q][l % 16], q = 0..7, and returns D[4 (l / 16) + r][l % 16].
 enum { EPI_BIAS_RELU = 0, EPI_MASK = 1, EPI_PARTIAL = 2 };
+constexpr int KS = 32;          // K per staged step
+constexpr int KP = KS + 8;      // LDS row pitch (bf16): 80 bytes, 16-byte aligned rows
 
 template <int EPI>
 __global__ void __launch_bounds__(256)
     k_gemm(const bf16* __restrict__ A, int ar, int ac, const bf16* __restrict__ Bm, int br, int bc,
            int M, int N, int K, int kchunk, const float* __restrict__ bias,
            const bf16* __restrict__ mask, bf16* __restrict__ out, float* __restrict__ part) {
-    __shared__ bf16 As[64][16 + 4];
-    __shared__ bf16 Bt[64][16 + 4];
+    __shared__ __align__(16) bf16 As[64][KP];
+    __shared__ __align__(16) bf16 Bt[64][KP];
     const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
     const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -53,27 +60,25 @@ __global__ void __launch_bounds__(256)
     floatx4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-            const int r = e >> 4, kk = e & 15;
+    for (int k0 = kb; k0 < ke; k0 += KS) {
+        for (int e = threadIdx.x; e < 64 * KS; e += 256) {
+            const int r = e / KS, kk = e % KS;
             const int gi = i0 + r, gk = k0 + kk;
             As[r][kk] = (gi < M && gk < ke) ? A[(size_t)gi * ar + (size_t)gk * ac] : (bf16)0;
             const int gj = j0 + r;
             Bt[r][kk] = (gj < N && gk < ke) ? Bm[(size_t)gk * br + (size_t)gj * bc] : (bf16)0;
         }
         __syncthreads();
-        bf16x4_t af[2], bfv[2];
+        bf16x8_t af[2], bfv[2];
+        const int kq = (lane >> 4) * 8;
         for (int t = 0; t < 2; ++t) {
             const int ra = wi + t * 16 + (lane & 15), rb = wj + t * 16 + (lane & 15);
-            const int kq = (lane >> 4) * 4;
-            for (int q = 0; q < 4; ++q) {
-                af[t][q] = (short)As[ra][kq + q];
-                bfv[t][q] = (short)Bt[rb][kq + q];
-            }
+            af[t] = *reinterpret_cast<const bf16x8_t*>(&As[ra][kq]);
+            bfv[t] = *reinterpret_cast<const bf16x8_t*>(&Bt[rb][kq]);
         }
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfv[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
         __syncthreads();
     }
     for (int a = 0; a < 2; ++a)
@@ -105,12 +110,28 @@ __global__ void k_reduce_parts(const float* __restrict__ part, int splits, int n
 }
 
 // column sums of a bf16 [m x n] matrix (bias gradients), fixed order per column
-__global__ void k_colsum_bf16(const bf16* __restrict__ X, int m, int n, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    float s = 0.f;
-    for (int i = 0; i < m; ++i) s += from_bf16(X[(size_t)i * n + j]);
-    out[j] = s;
+// Column sums (bias gradients) in two fixed-order passes: block (g, r) sums, for 64
+// columns of group g, the rows [r R, (r+1) R) (4 row phases, then the phases in
+// order) into part[r][c]; k_reduce_parts then adds the row blocks in order.
+// WEIGHTED: sum_i w_i X[i][c], and column n (one past the last) gives sum_i w_i.
+template <bool WEIGHTED>
+__global__ void k_colsum_part(const bf16* __restrict__ X, const float* __restrict__ w, int m, int n,
+                              int R, float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
+    const int ncol = WEIGHTED ? n + 1 : n;
+    const int r0 = blockIdx.y * R, r1 = min(m, r0 + R);
+    float acc = 0.f;
+    if (c < ncol)
+        for (int i = r0 + q; i < r1; i += 4) {
+            const float x = c < n ? from_bf16(X[(size_t)i * n + c]) : 1.f;
+            acc += WEIGHTED ? w[i] * x : x;
+        }
+    red[q][cl] = acc;
+    __syncthreads();
+    if (q == 0 && c < ncol)
+        part[(size_t)blockIdx.y * ncol + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
 // ---------------------------------------------------------------- head, loss
@@ -167,22 +188,6 @@ __global__ void k_head_bwd(const float* __restrict__ dy, const bf16* __restrict_
     const int i = (int)(t / HID), j = (int)(t % HID);
     const bf16 h = H[t];
     dZ[t] = to_bf16((h != 0 && !(h & 0x8000)) ? dy[i] * w5[j] : 0.f);
-}
-
-// dw5_j = sum_i dy_i H4_ij (one thread per column, fixed order); db5 = sum dy
-__global__ void k_head_wgrad(const float* __restrict__ dy, const bf16* __restrict__ H, int m,
-                             float* __restrict__ dw5, float* __restrict__ db5) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < HID) {
-        float s = 0.f;
-        for (int i = 0; i < m; ++i) s += dy[i] * from_bf16(H[(size_t)i * HID + j]);
-        dw5[j] = s;
-    }
-    if (j == HID) {
-        float s = 0.f;
-        for (int i = 0; i < m; ++i) s += dy[i];
-        db5[0] = s;
-    }
 }
 
 // prediction out: scale * y, non-finite values as +inf (no information)
@@ -324,6 +329,22 @@ void gemm_fwd(const bf16* Hin, int m, int in, const bf16* W, const float* bias, 
                                                 out, nullptr);
 }
 
+// Rows per K chunk of the split-K weight-gradient GEMMs: at most kSplits chunks,
+// each a multiple of the GEMM's K step.
+constexpr int kSplits = 64;
+int split_chunk(int m) { return std::max(512, ((m + kSplits - 1) / kSplits + 31) / 32 * 32); }
+
+// out[c] = sum over the m rows of X[:, c] (w == nullptr) or of w_i X[i][c] with
+// out[n] = sum w_i; deterministic (fixed-order partials in p->part)
+void colsum(gbp_mlp p, const bf16* X, const float* w, int m, int n, float* out, hipStream_t s) {
+    const int R = 256;
+    const int ncol = w ? n + 1 : n;
+    const dim3 g((ncol + 63) / 64, (m + R - 1) / R);
+    if (w) k_colsum_part<true><<<g, 256, 0, s>>>(X, w, m, n, R, p->part);
+    else k_colsum_part<false><<<g, 256, 0, s>>>(X, nullptr, m, n, R, p->part);
+    k_reduce_parts<<<gbp_blocks(ncol, 256), 256, 0, s>>>(p->part, (int)g.y, ncol, out);
+}
+
 int forward_all(gbp_mlp p, const bf16* X, int m, hipStream_t s) {
     const bf16* hin = X;
     for (int l = 1; l <= NLAYER; ++l) {
@@ -340,8 +361,8 @@ int backward_all(gbp_mlp p, const bf16* X, int m, const float* target, hipStream
     const int nb = gbp_blocks(m, 256);
     k_mse<<<nb, 256, 0, s>>>(p->y, target, m, p->dy, p->part);
     k_sum_parts<<<1, 256, 0, s>>>(p->part, nb, 1.f / (float)m, p->loss);
-    k_head_wgrad<<<gbp_blocks(HID + 1, 64), 64, 0, s>>>(p->dy, p->H[NLAYER], m, p->grads + off_w5(),
-                                                        p->grads + off_w5() + HID);
+    // dw5 = H4^T dy and db5 = sum dy (parameter order: w5 then b5, adjacent)
+    colsum(p, p->H[NLAYER], p->dy, m, HID, p->grads + off_w5(), s);
     k_head_bwd<<<gbp_blocks((long long)m * HID, 256), 256, 0, s>>>(p->dy, p->H[NLAYER], m,
                                                                     p->params + off_w5(), p->dZ[0]);
     int cur = 0;
@@ -349,14 +370,14 @@ int backward_all(gbp_mlp p, const bf16* X, int m, const float* target, hipStream
         const int in = in_dim(l);
         const bf16* hprev = l > 1 ? p->H[l - 1] : X;
         // dW_l [256 x in] = dZ^T Hprev: A(i,k) = dZ[k*256 + i], B(k,j) = Hprev[k*in + j], split K
-        const int kchunk = 4096;
+        const int kchunk = split_chunk(m);
         const int splits = (m + kchunk - 1) / kchunk;
         dim3 g1((in + 63) / 64, (HID + 63) / 64, splits);
         k_gemm<EPI_PARTIAL><<<g1, 256, 0, s>>>(p->dZ[cur], 1, HID, hprev, in, 1, HID, in, m, kchunk,
                                                nullptr, nullptr, nullptr, p->part);
         k_reduce_parts<<<gbp_blocks(HID * in, 256), 256, 0, s>>>(p->part, splits, HID * in,
                                                                  p->grads + off_W(l));
-        k_colsum_bf16<<<1, 256, 0, s>>>(p->dZ[cur], m, HID, p->grads + off_b(l));
+        colsum(p, p->dZ[cur], nullptr, m, HID, p->grads + off_b(l), s);
         if (l > 1) {
             // dZ_{l-1} [m x in] = (dZ W_l) masked: A(i,k) = dZ[i*256 + k], B(k,j) = W[k*in + j]
             dim3 g2((in + 63) / 64, (m + 63) / 64, 1);
@@ -388,9 +409,9 @@ extern "C" int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp* out) {
     (void)hipGetDevice(&p->device);
     p->max_rows = max_rows;
     p->n_params = n_params_total();
-    const int kchunk = 4096;
-    p->part_n = std::max((size_t)((max_rows + kchunk - 1) / kchunk) * HID * HID,
-                         (size_t)gbp_blocks(max_rows, 256));
+    // split-K partials of a weight gradient, column-sum partials, loss partials
+    p->part_n = std::max({(size_t)kSplits * HID * HID, (size_t)((max_rows + 255) / 256) * (HID + 1),
+                          (size_t)gbp_blocks(max_rows, 256)});
     bool ok = hipMalloc((void**)&p->params, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->grads, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->m, sizeof(float) * p->n_params) == hipSuccess &&

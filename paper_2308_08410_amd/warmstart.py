@@ -88,32 +88,46 @@ class WarmStart:
 
 
 # ---------------------------------------------------------------- data, training, evaluation
-def random_case(xyz, candidates, seed, roots=(1, 8), t_range=(0.0, 20.0), vscale_range=(0.5, 1.5)):
-    """Random roots (count, nodes, onsets) and a smooth velocity scale."""
+def random_case(xyz, candidates, seed, roots=(1, 8), t_range=(0.0, 20.0), vscale_range=(0.5, 1.5),
+                with_scale=True):
+    """Random roots (count, nodes, onsets) and a smooth velocity scale (None
+    unless with_scale)."""
     import gbp_inputs as gi
     r = np.random.Generator(np.random.PCG64(seed))
     R = int(r.integers(roots[0], roots[1] + 1))
     rn, rt = gi.random_roots(candidates, R, t_range[0], t_range[1], seed=seed + 1)
     lo = float(r.uniform(vscale_range[0], 1.0))
     hi = float(r.uniform(1.0, vscale_range[1]))
-    vs = gi.smooth_field(xyz, lo, hi, seed=seed + 2)
+    vs = gi.smooth_field(xyz, lo, hi, seed=seed + 2) if with_scale else None
     return rn, rt, vs
 
 
-def make_dataset(plan, xyz, D, candidates, n_solves, seed=0, **kw):
-    """Cold solves of the mesh for random cases (the training targets)."""
+def make_dataset(plan, xyz, D, candidates, n_solves, seed=0, scale_bank=0, log_every=0, **kw):
+    """Cold solves of the mesh for random cases (the training targets).  With
+    scale_bank > 0 the velocity scales come from that many seeded smooth fields,
+    reused across cases (each paired with its own random roots and onsets), since
+    a smooth field over a large mesh takes longer to make than a solve."""
     dev = D.device
     data = []
+    bank = []
     for k in range(n_solves):
-        rn, rt, vs = random_case(xyz, candidates, seed + 7919 * k, **kw)
-        d = dict(root_node=torch.as_tensor(rn, device=dev), root_t=torch.as_tensor(rt, device=dev),
-                 vscale=torch.as_tensor(vs, device=dev))
+        rn, rt, vs = random_case(xyz, candidates, seed + 7919 * k,
+                                 with_scale=(k < scale_bank) if scale_bank else True, **kw)
+        if scale_bank:
+            if k < scale_bank:
+                bank.append(torch.as_tensor(vs, device=dev))
+            vsd = bank[k % scale_bank]
+        else:
+            vsd = torch.as_tensor(vs, device=dev)
+        d = dict(root_node=torch.as_tensor(rn, device=dev), root_t=torch.as_tensor(rt, device=dev), vscale=vsd)
         d["T"], _ = B.eikonal_forward(plan, D, d["vscale"], d["root_node"], d["root_t"])
         data.append(d)
+        if log_every and (k + 1) % log_every == 0:
+            print(f"[data] {k + 1} of {n_solves} solves", flush=True)
     return data
 
 
-def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_every=100, seed=0):
+def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_every=100, seed=0, verbose=False):
     """Adam on random row batches of the solves, cosine learning-rate decay.
     Returns [(step, mse in normalised time units)]."""
     if batch > ws.mlp.max_rows:
@@ -130,6 +144,8 @@ def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_ever
         ws.mlp.train_step(X, tgt, lr_s, loss=loss)
         if log_every and (s % log_every == 0 or s == steps - 1):
             hist.append((s, float(loss)))
+            if verbose:
+                print(f"[train] step {s} of {steps}: mse {hist[-1][1]:.4g}", flush=True)
     return hist
 
 
