@@ -8,7 +8,10 @@
 // span [Tmin, Tmax], so for t_s < Tmin - 6 tau every term is at rest and for
 // t_s > Tmax + 6 tau every term is at K1.  Only the window in between needs the
 // template; there the contraction (time x vertices) . (vertices x leads) runs on
-// v_mfma_f32_16x16x32_bf16 tiles whose A operand is generated in registers from T.
+// v_mfma_f32_16x16x16_bf16 tiles whose A operand is generated in registers from T.
+// (The K = 32 shape of gfx950 halves the matrix instructions but made both kernels
+// slower, 74 -> 106 us and 63 -> 67 us at 500k: they are bound by the template's
+// vector-ALU work and latency, and the wider operands raised register use.)
 // Both operands are split into bf16 hi + lo parts (three products, FP32
 // accumulation), since the lead weights sum to ~0 and the ECG is a cancellation.
 // The saturated part is a step function: the window's weight sum is added once at
@@ -23,8 +26,8 @@
 // chunks.  A chunk is an independent ECG on its own time grid; the backward adds
 // the contributions of later tiles and chunks to dT in launch order.
 //
-// MFMA 16x16x32 lane layout (checked on the device): lane l holds A[l % 16][8 (l / 16) + q]
-// and B[8 (l / 16) + q][l % 16], q = 0..7, and returns D[4 (l / 16) + r][l % 16], r = 0..3.
+// MFMA 16x16x16 lane layout: lane l holds A[l % 16][4 (l / 16) + q] and
+// B[4 (l / 16) + q][l % 16], q = 0..3, and returns D[4 (l / 16) + r][l % 16], r = 0..3.
 #include <math.h>
 #include <mutex>
 
@@ -33,8 +36,7 @@
 
 namespace {
 
-typedef short short8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr float kSat = 24.f;          // |4 xi / tau| beyond which sigma is saturated
@@ -54,12 +56,11 @@ __device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
     lo = (short)bf16_rne(x - __uint_as_float(h << 16));
 }
 
-__device__ __forceinline__ floatx4 mfma3(short8 ah, short8 al, short8 bh, short8 bl, floatx4 acc) {
-    const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah), Al = __builtin_bit_cast(bf16x8_t, al);
-    const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh), Bl = __builtin_bit_cast(bf16x8_t, bl);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc, 0, 0, 0);
+__device__ __forceinline__ floatx4 mfma3(bf16x4_t ah, bf16x4_t al, bf16x4_t bh, bf16x4_t bl,
+                                         floatx4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
     return acc;
 }
 
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kq = lane >> 4;
-    float wsum_all = 0.f;   // lane: lead col, vertices 8kq+q of each K-step
+    float wsum_all = 0.f;   // lane: lead col, vertices 4kq+r of each K-step
     for (int gi = wave; gi < groups_per_block; gi += 4) {
         const int g0 = vbeg + (blockIdx.x * groups_per_block + gi) * 64;
         if (g0 >= vend) break;
@@ -142,10 +143,10 @@ __global__ void __launch_bounds__(256)
         bool any;
         wave_window(Tl, ap, s_lo, s_hi, any);
         float wsum_fin = 0.f;
-        // weight sums (2 K-steps of 32 vertices)
-        for (int ks = 0; ks < 2; ++ks) {
-            for (int q = 0; q < 8; ++q) {
-                const int n = g0 + ks * 32 + kq * 8 + q;
+        // W fragments and sums (4 K-steps of 16 vertices)
+        for (int ks = 0; ks < 4; ++ks) {
+            for (int r = 0; r < 4; ++r) {
+                const int n = g0 + ks * 16 + kq * 4 + r;
                 const float w = (n < vend && col < Lt) ? W[(size_t)n * Ls + col] : 0.f;
                 const float t = n < vend ? T[n] : __builtin_huge_valf();
                 wsum_all += w;
@@ -158,29 +159,29 @@ __global__ void __launch_bounds__(256)
             floatx4 acc[4];
             for (int m = 0; m < 4; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
             const int ntile = min(4, (s_hi - s0 + 15) / 16);
-            for (int ks = 0; ks < 2; ++ks) {
-                float tv[8];
-                short8 bh, bl;
-                for (int q = 0; q < 8; ++q) {
-                    const int n = g0 + ks * 32 + kq * 8 + q;
+            for (int ks = 0; ks < 4; ++ks) {
+                float tv[4];
+                bf16x4_t bh, bl;
+                for (int r = 0; r < 4; ++r) {
+                    const int n = g0 + ks * 16 + kq * 4 + r;
                     const float w = (n < vend && col < Lt) ? W[(size_t)n * Ls + col] : 0.f;
-                    tv[q] = n < vend ? T[n] : __builtin_huge_valf();
+                    tv[r] = n < vend ? T[n] : __builtin_huge_valf();
                     short h, l;
                     split_bf16(w, h, l);
-                    bh[q] = h;
-                    bl[q] = l;
+                    bh[r] = h;
+                    bl[r] = l;
                 }
                 for (int m = 0; m < 4; ++m) {
                     if (m >= ntile) break;
                     const float t = ap.t0 + (float)(s0 + 16 * m + col) * ap.dt;
-                    short8 ah, al;
-                    for (int q = 0; q < 8; ++q) {
-                        const float e = __builtin_amdgcn_exp2f((tv[q] - t) * ap.c4);
+                    bf16x4_t ah, al;
+                    for (int r = 0; r < 4; ++r) {
+                        const float e = __builtin_amdgcn_exp2f((tv[r] - t) * ap.c4);
                         const float a = ap.amp * __builtin_amdgcn_rcpf(1.f + e);
                         short h, l;
                         split_bf16(a, h, l);
-                        ah[q] = h;
-                        al[q] = l;
+                        ah[r] = h;
+                        al[r] = l;
                     }
                     acc[m] = mfma3(ah, al, bh, bl, acc[m]);
                 }
@@ -292,22 +293,22 @@ __global__ void __launch_bounds__(256)
             const float tn = nrow < vend ? T[nrow] : __builtin_huge_valf();
             floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
             if (any) {
-                for (int s0 = s_lo; s0 < s_hi; s0 += 32) {   // K-steps of 32 time steps
-                    short8 ah, al, bh, bl;
-                    for (int q = 0; q < 8; ++q) {
-                        const int s = s0 + kq * 8 + q;
+                for (int s0 = s_lo; s0 < s_hi; s0 += 16) {
+                    bf16x4_t ah, al, bh, bl;
+                    for (int r = 0; r < 4; ++r) {
+                        const int s = s0 + kq * 4 + r;
                         const float t = ap.t0 + (float)s * ap.dt;
                         const float e = __builtin_amdgcn_exp2f((tn - t) * ap.c4);
-                        const float qq = __builtin_amdgcn_rcpf(1.f + e);
-                        const float omq = e < 1.f ? e * qq : 1.f - qq;
-                        const float a = (s < ap.S) ? ap.dudx * qq * omq : 0.f;
+                        const float q = __builtin_amdgcn_rcpf(1.f + e);
+                        const float omq = e < 1.f ? e * q : 1.f - q;
+                        const float a = (s < ap.S) ? ap.dudx * q * omq : 0.f;
                         short h, l;
                         split_bf16(a, h, l);
-                        ah[q] = h;
-                        al[q] = l;
+                        ah[r] = h;
+                        al[r] = l;
                         const int sc = s < S_pad ? s : S_pad - 1;
-                        bh[q] = (s < ap.S) ? gh[sc * 16 + col] : (short)0;
-                        bl[q] = (s < ap.S) ? glo[sc * 16 + col] : (short)0;
+                        bh[r] = (s < ap.S) ? gh[sc * 16 + col] : (short)0;
+                        bl[r] = (s < ap.S) ? glo[sc * 16 + col] : (short)0;
                     }
                     acc = mfma3(ah, al, bh, bl, acc);
                 }

@@ -85,30 +85,32 @@ def _mean_of(d, substr):
     return sum(vals) / len(vals), len(vals)
 
 
-def traffic(fetch_path, write_path, kernel="k_sweep", copy_substr="neg", copy_mib=256):
+def traffic(fetch_path, write_path, kernel="k_sweep", copy_substr="neg", copy_mib=256, match=None):
+    """match: the substring that selects the kernel's dispatches (default: its
+    name; e.g. one template instance)."""
     fetch = per_kernel(fetch_path, "FETCH_SIZE")
     write = per_kernel(write_path, "WRITE_SIZE")
     copy_kib = copy_mib * 1024.0
-    f_k, n_f = _mean_of(fetch, kernel)
-    w_k, n_w = _mean_of(write, kernel)
+    f_k, n_f = _mean_of(fetch, match or kernel)
+    w_k, n_w = _mean_of(write, match or kernel)
     f_c, _ = _mean_of(fetch, copy_substr)
     w_c, _ = _mean_of(write, copy_substr)
     sf, sw = copy_kib / f_c, copy_kib / w_c
-    return dict(kernel=kernel, dispatches=[n_f, n_w], fetch_kib_raw=f_k, write_kib_raw=w_k,
+    return dict(kernel=kernel, match=match or kernel, dispatches=[n_f, n_w], fetch_kib_raw=f_k, write_kib_raw=w_k,
                 copy_fetch_kib_raw=f_c, copy_write_kib_raw=w_c, copy_mib=copy_mib,
                 fetch_scale=sf, write_scale=sw,
                 bytes_per_launch=1024.0 * (f_k * sf + w_k * sw),
                 source_hash=source_hash(kernel))
 
 
-def mfma(path, kernel, source="ecg.hip", peak_tflops=2500.0):
+def mfma(path, kernel, source="ecg.hip", peak_tflops=2500.0, match=None):
     """Matrix-core use of one kernel from a `--pmc MfmaFlopsBF16 MfmaUtil` run:
     executed bf16 MFMA flops per dispatch, their rate over the dispatch's
     duration, and the fraction of cycles the matrix units were busy."""
     flops, util, dur = {}, {}, {}
     with open(_counter_csv(path), newline="") as f:
         for r in csv.DictReader(f):
-            if kernel not in r["Kernel_Name"]:
+            if (match or kernel) not in r["Kernel_Name"]:
                 continue
             d = r.get("Dispatch_Id") or r.get("Correlation_Id")
             v = float(r["Counter_Value"])
@@ -166,6 +168,24 @@ def valu(path, kernel, source="ecg.hip"):
                 source_hash=source_hash(kernel, source))
 
 
+def trace_table(stats_csv, top=12):
+    """Markdown table of the most expensive kernels of a `rocprofv3 --kernel-trace
+    --stats` run (names shortened to the function and its template arguments)."""
+    rows = []
+    with open(stats_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Name"]
+            short = re.sub(r"^void ", "", name.replace("(anonymous namespace)::", ""))
+            short = re.sub(r"\(.*$", "", short)
+            rows.append((short, int(r["Calls"]), float(r["TotalDurationNs"]) * 1e-6,
+                         float(r["AverageNs"]) * 1e-3, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[2])
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for short, calls, tot, avg, pct in rows[:top]:
+        out.append(f"| {short} | {calls} | {tot:.3f} | {avg:.2f} | {pct:.2f} |")
+    return "\n".join(out)
+
+
 def read_summary(path):
     """The JSON block of a summary written by this module, or None."""
     try:
@@ -184,13 +204,24 @@ def main(argv=None):
     ap.add_argument("--mfma", help="a --pmc MfmaFlopsBF16 MfmaUtil run (instead of --fetch/--write)")
     ap.add_argument("--valu", help="a --pmc SQ_INSTS_VALU SQ_INSTS_VALU_TRANS_F32 VALUBusy run")
     ap.add_argument("--kernel", default="k_sweep")
+    ap.add_argument("--match", default=None, help="substring selecting the kernel's dispatches "
+                                                  "(default: --kernel)")
+    ap.add_argument("--source", default=None, help="source file of --kernel for the hash "
+                                                   "(default: eikonal.hip for traffic, ecg.hip otherwise)")
+    ap.add_argument("--trace", help="a --kernel-trace --stats run's *_kernel_stats.csv: print its table")
     ap.add_argument("--copy", default="neg")
     ap.add_argument("--copy-mib", type=float, default=256)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", default="", help="the profiled command, recorded in the summary")
     args = ap.parse_args(argv)
+    if args.trace:
+        table = trace_table(args.trace)
+        with open(args.out, "w") as f:
+            f.write(table + "\n")
+        print(table)
+        return
     if args.mfma:
-        t = mfma(args.mfma, args.kernel)
+        t = mfma(args.mfma, args.kernel, source=args.source or "ecg.hip", match=args.match)
         with open(args.out, "w") as f:
             f.write(f"# Matrix-core use: {args.kernel}\n\n")
             f.write("One rocprofv3 counter run (derived counters MfmaFlopsBF16 = 512 x\n"
@@ -230,7 +261,7 @@ def main(argv=None):
         return
     if not (args.fetch and args.write):
         ap.error("--fetch and --write are required without --mfma or --valu")
-    t = traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_mib)
+    t = traffic(args.fetch, args.write, args.kernel, args.copy, args.copy_mib, match=args.match)
     with open(args.out, "w") as f:
         f.write(f"# HBM traffic per launch: {args.kernel}\n\n")
         f.write("Two rocprofv3 counter runs of the same command, FETCH_SIZE then WRITE_SIZE (KiB per\n"
