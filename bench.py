@@ -204,10 +204,12 @@ def _warm_accuracy(step, plan, D, vs, rn, rt, T, B, torch):
     return err, st
 
 
-def warm_single_form(st, prob, steps, torch, B, autotune):
-    """The same 500k iteration as one HIP-graph replay whose forward starts
-    (two-sided) from the previous iteration's activation times."""
+def warm_single_form(st, prob, steps, torch, B, autotune, ordered=False):
+    """The same 500k iteration as one HIP-graph replay whose forward starts from
+    the previous iteration's activation times: two-sided, or (ordered) a cold
+    solve whose hold-back is keyed by them (hold-back searched for that)."""
     plan, dev = st["plan"], st["D"].device
+    hold0 = B.get_hold(plan)
     L = prob.W.shape[1]
     S = prob.ap["n_steps"]
     bt = B.Batch([0, prob.n_v], S)
@@ -217,14 +219,22 @@ def warm_single_form(st, prob, steps, torch, B, autotune):
     tgt = st["target"].reshape(1, S, L).contiguous()
     B.eikonal_forward(plan, st["D"], st["vs"], st["rn"], st["rt"], out=T)
     B.eikonal_backward(plan, st["D"], st["vs"], st["rn"], st["rt"], T, torch.ones_like(T), want_D=False)
+    hold = None
+    if ordered:
+        hold = autotune.tune_hold(plan, st["D"], st["vs"], st["rn"], st["rt"], guess=T.clone(), repeats=1)
+        B.eikonal_forward(plan, st["D"], st["vs"], st["rn"], st["rt"], T_init=T, out=T)
     bud = autotune.budgets(plan, margin=1.5, extra=32)
     step = B.Step(plan, bt, st["D"], st["vs"], st["rn"], st["rt"], st["W"], st["ap"], tgt, T, ecg, loss,
                   warm=True, **bud)
     ms = _replay_timed(step, steps, torch)
+    work = B.forward_work(plan)
     err, status = _warm_accuracy(step, plan, st["D"], st["vs"], st["rn"], st["rt"], T, B, torch)
     step.close()
+    B.set_warm_order(plan, False)
+    B.set_hold(plan, *hold0)
     return dict(iters_per_s=1000.0 / ms, ms_per_step=ms, max_rel_T_vs_cold=err,
-                converged=bool(status["forward_converged"] and status["backward_settled"]), budgets=bud)
+                converged=bool(status["forward_converged"] and status["backward_settled"]), budgets=bud,
+                local_problems_per_step=work["face_solves"], hold=hold)
 
 
 def point_root_form(st, prob, steps, torch, gi, B, n_points=100, seed=41):
@@ -371,12 +381,16 @@ def learned_form(st, prob, torch, B, n_train=128, steps=1500, batch=16384, n_tes
         loss_first=hist[0][1], loss_last=hist[-1][1], held_out=n_test,
         guess_rel_l2=dict(mlp=mean(lambda r: r["guess_rel_l2"]["mlp"]), geo=mean(lambda r: r["guess_rel_l2"]["geo"])),
         local_problems=dict(cold=mean(lambda r: r["cold"]["face_solves"]),
-                            warm_mlp=mean(lambda r: r["warm_mlp"]["face_solves"])),
-        rounds=dict(cold=mean(lambda r: r["cold"]["rounds"]), warm_mlp=mean(lambda r: r["warm_mlp"]["rounds"])),
+                            warm_mlp=mean(lambda r: r["warm_mlp"]["face_solves"]),
+                            warm_mlp_ordered=mean(lambda r: r["warm_mlp_ordered"]["face_solves"])),
+        rounds=dict(cold=mean(lambda r: r["cold"]["rounds"]), warm_mlp=mean(lambda r: r["warm_mlp"]["rounds"]),
+                    warm_mlp_ordered=mean(lambda r: r["warm_mlp_ordered"]["rounds"])),
         ms=dict(cold=mean(lambda r: r["cold_ms"]), warm_mlp_incl_prediction=mean(lambda r: r["warm_ms"]),
+                warm_mlp_ordered_incl_prediction=mean(lambda r: r["ordered_ms"]),
                 predict=mean(lambda r: r["predict_ms"])),
         fallbacks=int(sum(r["warm_mlp"]["fallback"] for r in rows)),
-        max_rel_T_warm_vs_cold=max(r["warm_vs_cold_rel_max"]["mlp"] for r in rows))
+        max_rel_T_warm_vs_cold=max(r["warm_vs_cold_rel_max"]["mlp"] for r in rows),
+        max_rel_T_ordered_vs_cold=max(r["warm_vs_cold_rel_max"]["mlp_ordered"] for r in rows))
 
 
 def lead_field_form(st, prob, torch, B, reps=5):
@@ -477,15 +491,23 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
     out = dict(instances=n_inst, distinct_meshes=n_meshes, mesh_sizes=[int(m.n_v) for m in meshes],
                total_vertices=int(voff[-1]), total_tets=int(len(tets)), setup_s=t_setup,
                launch=dict(lanes=tune["lanes"], sweep_blocks=tune["sweep_blocks"], split=tune["split"]))
+    out["launch"]["hold"] = B.get_hold(plan)
     vs_start, rt_start = vs.clone(), rt.clone()
-    for warm in (False, True):
+    hold0 = B.get_hold(plan)
+    for mode in ("cold", "warm", "warm_ordered"):
+        warm = mode != "cold"
         vs.copy_(vs_start)
         rt.copy_(rt_start)
         T = torch.empty(len(xyz), dtype=torch.float32, device=dev)
         B.eikonal_forward(plan, D, vs, rn, rt, out=T)
         B.eikonal_backward(plan, D, vs, rn, rt, T, torch.ones_like(T), want_D=False)
+        hold = None
+        if mode == "warm_ordered":
+            # the hold-back searched for forwards ordered by the last times
+            hold = autotune.tune_hold(plan, D, vs, rn, rt, guess=T.clone(), repeats=1)
+            B.eikonal_forward(plan, D, vs, rn, rt, T_init=T, out=T)
         # a two-sided warm solve can need more rounds than the cold one it is sized from
-        bud = autotune.budgets(plan, margin=2.0 if warm else 1.5, extra=64 if warm else 32)
+        bud = autotune.budgets(plan, margin=2.0 if mode == "warm" else 1.5, extra=64 if mode == "warm" else 32)
         ecg = torch.empty((n_inst, S, L), dtype=torch.float32, device=dev)
         loss = torch.empty(n_inst, dtype=torch.float32, device=dev)
         step = B.Step(plan, bt, D, vs, rn, rt, W, apc, target, T, ecg, loss, warm=warm, **bud)
@@ -493,13 +515,15 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
         work = B.forward_work(plan)          # the last replay's forward
         err, status = _warm_accuracy(step, plan, D, vs, rn, rt, T, B, torch)
         step.close()
+        B.set_warm_order(plan, False)
+        B.set_hold(plan, *hold0)
         # algorithmic bytes of one replayed iteration: the forward's local problems,
         # the backward, the ECG forward and backward (the small misfit and Adam aside)
         nv, ne = int(voff[-1]), int(len(tets))
         alg = (work["face_solves"] * bytes_per_local_problem(nv, ne) + adjoint_bytes(nv, ne)
                + ecg_bytes(nv, L))
-        out["warm" if warm else "cold"] = dict(
-            ms_per_step=ms, instance_iters_per_s=n_inst * 1000.0 / ms,
+        out[mode] = dict(
+            hold=hold, ms_per_step=ms, instance_iters_per_s=n_inst * 1000.0 / ms,
             vertex_iters_per_s=int(voff[-1]) * 1000.0 / ms, max_rel_T_vs_cold=err,
             converged=bool(status["forward_converged"] and status["backward_settled"]), status=status,
             budgets=bud, backward=B.backward_info(plan), local_problems_per_step=work["face_solves"],
@@ -720,12 +744,15 @@ def main():
         sys.exit(2)
     from paper_2308_08410_amd import autotune
     if "warm" in forms:
-        t = time.time()
-        ws = warm_single_form(st, prob, args.form_steps, torch, B, autotune)
-        ws["speedup_vs_plain"] = ws["iters_per_s"] / (1000.0 / ms)
-        detail["warm_single_500k"] = ws
-        log(f"[bench] warm single form: {ws['iters_per_s']:.1f} iter/s (x{ws['speedup_vs_plain']:.2f}), "
-            f"max rel T vs cold {ws['max_rel_T_vs_cold']:.1e} ({time.time() - t:.1f}s)")
+        for ordered in (False, True):
+            t = time.time()
+            ws = warm_single_form(st, prob, args.form_steps, torch, B, autotune, ordered=ordered)
+            ws["speedup_vs_plain"] = ws["iters_per_s"] / (1000.0 / ms)
+            name = "ordered" if ordered else "two-sided"
+            detail["warm_ordered_single_500k" if ordered else "warm_single_500k"] = ws
+            log(f"[bench] warm single form ({name}): {ws['iters_per_s']:.1f} iter/s (x{ws['speedup_vs_plain']:.2f}), "
+                f"{ws['local_problems_per_step'] / 1e6:.1f}M local problems, "
+                f"max rel T vs cold {ws['max_rel_T_vs_cold']:.1e} ({time.time() - t:.1f}s)")
     if "points" in forms:
         t = time.time()
         pf = point_root_form(st, prob, args.form_steps, torch, gi, B)
@@ -755,12 +782,13 @@ def main():
     if "batched" in forms:
         t = time.time()
         bw = batched_form(dev, args.form_steps, torch, gi, B, autotune)
-        for k in ("cold", "warm"):
+        for k in ("cold", "warm", "warm_ordered"):
             f = bw[k]
             f["speedup_vs_plain_vertex_iters"] = f["vertex_iters_per_s"] / (prob.n_v * 1000.0 / ms)
             log(f"[bench] batched form ({k}): {bw['instances']} instances / {bw['total_vertices']} vertices, "
                 f"{f['instance_iters_per_s']:.1f} instance-iter/s, x{f['speedup_vs_plain_vertex_iters']:.2f} "
-                f"vertex-iter/s vs plain, max rel T vs cold {f['max_rel_T_vs_cold']:.1e}, "
+                f"vertex-iter/s vs plain, {f['local_problems_per_step'] / 1e6:.0f}M local problems, "
+                f"max rel T vs cold {f['max_rel_T_vs_cold']:.1e}, "
                 f"within budgets {f['converged']}")
         detail["batched"] = bw
         log(f"[bench] batched forms done ({time.time() - t:.1f}s)")
@@ -772,7 +800,9 @@ def main():
             f"{lf['train_seconds']:.1f}s training): guess error {lf['guess_rel_l2']['mlp']:.3f} (geometric "
             f"{lf['guess_rel_l2']['geo']:.3f}); warm {lf['ms']['warm_mlp_incl_prediction']:.2f} ms vs cold "
             f"{lf['ms']['cold']:.2f} ms, local problems x{lf['local_problems']['warm_mlp'] / lf['local_problems']['cold']:.2f}, "
-            f"rounds {lf['rounds']['warm_mlp']:.0f} vs {lf['rounds']['cold']:.0f} ({time.time() - t:.1f}s)")
+            f"rounds {lf['rounds']['warm_mlp']:.0f} vs {lf['rounds']['cold']:.0f}; ordered "
+            f"{lf['ms']['warm_mlp_ordered_incl_prediction']:.2f} ms, local problems "
+            f"x{lf['local_problems']['warm_mlp_ordered'] / lf['local_problems']['cold']:.2f} ({time.time() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()

@@ -105,7 +105,8 @@ int gbp_plan_sizes(gbp_plan plan, int *n_v, int *n_e);
  *              Non-NULL: a guess; the solve then uses the two-sided update
  *              (every node re-takes the minimum over its faces, roots also
  *              min with their onset), which converges to the same fixed point
- *              from any finite or infinite guess.
+ *              from any finite or infinite guess.  With gbp_plan_set_warm_order
+ *              on, the guess instead orders a cold solve (see there).
  *   T_out      device float [n_v]  (may alias T_init)
  *   stats      host, may be NULL
  * Unreached vertices get +inf.  Errors: GBP_ERR_ARG (root id out of range,
@@ -217,6 +218,23 @@ int gbp_plan_get_local_solver(gbp_plan plan, int *solver, int *n_f, int *lipschi
  */
 int gbp_plan_set_hold(gbp_plan plan, float delta, int window, int open_below);
 int gbp_plan_get_hold(gbp_plan plan, float *delta, int *window, int *open_below);
+
+/*
+ * gbp_plan_set_warm_order / gbp_plan_get_warm_order -- what a forward does with
+ * T_init.  on = 0 (the default): the two-sided warm update from T_init.  on = 1:
+ * the forward solves cold (from +inf, one-sided update, as with T_init NULL)
+ * and uses T_init only as an ordering guess for the hold-back: a vertex whose
+ * value has dropped is keyed by min(value, guess), so a value still above its
+ * guess waits until the front reaches the guess (Delta-stepping keyed by a
+ * prediction of the solution, e.g. the last iteration's times or the learned
+ * warm start's).  The fixed point is the cold solve's for any guess (NaN reads as
+ * +inf); the guess only changes the work.  With the hold-back off
+ * (gbp_plan_set_hold delta = 0) the guess is ignored.  T_init may alias T_out.
+ * Allocates n_v floats of device memory on first use (per plan).
+ * Errors: GBP_ERR_ARG (on not 0 or 1), GBP_ERR_NOMEM.
+ */
+int gbp_plan_set_warm_order(gbp_plan plan, int on);
+int gbp_plan_get_warm_order(gbp_plan plan, int *on);
 
 /*
  * gbp_plan_set_input_reuse -- lets gbp_eikonal_backward and gbp_parent_map keep

@@ -6,7 +6,9 @@ in a relaxation round, grid of a round, launches between convergence checks,
 queue split over the XCDs or not, then the cold forward's hold-back (bucket
 width in units of the front's mean advance per round, and when the next bucket
 opens) -- keeps the fastest, and records the rounds/levels that carried work so
-that graph-captured iterations can be given launch budgets.  Results are cached in a JSON file
+that graph-captured iterations can be given launch budgets.  tune_hold searches
+the hold-back alone, also for the ordered warm start (gbp_plan_set_warm_order:
+the forward solves cold, its evaluation order keyed by a guess of the solution).  Results are cached in a JSON file
 keyed by the mesh size class (override the path with GBP_TUNE_CACHE).
 """
 from __future__ import annotations
@@ -72,7 +74,9 @@ def _time(fn, repeats):
 def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, repeats=3,
          use_cache=True, save=True):
     """Pick and apply the fastest launch configuration; returns its record
-    (configuration, ms per forward[+backward], rounds, levels)."""
+    (configuration, ms per forward[+backward], rounds, levels).  Turns the plan's
+    warm order off (see tune_hold for the ordered warm start)."""
+    B.set_warm_order(plan, False)
     key = size_key(plan)
     db = _load() if use_cache else {}
     if use_cache and key in db:
@@ -110,26 +114,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
     B.set_queue_split(plan, best["split"])
     best.update(hold_delta=0.0, hold_window=0, hold_open=0)
     if space is None:
-        B.set_hold(plan, 0.0)
-        run()
-        fin = torch.isfinite(T)
-        rounds = max(B.last_counts(plan)["rounds"], 1)
-        span = float(T[fin].max() - T[fin].min()) if bool(fin.any()) else 0.0
-        unit = span / rounds                    # mean advance of the front per round
-        cap = best["sweep_blocks"] * (256 // best["lanes"])
-        for mult, window, frac in HOLD_SPACE:
-            if mult and not unit > 0:
-                continue
-            cfg = dict(hold_delta=mult * unit, hold_window=window,
-                       hold_open=(1 << 30) if frac is None else int(frac * cap))
-            B.set_hold(plan, cfg["hold_delta"], window, cfg["hold_open"])
-            run()
-            ms = _time(run, repeats)
-            if mult == 0:
-                best["ms"] = ms                 # the same configuration, timed again
-            elif ms < best["ms"]:
-                best.update(cfg, ms=ms)
-        B.set_hold(plan, best["hold_delta"], best["hold_window"], best["hold_open"])
+        best.update(tune_hold(plan, D, vscale, root_node, root_t, backward=backward, repeats=repeats))
     run()
     best.update(B.last_counts(plan))
     if save:
@@ -137,6 +122,46 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
         db[key] = best
         _save(db)
     return dict(best, cached=False)
+
+
+def tune_hold(plan: B.Plan, D, vscale, root_node, root_t, guess=None, backward=True, repeats=3):
+    """Search the hold-back (HOLD_SPACE) in the plan's current launch
+    configuration and apply the fastest; returns (hold_delta, hold_window,
+    hold_open, ms).  guess: time ordered warm forwards from it instead of cold
+    ones (the plan's warm order is left on; guess must not be the output)."""
+    ordered = guess is not None
+    gT = torch.ones(plan.n_v, dtype=torch.float32, device=D.device)
+    T = torch.empty(plan.n_v, dtype=torch.float32, device=D.device)
+    lanes, sweep_blocks = B.get_launch(plan)["lanes"], B.get_launch(plan)["sweep_blocks"]
+
+    def run():
+        B.eikonal_forward(plan, D, vscale, root_node, root_t, T_init=guess, out=T)
+        if backward:
+            B.eikonal_backward(plan, D, vscale, root_node, root_t, T, gT, want_D=False)
+
+    B.set_warm_order(plan, False)
+    B.set_hold(plan, 0.0)
+    B.eikonal_forward(plan, D, vscale, root_node, root_t, out=T)
+    fin = torch.isfinite(T)
+    rounds = max(B.last_counts(plan)["rounds"], 1)
+    span = float(T[fin].max() - T[fin].min()) if bool(fin.any()) else 0.0
+    unit = span / rounds                        # mean advance of the front per round
+    cap = sweep_blocks * (256 // lanes)
+    B.set_warm_order(plan, ordered)
+    best = None
+    for mult, window, frac in HOLD_SPACE:
+        if mult and not unit > 0:
+            continue
+        cfg = dict(hold_delta=mult * unit, hold_window=window,
+                   hold_open=(1 << 30) if frac is None else int(frac * cap))
+        B.set_hold(plan, cfg["hold_delta"], window, cfg["hold_open"])
+        run()
+        ms = _time(run, repeats)
+        if best is None or ms < best["ms"]:
+            best = dict(cfg, ms=ms)
+    B.set_hold(plan, best["hold_delta"], best["hold_window"], best["hold_open"])
+    run()
+    return best
 
 
 def budgets(plan: B.Plan, margin=1.25, extra=16, gs=32):

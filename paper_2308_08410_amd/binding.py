@@ -100,6 +100,8 @@ _forward_work = _sig("gbp_plan_forward_work", [c_void_p, c_void_p, c_void_p, c_v
 _set_hold = _sig("gbp_plan_set_hold", [c_void_p, c_float, c_int, c_int])
 _get_hold = _sig("gbp_plan_get_hold", [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int),
                                        ctypes.POINTER(c_int)])
+_set_warm_order = _sig("gbp_plan_set_warm_order", [c_void_p, c_int])
+_get_warm_order = _sig("gbp_plan_get_warm_order", [c_void_p, ctypes.POINTER(c_int)])
 _set_launch = _sig("gbp_plan_set_launch", [c_void_p, c_int, c_int, c_int, c_int])
 _get_launch = _sig("gbp_plan_get_launch", [c_void_p] + [ctypes.POINTER(c_int)] * 4)
 _set_split = _sig("gbp_plan_set_queue_split", [c_void_p, c_int])
@@ -526,6 +528,18 @@ def get_hold(plan: Plan):
     d, w, o = c_float(), c_int(), c_int()
     _check(_get_hold(plan.handle, ctypes.byref(d), ctypes.byref(w), ctypes.byref(o)))
     return d.value, w.value, o.value
+
+
+def set_warm_order(plan: Plan, on: bool):
+    """gbp_plan_set_warm_order: with on, a forward's T_init only orders the
+    hold-back of a cold solve instead of seeding the two-sided update."""
+    _check(_set_warm_order(plan.handle, 1 if on else 0))
+
+
+def get_warm_order(plan: Plan) -> bool:
+    v = c_int()
+    _check(_get_warm_order(plan.handle, ctypes.byref(v)))
+    return bool(v.value)
 
 
 def set_launch(plan: Plan, lanes=16, sweep_blocks=2048, level_blocks=2048, sync_batch=16):

@@ -180,11 +180,13 @@ __global__ void k_reduce_stats(const unsigned long long* __restrict__ blk, GbpCt
 // +inf, and T: +inf (T_init null, a cold start) or T_init (NaN read as +inf);
 // the queue marks are cleared when the control reset restarted the stamps.
 // only_T: T alone (the scales and onsets of the last preparation are kept).
+// G_init non-null: copied (NaN read as +inf) into guess, the hold-back's ordering key.
 __global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __restrict__ T_init,
                             const int* __restrict__ node_user, float* __restrict__ vs,
                             float* __restrict__ troot, float* __restrict__ T,
                             int* __restrict__ mark, int n_v, int only_T, GbpCtl* ctl,
-                            int* __restrict__ hold) {
+                            int* __restrict__ hold, const float* __restrict__ G_init,
+                            float* __restrict__ guess) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_v) return;
     if (ctl->marks_stale) mark[i] = 0;   // the stamps restarted from 1
@@ -208,6 +210,10 @@ __global__ void k_vertex_in(const float* __restrict__ vs_user, const float* __re
         if (t != t) t = GBP_INF;
     }
     T[i] = t;
+    if (G_init) {
+        const float gv = G_init[u];
+        guess[i] = gv == gv ? gv : GBP_INF;
+    }
 }
 
 // Per element: M = D_eff^{-1} = D^{-1} / sbar^2 and G = F^T M F (F: edges from v0).
@@ -411,10 +417,15 @@ __device__ __forceinline__ float face_value(const int* __restrict__ nent,
 // the queue shorter than open_below (the rest of the current bucket's tail, too
 // short to fill the grid) also opens the next non-empty bucket: every listed vertex
 // whose value has not dropped below that bucket pushes its neighbours (values
-// beyond the ring's last bucket wait there).  Only the order
-// of the relaxation changes (every held vertex is released before the solve
-// ends), so the fixed point is the same; a vertex that finds its bucket's list
-// full pushes at once.
+// beyond the ring's last bucket wait there).  With a guess of the solution
+// (guess non-null) the evaluation waits instead: a changed vertex pushes its
+// neighbours at once, but a neighbour whose guess lies beyond the window goes to
+// its guess's bucket list, not the queue, and is queued once that bucket opens,
+// when its upwind neighbours (smaller guesses) have had their turn; with a good
+// guess most vertices are evaluated about once.  Only the order of the
+// relaxation changes (every held vertex is released before the solve ends), so
+// the fixed point is the same for any guess; a vertex that finds its bucket's
+// list full is pushed (or queued) at once.
 struct HoldArgs {
     int* hold;          // [n_v] bucket a vertex was last appended to
     int* blist;         // [kHoldBuckets * bcap]
@@ -422,10 +433,37 @@ struct HoldArgs {
     float inv_delta;
     int open_below;     // open the next bucket once the queue is shorter than this
     int window;         // buckets past the current one that propagate at once (>= 0)
+    const float* guess; // [n_v] ordering guess (internal order) or null
 };
 
 __device__ __forceinline__ int bucket_of(float t, float tmin, float inv_delta) {
     return (int)fminf(floorf((t - tmin) * inv_delta), (float)(1 << 30));
+}
+
+constexpr int kHoldStage = 1024;   // held vertices staged per block in LDS
+
+// List vertex v in bucket b (once: a vertex already listed there is left alone).
+// Staged in the block's LDS (the block reserves list room per ring slot at its
+// end: one global atomic per slot, not per vertex), else appended directly.
+// False: the list is full (the caller pushes at once).
+__device__ __forceinline__ bool hold_list(int v, int b, const HoldArgs& ha, GbpCtl* ctl,
+                                          int* hold_v, unsigned char* hold_s, int* hold_n) {
+    if (ha.hold[v] == b) return true;
+    const int slot = b & (kHoldBuckets - 1);
+    const int hp = atomicAdd(hold_n, 1);
+    if (hp < kHoldStage) {
+        hold_v[hp] = v;
+        hold_s[hp] = (unsigned char)slot;
+        ha.hold[v] = b;
+        return true;
+    }
+    const int pos = atomicAdd(&ctl->bcnt[slot], 1);
+    if (pos < ha.bcap) {
+        ha.blist[(size_t)slot * ha.bcap + pos] = v;
+        ha.hold[v] = b;
+        return true;
+    }
+    return false;
 }
 
 template <bool TWO_SIDED, int L, int SOLVER, bool HOLD>
@@ -501,11 +539,13 @@ __global__ void __launch_bounds__(TPB)
     __shared__ int push_q[CAP];
     __shared__ int push_n, push_cnt[8], push_base[8];
     // held vertices staged per block (HOLD): vertex, ring slot
-    constexpr int kHoldStage = HOLD ? 1024 : 1;
-    __shared__ int hold_v[kHoldStage];
-    __shared__ unsigned char hold_s[kHoldStage];
+    __shared__ int hold_v[HOLD ? kHoldStage : 1];
+    __shared__ unsigned char hold_s[HOLD ? kHoldStage : 1];
     __shared__ int hold_n, hold_cnt[HOLD ? kHoldBuckets : 1], hold_base[HOLD ? kHoldBuckets : 1];
-    const bool have_open = HOLD && bopen >= 0 && (int)blockIdx.x * PER_BLOCK < nopen;
+    // an opening takes one lane group per listed vertex (its neighbours are pushed),
+    // or one thread (ordered: the vertex itself is queued)
+    const int open_per_block = HOLD && ha.guess ? TPB : PER_BLOCK;
+    const bool have_open = HOLD && bopen >= 0 && (int)blockIdx.x * open_per_block < nopen;
     if (lb * PER_BLOCK >= n && !have_open) return;   // no vertex for this block
     if (threadIdx.x == 0) {
         push_n = 0;
@@ -580,49 +620,52 @@ __global__ void __launch_bounds__(TPB)
         }
         if (changed) {
             if (lane == 0) ++upd;
+            // hold-back: the bucket opened by this round, if any, counts as current;
+            // lists go to buckets after it, up to the ring's last (blast)
+            int bce = 0, blast = 0;
+            bool can_hold = false;
             if constexpr (HOLD) {
-                // the bucket opened by this round, if any, counts as current; the
-                // ring's slot of the old current bucket is being cleared: skip it
-                const int bce = (bopen >= 0 ? bopen : bc) + ha.window;
+                bce = (bopen >= 0 ? bopen : bc) + ha.window;
+                blast = bc + kHoldBuckets - 1;
+                can_hold = max(bopen, bc) < blast;
+            }
+            if (HOLD && !ha.guess) {
                 int b = bucket_of(best, tmin, ha.inv_delta);
-                if (b > bce) {   // beyond the window: wait in b's list
-                    b = min(b, bc + kHoldBuckets - 1);
+                if (b > bce && can_hold) {   // beyond the window: wait in b's list
+                    b = min(b, blast);
                     int ok = 0;
-                    if (lane == 0) {
-                        if (ha.hold[i] == b) {
-                            ok = 1;
-                        } else {
-                            // staged in LDS; the block reserves list room per bucket at
-                            // the end (one global atomic per bucket, not per vertex)
-                            const int hp = atomicAdd(&hold_n, 1);
-                            if (hp < kHoldStage) {
-                                hold_v[hp] = i;
-                                hold_s[hp] = (unsigned char)(b & (kHoldBuckets - 1));
-                                ha.hold[i] = b;
-                                ok = 1;
-                            } else {
-                                const int slot = b & (kHoldBuckets - 1);
-                                const int pos = atomicAdd(&ctl->bcnt[slot], 1);
-                                if (pos < ha.bcap) {
-                                    ha.blist[(size_t)slot * ha.bcap + pos] = i;
-                                    ha.hold[i] = b;
-                                    ok = 1;
-                                }
-                            }
-                        }
-                    }
+                    if (lane == 0) ok = hold_list(i, b, ha, ctl, hold_v, hold_s, &hold_n) ? 1 : 0;
                     if (__shfl(ok, (threadIdx.x & 63) & ~(L - 1))) continue;
                 }
             }
             for (int a = adj0 + lane; a < adj1; a += L) {
                 const int nb = adj[a];
+                if (HOLD && ha.guess) {
+                    // ordered: a neighbour whose guess is beyond the window waits
+                    const float gn = ha.guess[nb];
+                    if (atomicMax(&mark[nb], stamp_next) < stamp_next) {
+                        const int b = bucket_of(gn, tmin, ha.inv_delta);
+                        if (b <= bce || !can_hold ||
+                            !hold_list(nb, min(b, blast), ha, ctl, hold_v, hold_s, &hold_n))
+                            xpush_node<false>(pb, nb, xq, qout, cnt_next);
+                    }
+                    continue;
+                }
                 if (atomicMax(&mark[nb], stamp_next) < stamp_next)
                     xpush_node<TWO_SIDED>(pb, nb, xq, qout, cnt_next);
             }
         }
     }
     if constexpr (HOLD) {
-        if (have_open) {
+        if (have_open && ha.guess) {
+            // ordered: open bucket bopen by queueing every vertex still listed in it
+            const int* lst = ha.blist + (size_t)(bopen & (kHoldBuckets - 1)) * ha.bcap;
+            for (int qi = blockIdx.x * TPB + threadIdx.x; qi < nopen; qi += gridDim.x * TPB) {
+                const int v = lst[qi];
+                if (ha.hold[v] == bopen && atomicMax(&mark[v], stamp_next) < stamp_next)
+                    xpush_node<true>(pb, v, xq, qout, cnt_next);
+            }
+        } else if (have_open) {
             // open bucket bopen: every listed vertex not below it pushes its neighbours
             const int* lst = ha.blist + (size_t)(bopen & (kHoldBuckets - 1)) * ha.bcap;
             for (int qi = blockIdx.x * PER_BLOCK + sub; qi < nopen; qi += gridDim.x * PER_BLOCK) {
@@ -658,6 +701,9 @@ __global__ void __launch_bounds__(TPB)
             const int pos = hold_base[sl] + atomicAdd(&hold_cnt[sl], 1);
             if (pos < ha.bcap) {
                 ha.blist[(size_t)sl * ha.bcap + pos] = v;
+            } else if (ha.guess) {
+                ha.hold[v] = INT_MIN;   // its list is full: queued now (claimed this round)
+                xpush_node<true>(pb, v, xq, qout, cnt_next);
             } else {
                 ha.hold[v] = INT_MIN;
                 for (int a = adj_ptr[v]; a < adj_ptr[v + 1]; ++a) {
@@ -1546,10 +1592,11 @@ static int check_roots(const float* D, const int32_t* root_node, const float* ro
 }
 
 // Control reset, metric, onsets and (cold == 1) +inf start with the roots' neighbours
-// queued, (cold == 0) T from T_init.  Enqueue only; no synchronisation.
+// queued, (cold == 0) T from T_init.  G_init (cold == 1 only): the hold-back's
+// ordering guess.  Enqueue only; no synchronisation.
 static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_t* root_node,
                    const float* root_t, int n_roots, int cold, const float* T_init,
-                   hipStream_t s) {
+                   hipStream_t s, const float* G_init = nullptr) {
     const int n_v = p->n_v, n_e = p->n_e;
     // A backward (cold == 2) may keep the element metric, scales and onsets of the
     // last full preparation when the caller allows it (gbp_plan_set_input_reuse)
@@ -1563,7 +1610,8 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
                                                      p->node_user, p->vs, p->troot, p->T, p->mark,
                                                      n_v, keep ? 1 : 0, p->ctl,
                                                      cold == 1 && p->hold_delta > 0.f ? p->hold
-                                                                                      : nullptr);
+                                                                                      : nullptr,
+                                                     G_init, p->guess);
     if (keep) {
         GBP_LAUNCH_CHECK();
         return GBP_OK;
@@ -1589,14 +1637,15 @@ static int prepare(gbp_plan p, const float* D, const float* vscale, const int32_
     return GBP_OK;
 }
 
-static void launch_round(gbp_plan p, bool cold, int r, hipStream_t s, int* st = nullptr) {
+static void launch_round(gbp_plan p, bool cold, bool ordered, int r, hipStream_t s,
+                         int* st = nullptr) {
     const int* qin = p->q[r & 1];
     int* qout = p->q[(r + 1) & 1];
     const int grid = std::min(p->sweep_blocks, kStatBlocks);
     ProfScope ps(GBP_PROF_FIM_SWEEP, s);
     const int open_below = p->hold_open > 0 ? p->hold_open : grid * (TPB / p->lanes) / 2;
     const HoldArgs ha{p->hold, p->blist, p->bcap, p->hold_delta > 0.f ? 1.f / p->hold_delta : 0.f,
-                      open_below, p->hold_window};
+                      open_below, p->hold_window, ordered ? p->guess : nullptr};
     const bool hold = cold && p->hold_delta > 0.f;
 #define GBP_SWEEP(TS, LN, SV, HD)                                                                  \
     k_sweep<TS, LN, SV, HD><<<grid, TPB, 0, s>>>(p->nptr, p->nent, p->tetv, p->tetg, p->troot,    \
@@ -1632,8 +1681,12 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
     int rc = check_roots(D, root_node, root_t, n_roots);
     if (rc) return rc;
     const int n_v = p->n_v;
-    const bool cold = (T_init == nullptr);
-    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, T_init, s))) return rc;
+    // ordered warm start: T_init orders the hold-back of a cold solve
+    const bool ordered = T_init && p->warm_order && p->hold_delta > 0.f;
+    const bool cold = !T_init || p->warm_order;
+    if ((rc = prepare(p, D, vscale, root_node, root_t, n_roots, cold ? 1 : 0, cold ? nullptr : T_init,
+                      s, ordered ? T_init : nullptr)))
+        return rc;
     k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
     if (!cold)
         k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, n_v, p->ctl, p->xq);
@@ -1641,10 +1694,10 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
     int r = 0;
     bool converged = true;
     if (budget > 0) {
-        for (; r < budget; ++r) launch_round(p, cold, r, s);
+        for (; r < budget; ++r) launch_round(p, cold, ordered, r, s);
     } else {
         rc = run_pipelined(
-            p, s, p->max_rounds, true, [&](int k, int* st) { launch_round(p, cold, k, s, st); },
+            p, s, p->max_rounds, true, [&](int k, int* st) { launch_round(p, cold, ordered, k, s, st); },
             r, converged);
         if (rc) {
             k_forward_end<<<1, 64, 0, s>>>(p->ctl, r);   // stamps used so far stay retired

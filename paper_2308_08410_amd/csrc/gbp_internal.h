@@ -119,6 +119,8 @@ struct gbp_plan_s {
     int* hold = nullptr;          // [n_v] bucket a vertex was last held in (allocated on use)
     int* blist = nullptr;         // [kHoldBuckets * bcap] held vertices per ring slot
     int bcap = 0;                 // entries per ring slot
+    int warm_order = 0;           // 1: a forward's T_init only orders the hold-back of a cold solve
+    float* guess = nullptr;       // [n_v] that ordering guess (internal order, allocated on use)
     // inputs of the last full preparation (element metric, scales, onsets): a
     // backward may reuse them when the caller allows it and passes the same arrays
     int reuse_inputs = 0;

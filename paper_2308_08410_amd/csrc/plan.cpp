@@ -77,7 +77,7 @@ static void plan_free(gbp_plan p) {
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
                     p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp, p->lip,
-                    p->pnode, p->partner, p->pairrem, p->hold, p->blist};
+                    p->pnode, p->partner, p->pairrem, p->hold, p->blist, p->guess};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -452,6 +452,25 @@ extern "C" int gbp_plan_set_hold(gbp_plan p, float delta, int window, int open_b
             return rc;
     }
     p->hold_delta = delta;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_set_warm_order(gbp_plan p, int on) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (on != 0 && on != 1) {
+        gbp_set_error("set_warm_order: on must be 0 or 1 (got %d)", on);
+        return GBP_ERR_ARG;
+    }
+    if (on && !p->guess && (rc = dalloc(&p->guess, (size_t)p->n_v))) return rc;
+    p->warm_order = on;
+    return GBP_OK;
+}
+
+extern "C" int gbp_plan_get_warm_order(gbp_plan p, int* on) {
+    int rc = gbp_plan_check(p);
+    if (rc) return rc;
+    if (on) *on = p->warm_order;
     return GBP_OK;
 }
 

@@ -5,7 +5,8 @@ A small network (libgbp's gbp_mlp: 16 -> 4 x 256 ReLU -> 1, bf16 matrix-core
 kernels) predicts the activation time of every vertex from its position, fibre
 direction, the sorted per-root values |x - x_r| / L + t_r / T_s and the velocity
 scale.  The prediction seeds the two-sided solve (gbp_eikonal_forward with
-T_init), whose fixed point is the cold solution whatever the guess, so the
+T_init), or, with the plan's warm order on, orders a cold solve's hold-back;
+either way the fixed point is the cold solution whatever the guess, so the
 prediction can only change the work, never the answer; a solve that does not
 converge from the guess is redone cold.
 
@@ -166,19 +167,25 @@ def _timed(fn):
 
 def evaluate(ws: WarmStart, plan, D, cases, repeats=3):
     """Per held-out case: cold solve, warm solve from the network's guess (time
-    includes the prediction) and from the geometric guess; work counters,
-    times, guess errors and the warm-vs-cold difference."""
+    includes the prediction; two-sided, and ordered: a cold solve whose hold-back
+    is keyed by the guess, in the plan's hold-back setting) and from the geometric
+    guess; work counters, times, guess errors and the warm-vs-cold difference."""
     rows = []
+    order0 = B.get_warm_order(plan)
     for d in cases:
         args = (plan, D, d["vscale"], d["root_node"], d["root_t"])
         best = {}
         for _ in range(repeats):
             (Tc, sc), tc = _timed(lambda: B.eikonal_forward(*args))
+            B.set_warm_order(plan, False)
             (Tw, sw), tw = _timed(lambda: ws.forward(*args))
+            B.set_warm_order(plan, True)
+            (To, so), to = _timed(lambda: ws.forward(*args))
+            B.set_warm_order(plan, order0)
             guess_m, tp = _timed(lambda: ws.predict(d["root_node"], d["root_t"], d["vscale"]))
             guess_g = geometric_guess(ws, d["root_node"], d["root_t"])
             (Tg, sg), tg = _timed(lambda: B.eikonal_forward(*args, T_init=guess_g))
-            for k, v in (("cold_ms", tc), ("warm_ms", tw), ("predict_ms", tp), ("geo_ms", tg)):
+            for k, v in (("cold_ms", tc), ("warm_ms", tw), ("ordered_ms", to), ("predict_ms", tp), ("geo_ms", tg)):
                 best[k] = min(best.get(k, v), v)
         fin = torch.isfinite(Tc)
         scale = float(Tc[fin].abs().max())
@@ -188,11 +195,14 @@ def evaluate(ws: WarmStart, plan, D, cases, repeats=3):
             cold=dict(rounds=sc["rounds"], face_solves=sc["face_solves"], node_updates=sc["node_updates"]),
             warm_mlp=dict(rounds=sw["rounds"], face_solves=sw["face_solves"],
                           node_updates=sw["node_updates"], fallback=sw["fallback"]),
+            warm_mlp_ordered=dict(rounds=so["rounds"], face_solves=so["face_solves"],
+                                  node_updates=so["node_updates"]),
             warm_geo=dict(rounds=sg["rounds"], face_solves=sg["face_solves"], node_updates=sg["node_updates"]),
             guess_rel_l2=dict(mlp=rel(guess_m), geo=rel(guess_g)),
             guess_max_abs_ms=dict(mlp=float((guess_m[fin] - Tc[fin]).abs().max()),
                                   geo=float((guess_g[fin] - Tc[fin]).abs().max())),
             warm_vs_cold_rel_max=dict(mlp=float((Tw[fin] - Tc[fin]).abs().max()) / scale,
+                                      mlp_ordered=float((To[fin] - Tc[fin]).abs().max()) / scale,
                                       geo=float((Tg[fin] - Tc[fin]).abs().max()) / scale),
             **best))
     return rows

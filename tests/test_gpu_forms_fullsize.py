@@ -128,8 +128,10 @@ def batched():
     return st
 
 
-@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("warm", ["cold", "two-sided", "ordered"])
 def test_batched_step_matches_oracle(batched, warm):
+    """Cold, warm-started (two-sided) and ordered (a cold solve keyed by the
+    guess) forwards in the captured step; the warm forms from a far guess."""
     from paper_2308_08410_amd import autotune
     b = batched
     plan, D, W, rn, dev = b["plan"], b["D"], b["W"], b["rn"], b["dev"]
@@ -138,14 +140,23 @@ def test_batched_step_matches_oracle(batched, warm):
     T = torch.empty(b["n_v"], dtype=torch.float32, device=dev)
     B().eikonal_forward(plan, D, vs, rn, rt, out=T)
     B().eikonal_backward(plan, D, vs, rn, rt, T, torch.ones_like(T), want_D=False)
-    bud = autotune.budgets(plan, margin=2.0 if warm else 1.5, extra=64 if warm else 32)
-    if warm:
+    if warm != "cold":
         # a far guess: the times of the hidden parameters
-        B().eikonal_forward(plan, D, b["vs_true"], rn, b["rt_true"], out=T)
+        G = torch.empty_like(T)
+        B().eikonal_forward(plan, D, b["vs_true"], rn, b["rt_true"], out=G)
+        if warm == "ordered":
+            B().set_warm_order(plan, True)
+            B().eikonal_forward(plan, D, vs, rn, rt, T_init=G, out=T)   # sizes the budgets
+        T.copy_(G)
+    bud = autotune.budgets(plan, margin=1.5 if warm == "cold" else 2.0, extra=32 if warm == "cold" else 64)
     ecg = torch.empty((len(b["wl"].mesh_of), b["S"], b["L"]), dtype=torch.float32, device=dev)
     loss = torch.empty(len(b["wl"].mesh_of), dtype=torch.float32, device=dev)
     print(f"[case] batched step warm={warm} budgets {bud}", flush=True)
-    step = B().Step(plan, b["batch"], D, vs, rn, rt, W, b["ap"], b["target"], T, ecg, loss, warm=warm, **bud)
+    try:
+        step = B().Step(plan, b["batch"], D, vs, rn, rt, W, b["ap"], b["target"], T, ecg, loss,
+                        warm=warm != "cold", **bud)
+    finally:
+        B().set_warm_order(plan, False)      # recorded into the step's graph already
     step.launch()
     status = B().plan_status(plan)
     assert status["err"] == 0 and status["forward_converged"] and status["backward_settled"], status

@@ -575,6 +575,54 @@ def test_hold_back_async_and_duplicate_roots():
     assert not B().plan_status(plan)["forward_converged"]
 
 
+@pytest.mark.parametrize("lanes,split", [(16, True), (8, False)])
+def test_ordered_warm_start_reaches_the_oracle(shell, lanes, split):
+    """The ordered warm start (a cold solve whose hold-back keys the evaluation
+    of pushed vertices by a guess of the solution) reaches the oracle's fixed
+    point from exact, perturbed, far, too low (all zero), all +inf and NaN-holed
+    guesses, for bucket widths from a fraction of an edge's travel time to many;
+    the guess may alias the output.  With the hold-back off the guess is ignored
+    and the solve is the plain cold one."""
+    dev = _dev()
+    c = shell
+    plan = c.plan
+    To = c.T_orc
+    r = np.random.Generator(np.random.PCG64(12))
+    holes = To.copy()
+    holes[r.random(len(To)) < 0.1] = np.nan
+    guesses = {"exact": To, "perturbed": To * (1 + 0.05 * r.uniform(-1, 1, len(To))), "far": 1.7 * To + 3.0,
+               "zero": np.zeros_like(To), "inf": np.full_like(To, np.inf), "nan holes": holes}
+    saved = B().get_launch(plan)
+    B().set_launch(plan, lanes, 1024, saved["level_blocks"], 16)
+    B().set_queue_split(plan, split)
+    try:
+        _, st0 = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt)
+        assert not B().get_warm_order(plan)
+        B().set_warm_order(plan, True)
+        assert B().get_warm_order(plan)
+        for delta, window, open_below in ((0.5, 0, 1 << 30), (2.0, 0, 0), (0.05, 0, 0), (1.0, 2, 1 << 30)):
+            B().set_hold(plan, delta, window, open_below)
+            for name, g in guesses.items():
+                print(f"[case] ordered warm start from {name} guess, hold {delta}/{window}/{open_below}, "
+                      f"lanes={lanes} split={split}", flush=True)
+                G = t32(g, dev)
+                T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt, T_init=G, out=G)
+                assert st["converged"] and st["unreached"] == 0
+                assert rel_max(T.cpu().numpy(), To) <= 1e-4
+                print(f"[ordered] {name}: {st['rounds']} rounds, {st['face_solves']} local problems (cold "
+                      f"{st0['rounds']}, {st0['face_solves']})", flush=True)
+        B().set_hold(plan, 0.0)
+        T, st = B().eikonal_forward(plan, c.D, c.vs, c.rn, c.rt, T_init=t32(guesses["far"], dev))
+        assert st["converged"] and rel_max(T.cpu().numpy(), To) <= 1e-4
+        assert st["face_solves"] < 2 * st0["face_solves"]       # not the two-sided update's work
+        assert B()._set_warm_order(plan.handle, 2) == -1          # GBP_ERR_ARG
+    finally:
+        B().set_warm_order(plan, False)
+        B().set_hold(plan, 0.0)
+        B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
+        B().set_queue_split(plan, True)
+
+
 def test_async_forward_and_backward(shell):
     """The enqueue-only forward and backward (fixed budgets, no synchronisation)
     give the synchronous calls' results; a budget that is too small and an input
