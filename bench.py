@@ -64,7 +64,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0   # dense bf16 matrix-core peak
 
 
-FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched", "learned")
+FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched", "learned", "inverse")
 
 
 def parse():
@@ -533,6 +533,42 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
     return out
 
 
+def inverse_form(dev, torch, gi, B, iters=20, n_nodes=1_000_000, starts=16, seed=5):
+    """The inverse problem (Sec. 2.4 Eq. (inverse_ecg)) as the multi-start fit:
+    `starts` fits of the 1M-vertex shell (8 roots, hidden smooth scale in
+    [0.5, 1.5]) as the instances of one union plan, every iteration one replay of
+    the captured step (cold forwards) for all starts; timed over `iters`
+    iterations after two untimed ones, the misfit of every start before and after."""
+    import numpy as np
+    from paper_2308_08410_amd.inverse import MultiStartFit
+    t0 = time.time()
+    p, vs_true, rt0 = gi.multistart_workload(n_nodes, starts, 8, seed)
+    a = p.ap
+    f32 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float32), device=dev)
+    plan1 = B.Plan(p.xyz, p.tets)
+    T_true, _ = B.eikonal_forward(plan1, f32(p.D), f32(vs_true), torch.as_tensor(p.root_node, device=dev),
+                                  f32(p.root_t))
+    apc = B.make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])
+    target = B.ecg_forward(T_true, f32(p.W), apc).cpu().numpy()
+    plan1.close()
+    vs0 = [np.ones(p.n_v, np.float32) for _ in range(starts)]
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0)
+    t_setup = time.time() - t0
+    fit.run(2, check_every=0)
+    loss0 = fit.loss.detach().cpu().numpy().copy()
+    out = fit.run(iters, check_every=iters)
+    loss1 = fit.loss.detach().cpu().numpy().copy()
+    st = B.plan_status(fit.plan)
+    res = dict(nodes=int(p.n_v), tets=int(p.n_e), starts=starts, union_vertices=int(fit.voff[-1]),
+               iters=iters, iters_per_s=out["iters_per_s"], start_iters_per_s=out["iters_per_s"] * starts,
+               ms_per_iter=1000.0 / out["iters_per_s"], setup_s=t_setup, budgets=fit.budgets,
+               loss_after_2=[float(x) for x in loss0], loss_after_last=[float(x) for x in loss1],
+               converged=bool(st["forward_converged"] and st["backward_settled"] and st["err"] == 0))
+    fit.step.close()
+    fit.plan.close()
+    return res
+
+
 def host_info():
     """CPU model and logical core count of the host this runs on."""
     model = None
@@ -609,6 +645,7 @@ def main():
         print("bench.py measures one GPU: there is no multi-GPU path (the solve of one mesh runs on "
               "one MI355X). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     import gbp_inputs as gi
     from paper_2308_08410_amd import binding as B
@@ -803,6 +840,14 @@ def main():
             f"rounds {lf['rounds']['warm_mlp']:.0f} vs {lf['rounds']['cold']:.0f}; ordered "
             f"{lf['ms']['warm_mlp_ordered_incl_prediction']:.2f} ms, local problems "
             f"x{lf['local_problems']['warm_mlp_ordered'] / lf['local_problems']['cold']:.2f} ({time.time() - t:.1f}s)")
+    if "inverse" in forms:
+        t = time.time()
+        inv = inverse_form(dev, torch, gi, B)
+        detail["inverse_multistart_1m"] = inv
+        log(f"[bench] inverse problem, {inv['starts']} starts x {inv['nodes']} vertices: "
+            f"{inv['iters_per_s']:.2f} iter/s ({inv['start_iters_per_s']:.1f} start-iter/s), misfit "
+            f"{np.mean(inv['loss_after_2']):.3g} -> {np.mean(inv['loss_after_last']):.3g} over {inv['iters']} "
+            f"iterations, within budgets {inv['converged']} (setup {inv['setup_s']:.1f}s, {time.time() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()

@@ -313,8 +313,12 @@ int gbp_lead_field(gbp_plan plan, const float *electrodes, int n_leads, float *W
  * gbp_tri_backward -- vector-Jacobian product along the FP64 geodesic parents:
  *   dL_dD [n_t*3] (off-diagonal doubled) / dL_dvscale [n_v] / dL_droot_t
  *   [n_roots], each may be NULL; the formulas of gbp_eikonal_backward with
- *   d sbar / d s = 1/3.  The adjoint sweeps to a relative change of 1e-7.
- *   Errors: as gbp_eikonal_backward.
+ *   d sbar / d s = 1/3.  The adjoint is the leaves-first level walk of
+ *   gbp_eikonal_backward (each vertex finished once its children are, in a
+ *   fixed order); vertices that parent-graph cycles leave unfinished take Jacobi
+ *   sweeps to a relative change of 1e-7.  Errors: as gbp_eikonal_backward.
+ * gbp_tri_backward_info -- the last backward's level count, the vertices the
+ *   walk left to the sweeps, and the sweeps taken (any pointer may be NULL).
  */
 typedef struct gbp_tri_plan_s *gbp_tri_plan;
 int gbp_tri_plan_create(const float *xy, int n_v, const int32_t *tris, int n_t, gbp_tri_plan *out);
@@ -325,6 +329,7 @@ int gbp_tri_backward(gbp_tri_plan plan, const float *D, const float *vscale,
                      const int32_t *root_node, const float *root_t, int n_roots, const float *T,
                      const float *dL_dT, float *dL_dD, float *dL_dvscale, float *dL_droot_t,
                      void *stream);
+int gbp_tri_backward_info(gbp_tri_plan plan, int *levels, int *cyclic, int *sweeps);
 
 /*
  * gbp_point_roots -- initial conditions at points inside elements (Sec. 2.3
@@ -633,6 +638,22 @@ int gbp_step_gradients(gbp_step step, float *dL_dT, float *dL_dvscale, float *dL
                        void *stream);
 
 /*
+ * gbp_step_get_state / gbp_step_set_state -- the fit's optimiser state that a
+ * step owns (Adam's first and second moments of the velocity scales and of the
+ * onsets, and the Adam step counter, Sec. 2.4), for checkpointing and resuming
+ * a fit: a step created from the same parameters, given the state saved after
+ * iteration k, continues with iteration k + 1.
+ *   m_vscale, v_vscale  device float [n_v]
+ *   m_root_t, v_root_t  device float [n_roots] (ignored when n_roots == 0)
+ *   counter             host int: the next update's index (>= 1; 1 before any)
+ * Synchronous on `stream`.  Errors: GBP_ERR_ARG (NULL buffer, counter < 1).
+ */
+int gbp_step_get_state(gbp_step step, float *m_vscale, float *v_vscale, float *m_root_t,
+                       float *v_root_t, int *counter, void *stream);
+int gbp_step_set_state(gbp_step step, const float *m_vscale, const float *v_vscale,
+                       const float *m_root_t, const float *v_root_t, int counter, void *stream);
+
+/*
  * Learned warm start (an extension beyond the paper, which solves every
  * forward from scratch): a multilayer perceptron 16 -> 256 -> 256 -> 256 -> 256
  * -> 1 with ReLU activations predicts activation times from per-vertex
@@ -676,6 +697,10 @@ int gbp_step_gradients(gbp_step step, float *dL_dT, float *dL_dvscale, float *dL
  * gbp_mlp_train_step: gbp_mlp_gradient followed by one Adam step (beta 0.9,
  *   0.999, eps 1e-8, bias-corrected) with learning rate lr on the fp32 masters
  *   and a refresh of their bf16 copies.
+ * gbp_mlp_get_state / gbp_mlp_set_state: host fp32 copies of Adam's moments
+ *   (gbp_mlp_num_params entries each) and the number of Adam steps taken, for
+ *   checkpointing and resuming training (with gbp_mlp_get/set_params);
+ *   synchronous on `stream`.  Errors: GBP_ERR_ARG (NULL buffer, step < 0).
  * All calls on one network are stream-ordered and must not overlap.
  */
 typedef struct gbp_mlp_s *gbp_mlp;
@@ -684,6 +709,8 @@ void gbp_mlp_destroy(gbp_mlp mlp);
 int gbp_mlp_num_params(gbp_mlp mlp);
 int gbp_mlp_set_params(gbp_mlp mlp, const float *params, void *stream);
 int gbp_mlp_get_params(gbp_mlp mlp, float *params, float *grads, void *stream);
+int gbp_mlp_get_state(gbp_mlp mlp, float *m, float *v, int *step, void *stream);
+int gbp_mlp_set_state(gbp_mlp mlp, const float *m, const float *v, int step, void *stream);
 int gbp_mlp_features(const float *xyz, const float *fibre, const float *vscale, int n_v,
                      const int32_t *rows, int n_rows, const float *root_xyz,
                      const float *root_t, int n_roots, const float *norm, const float *T,

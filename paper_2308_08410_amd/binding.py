@@ -119,6 +119,10 @@ _step_create = _sig("gbp_step_create", [c_void_p, ctypes.POINTER(c_void_p)])
 _step_launch = _sig("gbp_step_launch", [c_void_p, c_void_p])
 _step_destroy = _sig("gbp_step_destroy", [c_void_p], None)
 _step_gradients = _sig("gbp_step_gradients", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_step_get_state = _sig("gbp_step_get_state", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                               ctypes.POINTER(c_int), c_void_p])
+_step_set_state = _sig("gbp_step_set_state", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                               c_void_p])
 _point_roots = _sig("gbp_point_roots", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                         c_void_p, c_void_p, c_void_p])
 _point_roots_bwd = _sig("gbp_point_roots_backward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
@@ -141,6 +145,7 @@ _tri_forward = _sig("gbp_tri_forward", [c_void_p, c_void_p, c_void_p, c_void_p, 
                                         ctypes.POINTER(Stats), c_void_p])
 _tri_backward = _sig("gbp_tri_backward", [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p])
+_tri_backward_info = _sig("gbp_tri_backward_info", [c_void_p] + [ctypes.POINTER(c_int)] * 3)
 _last_error = _sig("gbp_last_error", [], ctypes.c_char_p)
 _version = _sig("gbp_version", [], ctypes.c_char_p)
 
@@ -395,6 +400,14 @@ def tri_backward(plan: TriPlan, D, vscale, root_node, root_t, T, dL_dT, want_D=T
                          _ptr(dt, torch.float32, (R,), "dL_droot_t"), _stream(stream)))
     return dD, dvs, dt
 
+
+
+def tri_backward_info(plan: TriPlan):
+    """The last triangle backward: adjoint levels, vertices left to the Jacobi
+    sweeps by parent-graph cycles, sweeps taken."""
+    v = [c_int() for _ in range(3)]
+    _check(_tri_backward_info(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(levels=v[0].value, cyclic=v[1].value, sweeps=v[2].value)
 
 def point_roots(plan: Plan, D, vscale, root_tet, root_xyz, root_t, stream=None):
     """Vertex roots of roots at points inside elements (Sec. 2.3 Eq. (upwind_xi)).
@@ -747,6 +760,29 @@ class Step:
         _check(_step_gradients(self._h, gT.data_ptr(), gv.data_ptr(), gr.data_ptr(), _stream(stream)))
         return gT, gv, gr[: self._R]
 
+    def get_state(self, stream=None):
+        """The fit's optimiser state (gbp_step_get_state): dict of device tensors
+        m_vscale, v_vscale, m_root_t, v_root_t and the int counter."""
+        f = lambda n: torch.empty(n, dtype=torch.float32, device=self._dev)
+        st = dict(m_vscale=f(self._n_v), v_vscale=f(self._n_v), m_root_t=f(max(self._R, 1)),
+                  v_root_t=f(max(self._R, 1)))
+        c = c_int()
+        _check(_step_get_state(self._h, *[st[k].data_ptr() for k in ("m_vscale", "v_vscale", "m_root_t",
+                                                                      "v_root_t")],
+                               ctypes.byref(c), _stream(stream)))
+        st["m_root_t"], st["v_root_t"] = st["m_root_t"][: self._R], st["v_root_t"][: self._R]
+        st["counter"] = c.value
+        return st
+
+    def set_state(self, state, stream=None):
+        """Restore a state from get_state (tensors or arrays of the same sizes)."""
+        t = lambda k, n: torch.as_tensor(np.asarray(state[k].cpu() if torch.is_tensor(state[k]) else state[k],
+                                                    np.float32), device=self._dev).reshape(n).contiguous()
+        mv, vv = t("m_vscale", self._n_v), t("v_vscale", self._n_v)
+        mr, vr = t("m_root_t", self._R), t("v_root_t", self._R)
+        _check(_step_set_state(self._h, mv.data_ptr(), vv.data_ptr(), mr.data_ptr() if self._R else None,
+                               vr.data_ptr() if self._R else None, int(state["counter"]), _stream(stream)))
+
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _step_destroy is not None:
@@ -766,6 +802,8 @@ _mlp_destroy = _sig("gbp_mlp_destroy", [c_void_p], None)
 _mlp_nparams = _sig("gbp_mlp_num_params", [c_void_p])
 _mlp_set = _sig("gbp_mlp_set_params", [c_void_p, c_void_p, c_void_p])
 _mlp_get = _sig("gbp_mlp_get_params", [c_void_p, c_void_p, c_void_p, c_void_p])
+_mlp_get_state = _sig("gbp_mlp_get_state", [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int), c_void_p])
+_mlp_set_state = _sig("gbp_mlp_set_state", [c_void_p, c_void_p, c_void_p, c_int, c_void_p])
 _mlp_features = _sig("gbp_mlp_features", [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p,
                                           c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p])
@@ -814,6 +852,21 @@ class MLP:
         if p.shape != (self.n_params,):
             raise ValueError(f"params must have shape ({self.n_params},)")
         _check(_mlp_set(self._h, p.ctypes.data, _stream(stream)))
+
+    def get_state(self, stream=None):
+        """Adam's moments and step count (gbp_mlp_get_state): dict m, v, step."""
+        m = np.empty(self.n_params, np.float32)
+        v = np.empty(self.n_params, np.float32)
+        k = c_int()
+        _check(_mlp_get_state(self._h, m.ctypes.data, v.ctypes.data, ctypes.byref(k), _stream(stream)))
+        return dict(m=m, v=v, step=k.value)
+
+    def set_state(self, state, stream=None):
+        m = np.ascontiguousarray(np.asarray(state["m"], np.float32))
+        v = np.ascontiguousarray(np.asarray(state["v"], np.float32))
+        if m.shape != (self.n_params,) or v.shape != (self.n_params,):
+            raise ValueError(f"moments must have shape ({self.n_params},)")
+        _check(_mlp_set_state(self._h, m.ctypes.data, v.ctypes.data, int(state["step"]), _stream(stream)))
 
     def forward(self, X, out_scale=1.0, out=None, stream=None):
         m = X.shape[0]

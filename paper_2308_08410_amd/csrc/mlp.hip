@@ -482,6 +482,33 @@ extern "C" int gbp_mlp_get_params(gbp_mlp p, float* host, float* grads_host, voi
     return GBP_OK;
 }
 
+extern "C" int gbp_mlp_get_state(gbp_mlp p, float* m_host, float* v_host, int* step, void* stream) {
+    if (!p || !m_host || !v_host || !step) {
+        gbp_set_error("mlp_get_state: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    GBP_HIP(hipMemcpyAsync(m_host, p->m, sizeof(float) * p->n_params, hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipMemcpyAsync(v_host, p->v, sizeof(float) * p->n_params, hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    *step = p->step;
+    return GBP_OK;
+}
+
+extern "C" int gbp_mlp_set_state(gbp_mlp p, const float* m_host, const float* v_host, int step,
+                                 void* stream) {
+    if (!p || !m_host || !v_host || step < 0) {
+        gbp_set_error("mlp_set_state: NULL argument or step < 0");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    GBP_HIP(hipMemcpyAsync(p->m, m_host, sizeof(float) * p->n_params, hipMemcpyHostToDevice, s));
+    GBP_HIP(hipMemcpyAsync(p->v, v_host, sizeof(float) * p->n_params, hipMemcpyHostToDevice, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    p->step = step;
+    return GBP_OK;
+}
+
 extern "C" int gbp_mlp_features(const float* xyz, const float* fibre, const float* vscale, int n_v,
                                 const int32_t* rows, int n_rows, const float* root_xyz,
                                 const float* root_t, int n_roots, const float* norm,

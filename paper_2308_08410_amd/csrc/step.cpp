@@ -156,6 +156,47 @@ extern "C" int gbp_step_gradients(gbp_step st, float* dL_dT, float* dL_dvscale, 
     return GBP_OK;
 }
 
+extern "C" int gbp_step_get_state(gbp_step st, float* m_vscale, float* v_vscale, float* m_root_t,
+                                  float* v_root_t, int* counter, void* stream) {
+    if (!st || !st->exec || !m_vscale || !v_vscale || !counter ||
+        (st->d.n_roots > 0 && (!m_root_t || !v_root_t))) {
+        gbp_set_error("step_get_state: NULL argument");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nv = st->n_v * sizeof(float), nr = st->d.n_roots * sizeof(float);
+    GBP_HIP(hipMemcpyAsync(m_vscale, st->m_vs, nv, hipMemcpyDeviceToDevice, s));
+    GBP_HIP(hipMemcpyAsync(v_vscale, st->v_vs, nv, hipMemcpyDeviceToDevice, s));
+    if (nr) {
+        GBP_HIP(hipMemcpyAsync(m_root_t, st->m_rt, nr, hipMemcpyDeviceToDevice, s));
+        GBP_HIP(hipMemcpyAsync(v_root_t, st->v_rt, nr, hipMemcpyDeviceToDevice, s));
+    }
+    GBP_HIP(hipMemcpyAsync(counter, st->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
+extern "C" int gbp_step_set_state(gbp_step st, const float* m_vscale, const float* v_vscale,
+                                  const float* m_root_t, const float* v_root_t, int counter,
+                                  void* stream) {
+    if (!st || !st->exec || !m_vscale || !v_vscale || counter < 1 ||
+        (st->d.n_roots > 0 && (!m_root_t || !v_root_t))) {
+        gbp_set_error("step_set_state: NULL argument or counter < 1");
+        return GBP_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nv = st->n_v * sizeof(float), nr = st->d.n_roots * sizeof(float);
+    GBP_HIP(hipMemcpyAsync(st->m_vs, m_vscale, nv, hipMemcpyDeviceToDevice, s));
+    GBP_HIP(hipMemcpyAsync(st->v_vs, v_vscale, nv, hipMemcpyDeviceToDevice, s));
+    if (nr) {
+        GBP_HIP(hipMemcpyAsync(st->m_rt, m_root_t, nr, hipMemcpyDeviceToDevice, s));
+        GBP_HIP(hipMemcpyAsync(st->v_rt, v_root_t, nr, hipMemcpyDeviceToDevice, s));
+    }
+    GBP_HIP(hipMemcpyAsync(st->counter, &counter, sizeof(int), hipMemcpyHostToDevice, s));
+    GBP_HIP(hipStreamSynchronize(s));
+    return GBP_OK;
+}
+
 extern "C" int gbp_step_launch(gbp_step st, void* stream) {
     if (!st || !st->exec) {
         gbp_set_error("step: not created");

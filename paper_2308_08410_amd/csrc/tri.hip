@@ -7,13 +7,16 @@
 //   with d = 2: two vertex candidates and one interior candidate, predicated);
 // * backward: geodesic parents in FP64 (the argmin is a decision taken by
 //   floating point: same precision as the reference), the adjoint
-//   lambda = g + P^T lambda (Sec. 2.3 Eq. (dto_grad)) by Jacobi sweeps over
-//   device-built child lists in a fixed order (exact after depth+1 sweeps on an
-//   acyclic parent graph, geometric on cycles), and the gradients w.r.t. the
-//   triangle tensors, nodal velocity scales and root onsets.
+//   lambda = g + P^T lambda (Sec. 2.3 Eq. (dto_grad)) as a leaves-first level
+//   walk over device-built child lists in a fixed order (as on tetrahedra: one
+//   launch per level, a vertex finished once all its children are), Jacobi
+//   sweeps only where parent-graph cycles leave vertices unfinished (geometric
+//   convergence there), and the gradients w.r.t. the triangle tensors, nodal
+//   velocity scales and root onsets.
 //
-// Meshes of the 2-D study are small (thousands of vertices): the kernels favour
-// simplicity over the tetrahedral path's latency hiding.
+// Meshes of the 2-D study are small (thousands of vertices); the kernels keep
+// the tetrahedral path's structure (queue, level walk, block-aggregated
+// counters) without its XCD and LDS-gather refinements.
 #include <math.h>
 
 #include <algorithm>
@@ -30,6 +33,8 @@ struct TriCtl {
     int unreached;
     int diff_bits[2];    // adjoint sweeps: largest |change| (float bits), by parity
     int lmax_bits[2];    // ... and largest |lambda|
+    int levels;          // adjoint: last level with work + 1
+    int remaining;       // adjoint: reached vertices the level walk has not finished
 };
 
 struct gbp_tri_plan_s {
@@ -52,7 +57,8 @@ struct gbp_tri_plan_s {
     int2* pnode = nullptr;
     float4* pa = nullptr;         // alpha_a, alpha_b, best, root_self
     int* ccnt = nullptr;          // [n_v+1]
-    int* cfill = nullptr;
+    int* cfill = nullptr;         // child fill cursors, then the level walk's remaining-children counts
+    int* rdy = nullptr;           // [n_v] level walk readiness stamps
     int* cchild = nullptr;        // [2 n_v]
     float* calpha = nullptr;
     float* lam[2] = {nullptr, nullptr};
@@ -60,6 +66,7 @@ struct gbp_tri_plan_s {
     float* dsbar = nullptr;
     int* scan_tmp = nullptr;
     int stamp = 1;
+    int last_levels = 0, last_cyclic = 0, last_sweeps = 0;   // of the last backward
     int max_rounds = 20000;
     float eps_rel = 1.0f / (1 << 20);
 };
@@ -83,7 +90,7 @@ void tri_free(gbp_tri_plan p) {
     void* ptrs[] = {p->xy,    p->tri,   p->vptr,   p->vent,   p->nbp,    p->nb,     p->minv,
                     p->T,     p->troot, p->q[0],   p->q[1],   p->mark,   p->ctl,    p->par,
                     p->pnode, p->pa,    p->ccnt,   p->cfill,  p->cchild, p->calpha, p->lam[0],
-                    p->lam[1], p->g,    p->dsbar,  p->scan_tmp};
+                    p->lam[1], p->g,    p->dsbar,  p->scan_tmp, p->rdy};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -91,6 +98,29 @@ void tri_free(gbp_tri_plan p) {
 }
 
 __device__ __forceinline__ bool fin(float x) { return x - x == 0.f; }
+
+// block reductions (one atomic per block instead of one per thread)
+__device__ __forceinline__ unsigned long long tri_block_sum(unsigned long long v) {
+    __shared__ unsigned long long part[TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (int w = 0; w < TPB / 64; ++w) t += part[w];
+    return t;
+}
+
+__device__ __forceinline__ float tri_block_max(float v) {
+    __shared__ float part[TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float t = 0.f;
+    for (int w = 0; w < TPB / 64; ++w) t = fmaxf(t, part[w]);
+    return t;
+}
 
 // face (a, b) of the triangle seen from its local vertex k: the other two
 // vertices in increasing local order
@@ -176,6 +206,14 @@ __global__ void __launch_bounds__(TPB)
                 float eps_rel) {
     const int n = ctl->count[s % 3];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->count[(s + 2) % 3] = 0;
+    if ((int)(blockIdx.x * blockDim.x) >= n) return;    // uniform over the block
+    // pushes collect in LDS; one atomic per block reserves their room in the queue
+    constexpr int kCap = 4096;
+    __shared__ int pbuf[kCap];
+    __shared__ int pn, pbase;
+    int* cnt_next = &ctl->count[(s + 1) % 3];
+    if (threadIdx.x == 0) pn = 0;
+    __syncthreads();
     unsigned long long solves = 0, upd = 0;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const int i = qin[k];
@@ -203,13 +241,25 @@ __global__ void __launch_bounds__(TPB)
             ++upd;
             for (int a = nbp[i]; a < nbp[i + 1]; ++a) {
                 const int w = nb[a];
-                if (atomicMax(&mark[w], stamp_next) < stamp_next)
-                    qout[atomicAdd(&ctl->count[(s + 1) % 3], 1)] = w;
+                if (atomicMax(&mark[w], stamp_next) < stamp_next) {
+                    const int pos = atomicAdd(&pn, 1);
+                    if (pos < kCap) pbuf[pos] = w;
+                    else qout[atomicAdd(cnt_next, 1)] = w;     // buffer full: straight to the queue
+                }
             }
         }
     }
-    if (solves) atomicAdd(&ctl->solves, solves);
-    if (upd) atomicAdd(&ctl->updates, upd);
+    __syncthreads();
+    const int m = min(pn, kCap);
+    if (threadIdx.x == 0) pbase = m > 0 ? atomicAdd(cnt_next, m) : 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < m; k += blockDim.x) qout[pbase + k] = pbuf[k];
+    solves = tri_block_sum(solves);
+    upd = tri_block_sum(upd);
+    if (threadIdx.x == 0) {
+        if (solves) atomicAdd(&ctl->solves, solves);
+        if (upd) atomicAdd(&ctl->updates, upd);
+    }
 }
 
 __global__ void k_tri_ctl_reset(TriCtl* ctl) {
@@ -359,13 +409,89 @@ __global__ void k_tri_adj_sweep(const int* __restrict__ cptr, const int* __restr
         ctl->diff_bits[(it + 1) & 1] = 0;
         ctl->lmax_bits[(it + 1) & 1] = 0;
     }
-    if (i >= n_v) return;
-    float l = g[i];
-    for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lin[cchild[k]];
-    lout[i] = l;
-    const float d = fabsf(l - lin[i]), a = fabsf(l);
-    if (d > 0.f) atomicMax(&ctl->diff_bits[it & 1], __float_as_int(d));
-    if (a > 0.f) atomicMax(&ctl->lmax_bits[it & 1], __float_as_int(a));
+    float d = 0.f, a = 0.f;
+    if (i < n_v) {
+        float l = g[i];
+        for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lin[cchild[k]];
+        lout[i] = l;
+        d = fabsf(l - lin[i]);
+        a = fabsf(l);
+    }
+    d = tri_block_max(d);
+    a = tri_block_max(a);
+    if (threadIdx.x == 0) {
+        if (d > 0.f) atomicMax(&ctl->diff_bits[it & 1], __float_as_int(d));
+        if (a > 0.f) atomicMax(&ctl->lmax_bits[it & 1], __float_as_int(a));
+    }
+}
+
+// Level walk (leaves first), as on tetrahedra: rdy[i] is the launch from which
+// vertex i may be finished (0 for leaves), or one of these markers.
+constexpr int kTriNever = 0x7fffffff;   // waiting for children
+constexpr int kTriDone = 0x7ffffffd;    // finished (or unreached)
+
+// rem: children per vertex (the sorted CSR range); ctl->remaining counts the
+// reached vertices (each level subtracts those it finishes)
+__global__ void k_tri_walk_init(const int* __restrict__ cptr, const float* __restrict__ T, int n_v,
+                                int* __restrict__ rem, int* __restrict__ rdy, TriCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool reached = false;
+    if (i < n_v) {
+        const int c = cptr[i + 1] - cptr[i];
+        rem[i] = c;
+        reached = T[i] < GBP_INF;
+        rdy[i] = !reached ? kTriDone : (c == 0 ? 0 : kTriNever);
+        if (reached && c == 0) ctl->count[0] = 1;   // the first launch has work
+    }
+    const unsigned long long r = tri_block_sum(reached ? 1ull : 0ull);
+    if (threadIdx.x == 0 && r) atomicAdd(&ctl->remaining, (int)r);
+}
+
+// One level: a vertex stamped for this launch has every child finished in an
+// earlier launch; it sums lambda = g + sum alpha_c lambda_c over its children in
+// child order (the order of a Jacobi sweep: the same value), and a parent whose
+// last child it was is stamped for the next launch (read only after this one).
+__global__ void k_tri_walk_level(int* __restrict__ rdy, const int* __restrict__ cptr,
+                                 const int* __restrict__ cchild, const float* __restrict__ calpha,
+                                 const float* __restrict__ g, float* lam, const int* __restrict__ par,
+                                 const int2* __restrict__ pnode, const float4* __restrict__ pa,
+                                 int* __restrict__ rem, int n_v, TriCtl* ctl, int s) {
+    const int flag = ctl->count[s % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(s + 2) % 3] = 0;
+        if (flag) atomicMax(&ctl->levels, s + 1);
+    }
+    if (flag == 0) return;
+    __shared__ int any_sh;
+    if (threadIdx.x == 0) any_sh = 0;
+    __syncthreads();
+    bool any = false;
+    unsigned long long fin_n = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_v; i += gridDim.x * blockDim.x) {
+        if (rdy[i] != s) continue;
+        ++fin_n;
+        float l = g[i];
+        for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lam[cchild[k]];
+        lam[i] = l;
+        rdy[i] = kTriDone;
+        if (par[i] < 0) continue;
+        const int2 q = pnode[i];
+        const float4 w = pa[i];
+        if (w.x > 0.f && atomicSub(&rem[q.x], 1) == 1) {
+            rdy[q.x] = s + 1;
+            any = true;
+        }
+        if (w.y > 0.f && atomicSub(&rem[q.y], 1) == 1) {
+            rdy[q.y] = s + 1;
+            any = true;
+        }
+    }
+    if (any) any_sh = 1;
+    fin_n = tri_block_sum(fin_n);     // (its barriers also publish any_sh)
+    if (threadIdx.x == 0) {
+        if (any_sh) ctl->count[(s + 1) % 3] = 1;
+        if (fin_n) atomicSub(&ctl->remaining, (int)fin_n);
+    }
 }
 
 __global__ void k_tri_grad_tri(const float2* __restrict__ xy, const int4* __restrict__ tri,
@@ -568,6 +694,7 @@ extern "C" int gbp_tri_plan_create(const float* xy, int n_v, const int32_t* tris
     TRI_TRY(tri_alloc(&p->pa, n_v));
     TRI_TRY(tri_alloc(&p->ccnt, (size_t)n_v + 1));
     TRI_TRY(tri_alloc(&p->cfill, n_v));
+    TRI_TRY(tri_alloc(&p->rdy, n_v));
     TRI_TRY(tri_alloc(&p->cchild, (size_t)2 * n_v));
     TRI_TRY(tri_alloc(&p->calpha, (size_t)2 * n_v));
     TRI_TRY(tri_alloc(&p->lam[0], n_v));
@@ -588,6 +715,17 @@ extern "C" int gbp_tri_plan_create(const float* xy, int n_v, const int32_t* tris
 }
 
 extern "C" void gbp_tri_plan_destroy(gbp_tri_plan p) { tri_free(p); }
+
+extern "C" int gbp_tri_backward_info(gbp_tri_plan p, int* levels, int* cyclic, int* sweeps) {
+    if (!p) {
+        gbp_set_error("null triangle plan");
+        return GBP_ERR_ARG;
+    }
+    if (levels) *levels = p->last_levels;
+    if (cyclic) *cyclic = p->last_cyclic;
+    if (sweeps) *sweeps = p->last_sweeps;
+    return GBP_OK;
+}
 
 extern "C" int gbp_tri_forward(gbp_tri_plan p, const float* D, const float* vscale,
                                const int32_t* root_node, const float* root_t, int n_roots,
@@ -664,29 +802,48 @@ extern "C" int gbp_tri_backward(gbp_tri_plan p, const float* D, const float* vsc
                                         p->calpha);
     k_tri_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
     k_tri_adj_init<<<nb, TPB, 0, s>>>(dL_dT, p->T, n_v, p->g, p->lam[0]);
+    // leaves-first level walk (cfill: the children each vertex still waits for),
+    // checked every 16 levels
+    k_tri_walk_init<<<nb, TPB, 0, s>>>(p->ccnt, p->T, n_v, p->cfill, p->rdy, p->ctl);
     GBP_LAUNCH_CHECK();
-    // Jacobi sweeps, checked every 16
-    const int cap = 8 * n_v + 64;
-    int it = 0;
-    bool settled = false;
-    while (it < cap) {
-        for (int b = 0; b < 16; ++b, ++it)
-            k_tri_adj_sweep<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->g, p->lam[it & 1],
-                                                p->lam[(it + 1) & 1], n_v, p->ctl, it);
+    const int wgrid = std::max(1, std::min(nb, 1024));
+    int level = 0;
+    while (level <= n_v + 1) {
+        for (int b = 0; b < 16; ++b, ++level)
+            k_tri_walk_level<<<wgrid, TPB, 0, s>>>(p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam[0],
+                                                   p->par, p->pnode, p->pa, p->cfill, n_v, p->ctl, level);
         GBP_LAUNCH_CHECK();
         if ((rc = tri_read(p, s))) return rc;
-        const float d = __builtin_bit_cast(float, p->ctl_host->diff_bits[(it - 1) & 1]);
-        const float a = __builtin_bit_cast(float, p->ctl_host->lmax_bits[(it - 1) & 1]);
-        if (d <= 1e-7f * a) {
-            settled = true;
-            break;
+        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
+        if (p->ctl_host->count[level % 3] == 0) break;
+    }
+    p->last_levels = p->ctl_host->levels;
+    p->last_cyclic = p->ctl_host->remaining;
+    // vertices on or above parent-graph cycles: Jacobi sweeps from the walk's
+    // values (finished vertices reproduce theirs), checked every 16
+    int it = 0;
+    if (p->ctl_host->remaining > 0) {
+        const int cap = 8 * n_v + 64;
+        bool settled = false;
+        while (it < cap) {
+            for (int b = 0; b < 16; ++b, ++it)
+                k_tri_adj_sweep<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->g, p->lam[it & 1],
+                                                    p->lam[(it + 1) & 1], n_v, p->ctl, it);
+            GBP_LAUNCH_CHECK();
+            if ((rc = tri_read(p, s))) return rc;
+            const float d = __builtin_bit_cast(float, p->ctl_host->diff_bits[(it - 1) & 1]);
+            const float a = __builtin_bit_cast(float, p->ctl_host->lmax_bits[(it - 1) & 1]);
+            if (d <= 1e-7f * a) {
+                settled = true;
+                break;
+            }
+        }
+        if (!settled) {
+            gbp_set_error("triangle adjoint did not settle in %d sweeps", it);
+            return GBP_ERR_NOT_CONVERGED;
         }
     }
-    if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
-    if (!settled) {
-        gbp_set_error("triangle adjoint did not settle in %d sweeps", it);
-        return GBP_ERR_NOT_CONVERGED;
-    }
+    p->last_sweeps = it;
     const float* lam = p->lam[it & 1];
     k_tri_fill<<<gbp_blocks(n_t, TPB), TPB, 0, s>>>(p->dsbar, 0.f, n_t);
     if (dL_dD) k_tri_fill<<<gbp_blocks(3LL * n_t, TPB), TPB, 0, s>>>(dL_dD, 0.f, 3 * n_t);

@@ -53,6 +53,11 @@ def test_slice_gradients_match_oracle(slice_case):
     dD, dvs, drt = B().tri_backward(c["plan"], c["D"], c["vs"], c["rn"], c["rt"], t32(T_in, c["dev"]),
                                     t32(g, c["dev"]))
     ref = O2.adjoint2(p.xyz, p.tets, p.D, p.vscale, p.root_node, p.root_t, T_in.astype(np.float64), g)
+    info = B().tri_backward_info(c["plan"])
+    print(f"[walk] slice: {info}", flush=True)
+    # the level walk finishes the adjoint (sweeps only on what cycles leave)
+    assert info["levels"] > 10 and info["cyclic"] <= p.n_v // 10
+    assert (info["sweeps"] == 0) == (info["cyclic"] == 0)
     assert rel_l2(dD.cpu().numpy(), ref["dD"]) <= 1e-3
     assert rel_l2(dvs.cpu().numpy(), ref["dvscale"]) <= 1e-3
     assert rel_l2(drt.cpu().numpy(), ref["droot_t"]) <= 1e-3
@@ -80,6 +85,9 @@ def test_square_anisotropic_matches_oracle(seed):
     dD, dvs, drt = B().tri_backward(plan, t32(D3, dev), t32(vs, dev), i32(rn, dev), t32(rt, dev),
                                     t32(T_in, dev), t32(g, dev))
     ref = O2.adjoint2(x, tris, D3, vs, rn, rt, T_in.astype(np.float64), g)
+    info = B().tri_backward_info(plan)
+    print(f"[walk] anisotropic square seed {seed}: {info}", flush=True)
+    assert info["levels"] > 10 and (info["sweeps"] == 0) == (info["cyclic"] == 0)
     assert rel_l2(dD.cpu().numpy(), ref["dD"]) <= 1e-3
     assert rel_l2(dvs.cpu().numpy(), ref["dvscale"]) <= 1e-3
     assert rel_l2(drt.cpu().numpy(), ref["droot_t"]) <= 1e-3
