@@ -571,16 +571,9 @@ def inverse_form(dev, torch, gi, B, iters=20, n_nodes=1_000_000, starts=16, seed
 
 def host_info():
     """CPU model and logical core count of the host this runs on."""
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return dict(cpu_model=model, nproc=os.cpu_count())
+    from paper_2308_08410_amd.runlog import host_info as info
+    h = info()
+    return dict(cpu_model=h["cpu_model"], nproc=h["nproc"])
 
 
 def cpu_baseline(prob, vs, rt, threads):

@@ -7,7 +7,12 @@ cold by default; `warm=True` starts it (two-sided) from the previous iteration's
 activation times, which reaches the same solution but is slower here, because
 every Adam step moves every activation time.  All arithmetic runs in libgbp.
 
-    python -m paper_2308_08410_amd.inverse --nodes 100000 --starts 4 --iters 100
+A fit can write a JSON-lines run log (host, device and configuration first, then
+the misfit of every start at each logged iteration) and checkpoints (parameters,
+the step's Adam state, the iteration) from which a new process resumes it.
+
+    python -m paper_2308_08410_amd.inverse --nodes 100000 --starts 4 --iters 100 \\
+        --log fit.jsonl --checkpoint fit.npz --checkpoint-every 25 [--resume]
 """
 from __future__ import annotations
 
@@ -21,6 +26,7 @@ import torch
 
 from . import autotune
 from . import binding as B
+from . import runlog
 from .batch import concat, shift_roots, union_mesh
 
 
@@ -61,20 +67,56 @@ class MultiStartFit:
                            lr_root_t=lr_root_t, vscale_lo=vscale_bounds[0], vscale_hi=vscale_bounds[1],
                            **self.budgets)
 
-    def run(self, iters, log_every=0, check_every=25):
+    def run(self, iters, log_every=0, check_every=25, start=0, log: runlog.RunLog | None = None,
+            checkpoint=None, checkpoint_every=0):
+        """Iterations start .. start + iters - 1 (start > 0 after `restore`).  The
+        misfits go to `history` (and `log`) every log_every iterations; with
+        `checkpoint` a checkpoint is written every checkpoint_every iterations and
+        after the last one."""
         hist = []
         t0 = time.perf_counter()
-        for k in range(iters):
+        end = start + iters
+        for k in range(start, end):
             self.step.launch()
             if check_every and (k + 1) % check_every == 0:
                 st = B.plan_status(self.plan)
                 if not (st["forward_converged"] and st["backward_settled"]) or st["err"]:
                     raise RuntimeError(f"iteration {k}: captured step out of budget or failed: {st}")
-            if log_every and (k % log_every == 0 or k == iters - 1):
-                hist.append((k, self.loss.detach().cpu().numpy().copy()))
+            if log_every and (k % log_every == 0 or k == end - 1):
+                loss = self.loss.detach().cpu().numpy().copy()
+                hist.append((k, loss))
+                if log is not None:
+                    log.write(event="iteration", iteration=k, loss=loss)
+            if checkpoint and ((checkpoint_every and (k + 1) % checkpoint_every == 0) or k == end - 1):
+                self.checkpoint(checkpoint, k + 1)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return dict(seconds=dt, iters_per_s=iters / dt, history=hist)
+        return dict(seconds=dt, iters_per_s=iters / max(dt, 1e-12), history=hist)
+
+    def checkpoint(self, path, iteration):
+        """Write the fit's state after `iteration` iterations: the parameters of
+        every start, the last activation times (the warm forward's guess) and the
+        step's Adam state."""
+        st = self.step.get_state()
+        runlog.save_checkpoint(path, iteration=np.int64(iteration), vscale=self.vs, root_t=self.rt, T=self.T,
+                               m_vscale=st["m_vscale"], v_vscale=st["v_vscale"], m_root_t=st["m_root_t"],
+                               v_root_t=st["v_root_t"], counter=np.int64(st["counter"]),
+                               n_v=np.int64(self.n_v), starts=np.int64(self.S))
+
+    def restore(self, path):
+        """Load a checkpoint written by a fit of the same mesh, starts and roots;
+        returns the number of iterations it had done."""
+        c = runlog.load_checkpoint(path)
+        if int(c["n_v"]) != self.n_v or int(c["starts"]) != self.S or c["root_t"].shape != tuple(self.rt.shape):
+            raise ValueError("checkpoint is of a different fit (mesh size, starts or roots)")
+        # in place: the captured step reads these buffers
+        self.vs.copy_(torch.as_tensor(c["vscale"], device=self.vs.device))
+        self.rt.copy_(torch.as_tensor(c["root_t"], device=self.rt.device))
+        self.T.copy_(torch.as_tensor(c["T"], device=self.T.device))
+        self.step.set_state(dict(m_vscale=c["m_vscale"], v_vscale=c["v_vscale"], m_root_t=c["m_root_t"],
+                                 v_root_t=c["v_root_t"], counter=int(c["counter"])))
+        torch.cuda.synchronize()
+        return int(c["iteration"])
 
     def instance(self, i):
         """(vscale, root_t, T) of start i (torch views)."""
@@ -100,6 +142,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--warm", action="store_true",
                     help="start each forward from the previous iteration's activation times")
+    ap.add_argument("--log", default="", help="JSON-lines run log (appended)")
+    ap.add_argument("--checkpoint", default="", help="checkpoint file (.npz)")
+    ap.add_argument("--checkpoint-every", type=int, default=0)
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
     args = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
     p, vs_true, rt0 = synthetic_problem(args.nodes, args.roots, args.seed, args.starts)
@@ -112,12 +158,18 @@ def main(argv=None):
                            B.make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])).cpu().numpy()
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(args.starts)]
     fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=args.warm)
-    out = fit.run(args.iters, log_every=max(1, args.iters // 10))
+    start = fit.restore(args.checkpoint) if args.resume else 0
+    log = runlog.RunLog(args.log, "inverse", dict(vars(args), n_v=p.n_v, n_e=p.n_e, start=start,
+                                                   budgets=fit.budgets)) if args.log else None
+    out = fit.run(args.iters, log_every=max(1, args.iters // 10), start=start, log=log,
+                  checkpoint=args.checkpoint or None, checkpoint_every=args.checkpoint_every)
+    if log is not None:
+        log.close(iters_per_s=out["iters_per_s"], seconds=out["seconds"])
     final = out["history"][-1][1]
     best = int(np.argmin(final))
     vs_b, rt_b, T_b = fit.instance(best)
     err_T = float((T_b.cpu() - T_true.cpu()).abs().max())
-    print(json.dumps(dict(nodes=p.n_v, starts=args.starts, iters=args.iters, warm=args.warm,
+    print(json.dumps(dict(nodes=p.n_v, starts=args.starts, iters=args.iters, start=start, warm=args.warm,
                           iters_per_s=out["iters_per_s"], seconds=out["seconds"], budgets=fit.budgets,
                           loss_first=[float(x) for x in out["history"][0][1]],
                           loss_final=[float(x) for x in final], best=best,

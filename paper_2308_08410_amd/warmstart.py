@@ -28,6 +28,7 @@ import numpy as np
 import torch
 
 from . import binding as B
+from . import runlog
 
 
 class WarmStart:
@@ -128,16 +129,38 @@ def make_dataset(plan, xyz, D, candidates, n_solves, seed=0, scale_bank=0, log_e
     return data
 
 
-def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_every=100, seed=0, verbose=False):
-    """Adam on random row batches of the solves, cosine learning-rate decay.
-    Returns [(step, mse in normalised time units)]."""
+def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_every=100, seed=0, verbose=False,
+          checkpoint=None, checkpoint_every=0, resume=False, log: runlog.RunLog | None = None, stop=None):
+    """Adam on random row batches of the solves, cosine learning-rate decay over
+    `steps` steps.  Returns [(step, mse in normalised time units)].  With
+    `checkpoint` the network, its Adam state, the step and the row generator's
+    state are saved every checkpoint_every steps and where the call stops; `stop`
+    ends the call before step `stop` of the schedule (a time-bounded job);
+    resume=True continues from the checkpoint (the same steps follow as in an
+    uninterrupted run)."""
     if batch > ws.mlp.max_rows:
         raise ValueError("batch exceeds the network's max_rows")
     g = torch.Generator(device=ws.device)
     g.manual_seed(seed)
     loss = torch.empty(1, dtype=torch.float32, device=ws.device)
     hist = []
-    for s in range(steps):
+    first = 0
+    if resume:
+        c = runlog.load_checkpoint(checkpoint)
+        ws.mlp.set_params(c["params"])
+        ws.mlp.set_state(dict(m=c["m"], v=c["v"], step=int(c["adam_step"])))
+        g.set_state(torch.as_tensor(c["rng"]))
+        first = int(c["step"])
+        hist = [(int(a), float(b)) for a, b in c["hist"]]
+
+    def save(done):
+        st = ws.mlp.get_state()
+        runlog.save_checkpoint(checkpoint, params=ws.mlp.get_params(), m=st["m"], v=st["v"],
+                               adam_step=np.int64(st["step"]), step=np.int64(done),
+                               rng=g.get_state().numpy(), hist=np.asarray(hist, np.float64).reshape(-1, 2))
+
+    last = steps if stop is None else min(int(stop), steps)
+    for s in range(first, last):
         d = data[s % len(data)]
         rows = torch.randint(0, ws.n_v, (batch,), dtype=torch.int32, device=ws.device, generator=g)
         X, tgt = ws.features(d["root_node"], d["root_t"], d["vscale"], rows=rows, T=d["T"])
@@ -147,6 +170,10 @@ def train(ws: WarmStart, data, steps, batch=8192, lr=1e-3, lr_min=1e-5, log_ever
             hist.append((s, float(loss)))
             if verbose:
                 print(f"[train] step {s} of {steps}: mse {hist[-1][1]:.4g}", flush=True)
+            if log is not None:
+                log.write(event="train", step=s, mse=hist[-1][1], lr=lr_s)
+        if checkpoint and ((checkpoint_every and (s + 1) % checkpoint_every == 0) or s == last - 1):
+            save(s + 1)
     return hist
 
 
@@ -217,6 +244,10 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--test", type=int, default=6)
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--log", default="", help="JSON-lines run log (appended)")
+    ap.add_argument("--checkpoint", default="", help="training checkpoint file (.npz)")
+    ap.add_argument("--checkpoint-every", type=int, default=0)
+    ap.add_argument("--resume", action="store_true", help="continue training from --checkpoint")
     args = ap.parse_args(argv)
     import gbp_inputs as gi
     dev = torch.device("cuda", 0)
@@ -229,7 +260,10 @@ def main(argv=None):
     t_data = time.perf_counter() - t0
     ws = WarmStart(p.xyz, p.extra["node_fibre"], max_rows=max(args.batch, 1 << 16), seed=args.seed)
     t0 = time.perf_counter()
-    hist = train(ws, data, args.steps, batch=args.batch, lr=args.lr, log_every=max(1, args.steps // 20))
+    log = runlog.RunLog(args.log, "warmstart", dict(vars(args), n_v=p.n_v, n_e=p.n_e)) if args.log else None
+    hist = train(ws, data, args.steps, batch=args.batch, lr=args.lr, log_every=max(1, args.steps // 20),
+                 checkpoint=args.checkpoint or None, checkpoint_every=args.checkpoint_every,
+                 resume=args.resume, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     test = make_dataset(plan, p.xyz, D, p.extra["endo"], args.test, seed=900_000 + args.seed)
@@ -249,6 +283,8 @@ def main(argv=None):
                                geo=mean(lambda r: r["guess_rel_l2"]["geo"])),
         max_warm_vs_cold_rel=max(max(r["warm_vs_cold_rel_max"].values()) for r in rows),
         cases=rows)
+    if log is not None:
+        log.close(**{k: v for k, v in summary.items() if k != "cases"})
     print(json.dumps(summary), flush=True)
 
 

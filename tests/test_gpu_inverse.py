@@ -36,3 +36,52 @@ def test_multistart_fit_reduces_misfit(warm):
     err0 = np.abs(rt0[best] - p.root_t).mean()
     err1 = np.abs(rt_b.cpu().numpy() - p.root_t).mean()
     assert err1 < err0
+
+
+def test_fit_resumes_from_checkpoint(tmp_path):
+    """A fit checkpointed after k iterations and resumed by a new fit object (new
+    plan, new captured step) continues as the uninterrupted fit: parameters, Adam
+    state and counter match after 2k iterations.  The in-place relaxation's order
+    varies between runs in the last bits of T, so parameters are compared to 1e-5 of
+    their scale; the counter exactly.  The run log records the header and the
+    misfits."""
+    _dev()
+    from paper_2308_08410_amd import runlog
+    from paper_2308_08410_amd.inverse import MultiStartFit
+    p = gi.shell_problem(8_000, seed=13, n_roots=4, n_leads=12)
+    vs_true = gi.smooth_field(p.xyz, 0.7, 1.3, seed=23)
+    ap = dict(p.ap, n_steps=200)
+    To, _ = O.solve(p.xyz, p.tets, p.D, vs_true, p.root_node, p.root_t)
+    target = O.ecg_forward(To, p.W, ap)
+    rng = np.random.Generator(np.random.PCG64(4))
+    vs0 = [np.ones(p.n_v, np.float32) for _ in range(2)]
+    rt0 = [(p.root_t + rng.uniform(-6, 6, size=len(p.root_t))).astype(np.float32) for _ in range(2)]
+    make = lambda: MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, ap, vs0, rt0)
+    k = 15
+    full = make()
+    full.run(2 * k, check_every=k)
+    ref = full.step.get_state()
+    vs_ref, rt_ref = full.vs.cpu().numpy(), full.rt.cpu().numpy()
+    ck = str(tmp_path / "fit.npz")
+    logp = str(tmp_path / "fit.jsonl")
+    first = make()
+    log = runlog.RunLog(logp, "inverse", dict(iters=k), device=True)
+    first.run(k, log_every=5, check_every=k, log=log, checkpoint=ck)
+    log.close()
+    del first
+    second = make()
+    assert second.restore(ck) == k
+    assert second.step.get_state()["counter"] == k + 1
+    second.run(k, start=k, check_every=k)
+    got = second.step.get_state()
+    assert got["counter"] == ref["counter"] == 2 * k + 1
+    assert np.abs(second.vs.cpu().numpy() - vs_ref).max() <= 1e-5 * np.abs(vs_ref).max()
+    assert np.abs(second.rt.cpu().numpy() - rt_ref).max() <= 1e-5 * np.abs(rt_ref).max()
+    for name in ("m_vscale", "v_vscale", "m_root_t", "v_root_t"):
+        a, b = got[name].cpu().numpy(), ref[name].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-30), name
+    recs = runlog.read_log(logp)
+    assert recs[0]["event"] == "start" and recs[0]["device"]["library"].startswith("gbp")
+    assert [r["iteration"] for r in recs if r["event"] == "iteration"] == [0, 5, 10, 14]
+    with pytest.raises(ValueError):
+        MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, ap, vs0[:1], rt0[:1]).restore(ck)

@@ -227,3 +227,30 @@ def test_training_reduces_loss_and_warm_start_equals_cold():
     print("warm start:", rows[0])
     assert rows[0]["warm_vs_cold_rel_max"]["mlp"] <= 1e-4
     assert rows[0]["warm_vs_cold_rel_max"]["geo"] <= 1e-4
+
+
+def test_training_resumes_from_checkpoint(tmp_path):
+    """Training stopped half-way through its schedule (checkpoint written) and
+    resumed by a new network object follows the uninterrupted run exactly: the
+    same row batches from the restored generator, the same Adam state, and
+    deterministic kernels, so the parameters and moments are bitwise equal."""
+    _dev()
+    from paper_2308_08410_amd import warmstart as WS
+    p = gi.shell_problem(6_000, seed=11)
+    plan = B().Plan(p.xyz, p.tets)
+    D = torch.as_tensor(p.D, device="cuda")
+    data = WS.make_dataset(plan, p.xyz, D, p.extra["endo"], 3, seed=77)
+    ck = str(tmp_path / "train.npz")
+    net = lambda seed: WS.WarmStart(p.xyz, p.extra["node_fibre"], max_rows=4096, seed=seed)
+    full = net(4)
+    h_full = WS.train(full, data, 24, batch=2048, log_every=4, seed=9)
+    part = net(4)
+    WS.train(part, data, 24, batch=2048, log_every=4, seed=9, checkpoint=ck, stop=12)
+    assert part.mlp.get_state()["step"] == 12
+    resumed = net(123)                      # initial weights replaced by the checkpoint's
+    h_res = WS.train(resumed, data, 24, batch=2048, log_every=4, seed=9, checkpoint=ck, resume=True)
+    assert np.array_equal(resumed.mlp.get_params(), full.mlp.get_params())
+    a, b = resumed.mlp.get_state(), full.mlp.get_state()
+    assert a["step"] == b["step"] == 24
+    assert np.array_equal(a["m"], b["m"]) and np.array_equal(a["v"], b["v"])
+    assert h_res == h_full
