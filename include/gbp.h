@@ -105,8 +105,11 @@ int gbp_plan_sizes(gbp_plan plan, int *n_v, int *n_e);
  *              Non-NULL: a guess; the solve then uses the two-sided update
  *              (every node re-takes the minimum over its faces, roots also
  *              min with their onset), which converges to the same fixed point
- *              from any finite or infinite guess.  With gbp_plan_set_warm_order
- *              on, the guess instead orders a cold solve (see there).
+ *              from any finite or infinite guess: the guess is taken as +inf on
+ *              every connected component of the mesh that holds no root (there
+ *              the two-sided update would raise the values without end).  With
+ *              gbp_plan_set_warm_order on, the guess instead orders a cold
+ *              solve (see there).
  *   T_out      device float [n_v]  (may alias T_init)
  *   stats      host, may be NULL
  * Unreached vertices get +inf.  Errors: GBP_ERR_ARG (root id out of range,

@@ -317,6 +317,27 @@ __global__ void k_roots(const int* __restrict__ root_node, const float* __restri
     }
 }
 
+// Two-sided warm start: a connected component without a root has no finite fixed
+// point to reach (each round would raise its values by at least an edge cost), so
+// its guess is dropped to +inf.  Components holding a root vertex (finite onset)
+// are flagged, then the others cleared.
+__global__ void k_comp_flag(const float* __restrict__ troot, const int* __restrict__ comp, int n_v,
+                            int* __restrict__ comp_root) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_v && troot[i] < GBP_INF) comp_root[comp[i]] = 1;
+}
+
+__global__ void k_comp_clear(const int* __restrict__ comp, const int* __restrict__ comp_root, int n_v,
+                             float* __restrict__ T) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_v && !comp_root[comp[i]]) T[i] = GBP_INF;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_queue_all(int* __restrict__ q, int* __restrict__ mark, int n_v, GbpCtl* ctl,
                             XcdQueues xq) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1688,8 +1709,12 @@ int gbp_forward_impl(gbp_plan p, const float* D, const float* vscale, const int3
                       s, ordered ? T_init : nullptr)))
         return rc;
     k_zero_u64<<<gbp_blocks(2 * kStatBlocks, TPB), TPB, 0, s>>>(p->blk, 2 * kStatBlocks);
-    if (!cold)
+    if (!cold) {
+        k_fill_int<<<gbp_blocks(p->n_comp, TPB), TPB, 0, s>>>(p->comp_root, 0, p->n_comp);
+        k_comp_flag<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->troot, p->comp, n_v, p->comp_root);
+        k_comp_clear<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->comp, p->comp_root, n_v, p->T);
         k_queue_all<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->q[0], p->mark, n_v, p->ctl, p->xq);
+    }
     GBP_LAUNCH_CHECK();
     int r = 0;
     bool converged = true;

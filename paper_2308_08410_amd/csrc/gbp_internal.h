@@ -97,6 +97,9 @@ struct gbp_plan_s {
     int* nent = nullptr;          // [4 n_e] element ids sorted by (node, local slot, element)
     int* adj_ptr = nullptr;       // [n_v+1] unique neighbour lists
     int* adj = nullptr;           // [n_adj]
+    int* comp = nullptr;          // [n_v] connected component of each vertex
+    int* comp_root = nullptr;     // [n_comp] per call: the component holds a root
+    int n_comp = 0;
 
     // per-call workspace (device)
     float4* tetg = nullptr;       // [2 n_e]: (G11,G22,G33,G12), (G13,G23,sbar,0)

@@ -77,7 +77,8 @@ static void plan_free(gbp_plan p) {
                     p->adj_ptr, p->adj, p->tetg, p->vs, p->T, p->troot, p->q[0], p->q[1],
                     p->mark, p->ctl, p->blk, p->par, p->pa, p->ccnt, p->cfill, p->rem, p->cchild,
                     p->calpha, p->lam, p->contrib, p->cslot, p->g, p->dsbar, p->done, p->rdy, p->scan_tmp, p->lip,
-                    p->pnode, p->partner, p->pairrem, p->hold, p->blist, p->guess};
+                    p->pnode, p->partner, p->pairrem, p->hold, p->blist, p->guess, p->comp,
+                    p->comp_root};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -269,6 +270,31 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
         adj_ptr[i + 1] = (int)adj.size();
     }
 
+    // ---- connected components (internal numbering): a two-sided warm start sets
+    // the guess of every component without a root to +inf
+    std::vector<int> comp(n_v);
+    std::iota(comp.begin(), comp.end(), 0);
+    auto find = [&comp](int x) {
+        while (comp[x] != x) x = comp[x] = comp[comp[x]];
+        return x;
+    };
+    for (int j = 0; j < n_e; ++j) {
+        const int* v = &tvs[j].x;
+        for (int k = 1; k < 4; ++k) {
+            const int a = find(v[0]), r = find(v[k]);
+            if (r != a) comp[std::max(r, a)] = std::min(r, a);   // roots link to the smaller root
+        }
+    }
+    int n_comp = 0;
+    {
+        std::vector<int> root(n_v), label(n_v, -1);
+        for (int i = 0; i < n_v; ++i) root[i] = find(i);   // before relabelling in place
+        for (int i = 0; i < n_v; ++i) {
+            if (label[root[i]] < 0) label[root[i]] = n_comp++;
+            comp[i] = label[root[i]];
+        }
+    }
+
     std::vector<float4> x4(n_v);
     for (int i = 0; i < n_v; ++i) {
         int u = node_user[i];
@@ -298,6 +324,9 @@ extern "C" int gbp_plan_create(const float* xyz, int n_v, const int32_t* tets, i
     TRY(upload(&p->nent, nent.data(), (size_t)n_e * 4));
     TRY(upload(&p->adj_ptr, adj_ptr.data(), n_v + 1));
     TRY(upload(&p->adj, adj.data(), adj.size()));
+    TRY(upload(&p->comp, comp.data(), n_v));
+    TRY(dalloc(&p->comp_root, (size_t)n_comp));
+    p->n_comp = n_comp;
     TRY(dalloc(&p->tetg, (size_t)n_e * 2));
     TRY(dalloc(&p->vs, n_v));
     TRY(dalloc(&p->T, n_v));

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gbp.h"
+#include "gbp_internal.h"   // the plan's arrays are host memory under the stand-ins
 
 extern "C" void stub_fail_after(int n);
 extern "C" int stub_allocations(void);
@@ -144,6 +145,27 @@ int main() {
         t.resize(4 * 255);
         expect("255 elements in one slot", gbp_plan_create(q.data(), (int)q.size() / 3, t.data(), 255, nullptr, &p),
                GBP_OK);
+        gbp_plan_destroy(p);
+        p = nullptr;
+    }
+
+    {
+        // connected components (a two-sided warm start drops the guess on the
+        // components without a root): the cube plus a separate element, in an
+        // order where the far element's vertices are linked after the cube's
+        std::vector<float> q = xyz;
+        std::vector<int32_t> t = tets;
+        const float far[12] = {10, 10, 10, 11, 10, 10, 10, 11, 10, 10, 10, 11};
+        q.insert(q.end(), far, far + 12);
+        t.insert(t.end(), {n_v + 3, n_v + 1, n_v, n_v + 2});
+        expect("two components", gbp_plan_create(q.data(), n_v + 4, t.data(), n_e + 1, nullptr, &p), GBP_OK);
+        int bad = p->n_comp == 2 ? 0 : 1;
+        for (int i = 0; i < n_v + 4; ++i) {
+            const int u = p->node_user[i];
+            bad += p->comp[i] != (u < n_v ? p->comp[p->node_int[0]] : p->comp[p->node_int[n_v]]);
+        }
+        bad += p->comp[p->node_int[0]] == p->comp[p->node_int[n_v]];
+        expect("component labels", bad, 0);
         gbp_plan_destroy(p);
         p = nullptr;
     }

@@ -160,6 +160,20 @@ def test_duplicate_roots_and_unreached_component():
     assert np.all(np.isinf(Tg[n:]))
     assert rel_max(Tg, To) <= 1e-4
     assert Tg[0] == pytest.approx(0.1)
+    # a two-sided warm start with a finite guess on the rootless component: the
+    # guess is dropped there (no finite fixed point), so the solve converges
+    guess = np.where(np.isfinite(To), 1.3 * To + 0.2, 5.0).astype(np.float32)
+    Tw, stw = B().eikonal_forward(plan, t32(D, dev), None, i32(rn, dev), t32(rt, dev), T_init=t32(guess, dev))
+    assert stw["converged"] and stw["unreached"] == 4 and stw["rounds"] < 200
+    assert rel_max(Tw.cpu().numpy(), To) <= 1e-4
+    # roots on both components: both reached, from the same guess
+    rn2 = np.array([0, n + 2], np.int32)
+    rt2 = np.array([0.0, 0.5], np.float32)
+    To2, _ = O.solve(xyz, tets, D, None, rn2, rt2)
+    Tw2, stw2 = B().eikonal_forward(plan, t32(D, dev), None, i32(rn2, dev), t32(rt2, dev),
+                                    T_init=t32(guess, dev))
+    assert stw2["converged"] and stw2["unreached"] == 0
+    assert rel_max(Tw2.cpu().numpy(), To2) <= 1e-4
 
 
 def test_duplicate_roots_with_negative_and_signed_zero_onsets():
