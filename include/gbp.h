@@ -318,8 +318,9 @@ int gbp_lead_field(gbp_plan plan, const float *electrodes, int n_leads, float *W
  *   [n_roots], each may be NULL; the formulas of gbp_eikonal_backward with
  *   d sbar / d s = 1/3.  The adjoint is the leaves-first level walk of
  *   gbp_eikonal_backward (each vertex finished once its children are, in a
- *   fixed order); vertices that parent-graph cycles leave unfinished take Jacobi
- *   sweeps to a relative change of 1e-7.  Errors: as gbp_eikonal_backward.
+ *   fixed order); the vertices that parent-graph cycles leave unfinished take
+ *   Gauss-Seidel sweeps to a relative change of 1e-7.  Errors: as
+ *   gbp_eikonal_backward.
  * gbp_tri_backward_info -- the last backward's level count, the vertices the
  *   walk left to the sweeps, and the sweeps taken (any pointer may be NULL).
  */

@@ -7,10 +7,11 @@
 //   with d = 2: two vertex candidates and one interior candidate, predicated);
 // * backward: geodesic parents in FP64 (the argmin is a decision taken by
 //   floating point: same precision as the reference), the adjoint
-//   lambda = g + P^T lambda (Sec. 2.3 Eq. (dto_grad)) as a leaves-first level
-//   walk over device-built child lists in a fixed order (as on tetrahedra: one
-//   launch per level, a vertex finished once all its children are), Jacobi
-//   sweeps only where parent-graph cycles leave vertices unfinished (geometric
+//   lambda = g + P^T lambda (Sec. 2.3 Eq. (dto_grad)) as a leaves-first walk
+//   over device-built child lists in a fixed order (a vertex finished once all
+//   its children are, two-cycles solved as pairs; the whole walk in one
+//   work-group, since these parent graphs are deep and narrow), Gauss-Seidel
+//   sweeps over just the vertices that longer cycles leave unfinished (geometric
 //   convergence there), and the gradients w.r.t. the triangle tensors, nodal
 //   velocity scales and root onsets.
 //
@@ -35,6 +36,8 @@ struct TriCtl {
     int lmax_bits[2];    // ... and largest |lambda|
     int levels;          // adjoint: last level with work + 1
     int remaining;       // adjoint: reached vertices the level walk has not finished
+    int nlist;           // adjoint: length of the list of those vertices
+    int rounds;          // forward: last round with work + 1
 };
 
 struct gbp_tri_plan_s {
@@ -53,12 +56,16 @@ struct gbp_tri_plan_s {
     int* mark = nullptr;
     TriCtl* ctl = nullptr;
     TriCtl* ctl_host = nullptr;
+    TriCtl* ctl_pipe = nullptr;   // pinned [2]: control block after each batch of rounds
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int* par = nullptr;
     int2* pnode = nullptr;
     float4* pa = nullptr;         // alpha_a, alpha_b, best, root_self
     int* ccnt = nullptr;          // [n_v+1]
     int* cfill = nullptr;         // child fill cursors, then the level walk's remaining-children counts
-    int* rdy = nullptr;           // [n_v] level walk readiness stamps
+    int* rdy = nullptr;           // [n_v] adjoint walk: finished flags
+    int* partner = nullptr;       // [n_v] two-cycle partner or -1
+    int* pairrem = nullptr;       // [n_v] members of a two-cycle not yet ready (at the smaller one)
     int* cchild = nullptr;        // [2 n_v]
     float* calpha = nullptr;
     float* lam[2] = {nullptr, nullptr};
@@ -90,10 +97,13 @@ void tri_free(gbp_tri_plan p) {
     void* ptrs[] = {p->xy,    p->tri,   p->vptr,   p->vent,   p->nbp,    p->nb,     p->minv,
                     p->T,     p->troot, p->q[0],   p->q[1],   p->mark,   p->ctl,    p->par,
                     p->pnode, p->pa,    p->ccnt,   p->cfill,  p->cchild, p->calpha, p->lam[0],
-                    p->lam[1], p->g,    p->dsbar,  p->scan_tmp, p->rdy};
+                    p->lam[1], p->g,    p->dsbar,  p->scan_tmp, p->rdy, p->partner, p->pairrem};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+    if (p->ctl_pipe) (void)hipHostFree(p->ctl_pipe);
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -205,7 +215,10 @@ __global__ void __launch_bounds__(TPB)
                 int* __restrict__ qout, int* __restrict__ mark, TriCtl* ctl, int s, int stamp_next,
                 float eps_rel) {
     const int n = ctl->count[s % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->count[(s + 2) % 3] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(s + 2) % 3] = 0;
+        if (n > 0) atomicMax(&ctl->rounds, s + 1);
+    }
     if ((int)(blockIdx.x * blockDim.x) >= n) return;    // uniform over the block
     // pushes collect in LDS; one atomic per block reserves their room in the queue
     constexpr int kCap = 4096;
@@ -398,24 +411,25 @@ __global__ void k_tri_adj_init(const float* __restrict__ dLdT, const float* __re
     lam[i] = v;
 }
 
-// one Jacobi sweep of lambda = g + P^T lambda; records max |change| and max
-// |lambda| (non-negative float bits order like ints) in the slot of its parity
-__global__ void k_tri_adj_sweep(const int* __restrict__ cptr, const int* __restrict__ cchild,
-                                const float* __restrict__ calpha, const float* __restrict__ g,
-                                const float* __restrict__ lin, float* __restrict__ lout, int n_v,
-                                TriCtl* ctl, int it) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Gauss-Seidel sweep (in place) over the vertices the level walk left unfinished
+// (on or above parent-graph cycles; every cycle leaks weight to parents outside
+// it, so the sweeps contract); records the largest |change| and |lambda|.
+__global__ void k_tri_adj_gs(const int* __restrict__ list, const int* __restrict__ cptr,
+                             const int* __restrict__ cchild, const float* __restrict__ calpha,
+                             const float* __restrict__ g, float* lam, TriCtl* ctl, int it) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->diff_bits[(it + 1) & 1] = 0;
         ctl->lmax_bits[(it + 1) & 1] = 0;
     }
+    const int n = ctl->nlist;
     float d = 0.f, a = 0.f;
-    if (i < n_v) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int i = list[q];
         float l = g[i];
-        for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lin[cchild[k]];
-        lout[i] = l;
-        d = fabsf(l - lin[i]);
-        a = fabsf(l);
+        for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lam[cchild[k]];
+        d = fmaxf(d, fabsf(l - lam[i]));
+        a = fmaxf(a, fabsf(l));
+        lam[i] = l;
     }
     d = tri_block_max(d);
     a = tri_block_max(a);
@@ -425,73 +439,171 @@ __global__ void k_tri_adj_sweep(const int* __restrict__ cptr, const int* __restr
     }
 }
 
-// Level walk (leaves first), as on tetrahedra: rdy[i] is the launch from which
-// vertex i may be finished (0 for leaves), or one of these markers.
-constexpr int kTriNever = 0x7fffffff;   // waiting for children
-constexpr int kTriDone = 0x7ffffffd;    // finished (or unreached)
+// Two-cycles of the parent graph: a and c are partners when each is a weighted
+// parent of the other (the anisotropic scheme is not causal).  The walk leaves the
+// mutual edge out of both readiness counts and solves the pair jointly once both
+// members' other children are finished.  A vertex picks its smallest mutual
+// parent; a pair is kept only if both picked each other (pairrem: 2 at the
+// smaller member, -1 at the larger until k_tri_partner_fix, 0 elsewhere).
+__device__ __forceinline__ bool tri_weighted_parent(int2 pn, float4 w, int x) {
+    return (pn.x == x && w.x > 0.f) || (pn.y == x && w.y > 0.f);
+}
 
-// rem: children per vertex (the sorted CSR range); ctl->remaining counts the
-// reached vertices (each level subtracts those it finishes)
-__global__ void k_tri_walk_init(const int* __restrict__ cptr, const float* __restrict__ T, int n_v,
-                                int* __restrict__ rem, int* __restrict__ rdy, TriCtl* ctl) {
+__global__ void k_tri_partner(const int* __restrict__ par, const int2* __restrict__ pnode,
+                              const float4* __restrict__ pa, int n_v, int* __restrict__ partner) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    int best = -1;
+    if (par[a] >= 0) {
+        const int2 pn = pnode[a];
+        const float4 w = pa[a];
+        const int cand[2] = {w.x > 0.f ? pn.x : -1, w.y > 0.f ? pn.y : -1};
+        for (int k = 0; k < 2; ++k) {
+            const int c = cand[k];
+            if (c >= 0 && par[c] >= 0 && tri_weighted_parent(pnode[c], pa[c], a) && (best < 0 || c < best))
+                best = c;
+        }
+    }
+    partner[a] = best;
+}
+
+__global__ void k_tri_partner_sym(const int* __restrict__ partner, int n_v, int* __restrict__ pairrem) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    const int c = partner[a];
+    const bool ok = c >= 0 && partner[c] == a;
+    pairrem[a] = ok ? (a < c ? 2 : -1) : 0;
+}
+
+__global__ void k_tri_partner_fix(int* __restrict__ partner, int* __restrict__ pairrem, int n_v) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n_v) return;
+    const int r = pairrem[a];
+    if (r == 0) partner[a] = -1;
+    if (r < 0) pairrem[a] = 0;
+}
+
+// rem: the children a vertex waits for (its sorted CSR range but its partner);
+// done: 1 for unreached vertices; ctl->remaining: the reached vertices (the walk
+// subtracts those it finishes)
+__global__ void k_tri_walk_init(const int* __restrict__ cptr, const int* __restrict__ partner,
+                                const float* __restrict__ T, int n_v, int* __restrict__ rem,
+                                int* __restrict__ done, TriCtl* ctl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool reached = false;
     if (i < n_v) {
-        const int c = cptr[i + 1] - cptr[i];
-        rem[i] = c;
+        rem[i] = cptr[i + 1] - cptr[i] - (partner[i] >= 0 ? 1 : 0);
         reached = T[i] < GBP_INF;
-        rdy[i] = !reached ? kTriDone : (c == 0 ? 0 : kTriNever);
-        if (reached && c == 0) ctl->count[0] = 1;   // the first launch has work
+        done[i] = reached ? 0 : 1;
     }
     const unsigned long long r = tri_block_sum(reached ? 1ull : 0ull);
     if (threadIdx.x == 0 && r) atomicAdd(&ctl->remaining, (int)r);
 }
 
-// One level: a vertex stamped for this launch has every child finished in an
-// earlier launch; it sums lambda = g + sum alpha_c lambda_c over its children in
-// child order (the order of a Jacobi sweep: the same value), and a parent whose
-// last child it was is stamped for the next launch (read only after this one).
-__global__ void k_tri_walk_level(int* __restrict__ rdy, const int* __restrict__ cptr,
-                                 const int* __restrict__ cchild, const float* __restrict__ calpha,
-                                 const float* __restrict__ g, float* lam, const int* __restrict__ par,
-                                 const int2* __restrict__ pnode, const float4* __restrict__ pa,
-                                 int* __restrict__ rem, int n_v, TriCtl* ctl, int s) {
-    const int flag = ctl->count[s % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[(s + 2) % 3] = 0;
-        if (flag) atomicMax(&ctl->levels, s + 1);
-    }
-    if (flag == 0) return;
-    __shared__ int any_sh;
-    if (threadIdx.x == 0) any_sh = 0;
-    __syncthreads();
-    bool any = false;
-    unsigned long long fin_n = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_v; i += gridDim.x * blockDim.x) {
-        if (rdy[i] != s) continue;
-        ++fin_n;
-        float l = g[i];
-        for (int k = cptr[i]; k < cptr[i + 1]; ++k) l += calpha[k] * lam[cchild[k]];
-        lam[i] = l;
-        rdy[i] = kTriDone;
-        if (par[i] < 0) continue;
-        const int2 q = pnode[i];
-        const float4 w = pa[i];
-        if (w.x > 0.f && atomicSub(&rem[q.x], 1) == 1) {
-            rdy[q.x] = s + 1;
-            any = true;
-        }
-        if (w.y > 0.f && atomicSub(&rem[q.y], 1) == 1) {
-            rdy[q.y] = s + 1;
-            any = true;
-        }
-    }
-    if (any) any_sh = 1;
-    fin_n = tri_block_sum(fin_n);     // (its barriers also publish any_sh)
+constexpr int kWalkThreads = 1024;
+
+// A finished vertex releases its weighted parents (but `skip`); a parent whose
+// last awaited child this was joins the next frontier.
+__device__ __forceinline__ void tri_release(int x, int skip, const int* __restrict__ par,
+                                            const int2* __restrict__ pnode,
+                                            const float4* __restrict__ pa, int* __restrict__ rem,
+                                            int* __restrict__ next, int* n_next) {
+    if (par[x] < 0) return;
+    const int2 pn = pnode[x];
+    const float4 w = pa[x];
+    if (w.x > 0.f && pn.x != skip && atomicSub(&rem[pn.x], 1) == 1) next[atomicAdd(n_next, 1)] = pn.x;
+    if (w.y > 0.f && pn.y != skip && atomicSub(&rem[pn.y], 1) == 1) next[atomicAdd(n_next, 1)] = pn.y;
+}
+
+// The whole leaves-first walk in one work-group: the 2-D study's parent graphs are
+// deep and narrow (~2,000 levels of ~100 vertices at 250k vertices), so a launch
+// (and a convergence read) per level would cost more than the level's work.
+// Each level's frontier lives in global memory (qa / qb, each vertex enters once);
+// block barriers order the levels, which makes every earlier level's lambdas
+// visible to the next.  A vertex sums lambda = g + sum alpha_c lambda_c over its
+// children in child order (the value a sweep of lambda = g + P^T lambda gives);
+// the second member of a two-cycle to become ready solves the pair
+//   lam_a = S_a + w_ca lam_c,  lam_c = S_c + w_ac lam_a.
+// Ends when a frontier is empty (each vertex enters at most once, so after at
+// most n_v levels).
+__global__ void __launch_bounds__(kWalkThreads)
+    k_tri_walk(const int* __restrict__ cptr, const int* __restrict__ cchild,
+               const float* __restrict__ calpha, const float* __restrict__ g, float* lam,
+               const int* __restrict__ par, const int2* __restrict__ pnode,
+               const float4* __restrict__ pa, const int* __restrict__ partner,
+               int* __restrict__ rem, int* __restrict__ pairrem, int* __restrict__ done,
+               const float* __restrict__ T, int* qa, int* qb, int n_v, TriCtl* ctl) {
+    __shared__ int n_cur, n_next, n_fin;
     if (threadIdx.x == 0) {
-        if (any_sh) ctl->count[(s + 1) % 3] = 1;
-        if (fin_n) atomicSub(&ctl->remaining, (int)fin_n);
+        n_cur = 0;
+        n_fin = 0;
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_v; i += blockDim.x)
+        if (T[i] < GBP_INF && rem[i] == 0) qa[atomicAdd(&n_cur, 1)] = i;
+    __syncthreads();
+    int* cur = qa;
+    int* nxt = qb;
+    int level = 0;
+    while (n_cur > 0) {
+        const int n = n_cur;
+        __syncthreads();                    // everyone has read n_cur
+        if (threadIdx.x == 0) n_next = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const int x = cur[k];
+            const int q = partner[x];
+            if (q < 0) {
+                float l = g[x];
+                for (int e = cptr[x]; e < cptr[x + 1]; ++e) l += calpha[e] * lam[cchild[e]];
+                lam[x] = l;
+                done[x] = 1;
+                atomicAdd(&n_fin, 1);
+                tri_release(x, -1, par, pnode, pa, rem, nxt, &n_next);
+                continue;
+            }
+            if (atomicSub(&pairrem[min(x, q)], 1) != 1) continue;   // partner not ready yet
+            float S[2], w[2];
+            const int pr[2] = {x, q};
+            for (int m = 0; m < 2; ++m) {
+                const int a = pr[m], o = pr[1 - m];
+                float l = g[a], wo = 0.f;
+                for (int e = cptr[a]; e < cptr[a + 1]; ++e) {
+                    const int c = cchild[e];
+                    if (c == o) wo = calpha[e];
+                    else l += calpha[e] * lam[c];
+                }
+                S[m] = l;
+                w[m] = wo;                  // weight of a in o's parent face
+            }
+            const float lx = (S[0] + w[0] * S[1]) / (1.f - w[0] * w[1]);
+            lam[x] = lx;
+            lam[q] = S[1] + w[1] * lx;
+            done[x] = 1;
+            done[q] = 1;
+            atomicAdd(&n_fin, 2);
+            tri_release(x, q, par, pnode, pa, rem, nxt, &n_next);
+            tri_release(q, x, par, pnode, pa, rem, nxt, &n_next);
+        }
+        __syncthreads();                    // the level's lambdas, releases and n_next
+        if (threadIdx.x == 0) n_cur = n_next;
+        int* t = cur;
+        cur = nxt;
+        nxt = t;
+        ++level;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->levels = level;
+        atomicSub(&ctl->remaining, n_fin);
+    }
+}
+
+// the reached vertices the walk left unfinished (on or above longer cycles), as a list
+__global__ void k_tri_walk_list(const int* __restrict__ done, int n_v, int* __restrict__ list,
+                                TriCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_v && !done[i]) list[atomicAdd(&ctl->nlist, 1)] = i;
 }
 
 __global__ void k_tri_grad_tri(const float2* __restrict__ xy, const int4* __restrict__ tri,
@@ -695,16 +807,20 @@ extern "C" int gbp_tri_plan_create(const float* xy, int n_v, const int32_t* tris
     TRI_TRY(tri_alloc(&p->ccnt, (size_t)n_v + 1));
     TRI_TRY(tri_alloc(&p->cfill, n_v));
     TRI_TRY(tri_alloc(&p->rdy, n_v));
+    TRI_TRY(tri_alloc(&p->partner, n_v));
+    TRI_TRY(tri_alloc(&p->pairrem, n_v));
     TRI_TRY(tri_alloc(&p->cchild, (size_t)2 * n_v));
     TRI_TRY(tri_alloc(&p->calpha, (size_t)2 * n_v));
     TRI_TRY(tri_alloc(&p->lam[0], n_v));
-    TRI_TRY(tri_alloc(&p->lam[1], n_v));
     TRI_TRY(tri_alloc(&p->g, n_v));
     TRI_TRY(tri_alloc(&p->dsbar, n_t));
     TRI_TRY(tri_alloc(&p->scan_tmp, (size_t)(n_v / 256 + 2)));
 #undef TRI_UP
 #undef TRI_TRY
     if (hipHostMalloc((void**)&p->ctl_host, sizeof(TriCtl)) != hipSuccess ||
+        hipHostMalloc((void**)&p->ctl_pipe, 2 * sizeof(TriCtl)) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev[1], hipEventDisableTiming) != hipSuccess ||
         hipMemset(p->mark, 0, (size_t)n_v * sizeof(int)) != hipSuccess) {
         gbp_set_error("pinned control block or mark reset failed");
         tri_free(p);
@@ -740,7 +856,11 @@ extern "C" int gbp_tri_forward(gbp_tri_plan p, const float* D, const float* vsca
     const int n_v = p->n_v;
     if ((rc = tri_prepare(p, D, vscale, root_node, root_t, n_roots, true, s))) return rc;
     const int grid = std::max(1, std::min(gbp_blocks(n_v, TPB), 1024));
-    int r = 0;
+    // batches of 8 rounds; the host checks batch k's queue length (copied into
+    // pinned memory behind it, with an event) only once batch k + 1 is queued, so
+    // the device never waits for the check; a finished solve costs one batch of
+    // empty rounds (each returns at once)
+    int r = 0, batch = 0, r_prev = 0;
     bool converged = false;
     while (r < p->max_rounds) {
         for (int b = 0; b < 8; ++b, ++r)
@@ -748,20 +868,28 @@ extern "C" int gbp_tri_forward(gbp_tri_plan p, const float* D, const float* vsca
                                               p->T, p->q[r & 1], p->q[(r + 1) & 1], p->mark, p->ctl, r,
                                               p->stamp + r + 1, p->eps_rel);
         GBP_LAUNCH_CHECK();
-        if ((rc = tri_read(p, s))) return rc;
-        if (p->ctl_host->err) break;
-        if (p->ctl_host->count[r % 3] == 0) {
-            converged = true;
-            break;
+        GBP_HIP(hipMemcpyAsync(p->ctl_pipe + (batch & 1), p->ctl, sizeof(TriCtl), hipMemcpyDeviceToHost, s));
+        GBP_HIP(hipEventRecord(p->ev[batch & 1], s));
+        if (batch > 0) {
+            GBP_HIP(hipEventSynchronize(p->ev[(batch - 1) & 1]));
+            const TriCtl& c = p->ctl_pipe[(batch - 1) & 1];
+            if (c.err) break;
+            if (c.count[r_prev % 3] == 0) {
+                converged = true;
+                break;
+            }
         }
+        r_prev = r;
+        ++batch;
     }
     p->stamp += r + 2;
     k_tri_count_inf<<<gbp_blocks(n_v, TPB), TPB, 0, s>>>(p->T, n_v, p->ctl);
     GBP_HIP(hipMemcpyAsync(T_out, p->T, (size_t)n_v * sizeof(float), hipMemcpyDeviceToDevice, s));
     if ((rc = tri_read(p, s))) return rc;
     const TriCtl& c = *p->ctl_host;
+    if (!converged && !c.err && c.count[r % 3] == 0) converged = true;   // the cap's last batch finished it
     if (stats) {
-        stats->rounds = r;
+        stats->rounds = c.rounds;
         stats->converged = converged ? 1 : 0;
         stats->face_solves = (int64_t)c.solves;
         stats->node_updates = (int64_t)c.updates;
@@ -802,33 +930,33 @@ extern "C" int gbp_tri_backward(gbp_tri_plan p, const float* D, const float* vsc
                                         p->calpha);
     k_tri_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v);
     k_tri_adj_init<<<nb, TPB, 0, s>>>(dL_dT, p->T, n_v, p->g, p->lam[0]);
-    // leaves-first level walk (cfill: the children each vertex still waits for),
-    // checked every 16 levels
-    k_tri_walk_init<<<nb, TPB, 0, s>>>(p->ccnt, p->T, n_v, p->cfill, p->rdy, p->ctl);
+    // two-cycles, then the leaves-first walk in one work-group (cfill: the children
+    // each vertex still waits for; rdy: finished flags; the forward's queues hold
+    // the frontiers)
+    k_tri_partner<<<nb, TPB, 0, s>>>(p->par, p->pnode, p->pa, n_v, p->partner);
+    k_tri_partner_sym<<<nb, TPB, 0, s>>>(p->partner, n_v, p->pairrem);
+    k_tri_partner_fix<<<nb, TPB, 0, s>>>(p->partner, p->pairrem, n_v);
+    k_tri_walk_init<<<nb, TPB, 0, s>>>(p->ccnt, p->partner, p->T, n_v, p->cfill, p->rdy, p->ctl);
+    k_tri_walk<<<1, kWalkThreads, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->g, p->lam[0], p->par, p->pnode,
+                                          p->pa, p->partner, p->cfill, p->pairrem, p->rdy, p->T, p->q[0],
+                                          p->q[1], n_v, p->ctl);
     GBP_LAUNCH_CHECK();
-    const int wgrid = std::max(1, std::min(nb, 1024));
-    int level = 0;
-    while (level <= n_v + 1) {
-        for (int b = 0; b < 16; ++b, ++level)
-            k_tri_walk_level<<<wgrid, TPB, 0, s>>>(p->rdy, p->ccnt, p->cchild, p->calpha, p->g, p->lam[0],
-                                                   p->par, p->pnode, p->pa, p->cfill, n_v, p->ctl, level);
-        GBP_LAUNCH_CHECK();
-        if ((rc = tri_read(p, s))) return rc;
-        if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
-        if (p->ctl_host->count[level % 3] == 0) break;
-    }
+    if ((rc = tri_read(p, s))) return rc;
+    if (p->ctl_host->err) return gbp_err_from_bits(p->ctl_host->err);
     p->last_levels = p->ctl_host->levels;
     p->last_cyclic = p->ctl_host->remaining;
-    // vertices on or above parent-graph cycles: Jacobi sweeps from the walk's
-    // values (finished vertices reproduce theirs), checked every 16
+    // vertices on or above parent-graph cycles: Gauss-Seidel sweeps over just
+    // those (their children outside the list are final), checked every 16
     int it = 0;
     if (p->ctl_host->remaining > 0) {
+        k_tri_walk_list<<<nb, TPB, 0, s>>>(p->rdy, n_v, p->cfill, p->ctl);   // rem is no longer needed
+        const int gs_grid = std::max(1, std::min(gbp_blocks(p->ctl_host->remaining, TPB), 1024));
         const int cap = 8 * n_v + 64;
         bool settled = false;
         while (it < cap) {
             for (int b = 0; b < 16; ++b, ++it)
-                k_tri_adj_sweep<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->g, p->lam[it & 1],
-                                                    p->lam[(it + 1) & 1], n_v, p->ctl, it);
+                k_tri_adj_gs<<<gs_grid, TPB, 0, s>>>(p->cfill, p->ccnt, p->cchild, p->calpha, p->g,
+                                                     p->lam[0], p->ctl, it);
             GBP_LAUNCH_CHECK();
             if ((rc = tri_read(p, s))) return rc;
             const float d = __builtin_bit_cast(float, p->ctl_host->diff_bits[(it - 1) & 1]);
@@ -844,7 +972,7 @@ extern "C" int gbp_tri_backward(gbp_tri_plan p, const float* D, const float* vsc
         }
     }
     p->last_sweeps = it;
-    const float* lam = p->lam[it & 1];
+    const float* lam = p->lam[0];
     k_tri_fill<<<gbp_blocks(n_t, TPB), TPB, 0, s>>>(p->dsbar, 0.f, n_t);
     if (dL_dD) k_tri_fill<<<gbp_blocks(3LL * n_t, TPB), TPB, 0, s>>>(dL_dD, 0.f, 3 * n_t);
     k_tri_grad_tri<<<nb, TPB, 0, s>>>(p->xy, p->tri, D, vscale, p->par, p->pnode, p->pa, lam, n_v,
