@@ -602,9 +602,24 @@ def cpu_baseline(prob, vs, rt, threads):
         res = O.adjoint(prob.xyz, prob.tets, prob.D, vs, prob.root_node, rt, T, g, par=par)
         O.adam_step(vs, res["dvscale"], np.zeros_like(vs), np.zeros_like(vs), 1, lr=0.01)
         t4 = time.perf_counter()
+    # the same oracle on one thread and on `threads`, over a bounded sample: a full
+    # Alg. 2 solve on the 64k-vertex member of the same shell family
+    import gbp_inputs as gi
+    small = gi.shell_problem(64_000, seed=2, n_roots=5, n_leads=12)
+    Minv_s = O.metric_inverse(small.D, None, small.tets)
+    solve_s = {}
+    for n in sorted({1, threads}):
+        O.set_threads(n)
+        with threadpool_limits(limits=n):
+            ts = time.perf_counter()
+            O.fim(small.xyz, small.tets, Minv_s, small.root_node, small.root_t)
+            solve_s[str(n)] = time.perf_counter() - ts
     O.set_threads(1)
     total = t4 - t0
     return dict(value=1.0 / total, unit="iter/s", cores=threads, kind="oracle", **host_info(),
+                thread_scaling=dict(sample=f"one Alg. 2 solve on the {small.n_v}-vertex member of the same "
+                                           f"shell family", seconds=solve_s,
+                                    speedup=solve_s["1"] / solve_s[str(threads)]),
                 seconds=dict(eikonal=t1 - t0, parents=t2 - t1, ecg=t3 - t2, adjoint_adam=t4 - t3, total=total),
                 sample=(f"one full FP64 oracle iteration on the benchmark workload itself ({prob.n_v} vertices, "
                         f"{prob.n_e} tets, same inputs): Alg. 2 Jacobi ({st['sweeps']} sweeps, "
