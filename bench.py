@@ -67,6 +67,18 @@ PEAK_BF16_TFLOPS = 2500.0   # dense bf16 matrix-core peak
 FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched", "learned", "inverse")
 
 
+# Launch configuration of the plain iteration on this workload: the autotuner's
+# search (autotune.tune) followed by a finer sweep of the hold-back around its
+# pick, timed with this script (16 lanes per vertex, 1024 blocks per relaxation
+# round, convergence read every 16 launches, 2048 blocks per adjoint level, queue
+# split over the XCDs; hold-back buckets of 2.5 ms, no window, the next bucket
+# opened while fewer than 16384 vertices -- one round's grid -- are queued).
+# Fixed so that a profiled run of the same command times the same kernels;
+# --tune searches again.
+DEFAULT_LAUNCH = "16,1024,16,2048,1"
+DEFAULT_HOLD = "2.5,0,16384"
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,13 +91,13 @@ def parse():
                     help="host threads of the CPU baseline (0: min(16, cores))")
     ap.add_argument("--cpu-only", action="store_true",
                     help="time only the CPU baseline on this host (no GPU) and print it")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configuration")
-    ap.add_argument("--launch", default="", metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS,SPLIT",
-                    help="use this launch configuration instead of autotuning (e.g. to profile the "
-                         "configuration a timed run chose)")
-    ap.add_argument("--hold", default="", metavar="DELTA,WINDOW,OPEN_BELOW",
-                    help="with --launch: the cold forward's hold-back (bucket width in ms, window, "
-                         "opening threshold)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner instead of the fixed configuration")
+    ap.add_argument("--launch", default=DEFAULT_LAUNCH, metavar="LANES,BLOCKS,BATCH,LEVEL_BLOCKS,SPLIT",
+                    help="launch configuration (default: the one tuned for the benchmark workload)")
+    ap.add_argument("--hold", default=DEFAULT_HOLD, metavar="DELTA,WINDOW,OPEN_BELOW",
+                    help="the cold forward's hold-back (bucket width in ms, window, opening threshold; "
+                         "delta 0 turns it off)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip every form beside the plain iteration")
     ap.add_argument("--forms", default=",".join(FORMS), metavar="LIST",
@@ -664,14 +676,16 @@ def main():
     log(f"[bench] shell n_v={prob.n_v} n_e={prob.n_e} generated in {time.time() - t:.1f}s")
     st = make_state(prob, dev, torch, gi, B)
     tuned = None
-    if args.launch:
+    if args.no_tune:
+        pass
+    elif not args.tune:
         lanes, blocks, batch, lblocks, split = (int(x) for x in args.launch.split(",")[:5])
         B.set_launch(st["plan"], lanes, blocks, lblocks, batch)
         B.set_queue_split(st["plan"], split)
-        if args.hold:
-            d, w, o = args.hold.split(",")
-            B.set_hold(st["plan"], float(d), int(w), int(o))
-    elif not args.no_tune:
+        d, w, o = args.hold.split(",")
+        B.set_hold(st["plan"], float(d), int(w), int(o))
+        log(f"[bench] launch {args.launch}, hold-back {args.hold}")
+    else:
         from paper_2308_08410_amd import autotune
         t = time.time()
         tuned = autotune.tune(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], use_cache=False, save=False)

@@ -28,7 +28,8 @@ LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
 # hold-back candidates, searched last: (bucket width / mean front advance per round,
 # buckets past the current one that propagate, opening threshold / vertices one
 # round's grid takes at once, None: open a bucket every round); (0, 0, 0) is off
-HOLD_SPACE = ((0, 0, 0.0), (1, 2, None), (1, 4, None), (4, 0, 2.0), (8, 0, 0.5))
+HOLD_SPACE = ((0, 0, 0.0), (1, 2, None), (2, 0, 1.0), (2, 0, 2.0), (3, 0, 1.0), (4, 0, 1.0), (4, 0, 2.0),
+              (4, 0, 4.0))
 
 
 def cache_path() -> str:
