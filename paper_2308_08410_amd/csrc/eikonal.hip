@@ -522,13 +522,14 @@ __global__ void __launch_bounds__(TPB)
         for (int xs = 0; xs < 8; ++xs) tot += ctl->qcnt[s % 3][xs];
         if (tot == 0) {
             // nothing is evaluated, so no list grows: skip to the next non-empty bucket
-            for (int k = 1; k < kHoldBuckets; ++k) {
-                const int c = ctl->bcnt[(bc + k) & (kHoldBuckets - 1)];
-                if (c > 0) {
-                    bopen = bc + k;
-                    nopen = min(c, ha.bcap);
-                    break;
-                }
+            // (lane k of each wave reads bucket bc + 1 + k, a ballot finds the first)
+            const int k = threadIdx.x & 63;
+            const int c = k < kHoldBuckets - 1 ? ctl->bcnt[(bc + 1 + k) & (kHoldBuckets - 1)] : 0;
+            const unsigned long long nz = __ballot(c > 0);
+            if (nz) {
+                const int first = __ffsll(nz) - 1;
+                bopen = bc + 1 + first;
+                nopen = min(__shfl(c, first), ha.bcap);
             }
         } else if (tot < ha.open_below) {
             // the tail of the current bucket: open the next one beside it; this
