@@ -163,20 +163,27 @@ def test_full_forward_with_fista(full, launch):
     assert np.all(Tg >= full.T_ref * (1 - 1e-5) - 1e-6)
 
 
-@pytest.mark.parametrize("launch", [(16, 1024, 32, 2048, True), (8, 512, 16, 512, False), (32, 2048, 64, 1024, True)])
+@pytest.mark.parametrize("launch", [(16, 1024, 16, 2048, True, (2.5, 0, 16384)),
+                                    (16, 1024, 32, 2048, True, (4.0, 0, 32768)),
+                                    (8, 512, 16, 512, False, (0.0, 0, 0)),
+                                    (32, 2048, 64, 1024, True, (1.0, 2, 1 << 30))])
 def test_full_forward_and_gradients_in_launch_configs(full, launch):
     """The 500k forward against the stored oracle times, and the gradients against
-    those of the default configuration, in the configuration the benchmark's
-    autotuner picks (first) and two others from its search space."""
-    lanes, blocks, batch, lblocks, split = launch
+    those of the default configuration, in the benchmark's launch configuration
+    (first: the one bench.py times, hold-back included) and others from the
+    autotuner's search space."""
+    lanes, blocks, batch, lblocks, split, hold = launch
     plan = full.plan
     saved = B().get_launch(plan)
     saved_split = B().get_queue_split(plan)
+    saved_hold = B().get_hold(plan)
     g = t32(np.random.Generator(np.random.PCG64(12)).normal(size=full.p.n_v), full.dev)
     ref = B().eikonal_backward(plan, full.D, full.vst, full.rn, full.rtt, full.T_ref_dev, g)
     B().set_launch(plan, lanes, blocks, lblocks, batch)
     B().set_queue_split(plan, split)
+    B().set_hold(plan, *hold)
     try:
+        print(f"[case] 500k launch {launch}", flush=True)
         T, st = B().eikonal_forward(plan, full.D, full.vst, full.rn, full.rtt)
         assert st["converged"]
         assert rel_max(T.cpu().numpy(), full.T_ref) <= 1e-4
@@ -186,3 +193,4 @@ def test_full_forward_and_gradients_in_launch_configs(full, launch):
     finally:
         B().set_launch(plan, saved["lanes"], saved["sweep_blocks"], saved["level_blocks"], saved["sync_batch"])
         B().set_queue_split(plan, saved_split)
+        B().set_hold(plan, *saved_hold)
