@@ -624,7 +624,9 @@ typedef struct {
     float *loss;                /* [n_inst] output */
     float lr_vscale, lr_root_t, vscale_lo, vscale_hi;
     int round_budget, level_budget, gs_budget;
-    int warm;                   /* 1: forward starts from T (two-sided update) */
+    int warm;                   /* 1: forward warm-started from T: two-sided update,
+                                   or (plan's warm order on at creation) a cold
+                                   solve ordered by T */
     int reserved[4];            /* must be zero */
 } gbp_step_desc;
 typedef struct gbp_step_s *gbp_step;
@@ -661,8 +663,9 @@ int gbp_step_set_state(gbp_step step, const float *m_vscale, const float *v_vsca
  * Learned warm start (an extension beyond the paper, which solves every
  * forward from scratch): a multilayer perceptron 16 -> 256 -> 256 -> 256 -> 256
  * -> 1 with ReLU activations predicts activation times from per-vertex
- * features; its prediction seeds gbp_eikonal_forward's T_init (two-sided
- * update), whose fixed point is the cold solution whatever the guess.
+ * features; its prediction is gbp_eikonal_forward's T_init (the two-sided
+ * update, or the ordering guess of gbp_plan_set_warm_order), whose fixed point
+ * is the cold solution whatever the guess.
  *
  * Precision: features and hidden weights are bf16, products accumulate in
  * fp32 on the matrix cores, hidden activations are stored as bf16; the output

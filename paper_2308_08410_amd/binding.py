@@ -403,7 +403,7 @@ def tri_backward(plan: TriPlan, D, vscale, root_node, root_t, T, dL_dT, want_D=T
 
 
 def tri_backward_info(plan: TriPlan):
-    """The last triangle backward: adjoint levels, vertices left to the Jacobi
+    """The last triangle backward: adjoint levels, vertices left to the Gauss-Seidel
     sweeps by parent-graph cycles, sweeps taken."""
     v = [c_int() for _ in range(3)]
     _check(_tri_backward_info(plan.handle, *[ctypes.byref(x) for x in v]))
