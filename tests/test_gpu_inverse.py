@@ -42,8 +42,9 @@ def test_fit_resumes_from_checkpoint(tmp_path):
     """A fit checkpointed after k iterations and resumed by a new fit object (new
     plan, new captured step) continues as the uninterrupted fit: parameters, Adam
     state and counter match after 2k iterations.  The in-place relaxation's order
-    varies between runs in the last bits of T, so parameters are compared to 1e-5 of
-    their scale; the counter exactly.  The run log records the header and the
+    varies between runs in the last bits of T, so parameters are compared to 1e-4 of
+    their scale (a fresh optimiser state lands more than 1e-3 away); the counter
+    exactly.  The run log records the header and the
     misfits."""
     _dev()
     from paper_2308_08410_amd import runlog
@@ -75,8 +76,22 @@ def test_fit_resumes_from_checkpoint(tmp_path):
     second.run(k, start=k, check_every=k)
     got = second.step.get_state()
     assert got["counter"] == ref["counter"] == 2 * k + 1
-    assert np.abs(second.vs.cpu().numpy() - vs_ref).max() <= 1e-5 * np.abs(vs_ref).max()
-    assert np.abs(second.rt.cpu().numpy() - rt_ref).max() <= 1e-5 * np.abs(rt_ref).max()
+    d_vs = np.abs(second.vs.cpu().numpy() - vs_ref).max() / np.abs(vs_ref).max()
+    d_rt = np.abs(second.rt.cpu().numpy() - rt_ref).max() / np.abs(rt_ref).max()
+    print(f"[resume] max rel difference after {2 * k} iterations: vscale {d_vs:.2e}, onsets {d_rt:.2e}", flush=True)
+    # run to run, the relaxation order moves T in its last bits and the fit by ~1e-6
+    assert d_vs <= 1e-4 and d_rt <= 1e-4
+    # the bar tells a restored optimiser from a fresh one: the same parameters with
+    # Adam's moments and counter reset end up far away
+    third = make()
+    third.restore(ck)
+    st0 = third.step.get_state()
+    third.step.set_state(dict(m_vscale=st0["m_vscale"] * 0, v_vscale=st0["v_vscale"] * 0,
+                              m_root_t=st0["m_root_t"] * 0, v_root_t=st0["v_root_t"] * 0, counter=1))
+    third.run(k, start=k, check_every=k)
+    d_fresh = np.abs(third.vs.cpu().numpy() - vs_ref).max() / np.abs(vs_ref).max()
+    print(f"[resume] with a fresh optimiser instead: vscale {d_fresh:.2e}", flush=True)
+    assert d_fresh > 10 * 1e-4
     for name in ("m_vscale", "v_vscale", "m_root_t", "v_root_t"):
         a, b = got[name].cpu().numpy(), ref[name].cpu().numpy()
         assert np.abs(a - b).max() <= 1e-4 * max(np.abs(b).max(), 1e-30), name
