@@ -379,7 +379,7 @@ def learned_form(st, prob, torch, B, n_train=128, steps=1500, batch=16384, n_tes
     data = WS.make_dataset(plan, prob.xyz, D, prob.extra["endo"], n_train, seed=1000 * seed, scale_bank=32)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    ws = WS.WarmStart(prob.xyz, prob.extra["node_fibre"], max_rows=max(batch, 1 << 16), seed=seed)
+    ws = WS.WarmStart(prob.xyz, prob.extra["node_fibre"], max_rows=batch, seed=seed)
     t0 = time.perf_counter()
     hist = WS.train(ws, data, steps, batch=batch, lr=1e-3, log_every=max(1, steps // 5))
     torch.cuda.synchronize()

@@ -675,8 +675,8 @@ int gbp_step_set_state(gbp_step step, const float *m_vscale, const float *v_vsca
  * b1[256], W2[256][256], b2, W3[256][256], b3, W4[256][256], b4, w5[256], b5[1]
  * (row-major, W_l maps layer l-1 to layer l).
  *
- * gbp_mlp_create: allocates a network for batches of up to max_rows rows
- *   (1 <= max_rows <= 2^21),
+ * gbp_mlp_create: allocates a network for training batches of up to max_rows
+ *   rows (1 <= max_rows <= 2^21),
  *   He-normal weights from `seed` (column 16 of W1, the pad feature, is zero),
  *   zero biases and moments.  Errors: GBP_ERR_ARG, GBP_ERR_NOMEM, GBP_ERR_HIP.
  * gbp_mlp_set_params / gbp_mlp_get_params: host fp32 copies of the parameter
@@ -695,9 +695,13 @@ int gbp_step_set_state(gbp_step step, const float *m_vscale, const float *v_vsca
  *   norm: HOST float[5] = {cx, cy, cz, len_scale, time_scale}.  With T (device
  *   [n_v]) and target (device [n_rows]) non-NULL, also target[r] = T[rows[r]] /
  *   time_scale (training data).  Errors: GBP_ERR_ARG.
- * gbp_mlp_forward: y[m] = out_scale * MLP(X) for m <= max_rows rows (device);
- *   non-finite predictions are written as +inf, which the warm-started solve
- *   treats as no information.
+ * gbp_mlp_forward: y[m] = out_scale * MLP(X) for 1 <= m <= 2^27 rows (device;
+ *   not limited by max_rows: the whole network runs in one kernel per 64 or 128
+ *   rows with the activations kept on chip, rounded as in gbp_mlp_gradient's
+ *   forward pass); non-finite predictions are written as +inf, which the
+ *   warm-started solve treats as no information.  X must be 16-byte aligned
+ *   (rows are read in 16-byte pieces).  Errors: GBP_ERR_ARG (rows, NULL,
+ *   alignment).
  * gbp_mlp_gradient: forward, mean squared error against target[m] (device),
  *   written to *loss (device, may be NULL), and the parameter gradient (kept in
  *   the network; read with gbp_mlp_get_params).

@@ -29,6 +29,13 @@ constexpr int IN = 16;      // 15 features + 1 zero pad
 constexpr int HID = 256;
 constexpr int NLAYER = 4;   // hidden layers
 
+// flat parameter layout: W1 [256x16], b1, W2 [256x256], b2, W3, b3, W4, b4, w5 [256], b5 [1]
+__host__ __device__ constexpr int off_W_dev(int l) {   // l = 1..4
+    return l == 1 ? 0 : HID * IN + HID + (l - 2) * (HID * HID + HID);
+}
+__host__ __device__ constexpr int off_b_dev(int l) { return off_W_dev(l) + (l == 1 ? HID * IN : HID * HID); }
+__host__ __device__ constexpr int off_w5_dev() { return off_W_dev(4) + HID * HID + HID; }
+
 __device__ __forceinline__ bf16 to_bf16(float x) {
     const unsigned u = __float_as_uint(x);
     return (bf16)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
@@ -189,6 +196,142 @@ __global__ void k_head_bwd(const float* __restrict__ dy, const bf16* __restrict_
     const bf16 h = H[t];
     dZ[t] = to_bf16((h != 0 && !(h & 0x8000)) ? dy[i] * w5[j] : 0.f);
 }
+
+// ---------------------------------------------------------------- fused inference
+// The whole network for a tile of 16 TR rows in one block of 4 waves: the
+// activations stay in LDS (16 TR x 256 bf16, overwritten layer by layer), only
+// the features come in and the predictions go out.  Wave w computes the output
+// columns [64 w, 64 w + 64) of a layer for all the tile's rows as the transposed
+// product W H^T: TR x 4 tiles of v_mfma_f32_16x16x32_bf16 per K step of 32, the
+// A operand (a weight row's 8 consecutive K values) loaded straight from global
+// memory (a layer's 128 KB of weights stay in L2; each fragment serves 16 TR
+// rows), the B operand (an activation row's 8 K values) read from LDS, the next
+// step's weight fragments in flight while the current step multiplies.  A
+// layer's output overwrites its input only after every wave has finished
+// reading it.  Rounding as in the layered kernels: H = bf16(relu(fp32 acc + b)),
+// the head in fp32.
+constexpr int HP = HID + 8;   // LDS row pitch (bf16): 528 bytes, 16-byte aligned rows
+
+__device__ __forceinline__ bf16x8_t ld8(const bf16* p) {
+    return *reinterpret_cast<const bf16x8_t*>(p);
+}
+
+// layer output bf16(relu(acc + b)) into the wave's 64 columns of H.  The tiles
+// hold the layer's output transposed (column j of the layer = row of the tile),
+// so a lane's 4 values are 4 consecutive columns of one row: one 8-byte store.
+template <int TR>
+__device__ __forceinline__ void infer_store(bf16 (*H)[HP], const floatx4 (&acc)[TR][4],
+                                            const float* __restrict__ bias, int j0, int lr, int lq) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = j0 + c * 16 + 4 * lq;
+        const float b0 = bias[j], b1 = bias[j + 1], b2 = bias[j + 2], b3 = bias[j + 3];
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const unsigned lo = to_bf16(fmaxf(acc[t][c][0] + b0, 0.f)) |
+                                ((unsigned)to_bf16(fmaxf(acc[t][c][1] + b1, 0.f)) << 16);
+            const unsigned hi = to_bf16(fmaxf(acc[t][c][2] + b2, 0.f)) |
+                                ((unsigned)to_bf16(fmaxf(acc[t][c][3] + b3, 0.f)) << 16);
+            *reinterpret_cast<uint2*>(&H[t * 16 + lr][j]) = make_uint2(lo, hi);
+        }
+    }
+}
+
+template <int TR>
+__global__ void __launch_bounds__(256, 2)
+    k_mlp_infer(const bf16* __restrict__ X, int m, const bf16* __restrict__ W1,
+                const bf16* __restrict__ W2, const bf16* __restrict__ W3, const bf16* __restrict__ W4,
+                const float* __restrict__ params, float out_scale, float* __restrict__ y) {
+    constexpr int IB = 16 * TR;                // rows per block
+    __shared__ __align__(16) bf16 H[IB][HP];
+    const int i0 = blockIdx.x * IB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = wave * 64;                  // this wave's output columns
+    const int lr = lane & 15, lq = lane >> 4;  // row (A) / column (B) in a 16-tile, K quarter
+    floatx4 acc[TR][4];
+    bf16x8_t zero8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
+    // layer 1: K = 16 features; quarters 2 and 3 of the 32-wide K step are zero
+    {
+        bf16x8_t bw[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bw[c] = lq < 2 ? ld8(W1 + (size_t)(j0 + c * 16 + lr) * IN + 8 * lq) : zero8;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int i = i0 + t * 16 + lr;
+            const bf16x8_t af = (lq < 2 && i < m) ? ld8(X + (size_t)i * IN + 8 * lq) : zero8;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, floatx4{0.f, 0.f, 0.f, 0.f},
+                                                                    0, 0, 0);
+        }
+        infer_store<TR>(H, acc, params + off_b_dev(1), j0, lr, lq);
+        __syncthreads();
+    }
+    // layers 2..4: K = 256 in 8 steps
+#pragma unroll 1
+    for (int l = 2; l <= NLAYER; ++l) {
+        const bf16* W = l == 2 ? W2 : l == 3 ? W3 : W4;
+#pragma unroll
+        for (int t = 0; t < TR; ++t)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        bf16x8_t bw[4], bn[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bw[c] = ld8(W + (size_t)(j0 + c * 16 + lr) * HID + 8 * lq);
+#pragma unroll 2
+        for (int ks = 0; ks < HID / 32; ++ks) {
+            if (ks + 1 < HID / 32) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    bn[c] = ld8(W + (size_t)(j0 + c * 16 + lr) * HID + (ks + 1) * 32 + 8 * lq);
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&H[t * 16 + lr][ks * 32 + 8 * lq]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, acc[t][c], 0, 0, 0);
+            }
+            if (ks + 1 < HID / 32) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) bw[c] = bn[c];
+            }
+        }
+        __syncthreads();                       // every wave has read this layer's input
+        infer_store<TR>(H, acc, params + off_b_dev(l), j0, lr, lq);
+        __syncthreads();
+    }
+    // head: y = H4 . w5 + b5 in fp32, 256 / IB threads per row
+    constexpr int TPR = 256 / IB;              // threads per row
+    constexpr int CPT = HID / TPR;             // columns per thread
+    const float* w5 = params + off_w5_dev();
+    const int row = threadIdx.x / TPR, part = threadIdx.x % TPR;
+    float sum = 0.f;
+#pragma unroll 4
+    for (int j = part * CPT; j < part * CPT + CPT; j += 8) {
+        const uint4 u = *reinterpret_cast<const uint4*>(&H[row][j]);
+        const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sum += __uint_as_float(w[q] << 16) * w5[j + 2 * q];
+            sum += __uint_as_float(w[q] & 0xffff0000u) * w5[j + 2 * q + 1];
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < TPR; o <<= 1) sum += __shfl_xor(sum, o);
+    const int i = i0 + row;
+    if (part == 0 && i < m) {
+        const float v = out_scale * (sum + w5[HID]);
+        y[i] = isfinite(v) ? v : __builtin_huge_valf();
+    }
+}
+// rows per block 16 TR: 128 once there are enough rows to give every CU a block
+// (fewer weight fetches per row), else 64 (more blocks for small batches)
+constexpr int kInferRowsLarge = 32768;
+// inference keeps nothing per row on the device: any batch up to 2^27 rows
+constexpr int kInferRowsMax = 1 << 27;
 
 // prediction out: scale * y, non-finite values as +inf (no information)
 __global__ void k_scale_out(const float* __restrict__ y, int m, float scale, float* __restrict__ out) {
@@ -528,15 +671,25 @@ extern "C" int gbp_mlp_features(const float* xyz, const float* fibre, const floa
 
 extern "C" int gbp_mlp_forward(gbp_mlp p, const uint16_t* X, int m, float out_scale, float* y,
                                void* stream) {
-    int rc = check_rows(p, m);
-    if (rc) return rc;
+    if (!p || m < 1 || m > kInferRowsMax) {
+        gbp_set_error("mlp_forward: rows must be in [1, %d]", kInferRowsMax);
+        return GBP_ERR_ARG;
+    }
     if (!X || !y) {
         gbp_set_error("mlp_forward: NULL argument");
         return GBP_ERR_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = forward_all(p, (const bf16*)X, m, s))) return rc;
-    k_scale_out<<<gbp_blocks(m, 256), 256, 0, s>>>(p->y, m, out_scale, y);
+    if (reinterpret_cast<uintptr_t>(X) & 15) {
+        gbp_set_error("mlp_forward: X must be 16-byte aligned");
+        return GBP_ERR_ARG;
+    }
+    if (m >= kInferRowsLarge)
+        k_mlp_infer<8><<<(m + 127) / 128, 256, 0, s>>>((const bf16*)X, m, p->wbf[0], p->wbf[1], p->wbf[2],
+                                                      p->wbf[3], p->params, out_scale, y);
+    else
+        k_mlp_infer<4><<<(m + 63) / 64, 256, 0, s>>>((const bf16*)X, m, p->wbf[0], p->wbf[1], p->wbf[2],
+                                                    p->wbf[3], p->params, out_scale, y);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }

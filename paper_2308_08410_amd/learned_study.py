@@ -46,7 +46,7 @@ def main(argv=None):
     test = WS.make_dataset(plan, p.xyz, D, p.extra["endo"], args.test, seed=9_000_000)
     print(json.dumps(dict(nodes=p.n_v, solves=max(sizes), data_seconds=t_data)), flush=True)
     for n in sizes:
-        ws = WS.WarmStart(p.xyz, p.extra["node_fibre"], max_rows=max(args.batch, 1 << 16), seed=args.seed)
+        ws = WS.WarmStart(p.xyz, p.extra["node_fibre"], max_rows=args.batch, seed=args.seed)
         steps = max(args.min_steps, int(args.steps_per_solve * n))
         t0 = time.perf_counter()
         print(f"[train] {n} solves, {steps} steps", flush=True)

@@ -47,7 +47,6 @@ class WarmStart:
         self.xyz_h = xyz
         self.xyz = torch.as_tensor(xyz, device=dev)
         self.fibre = torch.as_tensor(np.ascontiguousarray(node_fibre, np.float32), device=dev)
-        self.rows_all = torch.arange(self.n_v, dtype=torch.int32, device=dev)
         self.mlp = B.MLP(max_rows, seed)
         self.device = dev
 
@@ -62,16 +61,13 @@ class WarmStart:
                               vscale=vscale, rows=rows, T=T)
 
     def predict(self, root_node, root_t, vscale=None, out=None):
-        """Predicted activation times [n_v] (device), in chunks of max_rows."""
+        """Predicted activation times [n_v] (device): the features of every vertex,
+        then one inference pass over all of them."""
         if out is None:
             out = torch.empty(self.n_v, dtype=torch.float32, device=self.device)
         rx = self.root_xyz(root_node)
-        step = self.mlp.max_rows
-        for a in range(0, self.n_v, step):
-            b = min(self.n_v, a + step)
-            X = B.mlp_features(self.xyz, self.fibre, rx, root_t, self.norm, vscale=vscale,
-                               rows=self.rows_all[a:b])
-            self.mlp.forward(X, out_scale=self.time_scale, out=out[a:b])
+        X = B.mlp_features(self.xyz, self.fibre, rx, root_t, self.norm, vscale=vscale)
+        self.mlp.forward(X, out_scale=self.time_scale, out=out)
         return out
 
     def forward(self, plan, D, vscale, root_node, root_t, out=None, fallback=True):
@@ -258,7 +254,7 @@ def main(argv=None):
     data = make_dataset(plan, p.xyz, D, p.extra["endo"], args.solves, seed=1000 + args.seed)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    ws = WarmStart(p.xyz, p.extra["node_fibre"], max_rows=max(args.batch, 1 << 16), seed=args.seed)
+    ws = WarmStart(p.xyz, p.extra["node_fibre"], max_rows=args.batch, seed=args.seed)
     t0 = time.perf_counter()
     log = runlog.RunLog(args.log, "warmstart", dict(vars(args), n_v=p.n_v, n_e=p.n_e)) if args.log else None
     hist = train(ws, data, args.steps, batch=args.batch, lr=args.lr, log_every=max(1, args.steps // 20),

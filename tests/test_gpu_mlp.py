@@ -116,12 +116,14 @@ def test_features_match_oracle(shell):
     assert np.all(np.abs(bits_to_f64(X1) - Xo1) <= U_BF16 * np.abs(Xo1) + 1e-6)
 
 
-@pytest.mark.parametrize("m", [1, 63, 3000])
+@pytest.mark.parametrize("m", [1, 63, 3000, 4096, 40_000])
 def test_forward_matches_oracle(m):
+    """Both row tilings of the inference kernel (64 rows per block below 32768
+    rows, 128 above), ragged tails included."""
     _dev()
     params = gi.mlp_params(7)
     bits, vals = gi.mlp_rows(m, seed=m)
-    net = B().MLP(4096, seed=0)
+    net = B().MLP(max(m, 4096), seed=0)
     net.set_params(params)
     Xd = torch.as_tensor(bits, device="cuda")
     y = net.forward(Xd).cpu().numpy()
@@ -194,11 +196,23 @@ def test_train_step_is_adam_on_the_gradient():
 
 
 def test_bad_sizes_rejected():
+    """Training batches are bounded by max_rows; inference, which keeps nothing per
+    row on the device, is not."""
     _dev()
     net = B().MLP(100, seed=0)
     bits, _ = gi.mlp_rows(101, seed=1)
+    Xd = torch.as_tensor(bits, device="cuda")
     with pytest.raises(B().GbpError):
-        net.forward(torch.as_tensor(bits, device="cuda"))
+        net.gradient(Xd, torch.zeros(101, device="cuda"))
+    y = net.forward(Xd)
+    assert torch.equal(y[:100], net.forward(Xd[:100].contiguous()))
+    # the inference kernel reads feature rows in 16-byte pieces: a misaligned X is refused
+    flat = torch.as_tensor(bits, device="cuda").reshape(-1)
+    shifted = torch.empty(flat.numel() + 8, dtype=flat.dtype, device="cuda")
+    view = shifted[1:1 + 50 * 16].view(50, 16)
+    view.copy_(flat[:50 * 16].view(50, 16))
+    with pytest.raises(B().GbpError, match="aligned"):
+        net.forward(view)
 
 
 def test_training_reduces_loss_and_warm_start_equals_cold():
