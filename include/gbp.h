@@ -704,7 +704,10 @@ int gbp_step_set_state(gbp_step step, const float *m_vscale, const float *v_vsca
  *   alignment).
  * gbp_mlp_gradient: forward, mean squared error against target[m] (device),
  *   written to *loss (device, may be NULL), and the parameter gradient (kept in
- *   the network; read with gbp_mlp_get_params).
+ *   the network; read with gbp_mlp_get_params); m <= max_rows, X 16-byte
+ *   aligned.  Deterministic: every sum runs in a fixed order (per-tile and
+ *   per-split partials, then a fixed-order reduction), so equal inputs give
+ *   bitwise-equal gradients.  Errors: GBP_ERR_ARG (rows, NULL, alignment).
  * gbp_mlp_train_step: gbp_mlp_gradient followed by one Adam step (beta 0.9,
  *   0.999, eps 1e-8, bias-corrected) with learning rate lr on the fp32 masters
  *   and a refresh of their bf16 copies.

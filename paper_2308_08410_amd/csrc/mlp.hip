@@ -42,118 +42,7 @@ __device__ __forceinline__ bf16 to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
-// ---------------------------------------------------------------- GEMM
-// C[i][j] = sum_k A(i,k) B(k,j) with A(i,k) = A[i*ar + k*ac], B(k,j) = B[k*br + j*bc]
-// (bf16), 64x64 tile per block of 4 waves, each wave 32x32 = 2x2 tiles of
-// v_mfma_f32_16x16x32_bf16, K in steps of 32 staged through LDS (B stored
-// transposed so that a lane's 8 consecutive K values are one 16-byte read).
-// MFMA 16x16x32 lane layout: lane l holds A[l % 16][8 (l / 16) + q] and
-// B[8 (l / 16) + q][l % 16], q = 0..7, and returns D[4 (l / 16) + r][l % 16].
-enum { EPI_BIAS_RELU = 0, EPI_MASK = 1, EPI_PARTIAL = 2 };
-constexpr int KS = 32;          // K per staged step
-constexpr int KP = KS + 8;      // LDS row pitch (bf16): 80 bytes, 16-byte aligned rows
-
-template <int EPI>
-__global__ void __launch_bounds__(256)
-    k_gemm(const bf16* __restrict__ A, int ar, int ac, const bf16* __restrict__ Bm, int br, int bc,
-           int M, int N, int K, int kchunk, const float* __restrict__ bias,
-           const bf16* __restrict__ mask, bf16* __restrict__ out, float* __restrict__ part) {
-    __shared__ __align__(16) bf16 As[64][KP];
-    __shared__ __align__(16) bf16 Bt[64][KP];
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-    floatx4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += KS) {
-        for (int e = threadIdx.x; e < 64 * KS; e += 256) {
-            const int r = e / KS, kk = e % KS;
-            const int gi = i0 + r, gk = k0 + kk;
-            As[r][kk] = (gi < M && gk < ke) ? A[(size_t)gi * ar + (size_t)gk * ac] : (bf16)0;
-            const int gj = j0 + r;
-            Bt[r][kk] = (gj < N && gk < ke) ? Bm[(size_t)gk * br + (size_t)gj * bc] : (bf16)0;
-        }
-        __syncthreads();
-        bf16x8_t af[2], bfv[2];
-        const int kq = (lane >> 4) * 8;
-        for (int t = 0; t < 2; ++t) {
-            const int ra = wi + t * 16 + (lane & 15), rb = wj + t * 16 + (lane & 15);
-            af[t] = *reinterpret_cast<const bf16x8_t*>(&As[ra][kq]);
-            bfv[t] = *reinterpret_cast<const bf16x8_t*>(&Bt[rb][kq]);
-        }
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfv[b], acc[a][b], 0, 0, 0);
-        __syncthreads();
-    }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wi + a * 16 + (lane >> 4) * 4 + r;
-                const int j = j0 + wj + b * 16 + (lane & 15);
-                if (i >= M || j >= N) continue;
-                const float v = acc[a][b][r];
-                if (EPI == EPI_BIAS_RELU) {
-                    out[(size_t)i * N + j] = to_bf16(fmaxf(v + bias[j], 0.f));
-                } else if (EPI == EPI_MASK) {
-                    const bf16 h = mask[(size_t)i * N + j];
-                    out[(size_t)i * N + j] = to_bf16((h != 0 && !(h & 0x8000)) ? v : 0.f);
-                } else {
-                    part[(size_t)blockIdx.z * M * N + (size_t)i * N + j] = v;
-                }
-            }
-}
-
-// sum of split-K partials (fixed order)
-__global__ void k_reduce_parts(const float* __restrict__ part, int splits, int n,
-                               float* __restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + t];
-    out[t] = s;
-}
-
-// column sums of a bf16 [m x n] matrix (bias gradients), fixed order per column
-// Column sums (bias gradients) in two fixed-order passes: block (g, r) sums, for 64
-// columns of group g, the rows [r R, (r+1) R) (4 row phases, then the phases in
-// order) into part[r][c]; k_reduce_parts then adds the row blocks in order.
-// WEIGHTED: sum_i w_i X[i][c], and column n (one past the last) gives sum_i w_i.
-template <bool WEIGHTED>
-__global__ void k_colsum_part(const bf16* __restrict__ X, const float* __restrict__ w, int m, int n,
-                              int R, float* __restrict__ part) {
-    __shared__ float red[4][64];
-    const int cl = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + cl;
-    const int ncol = WEIGHTED ? n + 1 : n;
-    const int r0 = blockIdx.y * R, r1 = min(m, r0 + R);
-    float acc = 0.f;
-    if (c < ncol)
-        for (int i = r0 + q; i < r1; i += 4) {
-            const float x = c < n ? from_bf16(X[(size_t)i * n + c]) : 1.f;
-            acc += WEIGHTED ? w[i] * x : x;
-        }
-    red[q][cl] = acc;
-    __syncthreads();
-    if (q == 0 && c < ncol)
-        part[(size_t)blockIdx.y * ncol + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
-}
-
-// ---------------------------------------------------------------- head, loss
-// y_i = H4_i . w5 + b5 (16 lanes per row, fp32)
-__global__ void k_head(const bf16* __restrict__ H, int m, const float* __restrict__ w5,
-                       const float* __restrict__ b5, float* __restrict__ y) {
-    const int lane = threadIdx.x & 15;
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (i >= m) return;
-    float s = 0.f;
-    for (int j = lane; j < HID; j += 16) s += from_bf16(H[(size_t)i * HID + j]) * w5[j];
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) y[i] = s + b5[0];
-}
-
+// ---------------------------------------------------------------- loss
 // dy = 2 (y - t) / m, squared error partial sums per block
 __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int m,
                       float* __restrict__ dy, float* __restrict__ part) {
@@ -187,41 +76,63 @@ __global__ void k_sum_parts(const float* __restrict__ part, int n, float scale, 
     if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
-// dZ4 = bf16(dy_i w5_j [H4 > 0])
-__global__ void k_head_bwd(const float* __restrict__ dy, const bf16* __restrict__ H, int m,
-                           const float* __restrict__ w5, bf16* __restrict__ dZ) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (size_t)m * HID) return;
-    const int i = (int)(t / HID), j = (int)(t % HID);
-    const bf16 h = H[t];
-    dZ[t] = to_bf16((h != 0 && !(h & 0x8000)) ? dy[i] * w5[j] : 0.f);
-}
-
-// ---------------------------------------------------------------- fused inference
-// The whole network for a tile of 16 TR rows in one block of 4 waves: the
-// activations stay in LDS (16 TR x 256 bf16, overwritten layer by layer), only
-// the features come in and the predictions go out.  Wave w computes the output
-// columns [64 w, 64 w + 64) of a layer for all the tile's rows as the transposed
-// product W H^T: TR x 4 tiles of v_mfma_f32_16x16x32_bf16 per K step of 32, the
-// A operand (a weight row's 8 consecutive K values) loaded straight from global
-// memory (a layer's 128 KB of weights stay in L2; each fragment serves 16 TR
-// rows), the B operand (an activation row's 8 K values) read from LDS, the next
-// step's weight fragments in flight while the current step multiplies.  A
-// layer's output overwrites its input only after every wave has finished
-// reading it.  Rounding as in the layered kernels: H = bf16(relu(fp32 acc + b)),
-// the head in fp32.
+// ---------------------------------------------------------------- fused row-tile kernels
+// A block of 4 waves owns a tile of 16 TR rows and runs the network's 256-wide layers
+// on it with the tile in LDS (16 TR x 256 bf16, overwritten layer by layer).  Wave w
+// computes the output columns [64 w, 64 w + 64) of a layer for all the tile's rows as
+// the transposed product A S^T: TR x 4 tiles of v_mfma_f32_16x16x32_bf16 per K step of
+// 32, the A operand (a row of a 256 x 256 weight matrix, 8 consecutive K values per
+// lane) loaded straight from global memory (the matrix stays in L2; each fragment
+// serves 16 TR rows), the B operand (a tile row's 8 K values) read from LDS, the next
+// step's weight fragments in flight while the current step multiplies.  A lane's 4
+// results are 4 consecutive columns of one row, stored with one 8-byte write.  A
+// layer's output overwrites its input only after every wave has finished reading it.
+//   forward:  H_l = bf16(relu(W_l H_{l-1} + b_l)), then y = H_4 . w5 + b5 in fp32;
+//   backward: dZ_{l-1} = bf16((W_l^T dZ_l) [H_{l-1} > 0]) with A = W_l^T (a bf16
+//             copy kept transposed).
 constexpr int HP = HID + 8;   // LDS row pitch (bf16): 528 bytes, 16-byte aligned rows
 
 __device__ __forceinline__ bf16x8_t ld8(const bf16* p) {
     return *reinterpret_cast<const bf16x8_t*>(p);
 }
+__device__ __forceinline__ bool relu_on(bf16 h) { return h != 0 && !(h & 0x8000); }
 
-// layer output bf16(relu(acc + b)) into the wave's 64 columns of H.  The tiles
-// hold the layer's output transposed (column j of the layer = row of the tile),
-// so a lane's 4 values are 4 consecutive columns of one row: one 8-byte store.
+// acc[t][c][r] = sum_k A[j][k] S[16 t + lr][k] with j = j0 + 16 c + 4 lq + r
 template <int TR>
-__device__ __forceinline__ void infer_store(bf16 (*H)[HP], const floatx4 (&acc)[TR][4],
-                                            const float* __restrict__ bias, int j0, int lr, int lq) {
+__device__ __forceinline__ void tile_layer(const bf16* __restrict__ A, bf16 (*S)[HP],
+                                           floatx4 (&acc)[TR][4], int j0, int lr, int lq) {
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8_t bw[4], bn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bw[c] = ld8(A + (size_t)(j0 + c * 16 + lr) * HID + 8 * lq);
+#pragma unroll 2
+    for (int ks = 0; ks < HID / 32; ++ks) {
+        if (ks + 1 < HID / 32) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                bn[c] = ld8(A + (size_t)(j0 + c * 16 + lr) * HID + (ks + 1) * 32 + 8 * lq);
+        }
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&S[t * 16 + lr][ks * 32 + 8 * lq]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, acc[t][c], 0, 0, 0);
+        }
+        if (ks + 1 < HID / 32) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bw[c] = bn[c];
+        }
+    }
+}
+
+// forward epilogue: S = bf16(relu(acc + b)) in the wave's 64 columns
+template <int TR>
+__device__ __forceinline__ void relu_store(bf16 (*S)[HP], const floatx4 (&acc)[TR][4],
+                                           const float* __restrict__ bias, int j0, int lr, int lq) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int j = j0 + c * 16 + 4 * lq;
@@ -232,28 +143,112 @@ __device__ __forceinline__ void infer_store(bf16 (*H)[HP], const floatx4 (&acc)[
                                 ((unsigned)to_bf16(fmaxf(acc[t][c][1] + b1, 0.f)) << 16);
             const unsigned hi = to_bf16(fmaxf(acc[t][c][2] + b2, 0.f)) |
                                 ((unsigned)to_bf16(fmaxf(acc[t][c][3] + b3, 0.f)) << 16);
-            *reinterpret_cast<uint2*>(&H[t * 16 + lr][j]) = make_uint2(lo, hi);
+            *reinterpret_cast<uint2*>(&S[t * 16 + lr][j]) = make_uint2(lo, hi);
         }
     }
 }
 
+// backward epilogue: S = bf16(acc) where the forward activation Hp (row-major
+// [m][256]) of the element is positive, else 0; rows at or past m are zero
 template <int TR>
+__device__ __forceinline__ void mask_store(bf16 (*S)[HP], const floatx4 (&acc)[TR][4],
+                                           const bf16* __restrict__ Hp, int i0, int m, int j0, int lr,
+                                           int lq) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = j0 + c * 16 + 4 * lq;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int i = i0 + t * 16 + lr;
+            const uint2 h = i < m ? *reinterpret_cast<const uint2*>(Hp + (size_t)i * HID + j) : make_uint2(0u, 0u);
+            const unsigned z0 = relu_on((bf16)(h.x & 0xffffu)) ? to_bf16(acc[t][c][0]) : 0u;
+            const unsigned z1 = relu_on((bf16)(h.x >> 16)) ? to_bf16(acc[t][c][1]) : 0u;
+            const unsigned z2 = relu_on((bf16)(h.y & 0xffffu)) ? to_bf16(acc[t][c][2]) : 0u;
+            const unsigned z3 = relu_on((bf16)(h.y >> 16)) ? to_bf16(acc[t][c][3]) : 0u;
+            *reinterpret_cast<uint2*>(&S[t * 16 + lr][j]) = make_uint2(z0 | (z1 << 16), z2 | (z3 << 16));
+        }
+    }
+}
+
+// the tile's rows below m into dst (row-major [m][256])
+template <int IB>
+__device__ __forceinline__ void tile_store_rows(bf16 (*S)[HP], bf16* __restrict__ dst, int i0, int m) {
+    for (int e = threadIdx.x; e < IB * (HID / 8); e += 256) {
+        const int r = e / (HID / 8), cc = e % (HID / 8);
+        if (i0 + r < m)
+            *reinterpret_cast<uint4*>(dst + (size_t)(i0 + r) * HID + 8 * cc) =
+                *reinterpret_cast<const uint4*>(&S[r][8 * cc]);
+    }
+}
+
+// the tile transposed into dst ([256][mp]): dst[c][i0 + r] = S[r][c], zero for rows at
+// or past m; thread c (one per column) also returns the column's sum over the tile's
+// rows, in row order, in fp32
+template <int IB>
+__device__ __forceinline__ float tile_store_T(bf16 (*S)[HP], bf16* __restrict__ dst, int mp, int i0, int m) {
+    const int c = threadIdx.x;
+    bf16* d = dst + (size_t)c * mp + i0;
+    float s = 0.f;
+#pragma unroll 2
+    for (int g = 0; g < IB / 8; ++g) {
+        unsigned w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 8 * g + 2 * q;
+            const bf16 a = i0 + r < m ? S[r][c] : (bf16)0;
+            const bf16 b = i0 + r + 1 < m ? S[r + 1][c] : (bf16)0;
+            s += from_bf16(a);
+            s += from_bf16(b);
+            w[q] = a | ((unsigned)b << 16);
+        }
+        *reinterpret_cast<uint4*>(d + 8 * g) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    return s;
+}
+
+// What the training forward keeps for the backward pass.
+struct MlpKeep {
+    bf16* H[NLAYER];   // activations H1..H4, row-major [m][256]
+    bf16* T[NLAYER];   // the layers' inputs transposed: X^T [16][mp], H1^T, H2^T, H3^T [256][mp]
+    int mp;            // row pitch of the transposed buffers (multiple of 128)
+};
+
+// The network on a tile of 16 TR rows of X [m][16] (16-byte aligned rows).
+// Inference (TRAIN false): y = out_scale * (H4 . w5 + b5), non-finite values as +inf.
+// Training: y = H4 . w5 + b5 as is, and the activations kept as listed in MlpKeep.
+template <int TR, bool TRAIN>
 __global__ void __launch_bounds__(256, 2)
-    k_mlp_infer(const bf16* __restrict__ X, int m, const bf16* __restrict__ W1,
-                const bf16* __restrict__ W2, const bf16* __restrict__ W3, const bf16* __restrict__ W4,
-                const float* __restrict__ params, float out_scale, float* __restrict__ y) {
+    k_mlp_fwd(const bf16* __restrict__ X, int m, const bf16* __restrict__ W1, const bf16* __restrict__ W2,
+              const bf16* __restrict__ W3, const bf16* __restrict__ W4, const float* __restrict__ params,
+              float out_scale, float* __restrict__ y, MlpKeep keep) {
     constexpr int IB = 16 * TR;                // rows per block
-    __shared__ __align__(16) bf16 H[IB][HP];
+    __shared__ __align__(16) bf16 S[IB][HP];
     const int i0 = blockIdx.x * IB;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j0 = wave * 64;                  // this wave's output columns
-    const int lr = lane & 15, lq = lane >> 4;  // row (A) / column (B) in a 16-tile, K quarter
+    const int lr = lane & 15, lq = lane >> 4;  // row in a 16-tile, K quarter
     floatx4 acc[TR][4];
-    bf16x8_t zero8;
+    if (TRAIN) {
+        // X^T for the first layer's weight gradient
+        for (int e = threadIdx.x; e < IN * (IB / 8); e += 256) {
+            const int c = e % IN, g = e / IN;
+            unsigned w[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 8 * g + 2 * q;
+                const unsigned a = i < m ? X[(size_t)i * IN + c] : 0u;
+                const unsigned b = i + 1 < m ? X[(size_t)(i + 1) * IN + c] : 0u;
+                w[q] = a | (b << 16);
+            }
+            *reinterpret_cast<uint4*>(keep.T[0] + (size_t)c * keep.mp + i0 + 8 * g) =
+                make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
     // layer 1: K = 16 features; quarters 2 and 3 of the 32-wide K step are zero
     {
+        bf16x8_t zero8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
         bf16x8_t bw[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) bw[c] = lq < 2 ? ld8(W1 + (size_t)(j0 + c * 16 + lr) * IN + 8 * lq) : zero8;
@@ -266,42 +261,24 @@ __global__ void __launch_bounds__(256, 2)
                 acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, floatx4{0.f, 0.f, 0.f, 0.f},
                                                                     0, 0, 0);
         }
-        infer_store<TR>(H, acc, params + off_b_dev(1), j0, lr, lq);
+        relu_store<TR>(S, acc, params + off_b_dev(1), j0, lr, lq);
         __syncthreads();
+        if (TRAIN) {
+            tile_store_rows<IB>(S, keep.H[0], i0, m);
+            tile_store_T<IB>(S, keep.T[1], keep.mp, i0, m);
+        }
     }
-    // layers 2..4: K = 256 in 8 steps
+    // layers 2..4: K = 256
 #pragma unroll 1
     for (int l = 2; l <= NLAYER; ++l) {
-        const bf16* W = l == 2 ? W2 : l == 3 ? W3 : W4;
-#pragma unroll
-        for (int t = 0; t < TR; ++t)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-        bf16x8_t bw[4], bn[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bw[c] = ld8(W + (size_t)(j0 + c * 16 + lr) * HID + 8 * lq);
-#pragma unroll 2
-        for (int ks = 0; ks < HID / 32; ++ks) {
-            if (ks + 1 < HID / 32) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    bn[c] = ld8(W + (size_t)(j0 + c * 16 + lr) * HID + (ks + 1) * 32 + 8 * lq);
-            }
-#pragma unroll
-            for (int t = 0; t < TR; ++t) {
-                const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&H[t * 16 + lr][ks * 32 + 8 * lq]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, acc[t][c], 0, 0, 0);
-            }
-            if (ks + 1 < HID / 32) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) bw[c] = bn[c];
-            }
-        }
+        tile_layer<TR>(l == 2 ? W2 : l == 3 ? W3 : W4, S, acc, j0, lr, lq);
         __syncthreads();                       // every wave has read this layer's input
-        infer_store<TR>(H, acc, params + off_b_dev(l), j0, lr, lq);
+        relu_store<TR>(S, acc, params + off_b_dev(l), j0, lr, lq);
         __syncthreads();
+        if (TRAIN) {
+            tile_store_rows<IB>(S, l == 2 ? keep.H[1] : l == 3 ? keep.H[2] : keep.H[3], i0, m);
+            if (l < NLAYER) tile_store_T<IB>(S, l == 2 ? keep.T[2] : keep.T[3], keep.mp, i0, m);
+        }
     }
     // head: y = H4 . w5 + b5 in fp32, 256 / IB threads per row
     constexpr int TPR = 256 / IB;              // threads per row
@@ -311,7 +288,7 @@ __global__ void __launch_bounds__(256, 2)
     float sum = 0.f;
 #pragma unroll 4
     for (int j = part * CPT; j < part * CPT + CPT; j += 8) {
-        const uint4 u = *reinterpret_cast<const uint4*>(&H[row][j]);
+        const uint4 u = *reinterpret_cast<const uint4*>(&S[row][j]);
         const unsigned w[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -323,22 +300,225 @@ __global__ void __launch_bounds__(256, 2)
     for (int o = 1; o < TPR; o <<= 1) sum += __shfl_xor(sum, o);
     const int i = i0 + row;
     if (part == 0 && i < m) {
-        const float v = out_scale * (sum + w5[HID]);
-        y[i] = isfinite(v) ? v : __builtin_huge_valf();
+        if (TRAIN) {
+            y[i] = sum + w5[HID];
+        } else {
+            const float v = out_scale * (sum + w5[HID]);
+            y[i] = isfinite(v) ? v : __builtin_huge_valf();
+        }
     }
 }
-// rows per block 16 TR: 128 once there are enough rows to give every CU a block
-// (fewer weight fetches per row), else 64 (more blocks for small batches)
-constexpr int kInferRowsLarge = 32768;
+
+// Per-block partial sums the backward chain leaves for the reduction: db1..db4
+// (column sums of dZ_l), dw5 (sum of dy_i H4_i), db5 (sum of dy_i).
+constexpr int kBwdPart = NLAYER * HID + HID + 1;
+
+struct MlpBwd {
+    const bf16* H[NLAYER];        // activations H1..H4, row-major [m][256]
+    const bf16* WT[NLAYER - 1];   // W2^T, W3^T, W4^T (bf16 [256][256])
+    const float* dy;              // [m]
+    const float* w5;              // w5 [256] (fp32)
+    bf16* dZT[NLAYER];            // dZ1..dZ4 transposed [256][mp]
+    float* part;                  // [blocks][kBwdPart]
+    int m, mp;
+};
+
+// The backward chain on a tile of 16 TR rows: dZ4 from dy, then dZ3, dZ2, dZ1, each
+// kept transposed for the weight gradients, with the bias and head partial sums.
+template <int TR>
+__global__ void __launch_bounds__(256, 2) k_mlp_bwd(MlpBwd a) {
+    constexpr int IB = 16 * TR;
+    __shared__ __align__(16) bf16 S[IB][HP];
+    __shared__ float red[8][HID + 1];
+    const int i0 = blockIdx.x * IB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = wave * 64;
+    const int lr = lane & 15, lq = lane >> 4;
+    float* part = a.part + (size_t)blockIdx.x * kBwdPart;
+    {
+        // dZ4 = bf16(dy_i w5_j [H4 > 0]); thread: 8 columns, rows ph, ph + 8, ... in order
+        const int cc = threadIdx.x & 31, ph = threadIdx.x >> 5;
+        float w5v[8], sw[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            w5v[q] = a.w5[8 * cc + q];
+            sw[q] = 0.f;
+        }
+        float sd = 0.f;
+        for (int r = ph; r < IB; r += 8) {
+            const int i = i0 + r;
+            uint4 h = make_uint4(0u, 0u, 0u, 0u);
+            float d = 0.f;
+            if (i < a.m) {
+                h = *reinterpret_cast<const uint4*>(a.H[3] + (size_t)i * HID + 8 * cc);
+                d = a.dy[i];
+            }
+            const unsigned hw[4] = {h.x, h.y, h.z, h.w};
+            unsigned o[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bf16 h0 = (bf16)(hw[q] & 0xffffu), h1 = (bf16)(hw[q] >> 16);
+                sw[2 * q] += d * from_bf16(h0);
+                sw[2 * q + 1] += d * from_bf16(h1);
+                const unsigned z0 = relu_on(h0) ? to_bf16(d * w5v[2 * q]) : 0u;
+                const unsigned z1 = relu_on(h1) ? to_bf16(d * w5v[2 * q + 1]) : 0u;
+                o[q] = z0 | (z1 << 16);
+            }
+            sd += d;
+            *reinterpret_cast<uint4*>(&S[r][8 * cc]) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[ph][8 * cc + q] = sw[q];
+        if (cc == 0) red[ph][HID] = sd;
+    }
+    __syncthreads();
+    {
+        const int c = threadIdx.x;
+        float s = 0.f;
+#pragma unroll
+        for (int ph = 0; ph < 8; ++ph) s += red[ph][c];
+        part[NLAYER * HID + c] = s;
+        if (c == 0) {
+            float t = 0.f;
+#pragma unroll
+            for (int ph = 0; ph < 8; ++ph) t += red[ph][HID];
+            part[NLAYER * HID + HID] = t;
+        }
+    }
+    part[(NLAYER - 1) * HID + threadIdx.x] = tile_store_T<IB>(S, a.dZT[NLAYER - 1], a.mp, i0, a.m);
+    floatx4 acc[TR][4];
+#pragma unroll 1
+    for (int l = NLAYER; l >= 2; --l) {
+        tile_layer<TR>(l == 4 ? a.WT[2] : l == 3 ? a.WT[1] : a.WT[0], S, acc, j0, lr, lq);
+        __syncthreads();
+        mask_store<TR>(S, acc, l == 4 ? a.H[2] : l == 3 ? a.H[1] : a.H[0], i0, a.m, j0, lr, lq);
+        __syncthreads();
+        part[(l - 2) * HID + threadIdx.x] =
+            tile_store_T<IB>(S, l == 4 ? a.dZT[2] : l == 3 ? a.dZT[1] : a.dZT[0], a.mp, i0, a.m);
+    }
+}
+
+// ---------------------------------------------------------------- weight gradients
+// dW_l[j][n] = sum_i dZ_l[i][j] H_{l-1}[i][n] (H_0 = X) over the rows [kb, ke) of a
+// split, from the transposed copies (both operands K-contiguous): a block computes 128
+// (j) x NB (n) of one layer, K steps of 32 staged through LDS in two buffers (the next
+// step's global loads in flight while the current one multiplies); waves 2 x 2 of 64 x 64
+// (NB = 128, layers 2..4: block x = 4 (l - 2) + 2 j-tile + n-tile) or 4 x 1 of 32 x 16
+// (NB = 16, layer 1: block x = j-tile).  Fixed-order fp32 partials per split.
+constexpr int KP = 40;   // LDS row pitch (bf16) of a staged K step: 80 bytes
+
+struct MlpWgrad {
+    const bf16* dZT[NLAYER];   // [256][mp]
+    const bf16* T[NLAYER];     // X^T [16][mp], H1^T, H2^T, H3^T [256][mp]
+    float* part;               // [splits][n_params]
+    int mp, kend, kchunk;      // kend: m rounded up to 32 (the transposed rows are zero there)
+    int n_params;
+};
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_mlp_wgrad(MlpWgrad a) {
+    constexpr int TJ = NB == 128 ? 4 : 2, TN = NB == 128 ? 4 : 1;
+    constexpr int in = NB == 128 ? HID : IN;
+    const int l = NB == 128 ? 2 + (int)blockIdx.x / 4 : 1;
+    const int jt = NB == 128 ? (blockIdx.x >> 1) & 1 : blockIdx.x, nt = NB == 128 ? blockIdx.x & 1 : 0;
+    const bf16* A = (l == 1 ? a.dZT[0] : l == 2 ? a.dZT[1] : l == 3 ? a.dZT[2] : a.dZT[3]) +
+                    (size_t)(jt * 128) * a.mp;
+    const bf16* Bm = (l == 1 ? a.T[0] : l == 2 ? a.T[1] : l == 3 ? a.T[2] : a.T[3]) + (size_t)(nt * NB) * a.mp;
+    const int kb = blockIdx.y * a.kchunk, ke = min(a.kend, kb + a.kchunk);
+    __shared__ __align__(16) bf16 As[2][128][KP];
+    __shared__ __align__(16) bf16 Bs[2][NB][KP];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int wj = NB == 128 ? (wave >> 1) * 64 : wave * 32, wn = NB == 128 ? (wave & 1) * 64 : 0;
+    floatx4 acc[TJ][TN];
+#pragma unroll
+    for (int x = 0; x < TJ; ++x)
+#pragma unroll
+        for (int z = 0; z < TN; ++z) acc[x][z] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // staging: A 128 rows x 4 chunks of 16 bytes (2 per thread), B NB rows x 4 chunks
+    uint4 ra[2], rb[2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e >> 2, q = e & 3;
+            ra[u] = *reinterpret_cast<const uint4*>(A + (size_t)row * a.mp + k0 + 8 * q);
+            if (e < NB * 4) rb[u] = *reinterpret_cast<const uint4*>(Bm + (size_t)row * a.mp + k0 + 8 * q);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e >> 2, q = e & 3;
+            *reinterpret_cast<uint4*>(&As[buf][row][8 * q]) = ra[u];
+            if (e < NB * 4) *reinterpret_cast<uint4*>(&Bs[buf][row][8 * q]) = rb[u];
+        }
+    };
+    if (kb < ke) {
+        gload(kb);
+        lstore(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+        const bool more = k0 + 32 < ke;
+        if (more) gload(k0 + 32);
+        bf16x8_t af[TJ], bfr[TN];
+#pragma unroll
+        for (int x = 0; x < TJ; ++x) af[x] = *reinterpret_cast<const bf16x8_t*>(&As[buf][wj + x * 16 + lr][8 * lq]);
+#pragma unroll
+        for (int z = 0; z < TN; ++z) bfr[z] = *reinterpret_cast<const bf16x8_t*>(&Bs[buf][wn + z * 16 + lr][8 * lq]);
+#pragma unroll
+        for (int x = 0; x < TJ; ++x)
+#pragma unroll
+            for (int z = 0; z < TN; ++z)
+                acc[x][z] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x], bfr[z], acc[x][z], 0, 0, 0);
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // lane holds D[j = wj + 16 x + 4 lq + r][n = wn + 16 z + lr]
+    float* out = a.part + (size_t)blockIdx.y * a.n_params + off_W_dev(l);
+#pragma unroll
+    for (int x = 0; x < TJ; ++x)
+#pragma unroll
+        for (int z = 0; z < TN; ++z)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = jt * 128 + wj + x * 16 + 4 * lq + r, n = nt * NB + wn + z * 16 + lr;
+                out[(size_t)j * in + n] = acc[x][z][r];
+            }
+}
+
+// gradient = the splits' weight partials (W1..W4) or the backward blocks' partials
+// (b1..b4, w5, b5), each summed in a fixed order
+__global__ void k_mlp_grad_reduce(const float* __restrict__ pw, int splits, const float* __restrict__ pb,
+                                  int blocks, int n_params, float* __restrict__ g) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_params) return;
+    int col = -1;   // column of the backward partials, or -1 for a weight entry
+    for (int l = 1; l <= NLAYER; ++l)
+        if (e >= off_b_dev(l) && e < off_b_dev(l) + HID) col = (l - 1) * HID + (e - off_b_dev(l));
+    if (e >= off_w5_dev()) col = NLAYER * HID + (e - off_w5_dev());
+    float s = 0.f;
+    if (col < 0)
+        for (int z = 0; z < splits; ++z) s += pw[(size_t)z * n_params + e];
+    else
+        for (int b = 0; b < blocks; ++b) s += pb[(size_t)b * kBwdPart + col];
+    g[e] = s;
+}
+
+// inference rows per block 16 TR: 128 once there are enough rows to give every CU a
+// block (fewer weight fetches per row), else 64 (more blocks for small batches)
+constexpr int kRowsLarge = 32768;
 // inference keeps nothing per row on the device: any batch up to 2^27 rows
 constexpr int kInferRowsMax = 1 << 27;
 
-// prediction out: scale * y, non-finite values as +inf (no information)
-__global__ void k_scale_out(const float* __restrict__ y, int m, float scale, float* __restrict__ out) {
+// WT[n][j] = bf16(W[j][n]) for a 256 x 256 weight
+__global__ void k_cast_bf16_T(const float* __restrict__ W, bf16* __restrict__ WT) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= m) return;
-    const float v = scale * y[t];
-    out[t] = isfinite(v) ? v : __builtin_huge_valf();
+    if (t >= HID * HID) return;
+    const int n = t / HID, j = t % HID;
+    WT[t] = to_bf16(W[(size_t)j * HID + n]);
 }
 
 __global__ void k_cast_bf16(const float* __restrict__ x, int n, bf16* __restrict__ y) {
@@ -415,6 +595,7 @@ __global__ void k_features(const float* __restrict__ xyz, const float* __restric
 struct gbp_mlp_s {
     int device = 0;
     int max_rows = 0;
+    int mp = 0;                // row pitch of the transposed training buffers
     int n_params = 0;
     int step = 0;
     float* params = nullptr;   // fp32 masters, flat
@@ -422,36 +603,39 @@ struct gbp_mlp_s {
     float* m = nullptr;
     float* v = nullptr;
     bf16* wbf[NLAYER] = {};    // bf16 copies of W1..W4
-    bf16* H[NLAYER + 1] = {};  // H[0] unused (X is the input), H[1..4] activations [rows x 256]
-    bf16* dZ[2] = {};          // ping-pong [rows x 256]
+    bf16* wT = nullptr;        // bf16 W2^T, W3^T, W4^T [3][256][256]
+    bf16* H = nullptr;         // activations H1..H4 [4][max_rows][256]
+    bf16* T = nullptr;         // X^T [16][mp], H1^T..H3^T [3][256][mp]
+    bf16* dZT = nullptr;       // dZ1^T..dZ4^T [4][256][mp]
     float* y = nullptr;
     float* dy = nullptr;
-    float* part = nullptr;     // split-K partials / loss partials
-    size_t part_n = 0;
+    float* part = nullptr;     // loss partials
+    float* part_w = nullptr;   // weight-gradient partials [kMaxSplits][n_params]
+    float* part_b = nullptr;   // backward-chain partials [blocks][kBwdPart]
     float* loss = nullptr;     // [1]
 };
 
 namespace {
 // flat layout: W1 [256x16], b1, W2 [256x256], b2, W3, b3, W4, b4, w5 [256], b5 [1]
-int off_W(int l) {   // l = 1..4
-    if (l == 1) return 0;
-    return HID * IN + HID + (l - 2) * (HID * HID + HID);
-}
-int off_b(int l) { return off_W(l) + (l == 1 ? HID * IN : HID * HID); }
-int off_w5() { return off_W(4) + HID * HID + HID; }
+int off_W(int l) { return off_W_dev(l); }   // l = 1..4
+int off_b(int l) { return off_b_dev(l); }
+int off_w5() { return off_w5_dev(); }
 int n_params_total() { return off_w5() + HID + 1; }
 int in_dim(int l) { return l == 1 ? IN : HID; }
 
+// Row chunks of the weight-gradient splits: at most kMaxSplits chunks of a multiple of
+// 32 rows, at least 256.
+constexpr int kMaxSplits = 32;
+int wgrad_chunk(int kend) { return std::max(256, ((kend + kMaxSplits - 1) / kMaxSplits + 31) / 32 * 32); }
+
 void free_mlp(gbp_mlp p) {
     if (!p) return;
-    void* ptrs[] = {p->params, p->grads, p->m, p->v, p->y, p->dy, p->part, p->loss,
-                    p->dZ[0], p->dZ[1]};
+    void* ptrs[] = {p->params, p->grads, p->m, p->v, p->wT, p->H, p->T, p->dZT, p->y, p->dy,
+                    p->part, p->part_w, p->part_b, p->loss};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (int l = 0; l < NLAYER; ++l)
         if (p->wbf[l]) (void)hipFree(p->wbf[l]);
-    for (int l = 0; l <= NLAYER; ++l)
-        if (p->H[l]) (void)hipFree(p->H[l]);
     delete p;
 }
 
@@ -459,78 +643,80 @@ int refresh_bf16(gbp_mlp p, hipStream_t s) {
     for (int l = 1; l <= NLAYER; ++l) {
         const int n = HID * in_dim(l);
         k_cast_bf16<<<gbp_blocks(n, 256), 256, 0, s>>>(p->params + off_W(l), n, p->wbf[l - 1]);
+        if (l > 1)
+            k_cast_bf16_T<<<gbp_blocks(HID * HID, 256), 256, 0, s>>>(p->params + off_W(l),
+                                                                     p->wT + (size_t)(l - 2) * HID * HID);
     }
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
 
-void gemm_fwd(const bf16* Hin, int m, int in, const bf16* W, const float* bias, bf16* out,
-              hipStream_t s) {
-    // out[m x 256] = relu(Hin[m x in] W^T + b): A(i,k) = Hin[i*in + k], B(k,j) = W[j*in + k]
-    dim3 grid((HID + 63) / 64, (m + 63) / 64, 1);
-    k_gemm<EPI_BIAS_RELU><<<grid, 256, 0, s>>>(Hin, in, 1, W, 1, in, m, HID, in, in, bias, nullptr,
-                                                out, nullptr);
+MlpKeep keep_of(gbp_mlp p) {
+    MlpKeep k{};
+    for (int l = 0; l < NLAYER; ++l) k.H[l] = p->H + (size_t)l * p->max_rows * HID;
+    k.T[0] = p->T;
+    for (int l = 1; l < NLAYER; ++l) k.T[l] = p->T + (size_t)(IN + (l - 1) * HID) * p->mp;
+    k.mp = p->mp;
+    return k;
 }
 
-// Rows per K chunk of the split-K weight-gradient GEMMs: at most kSplits chunks,
-// each a multiple of the GEMM's K step.
-constexpr int kSplits = 64;
-int split_chunk(int m) { return std::max(512, ((m + kSplits - 1) / kSplits + 31) / 32 * 32); }
-
-// out[c] = sum over the m rows of X[:, c] (w == nullptr) or of w_i X[i][c] with
-// out[n] = sum w_i; deterministic (fixed-order partials in p->part)
-void colsum(gbp_mlp p, const bf16* X, const float* w, int m, int n, float* out, hipStream_t s) {
-    const int R = 256;
-    const int ncol = w ? n + 1 : n;
-    const dim3 g((ncol + 63) / 64, (m + R - 1) / R);
-    if (w) k_colsum_part<true><<<g, 256, 0, s>>>(X, w, m, n, R, p->part);
-    else k_colsum_part<false><<<g, 256, 0, s>>>(X, nullptr, m, n, R, p->part);
-    k_reduce_parts<<<gbp_blocks(ncol, 256), 256, 0, s>>>(p->part, (int)g.y, ncol, out);
-}
-
-int forward_all(gbp_mlp p, const bf16* X, int m, hipStream_t s) {
-    const bf16* hin = X;
-    for (int l = 1; l <= NLAYER; ++l) {
-        gemm_fwd(hin, m, in_dim(l), p->wbf[l - 1], p->params + off_b(l), p->H[l], s);
-        hin = p->H[l];
+// the network on m rows of X: inference (y = out_scale * prediction) or the training
+// forward (raw y in p->y, activations kept)
+void launch_fwd(gbp_mlp p, const bf16* X, int m, float out_scale, float* y, bool train, hipStream_t s) {
+    const MlpKeep k = train ? keep_of(p) : MlpKeep{};
+    if (m >= kRowsLarge) {
+        if (train)
+            k_mlp_fwd<8, true><<<(m + 127) / 128, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
+                                                               p->params, 1.f, y, k);
+        else
+            k_mlp_fwd<8, false><<<(m + 127) / 128, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
+                                                                p->params, out_scale, y, k);
+    } else {
+        if (train)
+            k_mlp_fwd<4, true><<<(m + 63) / 64, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
+                                                             p->params, 1.f, y, k);
+        else
+            k_mlp_fwd<4, false><<<(m + 63) / 64, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
+                                                              p->params, out_scale, y, k);
     }
-    k_head<<<gbp_blocks(16LL * m, 256), 256, 0, s>>>(p->H[NLAYER], m, p->params + off_w5(),
-                                                     p->params + off_w5() + HID, p->y);
-    GBP_LAUNCH_CHECK();
-    return GBP_OK;
 }
 
-int backward_all(gbp_mlp p, const bf16* X, int m, const float* target, hipStream_t s) {
+// loss, backward chain, weight gradients, reduction into p->grads
+void launch_bwd(gbp_mlp p, int m, const float* target, hipStream_t s) {
     const int nb = gbp_blocks(m, 256);
     k_mse<<<nb, 256, 0, s>>>(p->y, target, m, p->dy, p->part);
     k_sum_parts<<<1, 256, 0, s>>>(p->part, nb, 1.f / (float)m, p->loss);
-    // dw5 = H4^T dy and db5 = sum dy (parameter order: w5 then b5, adjacent)
-    colsum(p, p->H[NLAYER], p->dy, m, HID, p->grads + off_w5(), s);
-    k_head_bwd<<<gbp_blocks((long long)m * HID, 256), 256, 0, s>>>(p->dy, p->H[NLAYER], m,
-                                                                    p->params + off_w5(), p->dZ[0]);
-    int cur = 0;
-    for (int l = NLAYER; l >= 1; --l) {
-        const int in = in_dim(l);
-        const bf16* hprev = l > 1 ? p->H[l - 1] : X;
-        // dW_l [256 x in] = dZ^T Hprev: A(i,k) = dZ[k*256 + i], B(k,j) = Hprev[k*in + j], split K
-        const int kchunk = split_chunk(m);
-        const int splits = (m + kchunk - 1) / kchunk;
-        dim3 g1((in + 63) / 64, (HID + 63) / 64, splits);
-        k_gemm<EPI_PARTIAL><<<g1, 256, 0, s>>>(p->dZ[cur], 1, HID, hprev, in, 1, HID, in, m, kchunk,
-                                               nullptr, nullptr, nullptr, p->part);
-        k_reduce_parts<<<gbp_blocks(HID * in, 256), 256, 0, s>>>(p->part, splits, HID * in,
-                                                                 p->grads + off_W(l));
-        colsum(p, p->dZ[cur], nullptr, m, HID, p->grads + off_b(l), s);
-        if (l > 1) {
-            // dZ_{l-1} [m x in] = (dZ W_l) masked: A(i,k) = dZ[i*256 + k], B(k,j) = W[k*in + j]
-            dim3 g2((in + 63) / 64, (m + 63) / 64, 1);
-            k_gemm<EPI_MASK><<<g2, 256, 0, s>>>(p->dZ[cur], HID, 1, p->wbf[l - 1], in, 1, m, in, HID,
-                                                HID, nullptr, hprev, p->dZ[1 - cur], nullptr);
-            cur = 1 - cur;
-        }
+    const MlpKeep k = keep_of(p);
+    MlpBwd b{};
+    for (int l = 0; l < NLAYER; ++l) {
+        b.H[l] = k.H[l];
+        b.dZT[l] = p->dZT + (size_t)l * HID * p->mp;
     }
-    GBP_LAUNCH_CHECK();
-    return GBP_OK;
+    for (int l = 0; l < NLAYER - 1; ++l) b.WT[l] = p->wT + (size_t)l * HID * HID;
+    b.dy = p->dy;
+    b.w5 = p->params + off_w5();
+    b.part = p->part_b;
+    b.m = m;
+    b.mp = p->mp;
+    const int ib = m >= kRowsLarge ? 128 : 64;
+    const int blocks = (m + ib - 1) / ib;
+    if (ib == 128) k_mlp_bwd<8><<<blocks, 256, 0, s>>>(b);
+    else k_mlp_bwd<4><<<blocks, 256, 0, s>>>(b);
+    MlpWgrad w{};
+    for (int l = 0; l < NLAYER; ++l) {
+        w.dZT[l] = b.dZT[l];
+        w.T[l] = k.T[l];
+    }
+    w.part = p->part_w;
+    w.mp = p->mp;
+    w.kend = (m + 31) / 32 * 32;
+    w.kchunk = wgrad_chunk(w.kend);
+    w.n_params = p->n_params;
+    const int splits = (w.kend + w.kchunk - 1) / w.kchunk;
+    k_mlp_wgrad<128><<<dim3(4 * (NLAYER - 1), splits), 256, 0, s>>>(w);
+    k_mlp_wgrad<16><<<dim3(HID / 128, splits), 256, 0, s>>>(w);
+    k_mlp_grad_reduce<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->part_w, splits, p->part_b, blocks,
+                                                                   p->n_params, p->grads);
 }
 
 int check_rows(gbp_mlp p, int m) {
@@ -552,22 +738,24 @@ extern "C" int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp* out) {
     (void)hipGetDevice(&p->device);
     p->max_rows = max_rows;
     p->n_params = n_params_total();
-    // split-K partials of a weight gradient, column-sum partials, loss partials
-    p->part_n = std::max({(size_t)kSplits * HID * HID, (size_t)((max_rows + 255) / 256) * (HID + 1),
-                          (size_t)gbp_blocks(max_rows, 256)});
+    p->mp = (max_rows + 127) / 128 * 128;
+    const size_t mr = (size_t)max_rows, mp = (size_t)p->mp;
     bool ok = hipMalloc((void**)&p->params, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->grads, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->m, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->v, sizeof(float) * p->n_params) == hipSuccess &&
-              hipMalloc((void**)&p->y, sizeof(float) * max_rows) == hipSuccess &&
-              hipMalloc((void**)&p->dy, sizeof(float) * max_rows) == hipSuccess &&
-              hipMalloc((void**)&p->part, sizeof(float) * p->part_n) == hipSuccess &&
-              hipMalloc((void**)&p->loss, sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&p->dZ[0], sizeof(bf16) * max_rows * HID) == hipSuccess &&
-              hipMalloc((void**)&p->dZ[1], sizeof(bf16) * max_rows * HID) == hipSuccess;
+              hipMalloc((void**)&p->wT, sizeof(bf16) * (NLAYER - 1) * HID * HID) == hipSuccess &&
+              hipMalloc((void**)&p->H, sizeof(bf16) * NLAYER * mr * HID) == hipSuccess &&
+              hipMalloc((void**)&p->T, sizeof(bf16) * (IN + (NLAYER - 1) * HID) * mp) == hipSuccess &&
+              hipMalloc((void**)&p->dZT, sizeof(bf16) * NLAYER * HID * mp) == hipSuccess &&
+              hipMalloc((void**)&p->y, sizeof(float) * mr) == hipSuccess &&
+              hipMalloc((void**)&p->dy, sizeof(float) * mr) == hipSuccess &&
+              hipMalloc((void**)&p->part, sizeof(float) * gbp_blocks(max_rows, 256)) == hipSuccess &&
+              hipMalloc((void**)&p->part_w, sizeof(float) * kMaxSplits * p->n_params) == hipSuccess &&
+              hipMalloc((void**)&p->part_b, sizeof(float) * ((mr + 63) / 64) * kBwdPart) == hipSuccess &&
+              hipMalloc((void**)&p->loss, sizeof(float)) == hipSuccess;
     for (int l = 1; ok && l <= NLAYER; ++l)
-        ok = hipMalloc((void**)&p->wbf[l - 1], sizeof(bf16) * HID * in_dim(l)) == hipSuccess &&
-             hipMalloc((void**)&p->H[l], sizeof(bf16) * max_rows * HID) == hipSuccess;
+        ok = hipMalloc((void**)&p->wbf[l - 1], sizeof(bf16) * HID * in_dim(l)) == hipSuccess;
     if (!ok) {
         gbp_set_error("mlp: allocation failed");
         free_mlp(p);
@@ -684,12 +872,7 @@ extern "C" int gbp_mlp_forward(gbp_mlp p, const uint16_t* X, int m, float out_sc
         gbp_set_error("mlp_forward: X must be 16-byte aligned");
         return GBP_ERR_ARG;
     }
-    if (m >= kInferRowsLarge)
-        k_mlp_infer<8><<<(m + 127) / 128, 256, 0, s>>>((const bf16*)X, m, p->wbf[0], p->wbf[1], p->wbf[2],
-                                                      p->wbf[3], p->params, out_scale, y);
-    else
-        k_mlp_infer<4><<<(m + 63) / 64, 256, 0, s>>>((const bf16*)X, m, p->wbf[0], p->wbf[1], p->wbf[2],
-                                                    p->wbf[3], p->params, out_scale, y);
+    launch_fwd(p, (const bf16*)X, m, out_scale, y, false, s);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -702,9 +885,14 @@ extern "C" int gbp_mlp_gradient(gbp_mlp p, const uint16_t* X, int m, const float
         gbp_set_error("mlp_gradient: NULL argument");
         return GBP_ERR_ARG;
     }
+    if (reinterpret_cast<uintptr_t>(X) & 15) {
+        gbp_set_error("mlp_gradient: X must be 16-byte aligned");
+        return GBP_ERR_ARG;
+    }
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = forward_all(p, (const bf16*)X, m, s))) return rc;
-    if ((rc = backward_all(p, (const bf16*)X, m, target, s))) return rc;
+    launch_fwd(p, (const bf16*)X, m, 1.f, p->y, true, s);
+    launch_bwd(p, m, target, s);
+    GBP_LAUNCH_CHECK();
     if (loss) GBP_HIP(hipMemcpyAsync(loss, p->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return GBP_OK;
 }

@@ -137,17 +137,24 @@ def test_forward_matches_oracle(m):
     assert np.array_equal(net.get_params(), params)
 
 
-@pytest.mark.parametrize("m", [700, 5000])
+@pytest.mark.parametrize("m", [700, 5000, 33_000])
 def test_gradient_matches_oracle(m):
+    """Both row tilings of the fused forward and backward (64 rows per block below
+    32768 rows, 128 above), ragged tails, several weight-gradient splits; the
+    gradient is bitwise repeatable."""
     _dev()
     params = gi.mlp_params(8)
     bits, vals = gi.mlp_rows(m, seed=100 + m)
     r = np.random.Generator(np.random.PCG64(m))
     t = r.normal(size=m).astype(np.float32)
-    net = B().MLP(8192, seed=0)
+    net = B().MLP(max(m, 8192), seed=0)
     net.set_params(params)
-    loss = net.gradient(torch.as_tensor(bits, device="cuda"), t32(t, "cuda"))
+    Xd, td = torch.as_tensor(bits, device="cuda"), t32(t, "cuda")
+    loss = net.gradient(Xd, td)
     _, g = net.get_params(grads=True)
+    loss2 = net.gradient(Xd, td)
+    _, g2 = net.get_params(grads=True)
+    assert np.array_equal(g, g2) and float(loss) == float(loss2)
     lo, _, c = M.loss_and_gradient(params, vals, t, cache=True)
     _, sig = forward_sigma(params, vals)
     # loss = mean (y - t)^2 moves by at most 2 rms(y - t) rms(dy) (Cauchy-Schwarz)
