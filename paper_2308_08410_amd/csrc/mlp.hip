@@ -416,17 +416,15 @@ struct MlpWgrad {
 };
 
 template <int NB>
-__global__ void __launch_bounds__(256) k_mlp_wgrad(MlpWgrad a) {
+__device__ __forceinline__ void wgrad_tile(const MlpWgrad& a, int tile, bf16 (*As)[128][KP], bf16 (*Bs)[NB][KP]) {
     constexpr int TJ = NB == 128 ? 4 : 2, TN = NB == 128 ? 4 : 1;
     constexpr int in = NB == 128 ? HID : IN;
-    const int l = NB == 128 ? 2 + (int)blockIdx.x / 4 : 1;
-    const int jt = NB == 128 ? (blockIdx.x >> 1) & 1 : blockIdx.x, nt = NB == 128 ? blockIdx.x & 1 : 0;
+    const int l = NB == 128 ? 2 + tile / 4 : 1;
+    const int jt = NB == 128 ? (tile >> 1) & 1 : tile, nt = NB == 128 ? tile & 1 : 0;
     const bf16* A = (l == 1 ? a.dZT[0] : l == 2 ? a.dZT[1] : l == 3 ? a.dZT[2] : a.dZT[3]) +
                     (size_t)(jt * 128) * a.mp;
     const bf16* Bm = (l == 1 ? a.T[0] : l == 2 ? a.T[1] : l == 3 ? a.T[2] : a.T[3]) + (size_t)(nt * NB) * a.mp;
     const int kb = blockIdx.y * a.kchunk, ke = min(a.kend, kb + a.kchunk);
-    __shared__ __align__(16) bf16 As[2][128][KP];
-    __shared__ __align__(16) bf16 Bs[2][NB][KP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int lr = lane & 15, lq = lane >> 4;
     const int wj = NB == 128 ? (wave >> 1) * 64 : wave * 32, wn = NB == 128 ? (wave & 1) * 64 : 0;
@@ -489,45 +487,77 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(MlpWgrad a) {
             }
 }
 
-// gradient = the splits' weight partials (W1..W4) or the backward blocks' partials
-// (b1..b4, w5, b5), each summed in a fixed order
-__global__ void k_mlp_grad_reduce(const float* __restrict__ pw, int splits, const float* __restrict__ pb,
-                                  int blocks, int n_params, float* __restrict__ g) {
+// blocks x < 12: layers 2..4 (NB = 128); x = 12, 13: layer 1 (NB = 16); y: the split
+constexpr int kWgradTiles = 4 * (NLAYER - 1) + HID / 128;
+__global__ void __launch_bounds__(256) k_mlp_wgrad(MlpWgrad a) {
+    __shared__ __align__(16) bf16 As[2][128][KP];
+    __shared__ __align__(16) bf16 Bs[2][128][KP];
+    if (blockIdx.x < 4 * (NLAYER - 1))
+        wgrad_tile<128>(a, blockIdx.x, As, Bs);
+    else
+        wgrad_tile<16>(a, blockIdx.x - 4 * (NLAYER - 1), As, reinterpret_cast<bf16(*)[16][KP]>(&Bs[0][0][0]));
+}
+
+// weight gradients: the splits' partials of each W1..W4 entry, summed in split order
+__global__ void k_mlp_reduce_w(const float* __restrict__ pw, int splits, int n_params, float* __restrict__ g) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_params) return;
-    int col = -1;   // column of the backward partials, or -1 for a weight entry
-    for (int l = 1; l <= NLAYER; ++l)
-        if (e >= off_b_dev(l) && e < off_b_dev(l) + HID) col = (l - 1) * HID + (e - off_b_dev(l));
-    if (e >= off_w5_dev()) col = NLAYER * HID + (e - off_w5_dev());
+    bool weight = false;
+    for (int l = 1; l <= NLAYER; ++l) weight |= e >= off_W_dev(l) && e < off_b_dev(l);
+    if (!weight) return;
     float s = 0.f;
-    if (col < 0)
-        for (int z = 0; z < splits; ++z) s += pw[(size_t)z * n_params + e];
-    else
-        for (int b = 0; b < blocks; ++b) s += pb[(size_t)b * kBwdPart + col];
+#pragma unroll 8
+    for (int z = 0; z < splits; ++z) s += pw[(size_t)z * n_params + e];
     g[e] = s;
 }
 
-// inference rows per block 16 TR: 128 once there are enough rows to give every CU a
-// block (fewer weight fetches per row), else 64 (more blocks for small batches)
-constexpr int kRowsLarge = 32768;
+// b1..b4, w5, b5: one wave per entry; lane k sums the backward blocks k, k + 64, ... in
+// order, then a fixed butterfly adds the lanes (the same order on every call)
+__global__ void k_mlp_reduce_b(const float* __restrict__ pb, int blocks, float* __restrict__ g) {
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (col >= kBwdPart) return;
+    float s = 0.f;
+    for (int b = lane; b < blocks; b += 64) s += pb[(size_t)b * kBwdPart + col];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0)
+        g[col < NLAYER * HID ? off_b_dev(col / HID + 1) + col % HID : off_w5_dev() + (col - NLAYER * HID)] = s;
+}
+
+// Rows per block (16 TR) of the row-tile kernels: a larger tile fetches the weights
+// fewer times per row, more blocks hide more latency; the steps are where the
+// measured forward and training times cross (128 rows from 65536 rows, 64 from
+// 16384, else 32).
+__host__ int tile_rows(int m) { return m >= 65536 ? 128 : m >= 16384 ? 64 : 32; }
 // inference keeps nothing per row on the device: any batch up to 2^27 rows
 constexpr int kInferRowsMax = 1 << 27;
 
-// WT[n][j] = bf16(W[j][n]) for a 256 x 256 weight
-__global__ void k_cast_bf16_T(const float* __restrict__ W, bf16* __restrict__ WT) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= HID * HID) return;
-    const int n = t / HID, j = t % HID;
-    WT[t] = to_bf16(W[(size_t)j * HID + n]);
+// The bf16 copies of the hidden weights the kernels read: W1..W4 as stored and
+// W2^T..W4^T (WT[n][j] = W[j][n]) for the backward chain.
+struct MlpCopies {
+    bf16* w[NLAYER];
+    bf16* wT;   // [3][256][256]
+};
+
+__device__ __forceinline__ void write_copies(const MlpCopies& c, int e, float v) {
+#pragma unroll
+    for (int l = 1; l <= NLAYER; ++l)
+        if (e >= off_W_dev(l) && e < off_b_dev(l)) {
+            const int k = e - off_W_dev(l);
+            const bf16 h = to_bf16(v);
+            c.w[l - 1][k] = h;
+            if (l > 1) c.wT[(size_t)(l - 2) * HID * HID + (k % HID) * HID + k / HID] = h;
+        }
 }
 
-__global__ void k_cast_bf16(const float* __restrict__ x, int n, bf16* __restrict__ y) {
+__global__ void k_refresh_copies(const float* __restrict__ p, int n, MlpCopies c) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) y[t] = to_bf16(x[t]);
+    if (t < n) write_copies(c, t, p[t]);
 }
 
+// one Adam step on the fp32 masters, refreshing their bf16 copies
 __global__ void k_adam_flat(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int n, float lr, float c1, float c2) {
+                            float* __restrict__ v, int n, float lr, float c1, float c2, MlpCopies c) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const float gi = g[t];
@@ -535,7 +565,9 @@ __global__ void k_adam_flat(float* __restrict__ p, const float* __restrict__ g, 
     const float vi = 0.999f * v[t] + 0.001f * gi * gi;
     m[t] = mi;
     v[t] = vi;
-    p[t] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    const float pi = p[t] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    p[t] = pi;
+    write_copies(c, t, pi);
 }
 
 // ---------------------------------------------------------------- features
@@ -639,14 +671,15 @@ void free_mlp(gbp_mlp p) {
     delete p;
 }
 
+MlpCopies copies_of(gbp_mlp p) {
+    MlpCopies c{};
+    for (int l = 0; l < NLAYER; ++l) c.w[l] = p->wbf[l];
+    c.wT = p->wT;
+    return c;
+}
+
 int refresh_bf16(gbp_mlp p, hipStream_t s) {
-    for (int l = 1; l <= NLAYER; ++l) {
-        const int n = HID * in_dim(l);
-        k_cast_bf16<<<gbp_blocks(n, 256), 256, 0, s>>>(p->params + off_W(l), n, p->wbf[l - 1]);
-        if (l > 1)
-            k_cast_bf16_T<<<gbp_blocks(HID * HID, 256), 256, 0, s>>>(p->params + off_W(l),
-                                                                     p->wT + (size_t)(l - 2) * HID * HID);
-    }
+    k_refresh_copies<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->params, p->n_params, copies_of(p));
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -664,21 +697,21 @@ MlpKeep keep_of(gbp_mlp p) {
 // forward (raw y in p->y, activations kept)
 void launch_fwd(gbp_mlp p, const bf16* X, int m, float out_scale, float* y, bool train, hipStream_t s) {
     const MlpKeep k = train ? keep_of(p) : MlpKeep{};
-    if (m >= kRowsLarge) {
-        if (train)
-            k_mlp_fwd<8, true><<<(m + 127) / 128, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
-                                                               p->params, 1.f, y, k);
-        else
-            k_mlp_fwd<8, false><<<(m + 127) / 128, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
-                                                                p->params, out_scale, y, k);
+    const int ib = tile_rows(m), blocks = (m + ib - 1) / ib;
+#define GBP_FWD(TR, TRAIN)                                                                              \
+    k_mlp_fwd<TR, TRAIN><<<blocks, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3], p->params, \
+                                                TRAIN ? 1.f : out_scale, y, k)
+    if (ib == 128) {
+        if (train) GBP_FWD(8, true);
+        else GBP_FWD(8, false);
+    } else if (ib == 64) {
+        if (train) GBP_FWD(4, true);
+        else GBP_FWD(4, false);
     } else {
-        if (train)
-            k_mlp_fwd<4, true><<<(m + 63) / 64, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
-                                                             p->params, 1.f, y, k);
-        else
-            k_mlp_fwd<4, false><<<(m + 63) / 64, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3],
-                                                              p->params, out_scale, y, k);
+        if (train) GBP_FWD(2, true);
+        else GBP_FWD(2, false);
     }
+#undef GBP_FWD
 }
 
 // loss, backward chain, weight gradients, reduction into p->grads
@@ -698,10 +731,10 @@ void launch_bwd(gbp_mlp p, int m, const float* target, hipStream_t s) {
     b.part = p->part_b;
     b.m = m;
     b.mp = p->mp;
-    const int ib = m >= kRowsLarge ? 128 : 64;
-    const int blocks = (m + ib - 1) / ib;
+    const int ib = tile_rows(m), blocks = (m + ib - 1) / ib;
     if (ib == 128) k_mlp_bwd<8><<<blocks, 256, 0, s>>>(b);
-    else k_mlp_bwd<4><<<blocks, 256, 0, s>>>(b);
+    else if (ib == 64) k_mlp_bwd<4><<<blocks, 256, 0, s>>>(b);
+    else k_mlp_bwd<2><<<blocks, 256, 0, s>>>(b);
     MlpWgrad w{};
     for (int l = 0; l < NLAYER; ++l) {
         w.dZT[l] = b.dZT[l];
@@ -713,10 +746,9 @@ void launch_bwd(gbp_mlp p, int m, const float* target, hipStream_t s) {
     w.kchunk = wgrad_chunk(w.kend);
     w.n_params = p->n_params;
     const int splits = (w.kend + w.kchunk - 1) / w.kchunk;
-    k_mlp_wgrad<128><<<dim3(4 * (NLAYER - 1), splits), 256, 0, s>>>(w);
-    k_mlp_wgrad<16><<<dim3(HID / 128, splits), 256, 0, s>>>(w);
-    k_mlp_grad_reduce<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->part_w, splits, p->part_b, blocks,
-                                                                   p->n_params, p->grads);
+    k_mlp_wgrad<<<dim3(kWgradTiles, splits), 256, 0, s>>>(w);
+    k_mlp_reduce_w<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->part_w, splits, p->n_params, p->grads);
+    k_mlp_reduce_b<<<(kBwdPart + 3) / 4, 256, 0, s>>>(p->part_b, blocks, p->grads);
 }
 
 int check_rows(gbp_mlp p, int m) {
@@ -752,7 +784,7 @@ extern "C" int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp* out) {
               hipMalloc((void**)&p->dy, sizeof(float) * mr) == hipSuccess &&
               hipMalloc((void**)&p->part, sizeof(float) * gbp_blocks(max_rows, 256)) == hipSuccess &&
               hipMalloc((void**)&p->part_w, sizeof(float) * kMaxSplits * p->n_params) == hipSuccess &&
-              hipMalloc((void**)&p->part_b, sizeof(float) * ((mr + 63) / 64) * kBwdPart) == hipSuccess &&
+              hipMalloc((void**)&p->part_b, sizeof(float) * ((mr + 31) / 32) * kBwdPart) == hipSuccess &&
               hipMalloc((void**)&p->loss, sizeof(float)) == hipSuccess;
     for (int l = 1; ok && l <= NLAYER; ++l)
         ok = hipMalloc((void**)&p->wbf[l - 1], sizeof(bf16) * HID * in_dim(l)) == hipSuccess;
@@ -906,7 +938,7 @@ extern "C" int gbp_mlp_train_step(gbp_mlp p, const uint16_t* X, int m, const flo
     const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, p->step)));
     const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, p->step)));
     k_adam_flat<<<gbp_blocks(p->n_params, 256), 256, 0, s>>>(p->params, p->grads, p->m, p->v,
-                                                             p->n_params, lr, c1, c2);
+                                                             p->n_params, lr, c1, c2, copies_of(p));
     GBP_LAUNCH_CHECK();
-    return refresh_bf16(p, s);
+    return GBP_OK;
 }

@@ -116,10 +116,10 @@ def test_features_match_oracle(shell):
     assert np.all(np.abs(bits_to_f64(X1) - Xo1) <= U_BF16 * np.abs(Xo1) + 1e-6)
 
 
-@pytest.mark.parametrize("m", [1, 63, 3000, 4096, 40_000])
+@pytest.mark.parametrize("m", [1, 63, 3000, 4096, 40_000, 70_000])
 def test_forward_matches_oracle(m):
-    """Both row tilings of the inference kernel (64 rows per block below 32768
-    rows, 128 above), ragged tails included."""
+    """Every row tiling of the inference kernel (32 rows per block below 16384 rows,
+    64 below 65536, 128 above), ragged tails included."""
     _dev()
     params = gi.mlp_params(7)
     bits, vals = gi.mlp_rows(m, seed=m)
@@ -137,11 +137,11 @@ def test_forward_matches_oracle(m):
     assert np.array_equal(net.get_params(), params)
 
 
-@pytest.mark.parametrize("m", [700, 5000, 33_000])
+@pytest.mark.parametrize("m", [700, 40_000, 66_000])
 def test_gradient_matches_oracle(m):
-    """Both row tilings of the fused forward and backward (64 rows per block below
-    32768 rows, 128 above), ragged tails, several weight-gradient splits; the
-    gradient is bitwise repeatable."""
+    """Every row tiling of the fused forward and backward (32, 64 and 128 rows per
+    block), ragged tails, one to many weight-gradient splits; the gradient is
+    bitwise repeatable."""
     _dev()
     params = gi.mlp_params(8)
     bits, vals = gi.mlp_rows(m, seed=100 + m)
