@@ -97,34 +97,61 @@ __device__ __forceinline__ bf16x8_t ld8(const bf16* p) {
 }
 __device__ __forceinline__ bool relu_on(bf16 h) { return h != 0 && !(h & 0x8000); }
 
-// acc[t][c][r] = sum_k A[j][k] S[16 t + lr][k] with j = j0 + 16 c + 4 lq + r
+// acc[t][c][r] = sum_k A[j][k] S[16 t + lr][k] with j = j0 + 16 c + 4 lq + r.  The
+// weight fragments run D K steps ahead of the multiplies (a ring of D + 1 steps): 3
+// for the small tiles, whose few multiplies per step would otherwise wait on the
+// loads, 1 for the 128-row tile (registers).
 template <int TR>
 __device__ __forceinline__ void tile_layer(const bf16* __restrict__ A, bf16 (*S)[HP],
                                            floatx4 (&acc)[TR][4], int j0, int lr, int lq) {
+    constexpr int NS = HID / 32;   // K steps
 #pragma unroll
     for (int t = 0; t < TR; ++t)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    bf16x8_t bw[4], bn[4];
+    const bf16* a0 = A + (size_t)(j0 + lr) * HID + 8 * lq;
+    if constexpr (TR >= 8) {
+        bf16x8_t bw[4], bn[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) bw[c] = ld8(A + (size_t)(j0 + c * 16 + lr) * HID + 8 * lq);
+        for (int c = 0; c < 4; ++c) bw[c] = ld8(a0 + (size_t)c * 16 * HID);
 #pragma unroll 2
-    for (int ks = 0; ks < HID / 32; ++ks) {
-        if (ks + 1 < HID / 32) {
+        for (int ks = 0; ks < NS; ++ks) {
+            if (ks + 1 < NS) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                bn[c] = ld8(A + (size_t)(j0 + c * 16 + lr) * HID + (ks + 1) * 32 + 8 * lq);
+                for (int c = 0; c < 4; ++c) bn[c] = ld8(a0 + (size_t)c * 16 * HID + (ks + 1) * 32);
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&S[t * 16 + lr][ks * 32 + 8 * lq]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, acc[t][c], 0, 0, 0);
+            }
+            if (ks + 1 < NS) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) bw[c] = bn[c];
+            }
         }
+    } else {
+        constexpr int D = 3;
+        bf16x8_t ring[D + 1][4];
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&S[t * 16 + lr][ks * 32 + 8 * lq]);
+        for (int d = 0; d < D; ++d)
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, acc[t][c], 0, 0, 0);
-        }
-        if (ks + 1 < HID / 32) {
+            for (int c = 0; c < 4; ++c) ring[d][c] = ld8(a0 + (size_t)c * 16 * HID + d * 32);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) bw[c] = bn[c];
+        for (int ks = 0; ks < NS; ++ks) {
+            if (ks + D < NS) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ring[(ks + D) % (D + 1)][c] = ld8(a0 + (size_t)c * 16 * HID + (ks + D) * 32);
+            }
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&S[t * 16 + lr][ks * 32 + 8 * lq]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ring[ks % (D + 1)][c], af, acc[t][c], 0, 0, 0);
+            }
         }
     }
 }
@@ -401,11 +428,12 @@ __global__ void __launch_bounds__(256, 2) k_mlp_bwd(MlpBwd a) {
 // ---------------------------------------------------------------- weight gradients
 // dW_l[j][n] = sum_i dZ_l[i][j] H_{l-1}[i][n] (H_0 = X) over the rows [kb, ke) of a
 // split, from the transposed copies (both operands K-contiguous): a block computes 128
-// (j) x NB (n) of one layer, K steps of 32 staged through LDS in two buffers (the next
+// (j) x NB (n) of one layer, K steps of 64 staged through LDS in two buffers (the next
 // step's global loads in flight while the current one multiplies); waves 2 x 2 of 64 x 64
 // (NB = 128, layers 2..4: block x = 4 (l - 2) + 2 j-tile + n-tile) or 4 x 1 of 32 x 16
 // (NB = 16, layer 1: block x = j-tile).  Fixed-order fp32 partials per split.
-constexpr int KP = 40;   // LDS row pitch (bf16) of a staged K step: 80 bytes
+constexpr int KW = 64;         // K per staged step of the weight gradients
+constexpr int KP = KW + 8;     // LDS row pitch (bf16): 144 bytes, conflict-free 16-byte reads
 
 struct MlpWgrad {
     const bf16* dZT[NLAYER];   // [256][mp]
@@ -433,22 +461,26 @@ __device__ __forceinline__ void wgrad_tile(const MlpWgrad& a, int tile, bf16 (*A
     for (int x = 0; x < TJ; ++x)
 #pragma unroll
         for (int z = 0; z < TN; ++z) acc[x][z] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // staging: A 128 rows x 4 chunks of 16 bytes (2 per thread), B NB rows x 4 chunks
-    uint4 ra[2], rb[2];
+    // staging: A 128 rows x 8 chunks of 16 bytes (4 per thread), B NB rows x 8 chunks;
+    // chunks at or past ke (a multiple of 32) are zero
+    uint4 ra[4], rb[4];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = threadIdx.x + 256 * u, row = e >> 2, q = e & 3;
-            ra[u] = *reinterpret_cast<const uint4*>(A + (size_t)row * a.mp + k0 + 8 * q);
-            if (e < NB * 4) rb[u] = *reinterpret_cast<const uint4*>(Bm + (size_t)row * a.mp + k0 + 8 * q);
+        for (int u = 0; u < 4; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e >> 3, q = e & 7;
+            const bool in_k = k0 + 8 * q < ke;
+            ra[u] = in_k ? *reinterpret_cast<const uint4*>(A + (size_t)row * a.mp + k0 + 8 * q) : make_uint4(0u, 0u, 0u, 0u);
+            if (e < NB * 8)
+                rb[u] = in_k ? *reinterpret_cast<const uint4*>(Bm + (size_t)row * a.mp + k0 + 8 * q)
+                             : make_uint4(0u, 0u, 0u, 0u);
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = threadIdx.x + 256 * u, row = e >> 2, q = e & 3;
+        for (int u = 0; u < 4; ++u) {
+            const int e = threadIdx.x + 256 * u, row = e >> 3, q = e & 7;
             *reinterpret_cast<uint4*>(&As[buf][row][8 * q]) = ra[u];
-            if (e < NB * 4) *reinterpret_cast<uint4*>(&Bs[buf][row][8 * q]) = rb[u];
+            if (e < NB * 8) *reinterpret_cast<uint4*>(&Bs[buf][row][8 * q]) = rb[u];
         }
     };
     if (kb < ke) {
@@ -457,19 +489,24 @@ __device__ __forceinline__ void wgrad_tile(const MlpWgrad& a, int tile, bf16 (*A
     }
     __syncthreads();
     int buf = 0;
-    for (int k0 = kb; k0 < ke; k0 += 32) {
-        const bool more = k0 + 32 < ke;
-        if (more) gload(k0 + 32);
-        bf16x8_t af[TJ], bfr[TN];
+    for (int k0 = kb; k0 < ke; k0 += KW) {
+        const bool more = k0 + KW < ke;
+        if (more) gload(k0 + KW);
 #pragma unroll
-        for (int x = 0; x < TJ; ++x) af[x] = *reinterpret_cast<const bf16x8_t*>(&As[buf][wj + x * 16 + lr][8 * lq]);
+        for (int kk = 0; kk < KW; kk += 32) {
+            bf16x8_t af[TJ], bfr[TN];
 #pragma unroll
-        for (int z = 0; z < TN; ++z) bfr[z] = *reinterpret_cast<const bf16x8_t*>(&Bs[buf][wn + z * 16 + lr][8 * lq]);
-#pragma unroll
-        for (int x = 0; x < TJ; ++x)
+            for (int x = 0; x < TJ; ++x)
+                af[x] = *reinterpret_cast<const bf16x8_t*>(&As[buf][wj + x * 16 + lr][kk + 8 * lq]);
 #pragma unroll
             for (int z = 0; z < TN; ++z)
-                acc[x][z] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x], bfr[z], acc[x][z], 0, 0, 0);
+                bfr[z] = *reinterpret_cast<const bf16x8_t*>(&Bs[buf][wn + z * 16 + lr][kk + 8 * lq]);
+#pragma unroll
+            for (int x = 0; x < TJ; ++x)
+#pragma unroll
+                for (int z = 0; z < TN; ++z)
+                    acc[x][z] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x], bfr[z], acc[x][z], 0, 0, 0);
+        }
         if (more) lstore(buf ^ 1);
         __syncthreads();
         buf ^= 1;
@@ -656,9 +693,9 @@ int n_params_total() { return off_w5() + HID + 1; }
 int in_dim(int l) { return l == 1 ? IN : HID; }
 
 // Row chunks of the weight-gradient splits: at most kMaxSplits chunks of a multiple of
-// 32 rows, at least 256.
+// the staged K step, at least 256 rows.
 constexpr int kMaxSplits = 32;
-int wgrad_chunk(int kend) { return std::max(256, ((kend + kMaxSplits - 1) / kMaxSplits + 31) / 32 * 32); }
+int wgrad_chunk(int kend) { return std::max(256, ((kend + kMaxSplits - 1) / kMaxSplits + KW - 1) / KW * KW); }
 
 void free_mlp(gbp_mlp p) {
     if (!p) return;
