@@ -47,6 +47,27 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
     return t;
 }
 
+// Sums of two values over the block (fixed order); results valid in thread 0.
+__device__ __forceinline__ void block_sum2_u64(unsigned long long& a, unsigned long long& b) {
+    __shared__ unsigned long long red2[2][TPB / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red2[0][threadIdx.x >> 6] = a;
+        red2[1][threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = 0;
+        for (int w = 0; w < TPB / 64; ++w) {
+            a += red2[0][w];
+            b += red2[1][w];
+        }
+    }
+}
+
 __device__ __forceinline__ float block_max_f(float v) {
     __shared__ float red[TPB / 64];
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -704,18 +725,31 @@ __global__ void __launch_bounds__(TPB)
         }
     }
     if constexpr (HOLD) {
-        // the staged holds: count per ring slot, reserve room with one atomic per
-        // slot, scatter; a vertex that finds its list full pushes its neighbours now
+        // the staged holds and the pushed vertices together: count per ring slot and
+        // per sub-queue, reserve room with one atomic per non-empty slot or sub-queue
+        // (all in one pass), scatter; a vertex that finds its list full pushes its
+        // neighbours straight to the global queue
         __syncthreads();
         const int nh = min(hold_n, kHoldStage);
+        const int np = min(push_n, CAP);
         if (threadIdx.x < kHoldBuckets) hold_cnt[threadIdx.x] = 0;
+        if (threadIdx.x < 8) push_cnt[threadIdx.x] = 0;
         __syncthreads();
         for (int k = threadIdx.x; k < nh; k += blockDim.x) atomicAdd(&hold_cnt[hold_s[k]], 1);
+        if (split)
+            for (int k = threadIdx.x; k < np; k += blockDim.x) atomicAdd(&push_cnt[xcd_of(push_q[k], xq.R)], 1);
+        else if (threadIdx.x == 0)
+            push_cnt[0] = np;
         __syncthreads();
         if (threadIdx.x < kHoldBuckets) {
             const int m = hold_cnt[threadIdx.x];
             hold_base[threadIdx.x] = m > 0 ? atomicAdd(&ctl->bcnt[threadIdx.x], m) : 0;
             hold_cnt[threadIdx.x] = 0;
+        } else if (threadIdx.x < kHoldBuckets + 8) {
+            const int xs = threadIdx.x - kHoldBuckets;
+            const int m = push_cnt[xs];
+            push_base[xs] = m > 0 ? xq.off[xs] + atomicAdd(&cnt_next[xs], m) : 0;
+            push_cnt[xs] = 0;
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nh; k += blockDim.x) {
@@ -725,24 +759,36 @@ __global__ void __launch_bounds__(TPB)
                 ha.blist[(size_t)sl * ha.bcap + pos] = v;
             } else if (ha.guess) {
                 ha.hold[v] = INT_MIN;   // its list is full: queued now (claimed this round)
-                xpush_node<true>(pb, v, xq, qout, cnt_next);
+                const int x2 = split ? xcd_of(v, xq.R) : 0;
+                qout[xq.off[x2] + atomicAdd(&cnt_next[x2], 1)] = v;
             } else {
                 ha.hold[v] = INT_MIN;
                 for (int a = adj_ptr[v]; a < adj_ptr[v + 1]; ++a) {
                     const int nb = adj[a];
-                    if (atomicMax(&mark[nb], stamp_next) < stamp_next)
-                        xpush_node<TWO_SIDED>(pb, nb, xq, qout, cnt_next);
+                    if (atomicMax(&mark[nb], stamp_next) < stamp_next) {
+                        const int x2 = split ? xcd_of(nb, xq.R) : 0;
+                        qout[xq.off[x2] + atomicAdd(&cnt_next[x2], 1)] = nb;
+                    }
                 }
             }
         }
+        if (split) {
+            for (int k = threadIdx.x; k < np; k += blockDim.x) {
+                const int v = push_q[k];
+                const int x2 = xcd_of(v, xq.R);
+                qout[push_base[x2] + atomicAdd(&push_cnt[x2], 1)] = v;
+            }
+        } else {
+            for (int k = threadIdx.x; k < np; k += blockDim.x) qout[push_base[0] + k] = push_q[k];
+        }
+    } else {
+        xpush_flush(pb, xq, qout, cnt_next, push_cnt, push_base);
     }
-    xpush_flush(pb, xq, qout, cnt_next, push_cnt, push_base);
     // per-block counters: one writer per slot, no contended atomics
-    solves = block_sum_u64(solves);
-    upd = block_sum_u64(upd);
+    block_sum2_u64(solves, upd);
     if (threadIdx.x == 0) {
-        blk[2 * blockIdx.x] += solves;
-        blk[2 * blockIdx.x + 1] += upd;
+        __hip_atomic_fetch_add(&blk[2 * blockIdx.x], solves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&blk[2 * blockIdx.x + 1], upd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
