@@ -68,14 +68,15 @@ FORMS = ("warm", "points", "leadfield", "fista", "slice", "batched", "learned", 
 
 
 # Launch configuration of the plain iteration on this workload: the autotuner's
-# search (autotune.tune) followed by a finer sweep of the hold-back around its
-# pick, timed with this script (16 lanes per vertex, 1024 blocks per relaxation
-# round, convergence read every 16 launches, 2048 blocks per adjoint level, queue
-# split over the XCDs; hold-back buckets of 2.5 ms, no window, the next bucket
-# opened while fewer than 16384 vertices -- one round's grid -- are queued).
-# Fixed so that a profiled run of the same command times the same kernels;
-# --tune searches again.
-DEFAULT_LAUNCH = "16,1024,16,2048,1"
+# search (autotune.tune) followed by finer sweeps of the relaxation grid and the
+# hold-back around its pick, timed with this script (16 lanes per vertex, 768
+# blocks per relaxation round -- three per CU: 1024 and 896 were 2-3% slower, 640
+# and 512 slower still --, convergence read every 16 launches, 2048 blocks per
+# adjoint level, queue split over the XCDs; hold-back buckets of 2.5 ms, no window,
+# the next bucket opened while fewer than 16384 vertices are queued).  Fixed so
+# that a profiled run of the same command times the same kernels; --tune
+# searches again.
+DEFAULT_LAUNCH = "16,768,16,2048,1"
 DEFAULT_HOLD = "2.5,0,16384"
 
 

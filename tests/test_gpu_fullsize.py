@@ -163,7 +163,7 @@ def test_full_forward_with_fista(full, launch):
     assert np.all(Tg >= full.T_ref * (1 - 1e-5) - 1e-6)
 
 
-@pytest.mark.parametrize("launch", [(16, 1024, 16, 2048, True, (2.5, 0, 16384)),
+@pytest.mark.parametrize("launch", [(16, 768, 16, 2048, True, (2.5, 0, 16384)),
                                     (16, 1024, 32, 2048, True, (4.0, 0, 32768)),
                                     (8, 512, 16, 512, False, (0.0, 0, 0)),
                                     (32, 2048, 64, 1024, True, (1.0, 2, 1 << 30))])
