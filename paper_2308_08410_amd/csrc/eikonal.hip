@@ -599,16 +599,20 @@ __global__ void __launch_bounds__(TPB)
     const int lane = threadIdx.x & (L - 1);
     const int sub = threadIdx.x / L;                // vertex slot of this lane group
     unsigned long long solves = 0, upd = 0;
-    // software pipeline over the lane group's passes: the queue entry two passes
-    // ahead and the vertex record (patch pointer, value, neighbour range) one pass
-    // ahead are in flight while the current vertex is relaxed (T[i] has one writer,
-    // the group that holds i, and i is queued at most once per round)
+    // software pipeline over the lane group's passes (hold-back rounds): the queue
+    // entry two passes ahead and the vertex record (patch pointer, value, neighbour
+    // range) one pass ahead are in flight while the current vertex is relaxed (T[i]
+    // has one writer, the group that holds i, and i is queued at most once per round).
+    // Measured: it pays on the hold-back's short rounds and costs on long plain ones
+    // (many passes per block, where the extra loads in flight compete for the memory
+    // pipeline), so plain and two-sided rounds load each vertex when they reach it.
+    constexpr bool PIPE = HOLD;
     const int stride = nbx * PER_BLOCK;
     int f_iq = 0;                                   // entry of the next pass
     int2 c_p = make_int2(0, 0);                     // record of the current pass
     float c_t = 0.f, c_tr = 0.f;
     int c_a0 = 0, c_a1 = 0, c_i = 0;
-    {
+    if constexpr (PIPE) {
         const int q0 = lb * PER_BLOCK + sub, q1 = q0 + stride;
         const int iq0 = q0 < n ? pre : 0;
         c_i = min(max(iq0, 0), n_v - 1);
@@ -622,12 +626,21 @@ __global__ void __launch_bounds__(TPB)
     for (int base = lb * PER_BLOCK; base < n; base += stride) {
         const int qi = base + sub;
         const bool act = qi < n;                    // uniform over the lane group
+        if constexpr (!PIPE) {
+            const int iq = act ? (qi == qi0 ? pre : qx[qi]) : 0;
+            c_i = min(max(iq, 0), n_v - 1);
+            c_p = act ? nptr[c_i] : make_int2(0, 0);
+            c_t = T[c_i];
+            c_tr = TWO_SIDED ? troot[c_i] : 0.f;
+            c_a0 = adj_ptr[c_i];
+            c_a1 = adj_ptr[c_i + 1];
+        }
         const int i = c_i;
         const int2 p = c_p;
         const float told = c_t;
         const float tr = c_tr;
         const int adj0 = c_a0, adj1 = c_a1;
-        {
+        if constexpr (PIPE) {
             const int q1 = qi + stride, q2 = qi + 2 * stride;
             c_i = min(max(f_iq, 0), n_v - 1);
             c_p = q1 < n ? nptr[c_i] : make_int2(0, 0);
