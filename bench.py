@@ -550,7 +550,8 @@ def inverse_form(dev, torch, gi, B, iters=20, n_nodes=1_000_000, starts=16, seed
     """The inverse problem (Sec. 2.4 Eq. (inverse_ecg)) as the multi-start fit:
     `starts` fits of the 1M-vertex shell (8 roots, hidden smooth scale in
     [0.5, 1.5]) as the instances of one union plan, every iteration one replay of
-    the captured step (cold forwards) for all starts; timed over `iters`
+    the captured step (cold forwards, in the launch configuration and hold-back the
+    autotuner picks for the union plan) for all starts; timed over `iters`
     iterations after two untimed ones, the misfit of every start before and after."""
     import numpy as np
     from paper_2308_08410_amd.inverse import MultiStartFit
@@ -565,7 +566,7 @@ def inverse_form(dev, torch, gi, B, iters=20, n_nodes=1_000_000, starts=16, seed
     target = B.ecg_forward(T_true, f32(p.W), apc).cpu().numpy()
     plan1.close()
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(starts)]
-    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0)
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, tune=True)
     t_setup = time.time() - t0
     fit.run(2, check_every=0)
     loss0 = fit.loss.detach().cpu().numpy().copy()
@@ -575,6 +576,8 @@ def inverse_form(dev, torch, gi, B, iters=20, n_nodes=1_000_000, starts=16, seed
     res = dict(nodes=int(p.n_v), tets=int(p.n_e), starts=starts, union_vertices=int(fit.voff[-1]),
                iters=iters, iters_per_s=out["iters_per_s"], start_iters_per_s=out["iters_per_s"] * starts,
                ms_per_iter=1000.0 / out["iters_per_s"], setup_s=t_setup, budgets=fit.budgets,
+               launch={k: fit.tuned[k] for k in ("lanes", "sweep_blocks", "level_blocks", "sync_batch", "split",
+                                                  "hold_delta", "hold_window", "hold_open")},
                loss_after_2=[float(x) for x in loss0], loss_after_last=[float(x) for x in loss1],
                converged=bool(st["forward_converged"] and st["backward_settled"] and st["err"] == 0))
     fit.step.close()

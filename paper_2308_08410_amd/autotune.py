@@ -25,6 +25,11 @@ SPACE = [dict(lanes=lanes, sweep_blocks=sb, level_blocks=2048, sync_batch=bt, sp
          for sp in (1, 0) for lanes in (8, 16, 32) for sb in (256, 512, 768, 1024, 1536, 2048)
          for bt in (16, 32, 64)]
 LEVEL_SPACE = (256, 512, 1024, 2048)   # searched second, with the best of SPACE
+# a short list for plans of millions of vertices, where every trial costs a
+# forward and backward of the whole union (16 lanes, convergence read every 16
+# launches, 2048 blocks per level: the full search's picks on such plans)
+SPACE_LARGE = [dict(lanes=16, sweep_blocks=sb, level_blocks=2048, sync_batch=16, split=sp)
+               for sp in (1, 0) for sb in (768, 1024, 2048)]
 # hold-back candidates, searched last: (bucket width / mean front advance per round,
 # buckets past the current one that propagate, opening threshold / vertices one
 # round's grid takes at once, None: open a bucket every round); (0, 0, 0) is off
@@ -73,10 +78,12 @@ def _time(fn, repeats):
 
 
 def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, repeats=3,
-         use_cache=True, save=True):
+         use_cache=True, save=True, hold=None):
     """Pick and apply the fastest launch configuration; returns its record
     (configuration, ms per forward[+backward], rounds, levels).  Turns the plan's
-    warm order off (see tune_hold for the ordered warm start)."""
+    warm order off (see tune_hold for the ordered warm start).  The adjoint's grid
+    and the hold-back are searched after the launch space when `space` is the
+    full one (hold: None) or when hold is True."""
     B.set_warm_order(plan, False)
     key = size_key(plan)
     db = _load() if use_cache else {}
@@ -114,7 +121,7 @@ def tune(plan: B.Plan, D, vscale, root_node, root_t, backward=True, space=None, 
     B.set_launch(plan, best["lanes"], best["sweep_blocks"], best["level_blocks"], best["sync_batch"])
     B.set_queue_split(plan, best["split"])
     best.update(hold_delta=0.0, hold_window=0, hold_open=0)
-    if space is None:
+    if (space is None) if hold is None else hold:
         best.update(tune_hold(plan, D, vscale, root_node, root_t, backward=backward, repeats=repeats))
     run()
     best.update(B.last_counts(plan))

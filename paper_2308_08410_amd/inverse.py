@@ -35,7 +35,10 @@ class MultiStartFit:
     scale), fitted to the same target ECG."""
 
     def __init__(self, xyz, tets, D, W, root_node, target, ap: dict, vscale0, root_t0, warm=False,
-                 lr_vscale=0.01, lr_root_t=0.5, vscale_bounds=(0.2, 5.0), device="cuda"):
+                 lr_vscale=0.01, lr_root_t=0.5, vscale_bounds=(0.2, 5.0), device="cuda", tune=False):
+        """tune: search the launch configuration (the short list for large plans)
+        and the cold forward's hold-back for this union plan first, else the plan's
+        defaults (no hold-back)."""
         S = len(vscale0)
         n_v = len(xyz)
         dev = torch.device(device)
@@ -56,6 +59,10 @@ class MultiStartFit:
         self.T = torch.empty(S * n_v, dtype=torch.float32, device=dev)
         self.ecg = torch.empty_like(self.target)
         self.loss = torch.empty(S, dtype=torch.float32, device=dev)
+        self.tuned = None
+        if tune:
+            self.tuned = autotune.tune(self.plan, self.D, self.vs, self.rn, self.rt, use_cache=False,
+                                       save=False, repeats=1, space=autotune.SPACE_LARGE, hold=True)
         # one synchronous pass sizes the launch budgets of the captured step
         B.eikonal_forward(self.plan, self.D, self.vs, self.rn, self.rt, out=self.T)
         B.eikonal_backward(self.plan, self.D, self.vs, self.rn, self.rt, self.T,
@@ -140,6 +147,8 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--roots", type=int, default=8)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--tune", action="store_true",
+                    help="search the launch configuration and hold-back for the union plan first")
     ap.add_argument("--warm", action="store_true",
                     help="start each forward from the previous iteration's activation times")
     ap.add_argument("--log", default="", help="JSON-lines run log (appended)")
@@ -157,7 +166,8 @@ def main(argv=None):
     target = B.ecg_forward(T_true, torch.as_tensor(p.W, device=dev),
                            B.make_ap(a["K0"], a["K1"], a["tau"], a["t0"], a["dt"], a["n_steps"])).cpu().numpy()
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(args.starts)]
-    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=args.warm)
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, a, vs0, rt0, warm=args.warm,
+                        tune=args.tune)
     start = fit.restore(args.checkpoint) if args.resume else 0
     log = runlog.RunLog(args.log, "inverse", dict(vars(args), n_v=p.n_v, n_e=p.n_e, start=start,
                                                    budgets=fit.budgets)) if args.log else None

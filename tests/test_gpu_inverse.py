@@ -12,8 +12,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("warm", [True, False])
-def test_multistart_fit_reduces_misfit(warm):
+@pytest.mark.parametrize("warm,tune", [(True, False), (False, False), (False, True)])
+def test_multistart_fit_reduces_misfit(warm, tune):
     _dev()
     from paper_2308_08410_amd.inverse import MultiStartFit
     p = gi.shell_problem(8_000, seed=13, n_roots=4, n_leads=12)
@@ -25,7 +25,11 @@ def test_multistart_fit_reduces_misfit(warm):
     starts = 3
     vs0 = [np.ones(p.n_v, np.float32) for _ in range(starts)]
     rt0 = [(p.root_t + rng.uniform(-6, 6, size=len(p.root_t))).astype(np.float32) for _ in range(starts)]
-    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, ap, vs0, rt0, warm=warm)
+    fit = MultiStartFit(p.xyz, p.tets, p.D, p.W, p.root_node, target, ap, vs0, rt0, warm=warm, tune=tune)
+    if tune:   # the searched launch and hold-back are the plan's when the step is captured
+        from paper_2308_08410_amd import binding as BB
+        assert BB.get_launch(fit.plan)["sweep_blocks"] == fit.tuned["sweep_blocks"]
+        assert BB.get_hold(fit.plan)[0] == pytest.approx(fit.tuned["hold_delta"])
     out = fit.run(120, log_every=10, check_every=10)
     first, last = out["history"][0][1], out["history"][-1][1]
     assert np.all(np.isfinite(last))
