@@ -43,26 +43,6 @@ __device__ __forceinline__ bf16 to_bf16(float x) {
 __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
 // ---------------------------------------------------------------- loss
-// dy = 2 (y - t) / m, squared error partial sums per block
-__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int m,
-                      float* __restrict__ dy, float* __restrict__ part) {
-    __shared__ float sh[256];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float e = 0.f;
-    if (i < m) {
-        const float d = y[i] - t[i];
-        dy[i] = 2.f * d / (float)m;
-        e = d * d;
-    }
-    sh[threadIdx.x] = e;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
-}
-
 __global__ void k_sum_parts(const float* __restrict__ part, int n, float scale, float* __restrict__ out) {
     __shared__ float sh[256];
     float s = 0.f;
@@ -90,6 +70,8 @@ __global__ void k_sum_parts(const float* __restrict__ part, int n, float scale, 
 //   forward:  H_l = bf16(relu(W_l H_{l-1} + b_l)), then y = H_4 . w5 + b5 in fp32;
 //   backward: dZ_{l-1} = bf16((W_l^T dZ_l) [H_{l-1} > 0]) with A = W_l^T (a bf16
 //             copy kept transposed).
+// Inference runs the forward alone; training runs forward, misfit and backward
+// chain in one kernel with H1..H3 kept in LDS for the backward's masks.
 constexpr int HP = HID + 8;   // LDS row pitch (bf16): 528 bytes, 16-byte aligned rows
 
 __device__ __forceinline__ bf16x8_t ld8(const bf16* p) {
@@ -175,36 +157,24 @@ __device__ __forceinline__ void relu_store(bf16 (*S)[HP], const floatx4 (&acc)[T
     }
 }
 
-// backward epilogue: S = bf16(acc) where the forward activation Hp (row-major
-// [m][256]) of the element is positive, else 0; rows at or past m are zero
+// backward epilogue: S = bf16(acc) where the forward activation in Hp (the same
+// tile's H_{l-1}, in LDS) is positive, else 0; rows at or past m are zero
 template <int TR>
-__device__ __forceinline__ void mask_store(bf16 (*S)[HP], const floatx4 (&acc)[TR][4],
-                                           const bf16* __restrict__ Hp, int i0, int m, int j0, int lr,
-                                           int lq) {
+__device__ __forceinline__ void mask_store(bf16 (*S)[HP], const floatx4 (&acc)[TR][4], bf16 (*Hp)[HP],
+                                           int i0, int m, int j0, int lr, int lq) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int j = j0 + c * 16 + 4 * lq;
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
-            const int i = i0 + t * 16 + lr;
-            const uint2 h = i < m ? *reinterpret_cast<const uint2*>(Hp + (size_t)i * HID + j) : make_uint2(0u, 0u);
+            const int r = t * 16 + lr;
+            const uint2 h = i0 + r < m ? *reinterpret_cast<const uint2*>(&Hp[r][j]) : make_uint2(0u, 0u);
             const unsigned z0 = relu_on((bf16)(h.x & 0xffffu)) ? to_bf16(acc[t][c][0]) : 0u;
             const unsigned z1 = relu_on((bf16)(h.x >> 16)) ? to_bf16(acc[t][c][1]) : 0u;
             const unsigned z2 = relu_on((bf16)(h.y & 0xffffu)) ? to_bf16(acc[t][c][2]) : 0u;
             const unsigned z3 = relu_on((bf16)(h.y >> 16)) ? to_bf16(acc[t][c][3]) : 0u;
-            *reinterpret_cast<uint2*>(&S[t * 16 + lr][j]) = make_uint2(z0 | (z1 << 16), z2 | (z3 << 16));
+            *reinterpret_cast<uint2*>(&S[r][j]) = make_uint2(z0 | (z1 << 16), z2 | (z3 << 16));
         }
-    }
-}
-
-// the tile's rows below m into dst (row-major [m][256])
-template <int IB>
-__device__ __forceinline__ void tile_store_rows(bf16 (*S)[HP], bf16* __restrict__ dst, int i0, int m) {
-    for (int e = threadIdx.x; e < IB * (HID / 8); e += 256) {
-        const int r = e / (HID / 8), cc = e % (HID / 8);
-        if (i0 + r < m)
-            *reinterpret_cast<uint4*>(dst + (size_t)(i0 + r) * HID + 8 * cc) =
-                *reinterpret_cast<const uint4*>(&S[r][8 * cc]);
     }
 }
 
@@ -233,85 +203,34 @@ __device__ __forceinline__ float tile_store_T(bf16 (*S)[HP], bf16* __restrict__ 
     return s;
 }
 
-// What the training forward keeps for the backward pass.
-struct MlpKeep {
-    bf16* H[NLAYER];   // activations H1..H4, row-major [m][256]
-    bf16* T[NLAYER];   // the layers' inputs transposed: X^T [16][mp], H1^T, H2^T, H3^T [256][mp]
-    int mp;            // row pitch of the transposed buffers (multiple of 128)
-};
+// layer 1 (K = 16 features; quarters 2 and 3 of the 32-wide K step are zero) on the
+// tile's rows of X into acc
+template <int TR>
+__device__ __forceinline__ void tile_layer1(const bf16* __restrict__ X, int i0, int m,
+                                            const bf16* __restrict__ W1, floatx4 (&acc)[TR][4], int j0,
+                                            int lr, int lq) {
+    bf16x8_t zero8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
+    bf16x8_t bw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bw[c] = lq < 2 ? ld8(W1 + (size_t)(j0 + c * 16 + lr) * IN + 8 * lq) : zero8;
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+        const int i = i0 + t * 16 + lr;
+        const bf16x8_t af = (lq < 2 && i < m) ? ld8(X + (size_t)i * IN + 8 * lq) : zero8;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    }
+}
 
-// The network on a tile of 16 TR rows of X [m][16] (16-byte aligned rows).
-// Inference (TRAIN false): y = out_scale * (H4 . w5 + b5), non-finite values as +inf.
-// Training: y = H4 . w5 + b5 as is, and the activations kept as listed in MlpKeep.
-template <int TR, bool TRAIN>
-__global__ void __launch_bounds__(256, 2)
-    k_mlp_fwd(const bf16* __restrict__ X, int m, const bf16* __restrict__ W1, const bf16* __restrict__ W2,
-              const bf16* __restrict__ W3, const bf16* __restrict__ W4, const float* __restrict__ params,
-              float out_scale, float* __restrict__ y, MlpKeep keep) {
-    constexpr int IB = 16 * TR;                // rows per block
-    __shared__ __align__(16) bf16 S[IB][HP];
-    const int i0 = blockIdx.x * IB;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j0 = wave * 64;                  // this wave's output columns
-    const int lr = lane & 15, lq = lane >> 4;  // row in a 16-tile, K quarter
-    floatx4 acc[TR][4];
-    if (TRAIN) {
-        // X^T for the first layer's weight gradient
-        for (int e = threadIdx.x; e < IN * (IB / 8); e += 256) {
-            const int c = e % IN, g = e / IN;
-            unsigned w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = i0 + 8 * g + 2 * q;
-                const unsigned a = i < m ? X[(size_t)i * IN + c] : 0u;
-                const unsigned b = i + 1 < m ? X[(size_t)(i + 1) * IN + c] : 0u;
-                w[q] = a | (b << 16);
-            }
-            *reinterpret_cast<uint4*>(keep.T[0] + (size_t)c * keep.mp + i0 + 8 * g) =
-                make_uint4(w[0], w[1], w[2], w[3]);
-        }
-    }
-    // layer 1: K = 16 features; quarters 2 and 3 of the 32-wide K step are zero
-    {
-        bf16x8_t zero8;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
-        bf16x8_t bw[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) bw[c] = lq < 2 ? ld8(W1 + (size_t)(j0 + c * 16 + lr) * IN + 8 * lq) : zero8;
-#pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            const int i = i0 + t * 16 + lr;
-            const bf16x8_t af = (lq < 2 && i < m) ? ld8(X + (size_t)i * IN + 8 * lq) : zero8;
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[c], af, floatx4{0.f, 0.f, 0.f, 0.f},
-                                                                    0, 0, 0);
-        }
-        relu_store<TR>(S, acc, params + off_b_dev(1), j0, lr, lq);
-        __syncthreads();
-        if (TRAIN) {
-            tile_store_rows<IB>(S, keep.H[0], i0, m);
-            tile_store_T<IB>(S, keep.T[1], keep.mp, i0, m);
-        }
-    }
-    // layers 2..4: K = 256
-#pragma unroll 1
-    for (int l = 2; l <= NLAYER; ++l) {
-        tile_layer<TR>(l == 2 ? W2 : l == 3 ? W3 : W4, S, acc, j0, lr, lq);
-        __syncthreads();                       // every wave has read this layer's input
-        relu_store<TR>(S, acc, params + off_b_dev(l), j0, lr, lq);
-        __syncthreads();
-        if (TRAIN) {
-            tile_store_rows<IB>(S, l == 2 ? keep.H[1] : l == 3 ? keep.H[2] : keep.H[3], i0, m);
-            if (l < NLAYER) tile_store_T<IB>(S, l == 2 ? keep.T[2] : keep.T[3], keep.mp, i0, m);
-        }
-    }
-    // head: y = H4 . w5 + b5 in fp32, 256 / IB threads per row
+// y for the tile's row `row` = H4 . w5 + b5 in fp32, 256 / IB threads per row (the
+// result is valid in every thread of the row)
+template <int IB>
+__device__ __forceinline__ float tile_head(bf16 (*S)[HP], const float* __restrict__ w5, int row, int part) {
     constexpr int TPR = 256 / IB;              // threads per row
     constexpr int CPT = HID / TPR;             // columns per thread
-    const float* w5 = params + off_w5_dev();
-    const int row = threadIdx.x / TPR, part = threadIdx.x % TPR;
     float sum = 0.f;
 #pragma unroll 4
     for (int j = part * CPT; j < part * CPT + CPT; j += 8) {
@@ -325,61 +244,133 @@ __global__ void __launch_bounds__(256, 2)
     }
 #pragma unroll
     for (int o = 1; o < TPR; o <<= 1) sum += __shfl_xor(sum, o);
-    const int i = i0 + row;
-    if (part == 0 && i < m) {
-        if (TRAIN) {
-            y[i] = sum + w5[HID];
-        } else {
-            const float v = out_scale * (sum + w5[HID]);
-            y[i] = isfinite(v) ? v : __builtin_huge_valf();
-        }
-    }
+    return sum + w5[HID];
 }
 
-// Per-block partial sums the backward chain leaves for the reduction: db1..db4
+// Inference on a tile of 16 TR rows of X [m][16] (16-byte aligned rows):
+// y = out_scale * (H4 . w5 + b5), non-finite values as +inf.
+template <int TR>
+__global__ void __launch_bounds__(256, 2)
+    k_mlp_fwd(const bf16* __restrict__ X, int m, const bf16* __restrict__ W1, const bf16* __restrict__ W2,
+              const bf16* __restrict__ W3, const bf16* __restrict__ W4, const float* __restrict__ params,
+              float out_scale, float* __restrict__ y) {
+    constexpr int IB = 16 * TR;                // rows per block
+    __shared__ __align__(16) bf16 S[IB][HP];
+    const int i0 = blockIdx.x * IB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = wave * 64;                  // this wave's output columns
+    const int lr = lane & 15, lq = lane >> 4;  // row in a 16-tile, K quarter
+    floatx4 acc[TR][4];
+    tile_layer1<TR>(X, i0, m, W1, acc, j0, lr, lq);
+    relu_store<TR>(S, acc, params + off_b_dev(1), j0, lr, lq);
+    __syncthreads();
+    // layers 2..4: the output overwrites the input once every wave has read it
+#pragma unroll 1
+    for (int l = 2; l <= NLAYER; ++l) {
+        tile_layer<TR>(l == 2 ? W2 : l == 3 ? W3 : W4, S, acc, j0, lr, lq);
+        __syncthreads();
+        relu_store<TR>(S, acc, params + off_b_dev(l), j0, lr, lq);
+        __syncthreads();
+    }
+    const int row = threadIdx.x / (256 / IB), part = threadIdx.x % (256 / IB);
+    const float v = out_scale * tile_head<IB>(S, params + off_w5_dev(), row, part);
+    const int i = i0 + row;
+    if (part == 0 && i < m) y[i] = isfinite(v) ? v : __builtin_huge_valf();
+}
+
+// Per-block partial sums a training block leaves for the reduction: db1..db4
 // (column sums of dZ_l), dw5 (sum of dy_i H4_i), db5 (sum of dy_i).
 constexpr int kBwdPart = NLAYER * HID + HID + 1;
 
-struct MlpBwd {
-    const bf16* H[NLAYER];        // activations H1..H4, row-major [m][256]
-    const bf16* WT[NLAYER - 1];   // W2^T, W3^T, W4^T (bf16 [256][256])
-    const float* dy;              // [m]
-    const float* w5;              // w5 [256] (fp32)
-    bf16* dZT[NLAYER];            // dZ1..dZ4 transposed [256][mp]
-    float* part;                  // [blocks][kBwdPart]
+struct MlpTrain {
+    const bf16* X;              // [m][16]
+    const float* target;        // [m]
+    const bf16* W[NLAYER];      // W1..W4 (bf16)
+    const bf16* WT[NLAYER - 1]; // W2^T, W3^T, W4^T (bf16 [256][256])
+    const float* params;        // fp32: biases, w5, b5
+    bf16* T[NLAYER];            // the layers' inputs transposed: X^T [16][mp], H1^T..H3^T [256][mp]
+    bf16* dZT[NLAYER];          // dZ1^T..dZ4^T [256][mp]
+    float* part;                // [blocks][kBwdPart]
+    float* loss_part;           // [blocks]: sum of (y - t)^2 over the block's rows
     int m, mp;
 };
 
-// The backward chain on a tile of 16 TR rows: dZ4 from dy, then dZ3, dZ2, dZ1, each
-// kept transposed for the weight gradients, with the bias and head partial sums.
+// One training pass on a tile of 16 TR rows: the forward (H1..H3 kept in LDS, the
+// layers' inputs written transposed for the weight gradients), y and the misfit,
+// dy = 2 (y - t) / m, then the backward chain dZ4 -> dZ1 with the ReLU masks read
+// from LDS, each dZ written transposed, and the block's bias and head partial sums
+// (fixed order).
 template <int TR>
-__global__ void __launch_bounds__(256, 2) k_mlp_bwd(MlpBwd a) {
+__global__ void __launch_bounds__(256) k_mlp_train(MlpTrain a) {
     constexpr int IB = 16 * TR;
-    __shared__ __align__(16) bf16 S[IB][HP];
+    __shared__ __align__(16) bf16 S[IB][HP];                // H4, then dZ4 .. dZ1
+    __shared__ __align__(16) bf16 Hs[NLAYER - 1][IB][HP];   // H1..H3
+    __shared__ float dys[IB], sq[IB];
     __shared__ float red[8][HID + 1];
-    const int i0 = blockIdx.x * IB;
+    const int i0 = blockIdx.x * IB, m = a.m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j0 = wave * 64;
     const int lr = lane & 15, lq = lane >> 4;
     float* part = a.part + (size_t)blockIdx.x * kBwdPart;
+    // X^T for the first layer's weight gradient
+    for (int e = threadIdx.x; e < IN * (IB / 8); e += 256) {
+        const int c = e % IN, g = e / IN;
+        unsigned w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + 8 * g + 2 * q;
+            const unsigned lo = i < m ? a.X[(size_t)i * IN + c] : 0u;
+            const unsigned hi = i + 1 < m ? a.X[(size_t)(i + 1) * IN + c] : 0u;
+            w[q] = lo | (hi << 16);
+        }
+        *reinterpret_cast<uint4*>(a.T[0] + (size_t)c * a.mp + i0 + 8 * g) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    // forward: H1..H3 into their own buffers (no overwrite, no barrier before the
+    // epilogue), H4 into S
+    floatx4 acc[TR][4];
+    tile_layer1<TR>(a.X, i0, m, a.W[0], acc, j0, lr, lq);
+    relu_store<TR>(Hs[0], acc, a.params + off_b_dev(1), j0, lr, lq);
+    __syncthreads();
+    tile_store_T<IB>(Hs[0], a.T[1], a.mp, i0, m);
+#pragma unroll 1
+    for (int l = 2; l <= NLAYER; ++l) {
+        tile_layer<TR>(a.W[l - 1], Hs[l - 2], acc, j0, lr, lq);
+        relu_store<TR>(l < NLAYER ? Hs[l - 1] : S, acc, a.params + off_b_dev(l), j0, lr, lq);
+        __syncthreads();
+        if (l < NLAYER) tile_store_T<IB>(Hs[l - 1], a.T[l], a.mp, i0, m);
+    }
+    // head, misfit, dy
     {
-        // dZ4 = bf16(dy_i w5_j [H4 > 0]); thread: 8 columns, rows ph, ph + 8, ... in order
+        const int row = threadIdx.x / (256 / IB), pt = threadIdx.x % (256 / IB);
+        const float yv = tile_head<IB>(S, a.params + off_w5_dev(), row, pt);
+        const int i = i0 + row;
+        if (pt == 0) {
+            const float d = i < m ? yv - a.target[i] : 0.f;
+            dys[row] = 2.f * d / (float)m;
+            sq[row] = d * d;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int r = 0; r < IB; ++r) t += sq[r];
+        a.loss_part[blockIdx.x] = t;
+    }
+    {
+        // dZ4 = bf16(dy_i w5_j [H4 > 0]) in place; dw5 and db5 partials (thread: 8
+        // columns, rows ph, ph + 8, ... in order; then the 8 row phases in order)
         const int cc = threadIdx.x & 31, ph = threadIdx.x >> 5;
+        const float* w5 = a.params + off_w5_dev();
         float w5v[8], sw[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            w5v[q] = a.w5[8 * cc + q];
+            w5v[q] = w5[8 * cc + q];
             sw[q] = 0.f;
         }
         float sd = 0.f;
         for (int r = ph; r < IB; r += 8) {
-            const int i = i0 + r;
-            uint4 h = make_uint4(0u, 0u, 0u, 0u);
-            float d = 0.f;
-            if (i < a.m) {
-                h = *reinterpret_cast<const uint4*>(a.H[3] + (size_t)i * HID + 8 * cc);
-                d = a.dy[i];
-            }
+            const float d = dys[r];
+            const uint4 h = *reinterpret_cast<const uint4*>(&S[r][8 * cc]);
             const unsigned hw[4] = {h.x, h.y, h.z, h.w};
             unsigned o[4];
 #pragma unroll
@@ -401,10 +392,10 @@ __global__ void __launch_bounds__(256, 2) k_mlp_bwd(MlpBwd a) {
     __syncthreads();
     {
         const int c = threadIdx.x;
-        float s = 0.f;
+        float sum = 0.f;
 #pragma unroll
-        for (int ph = 0; ph < 8; ++ph) s += red[ph][c];
-        part[NLAYER * HID + c] = s;
+        for (int ph = 0; ph < 8; ++ph) sum += red[ph][c];
+        part[NLAYER * HID + c] = sum;
         if (c == 0) {
             float t = 0.f;
 #pragma unroll
@@ -412,16 +403,15 @@ __global__ void __launch_bounds__(256, 2) k_mlp_bwd(MlpBwd a) {
             part[NLAYER * HID + HID] = t;
         }
     }
-    part[(NLAYER - 1) * HID + threadIdx.x] = tile_store_T<IB>(S, a.dZT[NLAYER - 1], a.mp, i0, a.m);
-    floatx4 acc[TR][4];
+    part[(NLAYER - 1) * HID + threadIdx.x] = tile_store_T<IB>(S, a.dZT[NLAYER - 1], a.mp, i0, m);
+    // backward chain: dZ_{l-1} = bf16((W_l^T dZ_l) [H_{l-1} > 0])
 #pragma unroll 1
     for (int l = NLAYER; l >= 2; --l) {
-        tile_layer<TR>(l == 4 ? a.WT[2] : l == 3 ? a.WT[1] : a.WT[0], S, acc, j0, lr, lq);
+        tile_layer<TR>(a.WT[l - 2], S, acc, j0, lr, lq);
+        __syncthreads();                       // every wave has read dZ_l
+        mask_store<TR>(S, acc, Hs[l - 2], i0, m, j0, lr, lq);
         __syncthreads();
-        mask_store<TR>(S, acc, l == 4 ? a.H[2] : l == 3 ? a.H[1] : a.H[0], i0, a.m, j0, lr, lq);
-        __syncthreads();
-        part[(l - 2) * HID + threadIdx.x] =
-            tile_store_T<IB>(S, l == 4 ? a.dZT[2] : l == 3 ? a.dZT[1] : a.dZT[0], a.mp, i0, a.m);
+        part[(l - 2) * HID + threadIdx.x] = tile_store_T<IB>(S, a.dZT[l - 2], a.mp, i0, m);
     }
 }
 
@@ -566,6 +556,9 @@ __global__ void k_mlp_reduce_b(const float* __restrict__ pb, int blocks, float* 
 // measured forward and training times cross (128 rows from 65536 rows, 64 from
 // 16384, else 32).
 __host__ int tile_rows(int m) { return m >= 65536 ? 128 : m >= 16384 ? 64 : 32; }
+// Rows per block of the training pass (H1..H3 stay in LDS: 32 rows take 76 KB, two
+// blocks per CU; 64 rows 144 KB, one)
+__host__ int train_rows(int m) { return m >= 65536 ? 64 : 32; }
 // inference keeps nothing per row on the device: any batch up to 2^27 rows
 constexpr int kInferRowsMax = 1 << 27;
 
@@ -673,12 +666,9 @@ struct gbp_mlp_s {
     float* v = nullptr;
     bf16* wbf[NLAYER] = {};    // bf16 copies of W1..W4
     bf16* wT = nullptr;        // bf16 W2^T, W3^T, W4^T [3][256][256]
-    bf16* H = nullptr;         // activations H1..H4 [4][max_rows][256]
     bf16* T = nullptr;         // X^T [16][mp], H1^T..H3^T [3][256][mp]
     bf16* dZT = nullptr;       // dZ1^T..dZ4^T [4][256][mp]
-    float* y = nullptr;
-    float* dy = nullptr;
-    float* part = nullptr;     // loss partials
+    float* part = nullptr;     // loss partials, one per training block
     float* part_w = nullptr;   // weight-gradient partials [kMaxSplits][n_params]
     float* part_b = nullptr;   // backward-chain partials [blocks][kBwdPart]
     float* loss = nullptr;     // [1]
@@ -699,8 +689,8 @@ int wgrad_chunk(int kend) { return std::max(256, ((kend + kMaxSplits - 1) / kMax
 
 void free_mlp(gbp_mlp p) {
     if (!p) return;
-    void* ptrs[] = {p->params, p->grads, p->m, p->v, p->wT, p->H, p->T, p->dZT, p->y, p->dy,
-                    p->part, p->part_w, p->part_b, p->loss};
+    void* ptrs[] = {p->params, p->grads, p->m, p->v, p->wT, p->T, p->dZT, p->part, p->part_w, p->part_b,
+                    p->loss};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (int l = 0; l < NLAYER; ++l)
@@ -721,61 +711,41 @@ int refresh_bf16(gbp_mlp p, hipStream_t s) {
     return GBP_OK;
 }
 
-MlpKeep keep_of(gbp_mlp p) {
-    MlpKeep k{};
-    for (int l = 0; l < NLAYER; ++l) k.H[l] = p->H + (size_t)l * p->max_rows * HID;
-    k.T[0] = p->T;
-    for (int l = 1; l < NLAYER; ++l) k.T[l] = p->T + (size_t)(IN + (l - 1) * HID) * p->mp;
-    k.mp = p->mp;
-    return k;
+// the network on m rows of X, y = out_scale * prediction
+void launch_infer(gbp_mlp p, const bf16* X, int m, float out_scale, float* y, hipStream_t s) {
+    const int ib = tile_rows(m), blocks = (m + ib - 1) / ib;
+    if (ib == 128)
+        k_mlp_fwd<8><<<blocks, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3], p->params, out_scale, y);
+    else if (ib == 64)
+        k_mlp_fwd<4><<<blocks, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3], p->params, out_scale, y);
+    else
+        k_mlp_fwd<2><<<blocks, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3], p->params, out_scale, y);
 }
 
-// the network on m rows of X: inference (y = out_scale * prediction) or the training
-// forward (raw y in p->y, activations kept)
-void launch_fwd(gbp_mlp p, const bf16* X, int m, float out_scale, float* y, bool train, hipStream_t s) {
-    const MlpKeep k = train ? keep_of(p) : MlpKeep{};
-    const int ib = tile_rows(m), blocks = (m + ib - 1) / ib;
-#define GBP_FWD(TR, TRAIN)                                                                              \
-    k_mlp_fwd<TR, TRAIN><<<blocks, 256, 0, s>>>(X, m, p->wbf[0], p->wbf[1], p->wbf[2], p->wbf[3], p->params, \
-                                                TRAIN ? 1.f : out_scale, y, k)
-    if (ib == 128) {
-        if (train) GBP_FWD(8, true);
-        else GBP_FWD(8, false);
-    } else if (ib == 64) {
-        if (train) GBP_FWD(4, true);
-        else GBP_FWD(4, false);
-    } else {
-        if (train) GBP_FWD(2, true);
-        else GBP_FWD(2, false);
-    }
-#undef GBP_FWD
-}
-
-// loss, backward chain, weight gradients, reduction into p->grads
-void launch_bwd(gbp_mlp p, int m, const float* target, hipStream_t s) {
-    const int nb = gbp_blocks(m, 256);
-    k_mse<<<nb, 256, 0, s>>>(p->y, target, m, p->dy, p->part);
-    k_sum_parts<<<1, 256, 0, s>>>(p->part, nb, 1.f / (float)m, p->loss);
-    const MlpKeep k = keep_of(p);
-    MlpBwd b{};
-    for (int l = 0; l < NLAYER; ++l) {
-        b.H[l] = k.H[l];
-        b.dZT[l] = p->dZT + (size_t)l * HID * p->mp;
-    }
-    for (int l = 0; l < NLAYER - 1; ++l) b.WT[l] = p->wT + (size_t)l * HID * HID;
-    b.dy = p->dy;
-    b.w5 = p->params + off_w5();
-    b.part = p->part_b;
-    b.m = m;
-    b.mp = p->mp;
-    const int ib = tile_rows(m), blocks = (m + ib - 1) / ib;
-    if (ib == 128) k_mlp_bwd<8><<<blocks, 256, 0, s>>>(b);
-    else if (ib == 64) k_mlp_bwd<4><<<blocks, 256, 0, s>>>(b);
-    else k_mlp_bwd<2><<<blocks, 256, 0, s>>>(b);
+// training pass (forward, misfit, backward chain), weight gradients, reductions into
+// p->grads and p->loss
+void launch_train(gbp_mlp p, const bf16* X, int m, const float* target, hipStream_t s) {
+    MlpTrain a{};
+    a.X = X;
+    a.target = target;
+    for (int l = 0; l < NLAYER; ++l) a.W[l] = p->wbf[l];
+    for (int l = 0; l < NLAYER - 1; ++l) a.WT[l] = p->wT + (size_t)l * HID * HID;
+    a.params = p->params;
+    a.T[0] = p->T;
+    for (int l = 1; l < NLAYER; ++l) a.T[l] = p->T + (size_t)(IN + (l - 1) * HID) * p->mp;
+    for (int l = 0; l < NLAYER; ++l) a.dZT[l] = p->dZT + (size_t)l * HID * p->mp;
+    a.part = p->part_b;
+    a.loss_part = p->part;
+    a.m = m;
+    a.mp = p->mp;
+    const int ib = train_rows(m), blocks = (m + ib - 1) / ib;
+    if (ib == 64) k_mlp_train<4><<<blocks, 256, 0, s>>>(a);
+    else k_mlp_train<2><<<blocks, 256, 0, s>>>(a);
+    k_sum_parts<<<1, 256, 0, s>>>(p->part, blocks, 1.f / (float)m, p->loss);
     MlpWgrad w{};
     for (int l = 0; l < NLAYER; ++l) {
-        w.dZT[l] = b.dZT[l];
-        w.T[l] = k.T[l];
+        w.dZT[l] = a.dZT[l];
+        w.T[l] = a.T[l];
     }
     w.part = p->part_w;
     w.mp = p->mp;
@@ -814,12 +784,9 @@ extern "C" int gbp_mlp_create(int max_rows, uint64_t seed, gbp_mlp* out) {
               hipMalloc((void**)&p->m, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->v, sizeof(float) * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->wT, sizeof(bf16) * (NLAYER - 1) * HID * HID) == hipSuccess &&
-              hipMalloc((void**)&p->H, sizeof(bf16) * NLAYER * mr * HID) == hipSuccess &&
               hipMalloc((void**)&p->T, sizeof(bf16) * (IN + (NLAYER - 1) * HID) * mp) == hipSuccess &&
               hipMalloc((void**)&p->dZT, sizeof(bf16) * NLAYER * HID * mp) == hipSuccess &&
-              hipMalloc((void**)&p->y, sizeof(float) * mr) == hipSuccess &&
-              hipMalloc((void**)&p->dy, sizeof(float) * mr) == hipSuccess &&
-              hipMalloc((void**)&p->part, sizeof(float) * gbp_blocks(max_rows, 256)) == hipSuccess &&
+              hipMalloc((void**)&p->part, sizeof(float) * ((mr + 31) / 32)) == hipSuccess &&
               hipMalloc((void**)&p->part_w, sizeof(float) * kMaxSplits * p->n_params) == hipSuccess &&
               hipMalloc((void**)&p->part_b, sizeof(float) * ((mr + 31) / 32) * kBwdPart) == hipSuccess &&
               hipMalloc((void**)&p->loss, sizeof(float)) == hipSuccess;
@@ -941,7 +908,7 @@ extern "C" int gbp_mlp_forward(gbp_mlp p, const uint16_t* X, int m, float out_sc
         gbp_set_error("mlp_forward: X must be 16-byte aligned");
         return GBP_ERR_ARG;
     }
-    launch_fwd(p, (const bf16*)X, m, out_scale, y, false, s);
+    launch_infer(p, (const bf16*)X, m, out_scale, y, s);
     GBP_LAUNCH_CHECK();
     return GBP_OK;
 }
@@ -959,8 +926,7 @@ extern "C" int gbp_mlp_gradient(gbp_mlp p, const uint16_t* X, int m, const float
         return GBP_ERR_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
-    launch_fwd(p, (const bf16*)X, m, 1.f, p->y, true, s);
-    launch_bwd(p, m, target, s);
+    launch_train(p, (const bf16*)X, m, target, s);
     GBP_LAUNCH_CHECK();
     if (loss) GBP_HIP(hipMemcpyAsync(loss, p->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return GBP_OK;
