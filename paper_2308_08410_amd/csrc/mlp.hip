@@ -2,7 +2,7 @@
 // activation times from per-vertex features, trained and evaluated with BF16
 // matrix-core kernels (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
 //
-// Precision policy (mirrored by the reference):
+// Precision policy:
 //   features X and the hidden-layer weights W1..W4 are rounded to bf16;
 //   Z_l = H_{l-1} W_l^T + b_l accumulates in fp32, H_l = bf16(relu(Z_l));
 //   y = H_4 . w5 + b5 in fp32 (w5, b5 fp32);
@@ -58,15 +58,16 @@ __global__ void k_sum_parts(const float* __restrict__ part, int n, float scale, 
 
 // ---------------------------------------------------------------- fused row-tile kernels
 // A block of 4 waves owns a tile of 16 TR rows and runs the network's 256-wide layers
-// on it with the tile in LDS (16 TR x 256 bf16, overwritten layer by layer).  Wave w
+// on it with the tile in LDS (16 TR x 256 bf16 per layer).  Wave w
 // computes the output columns [64 w, 64 w + 64) of a layer for all the tile's rows as
 // the transposed product A S^T: TR x 4 tiles of v_mfma_f32_16x16x32_bf16 per K step of
 // 32, the A operand (a row of a 256 x 256 weight matrix, 8 consecutive K values per
 // lane) loaded straight from global memory (the matrix stays in L2; each fragment
 // serves 16 TR rows), the B operand (a tile row's 8 K values) read from LDS, the next
 // step's weight fragments in flight while the current step multiplies.  A lane's 4
-// results are 4 consecutive columns of one row, stored with one 8-byte write.  A
-// layer's output overwrites its input only after every wave has finished reading it.
+// results are 4 consecutive columns of one row, stored with one 8-byte write.  Where a
+// layer's output overwrites its input, it does so only after every wave has finished
+// reading it.
 //   forward:  H_l = bf16(relu(W_l H_{l-1} + b_l)), then y = H_4 . w5 + b5 in fp32;
 //   backward: dZ_{l-1} = bf16((W_l^T dZ_l) [H_{l-1} > 0]) with A = W_l^T (a bf16
 //             copy kept transposed).
