@@ -2,8 +2,8 @@
 // (Sec. 3.1): the same three steps as on tetrahedra with a segment as the local
 // simplex.
 //
-// * forward: Alg. 2 as an active queue of vertices, one thread per queued vertex
-//   evaluating the local problems of its triangles (Sec. 2.2 Eq. (upwind_eq_lsqr)
+// * forward: Alg. 2 as an active queue of vertices, a group of lanes per queued
+//   vertex evaluating the local problems of its triangles (Sec. 2.2 Eq. (upwind_eq_lsqr)
 //   with d = 2: two vertex candidates and one interior candidate, predicated);
 // * backward: geodesic parents in FP64 (the argmin is a decision taken by
 //   floating point: same precision as the reference), the adjoint
@@ -207,33 +207,31 @@ __global__ void k_tri_roots(const int* __restrict__ root_node, const float* __re
     }
 }
 
-__global__ void __launch_bounds__(TPB)
-    k_tri_sweep(const float2* __restrict__ xy, const int4* __restrict__ tri,
-                const float4* __restrict__ minv, const int* __restrict__ vptr,
-                const int* __restrict__ vent, const int* __restrict__ nbp,
-                const int* __restrict__ nb, float* T, const int* __restrict__ qin,
-                int* __restrict__ qout, int* __restrict__ mark, TriCtl* ctl, int s, int stamp_next,
-                float eps_rel) {
-    const int n = ctl->count[s % 3];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[(s + 2) % 3] = 0;
-        if (n > 0) atomicMax(&ctl->rounds, s + 1);
-    }
-    if ((int)(blockIdx.x * blockDim.x) >= n) return;    // uniform over the block
-    // pushes collect in LDS; one atomic per block reserves their room in the queue
-    constexpr int kCap = 4096;
-    __shared__ int pbuf[kCap];
-    __shared__ int pn, pbase;
-    int* cnt_next = &ctl->count[(s + 1) % 3];
-    if (threadIdx.x == 0) pn = 0;
-    __syncthreads();
-    unsigned long long solves = 0, upd = 0;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+// Lanes per queued vertex in a relaxation round: the lanes of a group take the
+// vertex's triangles (and then its neighbours) in turn, so a round's chain of
+// dependent loads is one triangle's, not the sum over the vertex's triangles.
+// Narrow fronts (at most kNarrowFront queued vertices) take 8 lanes per vertex,
+// wider ones 4: the round is latency-bound when the front is narrow and bound by
+// the waves it issues when it is wide.
+constexpr int kNarrowFront = 1024;
+
+template <int L>
+__device__ __forceinline__ void tri_relax(const float2* __restrict__ xy, const int4* __restrict__ tri,
+                                          const float4* __restrict__ minv, const int* __restrict__ vptr,
+                                          const int* __restrict__ vent, const int* __restrict__ nbp,
+                                          const int* __restrict__ nb, float* T, const int* __restrict__ qin,
+                                          int n, int* __restrict__ qout, int* __restrict__ mark,
+                                          int* cnt_next, int stamp_next, float eps_rel, int* pbuf,
+                                          int* pn, int cap, unsigned long long& solves,
+                                          unsigned long long& upd) {
+    const int lane = threadIdx.x & (L - 1);
+    // k is the same in every lane of a group, so a group runs its passes together
+    for (int k = (blockIdx.x * TPB + threadIdx.x) / L; k < n; k += gridDim.x * (TPB / L)) {
         const int i = qin[k];
         const float told = T[i];
         float best = told;
         const float2 xi = xy[i];
-        for (int e = vptr[i]; e < vptr[i + 1]; ++e) {
+        for (int e = vptr[i] + lane; e < vptr[i + 1]; e += L) {
             const int code = vent[e];
             const int t = code >> 2;
             int ii, a, b;
@@ -247,21 +245,55 @@ __global__ void __launch_bounds__(TPB)
             best = fminf(best, tri_local<float>(qaa, qbb, qab, T[a], T[b]));
             ++solves;
         }
+#pragma unroll
+        for (int o = 1; o < L; o <<= 1) best = fminf(best, __shfl_xor(best, o));
         const bool changed = (told < GBP_INF) ? (best < told - eps_rel * fmaxf(1.f, fabsf(told)))
                                               : (best < GBP_INF);
-        if (best < told) T[i] = best;
+        if (lane == 0 && best < told) T[i] = best;
         if (changed) {
-            ++upd;
-            for (int a = nbp[i]; a < nbp[i + 1]; ++a) {
+            if (lane == 0) ++upd;
+            for (int a = nbp[i] + lane; a < nbp[i + 1]; a += L) {
                 const int w = nb[a];
                 if (atomicMax(&mark[w], stamp_next) < stamp_next) {
-                    const int pos = atomicAdd(&pn, 1);
-                    if (pos < kCap) pbuf[pos] = w;
+                    const int pos = atomicAdd(pn, 1);
+                    if (pos < cap) pbuf[pos] = w;
                     else qout[atomicAdd(cnt_next, 1)] = w;     // buffer full: straight to the queue
                 }
             }
         }
     }
+}
+
+// one relaxation round over the queue qin; the grid covers kNarrowFront vertices
+// at 8 lanes each or the mesh, whichever is less
+__global__ void __launch_bounds__(TPB)
+    k_tri_sweep(const float2* __restrict__ xy, const int4* __restrict__ tri,
+                const float4* __restrict__ minv, const int* __restrict__ vptr,
+                const int* __restrict__ vent, const int* __restrict__ nbp,
+                const int* __restrict__ nb, float* T, const int* __restrict__ qin,
+                int* __restrict__ qout, int* __restrict__ mark, TriCtl* ctl, int s, int stamp_next,
+                float eps_rel) {
+    const int n = ctl->count[s % 3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(s + 2) % 3] = 0;
+        if (n > 0) atomicMax(&ctl->rounds, s + 1);
+    }
+    const bool narrow = n <= kNarrowFront;
+    if ((int)(blockIdx.x * (narrow ? TPB / 8 : TPB / 4)) >= n) return;   // uniform over the block
+    // pushes collect in LDS; one atomic per block reserves their room in the queue
+    constexpr int kCap = 4096;
+    __shared__ int pbuf[kCap];
+    __shared__ int pn, pbase;
+    int* cnt_next = &ctl->count[(s + 1) % 3];
+    if (threadIdx.x == 0) pn = 0;
+    __syncthreads();
+    unsigned long long solves = 0, upd = 0;
+    if (narrow)
+        tri_relax<8>(xy, tri, minv, vptr, vent, nbp, nb, T, qin, n, qout, mark, cnt_next, stamp_next, eps_rel,
+                     pbuf, &pn, kCap, solves, upd);
+    else
+        tri_relax<4>(xy, tri, minv, vptr, vent, nbp, nb, T, qin, n, qout, mark, cnt_next, stamp_next, eps_rel,
+                     pbuf, &pn, kCap, solves, upd);
     __syncthreads();
     const int m = min(pn, kCap);
     if (threadIdx.x == 0) pbase = m > 0 ? atomicAdd(cnt_next, m) : 0;
@@ -504,13 +536,9 @@ constexpr int kWalkThreads = 1024;
 
 // A finished vertex releases its weighted parents (but `skip`); a parent whose
 // last awaited child this was joins the next frontier.
-__device__ __forceinline__ void tri_release(int x, int skip, const int* __restrict__ par,
-                                            const int2* __restrict__ pnode,
-                                            const float4* __restrict__ pa, int* __restrict__ rem,
+__device__ __forceinline__ void tri_release(int px, int2 pn, float4 w, int skip, int* __restrict__ rem,
                                             int* __restrict__ next, int* n_next) {
-    if (par[x] < 0) return;
-    const int2 pn = pnode[x];
-    const float4 w = pa[x];
+    if (px < 0) return;
     if (w.x > 0.f && pn.x != skip && atomicSub(&rem[pn.x], 1) == 1) next[atomicAdd(n_next, 1)] = pn.x;
     if (w.y > 0.f && pn.y != skip && atomicSub(&rem[pn.y], 1) == 1) next[atomicAdd(n_next, 1)] = pn.y;
 }
@@ -552,14 +580,35 @@ __global__ void __launch_bounds__(kWalkThreads)
         __syncthreads();
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
             const int x = cur[k];
+            // what depends on x alone, in one round trip
             const int q = partner[x];
+            const int e0 = cptr[x], e1 = cptr[x + 1];
+            const float gx = g[x];
+            const int px = par[x];
+            const int2 pn = pnode[x];
+            const float4 pw = pa[x];
             if (q < 0) {
-                float l = g[x];
-                for (int e = cptr[x]; e < cptr[x + 1]; ++e) l += calpha[e] * lam[cchild[e]];
+                // children four at a time: their ids and weights, then their lambdas,
+                // summed in child order
+                float l = gx;
+                for (int e = e0; e < e1; e += 4) {
+                    int c[4];
+                    float a[4], lc[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        c[j] = e + j < e1 ? cchild[e + j] : -1;
+                        a[j] = e + j < e1 ? calpha[e + j] : 0.f;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) lc[j] = c[j] >= 0 ? lam[c[j]] : 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (e + j < e1) l += a[j] * lc[j];
+                }
                 lam[x] = l;
                 done[x] = 1;
                 atomicAdd(&n_fin, 1);
-                tri_release(x, -1, par, pnode, pa, rem, nxt, &n_next);
+                tri_release(px, pn, pw, -1, rem, nxt, &n_next);
                 continue;
             }
             if (atomicSub(&pairrem[min(x, q)], 1) != 1) continue;   // partner not ready yet
@@ -582,8 +631,8 @@ __global__ void __launch_bounds__(kWalkThreads)
             done[x] = 1;
             done[q] = 1;
             atomicAdd(&n_fin, 2);
-            tri_release(x, q, par, pnode, pa, rem, nxt, &n_next);
-            tri_release(q, x, par, pnode, pa, rem, nxt, &n_next);
+            tri_release(px, pn, pw, q, rem, nxt, &n_next);
+            tri_release(par[q], pnode[q], pa[q], x, rem, nxt, &n_next);
         }
         __syncthreads();                    // the level's lambdas, releases and n_next
         if (threadIdx.x == 0) n_cur = n_next;
@@ -855,7 +904,9 @@ extern "C" int gbp_tri_forward(gbp_tri_plan p, const float* D, const float* vsca
     hipStream_t s = (hipStream_t)stream;
     const int n_v = p->n_v;
     if ((rc = tri_prepare(p, D, vscale, root_node, root_t, n_roots, true, s))) return rc;
-    const int grid = std::max(1, std::min(gbp_blocks(n_v, TPB), 1024));
+    // enough blocks for the widest narrow front at 8 lanes or for a wide front at 4
+    const size_t lanes_max = std::max<size_t>((size_t)std::min(n_v, kNarrowFront) * 8, (size_t)n_v * 4);
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>((lanes_max + TPB - 1) / TPB, 1024));
     // batches of 8 rounds; the host checks batch k's queue length (copied into
     // pinned memory behind it, with an event) only once batch k + 1 is queued, so
     // the device never waits for the check; a finished solve costs one batch of
