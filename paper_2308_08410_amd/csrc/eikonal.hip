@@ -1216,12 +1216,25 @@ __device__ __forceinline__ void publish(int x, float l, const float4* __restrict
 // A finished vertex releases its parents; a parent whose last child this was
 // becomes ready for the next launch (stamped with a plain store: it is only
 // read after this launch ends).
-__device__ __forceinline__ bool release_from(int4 pn, int skip, int* __restrict__ rem,
+__device__ __forceinline__ bool release_from(int4 pn, int skip, int self, int* __restrict__ rem,
                                              int* __restrict__ rdy, int next) {
     const int f[3] = {pn.x, pn.y, pn.z};
+    // the three releases in flight together, with no branch between them: a slot
+    // without a parent subtracts 0 from the finished vertex's own count (no longer
+    // read by anyone), and its result is ignored
+    bool v[3];
+    int r[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = f[k] >= 0 && f[k] != skip;
+        r[k] = atomicSub(&rem[v[k] ? f[k] : self], v[k] ? 1 : 0);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = v[k] ? r[k] : 0;
     bool any = false;
+#pragma unroll
     for (int k = 0; k < 3; ++k)
-        if (f[k] >= 0 && f[k] != skip && atomicSub(&rem[f[k]], 1) == 1) {
+        if (r[k] == 1) {
             rdy[f[k]] = next;
             any = true;
         }
@@ -1231,7 +1244,7 @@ __device__ __forceinline__ bool release_from(int4 pn, int skip, int* __restrict_
 __device__ __forceinline__ bool release_parents(int x, int skip, const int4* __restrict__ pnode,
                                                 int* __restrict__ rem, int* __restrict__ rdy,
                                                 int next) {
-    return release_from(pnode[x], skip, rem, rdy, next);
+    return release_from(pnode[x], skip, x, rem, rdy, next);
 }
 
 // One leaves-first level, as a scan over all vertices (one thread per vertex):
@@ -1300,7 +1313,7 @@ __global__ void __launch_bounds__(TPB)
             done[x] = 1;
             rdy[x] = kRdyDone;
             publish_to(l, csx, wx, contrib);
-            any |= release_from(pnx, -1, rem, rdy, s + 1);
+            any |= release_from(pnx, -1, x, rem, rdy, s + 1);
             continue;
         }
         if (atomicSub(&pairrem[min(x, q)], 1) != 1) {   // partner not ready yet
@@ -1331,7 +1344,7 @@ __global__ void __launch_bounds__(TPB)
         rdy[q] = kRdyDone;
         publish_to(lx, csx, wx, contrib);
         publish(q, lq, pa, cslot, contrib);
-        any |= release_from(pnx, q, rem, rdy, s + 1);
+        any |= release_from(pnx, q, x, rem, rdy, s + 1);
         any |= release_parents(q, x, pnode, rem, rdy, s + 1);
     }
     if (any) any_sh = 1;

@@ -536,11 +536,17 @@ constexpr int kWalkThreads = 1024;
 
 // A finished vertex releases its weighted parents (but `skip`); a parent whose
 // last awaited child this was joins the next frontier.
-__device__ __forceinline__ void tri_release(int px, int2 pn, float4 w, int skip, int* __restrict__ rem,
-                                            int* __restrict__ next, int* n_next) {
+__device__ __forceinline__ void tri_release(int px, int2 pn, float4 w, int skip, int self,
+                                            int* __restrict__ rem, int* __restrict__ next, int* n_next) {
     if (px < 0) return;
-    if (w.x > 0.f && pn.x != skip && atomicSub(&rem[pn.x], 1) == 1) next[atomicAdd(n_next, 1)] = pn.x;
-    if (w.y > 0.f && pn.y != skip && atomicSub(&rem[pn.y], 1) == 1) next[atomicAdd(n_next, 1)] = pn.y;
+    // both releases in flight together, with no branch between them: a parent that
+    // is not released takes 0 off the finished vertex's own count instead (no
+    // longer read by anyone), and its result is ignored
+    const bool va = w.x > 0.f && pn.x != skip, vb = w.y > 0.f && pn.y != skip;
+    const int ra = atomicSub(&rem[va ? pn.x : self], va ? 1 : 0);
+    const int rb = atomicSub(&rem[vb ? pn.y : self], vb ? 1 : 0);
+    if (va && ra == 1) next[atomicAdd(n_next, 1)] = pn.x;
+    if (vb && rb == 1) next[atomicAdd(n_next, 1)] = pn.y;
 }
 
 // The whole leaves-first walk in one work-group: the 2-D study's parent graphs are
@@ -608,7 +614,7 @@ __global__ void __launch_bounds__(kWalkThreads)
                 lam[x] = l;
                 done[x] = 1;
                 atomicAdd(&n_fin, 1);
-                tri_release(px, pn, pw, -1, rem, nxt, &n_next);
+                tri_release(px, pn, pw, -1, x, rem, nxt, &n_next);
                 continue;
             }
             if (atomicSub(&pairrem[min(x, q)], 1) != 1) continue;   // partner not ready yet
@@ -631,8 +637,8 @@ __global__ void __launch_bounds__(kWalkThreads)
             done[x] = 1;
             done[q] = 1;
             atomicAdd(&n_fin, 2);
-            tri_release(px, pn, pw, q, rem, nxt, &n_next);
-            tri_release(par[q], pnode[q], pa[q], x, rem, nxt, &n_next);
+            tri_release(px, pn, pw, q, x, rem, nxt, &n_next);
+            tri_release(par[q], pnode[q], pa[q], x, q, rem, nxt, &n_next);
         }
         __syncthreads();                    // the level's lambdas, releases and n_next
         if (threadIdx.x == 0) n_cur = n_next;
