@@ -1200,6 +1200,13 @@ __global__ void k_adj_init(const float* __restrict__ dLdT_user, const int* __res
     if (leaf) ctl->count[0] = 1;   // flag: the first launch has work
 }
 
+// Fixed entry slot r (0..7) of a vertex from its two loaded float4s.
+__device__ __forceinline__ float slot_of(float4 s0, float4 s1, int r) {
+    const float4 h = r < 4 ? s0 : s1;
+    const int k = r & 3;
+    return k == 0 ? h.x : k == 1 ? h.y : k == 2 ? h.z : h.w;
+}
+
 // A finished vertex hands alpha * lambda to its entries in its parents' child
 // lists (read only in later launches, after this one has ended).
 __device__ __forceinline__ void publish_to(float l, int4 cs, float4 w, float* __restrict__ contrib) {
@@ -1320,16 +1327,25 @@ __global__ void __launch_bounds__(TPB)
             rdy[x] = kRdyWait;
             continue;
         }
+        // x's own g, entry range and fixed slots come from the registers loaded above
+        // (no child of x other than q finishes in this launch, and q's entry is
+        // skipped); using them on this path too keeps the compiler from moving those
+        // loads behind the partner test, which would add a round trip to every level
         float S[2], w[2];
         const int pr[2] = {x, q};
         for (int m = 0; m < 2; ++m) {
             const int a = pr[m], o = pr[1 - m];
-            float l = g[a], wo = 0.f;
-            const int b = cptr[a];
-            for (int k = b; k < cptr[a + 1]; ++k) {
+            float l = m == 0 ? gx : g[a], wo = 0.f;
+            const int b = m == 0 ? cb : cptr[a];
+            const int e = m == 0 ? ce : cptr[a + 1];
+            for (int k = b; k < e; ++k) {
                 const int ch = cchild[k];
-                if (ch == o) wo = calpha[k];
-                else l += contrib[centry(a, k - b, k, n_v)];
+                if (ch == o) {
+                    wo = calpha[k];
+                } else {
+                    const int r = k - b;
+                    l += (m == 0 && r < kChildSlots) ? slot_of(s0, s1, r) : contrib[centry(a, r, k, n_v)];
+                }
             }
             S[m] = l;
             w[m] = wo;     // weight of a in o's parent face
