@@ -1129,7 +1129,7 @@ __global__ void k_child_fill(const int4* __restrict__ pnode, const float4* __res
     for (int k = 0; k < 3; ++k)
         if (f[k] >= 0) {
             const int pos = cptr[f[k]] + atomicAdd(&cfill[f[k]], 1);
-            cchild[pos] = c;
+            cchild[pos] = (c << 2) | k;     // unpacked by k_child_sort
             calpha[pos] = al[k];
         }
 }
@@ -1140,13 +1140,54 @@ __device__ __forceinline__ int centry(int x, int r, int k, int n_v) {
 }
 
 // Sort each child list by child id (fixed summation order -> deterministic), then
-// tell each child where its entry sits (the component of its cslot for this parent).
-__global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cchild,
-                             float* __restrict__ calpha, const int4* __restrict__ pnode, int n_v,
-                             int4* __restrict__ cslot) {
+// tell each child where its entry sits (the component of its cslot for this
+// parent).  The entries arrive as (child << 2 | which of the child's parents this
+// is) from k_child_fill; child ids are distinct within a list, so the packed keys
+// sort in child order, and the ids are written back unpacked.
+constexpr int kSortRegs = 16;   // child lists up to this long are sorted in registers
+
+__global__ void __launch_bounds__(TPB) k_child_sort(const int* __restrict__ cptr, int* __restrict__ cchild,
+                                                    float* __restrict__ calpha, int n_v,
+                                                    int4* __restrict__ cslot) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_v) return;
     const int b = cptr[p], e = cptr[p + 1];
+    if (e - b <= kSortRegs) {
+        // the list in registers (padded with INT_MAX) through a bitonic network
+        int ch[kSortRegs];
+        float al[kSortRegs];
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k) {
+            ch[k] = b + k < e ? cchild[b + k] : INT_MAX;
+            al[k] = b + k < e ? calpha[b + k] : 0.f;
+        }
+#pragma unroll
+        for (int k = 2; k <= kSortRegs; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+                for (int i = 0; i < kSortRegs; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const int u = ch[i], v = ch[l];
+                        const float fu = al[i], fv = al[l];
+                        const bool sw = (u > v) == ((i & k) == 0);
+                        ch[i] = sw ? v : u;
+                        ch[l] = sw ? u : v;
+                        al[i] = sw ? fv : fu;
+                        al[l] = sw ? fu : fv;
+                    }
+                }
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k)
+            if (b + k < e) {
+                const int c = ch[k] >> 2;
+                cchild[b + k] = c;
+                calpha[b + k] = al[k];
+                reinterpret_cast<int*>(&cslot[c])[ch[k] & 3] = centry(p, k, b + k, n_v);
+            }
+        return;
+    }
     for (int x = b + 1; x < e; ++x) {
         const int kc = cchild[x];
         const float ka = calpha[x];
@@ -1160,10 +1201,10 @@ __global__ void k_child_sort(const int* __restrict__ cptr, int* __restrict__ cch
         calpha[y + 1] = ka;
     }
     for (int x = b; x < e; ++x) {
-        const int c = cchild[x];
-        const int4 pn = pnode[c];
-        const int k = pn.x == p ? 0 : (pn.y == p ? 1 : 2);
-        reinterpret_cast<int*>(&cslot[c])[k] = centry(p, x - b, x, n_v);
+        const int v = cchild[x];
+        const int c = v >> 2;
+        cchild[x] = c;
+        reinterpret_cast<int*>(&cslot[c])[v & 3] = centry(p, x - b, x, n_v);
     }
 }
 
@@ -1974,7 +2015,7 @@ int gbp_backward_impl(gbp_plan p, const float* D, const float* vscale, const int
         if ((rc = gbp_scan_exclusive(p->done, p->ccnt, n_v, p->scan_tmp, s))) return rc;
         k_child_fill<<<nb, TPB, 0, s>>>(p->pnode, p->pa, n_v, p->ccnt, p->cfill, p->cchild,
                                         p->calpha);
-        k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, p->pnode, n_v, p->cslot);
+        k_child_sort<<<nb, TPB, 0, s>>>(p->ccnt, p->cchild, p->calpha, n_v, p->cslot);
         GBP_LAUNCH_CHECK();
     }
     // leaves-first level walk
