@@ -1427,6 +1427,10 @@ __global__ void k_adj_gs(const int* __restrict__ list, const int* __restrict__ c
     int* md_next = reinterpret_cast<int*>(slot & 1 ? &ctl->maxdiff : &ctl->maxdiff2);
     if (blockIdx.x == 0 && threadIdx.x == 0) *md_next = 0;
     const int n_list = ctl->remaining;
+    // a block with no listed vertex has nothing to add (in a budgeted backward most
+    // sweeps find the list empty: they must cost a launch, not 2 contended atomics
+    // per block)
+    if ((int)(blockIdx.x * blockDim.x) >= n_list) return;
     float d = 0.f, a = 0.f;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n_list; q += gridDim.x * blockDim.x) {
         const int i = list[q];
@@ -1438,9 +1442,9 @@ __global__ void k_adj_gs(const int* __restrict__ list, const int* __restrict__ c
     }
     d = block_max_f(d);
     a = block_max_f(a);
-    if (threadIdx.x == 0) {
-        atomicMax(md, __float_as_int(d));
-        atomicMax(&ctl->lmax_bits, __float_as_int(a));
+    if (threadIdx.x == 0) {   // both are >= 0 and start at 0: a zero changes no maximum
+        if (d > 0.f) atomicMax(md, __float_as_int(d));
+        if (a > 0.f) atomicMax(&ctl->lmax_bits, __float_as_int(a));
     }
 }
 
