@@ -931,21 +931,32 @@ __global__ void __launch_bounds__(TPB)
     const int2 p = reached ? nptr[i] : make_int2(0, 0);
     const int c0 = p.y & 255, c1 = (p.y >> 8) & 255, c2 = (p.y >> 16) & 255, c3 = (p.y >> 24) & 255;
     const int e01 = c0 + c1, e012 = e01 + c2, tot = e012 + c3;
-    // FP32 screen (the first kKeep values of each lane are kept for the second pass)
-    constexpr int kKeep = 4;
-    float keep[kKeep];
-    float b32 = GBP_INF;
-    for (int c = lane, k = 0; c < tot; c += L, ++k) {
+    // FP32 screen.  The lane's first kKeep entries (c = lane, lane + L, ...) are
+    // solved together -- their loads in flight at once, an entry past the patch
+    // repeating entry 0 and discarded -- and kept for the second pass.
+    constexpr int kKeep = 3;
+    auto screen = [&](int c) {
         const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
         const int t = nent[p.x + c];
         const int4 v = tetv[t];
         int a, b, cc;
         face_nodes_sel(v, K, a, b, cc);
-        const float v32 = local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
-                                           T[a], T[b], T[cc]);
-        if (k < kKeep) keep[k] = v32;
-        b32 = fminf(b32, v32);
+        return local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K), T[a], T[b],
+                                T[cc]);
+    };
+    float keep[kKeep];
+    float b32 = GBP_INF;
+    if (tot > 0) {
+        float v3[kKeep];
+#pragma unroll
+        for (int h = 0; h < kKeep; ++h) v3[h] = screen(lane + h * L < tot ? lane + h * L : 0);
+#pragma unroll
+        for (int h = 0; h < kKeep; ++h) {
+            keep[h] = lane + h * L < tot ? v3[h] : GBP_INF;
+            b32 = fminf(b32, keep[h]);
+        }
     }
+    for (int c = lane + kKeep * L; c < tot; c += L) b32 = fminf(b32, screen(c));
     for (int o = L / 2; o > 0; o >>= 1) b32 = fminf(b32, __shfl_xor(b32, o));
     const float cut = b32 + 1e-4f * fmaxf(1.f, fabsf(b32));
     // candidates of the FP64 decision: into the block's list, or (list full) solved here
@@ -954,15 +965,9 @@ __global__ void __launch_bounds__(TPB)
     for (int c = lane, k = 0; c < tot && b32 < GBP_INF; c += L, ++k) {
         float v32;
         if (k < kKeep) {
-            v32 = keep[k];
+            v32 = k == 0 ? keep[0] : k == 1 ? keep[1] : keep[2];
         } else {
-            const int K = (c < c0) ? 0 : (c < e01) ? 1 : (c < e012) ? 2 : 3;
-            const int t = nent[p.x + c];
-            const int4 v = tetv[t];
-            int a, b, cc;
-            face_nodes_sel(v, K, a, b, cc);
-            v32 = local_min<false>(face_q_rt(tetg[2 * (size_t)t], tetg[2 * (size_t)t + 1], K),
-                                   T[a], T[b], T[cc]);
+            v32 = screen(c);
         }
         if (!(v32 <= cut)) continue;
         const int q = atomicAdd(&n_cand, 1);
