@@ -1535,8 +1535,17 @@ __global__ void k_grad_node(const int2* __restrict__ nptr, const int* __restrict
     if (i >= n_v) return;                           // uniform over the L-lane group
     const int2 p = nptr[i];
     const int tot = (p.y & 255) + ((p.y >> 8) & 255) + ((p.y >> 16) & 255) + ((p.y >> 24) & 255);
+    // three entries per lane at a time (their loads in flight together), added in
+    // entry order
     float s = 0.f;
-    for (int c = lane; c < tot; c += L) s += dsbar[nent[p.x + c]];
+    for (int c = lane; c < tot; c += 3 * L) {
+        float v[3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) v[h] = dsbar[nent[p.x + (c + h * L < tot ? c + h * L : c)]];
+#pragma unroll
+        for (int h = 0; h < 3; ++h)
+            if (c + h * L < tot) s += v[h];
+    }
     for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) dvs_user[node_user[i]] = 0.25f * s;
 }
