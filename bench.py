@@ -781,6 +781,26 @@ def main():
         f"{bud['gs_budget']} sweeps), timed {args.steps} steps: {ms_enq:.3f} ms/step (wall {wall_enq:.3f}), "
         f"{ok}/{args.steps} within budgets")
     ms = ms_enq if enqueue else ms_sync
+    # the forward alone at the same parameters: synchronous call, and enqueue-only
+    # with the iteration's round budget (status checked after each)
+    nf = 10
+    e0.record()
+    for _ in range(nf):
+        B.eikonal_forward(st["plan"], st["D"], st["vs"], st["rn"], st["rt"])
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_sync = e0.elapsed_time(e1) / nf
+    fwd_ok = 0
+    e0.record()
+    for _ in range(nf):
+        B.eikonal_forward_async(st["plan"], st["D"], st["vs"], st["rn"], st["rt"], bud["round_budget"])
+        fs_ = B.plan_status(st["plan"])
+        fwd_ok += int(fs_["err"] == 0 and fs_["forward_converged"])
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_enq = e0.elapsed_time(e1) / nf
+    log(f"[bench] forward alone: {fwd_sync:.3f} ms synchronous, {fwd_enq:.3f} ms enqueue-only "
+        f"({fwd_ok}/{nf} within {bud['round_budget']} rounds)")
     log(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step ({'enqueue-only' if enqueue else 'synchronous'} "
         f"calls) loss={float(loss[0]):.4g}")
 
@@ -795,7 +815,9 @@ def main():
                   calls="enqueue-only" if enqueue else "synchronous",
                   synchronous_calls=dict(ms_per_step=ms_sync, iters_per_s=1000.0 / ms_sync, wall_ms_per_step=wall_sync),
                   enqueue_only_calls=dict(ms_per_step=ms_enq, iters_per_s=1000.0 / ms_enq, wall_ms_per_step=wall_enq,
-                                          steps_within_budgets=ok, **bud))
+                                          steps_within_budgets=ok, **bud),
+                  forward_alone=dict(synchronous_ms=fwd_sync, enqueue_only_ms=fwd_enq,
+                                     enqueue_only_within_budget=fwd_ok, solves=nf))
     if not args.no_profile:
         # per-kernel HIP-event timing on the launching stream, separate steps
         B.profile_reset()
