@@ -1472,6 +1472,18 @@ __global__ void k_grad_tet(const int4* __restrict__ tetv, const float4* __restri
     if (j >= n_e) return;
     const int4 v = tetv[j];
     const int vv[4] = {v.x, v.y, v.z, v.w};
+    // most elements are no vertex's parent element: those write zeros without
+    // reading the tensor, the metric or their user id (unless dL/dD is wanted)
+    int pk[4];
+#pragma unroll
+    for (int K = 0; K < 4; ++K) pk[K] = par[vv[K]];
+    bool any = false;
+#pragma unroll
+    for (int K = 0; K < 4; ++K) any |= pk[K] == ((j << 2) | K);
+    if (!any && !dD_user) {
+        dsbar[j] = 0.f;
+        return;
+    }
     const float sbar = tetg[2 * (size_t)j + 1].z;
     const int u = tet_user[j];
     const float* d6 = D + 6 * (size_t)u;
@@ -1482,7 +1494,7 @@ __global__ void k_grad_tet(const int4* __restrict__ tetv, const float4* __restri
     float g00 = 0, g11 = 0, g22 = 0, g01 = 0, g02 = 0, g12 = 0, gs = 0;
     for (int K = 0; K < 4; ++K) {
         const int i = vv[K];
-        if (par[i] != ((j << 2) | K)) continue;
+        if (pk[K] != ((j << 2) | K)) continue;
         const float l = lam[i];
         if (l == 0.f) continue;
         int f3[3];
