@@ -273,7 +273,10 @@ def warm_single_form(st, prob, steps, torch, B, autotune, ordered=False):
     if ordered:
         hold = autotune.tune_hold(plan, st["D"], st["vs"], st["rn"], st["rt"], guess=T.clone(), repeats=1)
         B.eikonal_forward(plan, st["D"], st["vs"], st["rn"], st["rt"], T_init=T, out=T)
-    bud = autotune.budgets(plan, margin=1.5, extra=32)
+    # budgets: the ordered (cold) solve's own counts + 8, as the plain iteration's; the
+    # two-sided solve is sized from a cold solve and gets room
+    bud = (autotune.budgets(plan, margin=1.0, extra=8) if ordered
+           else autotune.budgets(plan, margin=1.5, extra=32))
     step = B.Step(plan, bt, st["D"], st["vs"], st["rn"], st["rt"], st["W"], st["ap"], tgt, T, ecg, loss,
                   warm=True, **bud)
     ms = _replay_timed(step, steps, torch)
@@ -556,8 +559,10 @@ def batched_form(dev, steps, torch, gi, B, autotune, n_inst=64, n_meshes=8, seed
             # the hold-back searched for forwards ordered by the last times
             hold = autotune.tune_hold(plan, D, vs, rn, rt, guess=T.clone(), repeats=1)
             B.eikonal_forward(plan, D, vs, rn, rt, T_init=T, out=T)
-        # a two-sided warm solve can need more rounds than the cold one it is sized from
-        bud = autotune.budgets(plan, margin=2.0 if mode == "warm" else 1.5, extra=64 if mode == "warm" else 32)
+        # a two-sided warm solve can need more rounds than the cold one it is sized from;
+        # the cold and ordered solves get their own counts + 8, as the plain iteration
+        bud = (autotune.budgets(plan, margin=2.0, extra=64) if mode == "warm"
+               else autotune.budgets(plan, margin=1.0, extra=8))
         ecg = torch.empty((n_inst, S, L), dtype=torch.float32, device=dev)
         loss = torch.empty(n_inst, dtype=torch.float32, device=dev)
         step = B.Step(plan, bt, D, vs, rn, rt, W, apc, target, T, ecg, loss, warm=warm, **bud)
